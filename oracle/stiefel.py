@@ -1,0 +1,131 @@
+"""Preconditioned generalized-Stiefel components (Table 1) and the CCA /
+FDA costs, in plain FP64 with explicitly formed d x d matrices.
+
+St_B(p, d) = {X : X^T B X = I}, metric g(xi, eta) = tr(xi^T M eta) for a
+fixed SPD preconditioner M (Section 3 uses the sketched
+M = Z^T S^T S Z + lam I).  For CCA the manifold is the product
+St_Sxx x St_Syy with metric blkdiag(Mxx, Myy) and every component acts
+block by block (Section 4.2).
+
+Parity status: pinned.  Tests check tangency, idempotence and
+M-self-adjointness of the projection, that the Sylvester solve reduces to
+S = sym(X^T B xi) when M = B (Appendix B), that the Cholesky form of the QR
+retraction equals B^-1/2 qf(B^1/2 (X + xi)) literally, that the retraction
+lands on the manifold, and that the Riemannian gradient reproduces finite
+differences of the cost along retraction curves.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def sym(A):
+    return 0.5 * (A + A.T)
+
+
+def inner(xi, eta, M) -> float:
+    """Riemannian metric tr(xi^T M eta) (Table 1)."""
+    return float(np.trace(xi.T @ M @ eta))
+
+
+def sylvester_kron(A, C):
+    """Solve A S + S A = C (A SPD k x k) through the Kronecker form
+    (I (x) A + A^T (x) I) vec(S) = vec(C)."""
+    k = A.shape[0]
+    K = np.kron(np.eye(k), A) + np.kron(A.T, np.eye(k))
+    s = np.linalg.solve(K, C.reshape(-1, order="F"))
+    return s.reshape((k, k), order="F")
+
+
+def normal_coeff(X, B, M, xi):
+    """S_xi of Table 1: (X^T B M^-1 B X) S + S (X^T B M^-1 B X) =
+    X^T B xi + (X^T B xi)^T."""
+    BX = B @ X
+    A = BX.T @ np.linalg.solve(M, BX)
+    C = BX.T @ xi
+    return sylvester_kron(A, C + C.T)
+
+
+def project(X, B, M, xi):
+    """Orthogonal projection on T_X St_B in the M-metric (Table 1):
+    xi - M^-1 B X S_xi."""
+    S = normal_coeff(X, B, M, xi)
+    return xi - np.linalg.solve(M, B @ X) @ S
+
+
+def retract_qr(X, xi, B):
+    """QR retraction (Table 1): B^-1/2 qf(B^1/2 (X + xi)), computed as
+    (X + xi) L^-T with L L^T = (X + xi)^T B (X + xi), since qf(A) = A R^-1
+    for the positive-diagonal R of A = QR and R^T R = A^T A."""
+    Y = X + xi
+    L = np.linalg.cholesky(Y.T @ B @ Y)
+    return np.linalg.solve(L, Y.T).T
+
+
+def retract_qr_literal(X, xi, B):
+    """The same retraction written with B^1/2 and a Householder QR."""
+    w, Q = np.linalg.eigh(B)
+    Bh = (Q * np.sqrt(w)) @ Q.T
+    Bmh = (Q / np.sqrt(w)) @ Q.T
+    Qf, Rf = np.linalg.qr(Bh @ (X + xi))
+    Qf = Qf * np.sign(np.diag(Rf))[None, :]
+    return Bmh @ Qf
+
+
+def transport(X_new, B, M, xi):
+    """Vector transport by projection onto the new tangent space."""
+    return project(X_new, B, M, xi)
+
+
+def qf_B(X, B):
+    """qf_B(X) = B^-1/2 qf(B^1/2 X): the start point map of Algorithms
+    CCAopt and LDAopt."""
+    return retract_qr(X, np.zeros_like(X), B)
+
+
+# --------------------------------------------------------------- CCA ---
+def cca_blocks(X, Y, lam_x, lam_y):
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    Sxx = X.T @ X + lam_x * np.eye(X.shape[1])
+    Syy = Y.T @ Y + lam_y * np.eye(Y.shape[1])
+    Sxy = X.T @ Y
+    return Sxx, Syy, Sxy
+
+
+def cca_cost(U, V, Sxy, mu) -> float:
+    """f_CCA(Z) = -1/2 tr(Z^T [[0, Sxy], [Sxy^T, 0]] Z N)
+    = -tr(U^T Sxy V N) (Eq. costriemannianccaBrockett)."""
+    return -float(np.sum(np.diag(U.T @ Sxy @ V) * np.asarray(mu)))
+
+
+def cca_egrad(U, V, Sxy, mu):
+    """Euclidean gradient of the extended cost: -[Sxy V N; Sxy^T U N]."""
+    N = np.diag(mu)
+    return -(Sxy @ V @ N), -(Sxy.T @ U @ N)
+
+
+def cca_rgrad(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu):
+    """Riemannian gradient, Eq. gradCCA:
+    -[Pi_U(Mxx^-1 Sxy V N); Pi_V(Myy^-1 Sxy^T U N)]."""
+    gu, gv = cca_egrad(U, V, Sxy, mu)
+    return (project(U, Sxx, Mxx, np.linalg.solve(Mxx, gu)),
+            project(V, Syy, Myy, np.linalg.solve(Myy, gv)))
+
+
+# --------------------------------------------------------------- FDA ---
+def lda_cost(W, SB, mu) -> float:
+    """f_FDA(W) = -1/2 tr(W^T S_B W N) (Eq. lda_riemannian)."""
+    return -0.5 * float(np.sum(np.diag(W.T @ SB @ W) * np.asarray(mu)))
+
+
+def lda_egrad(W, SB, mu):
+    """Euclidean gradient -S_B W N (the differential of the cost above)."""
+    return -(SB @ W @ np.diag(mu))
+
+
+def lda_rgrad(W, B, SB, M, mu):
+    """Riemannian gradient Pi_W(M^-1 grad f) (Table 1 applied to the FDA
+    cost; Eq. LDAgrad read as grad = Pi(M^-1 (-S_B W N)), its printed
+    second term being the first written out)."""
+    return project(W, B, M, np.linalg.solve(M, lda_egrad(W, SB, mu)))

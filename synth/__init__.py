@@ -1,0 +1,234 @@
+"""Seeded synthetic workloads for sketched Riemannian CCA / FDA.
+
+This module only draws data.  It holds none of the method's arithmetic:
+no sketch, no Gram, no factorisation, no solver step.  Both the FP64 CPU
+oracle (``oracle/``) and the GPU library's tests and benchmark take their
+inputs from here, so the two sides see bit-identical matrices.
+
+Workload shapes follow the paper's setting of tall data with samples in
+rows (Section 2, Section 4 problem statement, Section 5 problem statement):
+
+* CCA: ``X`` (n x dx) and ``Y`` (n x dy) share a Gaussian latent factor
+  ``Z`` (n x r); ``X = (Z Wx + noise*E) diag(cx)``, ``Y = (Z Wy + noise*E')
+  diag(cy)`` with geometric column scales ``c_j = 10^(-decades*j/(d-1))``
+  (or ``10^(-decades*j/d)``) that make ``X^T X`` ill conditioned the way
+  the paper's synthetic experiment asks for (Section 6.2).
+* FDA: ``c`` classes with exactly ``n/c`` samples each (shuffled), class
+  means drawn from ``N(0, mean_std^2 I)``, and a shared within-class
+  covariance ``Q diag(lam) Q^T`` with ``lam_j = 10^(-decades*j/d)`` and a
+  Haar-random orthogonal ``Q``.
+* Planted CCA: matrices whose canonical correlations are known exactly,
+  used to pin the oracle.
+
+All draws use ``numpy.random.default_rng(seed)`` (PCG64).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+__all__ = [
+    "column_scales", "cca_latent", "lda_classes", "planted_cca",
+    "Workload", "workload", "serving_trace", "WORKLOADS",
+]
+
+
+def column_scales(d: int, decades: float, inclusive_end: bool) -> np.ndarray:
+    """Geometric column scales 1 -> 10^-decades.
+
+    ``inclusive_end=True`` gives ``10^(-decades*j/(d-1))`` (last column is
+    exactly ``10^-decades``); ``False`` gives ``10^(-decades*j/d)``.
+    """
+    if decades == 0 or d == 1:
+        return np.ones(d)
+    j = np.arange(d, dtype=np.float64)
+    den = (d - 1) if inclusive_end else d
+    return 10.0 ** (-decades * j / den)
+
+
+def cca_latent(n: int, dx: int, dy: int, *, r: int, noise: float = 0.1,
+               x_decades: float = 0.0, y_decades: float = 0.0,
+               inclusive_end: bool = True, seed: int = 0,
+               dtype=np.float64):
+    """Two views of one Gaussian latent factor (rows are samples)."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((n, r))
+    Wx = rng.standard_normal((r, dx))
+    Wy = rng.standard_normal((r, dy))
+    X = Z @ Wx
+    X += noise * rng.standard_normal((n, dx))
+    Y = Z @ Wy
+    Y += noise * rng.standard_normal((n, dy))
+    if x_decades:
+        X *= column_scales(dx, x_decades, inclusive_end)[None, :]
+    if y_decades:
+        Y *= column_scales(dy, y_decades, inclusive_end)[None, :]
+    return (np.ascontiguousarray(X, dtype=dtype),
+            np.ascontiguousarray(Y, dtype=dtype))
+
+
+def haar_orthogonal(d: int, rng: np.random.Generator) -> np.ndarray:
+    """Haar-distributed orthogonal matrix (QR of a Gaussian, signs fixed)."""
+    G = rng.standard_normal((d, d))
+    Q, Rg = np.linalg.qr(G)
+    Q *= np.sign(np.diag(Rg))[None, :]
+    return Q
+
+
+def lda_classes(n: int, d: int, c: int, *, mean_std: float = 2.0,
+                decades: float = 6.0, haar: bool = True, seed: int = 0,
+                dtype=np.float64):
+    """Labelled samples with equal priors and a shared covariance.
+
+    Returns ``(X, labels)`` with ``labels`` int32 in ``[0, c)``; every class
+    has exactly ``n // c`` samples (``n`` must be a multiple of ``c``).
+    """
+    if n % c:
+        raise ValueError("n must be a multiple of c for equal priors")
+    rng = np.random.default_rng(seed)
+    labels = np.repeat(np.arange(c, dtype=np.int32), n // c)
+    rng.shuffle(labels)
+    means = mean_std * rng.standard_normal((c, d))
+    lam = 10.0 ** (-decades * np.arange(d, dtype=np.float64) / d)
+    Q = haar_orthogonal(d, rng) if haar else np.eye(d)
+    G = rng.standard_normal((n, d))
+    G *= np.sqrt(lam)[None, :]
+    X = G @ Q.T
+    X += means[labels]
+    return np.ascontiguousarray(X, dtype=dtype), labels
+
+
+def planted_cca(n: int, r: int, rho, *, seed: int = 0, dtype=np.float64):
+    """CCA pair with canonical correlations exactly ``rho`` (lambda = 0).
+
+    ``X = E1 A`` and ``Y = (E1 diag(rho) + E2 diag(sqrt(1-rho^2))) B`` where
+    ``[E1 E2]`` has orthonormal columns (n x 2r) and ``A``, ``B`` are
+    invertible r x r.  Then the canonical correlations of (X, Y) are the
+    entries of ``rho`` and the weights are ``A^-1`` / ``B^-1`` columns.
+    Returns ``(X, Y, A, B)``.
+    """
+    rho = np.asarray(rho, dtype=np.float64)
+    assert rho.shape == (r,)
+    rng = np.random.default_rng(seed)
+    E, _ = np.linalg.qr(rng.standard_normal((n, 2 * r)))
+    E1, E2 = E[:, :r], E[:, r:]
+    A = rng.standard_normal((r, r)) + 3.0 * np.eye(r)
+    B = rng.standard_normal((r, r)) + 3.0 * np.eye(r)
+    X = E1 @ A
+    Y = (E1 * rho[None, :] + E2 * np.sqrt(1.0 - rho ** 2)[None, :]) @ B
+    return (np.ascontiguousarray(X, dtype=dtype),
+            np.ascontiguousarray(Y, dtype=dtype), A, B)
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One named synthetic workload (sizes and generator recipe)."""
+    name: str
+    problem: str          # "cca" or "lda"
+    n: int
+    dx: int
+    dy: int               # 0 for LDA
+    k: int
+    lam: float            # lambda_x = lambda_y; LDA: NaN means the 1e-6 rule
+    sketch: str           # "countsketch" or "srht"
+    s: int
+    dtype: str            # data dtype: "f64", "f32", "bf16"
+    seed: int
+    r: int = 8            # latent rank (CCA)
+    x_decades: float = 0.0
+    y_decades: float = 0.0
+    inclusive_end: bool = True
+    c: int = 0            # classes (LDA)
+
+    @property
+    def lam_value(self) -> float:
+        """lambda_x = lambda_y for CCA; the population 1e-6 rule for FDA."""
+        if self.problem == "lda":
+            return lda_population_lambda(self.n, self.dx)
+        return self.lam
+
+    def generate(self):
+        np_dtype = np.float64 if self.dtype == "f64" else np.float32
+        if self.problem == "cca":
+            return cca_latent(self.n, self.dx, self.dy, r=self.r, noise=0.1,
+                              x_decades=self.x_decades,
+                              y_decades=self.y_decades,
+                              inclusive_end=self.inclusive_end,
+                              seed=self.seed, dtype=np_dtype)
+        return lda_classes(self.n, self.dx, self.c, seed=self.seed,
+                           dtype=np_dtype)
+
+    def scaled(self, n: int | None = None, dx: int | None = None,
+               dy: int | None = None, s: int | None = None,
+               name: str | None = None) -> "Workload":
+        """Same recipe at other sizes (for tests that the oracle finishes)."""
+        return dataclasses.replace(
+            self, n=n or self.n, dx=dx or self.dx,
+            dy=(dy if dy is not None else self.dy), s=s or self.s,
+            name=name or self.name + "-scaled")
+
+
+WORKLOADS = {
+    # FP64 CCA, CountSketch s = 4 dx, X columns scaled 1 -> 1e-3.
+    "cca-f64-small": Workload("cca-f64-small", "cca", 2000, 60, 40, 5, 1e-3,
+                              "countsketch", 240, "f64", 12060 + 0, r=8,
+                              x_decades=3.0, inclusive_end=True),
+    # FP32 CCA, SRHT s = 4000, both views scaled 10^(-4j/d).
+    "cca-f32-srht": Workload("cca-f32-srht", "cca", 200_000, 1000, 1000, 10,
+                             1e-4, "srht", 4000, "f32", 12060 + 1, r=32,
+                             x_decades=4.0, y_decades=4.0,
+                             inclusive_end=False),
+    # FP32 FDA, CountSketch s = 8000 of the centred data, 20 classes.
+    "lda-f32": Workload("lda-f32", "lda", 100_000, 2000, 0, 19, float("nan"),
+                        "countsketch", 8000, "f32", 12060 + 2, c=20),
+    # Precision variant of the FP32 CCA workload (BF16 data and GEMMs).
+    "cca-bf16-srht": Workload("cca-bf16-srht", "cca", 200_000, 1000, 1000, 10,
+                              1e-4, "srht", 4000, "bf16", 12060 + 1, r=32,
+                              x_decades=4.0, y_decades=4.0,
+                              inclusive_end=False),
+}
+
+
+def workload(name: str) -> Workload:
+    return WORKLOADS[name]
+
+
+def lda_population_lambda(n: int, d: int, decades: float = 6.0) -> float:
+    """Regularisation for the FDA workload: 1e-6 times the mean eigenvalue
+    of the within-class scatter (the paper's synthetic rule, Section 6.2),
+    taken at its population value ``n * mean_j 10^(-decades*j/d)`` so that
+    it is fixed by the recipe rather than estimated from the draw."""
+    lam = 10.0 ** (-decades * np.arange(d, dtype=np.float64) / d)
+    return 1e-6 * n * float(lam.mean())
+
+
+@dataclasses.dataclass(frozen=True)
+class Request:
+    rid: int
+    arrival_s: float
+    n: int
+    dx: int
+    dy: int
+    k: int
+    seed: int
+
+
+def serving_trace(num: int = 512, rate_per_s: float = 200.0, *,
+                  n_range=(5000, 100_000), d_range=(64, 1024),
+                  k_range=(2, 16), seed: int = 12064):
+    """Poisson arrivals with independent uniform sizes per request."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_per_s, size=num)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(num):
+        out.append(Request(
+            rid=i, arrival_s=float(t[i]),
+            n=int(rng.integers(n_range[0], n_range[1] + 1)),
+            dx=int(rng.integers(d_range[0], d_range[1] + 1)),
+            dy=int(rng.integers(d_range[0], d_range[1] + 1)),
+            k=int(rng.integers(k_range[0], k_range[1] + 1)),
+            seed=1_000_000 + i))
+    return out
+
