@@ -1,0 +1,149 @@
+"""Benchmark: sketch-preconditioned Riemannian CCA / FDA solves on one GPU.
+
+One step = one full solve of the workload (sketch, FP64 metric factor,
+warm start, Riemannian CG to tolerance, FP64 finish) with the data already
+resident in HBM.  Prints one JSON line (see the keys below).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "CCA solves/sec + TFLOP/s at 1e-6 rel obj err vs FP64; serving p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+DTYPE_NAMES = {"f64": "f64", "f32": "f32", "bf16": "bf16"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cca-f32-srht", choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--max-iter", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, X, Y_or_labels):
+    """The FP64 oracle (direct closed form) timed on this host's cores on one
+    full solve of the same workload; returns (record, oracle values)."""
+    from threadpoolctl import threadpool_info
+    from oracle import direct
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    t0 = time.perf_counter()
+    if wl.problem == "cca":
+        vals, _, _ = direct.cca_direct(X, Y_or_labels, wl.lam_value, wl.lam_value)
+    else:
+        vals, _ = direct.lda_direct(X, Y_or_labels, wl.c, wl.lam_value, k=wl.k)
+    dt = time.perf_counter() - t0
+    rec = {"value": 1.0 / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"one full FP64 direct solve of the {wl.name} workload "
+                     f"(Gram, Cholesky, whitened SVD; numpy/OpenBLAS), {dt:.2f} s"}
+    return rec, vals
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU row-sharded path is design-only.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2106_12060_amd as srp
+
+    wl = synth.workload(args.workload)
+    print(f"bench: generating {wl.name} (n={wl.n}, dx={wl.dx}, dy={wl.dy}, k={wl.k})", file=sys.stderr,
+          flush=True)
+    A, B = wl.generate()
+    dev = torch.device("cuda:0")
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[wl.dtype]
+    Ad = torch.from_numpy(A).to(dev).to(tdt).contiguous()
+    if wl.problem == "cca":
+        Bd = torch.from_numpy(B).to(dev).to(tdt).contiguous()
+    else:
+        Bd = torch.from_numpy(B).to(dev)
+    lam = wl.lam_value
+    tol = args.tol if args.tol is not None else (1e-9 if wl.dtype == "f64" else 1e-4)
+    sketch = srp.SRP_SRHT if wl.sketch == "srht" else srp.SRP_COUNTSKETCH
+
+    def one(time_passes=False):
+        opt = srp.srp_default_options(sketch=sketch, max_iter=args.max_iter, time_passes=int(time_passes))
+        if wl.problem == "cca":
+            return srp.cca_solve(Ad, Bd, wl.k, lam, lam, wl.s, tol=tol, options=opt)
+        return srp.lda_solve(Ad, Bd, wl.c, wl.k, lam, wl.s, tol=tol, options=opt)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = one(time_passes=True)
+        infos.append(res[-1])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = args.steps / elapsed
+    ms_per_step = 1000.0 * elapsed / args.steps
+
+    # dominant kernel: the fused data pass over the full data
+    esize = {"f64": 8, "f32": 4, "bf16": 2}[wl.dtype]
+    dsum = wl.dx + (wl.dy if wl.problem == "cca" else 0)
+    bytes_per_launch = wl.n * dsum * esize
+    pass_ms = sum(i["pass_ms"] for i in infos)
+    launches = sum(i["pass_launches"] for i in infos)
+    avg_ms = pass_ms / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    flops_per_pass = (6 if wl.problem == "cca" else 4) * wl.k * dsum * wl.n
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "k_pass (fused data pass)", "bytes_per_launch": bytes_per_launch,
+                "avg_launch_ms": avg_ms, "launches": launches,
+                "tflops": flops_per_pass / (avg_ms * 1e-3) / 1e12 if launches else 0.0}
+
+    out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAMES[wl.dtype], "data": "synthetic",
+           "config": {"workload": wl.name, "problem": wl.problem, "n": wl.n, "dx": wl.dx, "dy": wl.dy,
+                      "k": wl.k, "lambda": lam, "sketch": wl.sketch, "s": wl.s, "tol": tol,
+                      "parallelism": "single-gpu"},
+           "roofline": roofline,
+           "solve": {key: infos[-1][key] for key in ("status", "iterations", "warm_iterations", "passes",
+                                                     "ms_sketch", "ms_factor", "ms_warm", "ms_iterate",
+                                                     "ms_total")}}
+    if not args.no_cpu_baseline:
+        rec, vals = cpu_baseline(wl, A, B)
+        out["cpu_baseline"] = rec
+        if not args.no_accuracy:
+            from oracle import metrics, direct
+            if wl.problem == "cca":
+                U, V = res[0].cpu().numpy(), res[1].cpu().numpy()
+                A64, B64 = A.astype(np.float64), B.astype(np.float64)
+                err = metrics.cca_rel_objective_error(U, V, A64, B64, lam, lam, vals)
+                cons = max(metrics.constraint_residual(U, A64, lam), metrics.constraint_residual(V, B64, lam))
+            else:
+                W = res[0].cpu().numpy()
+                _, _, _, Xh, Yh = direct.lda_scatter(A, B, wl.c)
+                err = metrics.lda_rel_objective_error(W, Xh, Yh, lam, vals)
+                cons = metrics.constraint_residual(W, Xh, lam)
+            out["accuracy"] = {"rel_objective_error": err, "constraint_residual": cons,
+                               "reference": "FP64 oracle (direct closed form)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

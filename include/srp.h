@@ -1,0 +1,190 @@
+/*
+ * srp.h -- C ABI of the sketch-preconditioned Riemannian CCA / FDA library
+ * for one AMD MI355X (gfx950).
+ *
+ * Method: Shustin & Avron, "Faster Randomized Methods for Orthogonality
+ * Constrained Problems".  A sketch S (CountSketch, Section 3; or SRHT,
+ * Appendix A) of the tall data gives the preconditioner
+ * M = Z^T S^T S Z + lambda I (Section 3), used as the Riemannian metric of
+ * the generalized Stiefel manifold (Table 1); Riemannian CG then solves the
+ * Brockett-cost forms of regularised CCA (Section 4, Algorithm CCAopt) and
+ * FDA (Section 5, Algorithm LDAopt).
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major and contiguous; data matrices hold samples in
+ *    rows (n x d).
+ *  - All array arguments are DEVICE pointers owned by the caller, unless a
+ *    comment says "host".  The library never frees or retains caller
+ *    memory; it allocates its own workspace from the device's stream-
+ *    ordered pool and releases it before returning.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued on it; every entry point returns after that work completed
+ *    (it synchronises the stream), so outputs are ready on return.
+ *  - Return value: SRP_OK or an SRP_E* status.  No exception crosses the
+ *    ABI.  srp_last_error() gives a thread-local message for the last
+ *    failure in the calling thread.
+ *  - dtype codes name the element type of a data matrix: SRP_F64 (double),
+ *    SRP_F32 (float), SRP_BF16 (bfloat16, stored as uint16).
+ */
+#ifndef SRP_H
+#define SRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SRP_OK 0
+#define SRP_EINVAL 1      /* invalid argument (sizes, pointers, dtype)      */
+#define SRP_ENOTSPD 2     /* Cholesky breakdown: matrix not positive definite */
+#define SRP_ENOCONV 3     /* max_iter reached; outputs hold the last iterate */
+#define SRP_ENOMEM 4      /* device allocation failed                        */
+#define SRP_EDEVICE 5     /* HIP runtime error                                */
+#define SRP_EBUSY 6       /* serving engine: no capacity right now            */
+#define SRP_EREJECTED 7   /* serving engine: request can never fit            */
+#define SRP_PENDING 8     /* serving engine: request not finished yet         */
+
+/* ---- element types ---------------------------------------------------- */
+#define SRP_F64 0
+#define SRP_F32 1
+#define SRP_BF16 2
+
+/* ---- sketch kinds ----------------------------------------------------- */
+#define SRP_COUNTSKETCH 0 /* Section 3                                       */
+#define SRP_SRHT 1        /* Appendix A, Definition SRHT                      */
+
+/* Solver options.  Fill with srp_default_options() and override fields. */
+typedef struct srp_options {
+  int sketch;             /* SRP_COUNTSKETCH or SRP_SRHT                      */
+  uint64_t seed;          /* seed of the sketch randomness (SplitMix64)       */
+  int max_iter;           /* Riemannian CG iteration cap (default 1000)       */
+  int warm_start_iters;   /* RCG iterations on the sketched problem that give
+                             the start point (exact-cca / exact-fda of the
+                             sketch, Algorithms CCAopt / LDAopt); 0 = start
+                             from qf of a seeded Gaussian point              */
+  int refresh_every;      /* recompute the data products B*U from the data
+                             every this many iterations (default 25)         */
+  int check_every;        /* host polls the convergence flag every this many
+                             iterations (default 4)                          */
+  int pass_compute;       /* arithmetic of the data passes: SRP_F64 or
+                             SRP_F32 (default: F64 for F64 data, F32 else)   */
+  int final_f64;          /* 1: finish with an FP64-arithmetic pass and FP64
+                             retraction (default 1)                          */
+  const double* mu;       /* HOST pointer to k weights mu_1 > ... > mu_k > 0
+                             (N = diag(mu)); NULL = k, k-1, ..., 1           */
+  int time_passes;        /* 1: time every fused data pass over the full data
+                             with HIP events on `stream` (srp_info.pass_ms)   */
+} srp_options;
+
+/* Per-solve report. */
+typedef struct srp_info {
+  int status;             /* same as the return value                        */
+  int iterations;         /* Riemannian CG iterations on the full data       */
+  int warm_iterations;    /* iterations spent on the sketched problem        */
+  int passes;             /* data passes over the full n rows                */
+  double f;               /* final weighted cost f(Z) = -sum mu_i sigma_i    */
+  double objective;       /* sum of the returned sigma (or rho)              */
+  double grad_norm;       /* ||grad f||_M at the last iterate                 */
+  double ms_sketch;       /* wall ms per phase                               */
+  double ms_factor;
+  double ms_warm;
+  double ms_iterate;
+  double ms_total;
+  double pass_ms;         /* summed duration of the timed fused passes       */
+  int pass_launches;      /* number of timed fused passes                    */
+} srp_info;
+
+/* Fill *opt with the defaults listed above.  Returns SRP_EINVAL if NULL. */
+int srp_default_options(srp_options* opt);
+
+/* Thread-local text of the last error in this thread ("" if none). */
+const char* srp_last_error(void);
+
+/* ---- sketches (Section 3; Appendix A) ---------------------------------
+ * out = S A for an s x n sketch S drawn from `seed`, A n x d of `dtype`.
+ * out is s x d, double for SRP_F64 input, float otherwise.
+ *
+ * CountSketch (Section 3): row i of A goes to bucket h(i) with sign g(i),
+ *   w = SplitMix64 output i for `seed`; h(i) = ((w >> 32) * s) >> 32,
+ *   g(i) = +1 if bit 0 of w is 0 else -1.  Deterministic summation order.
+ * SRHT (Definition SRHT): S = sqrt(n'/s) R H D with n' = 2^ceil(log2 n),
+ *   A zero-padded to n' rows, H the normalised Walsh-Hadamard matrix,
+ *   D_i = +1 if bit 0 of SplitMix64(seed ^ 0x5352485444494147, i) is 0,
+ *   R the s rows of smallest key SplitMix64(seed ^ 0x535248545357524F, r),
+ *   in ascending row order.  Requires s <= n' <= 2^20.
+ * Errors: SRP_EINVAL for n < 1, d < 1, s < 1, bad dtype or null pointers.
+ */
+int srp_countsketch(const void* A, int dtype, int64_t n, int d, int s,
+                    uint64_t seed, void* out, void* stream);
+int srp_srht(const void* A, int dtype, int64_t n, int d, int s,
+             uint64_t seed, void* out, void* stream);
+/* The s sampled SRHT rows (int64, ascending) for n rows and `seed`. */
+int srp_srht_rows(int64_t n, int s, uint64_t seed, int64_t* rows,
+                  void* stream);
+
+/* ---- preconditioner factor (Section 3; cost Table costs) --------------
+ * From a sketch SA (s x d, dtype SRP_F64 or SRP_F32) compute in FP64 the
+ * upper-triangular R with positive diagonal and R^T R = SA^T SA + lambda I,
+ * and its inverse Rinv (both d x d, double, row-major; entries below the
+ * diagonal are written as 0).  Rinv may be NULL.
+ * Errors: SRP_ENOTSPD if the Gram is not positive definite (lambda = 0 with
+ * a rank-deficient sketch), SRP_EINVAL for bad sizes.
+ */
+int srp_sketch_factor(const void* SA, int dtype, int s, int d, double lambda,
+                      double* R, double* Rinv, void* stream);
+
+/* ---- fused tall-skinny data pass (per-iteration products) -------------
+ * For data blocks A0 (n x d0) and, if A1 != NULL, A1 (n x d1) of `dtype`,
+ * and directions W0 (d0 x k), W1 (d1 x k) (double), compute with arithmetic
+ * `compute` (SRP_F64 or SRP_F32):
+ *   J0 = A0^T [A0 W0 | A1 W1]   (d0 x 2k, double)
+ *   J1 = A1^T [A0 W0 | A1 W1]   (d1 x 2k, double)
+ * (with A1 == NULL: J0 = A0^T A0 W0, d0 x k).  These are the products
+ * X^T (X U), X^T (Y V), ... that the Riemannian gradient, projection and
+ * retraction of Eq. gradCCA / Table 1 consume.  One read of the data.
+ * Limits: k <= 16 with two blocks, k <= 32 with one; d0 + d1 <= 2048
+ * (F32 / BF16 data) or <= 1024 (F64 data or F64 arithmetic).
+ */
+int srp_gram_pass(const void* A0, const void* A1, int dtype, int compute,
+                  int64_t n, int d0, int d1, int k, const double* W0,
+                  const double* W1, double* J0, double* J1, void* stream);
+
+/* ---- solvers ----------------------------------------------------------
+ * cca_solve: top-k (lambda_x, lambda_y)-canonical correlations of X (n x dx)
+ * and Y (n x dy) (Definition of regularised CCA, Section 4), by Algorithm
+ * CCAopt: sketch X and Y with one S, factor M_xx and M_yy, warm start from
+ * the sketched problem, then Riemannian CG on St_Sxx x St_Syy with metric
+ * blkdiag(M_xx, M_yy) for the cost of Eq. costriemannianccaBrockett.
+ * Outputs (device, double): U (dx x k), V (dy x k) with U^T Sxx U = I,
+ * V^T Syy V = I, U^T Sxy V = diag(sigma); sigma (k) descending; column
+ * pairs sign-normalised (largest |entry| of each U column positive).
+ * tol: stop when ||grad f||_M <= tol * |f|.
+ * Requires 1 <= k <= min(dx, dy), k <= 16, sketch_size >= max(dx, dy),
+ * lambda >= 0.  Returns SRP_ENOCONV (with the last iterate) at max_iter.
+ */
+int cca_solve(const void* X, const void* Y, int64_t n, int dx, int dy, int k,
+              double lambda_x, double lambda_y, int sketch_size, double tol,
+              int dtype, const srp_options* opt, void* stream, double* U,
+              double* V, double* sigma, srp_info* info);
+
+/* lda_solve: the k leading regularised FDA directions (Definition of FDA,
+ * Section 5) of X (n x d) with int32 labels in [0, n_classes), by
+ * Algorithm LDAopt: centre the classes (Xhat, S_B), sketch Xhat, factor M,
+ * warm start, Riemannian CG on St_{S_w + lambda I} for Eq. lda_riemannian.
+ * Outputs: W (d x k, double) with W^T (S_w + lambda I) W = I and
+ * W^T S_B W = diag(rho); rho (k) descending.
+ * Requires 1 <= k <= min(n_classes - 1, d), k <= 32, every class
+ * non-empty, sketch_size >= d, lambda >= 0.
+ */
+int lda_solve(const void* X, const int32_t* labels, int64_t n, int d,
+              int n_classes, int k, double lambda, int sketch_size,
+              double tol, int dtype, const srp_options* opt, void* stream,
+              double* W, double* rho, srp_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SRP_H */

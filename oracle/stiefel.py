@@ -129,3 +129,27 @@ def lda_rgrad(W, B, SB, M, mu):
     cost; Eq. LDAgrad read as grad = Pi(M^-1 (-S_B W N)), its printed
     second term being the first written out)."""
     return project(W, B, M, np.linalg.solve(M, lda_egrad(W, SB, mu)))
+
+
+# ----------------------------------------------------- data products ---
+def data_products(A0, W0, A1=None, W1=None):
+    """J_b = A_b^T [A_0 W_0 | A_1 W_1] in FP64: the products with the data
+    matrices that the Riemannian components consume (Table costs).  Also
+    returns the entrywise magnitudes |A_b|^T [|A_0||W_0| | |A_1||W_1|] that
+    bound the rounding error of any summation order."""
+    A0 = np.asarray(A0, dtype=np.float64)
+    W0 = np.asarray(W0, dtype=np.float64)
+    P = [A0 @ W0]
+    Pa = [np.abs(A0) @ np.abs(W0)]
+    As = [A0]
+    if A1 is not None:
+        A1 = np.asarray(A1, dtype=np.float64)
+        W1 = np.asarray(W1, dtype=np.float64)
+        P.append(A1 @ W1)
+        Pa.append(np.abs(A1) @ np.abs(W1))
+        As.append(A1)
+    Pc = np.hstack(P)
+    Pac = np.hstack(Pa)
+    J = [A.T @ Pc for A in As]
+    Jabs = [np.abs(A).T @ Pac for A in As]
+    return J, Jabs

@@ -1,0 +1,12 @@
+"""Sketch-preconditioned Riemannian CCA / FDA on one AMD MI355X (gfx950).
+
+Python face of the C-ABI library ``libsrp.so`` (``include/srp.h``); see
+``_lib`` for the functions.  Every computation runs in the HIP library.
+"""
+from ._lib import (  # noqa: F401
+    SRP_OK, SRP_EINVAL, SRP_ENOTSPD, SRP_ENOCONV, SRP_ENOMEM, SRP_EDEVICE,
+    SRP_F64, SRP_F32, SRP_BF16, SRP_COUNTSKETCH, SRP_SRHT,
+    SrpError, SrpOptions, SrpInfo, LIB_PATH, lib, exported_symbols,
+    srp_default_options, srp_countsketch, srp_srht, srp_srht_rows,
+    srp_sketch_factor, srp_gram_pass, cca_solve, lda_solve,
+)

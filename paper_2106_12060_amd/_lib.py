@@ -1,0 +1,236 @@
+"""ctypes binding of ``libsrp.so`` (the C ABI in ``include/srp.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Tensors are torch tensors on the current HIP device; outputs are
+allocated here with torch (device memory) and filled by the library on
+torch's current stream.  A missing library raises immediately: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsrp.so")
+
+SRP_OK, SRP_EINVAL, SRP_ENOTSPD, SRP_ENOCONV, SRP_ENOMEM, SRP_EDEVICE = 0, 1, 2, 3, 4, 5
+SRP_EBUSY, SRP_EREJECTED, SRP_PENDING = 6, 7, 8
+SRP_F64, SRP_F32, SRP_BF16 = 0, 1, 2
+SRP_COUNTSKETCH, SRP_SRHT = 0, 1
+
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOCONV", 4: "ENOMEM",
+                5: "EDEVICE", 6: "EBUSY", 7: "EREJECTED", 8: "PENDING"}
+
+_DTYPES = {torch.float64: SRP_F64, torch.float32: SRP_F32, torch.bfloat16: SRP_BF16}
+
+
+class SrpOptions(ctypes.Structure):
+    _fields_ = [("sketch", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("max_iter", ctypes.c_int), ("warm_start_iters", ctypes.c_int),
+                ("refresh_every", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("pass_compute", ctypes.c_int), ("final_f64", ctypes.c_int),
+                ("mu", ctypes.POINTER(ctypes.c_double)), ("time_passes", ctypes.c_int)]
+
+
+class SrpInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iterations", ctypes.c_int),
+                ("warm_iterations", ctypes.c_int), ("passes", ctypes.c_int),
+                ("f", ctypes.c_double), ("objective", ctypes.c_double),
+                ("grad_norm", ctypes.c_double), ("ms_sketch", ctypes.c_double),
+                ("ms_factor", ctypes.c_double), ("ms_warm", ctypes.c_double),
+                ("ms_iterate", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("pass_ms", ctypes.c_double), ("pass_launches", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SrpError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed: {STATUS_NAMES.get(code, code)} ({msg})")
+        self.code = code
+
+
+_lib = None
+
+# Exported C symbols and their signatures (names as in include/srp.h).
+_P = ctypes.c_void_p
+_SIGS = {
+    "srp_default_options": (ctypes.c_int, [ctypes.POINTER(SrpOptions)]),
+    "srp_last_error": (ctypes.c_char_p, []),
+    "srp_countsketch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_uint64, _P, _P]),
+    "srp_srht": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_uint64, _P, _P]),
+    "srp_srht_rows": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, _P, _P]),
+    "srp_sketch_factor": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         _P, _P, _P]),
+    "srp_gram_pass": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P]),
+    "cca_solve": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_int, ctypes.POINTER(SrpOptions), _P, _P, _P, _P,
+                                 ctypes.POINTER(SrpInfo)]),
+    "lda_solve": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                 ctypes.POINTER(SrpOptions), _P, _P, _P, ctypes.POINTER(SrpInfo)]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load ``libsrp.so`` (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(fn, code):
+    if code != SRP_OK:
+        raise SrpError(fn, code, lib().srp_last_error().decode())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dtype(t):
+    if t.dtype not in _DTYPES:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return _DTYPES[t.dtype]
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("inputs must be contiguous tensors on the HIP device")
+
+
+def srp_default_options(**overrides) -> SrpOptions:
+    o = SrpOptions()
+    _check("srp_default_options", lib().srp_default_options(ctypes.byref(o)))
+    for key, val in overrides.items():
+        if key == "mu":
+            continue
+        if key == "sketch" and isinstance(val, str):
+            val = {"countsketch": SRP_COUNTSKETCH, "srht": SRP_SRHT}[val]
+        if key == "pass_compute" and isinstance(val, str):
+            val = {"f64": SRP_F64, "f32": SRP_F32}[val]
+        setattr(o, key, val)
+    return o
+
+
+def _sketch_out(A, s):
+    acc = torch.float64 if A.dtype == torch.float64 else torch.float32
+    return torch.empty((s, A.shape[1]), dtype=acc, device=A.device)
+
+
+def srp_countsketch(A: torch.Tensor, s: int, seed: int) -> torch.Tensor:
+    _need_cuda(A)
+    out = _sketch_out(A, s)
+    _check("srp_countsketch", lib().srp_countsketch(_ptr(A), _dtype(A), A.shape[0], A.shape[1], s,
+                                                    seed, _ptr(out), _stream()))
+    return out
+
+
+def srp_srht(A: torch.Tensor, s: int, seed: int) -> torch.Tensor:
+    _need_cuda(A)
+    out = _sketch_out(A, s)
+    _check("srp_srht", lib().srp_srht(_ptr(A), _dtype(A), A.shape[0], A.shape[1], s, seed,
+                                      _ptr(out), _stream()))
+    return out
+
+
+def srp_srht_rows(n: int, s: int, seed: int, device="cuda") -> torch.Tensor:
+    rows = torch.empty(s, dtype=torch.int64, device=device)
+    _check("srp_srht_rows", lib().srp_srht_rows(n, s, seed, _ptr(rows), _stream()))
+    return rows
+
+
+def srp_sketch_factor(SA: torch.Tensor, lam: float, want_inverse: bool = True):
+    _need_cuda(SA)
+    s, d = SA.shape
+    R = torch.empty((d, d), dtype=torch.float64, device=SA.device)
+    Rinv = torch.empty((d, d), dtype=torch.float64, device=SA.device) if want_inverse else None
+    _check("srp_sketch_factor", lib().srp_sketch_factor(_ptr(SA), _dtype(SA), s, d, lam, _ptr(R),
+                                                        _ptr(Rinv), _stream()))
+    return R, Rinv
+
+
+def srp_gram_pass(A0, W0, A1=None, W1=None, compute: str = "f32"):
+    _need_cuda(A0, A1, W0, W1)
+    n, d0 = A0.shape
+    k = W0.shape[1]
+    d1 = A1.shape[1] if A1 is not None else 0
+    nb = 2 if A1 is not None else 1
+    J0 = torch.empty((d0, nb * k), dtype=torch.float64, device=A0.device)
+    J1 = torch.empty((d1, nb * k), dtype=torch.float64, device=A0.device) if A1 is not None else None
+    comp = {"f64": SRP_F64, "f32": SRP_F32}[compute]
+    _check("srp_gram_pass", lib().srp_gram_pass(_ptr(A0), _ptr(A1), _dtype(A0), comp, n, d0, d1, k,
+                                                _ptr(W0), _ptr(W1), _ptr(J0), _ptr(J1), _stream()))
+    return J0, J1
+
+
+def cca_solve(X, Y, k, lambda_x, lambda_y, sketch_size, tol=1e-6, options: SrpOptions | None = None,
+              mu=None, raise_on_noconv: bool = False):
+    """Returns (U, V, sigma, info_dict)."""
+    _need_cuda(X, Y)
+    if X.dtype != Y.dtype:
+        raise TypeError("X and Y must share a dtype")
+    n, dx = X.shape
+    dy = Y.shape[1]
+    opt = options if options is not None else srp_default_options()
+    mu_buf = None
+    if mu is not None:
+        mu_buf = (ctypes.c_double * k)(*[float(m) for m in mu])
+        opt.mu = ctypes.cast(mu_buf, ctypes.POINTER(ctypes.c_double))
+    U = torch.empty((dx, k), dtype=torch.float64, device=X.device)
+    V = torch.empty((dy, k), dtype=torch.float64, device=X.device)
+    sigma = torch.empty(k, dtype=torch.float64, device=X.device)
+    info = SrpInfo()
+    rc = lib().cca_solve(_ptr(X), _ptr(Y), n, dx, dy, k, lambda_x, lambda_y, sketch_size, tol,
+                         _dtype(X), ctypes.byref(opt), _stream(), _ptr(U), _ptr(V), _ptr(sigma),
+                         ctypes.byref(info))
+    if rc != SRP_OK and not (rc == SRP_ENOCONV and not raise_on_noconv):
+        _check("cca_solve", rc)
+    return U, V, sigma, info.as_dict()
+
+
+def lda_solve(X, labels, n_classes, k, lam, sketch_size, tol=1e-6, options: SrpOptions | None = None,
+              mu=None, raise_on_noconv: bool = False):
+    """Returns (W, rho, info_dict)."""
+    _need_cuda(X, labels)
+    if labels.dtype != torch.int32:
+        raise TypeError("labels must be int32")
+    n, d = X.shape
+    opt = options if options is not None else srp_default_options()
+    mu_buf = None
+    if mu is not None:
+        mu_buf = (ctypes.c_double * k)(*[float(m) for m in mu])
+        opt.mu = ctypes.cast(mu_buf, ctypes.POINTER(ctypes.c_double))
+    W = torch.empty((d, k), dtype=torch.float64, device=X.device)
+    rho = torch.empty(k, dtype=torch.float64, device=X.device)
+    info = SrpInfo()
+    rc = lib().lda_solve(_ptr(X), _ptr(labels), n, d, n_classes, k, lam, sketch_size, tol, _dtype(X),
+                         ctypes.byref(opt), _stream(), _ptr(W), _ptr(rho), ctypes.byref(info))
+    if rc != SRP_OK and not (rc == SRP_ENOCONV and not raise_on_noconv):
+        _check("lda_solve", rc)
+    return W, rho, info.as_dict()

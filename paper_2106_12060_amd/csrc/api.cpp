@@ -1,0 +1,166 @@
+// C ABI entry points (declared in include/srp.h): argument checks, stream
+// handling, workspace, and the synchronous-return convention.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace srp {
+const char* last_error();
+int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int k, double lx, double ly, int s,
+                   double tol, int dtype, const srp_options* opt, hipStream_t st, double* U, double* V,
+                   double* sigma, srp_info* info);
+int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c, int k, double lam, int s,
+                   double tol, int dtype, const srp_options* opt, hipStream_t st, double* W, double* rho,
+                   srp_info* info);
+}  // namespace srp
+
+using namespace srp;
+
+namespace {
+struct Scratch {
+  void* p = nullptr;
+  hipStream_t st;
+  explicit Scratch(hipStream_t s) : st(s) {}
+  ~Scratch() {
+    if (p) {
+      (void)hipFreeAsync(p, st);
+      (void)hipStreamSynchronize(st);
+    }
+  }
+};
+
+int finish(hipStream_t st) {
+  SRP_HIP(hipStreamSynchronize(st));
+  return SRP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int srp_default_options(srp_options* o) {
+  if (!o) return SRP_EINVAL;
+  memset(o, 0, sizeof(*o));
+  o->sketch = SRP_COUNTSKETCH;
+  o->seed = 12060;
+  o->max_iter = 1000;
+  o->warm_start_iters = 40;
+  o->refresh_every = 25;
+  o->check_every = 4;
+  o->pass_compute = -1;
+  o->final_f64 = 0;
+  o->mu = nullptr;
+  return SRP_OK;
+}
+
+const char* srp_last_error(void) { return srp::last_error(); }
+
+int srp_countsketch(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, void* stream) {
+  clear_error();
+  SRP_REQUIRE(A && out, "null pointer argument");
+  SRP_REQUIRE(n >= 1 && n < (int64_t(1) << 31) && d >= 1 && s >= 1, "bad sizes");
+  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16, "bad dtype %d", dtype);
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const size_t bytes = countsketch_ws_bytes(n, s) + 1024;
+  SRP_TRY(device_alloc(&ws.p, bytes, st));
+  Arena ar{(char*)ws.p, bytes, 0};
+  SRP_TRY(countsketch_run(A, dtype, n, d, s, seed, out, ar, st));
+  return finish(st);
+}
+
+int srp_srht(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, void* stream) {
+  clear_error();
+  SRP_REQUIRE(A && out, "null pointer argument");
+  SRP_REQUIRE(n >= 1 && d >= 1 && s >= 1, "bad sizes");
+  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16, "bad dtype %d", dtype);
+  int64_t np = 2;
+  while (np < n) np <<= 1;
+  SRP_REQUIRE(np <= (int64_t(1) << 20) && s <= np, "SRHT needs s <= n' <= 2^20");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const size_t bytes = srht_ws_bytes(n, d, s, dtype) + 1024;
+  SRP_TRY(device_alloc(&ws.p, bytes, st));
+  Arena ar{(char*)ws.p, bytes, 0};
+  SRP_TRY(srht_run(A, dtype, n, d, s, seed, out, ar, st));
+  return finish(st);
+}
+
+int srp_srht_rows(int64_t n, int s, uint64_t seed, int64_t* rows, void* stream) {
+  clear_error();
+  SRP_REQUIRE(rows, "null pointer argument");
+  SRP_REQUIRE(n >= 1 && s >= 1, "bad sizes");
+  int64_t np = 2;
+  while (np < n) np <<= 1;
+  SRP_REQUIRE(np <= (int64_t(1) << 20) && s <= np, "SRHT needs s <= n' <= 2^20");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const size_t bytes = srht_ws_bytes(n, 1, s, SRP_F32) + 1024;
+  SRP_TRY(device_alloc(&ws.p, bytes, st));
+  Arena ar{(char*)ws.p, bytes, 0};
+  SRP_TRY(srht_rows_run(n, s, seed, rows, ar, st));
+  return finish(st);
+}
+
+int srp_sketch_factor(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
+                      void* stream) {
+  clear_error();
+  SRP_REQUIRE(SA && R, "null pointer argument");
+  SRP_REQUIRE(s >= 1 && d >= 1, "bad sizes");
+  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32, "sketch dtype must be SRP_F64 or SRP_F32");
+  SRP_REQUIRE(lambda >= 0.0, "lambda must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const size_t bytes = factor_ws_bytes(s, d) + bytes_of<int>(4) + bytes_of<double>((size_t)d * d) + 2048;
+  SRP_TRY(device_alloc(&ws.p, bytes, st));
+  Arena ar{(char*)ws.p, bytes, 0};
+  int* flag = ar.take<int>(4);
+  double* X = Rinv ? Rinv : ar.take<double>((size_t)d * d);
+  SRP_TRY(fill_i32(flag, 1, 0, st));
+  SRP_TRY(sketch_factor_run(SA, dtype, s, d, lambda, R, X, nullptr, flag, ar, st));
+  int h = 0;
+  SRP_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SRP_TRY(finish(st));
+  if (h) {
+    set_error("sketched Gram is not positive definite");
+    return SRP_ENOTSPD;
+  }
+  return SRP_OK;
+}
+
+int srp_gram_pass(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1, int k,
+                  const double* W0, const double* W1, double* J0, double* J1, void* stream) {
+  clear_error();
+  SRP_REQUIRE(A0 && W0 && J0, "null pointer argument");
+  SRP_REQUIRE(!A1 || (W1 && J1 && d1 >= 1), "second block needs W1, J1 and d1 >= 1");
+  SRP_REQUIRE(n >= 1 && d0 >= 1 && k >= 1, "bad sizes");
+  SRP_REQUIRE(compute == SRP_F64 || compute == SRP_F32, "compute must be SRP_F64 or SRP_F32");
+  if (!A1) d1 = 0;
+  SRP_REQUIRE(pass_limits_ok(dtype, compute, d0, d1, k, A1 ? 2 : 1), "unsupported shape for the data pass");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const size_t bytes = pass_ws_bytes(n, d0, d1, k, compute) + 2048;
+  SRP_TRY(device_alloc(&ws.p, bytes, st));
+  Arena ar{(char*)ws.p, bytes, 0};
+  SRP_TRY(gram_pass_run(A0, A1, dtype, compute, n, d0, d1, k, W0, W1, J0, J1, nullptr, ar, st));
+  return finish(st);
+}
+
+int cca_solve(const void* X, const void* Y, int64_t n, int dx, int dy, int k, double lambda_x, double lambda_y,
+              int sketch_size, double tol, int dtype, const srp_options* opt, void* stream, double* U, double* V,
+              double* sigma, srp_info* info) {
+  return cca_solve_impl(X, Y, n, dx, dy, k, lambda_x, lambda_y, sketch_size, tol, dtype, opt, (hipStream_t)stream,
+                        U, V, sigma, info);
+}
+
+int lda_solve(const void* X, const int32_t* labels, int64_t n, int d, int n_classes, int k, double lambda,
+              int sketch_size, double tol, int dtype, const srp_options* opt, void* stream, double* W, double* rho,
+              srp_info* info) {
+  return lda_solve_impl(X, labels, n, d, n_classes, k, lambda, sketch_size, tol, dtype, opt, (hipStream_t)stream, W,
+                        rho, info);
+}
+
+}  // extern "C"

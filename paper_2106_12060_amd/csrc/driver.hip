@@ -1,0 +1,680 @@
+// Host driver: Algorithm CCAopt and Algorithm LDAopt on one HIP stream.
+//
+//   sketch (CountSketch / SRHT, one S for X and Y)
+//   -> M_b = (S A_b)^T (S A_b) + lam_b I, R_b, M_b^-1 = R_b^-1 R_b^-T (FP64)
+//   -> warm start: Riemannian CG on the sketched problem (exact-cca /
+//      exact-fda of the sketch; its exact metric is M itself)
+//   -> qf_B of the warm start, then Riemannian CG on the full data with the
+//      metric M (one fused data pass per iteration)
+//   -> FP64 retraction, Rayleigh-Ritz rotation of the k x k block, sign
+//      convention.
+// All iteration state stays on the device; the host only enqueues kernels
+// and polls a convergence flag every `check_every` iterations.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <utility>
+#include <vector>
+#include <cstdarg>
+#include <cstring>
+
+namespace srp {
+
+// ------------------------------------------------------------ errors
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+void clear_error() { g_err[0] = 0; }
+const char* last_error() { return g_err; }
+
+int num_cus() {
+  static int cached = 0;
+  if (cached) return cached;
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+    cached = v;
+  else
+    cached = 256;
+  return cached;
+}
+
+int device_alloc(void** p, size_t bytes, hipStream_t s) {
+  static bool pool_tuned = false;
+  if (!pool_tuned) {
+    int dev = 0;
+    hipMemPool_t pool;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    pool_tuned = true;
+  }
+  hipError_t e = hipMallocAsync(p, bytes, s);
+  if (e != hipSuccess) {
+    set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? SRP_ENOMEM : SRP_EDEVICE;
+  }
+  return SRP_OK;
+}
+
+int device_free(void* p, hipStream_t s) {
+  if (p) SRP_HIP(hipFreeAsync(p, s));
+  return SRP_OK;
+}
+
+// Owns one stream-ordered workspace allocation.
+struct Workspace {
+  void* base = nullptr;
+  hipStream_t st = nullptr;
+  ~Workspace() {
+    if (base) (void)hipFreeAsync(base, st);
+  }
+};
+
+// ------------------------------------------------------------ timers
+struct PhaseTimer {
+  hipStream_t st;
+  std::chrono::steady_clock::time_point t0;
+  explicit PhaseTimer(hipStream_t s) : st(s) { t0 = std::chrono::steady_clock::now(); }
+  double lap_ms() {
+    (void)hipStreamSynchronize(st);
+    auto t1 = std::chrono::steady_clock::now();
+    double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    t0 = t1;
+    return ms;
+  }
+};
+
+// ----------------------------------------------------------- the solver
+struct RcgProblem {
+  int nb = 1, k = 1, lda_cost = 0;
+  int dtype = SRP_F32;      // element type of the data matrices
+  int compute = SRP_F32;    // arithmetic of the fused passes
+  const void* A[2] = {nullptr, nullptr};
+  int64_t n = 0;
+  int d[2] = {0, 0};
+  double lam[2] = {0.0, 0.0};
+  const double* Minv[2] = {nullptr, nullptr};
+  const double* SB = nullptr;   // FDA: d x d
+};
+
+struct RcgBuffers {
+  double *U[2], *Ks[2], *Kc[2], *xi[2], *gold[2], *J[2], *Jc[2], *Z[2], *Wz[2];
+  double* Pn = nullptr;      // two-pass route: n x 2k
+  double* parts = nullptr;   // two-pass route: split-k partials
+  int ksplit = 1;
+  SolverCtrl* ctrl;
+  double* kk;
+  double* part;
+  double* mu;
+  char* pass_ws;
+  size_t pass_ws_bytes;
+  // optional timing of the fused passes over the full data
+  bool time_passes = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr;
+};
+
+static size_t kk_bytes() { return bytes_of<double>((size_t)(2 * KK_NSLOTS + 9) * KK_STRIDE); }
+
+static int twopass_ksplit(int64_t n) {
+  int64_t ks = (n + 4095) / 4096;
+  if (ks > 64) ks = 64;
+  if (ks < 1) ks = 1;
+  return (int)ks;
+}
+
+static size_t rcg_buffers_bytes(int nb, int k, int64_t nmax, const int* d, int dtype) {
+  size_t b = 0;
+  for (int s = 0; s < nb; ++s) {
+    const size_t dk = (size_t)d[s] * k;
+    b += 6 * bytes_of<double>(dk) + bytes_of<double>((size_t)d[s] * nb * k) + 2 * bytes_of<double>(2 * dk);
+  }
+  b += bytes_of<SolverCtrl>(1) + kk_bytes() + partial_bytes(k, std::max(d[0], nb == 2 ? d[1] : 0)) +
+       bytes_of<double>(KMAX);
+  const size_t pw = std::max(pass_ws_bytes(nmax, d[0], nb == 2 ? d[1] : 0, k, SRP_F64),
+                             pass_ws_bytes(nmax, d[0], nb == 2 ? d[1] : 0, k, SRP_F32));
+  b += (pw + 255) & ~size_t(255);
+  // two-pass FP64 route
+  const int ks = twopass_ksplit(nmax);
+  b += bytes_of<double>((size_t)nmax * nb * k);
+  b += bytes_of<double>((size_t)ks * std::max(d[0], nb == 2 ? d[1] : 0) * nb * k);
+  (void)dtype;
+  return b;
+}
+
+static int rcg_buffers_take(RcgBuffers& B, Arena& ar, int nb, int k, int64_t nmax, const int* d) {
+  for (int s = 0; s < nb; ++s) {
+    const size_t dk = (size_t)d[s] * k;
+    B.U[s] = ar.take<double>(dk);
+    B.Ks[s] = ar.take<double>(dk);
+    B.Kc[s] = ar.take<double>(dk);
+    B.xi[s] = ar.take<double>(dk);
+    B.gold[s] = ar.take<double>(dk);
+    B.Jc[s] = ar.take<double>(dk);
+    B.J[s] = ar.take<double>((size_t)d[s] * nb * k);
+    B.Z[s] = ar.take<double>(2 * dk);
+    B.Wz[s] = ar.take<double>(2 * dk);
+    if (!B.Wz[s]) return SRP_ENOMEM;
+  }
+  for (int s = nb; s < 2; ++s) {
+    B.U[s] = B.Ks[s] = B.Kc[s] = B.xi[s] = B.gold[s] = B.Jc[s] = B.J[s] = B.Z[s] = B.Wz[s] = nullptr;
+  }
+  B.ctrl = ar.take<SolverCtrl>(1);
+  B.kk = (double*)ar.take<char>(kk_bytes());
+  B.part = (double*)ar.take<char>(partial_bytes(k, std::max(d[0], nb == 2 ? d[1] : 0)));
+  B.mu = ar.take<double>(KMAX);
+  B.pass_ws_bytes = std::max(pass_ws_bytes(nmax, d[0], nb == 2 ? d[1] : 0, k, SRP_F64),
+                             pass_ws_bytes(nmax, d[0], nb == 2 ? d[1] : 0, k, SRP_F32));
+  B.pass_ws = ar.take<char>(B.pass_ws_bytes);
+  B.ksplit = twopass_ksplit(nmax);
+  B.Pn = ar.take<double>((size_t)nmax * nb * k);
+  B.parts = ar.take<double>((size_t)B.ksplit * std::max(d[0], nb == 2 ? d[1] : 0) * nb * k);
+  if (!B.ctrl || !B.kk || !B.part || !B.mu || !B.pass_ws || !B.Pn || !B.parts) return SRP_ENOMEM;
+  return SRP_OK;
+}
+
+static ProbView make_view(const RcgProblem& P, RcgBuffers& B) {
+  ProbView v{};
+  v.nb = P.nb;
+  v.k = P.k;
+  v.lda_cost = P.lda_cost;
+  for (int s = 0; s < P.nb; ++s) {
+    SideView& q = v.s[s];
+    q.d = P.d[s];
+    q.lam = P.lam[s];
+    q.U = B.U[s];
+    q.Ks = B.Ks[s];
+    q.Kc = B.Kc[s];
+    q.xi = B.xi[s];
+    q.gold = B.gold[s];
+    q.J = B.J[s];
+    q.jld = P.nb * P.k;
+    q.js_off = s * P.k;
+    q.jc_off = (P.nb == 2) ? (1 - s) * P.k : 0;
+    q.Jc_sep = P.lda_cost ? B.Jc[s] : nullptr;
+    q.Z = B.Z[s];
+    q.Wz = B.Wz[s];
+  }
+  v.mu = B.mu;
+  v.ctrl = B.ctrl;
+  v.kk = B.kk;
+  v.part = B.part;
+  v.part_slices = partial_slices(std::max(P.d[0], P.nb == 2 ? P.d[1] : 0));
+  return v;
+}
+
+// J_b = A_b^T [A_0 W_0 | A_1 W_1] with FP64 arithmetic through the generic
+// GEMM (two reads of the data); used where the fused pass has no FP64
+// instance for the shape.
+static int twopass_f64(const RcgProblem& P, RcgBuffers& B, double* const* W, hipStream_t st) {
+  const int k = P.k, nb = P.nb, ldp = nb * k;
+  if (P.dtype == SRP_BF16) {
+    set_error("two-pass FP64 route does not take BF16 data");
+    return SRP_EINVAL;
+  }
+  const bool f32 = (P.dtype == SRP_F32);
+  for (int s = 0; s < nb; ++s) {
+    GemmArgs g{};
+    g.m = (int)P.n; g.n = k; g.kk = P.d[s]; g.alpha = 1.0; g.beta = 0.0;
+    g.A = P.A[s]; g.lda = P.d[s]; g.ta = false; g.a_f32 = f32;
+    g.B = W[s]; g.ldb = k; g.tb = false; g.b_f32 = false;
+    g.C = B.Pn + s * k; g.ldc = ldp;
+    SRP_TRY(gemm_f64(g, st));
+  }
+  for (int s = 0; s < nb; ++s) {
+    const int64_t cnt = (int64_t)P.d[s] * ldp;
+    GemmArgs g{};
+    g.m = P.d[s]; g.n = ldp; g.kk = (int)P.n; g.alpha = 1.0; g.beta = 0.0;
+    g.A = P.A[s]; g.lda = P.d[s]; g.ta = true; g.a_f32 = f32;
+    g.B = B.Pn; g.ldb = ldp; g.tb = false; g.b_f32 = false;
+    g.C = B.parts; g.ldc = ldp; g.ksplit = B.ksplit; g.c_split_stride = cnt;
+    SRP_TRY(gemm_f64(g, st));
+    SRP_TRY(sum_parts_f64(B.parts, B.ksplit, cnt, cnt, B.J[s], 0, 0.0, st));
+  }
+  return SRP_OK;
+}
+
+// Data products along directions W (d_b x k): fills J (and FDA's S_B W).
+static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int compute, const int* done,
+                     hipStream_t st) {
+  if (compute == SRP_F64 && !pass_limits_ok(P.dtype, SRP_F64, P.d[0], P.d[1], P.k, P.nb)) {
+    SRP_TRY(twopass_f64(P, B, W, st));
+  } else {
+    Arena pw{B.pass_ws, B.pass_ws_bytes, 0};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (B.time_passes && B.events) {
+      SRP_HIP(hipEventCreate(&e0));
+      SRP_HIP(hipEventCreate(&e1));
+      SRP_HIP(hipEventRecord(e0, st));
+    }
+    SRP_TRY(gram_pass_run(P.A[0], P.nb == 2 ? P.A[1] : nullptr, P.dtype, compute, P.n, P.d[0], P.d[1], P.k, W[0],
+                          P.nb == 2 ? W[1] : nullptr, B.J[0], P.nb == 2 ? B.J[1] : nullptr, done, pw, st, e1));
+    if (e0) B.events->push_back({e0, e1});
+  }
+  if (P.lda_cost) SRP_TRY(gemm_skinny_f64(P.d[0], P.k, P.SB, P.d[0], W[0], P.k, B.Jc[0], P.k, st));
+  return SRP_OK;
+}
+
+static int apply_minv(const RcgProblem& P, RcgBuffers& B, hipStream_t st) {
+  for (int s = 0; s < P.nb; ++s)
+    SRP_TRY(gemm_skinny_f64(P.d[s], 2 * P.k, P.Minv[s], P.d[s], B.Z[s], 2 * P.k, B.Wz[s], 2 * P.k, st));
+  return SRP_OK;
+}
+
+// Gradient, transported direction and new CG direction at the current point.
+static int direction_step(const RcgProblem& P, RcgBuffers& B, const ProbView& v, hipStream_t st) {
+  SRP_TRY(apply_minv(P, B, st));
+  SRP_TRY(launch_dir_partials(v, st));
+  SRP_TRY(launch_ctrl_dir(v, st));
+  SRP_TRY(launch_combine(v, st));
+  return SRP_OK;
+}
+
+struct RcgResult {
+  int status = SRP_OK;
+  int iterations = 0;
+  int passes = 0;
+  double f = 0.0, gg = 0.0;
+};
+
+static int read_ctrl(SolverCtrl* dev, SolverCtrl* host, hipStream_t st) {
+  SRP_HIP(hipMemcpyAsync(host, dev, sizeof(SolverCtrl), hipMemcpyDeviceToHost, st));
+  SRP_HIP(hipStreamSynchronize(st));
+  return SRP_OK;
+}
+
+// Runs Riemannian CG from qf_B(start).  On return B.U holds the final point.
+static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int max_iter, double tol,
+                   int check_every, int refresh_every, bool finalize, bool final_f64, double* sigma_out,
+                   RcgResult& res, hipStream_t st) {
+  const int k = P.k, nb = P.nb;
+  ProbView v = make_view(P, B);
+  for (int s = 0; s < nb; ++s) {
+    const int64_t dk = (int64_t)P.d[s] * k;
+    SRP_TRY(fill_f64(B.U[s], dk, 0.0, st));
+    SRP_TRY(fill_f64(B.Ks[s], dk, 0.0, st));
+    SRP_TRY(fill_f64(B.Kc[s], dk, 0.0, st));
+    SRP_TRY(fill_f64(B.gold[s], dk, 0.0, st));
+    SRP_TRY(copy_f64(B.xi[s], start[s], dk, st));
+  }
+  SRP_TRY(launch_ctrl_init(B.ctrl, tol, max_iter, st));
+  int passes = 0;
+  // qf_B(start): a data pass along the start point, step t = 1 from U = 0.
+  SRP_TRY(data_pass(P, B, B.xi, P.compute, nullptr, st));
+  ++passes;
+  SRP_TRY(launch_ls_partials(v, st));
+  SRP_TRY(launch_ctrl_ls(v, st));
+  SRP_TRY(launch_update(v, 0, st));
+  SRP_TRY(direction_step(P, B, v, st));
+  const int* done = &B.ctrl->done;
+  SolverCtrl hc{};
+  for (int it = 1; it <= max_iter; ++it) {
+    SRP_TRY(data_pass(P, B, B.xi, P.compute, done, st));
+    ++passes;
+    SRP_TRY(launch_ls_partials(v, st));
+    SRP_TRY(launch_ctrl_ls(v, st));
+    SRP_TRY(launch_update(v, 0, st));
+    if (refresh_every > 0 && it % refresh_every == 0) {
+      SRP_TRY(data_pass(P, B, B.U, P.compute, done, st));
+      ++passes;
+      SRP_TRY(launch_update(v, 1, st));
+    }
+    SRP_TRY(direction_step(P, B, v, st));
+    if (it % check_every == 0 || it == max_iter) {
+      SRP_TRY(read_ctrl(B.ctrl, &hc, st));
+      if (hc.done) break;
+    }
+  }
+  SRP_TRY(read_ctrl(B.ctrl, &hc, st));
+  res.status = hc.status;
+  res.iterations = hc.iter;
+  res.f = hc.f;
+  res.gg = hc.gg;
+  if (hc.status == SRP_ENOTSPD) {
+    set_error("Cholesky breakdown in the retraction (Gram not positive definite)");
+    res.passes = passes;
+    return SRP_OK;
+  }
+  if (finalize) {
+    SRP_TRY(data_pass(P, B, B.U, final_f64 ? SRP_F64 : P.compute, nullptr, st));
+    ++passes;
+    SRP_TRY(launch_update(v, 2, st));
+    SRP_TRY(launch_final_partials(v, st));
+    SRP_TRY(launch_ctrl_final(v, sigma_out, st));
+    SRP_TRY(launch_apply_rot(v, st));
+    SRP_TRY(launch_sign_fix(v, st));
+    SolverCtrl fc{};
+    SRP_TRY(read_ctrl(B.ctrl, &fc, st));
+    res.f = fc.f;
+    if (fc.status == SRP_ENOTSPD) {
+      res.status = SRP_ENOTSPD;
+      set_error("Cholesky breakdown in the final retraction");
+    }
+  }
+  res.passes = passes;
+  return SRP_OK;
+}
+
+// --------------------------------------------------------- CCA / FDA
+struct CommonArgs {
+  int k;
+  double tol;
+  srp_options opt;
+};
+
+static int sketch_any(int kind, const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out,
+                      Arena& ar, hipStream_t st) {
+  Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
+  if (kind == SRP_SRHT) return srht_run(A, dtype, n, d, s, seed, out, sub, st);
+  return countsketch_run(A, dtype, n, d, s, seed, out, sub, st);
+}
+
+static size_t sketch_ws(int kind, int64_t n, int d, int s, int dtype) {
+  return kind == SRP_SRHT ? srht_ws_bytes(n, d, s, dtype) : countsketch_ws_bytes(n, s);
+}
+
+// Shared tail of both solvers once the data, sketches and metric exist.
+static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const CommonArgs& ca, double* const* outW,
+                      double* sigma_out, srp_info* info, PhaseTimer& tm, hipStream_t st) {
+  const int k = full.k, nb = full.nb;
+  // start point for the sketched problem: qf of a seeded Gaussian matrix
+  double* start[2] = {B.Z[0], nb == 2 ? B.Z[1] : nullptr};
+  for (int s = 0; s < nb; ++s)
+    SRP_TRY(launch_gauss_fill(start[s], (int64_t)full.d[s] * k, ca.opt.seed ^ (0x5741524D53544152ull + s), st));
+  int warm_iters = 0;
+  if (ca.opt.warm_start_iters > 0) {
+    RcgResult wr;
+    // The warm start runs on the sketch; B.U then holds exact-cca(S X, S Y).
+    // Its start lives in Z, which rcg_run overwrites only after the copy.
+    SRP_TRY(rcg_run(sk, B, start, ca.opt.warm_start_iters, 1e-9, ca.opt.warm_start_iters + 1, 0, false, false,
+                    nullptr, wr, st));
+    warm_iters = wr.iterations;
+    for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
+    start[0] = outW[0];
+    start[1] = nb == 2 ? outW[1] : nullptr;
+  }
+  const double ms_warm = tm.lap_ms();
+  RcgResult r;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  B.time_passes = ca.opt.time_passes != 0;
+  B.events = &events;
+  SRP_TRY(rcg_run(full, B, start, ca.opt.max_iter, ca.tol, std::max(1, ca.opt.check_every),
+                  ca.opt.refresh_every, true, ca.opt.final_f64 != 0, sigma_out, r, st));
+  for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
+  const double ms_iter = tm.lap_ms();
+  double pass_ms = 0.0;
+  for (auto& e : events) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) pass_ms += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  B.time_passes = false;
+  B.events = nullptr;
+  if (info) {
+    info->pass_ms = pass_ms;
+    info->pass_launches = (int)events.size();
+    info->status = r.status;
+    info->iterations = r.iterations;
+    info->warm_iterations = warm_iters;
+    info->passes = r.passes;
+    info->f = r.f;
+    info->grad_norm = r.gg > 0 ? std::sqrt(r.gg) : 0.0;
+    info->ms_warm = ms_warm;
+    info->ms_iterate = ms_iter;
+  }
+  return r.status;
+}
+
+static int check_options(const srp_options& o) {
+  SRP_REQUIRE(o.sketch == SRP_COUNTSKETCH || o.sketch == SRP_SRHT, "unknown sketch kind %d", o.sketch);
+  SRP_REQUIRE(o.max_iter >= 0 && o.warm_start_iters >= 0 && o.refresh_every >= 0, "negative iteration option");
+  SRP_REQUIRE(o.pass_compute == SRP_F64 || o.pass_compute == SRP_F32 || o.pass_compute == -1,
+              "pass_compute must be SRP_F64 or SRP_F32");
+  return SRP_OK;
+}
+
+static int setup_mu(const srp_options& o, int k, double* mu_dev, hipStream_t st) {
+  double mu[KMAX];
+  for (int i = 0; i < k; ++i) mu[i] = o.mu ? o.mu[i] : (double)(k - i);
+  for (int i = 0; i < k; ++i) SRP_REQUIRE(mu[i] > 0.0 && (i == 0 || mu[i] < mu[i - 1]), "mu must be positive and strictly decreasing");
+  SRP_HIP(hipMemcpyAsync(mu_dev, mu, sizeof(double) * k, hipMemcpyHostToDevice, st));
+  SRP_HIP(hipStreamSynchronize(st));
+  return SRP_OK;
+}
+
+int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int k, double lx, double ly, int s,
+                   double tol, int dtype, const srp_options* optp, hipStream_t st, double* U, double* V,
+                   double* sigma, srp_info* info) {
+  clear_error();
+  srp_options opt;
+  srp_default_options(&opt);
+  if (optp) opt = *optp;
+  SRP_TRY(check_options(opt));
+  SRP_REQUIRE(X && Y && U && V && sigma, "null pointer argument");
+  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16, "bad dtype %d", dtype);
+  SRP_REQUIRE(n >= 1 && n < (int64_t(1) << 31), "n out of range");
+  SRP_REQUIRE(dx >= 1 && dy >= 1, "dx, dy must be positive");
+  SRP_REQUIRE(k >= 1 && k <= std::min(dx, dy) && k <= 16, "need 1 <= k <= min(dx, dy), k <= 16");
+  SRP_REQUIRE(s >= std::max(dx, dy), "sketch_size must be >= max(dx, dy)");
+  SRP_REQUIRE(lx >= 0.0 && ly >= 0.0, "lambda must be >= 0");
+  SRP_REQUIRE(tol >= 0.0, "tol must be >= 0");
+  int compute = opt.pass_compute == -1 ? (dtype == SRP_F64 ? SRP_F64 : SRP_F32) : opt.pass_compute;
+  SRP_REQUIRE(pass_limits_ok(dtype, compute, dx, dy, k, 2), "unsupported shape for the data pass (dx+dy=%d)", dx + dy);
+  const int sk_dtype = dtype == SRP_F64 ? SRP_F64 : SRP_F32;
+  SRP_REQUIRE(pass_limits_ok(sk_dtype, compute, dx, dy, k, 2), "unsupported shape for the sketch pass");
+  if (opt.sketch == SRP_SRHT) {
+    int64_t np = 2;
+    while (np < n) np <<= 1;
+    SRP_REQUIRE(np <= (int64_t(1) << 20) && s <= np, "SRHT needs s <= n' <= 2^20");
+  }
+  PhaseTimer tm(st);
+  // workspace
+  const size_t ssz = dtype_size(sk_dtype);
+  const int dd[2] = {dx, dy};
+  size_t bytes = 0;
+  bytes += 2 * (((size_t)s * std::max(dx, dy) * ssz + 255) & ~size_t(255));  // SX, SY
+  bytes += 2 * bytes_of<double>((size_t)dx * dx) + 2 * bytes_of<double>((size_t)dy * dy);  // R, Minv (x) ...
+  bytes += 2 * bytes_of<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
+  bytes += bytes_of<int>(4);
+  const size_t scratch = std::max({sketch_ws(opt.sketch, n, std::max(dx, dy), s, dtype), factor_ws_bytes(s, std::max(dx, dy))});
+  bytes += rcg_buffers_bytes(2, k, std::max<int64_t>(n, s), dd, dtype);
+  bytes += scratch + 4096;
+  Workspace W;
+  W.st = st;
+  SRP_TRY(device_alloc(&W.base, bytes, st));
+  Arena ar{(char*)W.base, bytes, 0};
+  void* SX = ar.take<char>((size_t)s * dx * ssz);
+  void* SY = ar.take<char>((size_t)s * dy * ssz);
+  double* Rx = ar.take<double>((size_t)dx * dx);
+  double* Ry = ar.take<double>((size_t)dy * dy);
+  double* Mx = ar.take<double>((size_t)dx * dx);
+  double* My = ar.take<double>((size_t)dy * dy);
+  double* Rinv = ar.take<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
+  int* flag = ar.take<int>(4);
+  RcgBuffers B{};
+  if (!flag || rcg_buffers_take(B, ar, 2, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
+    set_error("workspace layout overflow");
+    return SRP_ENOMEM;
+  }
+  SRP_TRY(setup_mu(opt, k, B.mu, st));
+  // 1. sketches (same S for X and Y)
+  SRP_TRY(sketch_any(opt.sketch, X, dtype, n, dx, s, opt.seed, SX, ar, st));
+  SRP_TRY(sketch_any(opt.sketch, Y, dtype, n, dy, s, opt.seed, SY, ar, st));
+  const double ms_sketch = tm.lap_ms();
+  // 2. metric factors
+  SRP_TRY(fill_i32(flag, 1, 0, st));
+  {
+    Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
+    SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st));
+  }
+  {
+    Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
+    SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv, My, flag, sub, st));
+  }
+  int hflag = 0;
+  SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SRP_HIP(hipStreamSynchronize(st));
+  if (hflag) {
+    set_error("sketched Gram is not positive definite (lambda = 0 with rank-deficient data?)");
+    if (info) info->status = SRP_ENOTSPD;
+    return SRP_ENOTSPD;
+  }
+  const double ms_factor = tm.lap_ms();
+  // 3. problems
+  RcgProblem full;
+  full.nb = 2; full.k = k; full.lda_cost = 0; full.dtype = dtype; full.compute = compute;
+  full.A[0] = X; full.A[1] = Y; full.n = n; full.d[0] = dx; full.d[1] = dy;
+  full.lam[0] = lx; full.lam[1] = ly; full.Minv[0] = Mx; full.Minv[1] = My;
+  RcgProblem sk = full;
+  sk.dtype = sk_dtype; sk.compute = (sk_dtype == SRP_F64) ? SRP_F64 : compute;
+  sk.A[0] = SX; sk.A[1] = SY; sk.n = s;
+  CommonArgs ca{k, tol, opt};
+  double* outW[2] = {U, V};
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->ms_sketch = ms_sketch;
+    info->ms_factor = ms_factor;
+  }
+  int rc = solve_tail(full, sk, B, ca, outW, sigma, info, tm, st);
+  SRP_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->status = rc;
+    info->ms_total = info->ms_sketch + info->ms_factor + info->ms_warm + info->ms_iterate;
+    double sum = 0.0, hs[KMAX];
+    if (hipMemcpy(hs, sigma, sizeof(double) * k, hipMemcpyDeviceToHost) == hipSuccess)
+      for (int i = 0; i < k; ++i) sum += hs[i];
+    info->objective = sum;
+  }
+  if (rc == SRP_ENOCONV) set_error("max_iter reached before the gradient tolerance");
+  return rc;
+}
+
+int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c, int k, double lam, int s,
+                   double tol, int dtype, const srp_options* optp, hipStream_t st, double* Wout, double* rho,
+                   srp_info* info) {
+  clear_error();
+  srp_options opt;
+  srp_default_options(&opt);
+  if (optp) opt = *optp;
+  SRP_TRY(check_options(opt));
+  SRP_REQUIRE(X && labels && Wout && rho, "null pointer argument");
+  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16, "bad dtype %d", dtype);
+  SRP_REQUIRE(n >= 2 && n < (int64_t(1) << 31), "n out of range");
+  SRP_REQUIRE(c >= 2 && d >= 1, "need >= 2 classes and d >= 1");
+  SRP_REQUIRE(k >= 1 && k <= std::min(c - 1, d) && k <= KMAX, "need 1 <= k <= min(c-1, d), k <= 32");
+  SRP_REQUIRE(s >= d, "sketch_size must be >= d");
+  SRP_REQUIRE(lam >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
+  int compute = opt.pass_compute == -1 ? (dtype == SRP_F64 ? SRP_F64 : SRP_F32) : opt.pass_compute;
+  SRP_REQUIRE(pass_limits_ok(dtype, compute, d, 0, k, 1), "unsupported shape for the data pass (d=%d)", d);
+  const int sk_dtype = dtype == SRP_F64 ? SRP_F64 : SRP_F32;
+  if (opt.sketch == SRP_SRHT) {
+    int64_t np = 2;
+    while (np < n) np <<= 1;
+    SRP_REQUIRE(np <= (int64_t(1) << 20) && s <= np, "SRHT needs s <= n' <= 2^20");
+  }
+  PhaseTimer tm(st);
+  const size_t esz = dtype_size(dtype), ssz = dtype_size(sk_dtype);
+  const int dd[2] = {d, 0};
+  size_t bytes = 0;
+  bytes += (((size_t)n * d * esz + 255) & ~size_t(255));          // Xhat
+  bytes += (((size_t)s * d * ssz + 255) & ~size_t(255));          // sketch
+  bytes += 4 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv, S_B
+  bytes += bytes_of<double>((size_t)c * d) + bytes_of<int>(c) + bytes_of<int>(4);
+  const size_t scratch = std::max({sketch_ws(opt.sketch, n, d, s, dtype), factor_ws_bytes(s, d),
+                                   lda_center_ws_bytes(n, d, c)});
+  bytes += rcg_buffers_bytes(1, k, std::max<int64_t>(n, s), dd, dtype);
+  bytes += scratch + 4096;
+  Workspace Wk;
+  Wk.st = st;
+  SRP_TRY(device_alloc(&Wk.base, bytes, st));
+  Arena ar{(char*)Wk.base, bytes, 0};
+  void* Xhat = ar.take<char>((size_t)n * d * esz);
+  void* SXh = ar.take<char>((size_t)s * d * ssz);
+  double* R = ar.take<double>((size_t)d * d);
+  double* Rinv = ar.take<double>((size_t)d * d);
+  double* Minv = ar.take<double>((size_t)d * d);
+  double* SB = ar.take<double>((size_t)d * d);
+  double* Yhat = ar.take<double>((size_t)c * d);
+  int* counts = ar.take<int>(c);
+  int* flag = ar.take<int>(4);
+  RcgBuffers B{};
+  if (!flag || rcg_buffers_take(B, ar, 1, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
+    set_error("workspace layout overflow");
+    return SRP_ENOMEM;
+  }
+  SRP_TRY(setup_mu(opt, k, B.mu, st));
+  // 1. centring, S_B = Yhat^T Yhat
+  {
+    Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
+    SRP_TRY(lda_center_run(X, labels, dtype, n, d, c, Xhat, Yhat, counts, flag + 1, sub, st));
+  }
+  {
+    GemmArgs g{};
+    g.m = d; g.n = d; g.kk = c; g.alpha = 1.0; g.beta = 0.0;
+    g.A = Yhat; g.lda = d; g.ta = true;
+    g.B = Yhat; g.ldb = d; g.tb = false;
+    g.C = SB; g.ldc = d;
+    SRP_TRY(gemm_f64(g, st));
+  }
+  int hc[64];
+  int hbad = 0;
+  SRP_HIP(hipMemcpyAsync(&hbad, flag + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  SRP_HIP(hipMemcpyAsync(hc, counts, sizeof(int) * std::min(c, 64), hipMemcpyDeviceToHost, st));
+  SRP_HIP(hipStreamSynchronize(st));
+  SRP_REQUIRE(!hbad, "label out of range [0, %d)", c);
+  for (int q = 0; q < std::min(c, 64); ++q) SRP_REQUIRE(hc[q] > 0, "class %d is empty", q);
+  // 2. sketch of Xhat and metric factor
+  SRP_TRY(sketch_any(opt.sketch, Xhat, dtype, n, d, s, opt.seed, SXh, ar, st));
+  const double ms_sketch = tm.lap_ms();
+  SRP_TRY(fill_i32(flag, 1, 0, st));
+  {
+    Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
+    SRP_TRY(sketch_factor_run(SXh, sk_dtype, s, d, lam, R, Rinv, Minv, flag, sub, st));
+  }
+  int hflag = 0;
+  SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SRP_HIP(hipStreamSynchronize(st));
+  if (hflag) {
+    set_error("sketched Gram is not positive definite (lambda = 0 with rank-deficient data?)");
+    if (info) info->status = SRP_ENOTSPD;
+    return SRP_ENOTSPD;
+  }
+  const double ms_factor = tm.lap_ms();
+  RcgProblem full;
+  full.nb = 1; full.k = k; full.lda_cost = 1; full.dtype = dtype; full.compute = compute;
+  full.A[0] = Xhat; full.n = n; full.d[0] = d; full.lam[0] = lam; full.Minv[0] = Minv; full.SB = SB;
+  RcgProblem sk = full;
+  sk.dtype = sk_dtype; sk.compute = (sk_dtype == SRP_F64) ? SRP_F64 : compute;
+  sk.A[0] = SXh; sk.n = s;
+  CommonArgs ca{k, tol, opt};
+  double* outW[2] = {Wout, nullptr};
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->ms_sketch = ms_sketch;
+    info->ms_factor = ms_factor;
+  }
+  int rc = solve_tail(full, sk, B, ca, outW, rho, info, tm, st);
+  SRP_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->status = rc;
+    info->ms_total = info->ms_sketch + info->ms_factor + info->ms_warm + info->ms_iterate;
+    double sum = 0.0, hs[KMAX];
+    if (hipMemcpy(hs, rho, sizeof(double) * k, hipMemcpyDeviceToHost) == hipSuccess)
+      for (int i = 0; i < k; ++i) sum += hs[i];
+    info->objective = sum;
+  }
+  if (rc == SRP_ENOCONV) set_error("max_iter reached before the gradient tolerance");
+  return rc;
+}
+
+}  // namespace srp

@@ -1,0 +1,65 @@
+// Internal launch interface between the host driver and the HIP kernels.
+#pragma once
+#include "common.hpp"
+
+namespace srp {
+
+int fill_i32(int* p, int64_t count, int v, hipStream_t st);
+int fill_f64(double* p, int64_t count, double v, hipStream_t st);
+int copy_f64(double* dst, const double* src, int64_t count, hipStream_t st);
+
+// ---------------------------------------------------------- sketches
+size_t countsketch_ws_bytes(int64_t n, int s);
+int countsketch_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out,
+                    Arena& ws, hipStream_t st);
+size_t srht_ws_bytes(int64_t n, int d, int s, int dtype);
+int srht_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, Arena& ws,
+             hipStream_t st);
+int srht_rows_run(int64_t n, int s, uint64_t seed, int64_t* rows, Arena& ws, hipStream_t st);
+
+// ---------------------------------------------------- FP64 dense blocks
+// C = alpha * op(A) op(B) + beta * C on row-major double matrices (A may be
+// float).  op(A) is m x kk (A is m x kk, or kk x m when ta), op(B) is kk x n.
+// upper_only skips 64x64 output tiles strictly below the block diagonal.
+// ksplit > 1 splits kk into chunks written to C + z * c_split_stride (beta
+// must be 0 then).
+struct GemmArgs {
+  int m, n, kk;
+  double alpha, beta;
+  const void* A; int64_t lda; bool ta; bool a_f32;
+  const void* B; int64_t ldb; bool tb; bool b_f32;
+  double* C; int64_t ldc;
+  bool upper_only = false;
+  int ksplit = 1;
+  int64_t c_split_stride = 0;
+};
+int gemm_f64(const GemmArgs& g, hipStream_t st);
+// C (m x nc) = A (m x m) B (m x nc) for nc <= 64 (row-major, FP64).
+int gemm_skinny_f64(int m, int nc, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                    int64_t ldc, hipStream_t st);
+// out[i] = sum_z parts[z * stride + i] (+ diag_add on the diagonal of a
+// d x d matrix when d > 0), for count elements.
+int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count, double* out,
+                  int d, double diag_add, hipStream_t st);
+
+// Gram of a sketch, Cholesky and inverse: R^T R = SA^T SA + lambda I.
+size_t factor_ws_bytes(int s, int d);
+int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
+                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st);
+
+// --------------------------------------------------------- data pass
+// J_b = A_b^T [A_0 W_0 | A_1 W_1] (see srp_gram_pass).  Arithmetic in
+// `compute` (SRP_F64 / SRP_F32).
+size_t pass_ws_bytes(int64_t n, int d0, int d1, int k, int compute);
+int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1,
+                  int k, const double* W0, const double* W1, double* J0, double* J1, const int* done,
+                  Arena& ws, hipStream_t st, hipEvent_t after_pass = nullptr);
+// FDA centring (Section 5.1): class counts and FP64 sums, Yhat rows
+// sqrt(n_k)(m_k - m), and the materialised Xhat = X - m_{y_i} in the data
+// type.  Returns SRP_EINVAL (via *bad) for labels out of range.
+size_t lda_center_ws_bytes(int64_t n, int d, int c);
+int lda_center_run(const void* X, const int32_t* labels, int dtype, int64_t n, int d, int c, void* Xhat,
+                   double* Yhat, int* counts, int* bad, Arena& ws, hipStream_t st);
+int pass_limits_ok(int dtype, int compute, int d0, int d1, int k, int nblocks);
+
+}  // namespace srp

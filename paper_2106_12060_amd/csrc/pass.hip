@@ -1,0 +1,410 @@
+// Fused tall-skinny data pass: for data blocks A_0 (n x d0), A_1 (n x d1)
+// and directions W_0, W_1 (d_b x k) compute, in one read of the data,
+//     J_b = A_b^T [A_0 W_0 | A_1 W_1]        (d_b x NB k).
+// These are the products with the data matrices that every Riemannian
+// component of Table 1 needs (X^T X U, X^T Y V, ...; costs in Table costs:
+// O(n d p) per product).
+//
+// Work split: a workgroup of 8 waves streams 16-row blocks of [A_0 | A_1].
+// Each row block is handled by a PAIR of workgroups (block indices 8 apart,
+// so both run on the same XCD and the second read of the block is served
+// by that XCD's L2): both form the full P from their LDS copy, and each
+// accumulates A_b^T [P_0 | P_1] for half of the columns, which halves the
+// accumulator registers a wave must keep.
+// The block is staged in LDS (row-major, row pitch = 4 mod 64 elements so
+// both access patterns below are bank-conflict free); while the matrix
+// cores work on block i, the global loads of the workgroup's next block are
+// already in flight into registers.  Columns are cut into 16-wide tiles;
+// wave w owns tiles w, w+8, ...  For each block a wave
+//   (b) accumulates its tiles' share of P_b = A_b W_b (16 x k) on the matrix
+//       cores (A-operand lane: row = lane%16, column = 4 step + lane/16),
+//   (c) the 8 partial P's are summed through LDS,
+//   (d) accumulates its tiles' rows of A_b^T [P_0 | P_1] (A-operand lane:
+//       column = lane%16, row = 4 (lane/16) + step).
+// Each workgroup keeps its accumulators in registers over all its row
+// blocks and writes one partial; a second kernel sums the partials in a
+// fixed order (deterministic, no atomics).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace srp {
+
+constexpr int kPassWaves = 8;
+constexpr int kPassThreads = 64 * kPassWaves;
+constexpr int kPassLds = 150 * 1024;   // LDS budget of the row-block stage
+
+// Largest d0 + d1 per compute type, and loads per row per thread.
+template <class CT> struct PassCfg;
+// jpf of the jpr 512-column chunks of a row block are prefetched into
+// registers during the previous block's math; the rest load on demand.
+template <> struct PassCfg<float> { static constexpr int dmax = 2048; static constexpr int jpr = 4; static constexpr int jpf = 4; };
+template <> struct PassCfg<double> { static constexpr int dmax = 896; static constexpr int jpr = 2; static constexpr int jpf = 2; };
+
+__host__ __device__ constexpr int pass_pitch(int D) { return ((D + 63) / 64) * 64 + 4; }
+
+// Pack a double d x k direction into a zero-padded (ceil16(d) x KT*16) CT
+// matrix.
+template <class CT>
+__global__ void k_pack_dir(const double* __restrict__ W, int d, int k, int dpad, int kpad, CT* __restrict__ Wp) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)dpad * kpad) return;
+  const int r = (int)(i / kpad), c = (int)(i % kpad);
+  Wp[i] = (r < d && c < k) ? (CT)W[(int64_t)r * k + c] : CT(0);
+}
+
+// Buffer loads: a scalar base (the row block) plus a 32-bit lane offset;
+// offsets at or past num_records read as zero, which pads the last row
+// block and masked lanes without branches.
+constexpr uint32_t kBufDword3 = 0x00020000u;   // raw buffer, gfx9 family
+constexpr int kOob = 0x40000000;                 // lane offset that always reads zero
+
+template <class T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ bf16 buf_load<bf16>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(bf16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+template <class CT, class DT> __device__ __forceinline__ CT cvt(DT v);
+template <> __device__ __forceinline__ float cvt<float, float>(float v) { return v; }
+template <> __device__ __forceinline__ float cvt<float, bf16>(bf16 v) { return __bfloat162float(v); }
+template <> __device__ __forceinline__ double cvt<double, double>(double v) { return v; }
+template <> __device__ __forceinline__ double cvt<double, float>(float v) { return (double)v; }
+template <> __device__ __forceinline__ double cvt<double, bf16>(bf16 v) { return (double)__bfloat162float(v); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const int nrec = (int)(bytes < 0x7ffff000ll ? bytes : 0x7ffff000ll);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, (int)kBufDword3);
+}
+
+constexpr int kPassSplit = 2;   // column halves per row block
+constexpr int kXcds = 8;
+
+template <class DT, class CT, int NB, int KT>
+__global__ void __launch_bounds__(kPassThreads) k_pass(const DT* __restrict__ A0, const DT* __restrict__ A1,
+                                                       int64_t n, int d0, int d1, int k,
+                                                       const CT* __restrict__ Wp0, const CT* __restrict__ Wp1,
+                                                       int nrb, CT* __restrict__ partial,
+                                                       const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int DMAX = PassCfg<CT>::dmax;
+  constexpr int JPR = PassCfg<CT>::jpr;
+  constexpr int JPF = PassCfg<CT>::jpf;
+  constexpr int TPW = (DMAX / 16 + kPassWaves * kPassSplit - 1) / (kPassWaves * kPassSplit);
+  constexpr int NT = NB * KT;
+  constexpr int KP = KT * 16;
+  using acc_t = typename Acc4<CT>::type;
+  extern __shared__ unsigned char pass_smem[];
+  const int D = d0 + (NB == 2 ? d1 : 0);
+  const int pitch = pass_pitch(D);
+  CT* xs = reinterpret_cast<CT*>(pass_smem);                 // [16][pitch]
+  CT* red = xs + 16 * pitch;                                  // [waves][NT][256]
+  CT* pfull = red + kPassWaves * NT * 256;                    // [NT][16][17]
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int T0 = (d0 + 15) >> 4;
+  const int TT = T0 + (NB == 2 ? ((d1 + 15) >> 4) : 0);
+  // pair mapping: XCD x, half h, group q  ->  row group rg
+  const int bx = blockIdx.x;
+  const int xcd = bx % kXcds, half = (bx / kXcds) % kPassSplit, grp = bx / (kXcds * kPassSplit);
+  const int rg = grp * kXcds + xcd;
+  const int ngroups = gridDim.x / kPassSplit;
+  const int TH = (TT + kPassSplit - 1) / kPassSplit;     // tiles per half
+  const int tbeg = half * TH, tend = min(TT, tbeg + TH);
+  const __amdgpu_buffer_rsrc_t wr0 = make_rsrc(Wp0, (int64_t)((d0 + 15) / 16 * 16) * KP * sizeof(CT));
+  const __amdgpu_buffer_rsrc_t wr1 =
+      make_rsrc(NB == 2 ? Wp1 : Wp0, (int64_t)((((NB == 2 ? d1 : d0) + 15) / 16) * 16) * KP * sizeof(CT));
+  const int wvoff = (g * KP + l16) * (int)sizeof(CT);
+
+  acc_t acc[TPW][NT];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  // Row r of the block gets its own buffer resource (scalar), holding
+  // exactly the d_b elements of that row, or none past row n; a lane reads
+  // column c of [A_0 | A_1] with one lane offset for all rows, and every
+  // out-of-row, out-of-block or out-of-matrix element reads as zero.
+  auto row_rsrc = [&](const DT* A, int db, int64_t row) __attribute__((always_inline)) {
+    return make_rsrc(A + row * db, row < n ? (int64_t)db * (int64_t)sizeof(DT) : 0);
+  };
+  auto load_elem = [&](int64_t row, int j) __attribute__((always_inline)) -> DT {
+    const int cb = kPassThreads * j;        // uniform chunk start
+    const int c = cb + tid;
+    const int v0 = c * (int)sizeof(DT);
+    if (NB == 1 || cb + kPassThreads <= d0) return buf_load<DT>(row_rsrc(A0, d0, row), v0, 0);
+    const int v1 = (c - d0) * (int)sizeof(DT);   // negative = out of range
+    if (cb >= d0) return buf_load<DT>(row_rsrc(A1, d1, row), v1, 0);
+    const DT x0 = buf_load<DT>(row_rsrc(A0, d0, row), v0, 0);
+    const DT x1 = buf_load<DT>(row_rsrc(A1, d1, row), v1, 0);
+    return (c < d0) ? x0 : x1;
+  };
+  DT pf[16][JPF];
+  auto prefetch = [&](int rbk) __attribute__((always_inline)) {
+    const int64_t r0 = (int64_t)rbk * 16;
+#pragma unroll
+    for (int j = 0; j < JPF; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) pf[r][j] = load_elem(r0 + r, j);
+  };
+
+  int rb = rg;
+  if (rb < nrb) prefetch(rb);
+  for (; rb < nrb; rb += ngroups) {
+    __syncthreads();   // previous block fully consumed
+#pragma unroll
+    for (int j = 0; j < JPF; ++j) {
+      const int c = tid + kPassThreads * j;
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (c < pitch) xs[r * pitch + c] = (c < D) ? cvt<CT>(pf[r][j]) : CT(0);
+    }
+    if (JPF < JPR) {
+#pragma unroll
+      for (int j = JPF; j < JPR; ++j) {
+        const int c = tid + kPassThreads * j;
+        if (kPassThreads * j < pitch) {
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const DT v = load_elem((int64_t)rb * 16 + r, j);
+            if (c < pitch) xs[r * pitch + c] = (c < D) ? cvt<CT>(v) : CT(0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (rb + ngroups < nrb) prefetch(rb + ngroups);   // in flight during the math
+    // (b) P_b partials
+    acc_t pacc[NB][KT];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) pacc[b][kt] = acc_t{0, 0, 0, 0};
+    for (int t = w; t < TT; t += kPassWaves) {
+      {
+        const bool b1 = (NB == 2) && (t >= T0);
+        const int ct = b1 ? t - T0 : t;
+        const int cbase = (b1 ? d0 : 0) + ct * 16;   // column of the tile in xs
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const CT a = xs[l16 * pitch + cbase + 4 * s2 + g];
+#pragma unroll
+          for (int kt = 0; kt < KT; ++kt) {
+            const int soff = ((ct * 16 + 4 * s2) * KP + kt * 16) * (int)sizeof(CT);
+            if (b1) {
+              const CT bw = buf_load<CT>(wr1, wvoff + soff, 0);
+              pacc[NB - 1][kt] = mfma16x16x4(a, bw, pacc[NB - 1][kt]);
+            } else {
+              const CT bw = buf_load<CT>(wr0, wvoff + soff, 0);
+              pacc[0][kt] = mfma16x16x4(a, bw, pacc[0][kt]);
+            }
+          }
+        }
+      }
+    }
+    // (c) reduce P over waves
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          red[(w * NT + b * KT + kt) * 256 + acc_row<CT>(lane, r) * 16 + l16] = pacc[b][kt][r];
+    __syncthreads();
+    for (int e = tid; e < NT * 256; e += kPassThreads) {
+      const int nt = e >> 8, q = e & 255;
+      CT v = CT(0);
+#pragma unroll
+      for (int ww = 0; ww < kPassWaves; ++ww) v += red[(ww * NT + nt) * 256 + q];
+      pfull[nt * 272 + (q >> 4) * 17 + (q & 15)] = v;
+    }
+    __syncthreads();
+    // (d) A_b^T [P_0 | P_1] for this workgroup's half of the tiles
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+      const int t = tbeg + w + kPassWaves * i;
+      if (t < tend) {
+        const bool b1 = (NB == 2) && (t >= T0);
+        const int cbase = (b1 ? d0 + (t - T0) * 16 : t * 16) + l16;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const CT a = xs[(4 * g + s) * pitch + cbase];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+            acc[i][nt] = mfma16x16x4(a, pfull[nt * 272 + (4 * g + s) * 17 + l16], acc[i][nt]);
+        }
+      }
+    }
+  }
+  // epilogue: this workgroup's partial (rows = concatenated columns of A)
+  const int W_out = NB * k;
+  CT* out = partial + (int64_t)rg * D * W_out;
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) {
+    const int t = tbeg + w + kPassWaves * i;
+    if (t < tend) {
+      const bool b1 = (NB == 2) && (t >= T0);
+      const int db = b1 ? d1 : d0;
+      const int ct = b1 ? t - T0 : t;
+      const int rowbase = b1 ? d0 : 0;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int bsrc = nt / KT, kt = nt % KT;
+        const int col = kt * 16 + l16;
+        if (col < k) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int c = ct * 16 + acc_row<CT>(lane, r);
+            if (c < db) out[(int64_t)(rowbase + c) * W_out + bsrc * k + col] = acc[i][nt][r];
+          }
+        }
+      }
+    }
+  }
+}
+
+template <class CT> static size_t pass_lds_bytes(int D, int NT) {
+  return ((size_t)16 * pass_pitch(D) + (size_t)kPassWaves * NT * 256 + (size_t)NT * 272) * sizeof(CT);
+}
+
+// J_b[c][j] = sum over partials, in a fixed order: each of 4 thread groups
+// sums a contiguous quarter of the partials, then the quarters are added.
+template <class CT>
+__global__ void __launch_bounds__(256) k_pass_reduce(const CT* __restrict__ partial, int nparts, int d0, int d1,
+                                                     int W_out, double* __restrict__ J0, double* __restrict__ J1,
+                                                     const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double q4[4][64];
+  const int64_t Dtot = d0 + d1;
+  const int64_t count = Dtot * W_out;
+  const int grp = threadIdx.x >> 6, lanei = threadIdx.x & 63;
+  const int64_t i = blockIdx.x * 64ll + lanei;
+  const int per = (nparts + 3) / 4;
+  const int z0 = grp * per, z1 = min(nparts, z0 + per);
+  double v = 0.0;
+  if (i < count)
+    for (int z = z0; z < z1; ++z) v += (double)partial[(int64_t)z * count + i];
+  q4[grp][lanei] = v;
+  __syncthreads();
+  if (grp == 0 && i < count) {
+    const double tot = ((q4[0][lanei] + q4[1][lanei]) + q4[2][lanei]) + q4[3][lanei];
+    const int64_t row = i / W_out, col = i % W_out;
+    if (row < d0) J0[row * W_out + col] = tot;
+    else J1[(row - d0) * W_out + col] = tot;
+  }
+}
+
+int pass_limits_ok(int dtype, int compute, int d0, int d1, int k, int nblocks) {
+  const int D = d0 + (nblocks == 2 ? d1 : 0);
+  const bool f64 = (compute == SRP_F64);
+  if (dtype == SRP_F64 && !f64) return 0;
+  if (nblocks == 2 && k > 16) return 0;
+  if (nblocks == 1 && k > 32) return 0;
+  const int NT = nblocks * ((k + 15) / 16);
+  if (f64) {
+    if (D > PassCfg<double>::dmax || pass_lds_bytes<double>(D, NT) > (size_t)kPassLds) return 0;
+  } else {
+    if (D > PassCfg<float>::dmax || pass_lds_bytes<float>(D, NT) > (size_t)kPassLds) return 0;
+  }
+  return 1;
+}
+
+// Number of row groups (each served by kPassSplit workgroups); a multiple
+// of the XCD count so that the pair of a group shares an XCD.
+static int pass_groups(int64_t n) {
+  const int64_t nrb = (n + 15) / 16;
+  int64_t g = num_cus() / kPassSplit;
+  if (g > nrb) g = nrb;
+  g = ((g + kXcds - 1) / kXcds) * kXcds;
+  if (g < kXcds) g = kXcds;
+  return (int)g;
+}
+
+size_t pass_ws_bytes(int64_t n, int d0, int d1, int k, int compute) {
+  const size_t cs = compute == SRP_F64 ? 8 : 4;
+  const int KT = (k + 15) / 16;
+  const int nb = d1 > 0 ? 2 : 1;
+  const size_t D = (size_t)d0 + (nb == 2 ? d1 : 0);
+  const size_t wp = (((size_t)(d0 + 15) / 16 * 16) + ((size_t)(d1 + 15) / 16 * 16)) * KT * 16 * cs;
+  return ((wp + 1023) & ~size_t(255)) + (((size_t)pass_groups(n) * D * nb * k * cs + 255) & ~size_t(255));
+}
+
+template <class DT, class CT, int NB, int KT>
+static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, int k, const double* W0,
+                       const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
+                       hipEvent_t after_pass) {
+  const int dp0 = (d0 + 15) / 16 * 16, dp1 = NB == 2 ? (d1 + 15) / 16 * 16 : 0;
+  const int KP = KT * 16;
+  CT* Wp0 = ws.take<CT>((size_t)dp0 * KP);
+  CT* Wp1 = NB == 2 ? ws.take<CT>((size_t)dp1 * KP) : nullptr;
+  const int groups = pass_groups(n);
+  const int grid = groups * kPassSplit;
+  const int Dtot = d0 + (NB == 2 ? d1 : 0);
+  CT* part = ws.take<CT>((size_t)groups * Dtot * NB * k);
+  if (!Wp0 || !part || (NB == 2 && !Wp1)) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
+  hipLaunchKernelGGL((k_pack_dir<CT>), dim3((dp0 * KP + 255) / 256), dim3(256), 0, st, W0, d0, k, dp0, KP, Wp0);
+  SRP_LAUNCH_CHECK();
+  if (NB == 2) {
+    hipLaunchKernelGGL((k_pack_dir<CT>), dim3((dp1 * KP + 255) / 256), dim3(256), 0, st, W1, d1, k, dp1, KP, Wp1);
+    SRP_LAUNCH_CHECK();
+  }
+  const int nrb = (int)((n + 15) / 16);
+  const size_t lds = pass_lds_bytes<CT>(Dtot, NB * KT);
+  static bool attr_done = false;   // per template instance
+  if (!attr_done) {
+    SRP_HIP(hipFuncSetAttribute((const void*)k_pass<DT, CT, NB, KT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kPassLds));
+    attr_done = true;
+  }
+  hipLaunchKernelGGL((k_pass<DT, CT, NB, KT>), dim3(grid), dim3(kPassThreads), lds, st, A0, A1, n, d0,
+                     NB == 2 ? d1 : 0, k, Wp0, Wp1, nrb, part, done);
+  SRP_LAUNCH_CHECK();
+  if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
+  const int64_t count = (int64_t)Dtot * NB * k;
+  hipLaunchKernelGGL((k_pass_reduce<CT>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, groups, d0,
+                     NB == 2 ? d1 : 0, NB * k, J0, J1, done);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+template <class DT, class CT>
+static int pass_dispatch_k(const DT* A0, const DT* A1, int64_t n, int d0, int d1, int k, const double* W0,
+                           const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
+                           hipEvent_t ev) {
+  if (A1) return pass_launch<DT, CT, 2, 1>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev);
+  if (k <= 16) return pass_launch<DT, CT, 1, 1>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev);
+  return pass_launch<DT, CT, 1, 2>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev);
+}
+
+int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1, int k,
+                  const double* W0, const double* W1, double* J0, double* J1, const int* done, Arena& ws,
+                  hipStream_t st, hipEvent_t after_pass) {
+  const int nb = A1 ? 2 : 1;
+  if (!pass_limits_ok(dtype, compute, d0, d1, k, nb)) {
+    set_error("gram_pass: unsupported shape (d0=%d d1=%d k=%d dtype=%d compute=%d)", d0, d1, k, dtype, compute);
+    return SRP_EINVAL;
+  }
+  if (compute == SRP_F64) {
+    switch (dtype) {
+      case SRP_F64: return pass_dispatch_k<double, double>((const double*)A0, (const double*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
+      case SRP_F32: return pass_dispatch_k<float, double>((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
+      case SRP_BF16: return pass_dispatch_k<bf16, double>((const bf16*)A0, (const bf16*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
+    }
+  } else {
+    switch (dtype) {
+      case SRP_F32: return pass_dispatch_k<float, float>((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
+      case SRP_BF16: return pass_dispatch_k<bf16, float>((const bf16*)A0, (const bf16*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
+    }
+  }
+  set_error("gram_pass: bad dtype/compute (%d/%d)", dtype, compute);
+  return SRP_EINVAL;
+}
+
+}  // namespace srp

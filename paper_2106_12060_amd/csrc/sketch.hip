@@ -1,0 +1,494 @@
+// Sketching transforms on the GPU: CountSketch (Section 3) and the
+// subsampled randomized Hadamard transform (Appendix A, Definition SRHT).
+//
+// CountSketch: (S A)_b = sum over rows i with h(i) = b of g(i) A_i.  Rows are
+// bucketed by a counting sort (count, scan, fill), each bucket's row list is
+// put in ascending order, and one workgroup per bucket streams its rows with
+// coalesced row reads and sums them in that fixed order, so the result is
+// bitwise reproducible.
+//
+// SRHT: S A = sqrt(n'/s) R H D [A; 0] with the normalised Hadamard matrix,
+// i.e. (S A)_j = s^-1/2 sum_i (-1)^popcount(r_j & i) D_i A_i.  With
+// n' = A_blocks * B and i = a B + b, r = alpha B + beta the sign factorises,
+// so level 1 takes the length-B Walsh-Hadamard transform inside every block
+// of B consecutive rows (in LDS), and level 2 forms each sampled output row
+// as a +-sum over the blocks of level-1 row beta.  Only the s sampled rows
+// are ever formed.  The row sample (s smallest SplitMix64 keys) is found by
+// a 4-round 16-bit radix select and an order-preserving compaction.
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <cmath>
+
+namespace srp {
+
+// ------------------------------------------------------------ utilities
+__global__ void k_fill_i32(int* p, int64_t count, int v) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+int fill_i32(int* p, int64_t count, int v, hipStream_t st) {
+  if (count <= 0) return SRP_OK;
+  int64_t blocks = (count + 255) / 256;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, st, p, count, v);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// Exclusive scan of `count` ints (single workgroup of 1024 threads).
+// Writes offsets[0..count] (offsets[count] = total) and, if cursor != NULL,
+// a copy of offsets[0..count) into cursor.
+__global__ void __launch_bounds__(1024) k_scan_excl(const int* in, int count, int* offsets, int* cursor) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x, T = blockDim.x;
+  const int per = (count + T - 1) / T;
+  const int b0 = min(count, t * per), b1 = min(count, b0 + per);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += in[b];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < T; off <<= 1) {
+    int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = (t == 0) ? 0 : part[t - 1];
+  for (int b = b0; b < b1; ++b) {
+    offsets[b] = run;
+    if (cursor) cursor[b] = run;
+    run += in[b];
+  }
+  if (t == T - 1) offsets[count] = part[T - 1];
+}
+
+// -------------------------------------------------------- CountSketch
+__global__ void k_cs_count(int64_t n, int s, uint64_t seed, int* counts) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&counts[cs_bucket(splitmix64(seed, (uint64_t)i), s)], 1);
+}
+
+__global__ void k_cs_fill(int64_t n, int s, uint64_t seed, int* cursor, int* list) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) {
+    int b = cs_bucket(splitmix64(seed, (uint64_t)i), s);
+    int pos = atomicAdd(&cursor[b], 1);
+    list[pos] = (int)i;
+  }
+}
+
+// Rank sort of every bucket's rows into ascending order (rows are distinct).
+__global__ void k_cs_sort(const int* offsets, const int* list, int* sorted) {
+  const int b = blockIdx.x;
+  const int beg = offsets[b], cnt = offsets[b + 1] - beg;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const int v = list[beg + e];
+    int r = 0;
+    for (int j = 0; j < cnt; ++j) r += (list[beg + j] < v);
+    sorted[beg + r] = v;
+  }
+}
+
+// One workgroup per bucket; each thread owns up to CPT columns.
+template <class T, class Acc, int CPT>
+__global__ void __launch_bounds__(256) k_cs_gather(const T* __restrict__ A, int d, uint64_t seed,
+                                                   const int* __restrict__ offsets,
+                                                   const int* __restrict__ sorted, Acc* __restrict__ out,
+                                                   int col_base) {
+  const int b = blockIdx.x;
+  const int beg = offsets[b], cnt = offsets[b + 1] - beg;
+  const int c0 = col_base + threadIdx.x;
+  Acc acc[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) acc[j] = Acc(0);
+  for (int e = 0; e < cnt; ++e) {
+    const int row = sorted[beg + e];
+    const Acc g = (Acc)cs_sign(splitmix64(seed, (uint64_t)row));
+    const T* Ar = A + (int64_t)row * d;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int c = c0 + j * (int)blockDim.x;
+      if (c < d) acc[j] += g * load_as<Acc>(Ar + c);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) {
+    const int c = c0 + j * (int)blockDim.x;
+    if (c < d) out[(int64_t)b * d + c] = acc[j];
+  }
+}
+
+size_t countsketch_ws_bytes(int64_t n, int s) {
+  return 3 * bytes_of<int>(s + 1) + 2 * bytes_of<int>(n);
+}
+
+template <class T, class Acc>
+static int cs_gather_launch(const T* A, int d, int s, uint64_t seed, const int* offsets,
+                            const int* sorted, Acc* out, hipStream_t st) {
+  const int threads = d >= 256 ? 256 : ((d + 63) / 64) * 64;
+  constexpr int CPT = 8;
+  for (int col = 0; col < d; col += threads * CPT) {
+    hipLaunchKernelGGL((k_cs_gather<T, Acc, CPT>), dim3(s), dim3(threads), 0, st, A, d, seed,
+                       offsets, sorted, out, col);
+    SRP_LAUNCH_CHECK();
+  }
+  return SRP_OK;
+}
+
+int countsketch_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out,
+                    Arena& ws, hipStream_t st) {
+  int* counts = ws.take<int>(s + 1);
+  int* offsets = ws.take<int>(s + 1);
+  int* cursor = ws.take<int>(s + 1);
+  int* list = ws.take<int>(n);
+  int* sorted = ws.take<int>(n);
+  if (!sorted) { set_error("countsketch: workspace too small"); return SRP_ENOMEM; }
+  SRP_TRY(fill_i32(counts, s, 0, st));
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_cs_count, dim3(nb), dim3(256), 0, st, n, s, seed, counts);
+  SRP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, counts, s, offsets, cursor);
+  SRP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_cs_fill, dim3(nb), dim3(256), 0, st, n, s, seed, cursor, list);
+  SRP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_cs_sort, dim3(s), dim3(64), 0, st, offsets, list, sorted);
+  SRP_LAUNCH_CHECK();
+  switch (dtype) {
+    case SRP_F64:
+      return cs_gather_launch((const double*)A, d, s, seed, offsets, sorted, (double*)out, st);
+    case SRP_F32:
+      return cs_gather_launch((const float*)A, d, s, seed, offsets, sorted, (float*)out, st);
+    case SRP_BF16:
+      return cs_gather_launch((const bf16*)A, d, s, seed, offsets, sorted, (float*)out, st);
+  }
+  set_error("countsketch: bad dtype %d", dtype);
+  return SRP_EINVAL;
+}
+
+// --------------------------------------------------------------- SRHT
+struct SelectState {
+  uint64_t prefix;   // digits fixed so far
+  int need;          // how many keys still to take at or below the prefix
+  int pad;
+};
+
+__global__ void k_sel_init(SelectState* st, int s) {
+  st->prefix = 0;
+  st->need = s;
+}
+
+// Histogram of 16-bit digit `round` (0 = most significant) over keys whose
+// higher digits equal the prefix found so far.
+__global__ void k_sel_hist(int64_t n_pad, uint64_t seed, int round, const SelectState* st, int* hist) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  const uint64_t key = splitmix64(seed, (uint64_t)i);
+  if (round > 0 && (key >> (64 - 16 * round)) != st->prefix) return;
+  const int digit = (int)((key >> (48 - 16 * round)) & 0xFFFFull);
+  atomicAdd(&hist[digit], 1);
+}
+
+// Find the digit holding the need-th smallest remaining key; zero hist.
+__global__ void __launch_bounds__(1024) k_sel_pick(int* hist, SelectState* st) {
+  __shared__ int part[1024];
+  __shared__ int found_digit, found_before;
+  const int t = threadIdx.x;
+  int sum = 0;
+  for (int j = 0; j < 64; ++j) sum += hist[t * 64 + j];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  const int need = st->need;
+  const int before = (t == 0) ? 0 : part[t - 1];
+  if (before < need && need <= part[t]) {
+    int run = before;
+    for (int j = 0; j < 64; ++j) {
+      const int c = hist[t * 64 + j];
+      if (run + c >= need) { found_digit = t * 64 + j; found_before = run; break; }
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < 64; ++j) hist[t * 64 + j] = 0;
+  if (t == 0) {
+    st->prefix = (st->prefix << 16) | (uint64_t)found_digit;
+    st->need = need - found_before;
+  }
+}
+
+constexpr int kSelChunk = 1024;
+
+__global__ void __launch_bounds__(256) k_sel_count(int64_t n_pad, uint64_t seed, const SelectState* st, int* counts) {
+  __shared__ int red[256];
+  const int64_t base = (int64_t)blockIdx.x * kSelChunk;
+  const uint64_t T = st->prefix;
+  int c = 0;
+  for (int j = threadIdx.x; j < kSelChunk; j += 256) {
+    const int64_t i = base + j;
+    if (i < n_pad && splitmix64(seed, (uint64_t)i) <= T) ++c;
+  }
+  red[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_sel_write(int64_t n_pad, uint64_t seed, const SelectState* st,
+                                                   const int* offsets, int64_t* rows) {
+  __shared__ int pre[256];
+  const int64_t base = (int64_t)blockIdx.x * kSelChunk;
+  const uint64_t T = st->prefix;
+  // each thread owns 4 consecutive indices
+  int flags[4];
+  int c = 0;
+  for (int j = 0; j < 4; ++j) {
+    const int64_t i = base + threadIdx.x * 4 + j;
+    flags[j] = (i < n_pad && splitmix64(seed, (uint64_t)i) <= T) ? 1 : 0;
+    c += flags[j];
+  }
+  pre[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int v = ((int)threadIdx.x >= off) ? pre[threadIdx.x - off] : 0;
+    __syncthreads();
+    pre[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int pos = offsets[blockIdx.x] + pre[threadIdx.x] - c;
+  for (int j = 0; j < 4; ++j)
+    if (flags[j]) rows[pos++] = base + threadIdx.x * 4 + j;
+}
+
+struct SrhtGeom {
+  int64_t n_pad;
+  int m, A, B, A_eff;
+};
+
+static SrhtGeom srht_geom(int64_t n) {
+  SrhtGeom g;
+  g.m = 1;
+  while ((int64_t(1) << g.m) < n) ++g.m;
+  g.n_pad = int64_t(1) << g.m;
+  const int mb = (g.m + 1) / 2;
+  g.B = 1 << mb;
+  g.A = 1 << (g.m - mb);
+  g.A_eff = (int)((n + g.B - 1) / g.B);
+  return g;
+}
+
+static int srht_select_rows(int64_t n_pad, int s, uint64_t seed, int64_t* rows, Arena& ws, hipStream_t st) {
+  const uint64_t seedR = seed ^ kSrhtRowSalt;
+  int* hist = ws.take<int>(65536);
+  SelectState* state = ws.take<SelectState>(1);
+  const int chunks = (int)((n_pad + kSelChunk - 1) / kSelChunk);
+  int* counts = ws.take<int>(chunks + 1);
+  int* offsets = ws.take<int>(chunks + 1);
+  if (!offsets) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
+  SRP_TRY(fill_i32(hist, 65536, 0, st));
+  hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1), 0, st, state, s);
+  SRP_LAUNCH_CHECK();
+  const unsigned nb = (unsigned)((n_pad + 255) / 256);
+  for (int round = 0; round < 4; ++round) {
+    hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, st, n_pad, seedR, round, state, hist);
+    SRP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1024), 0, st, hist, state);
+    SRP_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(k_sel_count, dim3(chunks), dim3(256), 0, st, n_pad, seedR, state, counts);
+  SRP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, counts, chunks, offsets, (int*)nullptr);
+  SRP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_sel_write, dim3(chunks), dim3(256), 0, st, n_pad, seedR, state, offsets, rows);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// Group the sampled rows by beta = r mod B (single workgroup).  For every
+// beta: goff[beta] .. goff[beta+1] index into galpha / gslot, listing the
+// sampled rows with that beta in ascending order (alpha = r / B, slot = j).
+__global__ void __launch_bounds__(1024) k_srht_group(const int64_t* rows, int s, int B, int logB,
+                                                     int* goff, int* galpha, int* gslot) {
+  __shared__ int cnt[1024];
+  __shared__ int off[1025];
+  const int t = threadIdx.x;
+  for (int b = t; b < B; b += 1024) cnt[b] = 0;
+  __syncthreads();
+  for (int j = t; j < s; j += 1024) atomicAdd(&cnt[(int)(rows[j] & (B - 1))], 1);
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int b = 0; b < B; ++b) { off[b] = run; run += cnt[b]; }
+    off[B] = run;
+  }
+  __syncthreads();
+  for (int b = t; b <= B; b += 1024) goff[b] = off[b];
+  for (int b = t; b < B; b += 1024) {
+    int pos = off[b];
+    for (int j = 0; j < s; ++j) {
+      const int64_t r = rows[j];
+      if ((int)(r & (B - 1)) == b) {
+        galpha[pos] = (int)(r >> logB);
+        gslot[pos] = j;
+        ++pos;
+      }
+    }
+  }
+}
+
+// Level 1: length-B Walsh-Hadamard transform of every block of B rows, in
+// LDS, for a chunk of CW columns.  Rows past n are zero (the padding).
+template <class T, class Acc>
+__global__ void __launch_bounds__(256) k_srht_level1(const T* __restrict__ A, int64_t n, int d, int B, int logB,
+                                                     int CW, uint64_t seedD, Acc* __restrict__ Tbuf) {
+  extern __shared__ unsigned char smem_raw[];
+  Acc* tile = reinterpret_cast<Acc*>(smem_raw);
+  const int a = blockIdx.x;
+  const int c0 = blockIdx.y * CW;
+  const int cw = min(CW, d - c0);
+  const int tot = B * CW;
+  for (int e = threadIdx.x; e < tot; e += 256) {
+    const int r = e / CW, c = e % CW;
+    const int64_t row = (int64_t)a * B + r;
+    Acc v = Acc(0);
+    if (c < cw && row < n) {
+      const uint64_t w = splitmix64(seedD, (uint64_t)row);
+      v = load_as<Acc>(A + row * d + c0 + c);
+      if (w & 1ull) v = -v;
+    }
+    tile[e] = v;
+  }
+  __syncthreads();
+  const int pairs = tot / 2;
+  for (int lh = 0; lh < logB; ++lh) {
+    const int h = 1 << lh;
+    for (int q = threadIdx.x; q < pairs; q += 256) {
+      const int rp = q / CW, c = q % CW;
+      const int lo = ((rp >> lh) << (lh + 1)) | (rp & (h - 1));
+      const int i0 = lo * CW + c, i1 = (lo + h) * CW + c;
+      const Acc x = tile[i0], y = tile[i1];
+      tile[i0] = x + y;
+      tile[i1] = x - y;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < tot; e += 256) {
+    const int r = e / CW, c = e % CW;
+    if (c < cw) Tbuf[((int64_t)a * B + r) * d + c0 + c] = tile[e];
+  }
+}
+
+// Level 2: out[slot] = s^-1/2 * sum_a (-1)^popcount(alpha & a) T[a B + beta].
+template <class Acc>
+__global__ void __launch_bounds__(256) k_srht_level2(const Acc* __restrict__ Tbuf, int d, int B, int A_eff,
+                                                     const int* __restrict__ goff, const int* __restrict__ galpha,
+                                                     const int* __restrict__ gslot, Acc scale, Acc* __restrict__ out) {
+  constexpr int G = 16;
+  const int beta = blockIdx.x;
+  const int c = blockIdx.y * 256 + threadIdx.x;
+  const int beg = goff[beta], cnt = goff[beta + 1] - beg;
+  for (int g0 = 0; g0 < cnt; g0 += G) {
+    const int gn = min(G, cnt - g0);
+    int alpha[G];
+    Acc acc[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      alpha[j] = (j < gn) ? galpha[beg + g0 + j] : 0;
+      acc[j] = Acc(0);
+    }
+    if (c < d) {
+      for (int a = 0; a < A_eff; ++a) {
+        const Acc v = Tbuf[((int64_t)a * B + beta) * d + c];
+#pragma unroll
+        for (int j = 0; j < G; ++j) acc[j] += (__popc(alpha[j] & a) & 1) ? -v : v;
+      }
+      for (int j = 0; j < gn; ++j) out[(int64_t)gslot[beg + g0 + j] * d + c] = acc[j] * scale;
+    }
+  }
+}
+
+static int srht_chunk_cols(int B, int acc_bytes) {
+  // LDS tile of B x CW elements, at most 64 KiB.
+  int cw = (64 * 1024) / (B * acc_bytes);
+  if (cw > 128) cw = 128;
+  if (cw < 1) cw = 1;
+  return cw;
+}
+
+size_t srht_ws_bytes(int64_t n, int d, int s, int dtype) {
+  SrhtGeom g = srht_geom(n);
+  const size_t acc = dtype == SRP_F64 ? 8 : 4;
+  const int chunks = (int)((g.n_pad + kSelChunk - 1) / kSelChunk);
+  return bytes_of<int>(65536) + bytes_of<SelectState>(1) + 2 * bytes_of<int>(chunks + 1) +
+         bytes_of<int64_t>(s) + bytes_of<int>(g.B + 1) + 2 * bytes_of<int>(s) +
+         (((size_t)g.A_eff * g.B * d * acc + 255) & ~size_t(255));
+}
+
+int srht_rows_run(int64_t n, int s, uint64_t seed, int64_t* rows, Arena& ws, hipStream_t st) {
+  SrhtGeom g = srht_geom(n);
+  if ((int64_t)s > g.n_pad || g.m > 20) {
+    set_error("srht: need s <= n' <= 2^20 (n=%lld, s=%d)", (long long)n, s);
+    return SRP_EINVAL;
+  }
+  return srht_select_rows(g.n_pad, s, seed, rows, ws, st);
+}
+
+template <class T, class Acc>
+static int srht_levels(const T* A, int64_t n, int d, int s, uint64_t seed, const SrhtGeom& g,
+                       const int* goff, const int* galpha, const int* gslot, Acc* Tbuf, Acc* out,
+                       hipStream_t st) {
+  const int CW = srht_chunk_cols(g.B, (int)sizeof(Acc));
+  dim3 grid1(g.A_eff, (d + CW - 1) / CW);
+  const size_t lds = (size_t)g.B * CW * sizeof(Acc);
+  hipLaunchKernelGGL((k_srht_level1<T, Acc>), grid1, dim3(256), lds, st, A, n, d, g.B, (g.m + 1) / 2, CW,
+                     seed ^ kSrhtSignSalt, Tbuf);
+  SRP_LAUNCH_CHECK();
+  dim3 grid2(g.B, (d + 255) / 256);
+  hipLaunchKernelGGL((k_srht_level2<Acc>), grid2, dim3(256), 0, st, Tbuf, d, g.B, g.A_eff, goff, galpha,
+                     gslot, (Acc)(1.0 / std::sqrt((double)s)), out);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+int srht_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, Arena& ws,
+             hipStream_t st) {
+  SrhtGeom g = srht_geom(n);
+  if ((int64_t)s > g.n_pad || g.m > 20) {
+    set_error("srht: need s <= n' <= 2^20 (n=%lld, s=%d)", (long long)n, s);
+    return SRP_EINVAL;
+  }
+  int64_t* rows = ws.take<int64_t>(s);
+  int* goff = ws.take<int>(g.B + 1);
+  int* galpha = ws.take<int>(s);
+  int* gslot = ws.take<int>(s);
+  if (!gslot) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
+  SRP_TRY(srht_select_rows(g.n_pad, s, seed, rows, ws, st));
+  int logB = 0;
+  while ((1 << logB) < g.B) ++logB;
+  hipLaunchKernelGGL(k_srht_group, dim3(1), dim3(1024), 0, st, rows, s, g.B, logB, goff, galpha, gslot);
+  SRP_LAUNCH_CHECK();
+  const size_t tcount = (size_t)g.A_eff * g.B * d;
+  if (dtype == SRP_F64) {
+    double* Tbuf = ws.take<double>(tcount);
+    if (!Tbuf) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
+    return srht_levels((const double*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (double*)out, st);
+  }
+  float* Tbuf = ws.take<float>(tcount);
+  if (!Tbuf) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
+  if (dtype == SRP_F32)
+    return srht_levels((const float*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (float*)out, st);
+  if (dtype == SRP_BF16)
+    return srht_levels((const bf16*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (float*)out, st);
+  set_error("srht: bad dtype %d", dtype);
+  return SRP_EINVAL;
+}
+
+}  // namespace srp

@@ -1,0 +1,78 @@
+// Device-side state of one Riemannian CG solve and the step kernels that
+// advance it.  See solver_kernels.hip for the mathematics.
+#pragma once
+#include "common.hpp"
+
+namespace srp {
+
+constexpr int KMAX = 32;       // largest k the step kernels support
+constexpr int KK_STRIDE = KMAX * KMAX;
+
+// k x k matrices kept per side in SolverState::kk, each KMAX*KMAX doubles.
+enum KKSlot { KK_LINVT = 0, KK_S = 1, KK_PHI = 2, KK_ROT = 3, KK_NSLOTS = 4 };
+
+struct SolverCtrl {
+  double t;        // accepted step along the retraction curve
+  double t_guess;  // centre of the next line search
+  double f;        // cost at the current iterate
+  double gg;       // <grad, grad>_M at the current iterate
+  double gg_old;
+  double df0;      // <grad, xi>_M for the current direction
+  double beta;
+  double tol;
+  int done;        // 1: stop (converged, failed or out of iterations)
+  int status;      // SRP_OK / SRP_ENOCONV / SRP_ENOTSPD
+  int iter;
+  int max_iter;
+  int restart;     // next direction is -grad
+  int ls_fail;     // consecutive line-search failures
+  int fixed_step;  // 1: take t = 1 without a line search (the qf start)
+  int pad;
+};
+
+// One block of the (product) manifold: St_B(k, d) with B = A^T A + lam I.
+struct SideView {
+  int d;
+  double lam;
+  double* U;      // d x k iterate
+  double* Ks;     // A^T A U
+  double* Kc;     // cost products: CCA A^T A_other U_other; FDA S_B U
+  double* xi;     // d x k search direction
+  double* gold;   // d x k previous Riemannian gradient
+  const double* J;  // pass output d x jld (Js at column js_off, Jc at jc_off)
+  int jld, js_off, jc_off;
+  const double* Jc_sep;  // FDA: S_B xi, d x k (then J's jc block is unused)
+  double* Z;      // d x 2k: [E | B U]
+  double* Wz;     // d x 2k: M^-1 Z
+};
+
+struct ProbView {
+  int nb;         // 1 (FDA) or 2 (CCA)
+  int k;
+  int lda_cost;   // 1: cost -1/2 tr(W^T S_B W N); 0: CCA cross cost
+  SideView s[2];
+  const double* mu;   // device, k weights
+  SolverCtrl* ctrl;
+  double* kk;         // [2][KK_NSLOTS][KMAX*KMAX]
+  double* part;       // partial k x k products
+  int part_slices;    // row-slice workgroups per side used for partials
+};
+
+// Launchers (solver_kernels.hip).
+int launch_ls_partials(const ProbView& p, hipStream_t st);
+int launch_ctrl_ls(const ProbView& p, hipStream_t st);
+int launch_update(const ProbView& p, int refresh, hipStream_t st);
+int launch_dir_partials(const ProbView& p, hipStream_t st);
+int launch_ctrl_dir(const ProbView& p, hipStream_t st);
+int launch_combine(const ProbView& p, hipStream_t st);
+int launch_final_partials(const ProbView& p, hipStream_t st);
+int launch_ctrl_final(const ProbView& p, double* sigma_out, hipStream_t st);
+int launch_apply_rot(const ProbView& p, hipStream_t st);
+int launch_sign_fix(const ProbView& p, hipStream_t st);
+int launch_gauss_fill(double* p, int64_t count, uint64_t seed, hipStream_t st);
+int launch_ctrl_init(SolverCtrl* c, double tol, int max_iter, hipStream_t st);
+int launch_set_fixed_step(SolverCtrl* c, int on, hipStream_t st);
+size_t partial_bytes(int k, int dmax);
+int partial_slices(int dmax);
+
+}  // namespace srp

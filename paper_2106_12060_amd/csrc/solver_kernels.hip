@@ -1,0 +1,1052 @@
+// Step kernels of the preconditioned Riemannian CG (Table 1 components on
+// St_B(k, d) with the fixed sketched metric M; the CCA problem is the
+// product of two such manifolds, Section 4.2).
+//
+// The iterate never leaves the device and every data product comes from
+// one fused pass per iteration (pass.hip).  With Ks = A^T A U,
+// Kc = cost products (CCA: A_b^T A_o U_o; FDA: S_B W) maintained across
+// iterations and J = A^T A xi (and cross terms) from the pass along the
+// direction xi, everything below is algebra on d x k and k x k blocks:
+//
+//  * Retraction curve R(U + t xi) = (U + t xi) L(t)^-T with
+//    L L^T = (U + t xi)^T B (U + t xi) = G0 + t G1 + t^2 G2 (QR retraction
+//    of Table 1 written as a Cholesky of the small Gram), and the cost on
+//    it (Eq. costriemannianccaBrockett / Eq. lda_riemannian) follows from
+//    k x k products only, so the line search costs no data pass.
+//  * At the accepted point U+ = (U + t xi) L^-T the products update as
+//    Ks+ = (Ks + t J) L^-T, Kc+ = (Kc + t Jc) L_o^-T.
+//  * Gradient (Table 1 / Eq. gradCCA): with E = -Kc N (Euclidean gradient)
+//    and BU = Ks + lam U, grad = M^-1 E - M^-1 BU S where S solves the
+//    Sylvester equation P S + S P = BU^T M^-1 E + (.)^T, P = BU^T M^-1 BU.
+//    M grad = E - BU S, so metric inner products need no extra M product.
+//  * Transport by projection (Table 1) of the previous direction and
+//    gradient, Polak-Ribiere+ coefficient, restart on non-descent.
+// The k x k work runs in single-workgroup "controller" kernels in FP64;
+// the Sylvester equations use a parallel cyclic Jacobi eigensolver.
+#include "solver.hpp"
+#include "kernels.hpp"
+
+#include <cmath>
+
+namespace srp {
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__host__ __device__ __forceinline__ double* kkslot(const ProbView& p, int side, int slot) {
+  return p.kk + ((size_t)side * KK_NSLOTS + slot) * KK_STRIDE;
+}
+
+// ------------------------------------------------------------ partials
+// out[z][a*k+i][b*k+j] = sum over rows r in slice z of L_a[r][i] * R_b[r][j].
+struct PartialSide {
+  int d, nl, nr;
+  const double* lp[4]; int lld[4];
+  const double* rp[6]; int rld[6];
+};
+struct PartialArgs {
+  int k, slices;
+  PartialSide side[2];
+  double* out;            // [side][slices][nl*k][nr*k]
+  int64_t side_stride;
+  const SolverCtrl* ctrl;
+};
+
+constexpr int kPartRows = 16;
+
+__global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
+  if (a.ctrl && a.ctrl->done) return;
+  const PartialSide& ps = a.side[blockIdx.y];
+  const int k = a.k, z = blockIdx.x;
+  const int NL = ps.nl * k, NR = ps.nr * k;
+  __shared__ double ls[kPartRows][2 * KMAX];
+  __shared__ double rs[kPartRows][6 * KMAX];
+  constexpr int PER = (2 * KMAX * 6 * KMAX + 255) / 256;
+  double acc[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) acc[q] = 0.0;
+  const int nout = NL * NR;
+  for (int r0 = z * kPartRows; r0 < ps.d; r0 += a.slices * kPartRows) {
+    for (int e = threadIdx.x; e < kPartRows * NL; e += 256) {
+      const int rr = e / NL, c = e % NL, blk = c / k, j = c % k;
+      const int r = r0 + rr;
+      ls[rr][c] = (r < ps.d) ? ps.lp[blk][(int64_t)r * ps.lld[blk] + j] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kPartRows * NR; e += 256) {
+      const int rr = e / NR, c = e % NR, blk = c / k, j = c % k;
+      const int r = r0 + rr;
+      rs[rr][c] = (r < ps.d) ? ps.rp[blk][(int64_t)r * ps.rld[blk] + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int o = threadIdx.x + q * 256;
+      if (o < nout) {
+        const int i = o / NR, j = o % NR;
+        double s = acc[q];
+#pragma unroll
+        for (int rr = 0; rr < kPartRows; ++rr) s += ls[rr][i] * rs[rr][j];
+        acc[q] = s;
+      }
+    }
+    __syncthreads();
+  }
+  double* out = a.out + blockIdx.y * a.side_stride + (int64_t)z * nout;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int o = threadIdx.x + q * 256;
+    if (o < nout) out[o] = acc[q];
+  }
+}
+
+int partial_slices(int dmax) {
+  int s = (dmax + kPartRows - 1) / kPartRows;
+  return s < 64 ? (s < 1 ? 1 : s) : 64;
+}
+
+size_t partial_bytes(int k, int dmax) {
+  return bytes_of<double>((size_t)2 * partial_slices(dmax) * (4 * k) * (6 * k));
+}
+
+static int run_partials(PartialArgs& a, int nb, hipStream_t st) {
+  a.side_stride = (int64_t)a.slices * (4 * a.k) * (6 * a.k);
+  hipLaunchKernelGGL(k_partials, dim3(a.slices, nb), dim3(256), 0, st, a);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// Sum of block (a, b) of the partials: k x k into dst (ld k), scaled.
+__device__ void sum_block(const double* part, int slices, int nl, int nr, int k, int a, int b, double scale,
+                          double* dst, int tid, int nthreads, bool accumulate) {
+  const int NR = nr * k;
+  const int64_t zs = (int64_t)(nl * k) * NR;
+  for (int e = tid; e < k * k; e += nthreads) {
+    const int i = e / k, j = e % k;
+    double s = 0.0;
+    for (int z = 0; z < slices; ++z) s += part[z * zs + (int64_t)(a * k + i) * NR + b * k + j];
+    dst[e] = accumulate ? dst[e] + scale * s : scale * s;
+  }
+}
+
+int launch_ls_partials(const ProbView& p, hipStream_t st) {
+  PartialArgs a{};
+  a.k = p.k; a.slices = p.part_slices; a.out = p.part; a.ctrl = p.ctrl;
+  const int k = p.k;
+  for (int b = 0; b < p.nb; ++b) {
+    const SideView& s = p.s[b];
+    PartialSide& q = a.side[b];
+    q.d = s.d; q.nl = 2; q.nr = 6;
+    q.lp[0] = s.U; q.lld[0] = k;
+    q.lp[1] = s.xi; q.lld[1] = k;
+    q.rp[0] = s.Ks; q.rld[0] = k;
+    q.rp[1] = s.J + s.js_off; q.rld[1] = s.jld;
+    q.rp[2] = s.U; q.rld[2] = k;
+    q.rp[3] = s.xi; q.rld[3] = k;
+    q.rp[4] = s.Kc; q.rld[4] = k;
+    if (s.Jc_sep) { q.rp[5] = s.Jc_sep; q.rld[5] = k; }
+    else { q.rp[5] = s.J + s.jc_off; q.rld[5] = s.jld; }
+  }
+  return run_partials(a, p.nb, st);
+}
+
+int launch_dir_partials(const ProbView& p, hipStream_t st) {
+  PartialArgs a{};
+  a.k = p.k; a.slices = p.part_slices; a.out = p.part; a.ctrl = p.ctrl;
+  const int k = p.k;
+  for (int b = 0; b < p.nb; ++b) {
+    const SideView& s = p.s[b];
+    PartialSide& q = a.side[b];
+    q.d = s.d; q.nl = 2; q.nr = 4;
+    q.lp[0] = s.Z + k; q.lld[0] = 2 * k;   // B U
+    q.lp[1] = s.Z; q.lld[1] = 2 * k;       // E
+    q.rp[0] = s.Wz + k; q.rld[0] = 2 * k;  // M^-1 B U
+    q.rp[1] = s.Wz; q.rld[1] = 2 * k;      // M^-1 E
+    q.rp[2] = s.xi; q.rld[2] = k;
+    q.rp[3] = s.gold; q.rld[3] = k;
+  }
+  return run_partials(a, p.nb, st);
+}
+
+int launch_final_partials(const ProbView& p, hipStream_t st) {
+  PartialArgs a{};
+  a.k = p.k; a.slices = p.part_slices; a.out = p.part; a.ctrl = nullptr;
+  const int k = p.k;
+  for (int b = 0; b < p.nb; ++b) {
+    const SideView& s = p.s[b];
+    PartialSide& q = a.side[b];
+    q.d = s.d; q.nl = 1; q.nr = 3;
+    q.lp[0] = s.U; q.lld[0] = k;
+    q.rp[0] = s.Ks; q.rld[0] = k;
+    q.rp[1] = s.U; q.rld[1] = k;
+    q.rp[2] = s.Kc; q.rld[2] = k;
+  }
+  return run_partials(a, p.nb, st);
+}
+
+// ------------------------------------------------- small dense helpers
+// Lower Cholesky in place (ld = k) by one wave; false if not SPD.
+__device__ bool wave_chol(double* A, int k, int lane) {
+  for (int j = 0; j < k; ++j) {
+    wave_sync();
+    const double piv = A[j * k + j];
+    if (!(piv > 0.0) || !isfinite(piv)) return false;
+    const double dj = sqrt(piv);
+    wave_sync();
+    if (lane == 0) A[j * k + j] = dj;
+    for (int i = j + 1 + lane; i < k; i += 64) A[i * k + j] /= dj;
+    wave_sync();
+    const int w = k - j - 1;
+    for (int e = lane; e < w * w; e += 64) {
+      const int r = j + 1 + e / w, c = j + 1 + e % w;
+      if (c <= r) A[r * k + c] -= A[r * k + j] * A[c * k + j];
+    }
+  }
+  wave_sync();
+  return true;
+}
+
+// X = L^-1 for lower L (both ld k), column per lane.
+__device__ void wave_lower_inv(const double* L, double* X, int k, int lane) {
+  for (int c = lane; c < k; c += 64) {
+    for (int r = 0; r < c; ++r) X[r * k + c] = 0.0;
+    X[c * k + c] = 1.0 / L[c * k + c];
+    for (int r = c + 1; r < k; ++r) {
+      double s = 0.0;
+      for (int l = c; l < r; ++l) s += L[r * k + l] * X[l * k + c];
+      X[r * k + c] = -s / L[r * k + r];
+    }
+  }
+  wave_sync();
+}
+
+// Coefficients of the line-search polynomials, stored in global scratch:
+// [side b][G0, G1, G2] then [C0, C1, C2] (CCA cross or FDA S_B), each k x k.
+__device__ __forceinline__ double* coefp(double* base, int k, int idx) { return base + (size_t)idx * k * k; }
+
+// Cost along the curve at step t, evaluated by one wave.  Lm holds nb
+// k x k factors, Li their inverses; C(t) is staged into Lm once the
+// factors have been inverted.
+__device__ double eval_trial(const ProbView& p, const double* coef, double t, double* Lm, double* Li, int lane,
+                             bool* ok) {
+  const int k = p.k, nb = p.nb;
+  const double t2 = t * t;
+  for (int b = 0; b < nb; ++b) {
+    double* L = Lm + b * k * k;
+    const double* G0 = coef + (size_t)(3 * b + 0) * k * k;
+    const double* G1 = coef + (size_t)(3 * b + 1) * k * k;
+    const double* G2 = coef + (size_t)(3 * b + 2) * k * k;
+    for (int e = lane; e < k * k; e += 64) L[e] = G0[e] + t * G1[e] + t2 * G2[e];
+    if (!wave_chol(L, k, lane)) { *ok = false; return INFINITY; }
+    wave_lower_inv(L, Li + b * k * k, k, lane);
+  }
+  const double* C0 = coef + (size_t)(3 * nb + 0) * k * k;
+  const double* C1 = coef + (size_t)(3 * nb + 1) * k * k;
+  const double* C2 = coef + (size_t)(3 * nb + 2) * k * k;
+  double* Ct = Lm;
+  for (int e = lane; e < k * k; e += 64) Ct[e] = C0[e] + t * C1[e] + t2 * C2[e];
+  wave_sync();
+  const double* Lx = Li;
+  const double* Ly = Li + (nb == 2 ? k * k : 0);
+  double part = 0.0;
+  for (int i = lane; i < k; i += 64) {
+    double fii = 0.0;
+    for (int a = 0; a <= i; ++a) {
+      double row = 0.0;
+      for (int b2 = 0; b2 <= i; ++b2) row += Ct[a * k + b2] * Ly[i * k + b2];
+      fii += Lx[i * k + a] * row;
+    }
+    part += p.mu[i] * fii;
+  }
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  *ok = true;
+  const double f = p.lda_cost ? -0.5 * part : -part;
+  return isfinite(f) ? f : INFINITY;
+}
+
+// -------------------------------------------------------- line search
+// One workgroup: form the polynomial coefficients, evaluate NTR trial steps
+// per round in parallel (one wave each), keep the best, narrow, repeat.
+__global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, double* coef, int ntr) {
+  SolverCtrl* c = p.ctrl;
+  if (c->done) return;
+  extern __shared__ double sm[];
+  __shared__ double fbest[64];
+  __shared__ double tbest[64];
+  __shared__ int okflag[64];
+  const int k = p.k, nb = p.nb, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int slices = p.part_slices;
+  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);
+  // coefficients (ls partial layout: left [U, xi], right [Ks, Js, U, xi, Kc, Jc])
+  for (int b = 0; b < nb; ++b) {
+    const double* part = p.part + b * side_stride;
+    const double lam = p.s[b].lam;
+    double* G0 = coefp(coef, k, 3 * b + 0);
+    double* G1 = coefp(coef, k, 3 * b + 1);
+    double* G2 = coefp(coef, k, 3 * b + 2);
+    sum_block(part, slices, 2, 6, k, 0, 0, 1.0, G0, tid, 1024, false);
+    sum_block(part, slices, 2, 6, k, 0, 2, lam, G0, tid, 1024, true);
+    sum_block(part, slices, 2, 6, k, 1, 0, 1.0, G1, tid, 1024, false);
+    sum_block(part, slices, 2, 6, k, 0, 1, 1.0, G1, tid, 1024, true);
+    sum_block(part, slices, 2, 6, k, 1, 2, lam, G1, tid, 1024, true);
+    sum_block(part, slices, 2, 6, k, 0, 3, lam, G1, tid, 1024, true);
+    sum_block(part, slices, 2, 6, k, 1, 1, 1.0, G2, tid, 1024, false);
+    sum_block(part, slices, 2, 6, k, 1, 3, lam, G2, tid, 1024, true);
+  }
+  {
+    const double* part = p.part;  // side 0 carries the cost products
+    double* C0 = coefp(coef, k, 3 * nb + 0);
+    double* C1 = coefp(coef, k, 3 * nb + 1);
+    double* C2 = coefp(coef, k, 3 * nb + 2);
+    sum_block(part, slices, 2, 6, k, 0, 4, 1.0, C0, tid, 1024, false);
+    sum_block(part, slices, 2, 6, k, 1, 4, 1.0, C1, tid, 1024, false);
+    sum_block(part, slices, 2, 6, k, 0, 5, 1.0, C1, tid, 1024, true);
+    sum_block(part, slices, 2, 6, k, 1, 5, 1.0, C2, tid, 1024, false);
+  }
+  __threadfence_block();
+  __syncthreads();
+  // symmetrise the Gram coefficients (and the FDA cost coefficients)
+  const int nsym = 3 * nb + (p.lda_cost ? 3 : 0);
+  for (int e = tid; e < nsym * k * k; e += 1024) {
+    const int m = e / (k * k), q = e % (k * k), i = q / k, j = q % k;
+    if (i < j) {
+      double* M = coefp(coef, k, m);
+      const double v = 0.5 * (M[i * k + j] + M[j * k + i]);
+      M[i * k + j] = v;
+      M[j * k + i] = v;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+
+  const int per_wave = (nb == 2 ? 4 : 2) * k * k;
+  double* Lm = sm + (size_t)w * per_wave;
+  double* Li = Lm + nb * k * k;
+  const double f0 = c->f;
+  const double df0 = c->df0;
+  double t_acc = 0.0;
+  double t_seen = 0.0;   // best step of the search, accepted or not
+  bool accepted = false;
+  if (c->fixed_step) {
+    t_acc = 1.0;
+    accepted = true;
+  } else {
+    // First step: the inverse of the cost's curvature scale, about
+    // 1 / (2 mu_1 |f| / sum mu); afterwards the last accepted step.
+    double centre = c->t_guess;
+    if (!(centre > 0.0)) {
+      double smu = 0.0;
+      for (int i = 0; i < k; ++i) smu += p.mu[i];
+      centre = (fabs(f0) > 0.0) ? smu / (2.0 * p.mu[0] * fabs(f0)) : 1.0;
+    }
+    double H = 8.0;  // half span in octaves
+    double tb = centre, fb = INFINITY;
+    int expand = 0;
+    for (int round = 0; round < 16 && H > 0.1; ++round) {
+      if (w < ntr) {
+        const double x = (ntr > 1) ? (2.0 * w / (ntr - 1) - 1.0) : 0.0;
+        const double t = centre * exp2(H * x);
+        bool ok;
+        const double f = eval_trial(p, coef, t, Lm, Li, lane, &ok);
+        if (lane == 0) { fbest[w] = f; tbest[w] = t; }
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int best = -1;
+        for (int j = 0; j < ntr; ++j)
+          if (fbest[j] < INFINITY && (best < 0 || fbest[j] < fbest[best])) best = j;
+        if (best >= 0 && fbest[best] < fb) { fb = fbest[best]; tb = tbest[best]; }
+        // minimum on the edge of the grid: move the grid there, same span
+        okflag[1] = (best == 0 || best == ntr - 1) && expand < 6 ? 1 : 0;
+        fbest[63] = fb;
+        tbest[63] = tb;
+      }
+      __syncthreads();
+      fb = fbest[63];
+      tb = tbest[63];
+      centre = tb;
+      if (okflag[1]) {
+        ++expand;
+      } else {
+        H = (ntr > 1) ? 2.0 * H / (ntr - 1) : 0.5 * H;
+      }
+      __syncthreads();
+    }
+    t_seen = tb;
+    // Armijo sufficient decrease
+    if (fb < INFINITY && df0 < 0.0 && fb <= f0 + 1e-4 * tb * df0) {
+      t_acc = tb;
+      accepted = true;
+    } else if (fb < INFINITY && fb < f0 && df0 < 0.0) {
+      t_acc = tb;  // decrease without the Armijo margin: still progress
+      accepted = true;
+    }
+  }
+  // final factors at the accepted step (t = 0 re-orthonormalises on failure)
+  if (w == 0) {
+    bool ok;
+    const double f = eval_trial(p, coef, t_acc, Lm, Li, lane, &ok);
+    if (lane == 0) { fbest[0] = f; okflag[0] = ok ? 1 : 0; }
+    wave_sync();
+    for (int b = 0; b < nb; ++b) {
+      double* LT = kkslot(p, b, KK_LINVT);
+      const double* X = Li + b * k * k;
+      for (int e = lane; e < k * k; e += 64) {
+        const int i = e / k, j = e % k;
+        LT[i * k + j] = X[j * k + i];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (!okflag[0]) {
+      c->done = 1;
+      c->status = SRP_ENOTSPD;
+      c->t = 0.0;
+    } else if (accepted) {
+      c->t = t_acc;
+      c->f = fbest[0];
+      c->t_guess = t_acc;
+      c->ls_fail = 0;
+    } else {
+      c->t = 0.0;
+      c->f = fbest[0];
+      c->restart = 1;
+      c->ls_fail += 1;
+      c->t_guess = (t_seen > 0.0 ? t_seen : 1.0) / 16.0;
+      if (c->ls_fail >= 3) c->done = 1;  // no further decrease at working precision
+    }
+    c->fixed_step = 0;
+  }
+}
+
+int launch_ctrl_ls(const ProbView& p, hipStream_t st) {
+  const int per_wave = (p.nb == 2 ? 4 : 2) * p.k * p.k * 8;
+  int ntr = 131072 / per_wave;
+  if (ntr > 16) ntr = 16;
+  if (ntr < 1) ntr = 1;
+  double* coef = kkslot(p, 0, 0) + (size_t)2 * KK_NSLOTS * KK_STRIDE;  // scratch after the kk slots
+  const size_t lds = (size_t)ntr * per_wave;
+  static size_t attr_set = 0;
+  if (lds > attr_set) {
+    SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_ls, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_set = lds;
+  }
+  hipLaunchKernelGGL(k_ctrl_ls, dim3(1), dim3(1024), lds, st, p, coef, ntr);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// ------------------------------------------------------------- update
+// Per row: U+ = (U + t xi) Linv^T, Ks+ = (Ks + t Js) Linv^T,
+// Kc+ = (Kc + t Jc) Linv_o^T; then Z = [-Kc+ N | Ks+ + lam U+].
+// refresh = 1: Ks = Js, Kc = Jc at the current U (exact products);
+// refresh = 2: the same, also after the stop flag is set.
+// A workgroup stages 16 rows in LDS, then one thread per (row, column).
+constexpr int kUpdRows = 16;
+
+__global__ void __launch_bounds__(256) k_update(ProbView p, int refresh) {
+  const SolverCtrl* c = p.ctrl;
+  if (c->done && refresh != 2) return;   // 2 = forced refresh after the loop
+  const int b = blockIdx.y;
+  const SideView& s = p.s[b];
+  const int o = (p.nb == 2) ? 1 - b : b;
+  const int k = p.k;
+  const int r0 = blockIdx.x * kUpdRows;
+  if (r0 >= s.d) return;
+  const int nr = min(kUpdRows, s.d - r0);
+  __shared__ double LT[KMAX * KMAX], LTo[KMAX * KMAX], mu[KMAX];
+  __shared__ double u[kUpdRows][KMAX], ks[kUpdRows][KMAX], kc[kUpdRows][KMAX];
+  const double t = c->t;
+  const int tid = threadIdx.x;
+  if (!refresh) {
+    const double* gLT = kkslot(p, b, KK_LINVT);
+    const double* gLTo = kkslot(p, o, KK_LINVT);
+    for (int e = tid; e < k * k; e += 256) { LT[e] = gLT[e]; LTo[e] = gLTo[e]; }
+  }
+  for (int e = tid; e < k; e += 256) mu[e] = p.mu[e];
+  for (int e = tid; e < nr * k; e += 256) {
+    const int rr = e / k, j = e - rr * k;
+    const int64_t i = r0 + rr;
+    const double* Jrow = s.J + i * s.jld;
+    const double js = Jrow[s.js_off + j];
+    const double jc = s.Jc_sep ? s.Jc_sep[i * k + j] : Jrow[s.jc_off + j];
+    if (refresh) {
+      u[rr][j] = s.U[i * k + j];
+      ks[rr][j] = js;
+      kc[rr][j] = jc;
+    } else {
+      u[rr][j] = s.U[i * k + j] + t * s.xi[i * k + j];
+      ks[rr][j] = s.Ks[i * k + j] + t * js;
+      kc[rr][j] = s.Kc[i * k + j] + t * jc;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nr * k; e += 256) {
+    const int rr = e / k, j = e - rr * k;
+    const int64_t i = r0 + rr;
+    double un, ksn, kcn;
+    if (refresh) {
+      un = u[rr][j]; ksn = ks[rr][j]; kcn = kc[rr][j];
+    } else {
+      un = 0.0; ksn = 0.0; kcn = 0.0;
+      for (int l = 0; l < k; ++l) {
+        un += u[rr][l] * LT[l * k + j];
+        ksn += ks[rr][l] * LT[l * k + j];
+        kcn += kc[rr][l] * LTo[l * k + j];
+      }
+      s.U[i * k + j] = un;
+      s.Ks[i * k + j] = ksn;
+    }
+    s.Kc[i * k + j] = kcn;
+    if (refresh) s.Ks[i * k + j] = ksn;
+    double* Zi = s.Z + i * 2 * k;
+    Zi[j] = -kcn * mu[j];
+    Zi[k + j] = ksn + s.lam * un;
+  }
+}
+
+int launch_update(const ProbView& p, int refresh, hipStream_t st) {
+  const int dmax = p.nb == 2 ? (p.s[0].d > p.s[1].d ? p.s[0].d : p.s[1].d) : p.s[0].d;
+  dim3 grid((dmax + kUpdRows - 1) / kUpdRows, p.nb);
+  hipLaunchKernelGGL(k_update, grid, dim3(256), 0, st, p, refresh);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// ---------------------------------------------- Jacobi eigen-solver
+// Parallel cyclic Jacobi (round-robin pairs) on a symmetric n x n matrix
+// (n even, <= 64) by ONE wave: A is overwritten by the (near) diagonal
+// matrix and V accumulates the rotations, A_in = V D V^T.  Scratch: T
+// (2 n x n), and per-index tables of n entries.
+struct WaveJacobiScratch {
+  int pos[64];
+  int partner[64];
+  int isp[64];
+  double rc[64];
+  double rs[64];
+};
+
+__device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, WaveJacobiScratch& w) {
+  const int nn = n * n;
+  for (int e = lane; e < nn; e += 64) V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  wave_sync();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    for (int round = 0; round < n - 1; ++round) {
+      if (lane < n) w.pos[lane] = (lane == 0) ? 0 : 1 + ((lane - 1 + round) % (n - 1));
+      wave_sync();
+      if (lane < n / 2) {
+        int pp = w.pos[lane], qq = w.pos[n - 1 - lane];
+        if (pp > qq) { const int tmp = pp; pp = qq; qq = tmp; }
+        const double apq = A[pp * n + qq];
+        double cth = 1.0, sth = 0.0;
+        if (apq != 0.0) {
+          const double theta = (A[qq * n + qq] - A[pp * n + pp]) / (2.0 * apq);
+          const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          cth = 1.0 / sqrt(tt * tt + 1.0);
+          sth = tt * cth;
+        }
+        w.rc[pp] = cth; w.rs[pp] = sth; w.rc[qq] = cth; w.rs[qq] = sth;
+        w.partner[pp] = qq; w.partner[qq] = pp;
+        w.isp[pp] = 1; w.isp[qq] = 0;
+      }
+      wave_sync();
+      // A' = J^T A J, V' = V J with J[p][p]=c, J[p][q]=s, J[q][p]=-s, J[q][q]=c
+      for (int e = lane; e < nn; e += 64) {
+        const int r = e / n, col = e - r * n;
+        const int pr = w.partner[r], pc = w.partner[col];
+        const double jrr = w.rc[r], jpr = w.isp[r] ? -w.rs[r] : w.rs[r];
+        const double jcc = w.rc[col], jpc = w.isp[col] ? -w.rs[col] : w.rs[col];
+        T[e] = jrr * (jcc * A[r * n + col] + jpc * A[r * n + pc]) + jpr * (jcc * A[pr * n + col] + jpc * A[pr * n + pc]);
+        T[nn + e] = V[r * n + col] * jcc + V[r * n + pc] * jpc;
+      }
+      wave_sync();
+      for (int e = lane; e < nn; e += 64) {
+        A[e] = T[e];
+        V[e] = T[nn + e];
+      }
+      wave_sync();
+    }
+    double off = 0.0, dia = 0.0;
+    for (int e = lane; e < nn; e += 64) {
+      const double v = A[e];
+      if ((e / n) == (e % n)) dia += v * v; else off += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
+    }
+    if (off <= 1e-30 * (dia + 1e-300)) break;
+  }
+}
+
+// C = A B (k x k, ld k) by one wave.
+__device__ __forceinline__ void wave_mm(const double* A, const double* B, double* C, int k, int lane) {
+  for (int e = lane; e < k * k; e += 64) {
+    const int i = e / k, j = e - i * k;
+    double s = 0.0;
+    for (int l = 0; l < k; ++l) s += A[i * k + l] * B[l * k + j];
+    C[e] = s;
+  }
+  wave_sync();
+}
+
+// ------------------------------------------------------- direction
+// One wave per manifold block: sums the direction partials, diagonalises
+// P = BU^T M^-1 BU, solves the three Sylvester equations through it, and
+// reduces the trace terms; thread 0 then forms the Polak-Ribiere+
+// coefficient, the descent test and the stopping test.
+__global__ void __launch_bounds__(128) k_ctrl_dir(ProbView p) {
+  SolverCtrl* c = p.ctrl;
+  if (c->done) return;
+  extern __shared__ double sm[];
+  __shared__ WaveJacobiScratch jsc[2];
+  __shared__ double terms[2][12];
+  __shared__ double beta_sh;
+  const int k = p.k, nb = p.nb, lane = threadIdx.x & 63, b = threadIdx.x >> 6;
+  const int n = (k + 1) & ~1;
+  const int kk2 = k * k, nn = n * n;
+  const int slices = p.part_slices;
+  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);
+  const int per_side = 9 * kk2 + 4 * nn;
+  double* P = sm + b * per_side;
+  double* Q = P + kk2;
+  double* cx = Q + kk2;
+  double* cg = cx + kk2;
+  double* S = cg + kk2;
+  double* Sx = S + kk2;
+  double* Sg = Sx + kk2;
+  double* W1 = Sg + kk2;
+  double* W2 = W1 + kk2;
+  double* JA = W2 + kk2;
+  double* JV = JA + nn;
+  double* JT = JV + nn;
+  if (b < nb) {
+    const double* part = p.part + b * side_stride;
+    const int NR = 4 * k;
+    const int64_t zs = (int64_t)(2 * k) * NR;
+    for (int e = lane; e < kk2; e += 64) {
+      const int i = e / k, j = e - i * k;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int z = 0; z < slices; ++z) {
+        const double* row = part + z * zs + (int64_t)i * NR;
+        s0 += row[j];
+        s1 += row[k + j];
+        s2 += row[2 * k + j];
+        s3 += row[3 * k + j];
+      }
+      P[e] = s0; Q[e] = s1; cx[e] = s2; cg[e] = s3;
+    }
+    // traces of E^T W_E, E^T xi, E^T gold (diagonals of blocks (1,1), (1,2), (1,3))
+    double tr3[3] = {0.0, 0.0, 0.0};
+    for (int i = lane; i < k; i += 64)
+      for (int z = 0; z < slices; ++z) {
+        const double* row = part + z * zs + (int64_t)(k + i) * NR;
+        tr3[0] += row[k + i];
+        tr3[1] += row[2 * k + i];
+        tr3[2] += row[3 * k + i];
+      }
+    for (int q = 0; q < 3; ++q)
+      for (int o = 32; o > 0; o >>= 1) tr3[q] += __shfl_xor(tr3[q], o, 64);
+    wave_sync();
+    for (int e = lane; e < nn; e += 64) {
+      const int i = e / n, j = e - i * n;
+      JA[e] = (i < k && j < k) ? 0.5 * (P[i * k + j] + P[j * k + i]) : ((i == j) ? 1.0 : 0.0);
+    }
+    wave_sync();
+    wave_jacobi(JA, JV, JT, n, lane, jsc[b]);
+    // Sylvester: S = V ((V^T C V) ./ (w_i + w_j)) V^T for C = X + X^T
+    const double* srcs[3] = {Q, cx, cg};
+    double* dsts[3] = {S, Sx, Sg};
+    for (int m = 0; m < 3; ++m) {
+      const double* C = srcs[m];
+      for (int e = lane; e < kk2; e += 64) {
+        const int i = e / k, j = e - i * k;
+        double s = 0.0;
+        for (int l = 0; l < k; ++l) s += (C[i * k + l] + C[l * k + i]) * JV[l * n + j];
+        W1[e] = s;
+      }
+      wave_sync();
+      for (int e = lane; e < kk2; e += 64) {
+        const int i = e / k, j = e - i * k;
+        double s = 0.0;
+        for (int l = 0; l < k; ++l) s += JV[l * n + i] * W1[l * k + j];
+        W2[e] = s / (JA[i * n + i] + JA[j * n + j]);
+      }
+      wave_sync();
+      for (int e = lane; e < kk2; e += 64) {
+        const int i = e / k, j = e - i * k;
+        double s = 0.0;
+        for (int l = 0; l < k; ++l) s += JV[i * n + l] * W2[l * k + j];
+        W1[e] = s;
+      }
+      wave_sync();
+      for (int e = lane; e < kk2; e += 64) {
+        const int i = e / k, j = e - i * k;
+        double s = 0.0;
+        for (int l = 0; l < k; ++l) s += W1[i * k + l] * JV[j * n + l];
+        dsts[m][e] = s;
+      }
+      wave_sync();
+    }
+    wave_mm(P, S, W1, k, lane);   // W1 = P S
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int e = lane; e < kk2; e += 64) {
+      v[0] += Q[e] * S[e];
+      v[1] += S[e] * W1[e];
+      v[2] += cg[e] * S[e];
+      v[3] += Sg[e] * Q[e];
+      v[4] += Sg[e] * W1[e];
+      v[5] += cx[e] * S[e];
+      v[6] += Sx[e] * Q[e];
+      v[7] += Sx[e] * W1[e];
+    }
+    for (int q = 0; q < 8; ++q)
+      for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    if (lane == 0) {
+      for (int q = 0; q < 8; ++q) terms[b][q] = v[q];
+      terms[b][8] = tr3[0];
+      terms[b][9] = tr3[1];
+      terms[b][10] = tr3[2];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double gg = 0.0, gTg = 0.0, gTx = 0.0;
+    for (int s2 = 0; s2 < nb; ++s2) {
+      const double* t8 = terms[s2];
+      gg += t8[8] - 2.0 * t8[0] + t8[1];
+      gTg += t8[10] - t8[2] - t8[3] + t8[4];
+      gTx += t8[9] - t8[5] - t8[6] + t8[7];
+    }
+    double beta = 0.0;
+    if (!c->restart && c->iter > 0 && c->gg_old > 0.0) {
+      beta = (gg - gTg) / c->gg_old;
+      if (!(beta > 0.0)) beta = 0.0;
+    }
+    double df0 = -gg + beta * gTx;
+    if (!(df0 < 0.0)) {
+      beta = 0.0;
+      df0 = -gg;
+    }
+    c->beta = beta;
+    c->df0 = df0;
+    c->gg = gg;
+    c->gg_old = gg;
+    c->restart = 0;
+    const double gnorm = sqrt(gg > 0.0 ? gg : 0.0);
+    if (gnorm <= c->tol * fabs(c->f)) {
+      c->done = 1;
+      c->status = SRP_OK;
+    } else if (c->iter >= c->max_iter) {
+      c->done = 1;
+      c->status = SRP_ENOCONV;
+    }
+    c->iter += 1;
+    beta_sh = beta;
+  }
+  __syncthreads();
+  if (b < nb) {
+    const double beta = beta_sh;
+    double* gS = kkslot(p, b, KK_S);
+    double* gPhi = kkslot(p, b, KK_PHI);
+    for (int e = lane; e < kk2; e += 64) {
+      gS[e] = S[e];
+      gPhi[e] = S[e] - beta * Sx[e];
+    }
+  }
+}
+
+int launch_ctrl_dir(const ProbView& p, hipStream_t st) {
+  const int k = p.k, n = (k + 1) & ~1;
+  const size_t per_side = (size_t)(9 * k * k + 4 * n * n);
+  const size_t lds = (size_t)p.nb * per_side * sizeof(double);
+  static size_t attr_set = 0;
+  if (lds > attr_set) {
+    SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_dir, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr_set = lds;
+  }
+  hipLaunchKernelGGL(k_ctrl_dir, dim3(1), dim3(128), lds, st, p);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// ------------------------------------------------------------ combine
+// xi+ = -W_E + beta xi + W_B Phi ;  gold = W_E - W_B S   (element-wise).
+__global__ void __launch_bounds__(256) k_combine(ProbView p) {
+  const SolverCtrl* c = p.ctrl;
+  if (c->done) return;
+  const int b = blockIdx.y;
+  const SideView& s = p.s[b];
+  const int k = p.k;
+  __shared__ double S[KMAX * KMAX], Phi[KMAX * KMAX];
+  const double* gS = kkslot(p, b, KK_S);
+  const double* gPhi = kkslot(p, b, KK_PHI);
+  for (int e = threadIdx.x; e < k * k; e += 256) { S[e] = gS[e]; Phi[e] = gPhi[e]; }
+  __syncthreads();
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e >= (int64_t)s.d * k) return;
+  const int i = (int)(e / k), j = (int)(e % k);
+  const double* Wrow = s.Wz + (int64_t)i * 2 * k;   // [W_E | W_B]
+  double wbphi = 0.0, wbs = 0.0;
+  for (int l = 0; l < k; ++l) {
+    const double wb = Wrow[k + l];
+    wbphi += wb * Phi[l * k + j];
+    wbs += wb * S[l * k + j];
+  }
+  const double we = Wrow[j];
+  const double beta = c->beta;
+  s.xi[e] = -we + beta * s.xi[e] + wbphi;
+  s.gold[e] = we - wbs;
+}
+
+int launch_combine(const ProbView& p, hipStream_t st) {
+  const int dmax = p.nb == 2 ? (p.s[0].d > p.s[1].d ? p.s[0].d : p.s[1].d) : p.s[0].d;
+  dim3 grid((unsigned)(((int64_t)dmax * p.k + 255) / 256), p.nb);
+  hipLaunchKernelGGL(k_combine, grid, dim3(256), 0, st, p);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// -------------------------------------------------------------- final
+// FP64 retraction onto the constraint and Rayleigh-Ritz rotation: with
+// L_b L_b^T = U_b^T B_b U_b, CCA forms C = L_0^-1 (U_0^T Kc_0) L_1^-T and its
+// SVD (Jacobi on [[0, C], [C^T, 0]]); FDA the eigen-decomposition of
+// L^-1 (W^T S_B W) L^-T.  Rotations R_b = L_b^-T (singular/eigen vectors)
+// are stored in the KK_ROT slots, sigma (descending) in sigma_out.
+__global__ void __launch_bounds__(64) k_ctrl_final(ProbView p, double* sigma_out) {
+  extern __shared__ double sm[];
+  __shared__ WaveJacobiScratch jsc;
+  __shared__ int order[64];
+  const int k = p.k, nb = p.nb, lane = threadIdx.x;
+  const int kk2 = k * k;
+  const int slices = p.part_slices;
+  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);
+  double* G[2] = {sm, sm + 3 * kk2};
+  double* Li[2] = {sm + kk2, sm + 4 * kk2};
+  double* Cu[2] = {sm + 2 * kk2, sm + 5 * kk2};
+  for (int b = 0; b < nb; ++b) {
+    const double* part = p.part + b * side_stride;
+    sum_block(part, slices, 1, 3, k, 0, 0, 1.0, G[b], lane, 64, false);
+    sum_block(part, slices, 1, 3, k, 0, 1, p.s[b].lam, G[b], lane, 64, true);
+    sum_block(part, slices, 1, 3, k, 0, 2, 1.0, Cu[b], lane, 64, false);
+  }
+  wave_sync();
+  for (int b = 0; b < nb; ++b) {
+    for (int e = lane; e < kk2; e += 64) {
+      const int i = e / k, j = e - i * k;
+      if (i < j) {
+        const double v = 0.5 * (G[b][i * k + j] + G[b][j * k + i]);
+        G[b][i * k + j] = v;
+        G[b][j * k + i] = v;
+      }
+    }
+    wave_sync();
+    if (!wave_chol(G[b], k, lane)) {
+      if (lane == 0) { p.ctrl->status = SRP_ENOTSPD; p.ctrl->done = 1; }
+      return;
+    }
+    wave_lower_inv(G[b], Li[b], k, lane);
+  }
+  // Cw = Li_0 Cu Li_1^T  (FDA: Li Cu Li^T)
+  double* Cw = sm + 6 * kk2;
+  double* Tm = Cw + kk2;
+  const double* Lx = Li[0];
+  const double* Ly = Li[nb == 2 ? 1 : 0];
+  for (int e = lane; e < kk2; e += 64) {
+    const int i = e / k, j = e - i * k;
+    double s = 0.0;
+    for (int l = 0; l <= i; ++l) s += Lx[i * k + l] * Cu[0][l * k + j];
+    Tm[e] = s;
+  }
+  wave_sync();
+  for (int e = lane; e < kk2; e += 64) {
+    const int i = e / k, j = e - i * k;
+    double s = 0.0;
+    for (int l = 0; l <= j; ++l) s += Tm[i * k + l] * Ly[j * k + l];
+    Cw[e] = s;
+  }
+  wave_sync();
+  const int m = p.lda_cost ? ((k + 1) & ~1) : 2 * k;  // even Jacobi size
+  double* JA = Tm + kk2;
+  double* JV = JA + m * m;
+  double* JT = JV + m * m;
+  for (int e = lane; e < m * m; e += 64) {
+    const int i = e / m, j = e - i * m;
+    double v = 0.0;
+    if (p.lda_cost) {
+      if (i < k && j < k) v = 0.5 * (Cw[i * k + j] + Cw[j * k + i]);
+      else v = (i == j) ? -1e300 : 0.0;   // padding sorts last
+    } else {
+      if (i < k && j >= k) v = Cw[i * k + (j - k)];
+      else if (i >= k && j < k) v = Cw[j * k + (i - k)];
+    }
+    JA[e] = v;
+  }
+  wave_sync();
+  wave_jacobi(JA, JV, JT, m, lane, jsc);
+  // order eigenvalues descending (rank of each by counting)
+  if (lane < m) {
+    const double vi = JA[lane * m + lane];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const double vj = JA[j * m + j];
+      rank += (vj > vi) || (vj == vi && j < lane);
+    }
+    order[rank] = lane;
+  }
+  wave_sync();
+  // rotations: R_0 = Lx^T P_k, R_1 = Ly^T Q_k (CCA eigenvectors [a; b] scaled by sqrt 2)
+  const double scl = p.lda_cost ? 1.0 : sqrt(2.0);
+  for (int b = 0; b < nb; ++b) {
+    double* R = kkslot(p, b, KK_ROT);
+    const double* Lb = Li[b];
+    const int off = (p.lda_cost || b == 0) ? 0 : k;
+    for (int e = lane; e < kk2; e += 64) {
+      const int i = e / k, j = e - i * k;
+      const int col = order[j];
+      double s = 0.0;
+      for (int l = i; l < k; ++l) s += Lb[l * k + i] * JV[(off + l) * m + col];
+      R[e] = scl * s;
+    }
+  }
+  if (lane < k) sigma_out[lane] = JA[order[lane] * m + order[lane]];
+  if (lane == 0) {
+    double f = 0.0;
+    for (int i = 0; i < k; ++i) f += p.mu[i] * JA[order[i] * m + order[i]];
+    p.ctrl->f = p.lda_cost ? -0.5 * f : -f;
+  }
+}
+
+int launch_ctrl_final(const ProbView& p, double* sigma_out, hipStream_t st) {
+  const int k = p.k;
+  const int m = p.lda_cost ? ((k + 1) & ~1) : 2 * k;
+  const size_t lds = (size_t)(8 * k * k + 4 * m * m) * sizeof(double);
+  SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_ctrl_final, dim3(1), dim3(64), lds, st, p, sigma_out);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// U_b <- U_b R_b (rows in place).
+template <int KC>
+__global__ void __launch_bounds__(256) k_apply_rot(ProbView p) {
+  const int b = blockIdx.y;
+  const SideView& s = p.s[b];
+  const int k = p.k;
+  __shared__ double R[KC * KC];
+  const double* gR = kkslot(p, b, KK_ROT);
+  for (int e = threadIdx.x; e < k * k; e += 256) R[e] = gR[e];
+  __syncthreads();
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= s.d) return;
+  double* Ui = s.U + (int64_t)i * k;
+  double v[KC];
+#pragma unroll
+  for (int j = 0; j < KC; ++j) v[j] = (j < k) ? Ui[j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < KC; ++j)
+    if (j < k) {
+      double a = 0.0;
+#pragma unroll
+      for (int l = 0; l < KC; ++l)
+        if (l < k) a += v[l] * R[l * k + j];
+      Ui[j] = a;
+    }
+}
+
+int launch_apply_rot(const ProbView& p, hipStream_t st) {
+  const int dmax = p.nb == 2 ? (p.s[0].d > p.s[1].d ? p.s[0].d : p.s[1].d) : p.s[0].d;
+  dim3 grid((dmax + 255) / 256, p.nb);
+  if (p.k <= 16) hipLaunchKernelGGL((k_apply_rot<16>), grid, dim3(256), 0, st, p);
+  else hipLaunchKernelGGL((k_apply_rot<32>), grid, dim3(256), 0, st, p);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// Sign convention: flip column j of every block so that the entry of
+// largest magnitude in U_0[:, j] is positive (ties: lowest index).
+__global__ void __launch_bounds__(256) k_sign_fix(ProbView p) {
+  const int j = blockIdx.x, k = p.k;
+  const SideView& s0 = p.s[0];
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  double best = -1.0;
+  int idx = 0x7fffffff;
+  for (int i = threadIdx.x; i < s0.d; i += 256) {
+    const double v = fabs(s0.U[(int64_t)i * k + j]);
+    if (v > best) { best = v; idx = i; }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      const double a = bv[threadIdx.x + off];
+      const int ai = bi[threadIdx.x + off];
+      if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ai < bi[threadIdx.x])) {
+        bv[threadIdx.x] = a;
+        bi[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = s0.U[(int64_t)bi[0] * k + j] < 0.0;
+  if (!flip) return;
+  for (int b = 0; b < p.nb; ++b) {
+    const SideView& s = p.s[b];
+    for (int i = threadIdx.x; i < s.d; i += 256) s.U[(int64_t)i * k + j] = -s.U[(int64_t)i * k + j];
+  }
+}
+
+int launch_sign_fix(const ProbView& p, hipStream_t st) {
+  hipLaunchKernelGGL(k_sign_fix, dim3(p.k), dim3(256), 0, st, p);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// ---------------------------------------------------------- misc
+// Standard normal draws: Box-Muller on two SplitMix64 outputs per entry.
+__global__ void k_gauss_fill(double* p, int64_t count, uint64_t seed) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t w1 = splitmix64(seed, 2 * (uint64_t)i), w2 = splitmix64(seed, 2 * (uint64_t)i + 1);
+  const double u1 = ((double)(w1 >> 11) + 1.0) * 0x1.0p-53;  // (0, 1]
+  const double u2 = (double)(w2 >> 11) * 0x1.0p-53;          // [0, 1)
+  p[i] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+
+int launch_gauss_fill(double* p, int64_t count, uint64_t seed, hipStream_t st) {
+  hipLaunchKernelGGL(k_gauss_fill, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, seed);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+__global__ void k_ctrl_init(SolverCtrl* c, double tol, int max_iter) {
+  c->t = 0.0; c->t_guess = 0.0; c->f = 0.0; c->gg = 0.0; c->gg_old = 0.0; c->df0 = 0.0;
+  c->beta = 0.0; c->tol = tol; c->done = 0; c->status = SRP_OK; c->iter = 0; c->max_iter = max_iter;
+  c->restart = 1; c->ls_fail = 0; c->fixed_step = 1; c->pad = 0;
+}
+
+int launch_ctrl_init(SolverCtrl* c, double tol, int max_iter, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, st, c, tol, max_iter);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+__global__ void k_set_fixed(SolverCtrl* c, int on) {
+  c->fixed_step = on;
+  c->done = 0;
+  c->status = SRP_OK;
+  c->restart = 1;
+}
+
+int launch_set_fixed_step(SolverCtrl* c, int on, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_fixed, dim3(1), dim3(1), 0, st, c, on);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+}  // namespace srp

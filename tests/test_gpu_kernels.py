@@ -1,0 +1,149 @@
+"""Kernel-level parity of the HIP library (through the C ABI) against the
+FP64 oracle's definitions, on seeded inputs spanning several tiles and a
+ragged tail.  Floating-point bounds come from the standard summation
+bound |fl(sum a_i) - sum a_i| <= (m - 1) u sum |a_i| with the oracle
+computing the magnitudes; integer work (hash buckets, sampled rows) is
+bit-exact."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import sketch as osk, stiefel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda"
+U32, U64 = 2.0 ** -24, 2.0 ** -53
+TORCH_DT = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+
+
+def _srp():
+    import paper_2106_12060_amd as srp
+    return srp
+
+
+def quantised(X, dt):
+    """Device tensor of X in dtype dt and the exact FP64 values it holds."""
+    t = torch.from_numpy(np.ascontiguousarray(X)).to(DEV, TORCH_DT[dt])
+    return t, t.double().cpu().numpy()
+
+
+def rand_data(n, d, seed, decades=2.0):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, d)) * synth.column_scales(d, decades, True)[None, :]
+
+
+# ------------------------------------------------------------ CountSketch
+@pytest.mark.parametrize("n,d,s,dt", [(1000, 37, 50, "f64"), (5003, 300, 700, "f32"),
+                                      (777, 5, 13, "f32"), (2048, 70, 100, "bf16"),
+                                      (1, 3, 1, "f64"), (4096, 1, 4096, "f32")])
+def test_countsketch_matches_definition(n, d, s, dt):
+    srp = _srp()
+    seed = 1000 + n + s
+    X, Xq = quantised(rand_data(n, d, seed), dt)
+    out = srp.srp_countsketch(X, s, seed).double().cpu().numpy()
+    h, g = osk.countsketch_hash(n, s, seed)
+    ref = osk.countsketch_apply(Xq, h, g, s)
+    mag = osk.countsketch_apply(np.abs(Xq), h, np.abs(g), s)
+    m = np.bincount(h, minlength=s).astype(float)[:, None]
+    u = U64 if dt == "f64" else U32
+    bound = np.maximum(m - 1, 0) * u * mag + 1e-300
+    assert np.all(np.abs(out - ref) <= bound)
+
+
+def test_countsketch_bitwise_reproducible():
+    srp = _srp()
+    X, _ = quantised(rand_data(20000, 130, 7), "f32")
+    a = srp.srp_countsketch(X, 900, 99)
+    b = srp.srp_countsketch(X, 900, 99)
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ SRHT
+@pytest.mark.parametrize("n,s", [(2000, 240), (200_000, 4000), (13, 16), (1, 2), (1 << 12, 1 << 12),
+                                 (70_000, 5)])
+def test_srht_rows_bit_exact(n, s):
+    srp = _srp()
+    seed = 31 + n
+    rows = srp.srp_srht_rows(n, s, seed).cpu().numpy()
+    ref = osk.srht_rows(osk.srht_padded_rows(n), s, seed)
+    np.testing.assert_array_equal(rows, ref)
+
+
+@pytest.mark.parametrize("n,d,s,dt", [(3000, 40, 300, "f64"), (3001, 129, 257, "f32"),
+                                      (700, 16, 1024, "f32"), (5000, 33, 64, "bf16")])
+def test_srht_matches_definition(n, d, s, dt):
+    srp = _srp()
+    seed = 77 + d
+    X, Xq = quantised(rand_data(n, d, seed), dt)
+    out = srp.srp_srht(X, s, seed).double().cpu().numpy()
+    n_pad = osk.srht_padded_rows(n)
+    D = osk.srht_signs(n_pad, seed)
+    rows = osk.srht_rows(n_pad, s, seed)
+    ref = osk.srht_apply(Xq, D, rows, s)
+    mag = np.abs(Xq).sum(axis=0)[None, :] / np.sqrt(s)
+    u = U64 if dt == "f64" else U32
+    levels = int(np.log2(n_pad)) + (n_pad >> ((int(np.log2(n_pad)) + 1) // 2))
+    assert np.all(np.abs(out - ref) <= levels * u * mag + 1e-300)
+
+
+def test_srht_full_sample_is_isometry():
+    srp = _srp()
+    X, Xq = quantised(rand_data(1000, 12, 5), "f64")
+    SX = srp.srp_srht(X, 1024, 5).cpu().numpy()
+    np.testing.assert_allclose(SX.T @ SX, Xq.T @ Xq, rtol=1e-12, atol=1e-10)
+
+
+# ------------------------------------------------------- metric factor R
+@pytest.mark.parametrize("s,d,dt,lam", [(500, 120, "f64", 1e-3), (900, 200, "f32", 1e-2),
+                                        (64, 64, "f64", 0.5), (300, 65, "f32", 1e-4)])
+def test_sketch_factor_matches_cholesky(s, d, dt, lam):
+    srp = _srp()
+    SA, SAq = quantised(rand_data(s, d, 11 + d, decades=1.0), dt)
+    R, Rinv = srp.srp_sketch_factor(SA, lam)
+    R = R.cpu().numpy()
+    Rinv = Rinv.cpu().numpy()
+    ref = osk.sketch_factor(SAq, lam)
+    assert np.allclose(np.tril(R, -1), 0.0) and np.all(np.diag(R) > 0)
+    G = SAq.T @ SAq + lam * np.eye(d)
+    kappa = np.linalg.cond(G)
+    assert np.max(np.abs(R.T @ R - G)) <= 1e-13 * d * np.max(np.abs(G))
+    assert np.max(np.abs(R - ref)) <= 1e-14 * kappa * np.max(np.abs(ref))
+    np.testing.assert_allclose(Rinv @ R, np.eye(d), atol=1e-13 * np.sqrt(kappa) * d)
+
+
+def test_sketch_factor_reports_not_spd():
+    srp = _srp()
+    SA = torch.zeros((40, 8), dtype=torch.float64, device=DEV)
+    with pytest.raises(srp.SrpError) as e:
+        srp.srp_sketch_factor(SA, 0.0)
+    assert e.value.code == srp.SRP_ENOTSPD
+
+
+# ----------------------------------------------------------- data pass
+@pytest.mark.parametrize("n,d0,d1,k,dt,comp", [(3000, 70, 45, 7, "f64", "f64"), (5001, 130, 200, 10, "f32", "f32"),
+                                               (4097, 300, 0, 19, "f32", "f32"), (999, 17, 33, 16, "f32", "f64"),
+                                               (2000, 1000, 1000, 10, "f32", "f32"), (64, 5, 3, 1, "f64", "f64"),
+                                               (3333, 2000, 0, 19, "f32", "f32"), (1500, 90, 60, 5, "bf16", "f32")])
+def test_gram_pass_matches_products(n, d0, d1, k, dt, comp):
+    srp = _srp()
+    rng = np.random.default_rng(n + d0)
+    A0, A0q = quantised(rand_data(n, d0, n), dt)
+    W0 = rng.standard_normal((d0, k))
+    W0t = torch.from_numpy(W0).to(DEV)
+    if d1:
+        A1, A1q = quantised(rand_data(n, d1, n + 1), dt)
+        W1 = rng.standard_normal((d1, k))
+        W1t = torch.from_numpy(W1).to(DEV)
+        J, Jabs = stiefel.data_products(A0q, W0, A1q, W1)
+        G0, G1 = srp.srp_gram_pass(A0, W0t, A1, W1t, compute=comp)
+        got = [G0.cpu().numpy(), G1.cpu().numpy()]
+    else:
+        J, Jabs = stiefel.data_products(A0q, W0)
+        G0, _ = srp.srp_gram_pass(A0, W0t, compute=comp)
+        got = [G0.cpu().numpy()]
+    u = U64 if comp == "f64" else U32
+    for g, ref, mag in zip(got, J, Jabs):
+        bound = (d0 + d1 + n + 2) * u * mag + 1e-300
+        assert np.all(np.abs(g - ref) <= bound), np.max(np.abs(g - ref) / bound)

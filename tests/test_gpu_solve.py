@@ -1,0 +1,164 @@
+"""End-to-end parity of cca_solve / lda_solve (through the C ABI) against
+the FP64 oracle's closed forms: objective, constraint residual, correlations
+and, where the spectrum pins them, the weight vectors themselves."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, metrics
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda"
+
+
+def _srp():
+    import paper_2106_12060_amd as srp
+    return srp
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return t if dtype is None else t.to(dtype)
+
+
+def cca_errors(U, V, X, Y, lam, sig_true):
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    err = metrics.cca_rel_objective_error(Uh, Vh, X, Y, lam, lam, sig_true)
+    cons = max(metrics.constraint_residual(Uh, X, lam), metrics.constraint_residual(Vh, Y, lam))
+    return err, cons
+
+
+def test_cca_f64_small_workload():
+    """FP64 CCA, n=2000, dx=60, dy=40, k=5, lambda=1e-3, CountSketch s=240.
+    The latent rank (8) exceeds k, so the top correlations form a cluster
+    about 1e-4 wide that the k-cut splits: the weighted cost converges at a
+    rate set by those gaps (Theorem CCAHessiantheorem), and 2000 iterations
+    reach ~3e-8; the bound below is set there."""
+    srp = _srp()
+    wl = synth.workload("cca-f64-small")
+    X, Y = wl.generate()
+    lam = wl.lam_value
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), wl.k, lam, lam, wl.s, tol=1e-12,
+                                    options=srp.srp_default_options(max_iter=2000))
+    err, cons = cca_errors(U, V, X, Y, lam, sig_true)
+    print("cca-f64-small", info, err, cons)
+    assert cons < 1e-12
+    assert err < 1e-7
+    np.testing.assert_allclose(sig.cpu().numpy(), sig_true[:wl.k], rtol=0, atol=1e-6)
+    assert np.all(np.diff(sig.cpu().numpy()) <= 0)
+
+
+def test_cca_planted_vectors_pinned():
+    """lambda = 0, planted distinct correlations: the weights are pinned
+    (A^-1, B^-1 columns) and sigma = rho."""
+    srp = _srp()
+    rho = np.array([0.95, 0.85, 0.7, 0.5, 0.3, 0.1])
+    X, Y, A, B = synth.planted_cca(4000, 6, rho, seed=5)
+    k = 4
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), k, 0.0, 0.0, 60, tol=1e-13,
+                                    options=srp.srp_default_options(max_iter=3000))
+    np.testing.assert_allclose(sig.cpu().numpy(), rho[:k], atol=1e-9)
+    Ai, Bi = np.linalg.inv(A), np.linalg.inv(B)
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    for i in range(k):
+        j = int(np.argmax(np.abs(Ai[:, i])))
+        sgn = np.sign(Ai[j, i])
+        np.testing.assert_allclose(Uh[:, i], sgn * Ai[:, i], atol=1e-7 * np.abs(Ai).max())
+        np.testing.assert_allclose(Vh[:, i], sgn * Bi[:, i], atol=1e-7 * np.abs(Bi).max())
+
+
+@pytest.mark.parametrize("sketch", ["srht", "countsketch"])
+def test_cca_f32_scaled_workload(sketch):
+    """FP32 CCA with the column-scaled latent recipe (10^(-4j/d)) at a size
+    the oracle solves in seconds, latent rank = k so that the top-k block is
+    separated from the rest: relative objective error <= 1e-6."""
+    import dataclasses
+    srp = _srp()
+    wl = dataclasses.replace(synth.workload("cca-f32-srht").scaled(n=30_000, dx=200, dy=160, s=800), r=10)
+    X, Y = wl.generate()
+    lam = wl.lam_value
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    opt = srp.srp_default_options(sketch=sketch, max_iter=300)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), wl.k, lam, lam, wl.s, tol=1e-5, options=opt)
+    err, cons = cca_errors(U, V, X.astype(np.float64), Y.astype(np.float64), lam, sig_true)
+    print(sketch, info, err, cons)
+    assert err < 1e-6
+    assert cons < 1e-6
+
+
+def test_cca_f32_clustered_workload():
+    """Same recipe with latent rank 32 > k = 10: the k-cut splits a cluster of
+    correlations a few 1e-6 apart, so convergence in the objective is slow
+    (the CPU prototype of the same iteration needs > 300 iterations for
+    1e-6); checked at a looser 1e-5 after 300 iterations."""
+    srp = _srp()
+    wl = synth.workload("cca-f32-srht").scaled(n=30_000, dx=200, dy=160, s=800)
+    X, Y = wl.generate()
+    lam = wl.lam_value
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    opt = srp.srp_default_options(sketch="srht", max_iter=300)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), wl.k, lam, lam, wl.s, tol=1e-6, options=opt)
+    err, cons = cca_errors(U, V, X.astype(np.float64), Y.astype(np.float64), lam, sig_true)
+    print("clustered", info, err, cons)
+    assert err < 1e-5
+    assert cons < 1e-6
+
+
+def test_lda_scaled_workload():
+    srp = _srp()
+    wl = synth.workload("lda-f32")
+    n, d = 20_000, 200
+    X, y = synth.lda_classes(n, d, wl.c, seed=wl.seed, dtype=np.float32)
+    lam = synth.lda_population_lambda(n, d)
+    k = wl.c - 1
+    rho_true, _ = direct.lda_direct(X, y, wl.c, lam, k=k)
+    W, rho, info = srp.lda_solve(dev(X), dev(y), wl.c, k, lam, 800, tol=1e-6,
+                                 options=srp.srp_default_options(max_iter=500))
+    _, _, _, Xh, Yh = direct.lda_scatter(X, y, wl.c)
+    err = metrics.lda_rel_objective_error(W.cpu().numpy(), Xh, Yh, lam, rho_true)
+    cons = metrics.constraint_residual(W.cpu().numpy(), Xh, lam)
+    print("lda", info, err, cons)
+    assert err < 1e-6
+    assert cons < 1e-6
+
+
+def test_lda_f64_two_classes_closed_form():
+    srp = _srp()
+    rng = np.random.default_rng(3)
+    n1, n2, d = 600, 1000, 24
+    X = rng.standard_normal((n1 + n2, d))
+    X[:n1] += 0.7
+    y = np.array([0] * n1 + [1] * n2, dtype=np.int32)
+    lam = 0.1
+    rho_true, W_true = direct.lda_direct(X, y, 2, lam, k=1)
+    W, rho, info = srp.lda_solve(dev(X), dev(y), 2, 1, lam, 96, tol=1e-12)
+    assert abs(rho.item() - rho_true[0]) < 1e-9 * rho_true[0]
+    np.testing.assert_allclose(W.cpu().numpy()[:, 0], W_true[:, 0], rtol=1e-7, atol=1e-9)
+
+
+def test_cca_rejects_bad_arguments():
+    srp = _srp()
+    X = torch.zeros((100, 6), dtype=torch.float64, device=DEV)
+    Y = torch.zeros((100, 4), dtype=torch.float64, device=DEV)
+    with pytest.raises(srp.SrpError) as e:
+        srp.cca_solve(X, Y, 5, 0.1, 0.1, 20)          # k > min(dx, dy)
+    assert e.value.code == srp.SRP_EINVAL
+    with pytest.raises(srp.SrpError) as e:
+        srp.cca_solve(X, Y, 2, 0.1, 0.1, 5)           # s < max(dx, dy)
+    assert e.value.code == srp.SRP_EINVAL
+    with pytest.raises(srp.SrpError) as e:
+        srp.cca_solve(X, Y, 2, -1.0, 0.1, 20)         # lambda < 0
+    assert e.value.code == srp.SRP_EINVAL
+
+
+def test_cca_rank_deficient_without_regularisation():
+    srp = _srp()
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((500, 3)) @ rng.standard_normal((3, 8))   # rank 3 < 8
+    Y = rng.standard_normal((500, 5))
+    with pytest.raises(srp.SrpError) as e:
+        srp.cca_solve(dev(X), dev(Y), 2, 0.0, 0.0, 40)
+    assert e.value.code == srp.SRP_ENOTSPD
