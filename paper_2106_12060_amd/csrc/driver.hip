@@ -254,10 +254,9 @@ static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int c
     if (B.time_passes && B.events) {
       SRP_HIP(hipEventCreate(&e0));
       SRP_HIP(hipEventCreate(&e1));
-      SRP_HIP(hipEventRecord(e0, st));
     }
     SRP_TRY(gram_pass_run(P.A[0], P.nb == 2 ? P.A[1] : nullptr, P.dtype, compute, P.n, P.d[0], P.d[1], P.k, W[0],
-                          P.nb == 2 ? W[1] : nullptr, B.J[0], P.nb == 2 ? B.J[1] : nullptr, done, pw, st, e1));
+                          P.nb == 2 ? W[1] : nullptr, B.J[0], P.nb == 2 ? B.J[1] : nullptr, done, pw, st, e0, e1));
     if (e0) B.events->push_back({e0, e1});
   }
   if (P.lda_cost) SRP_TRY(gemm_skinny_f64(P.d[0], P.k, P.SB, P.d[0], W[0], P.k, B.Jc[0], P.k, st));

@@ -53,7 +53,8 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
 size_t pass_ws_bytes(int64_t n, int d0, int d1, int k, int compute);
 int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1,
                   int k, const double* W0, const double* W1, double* J0, double* J1, const int* done,
-                  Arena& ws, hipStream_t st, hipEvent_t after_pass = nullptr);
+                  Arena& ws, hipStream_t st, hipEvent_t before_pass = nullptr,
+                  hipEvent_t after_pass = nullptr);
 // FDA centring (Section 5.1): class counts and FP64 sums, Yhat rows
 // sqrt(n_k)(m_k - m), and the materialised Xhat = X - m_{y_i} in the data
 // type.  Returns SRP_EINVAL (via *bad) for labels out of range.

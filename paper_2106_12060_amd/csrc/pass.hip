@@ -339,7 +339,7 @@ size_t pass_ws_bytes(int64_t n, int d0, int d1, int k, int compute) {
 template <class DT, class CT, int NB, int KT>
 static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, int k, const double* W0,
                        const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
-                       hipEvent_t after_pass) {
+                       hipEvent_t before_pass, hipEvent_t after_pass) {
   const int dp0 = (d0 + 15) / 16 * 16, dp1 = NB == 2 ? (d1 + 15) / 16 * 16 : 0;
   const int KP = KT * 16;
   CT* Wp0 = ws.take<CT>((size_t)dp0 * KP);
@@ -363,6 +363,7 @@ static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, in
                                 kPassLds));
     attr_done = true;
   }
+  if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
   hipLaunchKernelGGL((k_pass<DT, CT, NB, KT>), dim3(grid), dim3(kPassThreads), lds, st, A0, A1, n, d0,
                      NB == 2 ? d1 : 0, k, Wp0, Wp1, nrb, part, done);
   SRP_LAUNCH_CHECK();
@@ -377,15 +378,15 @@ static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, in
 template <class DT, class CT>
 static int pass_dispatch_k(const DT* A0, const DT* A1, int64_t n, int d0, int d1, int k, const double* W0,
                            const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
-                           hipEvent_t ev) {
-  if (A1) return pass_launch<DT, CT, 2, 1>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev);
-  if (k <= 16) return pass_launch<DT, CT, 1, 1>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev);
-  return pass_launch<DT, CT, 1, 2>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev);
+                           hipEvent_t ev0, hipEvent_t ev) {
+  if (A1) return pass_launch<DT, CT, 2, 1>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+  if (k <= 16) return pass_launch<DT, CT, 1, 1>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+  return pass_launch<DT, CT, 1, 2>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
 }
 
 int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1, int k,
                   const double* W0, const double* W1, double* J0, double* J1, const int* done, Arena& ws,
-                  hipStream_t st, hipEvent_t after_pass) {
+                  hipStream_t st, hipEvent_t before_pass, hipEvent_t after_pass) {
   const int nb = A1 ? 2 : 1;
   if (!pass_limits_ok(dtype, compute, d0, d1, k, nb)) {
     set_error("gram_pass: unsupported shape (d0=%d d1=%d k=%d dtype=%d compute=%d)", d0, d1, k, dtype, compute);
@@ -393,14 +394,14 @@ int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_
   }
   if (compute == SRP_F64) {
     switch (dtype) {
-      case SRP_F64: return pass_dispatch_k<double, double>((const double*)A0, (const double*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
-      case SRP_F32: return pass_dispatch_k<float, double>((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
-      case SRP_BF16: return pass_dispatch_k<bf16, double>((const bf16*)A0, (const bf16*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
+      case SRP_F64: return pass_dispatch_k<double, double>((const double*)A0, (const double*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, before_pass, after_pass);
+      case SRP_F32: return pass_dispatch_k<float, double>((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, before_pass, after_pass);
+      case SRP_BF16: return pass_dispatch_k<bf16, double>((const bf16*)A0, (const bf16*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, before_pass, after_pass);
     }
   } else {
     switch (dtype) {
-      case SRP_F32: return pass_dispatch_k<float, float>((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
-      case SRP_BF16: return pass_dispatch_k<bf16, float>((const bf16*)A0, (const bf16*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, after_pass);
+      case SRP_F32: return pass_dispatch_k<float, float>((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, before_pass, after_pass);
+      case SRP_BF16: return pass_dispatch_k<bf16, float>((const bf16*)A0, (const bf16*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, before_pass, after_pass);
     }
   }
   set_error("gram_pass: bad dtype/compute (%d/%d)", dtype, compute);
