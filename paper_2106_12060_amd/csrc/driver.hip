@@ -104,12 +104,16 @@ struct RcgProblem {
   int d[2] = {0, 0};
   double lam[2] = {0.0, 0.0};
   const double* Minv[2] = {nullptr, nullptr};
-  const double* SB = nullptr;   // FDA: d x d
+  const double* Yhat = nullptr;  // FDA: c x d rows sqrt(n_j)(m_j - m); S_B = Yhat^T Yhat
+  int c = 0;
 };
 
 struct RcgBuffers {
   double *U[2], *Ks[2], *Kc[2], *xi[2], *gold[2], *J[2], *Jc[2], *Z[2], *Wz[2];
   double* Pn = nullptr;      // two-pass route: n x 2k
+  double* skw = nullptr;     // split-K partials of the skinny products
+  size_t skw_bytes = 0;
+  double* Tc = nullptr;      // FDA: Yhat W (c x k)
   double* parts = nullptr;   // two-pass route: split-k partials
   int ksplit = 1;
   SolverCtrl* ctrl;
@@ -132,8 +136,15 @@ static int twopass_ksplit(int64_t n) {
   return (int)ks;
 }
 
-static size_t rcg_buffers_bytes(int nb, int k, int64_t nmax, const int* d, int dtype) {
+static size_t skinny_bytes(int nb, int k, const int* d, int c) {
   size_t b = 0;
+  for (int s = 0; s < nb; ++s) b = std::max(b, skinny_ws_bytes(d[s], d[s], 2 * k));
+  if (c > 0) b = std::max({b, skinny_ws_bytes(c, d[0], k), skinny_ws_bytes(d[0], c, k)});
+  return b;
+}
+
+static size_t rcg_buffers_bytes(int nb, int k, int64_t nmax, const int* d, int dtype, int c = 0) {
+  size_t b = skinny_bytes(nb, k, d, c) + bytes_of<double>((size_t)std::max(c, 1) * k);
   for (int s = 0; s < nb; ++s) {
     const size_t dk = (size_t)d[s] * k;
     b += 6 * bytes_of<double>(dk) + bytes_of<double>((size_t)d[s] * nb * k) + 2 * bytes_of<double>(2 * dk);
@@ -151,7 +162,10 @@ static size_t rcg_buffers_bytes(int nb, int k, int64_t nmax, const int* d, int d
   return b;
 }
 
-static int rcg_buffers_take(RcgBuffers& B, Arena& ar, int nb, int k, int64_t nmax, const int* d) {
+static int rcg_buffers_take(RcgBuffers& B, Arena& ar, int nb, int k, int64_t nmax, const int* d, int c = 0) {
+  B.skw_bytes = skinny_bytes(nb, k, d, c);
+  B.skw = (double*)ar.take<char>(B.skw_bytes);
+  B.Tc = ar.take<double>((size_t)std::max(c, 1) * k);
   for (int s = 0; s < nb; ++s) {
     const size_t dk = (size_t)d[s] * k;
     B.U[s] = ar.take<double>(dk);
@@ -178,7 +192,7 @@ static int rcg_buffers_take(RcgBuffers& B, Arena& ar, int nb, int k, int64_t nma
   B.ksplit = twopass_ksplit(nmax);
   B.Pn = ar.take<double>((size_t)nmax * nb * k);
   B.parts = ar.take<double>((size_t)B.ksplit * std::max(d[0], nb == 2 ? d[1] : 0) * nb * k);
-  if (!B.ctrl || !B.kk || !B.part || !B.mu || !B.pass_ws || !B.Pn || !B.parts) return SRP_ENOMEM;
+  if (!B.ctrl || !B.kk || !B.part || !B.mu || !B.pass_ws || !B.Pn || !B.parts || !B.skw || !B.Tc) return SRP_ENOMEM;
   return SRP_OK;
 }
 
@@ -259,13 +273,17 @@ static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int c
                           P.nb == 2 ? W[1] : nullptr, B.J[0], P.nb == 2 ? B.J[1] : nullptr, done, pw, st, e0, e1));
     if (e0) B.events->push_back({e0, e1});
   }
-  if (P.lda_cost) SRP_TRY(gemm_skinny_f64(P.d[0], P.k, P.SB, P.d[0], W[0], P.k, B.Jc[0], P.k, st));
+  if (P.lda_cost) {   // S_B W = Yhat^T (Yhat W): c-row factor instead of the d x d matrix
+    SRP_TRY(gemm_skinny_f64(P.c, P.d[0], P.k, P.Yhat, P.d[0], false, W[0], P.k, B.Tc, P.k, B.skw, B.skw_bytes, st));
+    SRP_TRY(gemm_skinny_f64(P.d[0], P.c, P.k, P.Yhat, P.d[0], true, B.Tc, P.k, B.Jc[0], P.k, B.skw, B.skw_bytes, st));
+  }
   return SRP_OK;
 }
 
 static int apply_minv(const RcgProblem& P, RcgBuffers& B, hipStream_t st) {
   for (int s = 0; s < P.nb; ++s)
-    SRP_TRY(gemm_skinny_f64(P.d[s], 2 * P.k, P.Minv[s], P.d[s], B.Z[s], 2 * P.k, B.Wz[s], 2 * P.k, st));
+    SRP_TRY(gemm_skinny_f64(P.d[s], P.d[s], 2 * P.k, P.Minv[s], P.d[s], false, B.Z[s], 2 * P.k, B.Wz[s], 2 * P.k,
+                            B.skw, B.skw_bytes, st));
   return SRP_OK;
 }
 
@@ -587,11 +605,11 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   size_t bytes = 0;
   bytes += (((size_t)n * d * esz + 255) & ~size_t(255));          // Xhat
   bytes += (((size_t)s * d * ssz + 255) & ~size_t(255));          // sketch
-  bytes += 4 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv, S_B
+  bytes += 3 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv
   bytes += bytes_of<double>((size_t)c * d) + bytes_of<int>(c) + bytes_of<int>(4);
   const size_t scratch = std::max({sketch_ws(opt.sketch, n, d, s, dtype), factor_ws_bytes(s, d),
                                    lda_center_ws_bytes(n, d, c)});
-  bytes += rcg_buffers_bytes(1, k, std::max<int64_t>(n, s), dd, dtype);
+  bytes += rcg_buffers_bytes(1, k, std::max<int64_t>(n, s), dd, dtype, c);
   bytes += scratch + 4096;
   Workspace Wk;
   Wk.st = st;
@@ -602,28 +620,19 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   double* R = ar.take<double>((size_t)d * d);
   double* Rinv = ar.take<double>((size_t)d * d);
   double* Minv = ar.take<double>((size_t)d * d);
-  double* SB = ar.take<double>((size_t)d * d);
   double* Yhat = ar.take<double>((size_t)c * d);
   int* counts = ar.take<int>(c);
   int* flag = ar.take<int>(4);
   RcgBuffers B{};
-  if (!flag || rcg_buffers_take(B, ar, 1, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
+  if (!flag || rcg_buffers_take(B, ar, 1, k, std::max<int64_t>(n, s), dd, c) != SRP_OK) {
     set_error("workspace layout overflow");
     return SRP_ENOMEM;
   }
   SRP_TRY(setup_mu(opt, k, B.mu, st));
-  // 1. centring, S_B = Yhat^T Yhat
+  // 1. centring; S_B = Yhat^T Yhat stays factored
   {
     Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
     SRP_TRY(lda_center_run(X, labels, dtype, n, d, c, Xhat, Yhat, counts, flag + 1, sub, st));
-  }
-  {
-    GemmArgs g{};
-    g.m = d; g.n = d; g.kk = c; g.alpha = 1.0; g.beta = 0.0;
-    g.A = Yhat; g.lda = d; g.ta = true;
-    g.B = Yhat; g.ldb = d; g.tb = false;
-    g.C = SB; g.ldc = d;
-    SRP_TRY(gemm_f64(g, st));
   }
   int hc[64];
   int hbad = 0;
@@ -651,7 +660,8 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   const double ms_factor = tm.lap_ms();
   RcgProblem full;
   full.nb = 1; full.k = k; full.lda_cost = 1; full.dtype = dtype; full.compute = compute;
-  full.A[0] = Xhat; full.n = n; full.d[0] = d; full.lam[0] = lam; full.Minv[0] = Minv; full.SB = SB;
+  full.A[0] = Xhat; full.n = n; full.d[0] = d; full.lam[0] = lam; full.Minv[0] = Minv; full.Yhat = Yhat;
+  full.c = c;
   RcgProblem sk = full;
   sk.dtype = sk_dtype; sk.compute = (sk_dtype == SRP_F64) ? SRP_F64 : compute;
   sk.A[0] = SXh; sk.n = s;

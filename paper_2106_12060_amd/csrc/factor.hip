@@ -151,35 +151,48 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
 }
 
 // --------------------------------------------------------- skinny GEMM
-// C (m x nc) = A (m x m) B (m x nc), nc <= 64: the per-iteration products
-// with M^-1 (and S_B).  A workgroup owns 16 rows of A and streams them once;
-// B is staged through LDS in 64-row chunks.  Thread (r, jg) keeps the
+// C (m x nc) = op(A) (m x kk) B (kk x nc), nc <= 64: the per-iteration
+// products with M^-1 and the FDA between-class factor.  The contraction is
+// split over blockIdx.y into slices of kSkSlice; a workgroup owns 16 rows of
+// op(A) in its slice and streams them once through LDS together with the
+// matching rows of B, and writes a partial; a second kernel adds the
+// partials in slice order (deterministic).  Thread (r, jg) keeps the
 // columns jg, jg + 16, ... of row r.
 constexpr int kSkRows = 16;
 constexpr int kSkChunk = 64;
+constexpr int kSkSlice = 128;
 
-__global__ void __launch_bounds__(256) k_gemm_skinny(int m, int nc, const double* __restrict__ A, int64_t lda,
-                                                     const double* __restrict__ B, int64_t ldb,
-                                                     double* __restrict__ C, int64_t ldc) {
+__global__ void __launch_bounds__(256) k_gemm_skinny(int m, int kk, int nc, const double* __restrict__ A,
+                                                     int64_t lda, int ta, const double* __restrict__ B,
+                                                     int64_t ldb, double* __restrict__ part) {
   __shared__ double As[kSkRows][kSkChunk + 1];
   __shared__ double Bs[kSkChunk][64];
   const int r0 = blockIdx.x * kSkRows;
+  const int lbeg = blockIdx.y * kSkSlice, lend = min(kk, lbeg + kSkSlice);
   const int tid = threadIdx.x;
   const int r = tid >> 4, jg = tid & 15;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int l0 = 0; l0 < m; l0 += kSkChunk) {
-    for (int e = tid; e < kSkRows * kSkChunk; e += 256) {
-      const int rr = e / kSkChunk, ll = e % kSkChunk;
-      const int gr = r0 + rr, gl = l0 + ll;
-      As[rr][ll] = (gr < m && gl < m) ? A[(int64_t)gr * lda + gl] : 0.0;
+  for (int l0 = lbeg; l0 < lend; l0 += kSkChunk) {
+    if (ta) {
+      for (int e = tid; e < kSkRows * kSkChunk; e += 256) {
+        const int ll = e / kSkRows, rr = e % kSkRows;
+        const int gr = r0 + rr, gl = l0 + ll;
+        As[rr][ll] = (gr < m && gl < lend) ? A[(int64_t)gl * lda + gr] : 0.0;
+      }
+    } else {
+      for (int e = tid; e < kSkRows * kSkChunk; e += 256) {
+        const int rr = e / kSkChunk, ll = e % kSkChunk;
+        const int gr = r0 + rr, gl = l0 + ll;
+        As[rr][ll] = (gr < m && gl < lend) ? A[(int64_t)gr * lda + gl] : 0.0;
+      }
     }
     for (int e = tid; e < kSkChunk * nc; e += 256) {
       const int ll = e / nc, j = e % nc;
       const int gl = l0 + ll;
-      Bs[ll][j] = (gl < m) ? B[(int64_t)gl * ldb + j] : 0.0;
+      Bs[ll][j] = (gl < lend) ? B[(int64_t)gl * ldb + j] : 0.0;
     }
     __syncthreads();
-#pragma unroll 4
+#pragma unroll 8
     for (int ll = 0; ll < kSkChunk; ++ll) {
       const double a = As[r][ll];
 #pragma unroll
@@ -192,22 +205,52 @@ __global__ void __launch_bounds__(256) k_gemm_skinny(int m, int nc, const double
   }
   const int gr = r0 + r;
   if (gr < m) {
+    double* out = part + ((int64_t)blockIdx.y * m + gr) * nc;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = jg + 16 * q;
-      if (j < nc) C[(int64_t)gr * ldc + j] = acc[q];
+      if (j < nc) out[j] = acc[q];
     }
   }
 }
 
-int gemm_skinny_f64(int m, int nc, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-                    int64_t ldc, hipStream_t st) {
-  if (nc > 64) {
-    set_error("gemm_skinny: nc = %d > 64", nc);
+__global__ void __launch_bounds__(256) k_skinny_sum(int m, int nc, int nsl, const double* __restrict__ part,
+                                                    double* __restrict__ C, int64_t ldc) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t cnt = (int64_t)m * nc;
+  if (e >= cnt) return;
+  double s0 = 0.0, s1 = 0.0;
+  int z = 0;
+  for (; z + 2 <= nsl; z += 2) {
+    s0 += part[(int64_t)z * cnt + e];
+    s1 += part[(int64_t)(z + 1) * cnt + e];
+  }
+  if (z < nsl) s0 += part[(int64_t)z * cnt + e];
+  const int64_t row = e / nc, col = e % nc;
+  C[row * ldc + col] = s0 + s1;
+}
+
+size_t skinny_ws_bytes(int m, int kk, int nc) {
+  const size_t nsl = (size_t)(kk + kSkSlice - 1) / kSkSlice;
+  return bytes_of<double>(nsl * (size_t)m * nc);
+}
+
+int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
+                    double* C, int64_t ldc, double* ws, size_t ws_bytes, hipStream_t st) {
+  if (nc > 64 || nc < 1 || m < 1 || kk < 1) {
+    set_error("gemm_skinny: bad shape m=%d kk=%d nc=%d", m, kk, nc);
     return SRP_EINVAL;
   }
-  hipLaunchKernelGGL(k_gemm_skinny, dim3((m + kSkRows - 1) / kSkRows), dim3(256), 0, st, m, nc, A, lda, B, ldb, C,
-                     ldc);
+  const int nsl = (kk + kSkSlice - 1) / kSkSlice;
+  if (!ws || skinny_ws_bytes(m, kk, nc) > ws_bytes) {
+    set_error("gemm_skinny: workspace too small");
+    return SRP_ENOMEM;
+  }
+  hipLaunchKernelGGL(k_gemm_skinny, dim3((m + kSkRows - 1) / kSkRows, nsl), dim3(256), 0, st, m, kk, nc, A, lda,
+                     ta ? 1 : 0, B, ldb, ws);
+  SRP_LAUNCH_CHECK();
+  const int64_t cnt = (int64_t)m * nc;
+  hipLaunchKernelGGL(k_skinny_sum, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, m, nc, nsl, ws, C, ldc);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }

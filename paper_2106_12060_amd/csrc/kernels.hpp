@@ -34,9 +34,12 @@ struct GemmArgs {
   int64_t c_split_stride = 0;
 };
 int gemm_f64(const GemmArgs& g, hipStream_t st);
-// C (m x nc) = A (m x m) B (m x nc) for nc <= 64 (row-major, FP64).
-int gemm_skinny_f64(int m, int nc, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
-                    int64_t ldc, hipStream_t st);
+// C (m x nc) = op(A) (m x kk) B (kk x nc) for nc <= 64 (row-major, FP64;
+// op(A) = A^T when ta, A then kk x m).  ws holds the split-K partials
+// (skinny_ws_bytes).
+size_t skinny_ws_bytes(int m, int kk, int nc);
+int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
+                    double* C, int64_t ldc, double* ws, size_t ws_bytes, hipStream_t st);
 // out[i] = sum_z parts[z * stride + i] (+ diag_add on the diagonal of a
 // d x d matrix when d > 0), for count elements.
 int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count, double* out,

@@ -14,7 +14,10 @@
 // The block is staged in LDS (row-major, row pitch = 4 mod 64 elements so
 // both access patterns below are bank-conflict free); while the matrix
 // cores work on block i, the global loads of the workgroup's next block are
-// already in flight into registers.  Columns are cut into 16-wide tiles;
+// already in flight into registers.  The direction operands of a wave's
+// P tiles stay in registers for the whole launch when they fit (64 per
+// lane); otherwise they are re-read from L2 per block, before the next
+// block's loads are issued, so that a wait on them never waits on HBM.  Columns are cut into 16-wide tiles;
 // wave w owns tiles w, w+8, ...  For each block a wave
 //   (b) accumulates its tiles' share of P_b = A_b W_b (16 x k) on the matrix
 //       cores (A-operand lane: row = lane%16, column = 4 step + lane/16),
@@ -96,6 +99,8 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(const DT* __restrict__ A0
   constexpr int TPW = (DMAX / 16 + kPassWaves * kPassSplit - 1) / (kPassWaves * kPassSplit);
   constexpr int NT = NB * KT;
   constexpr int KP = KT * 16;
+  constexpr int TPB = (DMAX / 16 + kPassWaves - 1) / kPassWaves;        // P tiles per wave
+  constexpr bool WREG = TPB * 4 * KT * (int)sizeof(CT) <= 64 * 4;       // W operands in registers
   using acc_t = typename Acc4<CT>::type;
   extern __shared__ unsigned char pass_smem[];
   const int D = d0 + (NB == 2 ? d1 : 0);
@@ -127,6 +132,26 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(const DT* __restrict__ A0
   for (int i = 0; i < TPW; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  // direction operands of this wave's P tiles: tile t = w + 8 i, step s2
+  CT wreg[WREG ? TPB : 1][4][KT];
+  auto w_operand = [&](int t, int s2, int kt) __attribute__((always_inline)) -> CT {
+    const bool b1 = (NB == 2) && (t >= T0);
+    const int ct = b1 ? t - T0 : t;
+    const int soff = ((ct * 16 + 4 * s2) * KP + kt * 16) * (int)sizeof(CT);
+    return b1 ? buf_load<CT>(wr1, wvoff + soff, 0) : buf_load<CT>(wr0, wvoff + soff, 0);
+  };
+  if (WREG) {
+#pragma unroll
+    for (int i = 0; i < (WREG ? TPB : 1); ++i)
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+          const int t = w + kPassWaves * i;
+          wreg[i][s2][kt] = (t < TT) ? w_operand(t, s2, kt) : CT(0);
+        }
+  }
 
   // Row r of the block gets its own buffer resource (scalar), holding
   // exactly the d_b elements of that row, or none past row n; a lane reads
@@ -180,15 +205,17 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(const DT* __restrict__ A0
       }
     }
     __syncthreads();
-    if (rb + ngroups < nrb) prefetch(rb + ngroups);   // in flight during the math
+    if (WREG && rb + ngroups < nrb) prefetch(rb + ngroups);   // in flight during the math
     // (b) P_b partials
     acc_t pacc[NB][KT];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int kt = 0; kt < KT; ++kt) pacc[b][kt] = acc_t{0, 0, 0, 0};
-    for (int t = w; t < TT; t += kPassWaves) {
-      {
+#pragma unroll
+    for (int i = 0; i < TPB; ++i) {
+      const int t = w + kPassWaves * i;
+      if (t < TT) {
         const bool b1 = (NB == 2) && (t >= T0);
         const int ct = b1 ? t - T0 : t;
         const int cbase = (b1 ? d0 : 0) + ct * 16;   // column of the tile in xs
@@ -197,18 +224,14 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(const DT* __restrict__ A0
           const CT a = xs[l16 * pitch + cbase + 4 * s2 + g];
 #pragma unroll
           for (int kt = 0; kt < KT; ++kt) {
-            const int soff = ((ct * 16 + 4 * s2) * KP + kt * 16) * (int)sizeof(CT);
-            if (b1) {
-              const CT bw = buf_load<CT>(wr1, wvoff + soff, 0);
-              pacc[NB - 1][kt] = mfma16x16x4(a, bw, pacc[NB - 1][kt]);
-            } else {
-              const CT bw = buf_load<CT>(wr0, wvoff + soff, 0);
-              pacc[0][kt] = mfma16x16x4(a, bw, pacc[0][kt]);
-            }
+            const CT bw = WREG ? wreg[WREG ? i : 0][s2][kt] : w_operand(t, s2, kt);
+            if (b1) pacc[NB - 1][kt] = mfma16x16x4(a, bw, pacc[NB - 1][kt]);
+            else pacc[0][kt] = mfma16x16x4(a, bw, pacc[0][kt]);
           }
         }
       }
     }
+    if (!WREG && rb + ngroups < nrb) prefetch(rb + ngroups);   // in flight during (c), (d)
     // (c) reduce P over waves
 #pragma unroll
     for (int b = 0; b < NB; ++b)
@@ -268,6 +291,242 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(const DT* __restrict__ A0
       }
     }
   }
+}
+
+// ------------------------------------------------------------------
+// FP32 data and arithmetic: the same products with the row blocks moved
+// straight from HBM into LDS by the load unit (buffer loads with the LDS
+// flag, no VGPRs), double-buffered, so a workgroup can own whole rows:
+//   * 8-row blocks; block i+1 streams into the second LDS buffer while the
+//     matrix cores work on block i, and the only wait on it is at the top
+//     of the next iteration;
+//   * the barriers inside an iteration wait on LDS traffic only (an LDS
+//     fence would also wait on the in-flight block);
+//   * the direction operands of a wave's tiles stay in registers for the
+//     launch, and each wave accumulates A_b^T [P_0 | P_1] for the same
+//     tiles it used for P (no column split, no duplicated P).
+// Tile t of [A_0 | A_1] (16 columns; A_1's tiles follow A_0's) sits at LDS
+// column 16 t, so every operand address is one base register plus a
+// compile-time offset.  A load instruction moves CH = 64 VEC consecutive
+// floats of one row; the last chunk of each block is shifted back to end
+// on the block's last tile (it rewrites identical values), so no chunk
+// spills into the other block's columns.  The row pitch is 4 mod 32 floats
+// (bank-conflict free for both operand patterns).  P tiles use MFMA rows
+// 0-7 only (rows 8-15 repeat them).
+constexpr int kDmaRows = 8;
+constexpr int kDmaWaves = 8;
+constexpr int kDmaThreads = 64 * kDmaWaves;
+constexpr int kDmaMaxTiles = 128;   // 2048 columns of [A_0 | A_1]
+
+__device__ __forceinline__ void lds_only_barrier() {
+  // LDS traffic of this wave done, then the workgroup barrier; in-flight
+  // global-to-LDS loads of the next block are deliberately not waited on.
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int VEC>
+__device__ __forceinline__ void dma_row_chunk(__amdgpu_buffer_rsrc_t r, float* lds_dst, int voff) {
+  if constexpr (VEC == 4)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_dst, 16, voff, 0, 0, 0);
+  else
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_dst, 4, voff, 0, 0, 0);
+}
+
+__host__ __device__ constexpr int dma_pitch(int TT) { return ((TT * 16 + 31) / 32) * 32 + 4; }
+
+template <int NB, int KT, int VEC>
+__global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restrict__ A0, const float* __restrict__ A1,
+                                                          int64_t n, int d0, int d1, int k,
+                                                          const float* __restrict__ Wp0,
+                                                          const float* __restrict__ Wp1, int nrb,
+                                                          float* __restrict__ partial, const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int R = kDmaRows;
+  constexpr int CH = 64 * VEC;
+  constexpr int NT = NB * KT;
+  constexpr int KP = KT * 16;
+  constexpr int TPB = (kDmaMaxTiles + kDmaWaves - 1) / kDmaWaves;
+  using acc_t = f32x4;
+  extern __shared__ float dsm[];
+  const int T0 = (d0 + 15) >> 4;
+  const int T1 = NB == 2 ? ((d1 + 15) >> 4) : 0;
+  const int TT = T0 + T1;
+  const int nch0 = (T0 * 16 + CH - 1) / CH, nch1 = NB == 2 ? (T1 * 16 + CH - 1) / CH : 0;
+  const int nch = nch0 + nch1;
+  const int pitch = dma_pitch(TT);
+  float* red = dsm + 2 * R * pitch;              // [waves][NT][R x 16]
+  float* pfull = red + kDmaWaves * NT * R * 16;  // [NT][R][17]
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const __amdgpu_buffer_rsrc_t wr0 = make_rsrc(Wp0, (int64_t)T0 * 16 * KP * 4);
+  const __amdgpu_buffer_rsrc_t wr1 = make_rsrc(NB == 2 ? Wp1 : Wp0, (int64_t)(NB == 2 ? T1 : T0) * 16 * KP * 4);
+  const int wvoff = (g * KP + l16) * 4;
+
+  float wreg[TPB][4][KT];
+  acc_t acc[TPB][NT];
+#pragma unroll
+  for (int i = 0; i < TPB; ++i) {
+    const int t = w + kDmaWaves * i;
+    const bool b1 = (NB == 2) && (t >= T0);
+    const int ct = b1 ? t - T0 : t;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) {
+        const int soff = ((ct * 16 + 4 * s2) * KP + kt * 16) * 4;
+        float v = 0.f;
+        if (t < TT) v = b1 ? buf_load<float>(wr1, wvoff + soff, 0) : buf_load<float>(wr0, wvoff + soff, 0);
+        wreg[i][s2][kt] = v;
+      }
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  }
+
+  // Issue the loads of row block rbk into buffer xb: instruction q covers
+  // row q / nch, chunk q % nch; waves take instructions round-robin.
+  auto issue_block = [&](int rbk, float* xb) __attribute__((always_inline)) {
+    const int nq = R * nch;
+    for (int q = w; q < nq; q += kDmaWaves) {
+      const int r = q / nch, j = q - r * nch;
+      const int64_t row = (int64_t)rbk * R + r;
+      const bool s1 = (NB == 2) && (j >= nch0);
+      const int jj = s1 ? j - nch0 : j;
+      const int span = (s1 ? T1 : T0) * 16;
+      const int o = min(jj * CH, span - CH);
+      float* dst = xb + r * pitch + (s1 ? T0 * 16 : 0) + o;
+      const int voff = (o + lane * VEC) * 4;
+      if (s1) dma_row_chunk<VEC>(make_rsrc(A1 + row * d1, row < n ? (int64_t)d1 * 4 : 0), dst, voff);
+      else dma_row_chunk<VEC>(make_rsrc(A0 + row * d0, row < n ? (int64_t)d0 * 4 : 0), dst, voff);
+    }
+  };
+
+  // per-lane operand bases (floats); tile i adds 16 (w + 8 i)
+  const int base_b = (l16 & (R - 1)) * pitch + g + 16 * w;   // P phase: row l16 mod 8, column 4 s2 + g
+  const int base_d = g * pitch + l16 + 16 * w;               // J phase: row g + 4 s, column l16
+  const int pf_b = g * 17 + l16;                              // pfull row g + 4 s (as the J-phase A operand)
+
+  int rb = blockIdx.x;
+  int boff = 0;   // float offset of the current buffer
+  if (rb < nrb) issue_block(rb, dsm);
+  for (; rb < nrb; rb += gridDim.x) {
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the block (and W) have landed
+    __syncthreads();                 // ... and every wave's; the other buffer is free
+    const float* xs = dsm + boff;
+    if (rb + (int)gridDim.x < nrb) issue_block(rb + gridDim.x, dsm + (R * pitch - boff));
+    // (b) P_b partials over this wave's tiles
+    acc_t pacc[NB][KT];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int kt = 0; kt < KT; ++kt) pacc[b][kt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < TPB; ++i) {
+      const int t = w + kDmaWaves * i;
+      if (t < TT) {
+        const bool b1 = (NB == 2) && (t >= T0);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+          const float a = xs[base_b + 16 * kDmaWaves * i + 4 * s2];
+#pragma unroll
+          for (int kt = 0; kt < KT; ++kt) {
+            if (b1) pacc[NB - 1][kt] = mfma16x16x4(a, wreg[i][s2][kt], pacc[NB - 1][kt]);
+            else pacc[0][kt] = mfma16x16x4(a, wreg[i][s2][kt], pacc[0][kt]);
+          }
+        }
+      }
+    }
+    // (c) reduce P over waves (MFMA rows 0-7 live in lanes 0-31)
+    if (lane < 32) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            red[(w * NT + b * KT + kt) * (R * 16) + (4 * g + r) * 16 + l16] = pacc[b][kt][r];
+    }
+    lds_only_barrier();
+    for (int e = tid; e < NT * R * 16; e += kDmaThreads) {
+      const int nt = e / (R * 16), q = e - nt * (R * 16);
+      float v = 0.f;
+#pragma unroll
+      for (int ww = 0; ww < kDmaWaves; ++ww) v += red[(ww * NT + nt) * (R * 16) + q];
+      pfull[nt * (R * 17) + (q >> 4) * 17 + (q & 15)] = v;
+    }
+    lds_only_barrier();
+    // (d) A_b^T [P_0 | P_1] for this wave's tiles
+    float pb[R / 4][NT];
+#pragma unroll
+    for (int s = 0; s < R / 4; ++s)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) pb[s][nt] = pfull[nt * (R * 17) + pf_b + 4 * s * 17];
+#pragma unroll
+    for (int i = 0; i < TPB; ++i) {
+      const int t = w + kDmaWaves * i;
+      if (t < TT) {
+#pragma unroll
+        for (int s = 0; s < R / 4; ++s) {
+          const float a = xs[base_d + 4 * s * pitch + 16 * kDmaWaves * i];
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mfma16x16x4(a, pb[s][nt], acc[i][nt]);
+        }
+      }
+    }
+    boff = R * pitch - boff;
+  }
+  // epilogue: this workgroup's partial (rows = concatenated columns of A)
+  const int W_out = NB * k;
+  const int D = d0 + (NB == 2 ? d1 : 0);
+  float* out = partial + (int64_t)blockIdx.x * D * W_out;
+#pragma unroll
+  for (int i = 0; i < TPB; ++i) {
+    const int t = w + kDmaWaves * i;
+    if (t < TT) {
+      const bool b1 = (NB == 2) && (t >= T0);
+      const int db = b1 ? d1 : d0;
+      const int ct = b1 ? t - T0 : t;
+      const int rowbase = b1 ? d0 : 0;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const int bsrc = nt / KT, kt = nt % KT;
+        const int col = kt * 16 + l16;
+        if (col < k) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int c = ct * 16 + acc_row<float>(lane, r);
+            if (c < db) out[(int64_t)(rowbase + c) * W_out + bsrc * k + col] = acc[i][nt][r];
+          }
+        }
+      }
+    }
+  }
+}
+
+static size_t dma_lds_bytes(int d0, int d1, int NT) {
+  const int TT = (d0 + 15) / 16 + (d1 > 0 ? (d1 + 15) / 16 : 0);
+  const size_t pitch = (size_t)dma_pitch(TT);
+  return (2 * kDmaRows * pitch + (size_t)kDmaWaves * NT * kDmaRows * 16 + (size_t)NT * kDmaRows * 17) * sizeof(float);
+}
+
+// 16-byte loads need rows that start on 16-byte boundaries and blocks of
+// at least 16 tiles (one 256-float chunk); 4-byte loads blocks of 4 tiles.
+static int dma_vec(const void* A0, const void* A1, int d0, int d1) {
+  const int T0 = (d0 + 15) / 16, T1 = A1 ? (d1 + 15) / 16 : 0;
+  const bool al = ((uintptr_t)A0 % 16 == 0) && (!A1 || (uintptr_t)A1 % 16 == 0) && d0 % 4 == 0 && (!A1 || d1 % 4 == 0);
+  if (al && T0 >= 16 && (!A1 || T1 >= 16)) return 4;
+  if (T0 >= 4 && (!A1 || T1 >= 4)) return 1;
+  return 0;
+}
+
+static bool dma_fits(int d0, int d1, int k, int nb, int vec) {
+  if (vec == 0) return false;
+  if (k > 16) return false;   // two k-tiles would not fit the registers
+  const int TT = (d0 + 15) / 16 + (nb == 2 ? (d1 + 15) / 16 : 0);
+  if (TT > kDmaMaxTiles) return false;
+  const int NT = nb * ((k + 15) / 16);
+  return dma_lds_bytes(d0, nb == 2 ? d1 : 0, NT) <= (size_t)kPassLds + 8 * 1024;
 }
 
 template <class CT> static size_t pass_lds_bytes(int D, int NT) {
@@ -333,7 +592,8 @@ size_t pass_ws_bytes(int64_t n, int d0, int d1, int k, int compute) {
   const int nb = d1 > 0 ? 2 : 1;
   const size_t D = (size_t)d0 + (nb == 2 ? d1 : 0);
   const size_t wp = (((size_t)(d0 + 15) / 16 * 16) + ((size_t)(d1 + 15) / 16 * 16)) * KT * 16 * cs;
-  return ((wp + 1023) & ~size_t(255)) + (((size_t)pass_groups(n) * D * nb * k * cs + 255) & ~size_t(255));
+  const size_t slots = std::max<size_t>((size_t)pass_groups(n) * kPassSplit, (size_t)num_cus());
+  return ((wp + 1023) & ~size_t(255)) + ((slots * D * nb * k * cs + 255) & ~size_t(255));
 }
 
 template <class DT, class CT, int NB, int KT>
@@ -375,6 +635,56 @@ static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, in
   return SRP_OK;
 }
 
+template <int NB, int KT, int VEC>
+static int pass_launch_dma(const float* A0, const float* A1, int64_t n, int d0, int d1, int k, const double* W0,
+                           const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
+                           hipEvent_t before_pass, hipEvent_t after_pass) {
+  const int dp0 = (d0 + 15) / 16 * 16, dp1 = NB == 2 ? (d1 + 15) / 16 * 16 : 0;
+  const int KP = KT * 16;
+  float* Wp0 = ws.take<float>((size_t)dp0 * KP);
+  float* Wp1 = NB == 2 ? ws.take<float>((size_t)dp1 * KP) : nullptr;
+  const int nrb = (int)((n + kDmaRows - 1) / kDmaRows);
+  const int grid = std::max(1, std::min(num_cus(), nrb));
+  const int Dtot = d0 + (NB == 2 ? d1 : 0);
+  float* part = ws.take<float>((size_t)grid * Dtot * NB * k);
+  if (!Wp0 || !part || (NB == 2 && !Wp1)) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
+  hipLaunchKernelGGL((k_pack_dir<float>), dim3((dp0 * KP + 255) / 256), dim3(256), 0, st, W0, d0, k, dp0, KP, Wp0);
+  SRP_LAUNCH_CHECK();
+  if (NB == 2) {
+    hipLaunchKernelGGL((k_pack_dir<float>), dim3((dp1 * KP + 255) / 256), dim3(256), 0, st, W1, d1, k, dp1, KP, Wp1);
+    SRP_LAUNCH_CHECK();
+  }
+  const size_t lds = dma_lds_bytes(d0, NB == 2 ? d1 : 0, NB * KT);
+  static bool attr_done = false;   // per template instance
+  if (!attr_done) {
+    SRP_HIP(hipFuncSetAttribute((const void*)k_pass_dma<NB, KT, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kPassLds + 8 * 1024));
+    attr_done = true;
+  }
+  if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
+  hipLaunchKernelGGL((k_pass_dma<NB, KT, VEC>), dim3(grid), dim3(kDmaThreads), lds, st, A0, A1, n, d0,
+                     NB == 2 ? d1 : 0, k, Wp0, Wp1, nrb, part, done);
+  SRP_LAUNCH_CHECK();
+  if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
+  const int64_t count = (int64_t)Dtot * NB * k;
+  hipLaunchKernelGGL((k_pass_reduce<float>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, grid, d0,
+                     NB == 2 ? d1 : 0, NB * k, J0, J1, done);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+static int pass_dispatch_dma(const float* A0, const float* A1, int64_t n, int d0, int d1, int k, const double* W0,
+                             const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
+                             hipEvent_t ev0, hipEvent_t ev) {
+  const int vec = dma_vec(A0, A1, d0, d1);
+  if (A1) {
+    if (vec == 4) return pass_launch_dma<2, 1, 4>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+    return pass_launch_dma<2, 1, 1>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+  }
+  if (vec == 4) return pass_launch_dma<1, 1, 4>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+  return pass_launch_dma<1, 1, 1>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+}
+
 template <class DT, class CT>
 static int pass_dispatch_k(const DT* A0, const DT* A1, int64_t n, int d0, int d1, int k, const double* W0,
                            const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
@@ -400,7 +710,11 @@ int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_
     }
   } else {
     switch (dtype) {
-      case SRP_F32: return pass_dispatch_k<float, float>((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, before_pass, after_pass);
+      case SRP_F32:
+        if (dma_fits(d0, nb == 2 ? d1 : 0, k, nb, dma_vec(A0, A1, d0, d1)))
+          return pass_dispatch_dma((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st,
+                                   before_pass, after_pass);
+        return pass_dispatch_k<float, float>((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, before_pass, after_pass);
       case SRP_BF16: return pass_dispatch_k<bf16, float>((const bf16*)A0, (const bf16*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, before_pass, after_pass);
     }
   }

@@ -9,7 +9,7 @@ constexpr int KMAX = 32;       // largest k the step kernels support
 constexpr int KK_STRIDE = KMAX * KMAX;
 
 // k x k matrices kept per side in SolverState::kk, each KMAX*KMAX doubles.
-enum KKSlot { KK_LINVT = 0, KK_S = 1, KK_PHI = 2, KK_ROT = 3, KK_NSLOTS = 4 };
+enum KKSlot { KK_LINVT = 0, KK_S = 1, KK_PHI = 2, KK_ROT = 3, KK_EIG = 4, KK_NSLOTS = 5 };
 
 struct SolverCtrl {
   double t;        // accepted step along the retraction curve
@@ -27,7 +27,7 @@ struct SolverCtrl {
   int restart;     // next direction is -grad
   int ls_fail;     // consecutive line-search failures
   int fixed_step;  // 1: take t = 1 without a line search (the qf start)
-  int pad;
+  int eig_ok;      // KK_EIG holds the eigenvectors of the previous P
 };
 
 // One block of the (product) manifold: St_B(k, d) with B = A^T A + lam I.

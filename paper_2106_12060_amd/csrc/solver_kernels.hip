@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
 
 int partial_slices(int dmax) {
   int s = (dmax + kPartRows - 1) / kPartRows;
-  return s < 64 ? (s < 1 ? 1 : s) : 64;
+  return s < 16 ? (s < 1 ? 1 : s) : 16;
 }
 
 size_t partial_bytes(int k, int dmax) {
@@ -187,6 +187,33 @@ int launch_final_partials(const ProbView& p, hipStream_t st) {
 }
 
 // ------------------------------------------------- small dense helpers
+// Sum over the row-slice partials of up to four entries with weights:
+// sum_z sum_q w_q part[z * zs + i_q] (q < nq).  Two accumulators keep
+// several loads in flight; the order is fixed (deterministic).
+__device__ __forceinline__ double slice_sum(const double* __restrict__ part, int slices, int64_t zs, int nq,
+                                            int64_t i0, int64_t i1, int64_t i2, int64_t i3, double w0,
+                                            double w1, double w2, double w3) {
+  double s0 = 0.0, s1 = 0.0;
+  int z = 0;
+  for (; z + 2 <= slices; z += 2) {
+    const double* p0 = part + (int64_t)z * zs;
+    const double* p1 = p0 + zs;
+    s0 += w0 * p0[i0];
+    s1 += w0 * p1[i0];
+    if (nq > 1) { s0 += w1 * p0[i1]; s1 += w1 * p1[i1]; }
+    if (nq > 2) { s0 += w2 * p0[i2]; s1 += w2 * p1[i2]; }
+    if (nq > 3) { s0 += w3 * p0[i3]; s1 += w3 * p1[i3]; }
+  }
+  if (z < slices) {
+    const double* p0 = part + (int64_t)z * zs;
+    s0 += w0 * p0[i0];
+    if (nq > 1) s0 += w1 * p0[i1];
+    if (nq > 2) s0 += w2 * p0[i2];
+    if (nq > 3) s0 += w3 * p0[i3];
+  }
+  return s0 + s1;
+}
+
 // Lower Cholesky in place (ld = k) by one wave; false if not SPD.
 __device__ bool wave_chol(double* A, int k, int lane) {
   for (int j = 0; j < k; ++j) {
@@ -222,113 +249,190 @@ __device__ void wave_lower_inv(const double* L, double* X, int k, int lane) {
   wave_sync();
 }
 
-// Coefficients of the line-search polynomials, stored in global scratch:
-// [side b][G0, G1, G2] then [C0, C1, C2] (CCA cross or FDA S_B), each k x k.
-__device__ __forceinline__ double* coefp(double* base, int k, int idx) { return base + (size_t)idx * k * k; }
-
-// Cost along the curve at step t, evaluated by one wave.  Lm holds nb
-// k x k factors, Li their inverses; C(t) is staged into Lm once the
-// factors have been inverted.
-__device__ double eval_trial(const ProbView& p, const double* coef, double t, double* Lm, double* Li, int lane,
-                             bool* ok) {
-  const int k = p.k, nb = p.nb;
-  const double t2 = t * t;
-  for (int b = 0; b < nb; ++b) {
-    double* L = Lm + b * k * k;
-    const double* G0 = coef + (size_t)(3 * b + 0) * k * k;
-    const double* G1 = coef + (size_t)(3 * b + 1) * k * k;
-    const double* G2 = coef + (size_t)(3 * b + 2) * k * k;
-    for (int e = lane; e < k * k; e += 64) L[e] = G0[e] + t * G1[e] + t2 * G2[e];
-    if (!wave_chol(L, k, lane)) { *ok = false; return INFINITY; }
-    wave_lower_inv(L, Li + b * k * k, k, lane);
+// Lower Cholesky in place (ld k) by a group of gsize lanes (gl = lane in
+// the group); all lanes of the wave run the same loop, so two groups of 32
+// factor two matrices side by side.  A non-positive pivot is replaced by 1
+// to keep the loop uniform and reported through the return value.
+__device__ bool group_chol(double* A, int k, int gl, int gsize) {
+  bool ok = true;
+  for (int j = 0; j < k; ++j) {
+    wave_sync();
+    double piv = A[j * k + j];
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      ok = false;
+      piv = 1.0;
+    }
+    const double dj = sqrt(piv);
+    wave_sync();
+    if (gl == 0) A[j * k + j] = dj;
+    for (int i = j + 1 + gl; i < k; i += gsize) A[i * k + j] /= dj;
+    wave_sync();
+    const int w = k - j - 1;
+    for (int e = gl; e < w * w; e += gsize) {
+      const int r = j + 1 + e / w, c = j + 1 + e % w;
+      if (c <= r) A[r * k + c] -= A[r * k + j] * A[c * k + j];
+    }
   }
-  const double* C0 = coef + (size_t)(3 * nb + 0) * k * k;
-  const double* C1 = coef + (size_t)(3 * nb + 1) * k * k;
-  const double* C2 = coef + (size_t)(3 * nb + 2) * k * k;
-  double* Ct = Lm;
-  for (int e = lane; e < k * k; e += 64) Ct[e] = C0[e] + t * C1[e] + t2 * C2[e];
   wave_sync();
-  const double* Lx = Li;
-  const double* Ly = Li + (nb == 2 ? k * k : 0);
+  return ok;
+}
+
+// X = L^-1 for lower L (ld k): lane c of the group forward-substitutes
+// column c (no cross-lane dependence); each row's dot product is unrolled
+// to KC so its loads issue together.
+template <int KC>
+__device__ void group_lower_inv(const double* L, double* X, int k, int gl) {
+  if (gl < k) {
+    const int c = gl;
+    for (int r = 0; r < k; ++r) {
+      double v = 0.0;
+      if (r >= c) {
+        double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int l = 0; l < KC; ++l)
+          if (l >= c && l < r) s -= L[r * k + l] * X[l * k + c];
+        v = s / L[r * k + r];
+      }
+      X[r * k + c] = v;
+    }
+  }
+  wave_sync();
+}
+
+// sum_i mu_i (Lx^-1 C Ly^-T)_ii with Xx = Lx^-1, Xy = Ly^-1 (lower, ld k):
+// lane i forms row i; reduced over the wave.
+template <int KC>
+__device__ double trial_cost(const double* C, const double* Xx, const double* Xy, const double* mu, int k,
+                             int lane) {
   double part = 0.0;
-  for (int i = lane; i < k; i += 64) {
+  if (lane < k) {
+    const int i = lane;
     double fii = 0.0;
     for (int a = 0; a <= i; ++a) {
       double row = 0.0;
-      for (int b2 = 0; b2 <= i; ++b2) row += Ct[a * k + b2] * Ly[i * k + b2];
-      fii += Lx[i * k + a] * row;
+#pragma unroll
+      for (int b = 0; b < KC; ++b)
+        if (b <= i) row += C[a * k + b] * Xy[i * k + b];
+      fii += Xx[i * k + a] * row;
     }
-    part += p.mu[i] * fii;
+    part = mu[i] * fii;
   }
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-  *ok = true;
-  const double f = p.lda_cost ? -0.5 * part : -part;
+  return part;
+}
+
+// Line-search polynomial coefficients, k x k each, in LDS:
+// [side b][G0, G1, G2] then [C0, C1, C2] (CCA cross or FDA S_B).
+__device__ __forceinline__ const double* coefp(const double* base, int k, int idx) {
+  return base + (size_t)idx * k * k;
+}
+
+// Cost along the curve at step t, evaluated by one wave.  CCA factors the
+// two Grams in the two half-waves; Lm holds nb k x k factors, Li their
+// inverses; C(t) is staged into Lm once the factors have been inverted.
+template <int KC>
+__device__ double eval_trial(const ProbView& p, const double* coef, const double* mu, double t, double* Lm,
+                             double* Li, int lane, bool* ok) {
+  const int k = p.k, nb = p.nb, kk2 = k * k;
+  const int gsize = nb == 2 ? 32 : 64;
+  const int grp = nb == 2 ? (lane >> 5) : 0;
+  const int gl = nb == 2 ? (lane & 31) : lane;
+  const double t2 = t * t;
+  {
+    double* L = Lm + grp * kk2;
+    const double* G0 = coefp(coef, k, 3 * grp + 0);
+    const double* G1 = coefp(coef, k, 3 * grp + 1);
+    const double* G2 = coefp(coef, k, 3 * grp + 2);
+    for (int e = gl; e < kk2; e += gsize) L[e] = G0[e] + t * G1[e] + t2 * G2[e];
+    const bool good = group_chol(L, k, gl, gsize);
+    *ok = __all(good ? 1 : 0) != 0;
+    group_lower_inv<KC>(L, Li + grp * kk2, k, gl);
+  }
+  if (!*ok) return INFINITY;
+  const double* C0 = coefp(coef, k, 3 * nb + 0);
+  const double* C1 = coefp(coef, k, 3 * nb + 1);
+  const double* C2 = coefp(coef, k, 3 * nb + 2);
+  double* Ct = Lm;
+  for (int e = lane; e < kk2; e += 64) Ct[e] = C0[e] + t * C1[e] + t2 * C2[e];
+  wave_sync();
+  const double s = trial_cost<KC>(Ct, Li, Li + (nb == 2 ? kk2 : 0), mu, k, lane);
+  const double f = p.lda_cost ? -0.5 * s : -s;
   return isfinite(f) ? f : INFINITY;
 }
 
 // -------------------------------------------------------- line search
-// One workgroup: form the polynomial coefficients, evaluate NTR trial steps
-// per round in parallel (one wave each), keep the best, narrow, repeat.
-__global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, double* coef, int ntr) {
+// One workgroup.  All threads first reduce the row-slice partials into the
+// polynomial coefficients (LDS); then each round evaluates ntr trial steps
+// on a geometric grid in parallel (one wave each), keeps the best and
+// narrows the grid around it.  The winning wave's factor inverses are
+// stored directly when the best step comes from the last round.
+template <int KC>
+__global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, int ntr) {
   SolverCtrl* c = p.ctrl;
   if (c->done) return;
   extern __shared__ double sm[];
   __shared__ double fbest[64];
   __shared__ double tbest[64];
   __shared__ int okflag[64];
+  __shared__ double mu[KC];
   const int k = p.k, nb = p.nb, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int kk2 = k * k;
   const int slices = p.part_slices;
-  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);
+  const int NR = 6 * k;
+  const int64_t zs = (int64_t)(2 * k) * NR;
+  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);   // as laid out by run_partials
+  double* coef = sm;                                 // (3 nb + 3) k x k
+  const int ncoef = 3 * nb + 3;
   // coefficients (ls partial layout: left [U, xi], right [Ks, Js, U, xi, Kc, Jc])
-  for (int b = 0; b < nb; ++b) {
-    const double* part = p.part + b * side_stride;
-    const double lam = p.s[b].lam;
-    double* G0 = coefp(coef, k, 3 * b + 0);
-    double* G1 = coefp(coef, k, 3 * b + 1);
-    double* G2 = coefp(coef, k, 3 * b + 2);
-    sum_block(part, slices, 2, 6, k, 0, 0, 1.0, G0, tid, 1024, false);
-    sum_block(part, slices, 2, 6, k, 0, 2, lam, G0, tid, 1024, true);
-    sum_block(part, slices, 2, 6, k, 1, 0, 1.0, G1, tid, 1024, false);
-    sum_block(part, slices, 2, 6, k, 0, 1, 1.0, G1, tid, 1024, true);
-    sum_block(part, slices, 2, 6, k, 1, 2, lam, G1, tid, 1024, true);
-    sum_block(part, slices, 2, 6, k, 0, 3, lam, G1, tid, 1024, true);
-    sum_block(part, slices, 2, 6, k, 1, 1, 1.0, G2, tid, 1024, false);
-    sum_block(part, slices, 2, 6, k, 1, 3, lam, G2, tid, 1024, true);
+  for (int e = tid; e < ncoef * kk2; e += 1024) {
+    const int m = e / kk2, q = e - m * kk2, i = q / k, j = q - i * k;
+    const int64_t r0 = (int64_t)i * NR + j, r1 = (int64_t)(k + i) * NR + j;   // rows of U and xi
+    double v;
+    if (m < 3 * nb) {
+      const int b = m / 3, which = m - 3 * b;
+      const double lam = p.s[b].lam;
+      const double* part = p.part + b * side_stride;
+      if (which == 0)        // G0 = U^T Ks + lam U^T U
+        v = slice_sum(part, slices, zs, 2, r0, r0 + 2 * k, 0, 0, 1.0, lam, 0.0, 0.0);
+      else if (which == 1)   // G1 = xi^T Ks + U^T Js + lam (xi^T U + U^T xi)
+        v = slice_sum(part, slices, zs, 4, r1, r0 + k, r1 + 2 * k, r0 + 3 * k, 1.0, 1.0, lam, lam);
+      else                   // G2 = xi^T Js + lam xi^T xi
+        v = slice_sum(part, slices, zs, 2, r1 + k, r1 + 3 * k, 0, 0, 1.0, lam, 0.0, 0.0);
+    } else {
+      const int which = m - 3 * nb;   // side 0 carries the cost products
+      if (which == 0)        // C0 = U^T Kc
+        v = slice_sum(p.part, slices, zs, 1, r0 + 4 * k, 0, 0, 0, 1.0, 0.0, 0.0, 0.0);
+      else if (which == 1)   // C1 = xi^T Kc + U^T Jc
+        v = slice_sum(p.part, slices, zs, 2, r1 + 4 * k, r0 + 5 * k, 0, 0, 1.0, 1.0, 0.0, 0.0);
+      else                   // C2 = xi^T Jc
+        v = slice_sum(p.part, slices, zs, 1, r1 + 5 * k, 0, 0, 0, 1.0, 0.0, 0.0, 0.0);
+    }
+    coef[e] = v;
   }
-  {
-    const double* part = p.part;  // side 0 carries the cost products
-    double* C0 = coefp(coef, k, 3 * nb + 0);
-    double* C1 = coefp(coef, k, 3 * nb + 1);
-    double* C2 = coefp(coef, k, 3 * nb + 2);
-    sum_block(part, slices, 2, 6, k, 0, 4, 1.0, C0, tid, 1024, false);
-    sum_block(part, slices, 2, 6, k, 1, 4, 1.0, C1, tid, 1024, false);
-    sum_block(part, slices, 2, 6, k, 0, 5, 1.0, C1, tid, 1024, true);
-    sum_block(part, slices, 2, 6, k, 1, 5, 1.0, C2, tid, 1024, false);
-  }
-  __threadfence_block();
+  for (int e = tid; e < k; e += 1024) mu[e] = p.mu[e];
   __syncthreads();
   // symmetrise the Gram coefficients (and the FDA cost coefficients)
   const int nsym = 3 * nb + (p.lda_cost ? 3 : 0);
-  for (int e = tid; e < nsym * k * k; e += 1024) {
-    const int m = e / (k * k), q = e % (k * k), i = q / k, j = q % k;
+  for (int e = tid; e < nsym * kk2; e += 1024) {
+    const int m = e / kk2, q = e - m * kk2, i = q / k, j = q - i * k;
     if (i < j) {
-      double* M = coefp(coef, k, m);
+      double* M = coef + (size_t)m * kk2;
       const double v = 0.5 * (M[i * k + j] + M[j * k + i]);
       M[i * k + j] = v;
       M[j * k + i] = v;
     }
   }
-  __threadfence_block();
   __syncthreads();
 
-  const int per_wave = (nb == 2 ? 4 : 2) * k * k;
-  double* Lm = sm + (size_t)w * per_wave;
-  double* Li = Lm + nb * k * k;
+  const int per_wave = 2 * nb * kk2;
+  double* Lm = sm + (size_t)ncoef * kk2 + (size_t)w * per_wave;
+  double* Li = Lm + nb * kk2;
   const double f0 = c->f;
   const double df0 = c->df0;
   double t_acc = 0.0;
   double t_seen = 0.0;   // best step of the search, accepted or not
   bool accepted = false;
+  int winner = -1;       // wave holding the factors of the best step
   if (c->fixed_step) {
     t_acc = 1.0;
     accepted = true;
@@ -338,18 +442,18 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, double* coef, int 
     double centre = c->t_guess;
     if (!(centre > 0.0)) {
       double smu = 0.0;
-      for (int i = 0; i < k; ++i) smu += p.mu[i];
-      centre = (fabs(f0) > 0.0) ? smu / (2.0 * p.mu[0] * fabs(f0)) : 1.0;
+      for (int i = 0; i < k; ++i) smu += mu[i];
+      centre = (fabs(f0) > 0.0) ? smu / (2.0 * mu[0] * fabs(f0)) : 1.0;
     }
     double H = 8.0;  // half span in octaves
     double tb = centre, fb = INFINITY;
     int expand = 0;
-    for (int round = 0; round < 16 && H > 0.1; ++round) {
+    for (int round = 0; round < 16 && H > 0.25; ++round) {
       if (w < ntr) {
         const double x = (ntr > 1) ? (2.0 * w / (ntr - 1) - 1.0) : 0.0;
         const double t = centre * exp2(H * x);
         bool ok;
-        const double f = eval_trial(p, coef, t, Lm, Li, lane, &ok);
+        const double f = eval_trial<KC>(p, coef, mu, t, Lm, Li, lane, &ok);
         if (lane == 0) { fbest[w] = f; tbest[w] = t; }
       }
       __syncthreads();
@@ -357,7 +461,13 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, double* coef, int 
         int best = -1;
         for (int j = 0; j < ntr; ++j)
           if (fbest[j] < INFINITY && (best < 0 || fbest[j] < fbest[best])) best = j;
-        if (best >= 0 && fbest[best] < fb) { fb = fbest[best]; tb = tbest[best]; }
+        int win = -1;
+        if (best >= 0 && fbest[best] < fb) {
+          fb = fbest[best];
+          tb = tbest[best];
+          win = best;
+        }
+        okflag[2] = win;
         // minimum on the edge of the grid: move the grid there, same span
         okflag[1] = (best == 0 || best == ntr - 1) && expand < 6 ? 1 : 0;
         fbest[63] = fb;
@@ -367,6 +477,7 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, double* coef, int 
       fb = fbest[63];
       tb = tbest[63];
       centre = tb;
+      winner = okflag[2] >= 0 ? okflag[2] : -1;
       if (okflag[1]) {
         ++expand;
       } else {
@@ -383,18 +494,24 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, double* coef, int 
       t_acc = tb;  // decrease without the Armijo margin: still progress
       accepted = true;
     }
+    if (accepted && winner >= 0 && tbest[winner] != t_acc) winner = -1;
+    if (!accepted) winner = -1;
   }
-  // final factors at the accepted step (t = 0 re-orthonormalises on failure)
-  if (w == 0) {
-    bool ok;
-    const double f = eval_trial(p, coef, t_acc, Lm, Li, lane, &ok);
-    if (lane == 0) { fbest[0] = f; okflag[0] = ok ? 1 : 0; }
+  // factors at the accepted step: from the winning wave, else recomputed
+  // by wave 0 (t = 0 re-orthonormalises on failure)
+  const int src = winner >= 0 ? winner : 0;
+  if (w == src) {
+    double f;
+    bool ok = true;
+    if (winner >= 0) f = fbest[63];
+    else f = eval_trial<KC>(p, coef, mu, t_acc, Lm, Li, lane, &ok);
+    if (lane == 0) { fbest[62] = f; okflag[0] = ok ? 1 : 0; }
     wave_sync();
     for (int b = 0; b < nb; ++b) {
       double* LT = kkslot(p, b, KK_LINVT);
-      const double* X = Li + b * k * k;
-      for (int e = lane; e < k * k; e += 64) {
-        const int i = e / k, j = e % k;
+      const double* X = Li + b * kk2;
+      for (int e = lane; e < kk2; e += 64) {
+        const int i = e / k, j = e - i * k;
         LT[i * k + j] = X[j * k + i];
       }
     }
@@ -407,12 +524,12 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, double* coef, int 
       c->t = 0.0;
     } else if (accepted) {
       c->t = t_acc;
-      c->f = fbest[0];
+      c->f = fbest[62];
       c->t_guess = t_acc;
       c->ls_fail = 0;
     } else {
       c->t = 0.0;
-      c->f = fbest[0];
+      c->f = fbest[62];
       c->restart = 1;
       c->ls_fail += 1;
       c->t_guess = (t_seen > 0.0 ? t_seen : 1.0) / 16.0;
@@ -422,21 +539,32 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, double* coef, int 
   }
 }
 
-int launch_ctrl_ls(const ProbView& p, hipStream_t st) {
-  const int per_wave = (p.nb == 2 ? 4 : 2) * p.k * p.k * 8;
-  int ntr = 131072 / per_wave;
+template <int KC>
+static int launch_ctrl_ls_t(const ProbView& p, hipStream_t st) {
+  const int k = p.k, nb = p.nb;
+  const size_t coef_bytes = (size_t)(3 * nb + 3) * k * k * sizeof(double);
+  const size_t per_wave = (size_t)2 * nb * k * k * sizeof(double);
+  const size_t budget = 156 * 1024;
+  int ntr = (int)((budget - coef_bytes) / per_wave);
   if (ntr > 16) ntr = 16;
-  if (ntr < 1) ntr = 1;
-  double* coef = kkslot(p, 0, 0) + (size_t)2 * KK_NSLOTS * KK_STRIDE;  // scratch after the kk slots
-  const size_t lds = (size_t)ntr * per_wave;
+  if (ntr < 1) {
+    set_error("line search: k = %d too large for the LDS budget", k);
+    return SRP_EINVAL;
+  }
+  const size_t lds = coef_bytes + (size_t)ntr * per_wave;
   static size_t attr_set = 0;
   if (lds > attr_set) {
-    SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_ls, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_ls<KC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = lds;
   }
-  hipLaunchKernelGGL(k_ctrl_ls, dim3(1), dim3(1024), lds, st, p, coef, ntr);
+  hipLaunchKernelGGL(k_ctrl_ls<KC>, dim3(1), dim3(1024), lds, st, p, ntr);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
+}
+
+int launch_ctrl_ls(const ProbView& p, hipStream_t st) {
+  if (p.k <= 16) return launch_ctrl_ls_t<16>(p, st);
+  return launch_ctrl_ls_t<32>(p, st);
 }
 
 // ------------------------------------------------------------- update
@@ -534,6 +662,16 @@ __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, Wa
   for (int e = lane; e < nn; e += 64) V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
   wave_sync();
   for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = lane; e < nn; e += 64) {
+      const double v = A[e];
+      if ((e / n) == (e % n)) dia += v * v; else off += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
+    }
+    if (off <= 1e-30 * (dia + 1e-300)) break;
     for (int round = 0; round < n - 1; ++round) {
       if (lane < n) w.pos[lane] = (lane == 0) ? 0 : 1 + ((lane - 1 + round) % (n - 1));
       wave_sync();
@@ -569,48 +707,63 @@ __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, Wa
       }
       wave_sync();
     }
-    double off = 0.0, dia = 0.0;
-    for (int e = lane; e < nn; e += 64) {
-      const double v = A[e];
-      if ((e / n) == (e % n)) dia += v * v; else off += v * v;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o, 64);
-      dia += __shfl_xor(dia, o, 64);
-    }
-    if (off <= 1e-30 * (dia + 1e-300)) break;
   }
 }
 
-// C = A B (k x k, ld k) by one wave.
-__device__ __forceinline__ void wave_mm(const double* A, const double* B, double* C, int k, int lane) {
+// ------------------------------------------------------- direction
+// C = op(A) op(B) for k x k blocks by one wave; element (i, j) per lane,
+// the contraction unrolled to KC so its loads issue together.
+// A(i, l) = A[i * lda + l] (or A[l * lda + i] when ta); likewise B.
+template <int KC>
+__device__ __forceinline__ void wave_mm_t(const double* A, int lda, bool ta, const double* B, int ldb, bool tb,
+                                          double* C, int ldc, int k, int lane) {
   for (int e = lane; e < k * k; e += 64) {
     const int i = e / k, j = e - i * k;
     double s = 0.0;
-    for (int l = 0; l < k; ++l) s += A[i * k + l] * B[l * k + j];
-    C[e] = s;
+#pragma unroll
+    for (int l = 0; l < KC; ++l)
+      if (l < k) s += (ta ? A[l * lda + i] : A[i * lda + l]) * (tb ? B[j * ldb + l] : B[l * ldb + j]);
+    C[i * ldc + j] = s;
   }
   wave_sync();
 }
 
-// ------------------------------------------------------- direction
-// One wave per manifold block: sums the direction partials, diagonalises
-// P = BU^T M^-1 BU, solves the three Sylvester equations through it, and
-// reduces the trace terms; thread 0 then forms the Polak-Ribiere+
-// coefficient, the descent test and the stopping test.
-__global__ void __launch_bounds__(128) k_ctrl_dir(ProbView p) {
+// All threads first reduce the row-slice partials (P = BU^T M^-1 BU,
+// Q = BU^T M^-1 E, BU^T xi, BU^T gold and three traces per side) into LDS;
+// one wave per manifold block then diagonalises P (Jacobi, started from
+// the previous iteration's eigenvectors, which nearly diagonalise the new
+// P), solves the three Sylvester equations through it and reduces the
+// trace terms; thread 0 forms the Polak-Ribiere+ coefficient, the descent
+// test and the stopping test.
+template <int KC>
+__global__ void __launch_bounds__(256) k_ctrl_dir(ProbView p) {
   SolverCtrl* c = p.ctrl;
   if (c->done) return;
   extern __shared__ double sm[];
   __shared__ WaveJacobiScratch jsc[2];
   __shared__ double terms[2][12];
+  __shared__ double trv[2][3][KC];
   __shared__ double beta_sh;
-  const int k = p.k, nb = p.nb, lane = threadIdx.x & 63, b = threadIdx.x >> 6;
+  const int k = p.k, nb = p.nb, tid = threadIdx.x, lane = tid & 63, b = tid >> 6;
   const int n = (k + 1) & ~1;
   const int kk2 = k * k, nn = n * n;
   const int slices = p.part_slices;
-  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);
-  const int per_side = 9 * kk2 + 4 * nn;
+  const int NR = 4 * k;
+  const int64_t zs = (int64_t)(2 * k) * NR;
+  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);   // as laid out by run_partials
+  const int per_side = 9 * kk2 + 5 * nn;
+  for (int e = tid; e < nb * 4 * kk2; e += 256) {
+    const int sd = e / (4 * kk2), r = e - sd * 4 * kk2, blk = r / kk2, q = r - blk * kk2, i = q / k, j = q - i * k;
+    sm[(size_t)sd * per_side + r] =
+        slice_sum(p.part + sd * side_stride, slices, zs, 1, (int64_t)i * NR + blk * k + j, 0, 0, 0, 1.0, 0.0, 0.0, 0.0);
+  }
+  for (int e = tid; e < nb * 3 * k; e += 256) {
+    const int sd = e / (3 * k), r = e - sd * 3 * k, which = r / k, i = r - which * k;
+    trv[sd][which][i] = slice_sum(p.part + sd * side_stride, slices, zs, 1, (int64_t)(k + i) * NR + (which + 1) * k + i,
+                                  0, 0, 0, 1.0, 0.0, 0.0, 0.0);
+  }
+  __syncthreads();
+  const bool warm = c->eig_ok && (c->iter % 32 != 0);
   double* P = sm + b * per_side;
   double* Q = P + kk2;
   double* cx = Q + kk2;
@@ -622,41 +775,42 @@ __global__ void __launch_bounds__(128) k_ctrl_dir(ProbView p) {
   double* W2 = W1 + kk2;
   double* JA = W2 + kk2;
   double* JV = JA + nn;
-  double* JT = JV + nn;
+  double* JT = JV + nn;   // 2 nn
+  double* V0 = JT + 2 * nn;
   if (b < nb) {
-    const double* part = p.part + b * side_stride;
-    const int NR = 4 * k;
-    const int64_t zs = (int64_t)(2 * k) * NR;
-    for (int e = lane; e < kk2; e += 64) {
-      const int i = e / k, j = e - i * k;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      for (int z = 0; z < slices; ++z) {
-        const double* row = part + z * zs + (int64_t)i * NR;
-        s0 += row[j];
-        s1 += row[k + j];
-        s2 += row[2 * k + j];
-        s3 += row[3 * k + j];
-      }
-      P[e] = s0; Q[e] = s1; cx[e] = s2; cg[e] = s3;
-    }
-    // traces of E^T W_E, E^T xi, E^T gold (diagonals of blocks (1,1), (1,2), (1,3))
     double tr3[3] = {0.0, 0.0, 0.0};
-    for (int i = lane; i < k; i += 64)
-      for (int z = 0; z < slices; ++z) {
-        const double* row = part + z * zs + (int64_t)(k + i) * NR;
-        tr3[0] += row[k + i];
-        tr3[1] += row[2 * k + i];
-        tr3[2] += row[3 * k + i];
-      }
+    for (int i = lane; i < k; i += 64) {
+      tr3[0] += trv[b][0][i];
+      tr3[1] += trv[b][1][i];
+      tr3[2] += trv[b][2][i];
+    }
     for (int q = 0; q < 3; ++q)
       for (int o = 32; o > 0; o >>= 1) tr3[q] += __shfl_xor(tr3[q], o, 64);
-    wave_sync();
     for (int e = lane; e < nn; e += 64) {
       const int i = e / n, j = e - i * n;
       JA[e] = (i < k && j < k) ? 0.5 * (P[i * k + j] + P[j * k + i]) : ((i == j) ? 1.0 : 0.0);
     }
+    double* Vst = kkslot(p, b, KK_EIG);
+    if (warm) {
+      for (int e = lane; e < nn; e += 64) V0[e] = Vst[e];
+      wave_sync();
+      wave_mm_t<KC>(JA, n, false, V0, n, false, JT, n, n, lane);   // JA V0
+      wave_mm_t<KC>(V0, n, true, JT, n, false, JA, n, n, lane);   // V0^T (JA V0)
+      for (int e = lane; e < nn; e += 64) {
+        const int i = e / n, j = e - i * n;
+        JT[e] = 0.5 * (JA[i * n + j] + JA[j * n + i]);
+      }
+      wave_sync();
+      for (int e = lane; e < nn; e += 64) JA[e] = JT[e];
+    }
     wave_sync();
     wave_jacobi(JA, JV, JT, n, lane, jsc[b]);
+    if (warm) {
+      wave_mm_t<KC>(V0, n, false, JV, n, false, JT, n, n, lane);   // V = V0 J
+      for (int e = lane; e < nn; e += 64) JV[e] = JT[e];
+      wave_sync();
+    }
+    for (int e = lane; e < nn; e += 64) Vst[e] = JV[e];
     // Sylvester: S = V ((V^T C V) ./ (w_i + w_j)) V^T for C = X + X^T
     const double* srcs[3] = {Q, cx, cg};
     double* dsts[3] = {S, Sx, Sg};
@@ -665,33 +819,41 @@ __global__ void __launch_bounds__(128) k_ctrl_dir(ProbView p) {
       for (int e = lane; e < kk2; e += 64) {
         const int i = e / k, j = e - i * k;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s += (C[i * k + l] + C[l * k + i]) * JV[l * n + j];
+#pragma unroll
+        for (int l = 0; l < KC; ++l)
+          if (l < k) s += (C[i * k + l] + C[l * k + i]) * JV[l * n + j];
         W1[e] = s;
       }
       wave_sync();
       for (int e = lane; e < kk2; e += 64) {
         const int i = e / k, j = e - i * k;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s += JV[l * n + i] * W1[l * k + j];
+#pragma unroll
+        for (int l = 0; l < KC; ++l)
+          if (l < k) s += JV[l * n + i] * W1[l * k + j];
         W2[e] = s / (JA[i * n + i] + JA[j * n + j]);
       }
       wave_sync();
       for (int e = lane; e < kk2; e += 64) {
         const int i = e / k, j = e - i * k;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s += JV[i * n + l] * W2[l * k + j];
+#pragma unroll
+        for (int l = 0; l < KC; ++l)
+          if (l < k) s += JV[i * n + l] * W2[l * k + j];
         W1[e] = s;
       }
       wave_sync();
       for (int e = lane; e < kk2; e += 64) {
         const int i = e / k, j = e - i * k;
         double s = 0.0;
-        for (int l = 0; l < k; ++l) s += W1[i * k + l] * JV[j * n + l];
+#pragma unroll
+        for (int l = 0; l < KC; ++l)
+          if (l < k) s += W1[i * k + l] * JV[j * n + l];
         dsts[m][e] = s;
       }
       wave_sync();
     }
-    wave_mm(P, S, W1, k, lane);   // W1 = P S
+    wave_mm_t<KC>(P, k, false, S, k, false, W1, k, k, lane);   // W1 = P S
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int e = lane; e < kk2; e += 64) {
       v[0] += Q[e] * S[e];
@@ -713,7 +875,7 @@ __global__ void __launch_bounds__(128) k_ctrl_dir(ProbView p) {
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     double gg = 0.0, gTg = 0.0, gTx = 0.0;
     for (int s2 = 0; s2 < nb; ++s2) {
       const double* t8 = terms[s2];
@@ -736,6 +898,7 @@ __global__ void __launch_bounds__(128) k_ctrl_dir(ProbView p) {
     c->gg = gg;
     c->gg_old = gg;
     c->restart = 0;
+    c->eig_ok = 1;
     const double gnorm = sqrt(gg > 0.0 ? gg : 0.0);
     if (gnorm <= c->tol * fabs(c->f)) {
       c->done = 1;
@@ -759,18 +922,24 @@ __global__ void __launch_bounds__(128) k_ctrl_dir(ProbView p) {
   }
 }
 
-int launch_ctrl_dir(const ProbView& p, hipStream_t st) {
+template <int KC>
+static int launch_ctrl_dir_t(const ProbView& p, hipStream_t st) {
   const int k = p.k, n = (k + 1) & ~1;
-  const size_t per_side = (size_t)(9 * k * k + 4 * n * n);
+  const size_t per_side = (size_t)(9 * k * k + 5 * n * n);
   const size_t lds = (size_t)p.nb * per_side * sizeof(double);
   static size_t attr_set = 0;
   if (lds > attr_set) {
-    SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_dir, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_dir<KC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = lds;
   }
-  hipLaunchKernelGGL(k_ctrl_dir, dim3(1), dim3(128), lds, st, p);
+  hipLaunchKernelGGL(k_ctrl_dir<KC>, dim3(1), dim3(256), lds, st, p);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
+}
+
+int launch_ctrl_dir(const ProbView& p, hipStream_t st) {
+  if (p.k <= 16) return launch_ctrl_dir_t<16>(p, st);
+  return launch_ctrl_dir_t<32>(p, st);
 }
 
 // ------------------------------------------------------------ combine
@@ -1027,7 +1196,7 @@ int launch_gauss_fill(double* p, int64_t count, uint64_t seed, hipStream_t st) {
 __global__ void k_ctrl_init(SolverCtrl* c, double tol, int max_iter) {
   c->t = 0.0; c->t_guess = 0.0; c->f = 0.0; c->gg = 0.0; c->gg_old = 0.0; c->df0 = 0.0;
   c->beta = 0.0; c->tol = tol; c->done = 0; c->status = SRP_OK; c->iter = 0; c->max_iter = max_iter;
-  c->restart = 1; c->ls_fail = 0; c->fixed_step = 1; c->pad = 0;
+  c->restart = 1; c->ls_fail = 0; c->fixed_step = 1; c->eig_ok = 0;
 }
 
 int launch_ctrl_init(SolverCtrl* c, double tol, int max_iter, hipStream_t st) {

@@ -125,7 +125,10 @@ def test_sketch_factor_reports_not_spd():
 @pytest.mark.parametrize("n,d0,d1,k,dt,comp", [(3000, 70, 45, 7, "f64", "f64"), (5001, 130, 200, 10, "f32", "f32"),
                                                (4097, 300, 0, 19, "f32", "f32"), (999, 17, 33, 16, "f32", "f64"),
                                                (2000, 1000, 1000, 10, "f32", "f32"), (64, 5, 3, 1, "f64", "f64"),
-                                               (3333, 2000, 0, 19, "f32", "f32"), (1500, 90, 60, 5, "bf16", "f32")])
+                                               (3333, 2000, 0, 19, "f32", "f32"), (1500, 90, 60, 5, "bf16", "f32"),
+                                               (1003, 1000, 0, 10, "f32", "f32"), (777, 260, 516, 16, "f32", "f32"),
+                                               (130, 66, 70, 3, "f32", "f32"), (5, 64, 0, 4, "f32", "f32"),
+                                               (40001, 2000, 0, 12, "f32", "f32")])
 def test_gram_pass_matches_products(n, d0, d1, k, dt, comp):
     srp = _srp()
     rng = np.random.default_rng(n + d0)
