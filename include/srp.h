@@ -71,8 +71,9 @@ typedef struct srp_options {
                              iterations (default 4)                          */
   int pass_compute;       /* arithmetic of the data passes: SRP_F64 or
                              SRP_F32 (default: F64 for F64 data, F32 else)   */
-  int final_f64;          /* 1: finish with an FP64-arithmetic pass and FP64
-                             retraction (default 1)                          */
+  int final_f64;          /* 1: the last data pass (the one the final FP64
+                             retraction and Rayleigh-Ritz step use) runs in
+                             FP64 arithmetic (default 0)                     */
   const double* mu;       /* HOST pointer to k weights mu_1 > ... > mu_k > 0
                              (N = diag(mu)); NULL = k, k-1, ..., 1           */
   int time_passes;        /* 1: time every fused data pass over the full data
@@ -146,7 +147,9 @@ int srp_sketch_factor(const void* SA, int dtype, int s, int d, double lambda,
  * X^T (X U), X^T (Y V), ... that the Riemannian gradient, projection and
  * retraction of Eq. gradCCA / Table 1 consume.  One read of the data.
  * Limits: k <= 16 with two blocks, k <= 32 with one; d0 + d1 <= 2048
- * (F32 / BF16 data) or <= 1024 (F64 data or F64 arithmetic).
+ * (F32 / BF16 data with F32 arithmetic) or <= 896 (F64 arithmetic).
+ * Errors: SRP_EINVAL outside these limits or for a bad dtype / compute
+ * pair (F64 data needs F64 arithmetic).
  */
 int srp_gram_pass(const void* A0, const void* A1, int dtype, int compute,
                   int64_t n, int d0, int d1, int k, const double* W0,
