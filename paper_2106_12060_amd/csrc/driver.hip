@@ -20,6 +20,7 @@
 #include <vector>
 #include <cstdarg>
 #include <cstring>
+#include <mutex>
 
 namespace srp {
 
@@ -94,6 +95,51 @@ struct PhaseTimer {
   }
 };
 
+// A second stream per device (default priority) for work that is
+// independent of the caller's stream: CCA sketches and factors the Y view on
+// it while the X view runs on the caller's stream.
+static hipStream_t side_stream() {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
+// Fork/join of the side stream around a block of independent work.
+struct SideFork {
+  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t side = nullptr, main = nullptr;
+  bool open = false;
+  ~SideFork() {
+    // an early error return still joins, so the workspace is released (on
+    // the caller's stream) only after the side stream's work
+    if (open) (void)end(main);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+  }
+  int begin(hipStream_t st) {
+    main = st;
+    side = side_stream();
+    if (!side) { set_error("could not create a side stream"); return SRP_EDEVICE; }
+    SRP_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    SRP_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    SRP_HIP(hipEventRecord(fork, st));
+    SRP_HIP(hipStreamWaitEvent(side, fork, 0));
+    open = true;
+    return SRP_OK;
+  }
+  int end(hipStream_t st) {
+    open = false;
+    SRP_HIP(hipEventRecord(join, side));
+    SRP_HIP(hipStreamWaitEvent(st, join, 0));
+    return SRP_OK;
+  }
+};
+
 // ----------------------------------------------------------- the solver
 struct RcgProblem {
   int nb = 1, k = 1, lda_cost = 0;
@@ -138,7 +184,7 @@ static int twopass_ksplit(int64_t n) {
 
 static size_t skinny_bytes(int nb, int k, const int* d, int c) {
   size_t b = 0;
-  for (int s = 0; s < nb; ++s) b = std::max(b, skinny_ws_bytes(d[s], d[s], 2 * k));
+  for (int s = 0; s < nb; ++s) b += skinny_ws_bytes(d[s], d[s], 2 * k) + 256;
   if (c > 0) b = std::max({b, skinny_ws_bytes(c, d[0], k), skinny_ws_bytes(d[0], c, k)});
   return b;
 }
@@ -281,10 +327,10 @@ static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int c
 }
 
 static int apply_minv(const RcgProblem& P, RcgBuffers& B, hipStream_t st) {
+  SkinnyProb pr[2];
   for (int s = 0; s < P.nb; ++s)
-    SRP_TRY(gemm_skinny_f64(P.d[s], P.d[s], 2 * P.k, P.Minv[s], P.d[s], false, B.Z[s], 2 * P.k, B.Wz[s], 2 * P.k,
-                            B.skw, B.skw_bytes, st));
-  return SRP_OK;
+    pr[s] = SkinnyProb{P.d[s], P.d[s], 2 * P.k, P.Minv[s], P.d[s], false, B.Z[s], 2 * P.k, B.Wz[s], 2 * P.k};
+  return gemm_skinny_batch(P.nb, pr, B.skw, B.skw_bytes, st);
 }
 
 // Gradient, transported direction and new CG direction at the current point.
@@ -505,7 +551,7 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   bytes += bytes_of<int>(4);
   const size_t scratch = std::max({sketch_ws(opt.sketch, n, std::max(dx, dy), s, dtype), factor_ws_bytes(s, std::max(dx, dy))});
   bytes += rcg_buffers_bytes(2, k, std::max<int64_t>(n, s), dd, dtype);
-  bytes += scratch + 4096;
+  bytes += 2 * ((scratch + 255) & ~size_t(255)) + 4096;   // one scratch per view (the views run concurrently)
   Workspace W;
   W.st = st;
   SRP_TRY(device_alloc(&W.base, bytes, st));
@@ -517,27 +563,35 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   double* Mx = ar.take<double>((size_t)dx * dx);
   double* My = ar.take<double>((size_t)dy * dy);
   double* Rinv = ar.take<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
+  double* Rinv2 = ar.take<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
   int* flag = ar.take<int>(4);
   RcgBuffers B{};
-  if (!flag || rcg_buffers_take(B, ar, 2, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
+  if (!flag || !Rinv2 || rcg_buffers_take(B, ar, 2, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
     set_error("workspace layout overflow");
     return SRP_ENOMEM;
   }
   SRP_TRY(setup_mu(opt, k, B.mu, st));
-  // 1. sketches (same S for X and Y)
-  SRP_TRY(sketch_any(opt.sketch, X, dtype, n, dx, s, opt.seed, SX, ar, st));
-  SRP_TRY(sketch_any(opt.sketch, Y, dtype, n, dy, s, opt.seed, SY, ar, st));
-  const double ms_sketch = tm.lap_ms();
-  // 2. metric factors
   SRP_TRY(fill_i32(flag, 1, 0, st));
+  // 1-2. sketches (same S for X and Y) and metric factors: the Y view on the
+  // side stream, concurrently with the X view (separate scratch)
+  const size_t scr = (scratch + 255) & ~size_t(255);
+  Arena sx{ar.base + ar.used, scr, 0};
+  Arena sy{ar.base + ar.used + scr, scr, 0};
+  if (ar.used + 2 * scr > ar.cap) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+  SideFork fk;
+  SRP_TRY(fk.begin(st));
+  SRP_TRY(sketch_any(opt.sketch, Y, dtype, n, dy, s, opt.seed, SY, sy, fk.side));
   {
-    Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
+    Arena sub{sy.base, sy.cap, 0};
+    SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side));
+  }
+  SRP_TRY(sketch_any(opt.sketch, X, dtype, n, dx, s, opt.seed, SX, sx, st));
+  const double ms_sketch = tm.lap_ms();   // X view's sketch (Y's runs alongside)
+  {
+    Arena sub{sx.base, sx.cap, 0};
     SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st));
   }
-  {
-    Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
-    SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv, My, flag, sub, st));
-  }
+  SRP_TRY(fk.end(st));
   int hflag = 0;
   SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   SRP_HIP(hipStreamSynchronize(st));

@@ -38,7 +38,11 @@ int copy_f64(double* dst, const double* src, int64_t count, hipStream_t st) {
 
 // ------------------------------------------------------------- GEMM
 // One workgroup = one 64x64 output tile; 4 waves, each a 32x32 quadrant of
-// 2x2 MFMA tiles; the k dimension is staged through LDS 16 at a time.
+// 2x2 MFMA tiles.  The k dimension is staged through LDS 32 at a time; the
+// global loads of chunk i+1 are in flight in registers while the matrix
+// cores work on chunk i.
+constexpr int kGemmK = 32;
+
 template <class AT, class BT, bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int kk, double alpha, const AT* __restrict__ A,
                                                   int64_t lda, const BT* __restrict__ B, int64_t ldb, double beta,
@@ -50,8 +54,8 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int kk, double a
   const int kbeg = z * kchunk;
   const int kend = min(kk, kbeg + kchunk);
   C += (int64_t)z * c_split_stride;
-  __shared__ double As[16][65];
-  __shared__ double Bs[16][65];
+  __shared__ double As[kGemmK][65];
+  __shared__ double Bs[kGemmK][65];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wi = (w >> 1) * 32, wj = (w & 1) * 32;
   f64x4 acc[2][2];
@@ -59,26 +63,36 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int kk, double a
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+  constexpr int PER = kGemmK * 64 / 256;
+  double ra[PER], rb[PER];
+  auto load = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < PER; ++q) {
       const int e = t + q * 256;
       int kq, iq;
-      if (TA) { kq = e >> 6; iq = e & 63; } else { iq = e >> 4; kq = e & 15; }
+      if (TA) { kq = e >> 6; iq = e & 63; } else { iq = e >> 5; kq = e & 31; }
       const int gi = i0 + iq, gk = k0 + kq;
-      double v = 0.0;
-      if (gi < m && gk < kend) v = TA ? (double)A[(int64_t)gk * lda + gi] : (double)A[(int64_t)gi * lda + gk];
-      As[kq][iq] = v;
+      ra[q] = (gi < m && gk < kend) ? (TA ? (double)A[(int64_t)gk * lda + gi] : (double)A[(int64_t)gi * lda + gk])
+                                    : 0.0;
       int kb, jb;
-      if (!TB) { kb = e >> 6; jb = e & 63; } else { jb = e >> 4; kb = e & 15; }
+      if (!TB) { kb = e >> 6; jb = e & 63; } else { jb = e >> 5; kb = e & 31; }
       const int gj = j0 + jb, gk2 = k0 + kb;
-      double u = 0.0;
-      if (gj < n && gk2 < kend) u = TB ? (double)B[(int64_t)gj * ldb + gk2] : (double)B[(int64_t)gk2 * ldb + gj];
-      Bs[kb][jb] = u;
+      rb[q] = (gj < n && gk2 < kend) ? (TB ? (double)B[(int64_t)gj * ldb + gk2] : (double)B[(int64_t)gk2 * ldb + gj])
+                                     : 0.0;
+    }
+  };
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kGemmK) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = t + q * 256;
+      if (TA) As[e >> 6][e & 63] = ra[q]; else As[e & 31][e >> 5] = ra[q];
+      if (!TB) Bs[e >> 6][e & 63] = rb[q]; else Bs[e & 31][e >> 5] = rb[q];
     }
     __syncthreads();
+    if (k0 + kGemmK < kend) load(k0 + kGemmK);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < kGemmK / 4; ++s) {
       const int kl = 4 * s + (lane >> 4);
       const double a0 = As[kl][wi + (lane & 15)], a1 = As[kl][wi + 16 + (lane & 15)];
       const double b0 = Bs[kl][wj + (lane & 15)], b1 = Bs[kl][wj + 16 + (lane & 15)];
@@ -109,7 +123,7 @@ template <class AT, class BT>
 static int gemm_dispatch_t(const GemmArgs& g, hipStream_t st) {
   dim3 grid((g.n + 63) / 64, (g.m + 63) / 64, g.ksplit);
   int kchunk = g.kk;
-  if (g.ksplit > 1) kchunk = (((g.kk + g.ksplit - 1) / g.ksplit) + 15) / 16 * 16;
+  if (g.ksplit > 1) kchunk = (((g.kk + g.ksplit - 1) / g.ksplit) + kGemmK - 1) / kGemmK * kGemmK;
   const AT* A = (const AT*)g.A;
   const BT* B = (const BT*)g.B;
 #define SRP_GEMM_CASE(TA_, TB_)                                                                    \
@@ -158,67 +172,75 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
 // matching rows of B, and writes a partial; a second kernel adds the
 // partials in slice order (deterministic).  Thread (r, jg) keeps the
 // columns jg, jg + 16, ... of row r.
-constexpr int kSkRows = 16;
-constexpr int kSkChunk = 64;
 constexpr int kSkSlice = 128;
 
-__global__ void __launch_bounds__(256) k_gemm_skinny(int m, int kk, int nc, const double* __restrict__ A,
-                                                     int64_t lda, int ta, const double* __restrict__ B,
-                                                     int64_t ldb, double* __restrict__ part) {
-  __shared__ double As[kSkRows][kSkChunk + 1];
-  __shared__ double Bs[kSkChunk][64];
-  const int r0 = blockIdx.x * kSkRows;
-  const int lbeg = blockIdx.y * kSkSlice, lend = min(kk, lbeg + kSkSlice);
-  const int tid = threadIdx.x;
-  const int r = tid >> 4, jg = tid & 15;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int l0 = lbeg; l0 < lend; l0 += kSkChunk) {
-    if (ta) {
-      for (int e = tid; e < kSkRows * kSkChunk; e += 256) {
-        const int ll = e / kSkRows, rr = e % kSkRows;
-        const int gr = r0 + rr, gl = l0 + ll;
-        As[rr][ll] = (gr < m && gl < lend) ? A[(int64_t)gl * lda + gr] : 0.0;
-      }
-    } else {
-      for (int e = tid; e < kSkRows * kSkChunk; e += 256) {
-        const int rr = e / kSkChunk, ll = e % kSkChunk;
-        const int gr = r0 + rr, gl = l0 + ll;
-        As[rr][ll] = (gr < m && gl < lend) ? A[(int64_t)gr * lda + gl] : 0.0;
-      }
-    }
-    for (int e = tid; e < kSkChunk * nc; e += 256) {
-      const int ll = e / nc, j = e % nc;
-      const int gl = l0 + ll;
-      Bs[ll][j] = (gl < lend) ? B[(int64_t)gl * ldb + j] : 0.0;
+// Up to two independent problems per launch (blockIdx.z), e.g. both views.
+struct SkinnyBatch {
+  SkinnyProb p[2];
+  double* part[2];
+};
+
+// FP64 matrix cores: a workgroup (4 waves) owns 64 rows x up to 64 columns
+// of one contraction slice; wave w computes rows 16w..16w+15 for every
+// 16-column tile.  Operands are staged 32 contraction steps at a time.
+__global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
+  const SkinnyProb& pr = bt.p[blockIdx.z];
+  const int m = pr.m, kk = pr.kk, nc = pr.nc;
+  const double* __restrict__ A = pr.A;
+  const double* __restrict__ B = pr.B;
+  const int64_t lda = pr.lda, ldb = pr.ldb;
+  const int r0 = blockIdx.x * 64;
+  const int lbeg = blockIdx.y * kSkSlice;
+  if (r0 >= m || lbeg >= kk) return;
+  const int lend = min(kk, lbeg + kSkSlice);
+  const int nct = (nc + 15) >> 4;
+  __shared__ double As[32][65];   // [k][row]
+  __shared__ double Bs[32][65];   // [k][col]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  f64x4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int l0 = lbeg; l0 < lend; l0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      int rr, ll;
+      if (pr.ta) { ll = e >> 6; rr = e & 63; } else { rr = e >> 5; ll = e & 31; }
+      const int gr = r0 + rr, gl = l0 + ll;
+      As[ll][rr] = (gr < m && gl < lend) ? (pr.ta ? A[(int64_t)gl * lda + gr] : A[(int64_t)gr * lda + gl]) : 0.0;
+      const int bl = e >> 6, bj = e & 63;
+      const int gbl = l0 + bl;
+      Bs[bl][bj] = (bj < nc && gbl < lend) ? B[(int64_t)gbl * ldb + bj] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int ll = 0; ll < kSkChunk; ++ll) {
-      const double a = As[r][ll];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = jg + 16 * q;
-        if (j < nc) acc[q] += a * Bs[ll][j];
-      }
+    for (int s4 = 0; s4 < 8; ++s4) {
+      const int kl = 4 * s4 + (lane >> 4);
+      const double av = As[kl][16 * w + (lane & 15)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (q < nct) acc[q] = mfma16x16x4(av, Bs[kl][16 * q + (lane & 15)], acc[q]);
     }
     __syncthreads();
   }
-  const int gr = r0 + r;
-  if (gr < m) {
-    double* out = part + ((int64_t)blockIdx.y * m + gr) * nc;
+  double* out = bt.part[blockIdx.z] + (int64_t)blockIdx.y * m * nc;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = jg + 16 * q;
-      if (j < nc) out[j] = acc[q];
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + 16 * w + acc_row<double>(lane, r);
+      const int col = 16 * q + (lane & 15);
+      if (q < nct && row < m && col < nc) out[(int64_t)row * nc + col] = acc[q][r];
     }
-  }
 }
 
-__global__ void __launch_bounds__(256) k_skinny_sum(int m, int nc, int nsl, const double* __restrict__ part,
-                                                    double* __restrict__ C, int64_t ldc) {
+__global__ void __launch_bounds__(256) k_skinny_sum(SkinnyBatch bt) {
+  const SkinnyProb& pr = bt.p[blockIdx.y];
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
-  const int64_t cnt = (int64_t)m * nc;
+  const int64_t cnt = (int64_t)pr.m * pr.nc;
   if (e >= cnt) return;
+  const int nsl = (pr.kk + kSkSlice - 1) / kSkSlice;
+  const double* part = bt.part[blockIdx.y];
   double s0 = 0.0, s1 = 0.0;
   int z = 0;
   for (; z + 2 <= nsl; z += 2) {
@@ -226,8 +248,8 @@ __global__ void __launch_bounds__(256) k_skinny_sum(int m, int nc, int nsl, cons
     s1 += part[(int64_t)(z + 1) * cnt + e];
   }
   if (z < nsl) s0 += part[(int64_t)z * cnt + e];
-  const int64_t row = e / nc, col = e % nc;
-  C[row * ldc + col] = s0 + s1;
+  const int64_t row = e / pr.nc, col = e - row * pr.nc;
+  pr.C[row * pr.ldc + col] = s0 + s1;
 }
 
 size_t skinny_ws_bytes(int m, int kk, int nc) {
@@ -235,24 +257,38 @@ size_t skinny_ws_bytes(int m, int kk, int nc) {
   return bytes_of<double>(nsl * (size_t)m * nc);
 }
 
-int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
-                    double* C, int64_t ldc, double* ws, size_t ws_bytes, hipStream_t st) {
-  if (nc > 64 || nc < 1 || m < 1 || kk < 1) {
-    set_error("gemm_skinny: bad shape m=%d kk=%d nc=%d", m, kk, nc);
-    return SRP_EINVAL;
+int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_bytes, hipStream_t st) {
+  SkinnyBatch bt{};
+  size_t used = 0;
+  int gx = 1, gy = 1, sx = 1;
+  for (int q = 0; q < nprob; ++q) {
+    const SkinnyProb& p = probs[q];
+    if (p.nc > 64 || p.nc < 1 || p.m < 1 || p.kk < 1) {
+      set_error("gemm_skinny: bad shape m=%d kk=%d nc=%d", p.m, p.kk, p.nc);
+      return SRP_EINVAL;
+    }
+    bt.p[q] = p;
+    bt.part[q] = (double*)((char*)ws + used);
+    used += skinny_ws_bytes(p.m, p.kk, p.nc);
+    gx = std::max(gx, (p.m + 63) / 64);
+    gy = std::max(gy, (p.kk + kSkSlice - 1) / kSkSlice);
+    sx = std::max(sx, (int)(((int64_t)p.m * p.nc + 255) / 256));
   }
-  const int nsl = (kk + kSkSlice - 1) / kSkSlice;
-  if (!ws || skinny_ws_bytes(m, kk, nc) > ws_bytes) {
+  if (!ws || used > ws_bytes) {
     set_error("gemm_skinny: workspace too small");
     return SRP_ENOMEM;
   }
-  hipLaunchKernelGGL(k_gemm_skinny, dim3((m + kSkRows - 1) / kSkRows, nsl), dim3(256), 0, st, m, kk, nc, A, lda,
-                     ta ? 1 : 0, B, ldb, ws);
+  hipLaunchKernelGGL(k_gemm_skinny, dim3(gx, gy, nprob), dim3(256), 0, st, bt);
   SRP_LAUNCH_CHECK();
-  const int64_t cnt = (int64_t)m * nc;
-  hipLaunchKernelGGL(k_skinny_sum, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, m, nc, nsl, ws, C, ldc);
+  hipLaunchKernelGGL(k_skinny_sum, dim3(sx, nprob), dim3(256), 0, st, bt);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
+}
+
+int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
+                    double* C, int64_t ldc, double* ws, size_t ws_bytes, hipStream_t st) {
+  SkinnyProb p{m, kk, nc, A, lda, ta, B, ldb, C, ldc};
+  return gemm_skinny_batch(1, &p, ws, ws_bytes, st);
 }
 
 // --------------------------------------------------------- Cholesky
@@ -260,11 +296,26 @@ int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta
 // (upper triangle read): R_kk upper with R_kk^T R_kk = G_kk, written into R;
 // its inverse into Dinv (64 x 64, upper, identity-padded).  Sets *flag on a
 // non-positive pivot.
+//
+// Right-looking with one barrier per column: step j updates the trailing
+// triangle with the unscaled row j (a[r][c] -= a[j][r] a[j][c] / a[j][j])
+// and scales row j - 1 into its final form, so no thread reads a row that
+// another thread of the same step writes.  The inverse is back-substituted
+// by four lanes per column (one wave per 16 columns): the four partial dot
+// products of a row are combined with lane shuffles, so the only
+// dependence between rows is inside a wave.
+__device__ __forceinline__ void wave_fence_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ G, int64_t ld, int k0, int nb,
                                                      double* __restrict__ R, double* __restrict__ Dinv,
                                                      int* flag) {
   __shared__ double a[64][65];
   __shared__ double x[64][65];
+  __shared__ double piv[64];
   const int t = threadIdx.x;
   for (int e = t; e < 4096; e += 256) {
     const int r = e >> 6, c = e & 63;
@@ -279,34 +330,63 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
   }
   __syncthreads();
   for (int j = 0; j < 64; ++j) {
+    double p = a[j][j];
+    if (!(p > 0.0)) p = 1.0;
+    const double rp = 1.0 / p;
     if (t == 0) {
-      double p = a[j][j];
-      if (!(p > 0.0)) {
-        atomicOr(flag, 1);
-        p = 1.0;
-      }
-      a[j][j] = sqrt(p);
+      if (!(a[j][j] > 0.0)) atomicOr(flag, 1);
+      piv[j] = p;
     }
-    __syncthreads();
-    const double djj = a[j][j];
-    for (int c = j + 1 + t; c < 64; c += 256) a[j][c] /= djj;
-    __syncthreads();
-    const int w = 63 - j;  // trailing size
-    for (int e = t; e < w * w; e += 256) {
-      const int r = j + 1 + e / w, c = j + 1 + e % w;
-      if (r <= c) a[r][c] -= a[j][r] * a[j][c];
+    if (j > 0) {   // final form of row j - 1
+      const double dj = sqrt(piv[j - 1]);
+      for (int c = j - 1 + t; c < 64; c += 256) a[j - 1][c] = (c == j - 1) ? dj : a[j - 1][c] / dj;
+    }
+    {   // trailing triangle j < r <= c: thread (r0, c) takes rows j + 1 + r0 + 4 m;
+        // all loads of the step issue before the first store
+      const int c = t & 63, r0 = j + 1 + (t >> 6);
+      const double ajc = a[j][c] * rp;
+      double arc[16], ajr[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {   // unconditional loads (clamped rows) so they issue together
+        const int r = min(r0 + 4 * m, 63);
+        arc[m] = a[r][c];
+        ajr[m] = a[j][r];
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int r = r0 + 4 * m;
+        if (r <= c) a[r][c] = arc[m] - ajr[m] * ajc;
+      }
     }
     __syncthreads();
   }
-  // inverse of the upper factor, one column per thread
-  if (t < 64) {
-    const int c = t;
-    for (int r = 0; r < 64; ++r) x[r][c] = 0.0;
-    x[c][c] = 1.0 / a[c][c];
-    for (int r = c - 1; r >= 0; --r) {
+  {
+    const double d63 = sqrt(piv[63]);
+    if (t == 0) a[63][63] = d63;
+  }
+  __syncthreads();
+  // x = a^-1 (upper): lanes 4c .. 4c + 3 own column c
+  if (t < 64) piv[t] = 1.0 / a[t][t];
+  __syncthreads();
+  {
+    const int c = t >> 2, q = t & 3;
+    for (int r = 0; r < 64; ++r) x[r][c] = 0.0;   // (each of the 4 lanes writes the same zeros)
+    wave_fence_sync();
+    if (q == 0) x[c][c] = piv[c];
+    wave_fence_sync();
+    for (int r = 62; r >= 0; --r) {
       double s = 0.0;
-      for (int l = r + 1; l <= c; ++l) s += a[r][l] * x[l][c];
-      x[r][c] = -s / a[r][r];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {   // unconditional loads (clamped index), masked products
+        const int l = r + 1 + q + 4 * m;
+        const int lc = min(l, 63);
+        const double prod = a[r][lc] * x[lc][c];
+        s += (l <= c) ? prod : 0.0;
+      }
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      if (r < c && q == 0) x[r][c] = -s * piv[r];
+      wave_fence_sync();
     }
   }
   __syncthreads();
@@ -328,6 +408,8 @@ __global__ void k_place_diag_blocks(const double* __restrict__ Dinv, int d, doub
   }
 }
 
+constexpr int kInvSplit = 8;   // split of the contraction in the R^-1 block rows
+
 size_t factor_ws_bytes(int s, int d) {
   const int tiles = (d + 63) / 64;
   const int nupper = tiles * (tiles + 1) / 2;
@@ -337,7 +419,7 @@ size_t factor_ws_bytes(int s, int d) {
   if (ksplit < 1) ksplit = 1;
   const size_t dd = (size_t)d * d;
   return bytes_of<double>(dd) * (ksplit > 1 ? ksplit + 1 : 1) + bytes_of<double>((size_t)tiles * 4096) +
-         bytes_of<double>((size_t)64 * d) + bytes_of<double>(dd);
+         bytes_of<double>((size_t)64 * d) + bytes_of<double>(dd) + bytes_of<double>((size_t)kInvSplit * 64 * d);
 }
 
 int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
@@ -354,7 +436,8 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
   double* Dinv = ws.take<double>((size_t)tiles * 4096);
   double* Tmp = ws.take<double>((size_t)64 * d);
   double* X = Rinv ? Rinv : ws.take<double>(dd);
-  if (!G || !Dinv || !Tmp || !X || (ksplit > 1 && !parts)) {
+  double* Tparts = ws.take<double>((size_t)kInvSplit * 64 * d);
+  if (!G || !Dinv || !Tmp || !X || !Tparts || (ksplit > 1 && !parts)) {
     set_error("sketch_factor: workspace too small");
     return SRP_ENOMEM;
   }
@@ -409,8 +492,15 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
     a.m = 64; a.n = rest; a.kk = rest; a.alpha = 1.0; a.beta = 0.0;
     a.A = R + (int64_t)i0 * d + c1; a.lda = d; a.ta = false;
     a.B = X + (int64_t)c1 * d + c1; a.ldb = d; a.tb = false;
-    a.C = Tmp; a.ldc = rest;
-    SRP_TRY(gemm_f64(a, st));
+    const int ks = std::min(kInvSplit, (rest + 127) / 128);
+    if (ks > 1) {   // 64 x rest outputs are few tiles: split the contraction
+      a.C = Tparts; a.ldc = rest; a.ksplit = ks; a.c_split_stride = (int64_t)64 * rest;
+      SRP_TRY(gemm_f64(a, st));
+      SRP_TRY(sum_parts_f64(Tparts, ks, (int64_t)64 * rest, (int64_t)64 * rest, Tmp, 0, 0.0, st));
+    } else {
+      a.C = Tmp; a.ldc = rest;
+      SRP_TRY(gemm_f64(a, st));
+    }
     GemmArgs b{};
     b.m = 64; b.n = rest; b.kk = 64; b.alpha = -1.0; b.beta = 0.0;
     b.A = Dinv + (size_t)ib * 4096; b.lda = 64; b.ta = false;

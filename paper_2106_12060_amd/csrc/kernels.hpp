@@ -38,6 +38,14 @@ int gemm_f64(const GemmArgs& g, hipStream_t st);
 // op(A) = A^T when ta, A then kk x m).  ws holds the split-K partials
 // (skinny_ws_bytes).
 size_t skinny_ws_bytes(int m, int kk, int nc);
+struct SkinnyProb {
+  int m, kk, nc;
+  const double* A; int64_t lda; bool ta;
+  const double* B; int64_t ldb;
+  double* C; int64_t ldc;
+};
+// Up to two problems in one launch; ws holds skinny_ws_bytes of each, in order.
+int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_bytes, hipStream_t st);
 int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
                     double* C, int64_t ldc, double* ws, size_t ws_bytes, hipStream_t st);
 // out[i] = sum_z parts[z * stride + i] (+ diag_add on the diagonal of a

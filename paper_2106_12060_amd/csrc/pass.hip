@@ -45,14 +45,35 @@ template <> struct PassCfg<double> { static constexpr int dmax = 896; static con
 
 __host__ __device__ constexpr int pass_pitch(int D) { return ((D + 63) / 64) * 64 + 4; }
 
-// Pack a double d x k direction into a zero-padded (ceil16(d) x KT*16) CT
-// matrix.
+// Pack double d_b x k directions into zero-padded (ceil16(d_b) x kpad) CT
+// matrices, both blocks in one launch (block 1 follows block 0's elements).
 template <class CT>
-__global__ void k_pack_dir(const double* __restrict__ W, int d, int k, int dpad, int kpad, CT* __restrict__ Wp) {
+__global__ void k_pack_dir(const double* __restrict__ W0, int d0, int dpad0, CT* __restrict__ Wp0,
+                           const double* __restrict__ W1, int d1, int dpad1, CT* __restrict__ Wp1, int k, int kpad) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)dpad * kpad) return;
-  const int r = (int)(i / kpad), c = (int)(i % kpad);
+  const int64_t n0 = (int64_t)dpad0 * kpad;
+  const double* W = W0;
+  CT* Wp = Wp0;
+  int d = d0;
+  if (i >= n0) {
+    i -= n0;
+    if (i >= (int64_t)dpad1 * kpad) return;
+    W = W1;
+    Wp = Wp1;
+    d = d1;
+  }
+  const int r = (int)(i / kpad), c = (int)(i - (int64_t)r * kpad);
   Wp[i] = (r < d && c < k) ? (CT)W[(int64_t)r * k + c] : CT(0);
+}
+
+template <class CT>
+static int pack_dirs(const double* W0, int d0, int dp0, CT* Wp0, const double* W1, int d1, int dp1, CT* Wp1, int k,
+                     int KP, hipStream_t st) {
+  const int64_t tot = (int64_t)dp0 * KP + (Wp1 ? (int64_t)dp1 * KP : 0);
+  hipLaunchKernelGGL((k_pack_dir<CT>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, W0, d0, dp0, Wp0, W1,
+                     d1, Wp1 ? dp1 : 0, Wp1, k, KP);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
 }
 
 // Buffer loads: a scalar base (the row block) plus a 32-bit lane offset;
@@ -609,12 +630,7 @@ static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, in
   const int Dtot = d0 + (NB == 2 ? d1 : 0);
   CT* part = ws.take<CT>((size_t)groups * Dtot * NB * k);
   if (!Wp0 || !part || (NB == 2 && !Wp1)) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
-  hipLaunchKernelGGL((k_pack_dir<CT>), dim3((dp0 * KP + 255) / 256), dim3(256), 0, st, W0, d0, k, dp0, KP, Wp0);
-  SRP_LAUNCH_CHECK();
-  if (NB == 2) {
-    hipLaunchKernelGGL((k_pack_dir<CT>), dim3((dp1 * KP + 255) / 256), dim3(256), 0, st, W1, d1, k, dp1, KP, Wp1);
-    SRP_LAUNCH_CHECK();
-  }
+  SRP_TRY(pack_dirs<CT>(W0, d0, dp0, Wp0, W1, d1, dp1, Wp1, k, KP, st));
   const int nrb = (int)((n + 15) / 16);
   const size_t lds = pass_lds_bytes<CT>(Dtot, NB * KT);
   static bool attr_done = false;   // per template instance
@@ -644,16 +660,12 @@ static int pass_launch_dma(const float* A0, const float* A1, int64_t n, int d0, 
   float* Wp0 = ws.take<float>((size_t)dp0 * KP);
   float* Wp1 = NB == 2 ? ws.take<float>((size_t)dp1 * KP) : nullptr;
   const int nrb = (int)((n + kDmaRows - 1) / kDmaRows);
-  const int grid = std::max(1, std::min(num_cus(), nrb));
+  // at least 4 blocks per workgroup (fewer partials to add for short data)
+  const int grid = std::max(1, std::min(num_cus(), (nrb + 3) / 4));
   const int Dtot = d0 + (NB == 2 ? d1 : 0);
   float* part = ws.take<float>((size_t)grid * Dtot * NB * k);
   if (!Wp0 || !part || (NB == 2 && !Wp1)) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
-  hipLaunchKernelGGL((k_pack_dir<float>), dim3((dp0 * KP + 255) / 256), dim3(256), 0, st, W0, d0, k, dp0, KP, Wp0);
-  SRP_LAUNCH_CHECK();
-  if (NB == 2) {
-    hipLaunchKernelGGL((k_pack_dir<float>), dim3((dp1 * KP + 255) / 256), dim3(256), 0, st, W1, d1, k, dp1, KP, Wp1);
-    SRP_LAUNCH_CHECK();
-  }
+  SRP_TRY(pack_dirs<float>(W0, d0, dp0, Wp0, W1, d1, dp1, Wp1, k, KP, st));
   const size_t lds = dma_lds_bytes(d0, NB == 2 ? d1 : 0, NB * KT);
   static bool attr_done = false;   // per template instance
   if (!attr_done) {

@@ -314,7 +314,9 @@ static int srht_select_rows(int64_t n_pad, int s, uint64_t seed, int64_t* rows, 
 
 // Group the sampled rows by beta = r mod B (single workgroup).  For every
 // beta: goff[beta] .. goff[beta+1] index into galpha / gslot, listing the
-// sampled rows with that beta in ascending order (alpha = r / B, slot = j).
+// sampled rows with that beta (alpha = r / B, slot = j).  The order inside
+// a group does not affect any sum (level 2 sums over all blocks for every
+// row), so positions come from LDS atomics.
 __global__ void __launch_bounds__(1024) k_srht_group(const int64_t* rows, int s, int B, int logB,
                                                      int* goff, int* galpha, int* gslot) {
   __shared__ int cnt[1024];
@@ -331,16 +333,11 @@ __global__ void __launch_bounds__(1024) k_srht_group(const int64_t* rows, int s,
   }
   __syncthreads();
   for (int b = t; b <= B; b += 1024) goff[b] = off[b];
-  for (int b = t; b < B; b += 1024) {
-    int pos = off[b];
-    for (int j = 0; j < s; ++j) {
-      const int64_t r = rows[j];
-      if ((int)(r & (B - 1)) == b) {
-        galpha[pos] = (int)(r >> logB);
-        gslot[pos] = j;
-        ++pos;
-      }
-    }
+  for (int j = t; j < s; j += 1024) {
+    const int64_t r = rows[j];
+    const int pos = atomicAdd(&off[(int)(r & (B - 1))], 1);
+    galpha[pos] = (int)(r >> logB);
+    gslot[pos] = j;
   }
 }
 
@@ -383,6 +380,79 @@ __global__ void __launch_bounds__(256) k_srht_level1(const T* __restrict__ A, in
   for (int e = threadIdx.x; e < tot; e += 256) {
     const int r = e / CW, c = e % CW;
     if (c < cw) Tbuf[((int64_t)a * B + r) * d + c0 + c] = tile[e];
+  }
+}
+
+// Level 1 for B >= 64, in registers: a workgroup transforms block a for
+// CW = 16384 / B columns.  Thread (c, g) of G = 256 / CW row groups first
+// holds rows g + G i (i < 64) of column c: the butterflies over the six high
+// row bits run in registers; one LDS exchange then gives thread (c, h) the
+// rows lo + G (h 64/G + k), lo < G, k < 64/G, and the butterflies over the
+// low log2 G row bits run in registers too.  One barrier per block.
+template <class T, class Acc>
+__global__ void __launch_bounds__(256) k_srht_level1_reg(const T* __restrict__ A, int64_t n, int d, int logB,
+                                                         uint64_t seedD, Acc* __restrict__ Tbuf) {
+  extern __shared__ unsigned char smem_raw[];
+  Acc* tile = reinterpret_cast<Acc*>(smem_raw);   // [B][CW]
+  const int B = 1 << logB;
+  const int logCW = 14 - logB, CW = 1 << logCW;
+  const int logG = 8 - logCW, G = 1 << logG;
+  const int a = blockIdx.x;
+  const int c0 = blockIdx.y * CW;
+  const int c = threadIdx.x & (CW - 1), g = threadIdx.x >> logCW;
+  const bool col_ok = c0 + c < d;
+  // the block's signs D_i, one hash per row (after the tile)
+  Acc* sgn = tile + 16384;
+  for (int r = threadIdx.x; r < B; r += 256)
+    sgn[r] = (splitmix64(seedD, (uint64_t)((int64_t)a * B + r)) & 1ull) ? Acc(-1) : Acc(1);
+  __syncthreads();
+  Acc v[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    const int r = g + G * i;
+    const int64_t row = (int64_t)a * B + r;
+    Acc x = Acc(0);
+    if (col_ok && row < n) x = load_as<Acc>(A + row * d + c0 + c) * sgn[r];
+    v[i] = x;
+  }
+#pragma unroll
+  for (int h = 1; h < 64; h <<= 1)
+#pragma unroll
+    for (int i = 0; i < 64; ++i)
+      if ((i & h) == 0) {
+        const Acc x = v[i], y = v[i + h];
+        v[i] = x + y;
+        v[i + h] = x - y;
+      }
+#pragma unroll
+  for (int i = 0; i < 64; ++i) tile[(g + G * i) * CW + c] = v[i];
+  __syncthreads();
+  const int K = 64 >> logG;   // rows per low-bit group held by a thread
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    const int lo = i & (G - 1), k = i >> logG;
+    v[i] = tile[(lo + G * (g * K + k)) * CW + c];
+  }
+#pragma unroll
+  for (int lh = 0; lh < 4; ++lh) {   // G <= 16
+    if (lh < logG) {
+      const int h = 1 << lh;
+#pragma unroll
+      for (int i = 0; i < 64; ++i)
+        if ((i & h) == 0) {
+          const Acc x = v[i], y = v[i + h];
+          v[i] = x + y;
+          v[i + h] = x - y;
+        }
+    }
+  }
+  if (col_ok) {
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      const int lo = i & (G - 1), k = i >> logG;
+      const int r = lo + G * (g * K + k);
+      Tbuf[((int64_t)a * B + r) * d + c0 + c] = v[i];
+    }
   }
 }
 
@@ -445,11 +515,26 @@ template <class T, class Acc>
 static int srht_levels(const T* A, int64_t n, int d, int s, uint64_t seed, const SrhtGeom& g,
                        const int* goff, const int* galpha, const int* gslot, Acc* Tbuf, Acc* out,
                        hipStream_t st) {
-  const int CW = srht_chunk_cols(g.B, (int)sizeof(Acc));
-  dim3 grid1(g.A_eff, (d + CW - 1) / CW);
-  const size_t lds = (size_t)g.B * CW * sizeof(Acc);
-  hipLaunchKernelGGL((k_srht_level1<T, Acc>), grid1, dim3(256), lds, st, A, n, d, g.B, (g.m + 1) / 2, CW,
-                     seed ^ kSrhtSignSalt, Tbuf);
+  const int logB = (g.m + 1) / 2;
+  if (logB >= 6 && logB <= 10) {
+    const int CW = 16384 >> logB;
+    dim3 grid1(g.A_eff, (d + CW - 1) / CW);
+    const size_t lds = (size_t)(16384 + 1024) * sizeof(Acc);
+    static bool attr = false;
+    if (!attr) {
+      SRP_HIP(hipFuncSetAttribute((const void*)k_srht_level1_reg<T, Acc>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      attr = true;
+    }
+    hipLaunchKernelGGL((k_srht_level1_reg<T, Acc>), grid1, dim3(256), lds, st, A, n, d, logB,
+                       seed ^ kSrhtSignSalt, Tbuf);
+  } else {
+    const int CW = srht_chunk_cols(g.B, (int)sizeof(Acc));
+    dim3 grid1(g.A_eff, (d + CW - 1) / CW);
+    const size_t lds = (size_t)g.B * CW * sizeof(Acc);
+    hipLaunchKernelGGL((k_srht_level1<T, Acc>), grid1, dim3(256), lds, st, A, n, d, g.B, logB, CW,
+                       seed ^ kSrhtSignSalt, Tbuf);
+  }
   SRP_LAUNCH_CHECK();
   dim3 grid2(g.B, (d + 255) / 256);
   hipLaunchKernelGGL((k_srht_level2<Acc>), grid2, dim3(256), 0, st, Tbuf, d, g.B, g.A_eff, goff, galpha,

@@ -30,6 +30,13 @@
 
 namespace srp {
 
+// e / d for 0 <= e < 2^19 and 1 <= d <= 4096 without an integer division:
+// (e + 0.5) / d lies at least 0.5 / d from an integer, far more than the
+// error of the single-precision reciprocal and product.
+__device__ __forceinline__ int sdiv(int e, int d) {
+  return (int)(((float)e + 0.5f) * __builtin_amdgcn_rcpf((float)d));
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -56,6 +63,7 @@ struct PartialArgs {
 };
 
 constexpr int kPartRows = 16;
+constexpr int kMaxSlices = 16;   // row-slice partials per side
 
 __global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
   if (a.ctrl && a.ctrl->done) return;
@@ -71,12 +79,12 @@ __global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
   const int nout = NL * NR;
   for (int r0 = z * kPartRows; r0 < ps.d; r0 += a.slices * kPartRows) {
     for (int e = threadIdx.x; e < kPartRows * NL; e += 256) {
-      const int rr = e / NL, c = e % NL, blk = c / k, j = c % k;
+      const int rr = sdiv(e, NL), c = e - rr * NL, blk = sdiv(c, k), j = c - blk * k;
       const int r = r0 + rr;
       ls[rr][c] = (r < ps.d) ? ps.lp[blk][(int64_t)r * ps.lld[blk] + j] : 0.0;
     }
     for (int e = threadIdx.x; e < kPartRows * NR; e += 256) {
-      const int rr = e / NR, c = e % NR, blk = c / k, j = c % k;
+      const int rr = sdiv(e, NR), c = e - rr * NR, blk = sdiv(c, k), j = c - blk * k;
       const int r = r0 + rr;
       rs[rr][c] = (r < ps.d) ? ps.rp[blk][(int64_t)r * ps.rld[blk] + j] : 0.0;
     }
@@ -85,7 +93,7 @@ __global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
     for (int q = 0; q < PER; ++q) {
       const int o = threadIdx.x + q * 256;
       if (o < nout) {
-        const int i = o / NR, j = o % NR;
+        const int i = sdiv(o, NR), j = o - i * NR;
         double s = acc[q];
 #pragma unroll
         for (int rr = 0; rr < kPartRows; ++rr) s += ls[rr][i] * rs[rr][j];
@@ -104,7 +112,7 @@ __global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
 
 int partial_slices(int dmax) {
   int s = (dmax + kPartRows - 1) / kPartRows;
-  return s < 16 ? (s < 1 ? 1 : s) : 16;
+  return s < kMaxSlices ? (s < 1 ? 1 : s) : kMaxSlices;
 }
 
 size_t partial_bytes(int k, int dmax) {
@@ -124,7 +132,7 @@ __device__ void sum_block(const double* part, int slices, int nl, int nr, int k,
   const int NR = nr * k;
   const int64_t zs = (int64_t)(nl * k) * NR;
   for (int e = tid; e < k * k; e += nthreads) {
-    const int i = e / k, j = e % k;
+    const int i = sdiv(e, k), j = e - i * k;
     double s = 0.0;
     for (int z = 0; z < slices; ++z) s += part[z * zs + (int64_t)(a * k + i) * NR + b * k + j];
     dst[e] = accumulate ? dst[e] + scale * s : scale * s;
@@ -188,30 +196,26 @@ int launch_final_partials(const ProbView& p, hipStream_t st) {
 
 // ------------------------------------------------- small dense helpers
 // Sum over the row-slice partials of up to four entries with weights:
-// sum_z sum_q w_q part[z * zs + i_q] (q < nq).  Two accumulators keep
-// several loads in flight; the order is fixed (deterministic).
+// sum_z sum_q w_q part[z * zs + i_q] (q < nq).  The partials were written
+// by workgroups on other XCDs, so each load is a trip beyond this XCD's L2:
+// all of them are issued before the first is used (unrolled to the slice
+// cap), and the sum runs in a fixed order (deterministic).
 __device__ __forceinline__ double slice_sum(const double* __restrict__ part, int slices, int64_t zs, int nq,
                                             int64_t i0, int64_t i1, int64_t i2, int64_t i3, double w0,
                                             double w1, double w2, double w3) {
-  double s0 = 0.0, s1 = 0.0;
-  int z = 0;
-  for (; z + 2 <= slices; z += 2) {
-    const double* p0 = part + (int64_t)z * zs;
-    const double* p1 = p0 + zs;
-    s0 += w0 * p0[i0];
-    s1 += w0 * p1[i0];
-    if (nq > 1) { s0 += w1 * p0[i1]; s1 += w1 * p1[i1]; }
-    if (nq > 2) { s0 += w2 * p0[i2]; s1 += w2 * p1[i2]; }
-    if (nq > 3) { s0 += w3 * p0[i3]; s1 += w3 * p1[i3]; }
+  // unused entries point at i0 with weight 0; unused slices at slice 0 with
+  // weight 0: every load is unconditional, so they all issue together
+  const int64_t j1 = nq > 1 ? i1 : i0, j2 = nq > 2 ? i2 : i0, j3 = nq > 3 ? i3 : i0;
+  const double u1 = nq > 1 ? w1 : 0.0, u2 = nq > 2 ? w2 : 0.0, u3 = nq > 3 ? w3 : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int z = 0; z < kMaxSlices; ++z) {
+    const bool on = z < slices;
+    const double* pz = part + (int64_t)(on ? z : 0) * zs;
+    const double t = (w0 * pz[i0] + u1 * pz[j1]) + (u2 * pz[j2] + u3 * pz[j3]);
+    s += on ? t : 0.0;
   }
-  if (z < slices) {
-    const double* p0 = part + (int64_t)z * zs;
-    s0 += w0 * p0[i0];
-    if (nq > 1) s0 += w1 * p0[i1];
-    if (nq > 2) s0 += w2 * p0[i2];
-    if (nq > 3) s0 += w3 * p0[i3];
-  }
-  return s0 + s1;
+  return s;
 }
 
 // Lower Cholesky in place (ld = k) by one wave; false if not SPD.
@@ -227,7 +231,7 @@ __device__ bool wave_chol(double* A, int k, int lane) {
     wave_sync();
     const int w = k - j - 1;
     for (int e = lane; e < w * w; e += 64) {
-      const int r = j + 1 + e / w, c = j + 1 + e % w;
+      const int q = sdiv(e, w), r = j + 1 + q, c = j + 1 + (e - q * w);
       if (c <= r) A[r * k + c] -= A[r * k + j] * A[c * k + j];
     }
   }
@@ -269,7 +273,7 @@ __device__ bool group_chol(double* A, int k, int gl, int gsize) {
     wave_sync();
     const int w = k - j - 1;
     for (int e = gl; e < w * w; e += gsize) {
-      const int r = j + 1 + e / w, c = j + 1 + e % w;
+      const int q = sdiv(e, w), r = j + 1 + q, c = j + 1 + (e - q * w);
       if (c <= r) A[r * k + c] -= A[r * k + j] * A[c * k + j];
     }
   }
@@ -287,10 +291,14 @@ __device__ void group_lower_inv(const double* L, double* X, int k, int gl) {
     for (int r = 0; r < k; ++r) {
       double v = 0.0;
       if (r >= c) {
-        double s = (r == c) ? 1.0 : 0.0;
+        double acc4[4] = {0.0, 0.0, 0.0, 0.0};   // four short chains instead of one long one
 #pragma unroll
-        for (int l = 0; l < KC; ++l)
-          if (l >= c && l < r) s -= L[r * k + l] * X[l * k + c];
+        for (int l = 0; l < KC; ++l) {
+          const int lc = l < k ? l : 0;
+          const double prod = L[r * k + lc] * X[lc * k + c];
+          acc4[l & 3] += (l >= c && l < r) ? prod : 0.0;
+        }
+        const double s = ((r == c) ? 1.0 : 0.0) - ((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
         v = s / L[r * k + r];
       }
       X[r * k + c] = v;
@@ -309,11 +317,14 @@ __device__ double trial_cost(const double* C, const double* Xx, const double* Xy
     const int i = lane;
     double fii = 0.0;
     for (int a = 0; a <= i; ++a) {
-      double row = 0.0;
+      double r4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int b = 0; b < KC; ++b)
-        if (b <= i) row += C[a * k + b] * Xy[i * k + b];
-      fii += Xx[i * k + a] * row;
+      for (int b = 0; b < KC; ++b) {
+        const int bc = b < k ? b : 0;
+        const double prod = C[a * k + bc] * Xy[i * k + bc];
+        r4[b & 3] += (b <= i) ? prod : 0.0;
+      }
+      fii += Xx[i * k + a] * ((r4[0] + r4[1]) + (r4[2] + r4[3]));
     }
     part = mu[i] * fii;
   }
@@ -366,8 +377,10 @@ __device__ double eval_trial(const ProbView& p, const double* coef, const double
 // on a geometric grid in parallel (one wave each), keeps the best and
 // narrows the grid around it.  The winning wave's factor inverses are
 // stored directly when the best step comes from the last round.
+constexpr int kLsThreads = 512;   // 8 trial steps per round
+
 template <int KC>
-__global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, int ntr) {
+__global__ void __launch_bounds__(kLsThreads) k_ctrl_ls(ProbView p, int ntr) {
   SolverCtrl* c = p.ctrl;
   if (c->done) return;
   extern __shared__ double sm[];
@@ -384,8 +397,8 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, int ntr) {
   double* coef = sm;                                 // (3 nb + 3) k x k
   const int ncoef = 3 * nb + 3;
   // coefficients (ls partial layout: left [U, xi], right [Ks, Js, U, xi, Kc, Jc])
-  for (int e = tid; e < ncoef * kk2; e += 1024) {
-    const int m = e / kk2, q = e - m * kk2, i = q / k, j = q - i * k;
+  for (int e = tid; e < ncoef * kk2; e += kLsThreads) {
+    const int m = sdiv(e, kk2), q = e - m * kk2, i = sdiv(q, k), j = q - i * k;
     const int64_t r0 = (int64_t)i * NR + j, r1 = (int64_t)(k + i) * NR + j;   // rows of U and xi
     double v;
     if (m < 3 * nb) {
@@ -409,12 +422,12 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, int ntr) {
     }
     coef[e] = v;
   }
-  for (int e = tid; e < k; e += 1024) mu[e] = p.mu[e];
+  for (int e = tid; e < k; e += kLsThreads) mu[e] = p.mu[e];
   __syncthreads();
   // symmetrise the Gram coefficients (and the FDA cost coefficients)
   const int nsym = 3 * nb + (p.lda_cost ? 3 : 0);
-  for (int e = tid; e < nsym * kk2; e += 1024) {
-    const int m = e / kk2, q = e - m * kk2, i = q / k, j = q - i * k;
+  for (int e = tid; e < nsym * kk2; e += kLsThreads) {
+    const int m = sdiv(e, kk2), q = e - m * kk2, i = sdiv(q, k), j = q - i * k;
     if (i < j) {
       double* M = coef + (size_t)m * kk2;
       const double v = 0.5 * (M[i * k + j] + M[j * k + i]);
@@ -445,7 +458,7 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, int ntr) {
       for (int i = 0; i < k; ++i) smu += mu[i];
       centre = (fabs(f0) > 0.0) ? smu / (2.0 * mu[0] * fabs(f0)) : 1.0;
     }
-    double H = 8.0;  // half span in octaves
+    double H = 3.0;  // half span in octaves (the grid moves when the best step is on its edge)
     double tb = centre, fb = INFINITY;
     int expand = 0;
     for (int round = 0; round < 16 && H > 0.25; ++round) {
@@ -511,7 +524,7 @@ __global__ void __launch_bounds__(1024) k_ctrl_ls(ProbView p, int ntr) {
       double* LT = kkslot(p, b, KK_LINVT);
       const double* X = Li + b * kk2;
       for (int e = lane; e < kk2; e += 64) {
-        const int i = e / k, j = e - i * k;
+        const int i = sdiv(e, k), j = e - i * k;
         LT[i * k + j] = X[j * k + i];
       }
     }
@@ -546,7 +559,7 @@ static int launch_ctrl_ls_t(const ProbView& p, hipStream_t st) {
   const size_t per_wave = (size_t)2 * nb * k * k * sizeof(double);
   const size_t budget = 156 * 1024;
   int ntr = (int)((budget - coef_bytes) / per_wave);
-  if (ntr > 16) ntr = 16;
+  if (ntr > kLsThreads / 64) ntr = kLsThreads / 64;
   if (ntr < 1) {
     set_error("line search: k = %d too large for the LDS budget", k);
     return SRP_EINVAL;
@@ -557,7 +570,7 @@ static int launch_ctrl_ls_t(const ProbView& p, hipStream_t st) {
     SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_ls<KC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = lds;
   }
-  hipLaunchKernelGGL(k_ctrl_ls<KC>, dim3(1), dim3(1024), lds, st, p, ntr);
+  hipLaunchKernelGGL(k_ctrl_ls<KC>, dim3(1), dim3(kLsThreads), lds, st, p, ntr);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -575,6 +588,7 @@ int launch_ctrl_ls(const ProbView& p, hipStream_t st) {
 // A workgroup stages 16 rows in LDS, then one thread per (row, column).
 constexpr int kUpdRows = 16;
 
+template <int KC>
 __global__ void __launch_bounds__(256) k_update(ProbView p, int refresh) {
   const SolverCtrl* c = p.ctrl;
   if (c->done && refresh != 2) return;   // 2 = forced refresh after the loop
@@ -596,7 +610,7 @@ __global__ void __launch_bounds__(256) k_update(ProbView p, int refresh) {
   }
   for (int e = tid; e < k; e += 256) mu[e] = p.mu[e];
   for (int e = tid; e < nr * k; e += 256) {
-    const int rr = e / k, j = e - rr * k;
+    const int rr = sdiv(e, k), j = e - rr * k;
     const int64_t i = r0 + rr;
     const double* Jrow = s.J + i * s.jld;
     const double js = Jrow[s.js_off + j];
@@ -613,18 +627,23 @@ __global__ void __launch_bounds__(256) k_update(ProbView p, int refresh) {
   }
   __syncthreads();
   for (int e = tid; e < nr * k; e += 256) {
-    const int rr = e / k, j = e - rr * k;
+    const int rr = sdiv(e, k), j = e - rr * k;
     const int64_t i = r0 + rr;
     double un, ksn, kcn;
     if (refresh) {
       un = u[rr][j]; ksn = ks[rr][j]; kcn = kc[rr][j];
     } else {
-      un = 0.0; ksn = 0.0; kcn = 0.0;
-      for (int l = 0; l < k; ++l) {
-        un += u[rr][l] * LT[l * k + j];
-        ksn += ks[rr][l] * LT[l * k + j];
-        kcn += kc[rr][l] * LTo[l * k + j];
+      double u2[2] = {0.0, 0.0}, k2[2] = {0.0, 0.0}, c2[2] = {0.0, 0.0};
+#pragma unroll
+      for (int l = 0; l < KC; ++l) {   // unconditional LDS loads, masked terms
+        const int lc = l < k ? l : 0;
+        const double lt = LT[lc * k + j], lto = LTo[lc * k + j];
+        const double a1 = u[rr][lc] * lt, a2 = ks[rr][lc] * lt, a3 = kc[rr][lc] * lto;
+        u2[l & 1] += (l < k) ? a1 : 0.0;
+        k2[l & 1] += (l < k) ? a2 : 0.0;
+        c2[l & 1] += (l < k) ? a3 : 0.0;
       }
+      un = u2[0] + u2[1]; ksn = k2[0] + k2[1]; kcn = c2[0] + c2[1];
       s.U[i * k + j] = un;
       s.Ks[i * k + j] = ksn;
     }
@@ -639,7 +658,8 @@ __global__ void __launch_bounds__(256) k_update(ProbView p, int refresh) {
 int launch_update(const ProbView& p, int refresh, hipStream_t st) {
   const int dmax = p.nb == 2 ? (p.s[0].d > p.s[1].d ? p.s[0].d : p.s[1].d) : p.s[0].d;
   dim3 grid((dmax + kUpdRows - 1) / kUpdRows, p.nb);
-  hipLaunchKernelGGL(k_update, grid, dim3(256), 0, st, p, refresh);
+  if (p.k <= 16) hipLaunchKernelGGL(k_update<16>, grid, dim3(256), 0, st, p, refresh);
+  else hipLaunchKernelGGL(k_update<32>, grid, dim3(256), 0, st, p, refresh);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -659,13 +679,13 @@ struct WaveJacobiScratch {
 
 __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, WaveJacobiScratch& w) {
   const int nn = n * n;
-  for (int e = lane; e < nn; e += 64) V[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  for (int e = lane; e < nn; e += 64) V[e] = (e == sdiv(e, n) * (n + 1)) ? 1.0 : 0.0;
   wave_sync();
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int e = lane; e < nn; e += 64) {
       const double v = A[e];
-      if ((e / n) == (e % n)) dia += v * v; else off += v * v;
+      if (e == sdiv(e, n) * (n + 1)) dia += v * v; else off += v * v;
     }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_xor(off, o, 64);
@@ -693,7 +713,7 @@ __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, Wa
       wave_sync();
       // A' = J^T A J, V' = V J with J[p][p]=c, J[p][q]=s, J[q][p]=-s, J[q][q]=c
       for (int e = lane; e < nn; e += 64) {
-        const int r = e / n, col = e - r * n;
+        const int r = sdiv(e, n), col = e - r * n;
         const int pr = w.partner[r], pc = w.partner[col];
         const double jrr = w.rc[r], jpr = w.isp[r] ? -w.rs[r] : w.rs[r];
         const double jcc = w.rc[col], jpc = w.isp[col] ? -w.rs[col] : w.rs[col];
@@ -718,12 +738,15 @@ template <int KC>
 __device__ __forceinline__ void wave_mm_t(const double* A, int lda, bool ta, const double* B, int ldb, bool tb,
                                           double* C, int ldc, int k, int lane) {
   for (int e = lane; e < k * k; e += 64) {
-    const int i = e / k, j = e - i * k;
-    double s = 0.0;
+    const int i = sdiv(e, k), j = e - i * k;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int l = 0; l < KC; ++l)
-      if (l < k) s += (ta ? A[l * lda + i] : A[i * lda + l]) * (tb ? B[j * ldb + l] : B[l * ldb + j]);
-    C[i * ldc + j] = s;
+    for (int l = 0; l < KC; ++l) {
+      const int lc = l < k ? l : 0;
+      const double prod = (ta ? A[lc * lda + i] : A[i * lda + lc]) * (tb ? B[j * ldb + lc] : B[lc * ldb + j]);
+      s4[l & 3] += (l < k) ? prod : 0.0;
+    }
+    C[i * ldc + j] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   }
   wave_sync();
 }
@@ -736,7 +759,7 @@ __device__ __forceinline__ void wave_mm_t(const double* A, int lda, bool ta, con
 // trace terms; thread 0 forms the Polak-Ribiere+ coefficient, the descent
 // test and the stopping test.
 template <int KC>
-__global__ void __launch_bounds__(256) k_ctrl_dir(ProbView p) {
+__global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
   SolverCtrl* c = p.ctrl;
   if (c->done) return;
   extern __shared__ double sm[];
@@ -752,13 +775,13 @@ __global__ void __launch_bounds__(256) k_ctrl_dir(ProbView p) {
   const int64_t zs = (int64_t)(2 * k) * NR;
   const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);   // as laid out by run_partials
   const int per_side = 9 * kk2 + 5 * nn;
-  for (int e = tid; e < nb * 4 * kk2; e += 256) {
-    const int sd = e / (4 * kk2), r = e - sd * 4 * kk2, blk = r / kk2, q = r - blk * kk2, i = q / k, j = q - i * k;
+  for (int e = tid; e < nb * 4 * kk2; e += 512) {
+    const int sd = sdiv(e, 4 * kk2), r = e - sd * 4 * kk2, blk = sdiv(r, kk2), q = r - blk * kk2, i = sdiv(q, k), j = q - i * k;
     sm[(size_t)sd * per_side + r] =
         slice_sum(p.part + sd * side_stride, slices, zs, 1, (int64_t)i * NR + blk * k + j, 0, 0, 0, 1.0, 0.0, 0.0, 0.0);
   }
-  for (int e = tid; e < nb * 3 * k; e += 256) {
-    const int sd = e / (3 * k), r = e - sd * 3 * k, which = r / k, i = r - which * k;
+  for (int e = tid; e < nb * 3 * k; e += 512) {
+    const int sd = sdiv(e, 3 * k), r = e - sd * 3 * k, which = sdiv(r, k), i = r - which * k;
     trv[sd][which][i] = slice_sum(p.part + sd * side_stride, slices, zs, 1, (int64_t)(k + i) * NR + (which + 1) * k + i,
                                   0, 0, 0, 1.0, 0.0, 0.0, 0.0);
   }
@@ -787,7 +810,7 @@ __global__ void __launch_bounds__(256) k_ctrl_dir(ProbView p) {
     for (int q = 0; q < 3; ++q)
       for (int o = 32; o > 0; o >>= 1) tr3[q] += __shfl_xor(tr3[q], o, 64);
     for (int e = lane; e < nn; e += 64) {
-      const int i = e / n, j = e - i * n;
+      const int i = sdiv(e, n), j = e - i * n;
       JA[e] = (i < k && j < k) ? 0.5 * (P[i * k + j] + P[j * k + i]) : ((i == j) ? 1.0 : 0.0);
     }
     double* Vst = kkslot(p, b, KK_EIG);
@@ -797,7 +820,7 @@ __global__ void __launch_bounds__(256) k_ctrl_dir(ProbView p) {
       wave_mm_t<KC>(JA, n, false, V0, n, false, JT, n, n, lane);   // JA V0
       wave_mm_t<KC>(V0, n, true, JT, n, false, JA, n, n, lane);   // V0^T (JA V0)
       for (int e = lane; e < nn; e += 64) {
-        const int i = e / n, j = e - i * n;
+        const int i = sdiv(e, n), j = e - i * n;
         JT[e] = 0.5 * (JA[i * n + j] + JA[j * n + i]);
       }
       wave_sync();
@@ -817,38 +840,54 @@ __global__ void __launch_bounds__(256) k_ctrl_dir(ProbView p) {
     for (int m = 0; m < 3; ++m) {
       const double* C = srcs[m];
       for (int e = lane; e < kk2; e += 64) {
-        const int i = e / k, j = e - i * k;
-        double s = 0.0;
+        const int i = sdiv(e, k), j = e - i * k;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int l = 0; l < KC; ++l)
-          if (l < k) s += (C[i * k + l] + C[l * k + i]) * JV[l * n + j];
+        for (int l = 0; l < KC; ++l) {
+          const int lc = l < k ? l : 0;
+          const double prod = (C[i * k + lc] + C[lc * k + i]) * JV[lc * n + j];
+          s4[l & 3] += (l < k) ? prod : 0.0;
+        }
+        const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         W1[e] = s;
       }
       wave_sync();
       for (int e = lane; e < kk2; e += 64) {
-        const int i = e / k, j = e - i * k;
-        double s = 0.0;
+        const int i = sdiv(e, k), j = e - i * k;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int l = 0; l < KC; ++l)
-          if (l < k) s += JV[l * n + i] * W1[l * k + j];
+        for (int l = 0; l < KC; ++l) {
+          const int lc = l < k ? l : 0;
+          const double prod = JV[lc * n + i] * W1[lc * k + j];
+          s4[l & 3] += (l < k) ? prod : 0.0;
+        }
+        const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         W2[e] = s / (JA[i * n + i] + JA[j * n + j]);
       }
       wave_sync();
       for (int e = lane; e < kk2; e += 64) {
-        const int i = e / k, j = e - i * k;
-        double s = 0.0;
+        const int i = sdiv(e, k), j = e - i * k;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int l = 0; l < KC; ++l)
-          if (l < k) s += JV[i * n + l] * W2[l * k + j];
+        for (int l = 0; l < KC; ++l) {
+          const int lc = l < k ? l : 0;
+          const double prod = JV[i * n + lc] * W2[lc * k + j];
+          s4[l & 3] += (l < k) ? prod : 0.0;
+        }
+        const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         W1[e] = s;
       }
       wave_sync();
       for (int e = lane; e < kk2; e += 64) {
-        const int i = e / k, j = e - i * k;
-        double s = 0.0;
+        const int i = sdiv(e, k), j = e - i * k;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int l = 0; l < KC; ++l)
-          if (l < k) s += W1[i * k + l] * JV[j * n + l];
+        for (int l = 0; l < KC; ++l) {
+          const int lc = l < k ? l : 0;
+          const double prod = W1[i * k + lc] * JV[j * n + lc];
+          s4[l & 3] += (l < k) ? prod : 0.0;
+        }
+        const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
         dsts[m][e] = s;
       }
       wave_sync();
@@ -932,7 +971,7 @@ static int launch_ctrl_dir_t(const ProbView& p, hipStream_t st) {
     SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_dir<KC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     attr_set = lds;
   }
-  hipLaunchKernelGGL(k_ctrl_dir<KC>, dim3(1), dim3(256), lds, st, p);
+  hipLaunchKernelGGL(k_ctrl_dir<KC>, dim3(1), dim3(512), lds, st, p);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -944,6 +983,7 @@ int launch_ctrl_dir(const ProbView& p, hipStream_t st) {
 
 // ------------------------------------------------------------ combine
 // xi+ = -W_E + beta xi + W_B Phi ;  gold = W_E - W_B S   (element-wise).
+template <int KC>
 __global__ void __launch_bounds__(256) k_combine(ProbView p) {
   const SolverCtrl* c = p.ctrl;
   if (c->done) return;
@@ -957,13 +997,16 @@ __global__ void __launch_bounds__(256) k_combine(ProbView p) {
   __syncthreads();
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   if (e >= (int64_t)s.d * k) return;
-  const int i = (int)(e / k), j = (int)(e % k);
+  const int i = sdiv((int)e, k), j = (int)e - i * k;
   const double* Wrow = s.Wz + (int64_t)i * 2 * k;   // [W_E | W_B]
   double wbphi = 0.0, wbs = 0.0;
-  for (int l = 0; l < k; ++l) {
-    const double wb = Wrow[k + l];
-    wbphi += wb * Phi[l * k + j];
-    wbs += wb * S[l * k + j];
+#pragma unroll
+  for (int l = 0; l < KC; ++l) {   // unconditional loads, masked terms
+    const int lc = l < k ? l : 0;
+    const double wb = Wrow[k + lc];
+    const double a1 = wb * Phi[lc * k + j], a2 = wb * S[lc * k + j];
+    wbphi += (l < k) ? a1 : 0.0;
+    wbs += (l < k) ? a2 : 0.0;
   }
   const double we = Wrow[j];
   const double beta = c->beta;
@@ -974,7 +1017,8 @@ __global__ void __launch_bounds__(256) k_combine(ProbView p) {
 int launch_combine(const ProbView& p, hipStream_t st) {
   const int dmax = p.nb == 2 ? (p.s[0].d > p.s[1].d ? p.s[0].d : p.s[1].d) : p.s[0].d;
   dim3 grid((unsigned)(((int64_t)dmax * p.k + 255) / 256), p.nb);
-  hipLaunchKernelGGL(k_combine, grid, dim3(256), 0, st, p);
+  if (p.k <= 16) hipLaunchKernelGGL(k_combine<16>, grid, dim3(256), 0, st, p);
+  else hipLaunchKernelGGL(k_combine<32>, grid, dim3(256), 0, st, p);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -1005,7 +1049,7 @@ __global__ void __launch_bounds__(64) k_ctrl_final(ProbView p, double* sigma_out
   wave_sync();
   for (int b = 0; b < nb; ++b) {
     for (int e = lane; e < kk2; e += 64) {
-      const int i = e / k, j = e - i * k;
+      const int i = sdiv(e, k), j = e - i * k;
       if (i < j) {
         const double v = 0.5 * (G[b][i * k + j] + G[b][j * k + i]);
         G[b][i * k + j] = v;
@@ -1025,14 +1069,14 @@ __global__ void __launch_bounds__(64) k_ctrl_final(ProbView p, double* sigma_out
   const double* Lx = Li[0];
   const double* Ly = Li[nb == 2 ? 1 : 0];
   for (int e = lane; e < kk2; e += 64) {
-    const int i = e / k, j = e - i * k;
+    const int i = sdiv(e, k), j = e - i * k;
     double s = 0.0;
     for (int l = 0; l <= i; ++l) s += Lx[i * k + l] * Cu[0][l * k + j];
     Tm[e] = s;
   }
   wave_sync();
   for (int e = lane; e < kk2; e += 64) {
-    const int i = e / k, j = e - i * k;
+    const int i = sdiv(e, k), j = e - i * k;
     double s = 0.0;
     for (int l = 0; l <= j; ++l) s += Tm[i * k + l] * Ly[j * k + l];
     Cw[e] = s;
@@ -1043,7 +1087,7 @@ __global__ void __launch_bounds__(64) k_ctrl_final(ProbView p, double* sigma_out
   double* JV = JA + m * m;
   double* JT = JV + m * m;
   for (int e = lane; e < m * m; e += 64) {
-    const int i = e / m, j = e - i * m;
+    const int i = sdiv(e, m), j = e - i * m;
     double v = 0.0;
     if (p.lda_cost) {
       if (i < k && j < k) v = 0.5 * (Cw[i * k + j] + Cw[j * k + i]);
@@ -1074,7 +1118,7 @@ __global__ void __launch_bounds__(64) k_ctrl_final(ProbView p, double* sigma_out
     const double* Lb = Li[b];
     const int off = (p.lda_cost || b == 0) ? 0 : k;
     for (int e = lane; e < kk2; e += 64) {
-      const int i = e / k, j = e - i * k;
+      const int i = sdiv(e, k), j = e - i * k;
       const int col = order[j];
       double s = 0.0;
       for (int l = i; l < k; ++l) s += Lb[l * k + i] * JV[(off + l) * m + col];
@@ -1121,7 +1165,7 @@ __global__ void __launch_bounds__(256) k_apply_rot(ProbView p) {
       double a = 0.0;
 #pragma unroll
       for (int l = 0; l < KC; ++l)
-        if (l < k) a += v[l] * R[l * k + j];
+        a += (l < k) ? v[l] * R[(l < k ? l : 0) * k + j] : 0.0;
       Ui[j] = a;
     }
 }

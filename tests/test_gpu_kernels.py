@@ -72,7 +72,9 @@ def test_srht_rows_bit_exact(n, s):
 
 
 @pytest.mark.parametrize("n,d,s,dt", [(3000, 40, 300, "f64"), (3001, 129, 257, "f32"),
-                                      (700, 16, 1024, "f32"), (5000, 33, 64, "bf16")])
+                                      (700, 16, 1024, "f32"), (5000, 33, 64, "bf16"),
+                                      (140000, 37, 512, "f32"), (600000, 3, 256, "f32"),
+                                      (70000, 70, 400, "f64")])
 def test_srht_matches_definition(n, d, s, dt):
     srp = _srp()
     seed = 77 + d
