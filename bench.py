@@ -34,6 +34,10 @@ def parse():
     ap.add_argument("--workload", default="cca-f32-srht", choices=sorted(synth.WORKLOADS))
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--max-iter", type=int, default=300)
+    ap.add_argument("--weights", choices=["equal", "descending"], default="equal",
+                    help="N = I (unweighted trace, ordered by the closing Rayleigh-Ritz step; it optimises the "
+                         "reported objective sum sigma_i) or N = diag(k, ..., 1)")
+    ap.add_argument("--warm", type=int, default=None, help="warm-start iterations on the sketched problem")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -94,14 +98,17 @@ def main():
         print(json.dumps({"copy_probe_bytes": src.numel() * esize, "launches": 3}), flush=True)
         return
     lam = wl.lam_value
-    tol = args.tol if args.tol is not None else (1e-9 if wl.dtype == "f64" else 1e-4)
+    tol = args.tol if args.tol is not None else (1e-9 if wl.dtype == "f64" else 1e-5)
+    mu = [1.0] * wl.k if args.weights == "equal" else None
+    warm = args.warm if args.warm is not None else 60
+    extra = {"warm_start_iters": warm}
     sketch = srp.SRP_SRHT if wl.sketch == "srht" else srp.SRP_COUNTSKETCH
 
     def one(time_passes=False):
-        opt = srp.srp_default_options(sketch=sketch, max_iter=args.max_iter, time_passes=int(time_passes))
+        opt = srp.srp_default_options(sketch=sketch, max_iter=args.max_iter, time_passes=int(time_passes), **extra)
         if wl.problem == "cca":
-            return srp.cca_solve(Ad, Bd, wl.k, lam, lam, wl.s, tol=tol, options=opt)
-        return srp.lda_solve(Ad, Bd, wl.c, wl.k, lam, wl.s, tol=tol, options=opt)
+            return srp.cca_solve(Ad, Bd, wl.k, lam, lam, wl.s, tol=tol, options=opt, mu=mu)
+        return srp.lda_solve(Ad, Bd, wl.c, wl.k, lam, wl.s, tol=tol, options=opt, mu=mu)
 
     for _ in range(args.warmup):
         one()
@@ -136,28 +143,34 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAMES[wl.dtype], "data": "synthetic",
            "config": {"workload": wl.name, "problem": wl.problem, "n": wl.n, "dx": wl.dx, "dy": wl.dy,
                       "k": wl.k, "lambda": lam, "sketch": wl.sketch, "s": wl.s, "tol": tol,
+                      "weights": args.weights,
+                      "warm_start_iters": warm,
                       "parallelism": "single-gpu"},
            "roofline": roofline,
            "solve": {key: infos[-1][key] for key in ("status", "iterations", "warm_iterations", "passes",
                                                      "ms_sketch", "ms_factor", "ms_warm", "ms_iterate",
                                                      "ms_total")}}
+    vals = None
     if not args.no_cpu_baseline:
         rec, vals = cpu_baseline(wl, A, B)
         out["cpu_baseline"] = rec
-        if not args.no_accuracy:
-            from oracle import metrics, direct
-            if wl.problem == "cca":
-                U, V = res[0].cpu().numpy(), res[1].cpu().numpy()
-                A64, B64 = A.astype(np.float64), B.astype(np.float64)
-                err = metrics.cca_rel_objective_error(U, V, A64, B64, lam, lam, vals)
-                cons = max(metrics.constraint_residual(U, A64, lam), metrics.constraint_residual(V, B64, lam))
-            else:
-                W = res[0].cpu().numpy()
-                _, _, _, Xh, Yh = direct.lda_scatter(A, B, wl.c)
-                err = metrics.lda_rel_objective_error(W, Xh, Yh, lam, vals)
-                cons = metrics.constraint_residual(W, Xh, lam)
-            out["accuracy"] = {"rel_objective_error": err, "constraint_residual": cons,
-                               "reference": "FP64 oracle (direct closed form)"}
+    if not args.no_accuracy:
+        from oracle import metrics, direct
+        if vals is None:
+            vals = (direct.cca_direct(A, B, lam, lam)[0] if wl.problem == "cca"
+                    else direct.lda_direct(A, B, wl.c, lam, k=wl.k)[0])
+        if wl.problem == "cca":
+            U, V = res[0].cpu().numpy(), res[1].cpu().numpy()
+            A64, B64 = A.astype(np.float64), B.astype(np.float64)
+            err = metrics.cca_rel_objective_error(U, V, A64, B64, lam, lam, vals)
+            cons = max(metrics.constraint_residual(U, A64, lam), metrics.constraint_residual(V, B64, lam))
+        else:
+            W = res[0].cpu().numpy()
+            _, _, _, Xh, Yh = direct.lda_scatter(A, B, wl.c)
+            err = metrics.lda_rel_objective_error(W, Xh, Yh, lam, vals)
+            cons = metrics.constraint_residual(W, Xh, lam)
+        out["accuracy"] = {"rel_objective_error": err, "constraint_residual": cons,
+                           "reference": "FP64 oracle (direct closed form)"}
     print(json.dumps(out), flush=True)
 
 

@@ -71,11 +71,18 @@ typedef struct srp_options {
                              iterations (default 4)                          */
   int pass_compute;       /* arithmetic of the data passes: SRP_F64 or
                              SRP_F32 (default: F64 for F64 data, F32 else)   */
-  int final_f64;          /* 1: the last data pass (the one the final FP64
-                             retraction and Rayleigh-Ritz step use) runs in
-                             FP64 arithmetic (default 0)                     */
-  const double* mu;       /* HOST pointer to k weights mu_1 > ... > mu_k > 0
-                             (N = diag(mu)); NULL = k, k-1, ..., 1           */
+  int final_f64;          /* > 0 with F32 / BF16 passes: after the iteration
+                             converges, run up to this many closing
+                             iterations whose data products use FP64
+                             arithmetic (two GEMM reads of the data where the
+                             fused pass has no FP64 instance); the finishing
+                             pass is FP64 too.  Needs F32 or F64 data.
+                             0 = none (default)                              */
+  const double* mu;       /* HOST pointer to k weights mu_1 >= ... >= mu_k > 0
+                             (N = diag(mu)); NULL = k, k-1, ..., 1.  Equal
+                             weights (N = I) optimise the unweighted trace;
+                             the closing Rayleigh-Ritz step still returns
+                             ordered vectors                                 */
   int time_passes;        /* 1: time every fused data pass over the full data
                              with HIP events on `stream` (srp_info.pass_ms)   */
 } srp_options;

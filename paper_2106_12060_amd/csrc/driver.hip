@@ -470,9 +470,28 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   B.time_passes = ca.opt.time_passes != 0;
   B.events = &events;
+  // final_f64 > 0 with lower-precision passes: close with that many
+  // iterations whose data products run in FP64 arithmetic, from the point
+  // the FP32 (or BF16) iteration reached; the finishing pass is FP64 too.
+  const bool refine = ca.opt.final_f64 > 0 && full.compute != SRP_F64;
   SRP_TRY(rcg_run(full, B, start, ca.opt.max_iter, ca.tol, std::max(1, ca.opt.check_every),
-                  ca.opt.refresh_every, true, ca.opt.final_f64 != 0, sigma_out, r, st));
+                  ca.opt.refresh_every, !refine, ca.opt.final_f64 != 0, sigma_out, r, st));
   for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
+  if (refine && r.status != SRP_ENOTSPD) {
+    RcgProblem f64 = full;
+    f64.compute = SRP_F64;
+    double* rstart[2] = {outW[0], nb == 2 ? outW[1] : nullptr};
+    RcgResult r2;
+    SRP_TRY(rcg_run(f64, B, rstart, ca.opt.final_f64, ca.tol, std::max(1, ca.opt.check_every),
+                    ca.opt.refresh_every, true, true, sigma_out, r2, st));
+    for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
+    r.iterations += r2.iterations;
+    r.passes += r2.passes;
+    r.f = r2.f;
+    r.gg = r2.gg;
+    // the closing phase has a fixed budget: reaching it is not a failure
+    if (r2.status == SRP_ENOTSPD) r.status = SRP_ENOTSPD;
+  }
   const double ms_iter = tm.lap_ms();
   double pass_ms = 0.0;
   for (auto& e : events) {
@@ -509,7 +528,10 @@ static int check_options(const srp_options& o) {
 static int setup_mu(const srp_options& o, int k, double* mu_dev, hipStream_t st) {
   double mu[KMAX];
   for (int i = 0; i < k; ++i) mu[i] = o.mu ? o.mu[i] : (double)(k - i);
-  for (int i = 0; i < k; ++i) SRP_REQUIRE(mu[i] > 0.0 && (i == 0 || mu[i] < mu[i - 1]), "mu must be positive and strictly decreasing");
+  // Equal weights (N = I) give the unweighted trace cost: the top-k subspace
+  // is its critical set and the closing Rayleigh-Ritz rotation orders it.
+  for (int i = 0; i < k; ++i)
+    SRP_REQUIRE(mu[i] > 0.0 && (i == 0 || mu[i] <= mu[i - 1]), "mu must be positive and non-increasing");
   SRP_HIP(hipMemcpyAsync(mu_dev, mu, sizeof(double) * k, hipMemcpyHostToDevice, st));
   SRP_HIP(hipStreamSynchronize(st));
   return SRP_OK;
@@ -532,9 +554,14 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   SRP_REQUIRE(lx >= 0.0 && ly >= 0.0, "lambda must be >= 0");
   SRP_REQUIRE(tol >= 0.0, "tol must be >= 0");
   int compute = opt.pass_compute == -1 ? (dtype == SRP_F64 ? SRP_F64 : SRP_F32) : opt.pass_compute;
-  SRP_REQUIRE(pass_limits_ok(dtype, compute, dx, dy, k, 2), "unsupported shape for the data pass (dx+dy=%d)", dx + dy);
+  // FP64 arithmetic falls back to two GEMM reads of the data where the fused pass has no instance
+  const bool f64_ok = opt.final_f64 == 0 || dtype != SRP_BF16;
+  SRP_REQUIRE(f64_ok, "FP64 closing iterations need F32 or F64 data");
+  SRP_REQUIRE(pass_limits_ok(dtype, compute, dx, dy, k, 2) || (compute == SRP_F64 && dtype != SRP_BF16),
+              "unsupported shape for the data pass (dx+dy=%d)", dx + dy);
   const int sk_dtype = dtype == SRP_F64 ? SRP_F64 : SRP_F32;
-  SRP_REQUIRE(pass_limits_ok(sk_dtype, compute, dx, dy, k, 2), "unsupported shape for the sketch pass");
+  SRP_REQUIRE(pass_limits_ok(sk_dtype, compute, dx, dy, k, 2) || compute == SRP_F64,
+              "unsupported shape for the sketch pass");
   if (opt.sketch == SRP_SRHT) {
     int64_t np = 2;
     while (np < n) np <<= 1;
@@ -646,7 +673,9 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   SRP_REQUIRE(s >= d, "sketch_size must be >= d");
   SRP_REQUIRE(lam >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
   int compute = opt.pass_compute == -1 ? (dtype == SRP_F64 ? SRP_F64 : SRP_F32) : opt.pass_compute;
-  SRP_REQUIRE(pass_limits_ok(dtype, compute, d, 0, k, 1), "unsupported shape for the data pass (d=%d)", d);
+  SRP_REQUIRE(opt.final_f64 == 0 || dtype != SRP_BF16, "FP64 closing iterations need F32 or F64 data");
+  SRP_REQUIRE(pass_limits_ok(dtype, compute, d, 0, k, 1) || (compute == SRP_F64 && dtype != SRP_BF16),
+              "unsupported shape for the data pass (d=%d)", d);
   const int sk_dtype = dtype == SRP_F64 ? SRP_F64 : SRP_F32;
   if (opt.sketch == SRP_SRHT) {
     int64_t np = 2;
