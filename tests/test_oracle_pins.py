@@ -442,3 +442,62 @@ def test_cca_solution_independent_of_column_order():
     s2, U2, V2 = direct.cca_direct(X[:, perm], Y, 0.1, 0.1, k=2)
     np.testing.assert_allclose(s1, s2, rtol=1e-12)
     np.testing.assert_allclose(U1[perm], U2, atol=1e-10)
+
+
+# ------------------------------------------------------------ staging
+def test_bf16_round_definition():
+    from oracle import quant
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -9, -2.5, 0.0], dtype=np.float32)
+    r = quant.bf16_round(x)
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: tie to even -> 1
+    # 1 + 3 2^-8 is halfway between 1 + 2^-7 and 1 + 2^-6: tie to even -> 1 + 2^-6
+    np.testing.assert_array_equal(r, np.array([1.0, 1.0, 1.0 + 2.0 ** -6, 1.0, -2.5, 0.0], dtype=np.float32))
+    # every BF16 value has 8 significant bits: the low 16 bits are zero
+    assert np.all(r.view(np.uint32) & 0xFFFF == 0)
+    rng = np.random.default_rng(0)
+    y = rng.standard_normal(10000).astype(np.float32)
+    ry = quant.bf16_round(y)
+    assert np.all(np.abs(ry - y) <= 2.0 ** -8 * np.abs(y))   # unit roundoff of an 8-bit significand
+
+
+def test_fp8_table_matches_format():
+    from oracle import quant
+    vals, codes = quant.fp8_e4m3_table()
+    assert len(vals) == 127 and vals[0] == 0.0 and vals[-1] == 448.0
+    assert vals[1] == 2.0 ** -9                       # smallest subnormal
+    assert 2.0 ** -6 in vals and 2.0 ** -6 - 2.0 ** -9 in vals   # smallest normal, largest subnormal
+    assert np.all(np.diff(vals) > 0)
+    np.testing.assert_array_equal(quant.fp8_e4m3_decode(codes), vals)
+
+
+def test_fp8_encode_rounding_and_saturation():
+    from oracle import quant
+    dec = lambda x: quant.fp8_e4m3_decode(quant.fp8_e4m3_encode(np.array(x, dtype=np.float64)))
+    np.testing.assert_array_equal(dec([448.0, 500.0, 1e9, -1e9]), [448.0, 448.0, 448.0, -448.0])
+    # ties: 1 + 1/16 between 1 (m=0) and 1.125 (m=1) -> 1; 1 + 3/16 between 1.125 and 1.25 (m=2) -> 1.25
+    np.testing.assert_array_equal(dec([1.0625, 1.1875, -1.0625]), [1.0, 1.25, -1.0])
+    # subnormal grid 2^-9 and its ties
+    np.testing.assert_array_equal(dec([2.0 ** -9, 1.5 * 2.0 ** -9, 2.5 * 2.0 ** -9, 0.4 * 2.0 ** -9]),
+                                  [2.0 ** -9, 2.0 * 2.0 ** -9, 2.0 * 2.0 ** -9, 0.0])
+    # 464 = halfway between 448 and the (missing) 480: saturates to 448
+    np.testing.assert_array_equal(dec([464.0]), [448.0])
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-400, 400, 20000)
+    q = dec(x)
+    # relative error at most half an ulp of a 4-bit significand in the normal range
+    nrm = np.abs(x) >= 2.0 ** -6
+    assert np.all(np.abs(q[nrm] - x[nrm]) <= 2.0 ** -4 * np.abs(x[nrm]))
+
+
+def test_fp8_column_scales_are_powers_of_two_and_exact():
+    from oracle import quant
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((300, 7)) * np.array([1e-3, 1.0, 10.0, 448.0, 449.0, 1e5, 0.0])
+    sc = quant.fp8_column_scales(X)
+    assert np.all(np.log2(sc) == np.round(np.log2(sc)))
+    assert np.all(np.max(np.abs(X), axis=0) / sc <= 448.0)
+    assert sc[-1] == 1.0
+    codes, sc2 = quant.fp8_stage(X)
+    back = quant.fp8_unstage(codes, sc2)
+    ok = np.abs(X) >= 2.0 ** -6 * sc2[None, :]
+    assert np.all(np.abs(back - X)[ok] <= 2.0 ** -4 * np.abs(X)[ok])
