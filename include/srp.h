@@ -24,7 +24,8 @@
  *    ABI.  srp_last_error() gives a thread-local message for the last
  *    failure in the calling thread.
  *  - dtype codes name the element type of a data matrix: SRP_F64 (double),
- *    SRP_F32 (float), SRP_BF16 (bfloat16, stored as uint16).
+ *    SRP_F32 (float), SRP_BF16 (bfloat16, stored as uint16) and, as a
+ *    sketch input only, SRP_FP8E4M3 (uint8 codes with per-column scales).
  */
 #ifndef SRP_H
 #define SRP_H
@@ -51,6 +52,7 @@ extern "C" {
 #define SRP_F64 0
 #define SRP_F32 1
 #define SRP_BF16 2
+#define SRP_FP8E4M3 3     /* sketch input only: OCP E4M3 codes (see srp_stage_fp8) */
 
 /* ---- sketch kinds ----------------------------------------------------- */
 #define SRP_COUNTSKETCH 0 /* Section 3                                       */
@@ -85,6 +87,21 @@ typedef struct srp_options {
                              ordered vectors                                 */
   int time_passes;        /* 1: time every fused data pass over the full data
                              with HIP events on `stream` (srp_info.pass_ms)   */
+  /* Low-precision form: BF16 copies of the data (srp_stage_bf16) read by
+     BF16 matrix-core passes with FP32 accumulation until lowp_tol (or
+     lowp_max_iter iterations); the iteration then continues on the main
+     data to tol (refinement).  NULL = off.  CCA only; needs k <= 16.        */
+  const void* lowp_x;     /* device, n x dx BF16 copy of X                    */
+  const void* lowp_y;     /* device, n x dy BF16 copy of Y                    */
+  double lowp_tol;        /* gradient tolerance of the BF16 phase (1e-3)      */
+  int lowp_max_iter;      /* iteration cap of the BF16 phase (200)            */
+  /* Staged sketch input: the sketch reads these copies instead of the data
+     (CCA X / Y; FDA: ignored).  NULL = sketch the data.                      */
+  const void* sketch_x;
+  const void* sketch_y;
+  int sketch_dtype;       /* SRP_F32, SRP_BF16 or SRP_FP8E4M3                  */
+  const double* sketch_scale_x;   /* FP8: device column scales (srp_stage_fp8) */
+  const double* sketch_scale_y;
 } srp_options;
 
 /* Per-solve report. */
@@ -103,6 +120,8 @@ typedef struct srp_info {
   double ms_total;
   double pass_ms;         /* summed duration of the timed fused passes       */
   int pass_launches;      /* number of timed fused passes                    */
+  int lowp_iterations;    /* iterations of the BF16 phase                    */
+  double ms_lowp;         /* wall ms of the BF16 phase (inside ms_iterate)   */
 } srp_info;
 
 /* Fill *opt with the defaults listed above.  Returns SRP_EINVAL if NULL. */
@@ -110,6 +129,10 @@ int srp_default_options(srp_options* opt);
 
 /* Thread-local text of the last error in this thread ("" if none). */
 const char* srp_last_error(void);
+
+/* sizeof(srp_options) and sizeof(srp_info) as compiled into the library,
+ * for bindings to check their layouts.  Host only. */
+int srp_abi_sizes(size_t* options_bytes, size_t* info_bytes);
 
 /* ---- sketches (Section 3; Appendix A) ---------------------------------
  * out = S A for an s x n sketch S drawn from `seed`, A n x d of `dtype`.
@@ -123,6 +146,9 @@ const char* srp_last_error(void);
  *   D_i = +1 if bit 0 of SplitMix64(seed ^ 0x5352485444494147, i) is 0,
  *   R the s rows of smallest key SplitMix64(seed ^ 0x535248545357524F, r),
  *   in ascending row order.  Requires s <= n' <= 2^20.
+ * SRP_FP8E4M3 input (codes from srp_stage_fp8): the sketch of the decoded,
+ *   unscaled values, FP32; multiplying column j by scales[j] (exact) gives
+ *   the sketch of the staged matrix.
  * Errors: SRP_EINVAL for n < 1, d < 1, s < 1, bad dtype or null pointers.
  */
 int srp_countsketch(const void* A, int dtype, int64_t n, int d, int s,
@@ -132,6 +158,20 @@ int srp_srht(const void* A, int dtype, int64_t n, int d, int s,
 /* The s sampled SRHT rows (int64, ascending) for n rows and `seed`. */
 int srp_srht_rows(int64_t n, int s, uint64_t seed, int64_t* rows,
                   void* stream);
+
+/* ---- reduced-precision staging of the data ----------------------------
+ * The low-precision forms of the sketch and of the data passes read staged
+ * copies of X (row-major n x d).
+ * srp_stage_bf16: out[i] = X[i] rounded to BF16 (nearest, ties to even),
+ *   stored as uint16.
+ * srp_stage_fp8: per column j the smallest power of two scales[j] (double,
+ *   device) with max_i |X_ij| <= 448 scales[j]; out[i][j] = OCP FP8 E4M3
+ *   code of X_ij / scales[j] (nearest, ties to even mantissa, saturating at
+ *   +-448; 4 exponent bits, bias 7, 3 mantissa bits).  X is F32 or BF16.
+ * Errors: SRP_EINVAL for null pointers, n < 1, d < 1 or a bad dtype.
+ */
+int srp_stage_bf16(const float* X, int64_t n, int d, uint16_t* out, void* stream);
+int srp_stage_fp8(const void* X, int dtype, int64_t n, int d, uint8_t* out, double* scales, void* stream);
 
 /* ---- preconditioner factor (Section 3; cost Table costs) --------------
  * From a sketch SA (s x d, dtype SRP_F64 or SRP_F32) compute in FP64 the
@@ -153,8 +193,12 @@ int srp_sketch_factor(const void* SA, int dtype, int s, int d, double lambda,
  * (with A1 == NULL: J0 = A0^T A0 W0, d0 x k).  These are the products
  * X^T (X U), X^T (Y V), ... that the Riemannian gradient, projection and
  * retraction of Eq. gradCCA / Table 1 consume.  One read of the data.
- * Limits: k <= 16 with two blocks, k <= 32 with one; d0 + d1 <= 2048
- * (F32 / BF16 data with F32 arithmetic) or <= 896 (F64 arithmetic).
+ * compute = SRP_BF16 (BF16 data only): the products run on BF16 matrix
+ *   cores with FP32 accumulation; W is rounded to BF16 and A_b W_b is
+ *   rounded to BF16 before the second product.
+ * Limits: k <= 16 with two blocks, k <= 32 with one (k <= 16 for BF16
+ * arithmetic); d0 + d1 <= 2048 (F32 / BF16 data) or <= 896 (F64
+ * arithmetic).
  * Errors: SRP_EINVAL outside these limits or for a bad dtype / compute
  * pair (F64 data needs F64 arithmetic).
  */

@@ -78,11 +78,18 @@ def fp8_e4m3_decode(code) -> np.ndarray:
 
 
 def fp8_column_scales(X) -> np.ndarray:
-    """Per-column power-of-two scales (float64)."""
+    """Per-column power-of-two scales (float64): the smallest 2^e with
+    max |x| <= 448 2^e, found by exact comparisons."""
     amax = np.max(np.abs(np.asarray(X, dtype=np.float64)), axis=0)
     out = np.ones_like(amax)
-    nz = amax > 0
-    out[nz] = np.exp2(np.ceil(np.log2(amax[nz] / FP8_MAX)))
+    for j, a in enumerate(amax):
+        if a > 0:
+            e = int(np.ceil(np.log2(a / FP8_MAX)))
+            while a > FP8_MAX * 2.0 ** e:
+                e += 1
+            while a <= FP8_MAX * 2.0 ** (e - 1):
+                e -= 1
+            out[j] = 2.0 ** e
     return out
 
 

@@ -18,13 +18,14 @@ LIB_PATH = os.path.join(_HERE, "libsrp.so")
 
 SRP_OK, SRP_EINVAL, SRP_ENOTSPD, SRP_ENOCONV, SRP_ENOMEM, SRP_EDEVICE = 0, 1, 2, 3, 4, 5
 SRP_EBUSY, SRP_EREJECTED, SRP_PENDING = 6, 7, 8
-SRP_F64, SRP_F32, SRP_BF16 = 0, 1, 2
+SRP_F64, SRP_F32, SRP_BF16, SRP_FP8E4M3 = 0, 1, 2, 3
 SRP_COUNTSKETCH, SRP_SRHT = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOCONV", 4: "ENOMEM",
                 5: "EDEVICE", 6: "EBUSY", 7: "EREJECTED", 8: "PENDING"}
 
-_DTYPES = {torch.float64: SRP_F64, torch.float32: SRP_F32, torch.bfloat16: SRP_BF16}
+# uint8 tensors hold FP8 E4M3 codes (sketch input only)
+_DTYPES = {torch.float64: SRP_F64, torch.float32: SRP_F32, torch.bfloat16: SRP_BF16, torch.uint8: SRP_FP8E4M3}
 
 
 class SrpOptions(ctypes.Structure):
@@ -32,7 +33,11 @@ class SrpOptions(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("warm_start_iters", ctypes.c_int),
                 ("refresh_every", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("pass_compute", ctypes.c_int), ("final_f64", ctypes.c_int),
-                ("mu", ctypes.POINTER(ctypes.c_double)), ("time_passes", ctypes.c_int)]
+                ("mu", ctypes.POINTER(ctypes.c_double)), ("time_passes", ctypes.c_int),
+                ("lowp_x", ctypes.c_void_p), ("lowp_y", ctypes.c_void_p), ("lowp_tol", ctypes.c_double),
+                ("lowp_max_iter", ctypes.c_int), ("sketch_x", ctypes.c_void_p), ("sketch_y", ctypes.c_void_p),
+                ("sketch_dtype", ctypes.c_int), ("sketch_scale_x", ctypes.c_void_p),
+                ("sketch_scale_y", ctypes.c_void_p)]
 
 
 class SrpInfo(ctypes.Structure):
@@ -42,7 +47,8 @@ class SrpInfo(ctypes.Structure):
                 ("grad_norm", ctypes.c_double), ("ms_sketch", ctypes.c_double),
                 ("ms_factor", ctypes.c_double), ("ms_warm", ctypes.c_double),
                 ("ms_iterate", ctypes.c_double), ("ms_total", ctypes.c_double),
-                ("pass_ms", ctypes.c_double), ("pass_launches", ctypes.c_int)]
+                ("pass_ms", ctypes.c_double), ("pass_launches", ctypes.c_int),
+                ("lowp_iterations", ctypes.c_int), ("ms_lowp", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -61,11 +67,14 @@ _P = ctypes.c_void_p
 _SIGS = {
     "srp_default_options": (ctypes.c_int, [ctypes.POINTER(SrpOptions)]),
     "srp_last_error": (ctypes.c_char_p, []),
+    "srp_abi_sizes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "srp_countsketch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_uint64, _P, _P]),
     "srp_srht": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_uint64, _P, _P]),
     "srp_srht_rows": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, _P, _P]),
+    "srp_stage_bf16": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int, _P, _P]),
+    "srp_stage_fp8": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _P, _P, _P]),
     "srp_sketch_factor": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                          _P, _P, _P]),
     "srp_gram_pass": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
@@ -165,6 +174,26 @@ def srp_srht_rows(n: int, s: int, seed: int, device="cuda") -> torch.Tensor:
     return rows
 
 
+def srp_stage_bf16(X: torch.Tensor) -> torch.Tensor:
+    """BF16 copy of an FP32 matrix (nearest, ties to even)."""
+    _need_cuda(X)
+    if X.dtype != torch.float32:
+        raise TypeError("srp_stage_bf16 takes float32 data")
+    out = torch.empty(X.shape, dtype=torch.bfloat16, device=X.device)
+    _check("srp_stage_bf16", lib().srp_stage_bf16(_ptr(X), X.shape[0], X.shape[1], _ptr(out), _stream()))
+    return out
+
+
+def srp_stage_fp8(X: torch.Tensor):
+    """(E4M3 codes as uint8, per-column power-of-two scales as float64)."""
+    _need_cuda(X)
+    out = torch.empty(X.shape, dtype=torch.uint8, device=X.device)
+    scales = torch.empty(X.shape[1], dtype=torch.float64, device=X.device)
+    _check("srp_stage_fp8", lib().srp_stage_fp8(_ptr(X), _dtype(X), X.shape[0], X.shape[1], _ptr(out),
+                                                _ptr(scales), _stream()))
+    return out, scales
+
+
 def srp_sketch_factor(SA: torch.Tensor, lam: float, want_inverse: bool = True):
     _need_cuda(SA)
     s, d = SA.shape
@@ -183,21 +212,43 @@ def srp_gram_pass(A0, W0, A1=None, W1=None, compute: str = "f32"):
     nb = 2 if A1 is not None else 1
     J0 = torch.empty((d0, nb * k), dtype=torch.float64, device=A0.device)
     J1 = torch.empty((d1, nb * k), dtype=torch.float64, device=A0.device) if A1 is not None else None
-    comp = {"f64": SRP_F64, "f32": SRP_F32}[compute]
+    comp = {"f64": SRP_F64, "f32": SRP_F32, "bf16": SRP_BF16}[compute]
     _check("srp_gram_pass", lib().srp_gram_pass(_ptr(A0), _ptr(A1), _dtype(A0), comp, n, d0, d1, k,
                                                 _ptr(W0), _ptr(W1), _ptr(J0), _ptr(J1), _stream()))
     return J0, J1
 
 
+def _attach_staged(opt, lowp, sketch_input):
+    """Point the options at staged copies (kept alive by the caller)."""
+    if lowp is not None:
+        lx, ly = lowp
+        _need_cuda(lx, ly)
+        if lx.dtype != torch.bfloat16 or (ly is not None and ly.dtype != torch.bfloat16):
+            raise TypeError("low-precision copies must be bfloat16 (srp_stage_bf16)")
+        opt.lowp_x, opt.lowp_y = lx.data_ptr(), (ly.data_ptr() if ly is not None else None)
+    if sketch_input is not None:
+        sx, sy, scx, scy = sketch_input
+        _need_cuda(sx, sy, scx, scy)
+        opt.sketch_x, opt.sketch_y = sx.data_ptr(), (sy.data_ptr() if sy is not None else None)
+        opt.sketch_dtype = _dtype(sx)
+        opt.sketch_scale_x = scx.data_ptr() if scx is not None else None
+        opt.sketch_scale_y = scy.data_ptr() if scy is not None else None
+
+
 def cca_solve(X, Y, k, lambda_x, lambda_y, sketch_size, tol=1e-6, options: SrpOptions | None = None,
-              mu=None, raise_on_noconv: bool = False):
-    """Returns (U, V, sigma, info_dict)."""
+              mu=None, raise_on_noconv: bool = False, lowp=None, sketch_input=None):
+    """Returns (U, V, sigma, info_dict).
+
+    lowp = (Xb, Yb): BF16 copies for the low-precision phase (then refined on
+    X, Y); sketch_input = (Sx, Sy, scale_x, scale_y): staged copies the sketch
+    reads (FP8 codes with their column scales, or BF16 / F32 with None)."""
     _need_cuda(X, Y)
     if X.dtype != Y.dtype:
         raise TypeError("X and Y must share a dtype")
     n, dx = X.shape
     dy = Y.shape[1]
     opt = options if options is not None else srp_default_options()
+    _attach_staged(opt, lowp, sketch_input)
     mu_buf = None
     if mu is not None:
         mu_buf = (ctypes.c_double * k)(*[float(m) for m in mu])

@@ -53,16 +53,26 @@ int srp_default_options(srp_options* o) {
   o->pass_compute = -1;
   o->final_f64 = 0;
   o->mu = nullptr;
+  o->lowp_tol = 1e-3;
+  o->lowp_max_iter = 200;
+  o->sketch_dtype = SRP_F32;
   return SRP_OK;
 }
 
 const char* srp_last_error(void) { return srp::last_error(); }
 
+int srp_abi_sizes(size_t* options_bytes, size_t* info_bytes) {
+  if (options_bytes) *options_bytes = sizeof(srp_options);
+  if (info_bytes) *info_bytes = sizeof(srp_info);
+  return SRP_OK;
+}
+
 int srp_countsketch(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, void* stream) {
   clear_error();
   SRP_REQUIRE(A && out, "null pointer argument");
   SRP_REQUIRE(n >= 1 && n < (int64_t(1) << 31) && d >= 1 && s >= 1, "bad sizes");
-  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16, "bad dtype %d", dtype);
+  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16 || dtype == SRP_FP8E4M3, "bad dtype %d",
+              dtype);
   hipStream_t st = (hipStream_t)stream;
   Scratch ws(st);
   const size_t bytes = countsketch_ws_bytes(n, s) + 1024;
@@ -76,7 +86,8 @@ int srp_srht(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, v
   clear_error();
   SRP_REQUIRE(A && out, "null pointer argument");
   SRP_REQUIRE(n >= 1 && d >= 1 && s >= 1, "bad sizes");
-  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16, "bad dtype %d", dtype);
+  SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16 || dtype == SRP_FP8E4M3, "bad dtype %d",
+              dtype);
   int64_t np = 2;
   while (np < n) np <<= 1;
   SRP_REQUIRE(np <= (int64_t(1) << 20) && s <= np, "SRHT needs s <= n' <= 2^20");
@@ -86,6 +97,29 @@ int srp_srht(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, v
   SRP_TRY(device_alloc(&ws.p, bytes, st));
   Arena ar{(char*)ws.p, bytes, 0};
   SRP_TRY(srht_run(A, dtype, n, d, s, seed, out, ar, st));
+  return finish(st);
+}
+
+int srp_stage_bf16(const float* X, int64_t n, int d, uint16_t* out, void* stream) {
+  clear_error();
+  SRP_REQUIRE(X && out, "null pointer argument");
+  SRP_REQUIRE(n >= 1 && d >= 1, "bad sizes");
+  hipStream_t st = (hipStream_t)stream;
+  SRP_TRY(stage_bf16_run(X, n, d, out, st));
+  return finish(st);
+}
+
+int srp_stage_fp8(const void* X, int dtype, int64_t n, int d, uint8_t* out, double* scales, void* stream) {
+  clear_error();
+  SRP_REQUIRE(X && out && scales, "null pointer argument");
+  SRP_REQUIRE(n >= 1 && d >= 1, "bad sizes");
+  SRP_REQUIRE(dtype == SRP_F32 || dtype == SRP_BF16, "stage_fp8: data must be F32 or BF16");
+  hipStream_t st = (hipStream_t)stream;
+  Scratch ws(st);
+  const size_t bytes = stage_fp8_ws_bytes(d) + 1024;
+  SRP_TRY(device_alloc(&ws.p, bytes, st));
+  Arena ar{(char*)ws.p, bytes, 0};
+  SRP_TRY(stage_fp8_run(X, dtype, n, d, out, scales, ar, st));
   return finish(st);
 }
 
@@ -137,7 +171,8 @@ int srp_gram_pass(const void* A0, const void* A1, int dtype, int compute, int64_
   SRP_REQUIRE(A0 && W0 && J0, "null pointer argument");
   SRP_REQUIRE(!A1 || (W1 && J1 && d1 >= 1), "second block needs W1, J1 and d1 >= 1");
   SRP_REQUIRE(n >= 1 && d0 >= 1 && k >= 1, "bad sizes");
-  SRP_REQUIRE(compute == SRP_F64 || compute == SRP_F32, "compute must be SRP_F64 or SRP_F32");
+  SRP_REQUIRE(compute == SRP_F64 || compute == SRP_F32 || compute == SRP_BF16,
+              "compute must be SRP_F64, SRP_F32 or SRP_BF16");
   if (!A1) d1 = 0;
   SRP_REQUIRE(pass_limits_ok(dtype, compute, d0, d1, k, A1 ? 2 : 1), "unsupported shape for the data pass");
   hipStream_t st = (hipStream_t)stream;

@@ -70,8 +70,22 @@ template <> __device__ __forceinline__ float load_as<float, float>(const float* 
 template <> __device__ __forceinline__ float load_as<float, bf16>(const bf16* p) { return to_f32(*p); }
 template <> __device__ __forceinline__ float load_as<float, double>(const double* p) { return (float)*p; }
 
+// FP8 E4M3 code (OCP: bias 7, 3 mantissa bits, no infinities).
+struct fp8e4m3 {
+  uint8_t v;
+};
+__device__ __forceinline__ float fp8_to_f32(fp8e4m3 c) {
+  const int e = (c.v >> 3) & 15, m = c.v & 7;
+  const float mag = e ? ldexpf(1.0f + 0.125f * (float)m, e - 7) : 0.001953125f * (float)m;
+  return (c.v & 0x80) ? -mag : mag;
+}
+template <> __device__ __forceinline__ float load_as<float, fp8e4m3>(const fp8e4m3* p) { return fp8_to_f32(*p); }
+template <> __device__ __forceinline__ double load_as<double, fp8e4m3>(const fp8e4m3* p) {
+  return (double)fp8_to_f32(*p);
+}
+
 inline size_t dtype_size(int dtype) {
-  return dtype == SRP_F64 ? 8 : dtype == SRP_F32 ? 4 : 2;
+  return dtype == SRP_F64 ? 8 : dtype == SRP_F32 ? 4 : dtype == SRP_BF16 ? 2 : 1;
 }
 
 // ------------------------------------------------- counter-based hashing

@@ -466,6 +466,28 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
     start[1] = nb == 2 ? outW[1] : nullptr;
   }
   const double ms_warm = tm.lap_ms();
+  // low-precision phase (CCA): BF16 data, BF16 matrix-core passes
+  int lowp_iters = 0;
+  double ms_lowp = 0.0;
+  if (ca.opt.lowp_x && full.nb == 2) {
+    RcgProblem lp = full;
+    lp.A[0] = ca.opt.lowp_x;
+    lp.A[1] = ca.opt.lowp_y;
+    lp.dtype = SRP_BF16;
+    lp.compute = SRP_BF16;
+    RcgResult rl;
+    SRP_TRY(rcg_run(lp, B, start, std::max(1, ca.opt.lowp_max_iter), ca.opt.lowp_tol,
+                    std::max(1, ca.opt.check_every), ca.opt.refresh_every, false, false, nullptr, rl, st));
+    if (rl.status == SRP_ENOTSPD) {
+      set_error("Cholesky breakdown in the BF16 phase");
+      return SRP_ENOTSPD;
+    }
+    for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
+    start[0] = outW[0];
+    start[1] = outW[1];
+    lowp_iters = rl.iterations;
+    ms_lowp = tm.lap_ms();
+  }
   RcgResult r;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   B.time_passes = ca.opt.time_passes != 0;
@@ -492,7 +514,7 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
     // the closing phase has a fixed budget: reaching it is not a failure
     if (r2.status == SRP_ENOTSPD) r.status = SRP_ENOTSPD;
   }
-  const double ms_iter = tm.lap_ms();
+  const double ms_iter = tm.lap_ms() + ms_lowp;
   double pass_ms = 0.0;
   for (auto& e : events) {
     float ms = 0.f;
@@ -513,6 +535,8 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
     info->grad_norm = r.gg > 0 ? std::sqrt(r.gg) : 0.0;
     info->ms_warm = ms_warm;
     info->ms_iterate = ms_iter;
+    info->lowp_iterations = lowp_iters;
+    info->ms_lowp = ms_lowp;
   }
   return r.status;
 }
@@ -559,9 +583,24 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   SRP_REQUIRE(f64_ok, "FP64 closing iterations need F32 or F64 data");
   SRP_REQUIRE(pass_limits_ok(dtype, compute, dx, dy, k, 2) || (compute == SRP_F64 && dtype != SRP_BF16),
               "unsupported shape for the data pass (dx+dy=%d)", dx + dy);
-  const int sk_dtype = dtype == SRP_F64 ? SRP_F64 : SRP_F32;
+  const bool staged = opt.sketch_x != nullptr;
+  if (staged) {
+    SRP_REQUIRE(opt.sketch_y, "sketch_x and sketch_y go together");
+    SRP_REQUIRE(opt.sketch_dtype == SRP_F32 || opt.sketch_dtype == SRP_BF16 || opt.sketch_dtype == SRP_FP8E4M3,
+                "bad sketch_dtype %d", opt.sketch_dtype);
+    SRP_REQUIRE(opt.sketch_dtype != SRP_FP8E4M3 || (opt.sketch_scale_x && opt.sketch_scale_y),
+                "FP8 sketch input needs its column scales");
+  }
+  const void* skin_x = staged ? opt.sketch_x : X;
+  const void* skin_y = staged ? opt.sketch_y : Y;
+  const int skin_dtype = staged ? opt.sketch_dtype : dtype;
+  const int sk_dtype = skin_dtype == SRP_F64 ? SRP_F64 : SRP_F32;
   SRP_REQUIRE(pass_limits_ok(sk_dtype, compute, dx, dy, k, 2) || compute == SRP_F64,
               "unsupported shape for the sketch pass");
+  if (opt.lowp_x) {
+    SRP_REQUIRE(opt.lowp_y, "lowp_x and lowp_y go together");
+    SRP_REQUIRE(pass_limits_ok(SRP_BF16, SRP_BF16, dx, dy, k, 2), "unsupported shape for the BF16 pass");
+  }
   if (opt.sketch == SRP_SRHT) {
     int64_t np = 2;
     while (np < n) np <<= 1;
@@ -607,12 +646,14 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   if (ar.used + 2 * scr > ar.cap) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
   SideFork fk;
   SRP_TRY(fk.begin(st));
-  SRP_TRY(sketch_any(opt.sketch, Y, dtype, n, dy, s, opt.seed, SY, sy, fk.side));
+  SRP_TRY(sketch_any(opt.sketch, skin_y, skin_dtype, n, dy, s, opt.seed, SY, sy, fk.side));
+  if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SY, s, dy, opt.sketch_scale_y, fk.side));
   {
     Arena sub{sy.base, sy.cap, 0};
     SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side));
   }
-  SRP_TRY(sketch_any(opt.sketch, X, dtype, n, dx, s, opt.seed, SX, sx, st));
+  SRP_TRY(sketch_any(opt.sketch, skin_x, skin_dtype, n, dx, s, opt.seed, SX, sx, st));
+  if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SX, s, dx, opt.sketch_scale_x, st));
   const double ms_sketch = tm.lap_ms();   // X view's sketch (Y's runs alongside)
   {
     Arena sub{sx.base, sx.cap, 0};

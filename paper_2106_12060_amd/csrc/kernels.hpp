@@ -74,4 +74,12 @@ int lda_center_run(const void* X, const int32_t* labels, int dtype, int64_t n, i
                    double* Yhat, int* counts, int* bad, Arena& ws, hipStream_t st);
 int pass_limits_ok(int dtype, int compute, int d0, int d1, int k, int nblocks);
 
+// --------------------------------------------------------- staging
+int stage_bf16_run(const float* X, int64_t n, int d, uint16_t* out, hipStream_t st);
+size_t stage_fp8_ws_bytes(int d);
+int stage_fp8_run(const void* X, int dtype, int64_t n, int d, uint8_t* out, double* scales, Arena& ws,
+                  hipStream_t st);
+// A (rows x d, FP32) column j times scales[j] (powers of two: exact).
+int scale_cols_run(float* A, int64_t rows, int d, const double* scales, hipStream_t st);
+
 }  // namespace srp

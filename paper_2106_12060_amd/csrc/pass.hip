@@ -581,7 +581,303 @@ __global__ void __launch_bounds__(256) k_pass_reduce(const CT* __restrict__ part
   }
 }
 
+// ------------------------------------------------------------------
+// BF16 data with BF16 matrix-core products (FP32 accumulation): the
+// low-precision form of the pass.  Same streaming scheme as the FP32 DMA
+// pass (double-buffered global-to-LDS row blocks, direction operands in
+// registers, one workgroup owns whole rows), with 16-row blocks:
+//   (b) P_b = A_b W_b on 16x16x32 BF16 MFMA over 32-column tiles (A_1's
+//       tiles start on a 32-column boundary, so no tile mixes the blocks;
+//       the pad columns are zero in LDS and in the packed direction);
+//   (c) the wave partials of P are summed in FP32 and rounded to BF16,
+//       stored pcol-major so a lane's four rows are one 8-byte read;
+//   (d) A_b^T [P_0 | P_1] on 16x16x16 BF16 MFMA, the 16 rows of the block
+//       as the contraction.
+constexpr int kBfRows = 16;
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short s16x4_t __attribute__((ext_vector_type(4)));
+
+struct BfGeom {
+  int T0, T1, T0p, T1p, TTp, pitch;   // pitch in bf16 elements
+};
+__host__ __device__ inline BfGeom bf_geom(int d0, int d1) {
+  BfGeom g;
+  g.T0 = (d0 + 15) / 16;
+  g.T1 = (d1 + 15) / 16;
+  g.T0p = (g.T0 + 1) & ~1;
+  g.T1p = (g.T1 + 1) & ~1;
+  g.TTp = g.T0p + g.T1p;
+  g.pitch = g.TTp * 16 + 8;
+  return g;
+}
+
+template <int VEC>
+__device__ __forceinline__ void dma_row_chunk_bf(__amdgpu_buffer_rsrc_t r, unsigned short* lds_dst, int voff) {
+  if constexpr (VEC == 8)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_dst, 16, voff, 0, 0, 0);
+  else
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds_dst, 4, voff, 0, 0, 0);
+}
+
+// Pack double d x k directions into zero-padded (ceil32(d) x 16) BF16.
+__global__ void k_pack_dir_bf(const double* __restrict__ W0, int d0, int dp0, unsigned short* __restrict__ Wp0,
+                              const double* __restrict__ W1, int d1, int dp1, unsigned short* __restrict__ Wp1,
+                              int k) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n0 = dp0 * 16;
+  const double* W = W0;
+  unsigned short* Wp = Wp0;
+  int d = d0;
+  if (i >= n0) {
+    i -= n0;
+    if (i >= dp1 * 16) return;
+    W = W1; Wp = Wp1; d = d1;
+  }
+  const int r = i >> 4, c = i & 15;
+  const float v = (r < d && c < k) ? (float)W[(int64_t)r * k + c] : 0.0f;
+  const uint32_t u = __float_as_uint(v);
+  Wp[i] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <int NB, int VEC>
+__global__ void __launch_bounds__(kDmaThreads) k_pass_bf(const unsigned short* __restrict__ A0,
+                                                         const unsigned short* __restrict__ A1, int64_t n, int d0,
+                                                         int d1, int k, const unsigned short* __restrict__ Wp0,
+                                                         const unsigned short* __restrict__ Wp1, int nrb,
+                                                         float* __restrict__ partial, const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr int R = kBfRows;
+  constexpr int CH = 64 * VEC;          // bf16 elements per load instruction
+  constexpr int NT = NB;                // k <= 16: one k-tile per block
+  constexpr int TPB32 = (kDmaMaxTiles / 2 + kDmaWaves - 1) / kDmaWaves;   // 32-column P tiles per wave
+  constexpr int TPB = (kDmaMaxTiles + kDmaWaves - 1) / kDmaWaves;         // 16-column J tiles per wave
+  extern __shared__ unsigned short bsm[];
+  const BfGeom G = bf_geom(d0, NB == 2 ? d1 : 0);
+  const int pitch = G.pitch;
+  unsigned short* xsb0 = bsm;
+  float* red = reinterpret_cast<float*>(bsm + 2 * R * pitch);          // [waves][NT][256]
+  unsigned short* pb = reinterpret_cast<unsigned short*>(red + kDmaWaves * NT * 256);   // [NT][16 pcol][16 row]
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int nch0 = (G.T0 * 16 + CH - 1) / CH, nch1 = NB == 2 ? (G.T1 * 16 + CH - 1) / CH : 0;
+  const int nch = nch0 + nch1;
+
+  // zero the pad columns of both buffers once (no load ever writes them)
+  for (int e = tid; e < 2 * R * (G.TTp * 16); e += kDmaThreads) {
+    const int rr = e / (G.TTp * 16), c = e - rr * (G.TTp * 16);
+    const bool pad = (c >= G.T0 * 16 && c < G.T0p * 16) || (c >= G.T0p * 16 + G.T1 * 16);
+    if (pad) xsb0[rr * pitch + c] = 0;
+  }
+  // direction operands: 32-column tile T = w + 8 i, lane (l16, g) holds
+  // W[32 T + 8 g + e][l16] for e < 8 (A_1's rows start at T0p / 2)
+  bf16x8_t wreg[TPB32];
+#pragma unroll
+  for (int i = 0; i < TPB32; ++i) {
+    const int T = w + kDmaWaves * i;
+    const bool b1 = (NB == 2) && (2 * T >= G.T0p);
+    const int rowb = b1 ? 32 * T - 16 * G.T0p : 32 * T;
+    const unsigned short* Wp = b1 ? Wp1 : Wp0;
+    const int lim = b1 ? G.T1p * 16 : G.T0p * 16;
+    bf16x8_t v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = rowb + 8 * g + e;
+      const unsigned short bits = (2 * T < G.TTp && r < lim) ? Wp[r * 16 + l16] : (unsigned short)0;
+      v[e] = __builtin_bit_cast(__bf16, bits);
+    }
+    wreg[i] = v;
+  }
+  f32x4 acc[TPB][NT];
+#pragma unroll
+  for (int i = 0; i < TPB; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+  auto issue_block = [&](int rbk, unsigned short* xb) __attribute__((always_inline)) {
+    const int nq = R * nch;
+    for (int q = w; q < nq; q += kDmaWaves) {
+      const int r = q / nch, j = q - r * nch;
+      const int64_t row = (int64_t)rbk * R + r;
+      const bool s1 = (NB == 2) && (j >= nch0);
+      const int jj = s1 ? j - nch0 : j;
+      const int span = (s1 ? G.T1 : G.T0) * 16;
+      const int o = min(jj * CH, span - CH);
+      unsigned short* dst = xb + r * pitch + (s1 ? G.T0p * 16 : 0) + o;
+      const int voff = (o + lane * VEC) * 2;
+      if (s1) dma_row_chunk_bf<VEC>(make_rsrc(A1 + row * d1, row < n ? (int64_t)d1 * 2 : 0), dst, voff);
+      else dma_row_chunk_bf<VEC>(make_rsrc(A0 + row * d0, row < n ? (int64_t)d0 * 2 : 0), dst, voff);
+    }
+  };
+
+  const int base_b = l16 * pitch + 8 * g + 32 * w;    // P phase: row l16, columns 32 T + 8 g .. + 7
+  const int base_d = (4 * g) * pitch + l16 + 16 * w;  // J phase: rows 4 g .. 4 g + 3, column 16 t + l16
+  int rb = blockIdx.x;
+  int boff = 0;
+  if (rb < nrb) issue_block(rb, bsm);
+  for (; rb < nrb; rb += gridDim.x) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const unsigned short* xs = bsm + boff;
+    if (rb + (int)gridDim.x < nrb) issue_block(rb + gridDim.x, bsm + (R * pitch - boff));
+    // (b)
+    f32x4 pacc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) pacc[b] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < TPB32; ++i) {
+      const int T = w + kDmaWaves * i;
+      if (2 * T < G.TTp) {
+        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(xs + base_b + 32 * kDmaWaves * i);
+        if (NB == 2 && 2 * T >= G.T0p) pacc[NB - 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[i], pacc[NB - 1], 0, 0, 0);
+        else pacc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[i], pacc[0], 0, 0, 0);
+      }
+    }
+    // (c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(w * NT + b) * 256 + (4 * g + r) * 16 + l16] = pacc[b][r];
+    lds_only_barrier();
+    for (int e = tid; e < NT * 256; e += kDmaThreads) {
+      const int nt = e >> 8, q = e & 255;   // q = row * 16 + pcol
+      float v = 0.f;
+#pragma unroll
+      for (int ww = 0; ww < kDmaWaves; ++ww) v += red[(ww * NT + nt) * 256 + q];
+      const uint32_t u = __float_as_uint(v);
+      pb[nt * 256 + (q & 15) * 16 + (q >> 4)] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    }
+    lds_only_barrier();
+    // (d)
+    s16x4_t bop[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) bop[nt] = *reinterpret_cast<const s16x4_t*>(pb + nt * 256 + l16 * 16 + 4 * g);
+#pragma unroll
+    for (int i = 0; i < TPB; ++i) {
+      const int t = w + kDmaWaves * i;
+      if (t < G.TTp) {
+        const unsigned short* xp = xs + base_d + 16 * kDmaWaves * i;
+        s16x4_t a;
+        a[0] = (short)xp[0];
+        a[1] = (short)xp[pitch];
+        a[2] = (short)xp[2 * pitch];
+        a[3] = (short)xp[3 * pitch];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bop[nt], acc[i][nt], 0, 0, 0);
+      }
+    }
+    boff = R * pitch - boff;
+  }
+  // epilogue: tile t of the padded space -> block and tile, pads skipped
+  const int W_out = NB * k;
+  const int D = d0 + (NB == 2 ? d1 : 0);
+  float* out = partial + (int64_t)blockIdx.x * D * W_out;
+#pragma unroll
+  for (int i = 0; i < TPB; ++i) {
+    const int t = w + kDmaWaves * i;
+    if (t < G.TTp) {
+      bool b1 = false, ok = true;
+      int ct = t;
+      if (t >= G.T0) {
+        if (NB == 2 && t >= G.T0p && t < G.T0p + G.T1) { b1 = true; ct = t - G.T0p; }
+        else ok = false;
+      }
+      if (ok) {
+        const int db = b1 ? d1 : d0;
+        const int rowbase = b1 ? d0 : 0;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int col = l16;
+          if (col < k) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int c = ct * 16 + acc_row<float>(lane, r);
+              if (c < db) out[(int64_t)(rowbase + c) * W_out + nt * k + col] = acc[i][nt][r];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+static size_t bf_lds_bytes(int d0, int d1, int NT) {
+  const BfGeom G = bf_geom(d0, d1);
+  return (size_t)2 * kBfRows * G.pitch * 2 + (size_t)kDmaWaves * NT * 256 * 4 + (size_t)NT * 256 * 2;
+}
+
+static int bf_vec(const void* A0, const void* A1, int d0, int d1) {
+  const int T0 = (d0 + 15) / 16, T1 = A1 ? (d1 + 15) / 16 : 0;
+  const bool al16 = ((uintptr_t)A0 % 16 == 0) && (!A1 || (uintptr_t)A1 % 16 == 0) && d0 % 8 == 0 &&
+                    (!A1 || d1 % 8 == 0);
+  if (al16 && T0 * 16 >= 512 && (!A1 || T1 * 16 >= 512)) return 8;
+  const bool al4 = ((uintptr_t)A0 % 4 == 0) && (!A1 || (uintptr_t)A1 % 4 == 0) && d0 % 2 == 0 && (!A1 || d1 % 2 == 0);
+  if (al4 && T0 * 16 >= 128 && (!A1 || T1 * 16 >= 128)) return 2;
+  return 0;
+}
+
+static bool bf_fits(int d0, int d1, int k, int nb, int vec) {
+  if (vec == 0 || k > 16) return false;
+  const BfGeom G = bf_geom(d0, nb == 2 ? d1 : 0);
+  if (G.TTp > kDmaMaxTiles) return false;
+  return bf_lds_bytes(d0, nb == 2 ? d1 : 0, nb) <= (size_t)kPassLds + 8 * 1024;
+}
+
+template <int NB, int VEC>
+static int pass_launch_bf(const unsigned short* A0, const unsigned short* A1, int64_t n, int d0, int d1, int k,
+                          const double* W0, const double* W1, double* J0, double* J1, const int* done, Arena& ws,
+                          hipStream_t st, hipEvent_t before_pass, hipEvent_t after_pass) {
+  const BfGeom G = bf_geom(d0, NB == 2 ? d1 : 0);
+  const int dp0 = G.T0p * 16, dp1 = NB == 2 ? G.T1p * 16 : 0;
+  unsigned short* Wp0 = ws.take<unsigned short>((size_t)dp0 * 16);
+  unsigned short* Wp1 = NB == 2 ? ws.take<unsigned short>((size_t)dp1 * 16) : nullptr;
+  const int nrb = (int)((n + kBfRows - 1) / kBfRows);
+  const int grid = std::max(1, std::min(num_cus(), (nrb + 3) / 4));
+  const int Dtot = d0 + (NB == 2 ? d1 : 0);
+  float* part = ws.take<float>((size_t)grid * Dtot * NB * k);
+  if (!Wp0 || !part || (NB == 2 && !Wp1)) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
+  const int tot = dp0 * 16 + dp1 * 16;
+  hipLaunchKernelGGL(k_pack_dir_bf, dim3((tot + 255) / 256), dim3(256), 0, st, W0, d0, dp0, Wp0, W1, d1, dp1, Wp1,
+                     k);
+  SRP_LAUNCH_CHECK();
+  const size_t lds = bf_lds_bytes(d0, NB == 2 ? d1 : 0, NB);
+  static bool attr_done = false;
+  if (!attr_done) {
+    SRP_HIP(hipFuncSetAttribute((const void*)k_pass_bf<NB, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kPassLds + 8 * 1024));
+    attr_done = true;
+  }
+  if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
+  hipLaunchKernelGGL((k_pass_bf<NB, VEC>), dim3(grid), dim3(kDmaThreads), lds, st, A0, A1, n, d0, NB == 2 ? d1 : 0,
+                     k, Wp0, Wp1, nrb, part, done);
+  SRP_LAUNCH_CHECK();
+  if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
+  const int64_t count = (int64_t)Dtot * NB * k;
+  hipLaunchKernelGGL((k_pass_reduce<float>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, grid, d0,
+                     NB == 2 ? d1 : 0, NB * k, J0, J1, done);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+static int pass_dispatch_bf(const unsigned short* A0, const unsigned short* A1, int64_t n, int d0, int d1, int k,
+                            const double* W0, const double* W1, double* J0, double* J1, const int* done, Arena& ws,
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev) {
+  const int vec = bf_vec(A0, A1, d0, d1);
+  if (A1) {
+    if (vec == 8) return pass_launch_bf<2, 8>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+    return pass_launch_bf<2, 2>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+  }
+  if (vec == 8) return pass_launch_bf<1, 8>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+  return pass_launch_bf<1, 2>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+}
+
 int pass_limits_ok(int dtype, int compute, int d0, int d1, int k, int nblocks) {
+  if (compute == SRP_BF16) {
+    if (dtype != SRP_BF16 || k > 16) return 0;
+    const BfGeom G = bf_geom(d0, nblocks == 2 ? d1 : 0);
+    return G.TTp <= kDmaMaxTiles && bf_lds_bytes(d0, nblocks == 2 ? d1 : 0, nblocks) <= (size_t)kPassLds + 8 * 1024;
+  }
   const int D = d0 + (nblocks == 2 ? d1 : 0);
   const bool f64 = (compute == SRP_F64);
   if (dtype == SRP_F64 && !f64) return 0;
@@ -713,6 +1009,14 @@ int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_
   if (!pass_limits_ok(dtype, compute, d0, d1, k, nb)) {
     set_error("gram_pass: unsupported shape (d0=%d d1=%d k=%d dtype=%d compute=%d)", d0, d1, k, dtype, compute);
     return SRP_EINVAL;
+  }
+  if (compute == SRP_BF16) {   // BF16 matrix-core products: BF16 data only
+    if (dtype != SRP_BF16 || !bf_fits(d0, nb == 2 ? d1 : 0, k, nb, bf_vec(A0, A1, d0, d1))) {
+      set_error("gram_pass: BF16 products need BF16 data, k <= 16 and a supported shape");
+      return SRP_EINVAL;
+    }
+    return pass_dispatch_bf((const unsigned short*)A0, (const unsigned short*)A1, n, d0, d1, k, W0, W1, J0, J1, done,
+                            ws, st, before_pass, after_pass);
   }
   if (compute == SRP_F64) {
     switch (dtype) {

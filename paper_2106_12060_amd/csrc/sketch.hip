@@ -161,6 +161,8 @@ int countsketch_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t 
       return cs_gather_launch((const float*)A, d, s, seed, offsets, sorted, (float*)out, st);
     case SRP_BF16:
       return cs_gather_launch((const bf16*)A, d, s, seed, offsets, sorted, (float*)out, st);
+    case SRP_FP8E4M3:
+      return cs_gather_launch((const fp8e4m3*)A, d, s, seed, offsets, sorted, (float*)out, st);
   }
   set_error("countsketch: bad dtype %d", dtype);
   return SRP_EINVAL;
@@ -572,6 +574,8 @@ int srht_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, v
     return srht_levels((const float*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (float*)out, st);
   if (dtype == SRP_BF16)
     return srht_levels((const bf16*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (float*)out, st);
+  if (dtype == SRP_FP8E4M3)
+    return srht_levels((const fp8e4m3*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (float*)out, st);
   set_error("srht: bad dtype %d", dtype);
   return SRP_EINVAL;
 }

@@ -46,3 +46,13 @@ def test_default_options_host_only():
     assert o.max_iter == 1000 and o.sketch == srp.SRP_COUNTSKETCH
     o2 = srp.srp_default_options(sketch="srht", max_iter=7)
     assert o2.sketch == srp.SRP_SRHT and o2.max_iter == 7
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsrp.so not built")
+def test_struct_layouts_match_library():
+    import paper_2106_12060_amd as srp
+    from paper_2106_12060_amd import _lib
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert srp.lib().srp_abi_sizes(ctypes.byref(a), ctypes.byref(b)) == 0
+    assert a.value == ctypes.sizeof(_lib.SrpOptions)
+    assert b.value == ctypes.sizeof(_lib.SrpInfo)

@@ -152,3 +152,89 @@ def test_gram_pass_matches_products(n, d0, d1, k, dt, comp):
     for g, ref, mag in zip(got, J, Jabs):
         bound = (d0 + d1 + n + 2) * u * mag + 1e-300
         assert np.all(np.abs(g - ref) <= bound), np.max(np.abs(g - ref) / bound)
+
+
+# ---------------------------------------------------------- staging
+def test_stage_bf16_bit_exact():
+    from oracle import quant
+    srp = _srp()
+    rng = np.random.default_rng(11)
+    X = (rng.standard_normal((1037, 129)) * np.exp(rng.uniform(-20, 20, (1037, 129)))).astype(np.float32)
+    X[0, :5] = [0.0, -0.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -3.0e38]
+    got = srp.srp_stage_bf16(torch.from_numpy(X).to(DEV)).float().cpu().numpy()
+    np.testing.assert_array_equal(got.view(np.uint32), quant.bf16_round(X).view(np.uint32))
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_stage_fp8_bit_exact(dt):
+    from oracle import quant
+    srp = _srp()
+    rng = np.random.default_rng(12)
+    n, d = 3001, 67
+    X = (rng.standard_normal((n, d)) * np.exp(rng.uniform(-12, 12, d))[None, :]).astype(np.float32)
+    X[:, 5] = 0.0                                   # empty column: scale 1
+    X[7, 6] = 448.0 * 2.0 ** 3                      # column max exactly 448 2^3
+    X[:, 8] = np.float32(2.0 ** -9) * rng.integers(-20, 20, n)   # subnormal grid and ties
+    Xt = torch.from_numpy(X).to(DEV)
+    if dt == "bf16":
+        Xt = Xt.to(torch.bfloat16)
+        X = Xt.float().cpu().numpy()
+    codes, scales = srp.srp_stage_fp8(Xt)
+    ref_codes, ref_scales = quant.fp8_stage(X.astype(np.float64))
+    np.testing.assert_array_equal(scales.cpu().numpy(), ref_scales)
+    np.testing.assert_array_equal(codes.cpu().numpy(), ref_codes)
+
+
+@pytest.mark.parametrize("kind", ["countsketch", "srht"])
+def test_sketch_of_fp8_codes(kind):
+    """Sketch of the FP8-staged matrix = sketch of the decoded codes times the
+    column scales (exact: powers of two), against the oracle's sketch of the
+    unstaged-and-rescaled matrix."""
+    from oracle import quant
+    srp = _srp()
+    rng = np.random.default_rng(13)
+    n, d, s = 5000, 40, 256
+    X = rng.standard_normal((n, d)).astype(np.float32) * 3.0
+    codes, scales = srp.srp_stage_fp8(torch.from_numpy(X).to(DEV))
+    fn = srp.srp_countsketch if kind == "countsketch" else srp.srp_srht
+    out = fn(codes, s, 99).double().cpu().numpy() * scales.cpu().numpy()[None, :]
+    Xq = quant.fp8_unstage(codes.cpu().numpy(), scales.cpu().numpy())
+    ref = osk.sketch(Xq, kind, s, 99)
+    mag = np.abs(osk.sketch(np.abs(Xq), kind, s, 99)) + np.abs(Xq).sum(axis=0)[None, :] / np.sqrt(s)
+    assert np.all(np.abs(out - ref) <= 40 * U32 * mag)
+
+
+@pytest.mark.parametrize("n,d0,d1,k", [(3000, 520, 600, 10), (2001, 130, 200, 10), (1500, 1000, 0, 16),
+                                       (777, 264, 130, 3)])
+def test_gram_pass_bf16_products(n, d0, d1, k):
+    """BF16 matrix-core pass against the oracle on the same quantised
+    operands: BF16 data, BF16 direction, P = A W rounded to BF16 before
+    A^T P.  The bound allows P's rounding to land one BF16 ulp apart (the
+    kernel rounds an FP32 sum) plus FP32 accumulation."""
+    from oracle import quant
+    srp = _srp()
+    rng = np.random.default_rng(n + d0 + 7)
+    A0 = torch.from_numpy(rand_data(n, d0, n)).to(DEV).to(torch.bfloat16)
+    A0q = A0.float().cpu().numpy().astype(np.float64)
+    W0 = rng.standard_normal((d0, k))
+    W0q = quant.bf16_round(W0.astype(np.float32)).astype(np.float64)
+    blocks = [(A0, A0q, W0, W0q)]
+    if d1:
+        A1 = torch.from_numpy(rand_data(n, d1, n + 1)).to(DEV).to(torch.bfloat16)
+        A1q = A1.float().cpu().numpy().astype(np.float64)
+        W1 = rng.standard_normal((d1, k))
+        W1q = quant.bf16_round(W1.astype(np.float32)).astype(np.float64)
+        blocks.append((A1, A1q, W1, W1q))
+    P = np.concatenate([Aq @ Wq for _, Aq, _, Wq in blocks], axis=1)
+    Pq = quant.bf16_round(P.astype(np.float32)).astype(np.float64)
+    if d1:
+        G0, G1 = srp.srp_gram_pass(A0, torch.from_numpy(W0).to(DEV), A1, torch.from_numpy(W1).to(DEV),
+                                   compute="bf16")
+        got = [G0.cpu().numpy(), G1.cpu().numpy()]
+    else:
+        G0, _ = srp.srp_gram_pass(A0, torch.from_numpy(W0).to(DEV), compute="bf16")
+        got = [G0.cpu().numpy()]
+    for g, (_, Aq, _, _) in zip(got, blocks):
+        ref = Aq.T @ Pq
+        bound = 2.0 ** -7 * (np.abs(Aq).T @ np.abs(P)) + (Aq.shape[1] + n) * U32 * (np.abs(Aq).T @ np.abs(Pq))
+        assert np.all(np.abs(g - ref) <= bound + 1e-300), np.max(np.abs(g - ref) / (bound + 1e-300))

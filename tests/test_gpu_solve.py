@@ -170,3 +170,79 @@ def test_cca_rank_deficient_without_regularisation():
     with pytest.raises(srp.SrpError) as e:
         srp.cca_solve(dev(X), dev(Y), 2, 0.0, 0.0, 40)
     assert e.value.code == srp.SRP_ENOTSPD
+
+
+def _cca_case(n=30_000, dx=200, dy=160, s=800, r=10):
+    import dataclasses
+    wl = dataclasses.replace(synth.workload("cca-f32-srht").scaled(n=n, dx=dx, dy=dy, s=s), r=r)
+    X, Y = wl.generate()
+    return wl, X, Y
+
+
+def test_cca_equal_weights_objective_and_order():
+    """N = I (unweighted trace): the top-k subspace, ordered by the closing
+    Rayleigh-Ritz step; sigma against the oracle's."""
+    srp = _srp()
+    wl, X, Y = _cca_case()
+    lam = wl.lam_value
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), wl.k, lam, lam, wl.s, tol=1e-6, mu=[1.0] * wl.k,
+                                    options=srp.srp_default_options(sketch="srht", max_iter=300))
+    err, cons = cca_errors(U, V, X.astype(np.float64), Y.astype(np.float64), lam, sig_true)
+    print("N=I", info, err, cons)
+    assert err < 1e-6 and cons < 1e-6
+    s = sig.cpu().numpy()
+    assert np.all(np.diff(s) <= 0)
+    np.testing.assert_allclose(s, sig_true[:wl.k], rtol=0, atol=1e-5)
+
+
+def test_cca_bf16_phase_then_fp32_refinement():
+    """BF16 copies (srp_stage_bf16) drive the iteration on BF16 matrix
+    cores; the same call then refines on the FP32 data.  The BF16-only
+    answer is within 1e-3 of the FP64 objective; the refined one within
+    1e-6 (tolerances of the low-precision and FP32 forms)."""
+    srp = _srp()
+    wl, X, Y = _cca_case()
+    lam = wl.lam_value
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    Xd, Yd = dev(X), dev(Y)
+    Xb, Yb = srp.srp_stage_bf16(Xd), srp.srp_stage_bf16(Yd)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    # BF16 phase only: the FP32 refinement gets no iterations to work with
+    opt = srp.srp_default_options(sketch="srht", max_iter=1)
+    opt.lowp_tol = 1e-4
+    U, V, sig, info = srp.cca_solve(Xd, Yd, wl.k, lam, lam, wl.s, tol=1e-30, options=opt, mu=[1.0] * wl.k,
+                                    lowp=(Xb, Yb))
+    err_lp, _ = cca_errors(U, V, X64, Y64, lam, sig_true)
+    print("bf16 only", info, err_lp)
+    assert info["lowp_iterations"] >= 1
+    assert err_lp < 1e-3
+    opt = srp.srp_default_options(sketch="srht", max_iter=300)
+    U, V, sig, info = srp.cca_solve(Xd, Yd, wl.k, lam, lam, wl.s, tol=1e-6, options=opt, mu=[1.0] * wl.k,
+                                    lowp=(Xb, Yb))
+    err, cons = cca_errors(U, V, X64, Y64, lam, sig_true)
+    print("bf16 + fp32", info, err, cons)
+    assert err < 1e-6 and cons < 1e-6
+
+
+@pytest.mark.parametrize("fmt", ["fp8", "bf16"])
+def test_cca_staged_sketch_inputs(fmt):
+    """Sketch from an FP8 (with column scales) or BF16 staged copy: the
+    preconditioner changes, the fixed point does not (the critical points
+    do not depend on the metric), so the answer still meets 1e-6."""
+    srp = _srp()
+    wl, X, Y = _cca_case()
+    lam = wl.lam_value
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    Xd, Yd = dev(X), dev(Y)
+    if fmt == "fp8":
+        (cx, sx), (cy, sy) = srp.srp_stage_fp8(Xd), srp.srp_stage_fp8(Yd)
+        staged = (cx, cy, sx, sy)
+    else:
+        staged = (srp.srp_stage_bf16(Xd), srp.srp_stage_bf16(Yd), None, None)
+    U, V, sig, info = srp.cca_solve(Xd, Yd, wl.k, lam, lam, wl.s, tol=1e-6, mu=[1.0] * wl.k,
+                                    options=srp.srp_default_options(sketch="srht", max_iter=300),
+                                    sketch_input=staged)
+    err, cons = cca_errors(U, V, X.astype(np.float64), Y.astype(np.float64), lam, sig_true)
+    print(fmt, info, err, cons)
+    assert err < 1e-6 and cons < 1e-6
