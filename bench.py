@@ -82,7 +82,8 @@ def main():
           flush=True)
     A, B = wl.generate()
     dev = torch.device("cuda:0")
-    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[wl.dtype]
+    lowp_form = wl.dtype == "bf16"   # FP32 data, staged BF16 / FP8 copies, BF16 phase + FP32 refinement
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}[wl.dtype]
     Ad = torch.from_numpy(A).to(dev).to(tdt).contiguous()
     if wl.problem == "cca":
         Bd = torch.from_numpy(B).to(dev).to(tdt).contiguous()
@@ -103,11 +104,36 @@ def main():
     warm = args.warm if args.warm is not None else 60
     extra = {"warm_start_iters": warm}
     sketch = srp.SRP_SRHT if wl.sketch == "srht" else srp.SRP_COUNTSKETCH
+    staging = None
+    lowp = sketch_input = None
+    if lowp_form:
+        staging = {}
 
-    def one(time_passes=False):
-        opt = srp.srp_default_options(sketch=sketch, max_iter=args.max_iter, time_passes=int(time_passes), **extra)
+        def timed(fn, reps=3):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                r = fn()
+            torch.cuda.synchronize()
+            return r, (time.perf_counter() - t) / reps
+
+        nbytes = Ad.numel() * 4 + Bd.numel() * 4
+        (Xb, Yb), dt_b = timed(lambda: (srp.srp_stage_bf16(Ad), srp.srp_stage_bf16(Bd)))
+        staging["bf16"] = {"ms": dt_b * 1e3, "GB/s": (nbytes * 1.5) / dt_b / 1e9,
+                           "bytes": "read FP32 X, Y; write BF16 copies"}
+        ((cx, sx), (cy, sy)), dt_8 = timed(lambda: (srp.srp_stage_fp8(Ad), srp.srp_stage_fp8(Bd)))
+        staging["fp8_e4m3"] = {"ms": dt_8 * 1e3, "GB/s": (nbytes * 2.25) / dt_8 / 1e9,
+                               "bytes": "read FP32 X, Y twice (column maxima, then codes); write FP8 copies"}
+        lowp = (Xb, Yb)
+        sketch_input = (cx, cy, sx, sy)
+
+    def one(time_passes=False, max_iter=None, staged=True):
+        opt = srp.srp_default_options(sketch=sketch, max_iter=args.max_iter if max_iter is None else max_iter,
+                                      time_passes=int(time_passes), **extra)
         if wl.problem == "cca":
-            return srp.cca_solve(Ad, Bd, wl.k, lam, lam, wl.s, tol=tol, options=opt, mu=mu)
+            return srp.cca_solve(Ad, Bd, wl.k, lam, lam, wl.s, tol=tol, options=opt, mu=mu,
+                                 lowp=lowp if staged else None, sketch_input=sketch_input if staged else None)
         return srp.lda_solve(Ad, Bd, wl.c, wl.k, lam, wl.s, tol=tol, options=opt, mu=mu)
 
     for _ in range(args.warmup):
@@ -123,18 +149,21 @@ def main():
     value = args.steps / elapsed
     ms_per_step = 1000.0 * elapsed / args.steps
 
-    # dominant kernel: the fused data pass over the full data
+    # dominant kernel: the fused data pass over the full data (the BF16 pass
+    # in the low-precision form)
     esize = {"f64": 8, "f32": 4, "bf16": 2}[wl.dtype]
     dsum = wl.dx + (wl.dy if wl.problem == "cca" else 0)
     bytes_per_launch = wl.n * dsum * esize
-    pass_ms = sum(i["pass_ms"] for i in infos)
-    launches = sum(i["pass_launches"] for i in infos)
+    key_ms, key_n = ("lowp_pass_ms", "lowp_pass_launches") if lowp_form else ("pass_ms", "pass_launches")
+    pass_ms = sum(i[key_ms] for i in infos)
+    launches = sum(i[key_n] for i in infos)
     avg_ms = pass_ms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     flops_per_pass = (6 if wl.problem == "cca" else 4) * wl.k * dsum * wl.n
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k_pass (fused data pass)", "bytes_per_launch": bytes_per_launch,
+                "kernel": "k_pass_bf (BF16 data pass)" if lowp_form else "k_pass_dma (fused data pass)",
+                "bytes_per_launch": bytes_per_launch,
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "tflops": flops_per_pass / (avg_ms * 1e-3) / 1e12 if launches else 0.0}
 
@@ -149,7 +178,21 @@ def main():
            "roofline": roofline,
            "solve": {key: infos[-1][key] for key in ("status", "iterations", "warm_iterations", "passes",
                                                      "ms_sketch", "ms_factor", "ms_warm", "ms_iterate",
-                                                     "ms_total")}}
+                                                     "ms_total", "lowp_iterations", "ms_lowp")}}
+    if lowp_form:
+        out["config"]["form"] = ("sketch of FP8 E4M3 staged copies; BF16 matrix-core passes to gradient "
+                                 "tolerance 1e-3, then FP32 passes to tol; FP64 factors and k x k algebra")
+        out["staging"] = staging
+        # the FP32 form on the same data, for the speedup
+        one(staged=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            res32 = one(staged=False)
+        torch.cuda.synchronize()
+        ms32 = 1000.0 * (time.perf_counter() - t1) / args.steps
+        out["fp32_form"] = {"ms_per_step": ms32, "speedup_of_this_form": ms32 / ms_per_step}
+        res_before = one(max_iter=0)   # the BF16 phase only (no FP32 iteration)
     vals = None
     if not args.no_cpu_baseline:
         rec, vals = cpu_baseline(wl, A, B)
@@ -160,10 +203,18 @@ def main():
             vals = (direct.cca_direct(A, B, lam, lam)[0] if wl.problem == "cca"
                     else direct.lda_direct(A, B, wl.c, lam, k=wl.k)[0])
         if wl.problem == "cca":
-            U, V = res[0].cpu().numpy(), res[1].cpu().numpy()
             A64, B64 = A.astype(np.float64), B.astype(np.float64)
-            err = metrics.cca_rel_objective_error(U, V, A64, B64, lam, lam, vals)
-            cons = max(metrics.constraint_residual(U, A64, lam), metrics.constraint_residual(V, B64, lam))
+
+            def acc(r):
+                U, V = r[0].cpu().numpy(), r[1].cpu().numpy()
+                return (metrics.cca_rel_objective_error(U, V, A64, B64, lam, lam, vals),
+                        max(metrics.constraint_residual(U, A64, lam), metrics.constraint_residual(V, B64, lam)))
+            err, cons = acc(res)
+            if lowp_form:
+                eb, cb = acc(res_before)
+                e32, c32 = acc(res32)
+                out["accuracy_before_refinement"] = {"rel_objective_error": eb, "constraint_residual": cb}
+                out["fp32_form"]["rel_objective_error"] = e32
         else:
             W = res[0].cpu().numpy()
             _, _, _, Xh, Yh = direct.lda_scatter(A, B, wl.c)

@@ -122,6 +122,8 @@ typedef struct srp_info {
   int pass_launches;      /* number of timed fused passes                    */
   int lowp_iterations;    /* iterations of the BF16 phase                    */
   double ms_lowp;         /* wall ms of the BF16 phase (inside ms_iterate)   */
+  double lowp_pass_ms;    /* summed duration of its timed BF16 passes         */
+  int lowp_pass_launches;
 } srp_info;
 
 /* Fill *opt with the defaults listed above.  Returns SRP_EINVAL if NULL. */

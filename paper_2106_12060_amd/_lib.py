@@ -48,7 +48,8 @@ class SrpInfo(ctypes.Structure):
                 ("ms_factor", ctypes.c_double), ("ms_warm", ctypes.c_double),
                 ("ms_iterate", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("pass_ms", ctypes.c_double), ("pass_launches", ctypes.c_int),
-                ("lowp_iterations", ctypes.c_int), ("ms_lowp", ctypes.c_double)]
+                ("lowp_iterations", ctypes.c_int), ("ms_lowp", ctypes.c_double),
+                ("lowp_pass_ms", ctypes.c_double), ("lowp_pass_launches", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

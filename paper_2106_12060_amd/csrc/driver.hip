@@ -469,7 +469,10 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
   // low-precision phase (CCA): BF16 data, BF16 matrix-core passes
   int lowp_iters = 0;
   double ms_lowp = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> lowp_events;
   if (ca.opt.lowp_x && full.nb == 2) {
+    B.time_passes = ca.opt.time_passes != 0;
+    B.events = &lowp_events;
     RcgProblem lp = full;
     lp.A[0] = ca.opt.lowp_x;
     lp.A[1] = ca.opt.lowp_y;
@@ -478,6 +481,8 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
     RcgResult rl;
     SRP_TRY(rcg_run(lp, B, start, std::max(1, ca.opt.lowp_max_iter), ca.opt.lowp_tol,
                     std::max(1, ca.opt.check_every), ca.opt.refresh_every, false, false, nullptr, rl, st));
+    B.time_passes = false;
+    B.events = nullptr;
     if (rl.status == SRP_ENOTSPD) {
       set_error("Cholesky breakdown in the BF16 phase");
       return SRP_ENOTSPD;
@@ -524,7 +529,16 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
   }
   B.time_passes = false;
   B.events = nullptr;
+  double lowp_pass_ms = 0.0;
+  for (auto& e : lowp_events) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) lowp_pass_ms += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
   if (info) {
+    info->lowp_pass_ms = lowp_pass_ms;
+    info->lowp_pass_launches = (int)lowp_events.size();
     info->pass_ms = pass_ms;
     info->pass_launches = (int)events.size();
     info->status = r.status;
