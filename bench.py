@@ -46,6 +46,26 @@ def parse():
     return ap.parse_args()
 
 
+def profiled_traffic(profile_name):
+    """HBM bytes per launch from a committed PMC summary under profiles/, or
+    None when the summary is absent or the kernel source has changed since
+    the counters were taken (the summary records a hash of that source)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", profile_name)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_src = re.search(r"kernel_source: (\S+) sha256\[:16\]=([0-9a-f]{16})", txt)
+    m_val = re.search(r"traffic_bytes_per_launch: (\d+)", txt)
+    if not (m_src and m_val):
+        return None
+    src = os.path.join(ROOT, m_src.group(1))
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != m_src.group(2):
+        return None
+    return int(m_val.group(1))
+
+
 def cpu_baseline(wl, X, Y_or_labels, min_seconds=10.0, max_reps=20):
     """The FP64 oracle (direct closed form) timed on this host's cores: whole
     solves of the same workload, repeated until about min_seconds of CPU
@@ -160,8 +180,11 @@ def main():
     avg_ms = pass_ms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     flops_per_pass = (6 if wl.problem == "cca" else 4) * wl.k * dsum * wl.n
+    prof = (f"{'k_pass_bf' if lowp_form else 'k_pass_dma'}_{wl.problem}-{'bf16' if lowp_form else wl.dtype}"
+            f"-n{wl.n}-d{wl.dx}x{wl.dy}-k{wl.k}.md" if wl.problem == "cca"
+            else f"k_pass_{wl.problem}-{wl.dtype}-n{wl.n}-d{wl.dx}-k{wl.k}.md")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(prof),
                 "kernel": "k_pass_bf (BF16 data pass)" if lowp_form else "k_pass_dma (fused data pass)",
                 "bytes_per_launch": bytes_per_launch,
                 "avg_launch_ms": avg_ms, "launches": launches,
