@@ -31,7 +31,16 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cca-f32-srht", choices=sorted(synth.WORKLOADS))
+    ap.add_argument("--workload", default="cca-f32-srht", choices=sorted(synth.WORKLOADS) + ["serving"])
+    ap.add_argument("--slots", type=int, default=4, help="serving: engine worker slots")
+    ap.add_argument("--hw-queues", type=int, default=None,
+                    help="serving: HIP hardware queues for this process (GPU_MAX_HW_QUEUES, <= 16; "
+                         "default: the number of slots when above HIP's default of 4)")
+    ap.add_argument("--pool-gib", type=float, default=64.0, help="serving: engine pool (HBM budget) in GiB")
+    ap.add_argument("--stage", choices=["none", "bf16", "bf16fp8"], default="bf16",
+                    help="serving: staged copies per request (BF16 phase + FP32 refinement, FP8 sketch input)")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: Poisson arrival rate (requests/s)")
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--max-iter", type=int, default=300)
     ap.add_argument("--weights", choices=["equal", "descending"], default="equal",
@@ -88,12 +97,157 @@ def cpu_baseline(wl, X, Y_or_labels, min_seconds=10.0, max_reps=20):
     return rec, vals
 
 
+def pct(a, q):
+    return float(np.percentile(np.asarray(a, dtype=np.float64), q)) if len(a) else None
+
+
+def serve(args):
+    """Serving workload: a Poisson trace of CCA requests of mixed sizes
+    replayed in real time against the continuous-batching engine.  One step
+    is one replay of the whole trace."""
+    import torch
+    import paper_2106_12060_amd as srp
+    from oracle import direct, metrics
+
+    lam = 1e-3
+    trace = synth.serving_trace(args.requests, args.rate)
+    print(f"bench: serving trace of {len(trace)} requests at {args.rate}/s; drawing the data on the device",
+          file=sys.stderr, flush=True)
+    data = [synth.cca_latent_device(q.n, q.dx, q.dy, r=8, noise=0.1, x_decades=3.0, seed=q.seed) for q in trace]
+    torch.cuda.synchronize()
+    data_bytes = sum(X.numel() * 4 + Y.numel() * 4 for X, Y in data)
+    stage = {"none": srp.SRP_STAGE_NONE, "bf16": srp.SRP_STAGE_BF16, "bf16fp8": srp.SRP_STAGE_BF16_FP8}[args.stage]
+    tol = args.tol if args.tol is not None else 1e-5
+    warm = args.warm if args.warm is not None else 40
+
+    def opt():
+        return srp.srp_default_options(sketch=srp.SRP_COUNTSKETCH, max_iter=args.max_iter,
+                                       warm_start_iters=warm, time_passes=1)
+
+    def submit(eng, i):
+        q = trace[i]
+        X, Y = data[i]
+        return eng.submit_cca(X, Y, q.k, lam, lam, 4 * max(q.dx, q.dy), tol=tol, options=opt(),
+                              mu=[1.0] * q.k, stage=stage)
+
+    eng = srp.Engine(int(args.pool_gib * (1 << 30)), max_slots=args.slots)
+    # untimed warm-up: a few requests (code objects, kernel attributes)
+    for i in range(min(args.warmup * 4, len(trace))):
+        eng.wait(submit(eng, i))
+    replays = []
+    outs = None
+    for step in range(args.steps):
+        t0 = time.perf_counter()
+        tickets = []
+        for i, q in enumerate(trace):
+            dt = t0 + q.arrival_s - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(submit(eng, i))
+        outs = [eng.wait(t, raise_on_error=False) for t in tickets]
+        wall = time.perf_counter() - t0
+        replays.append((wall, outs))
+        print(f"bench: replay {step + 1}/{args.steps}: {wall:.2f} s", file=sys.stderr, flush=True)
+    st = eng.stats()
+    eng.close()
+    wall, outs = replays[-1]
+    recs = [o[-1] for o in outs]
+    lat = [r["t_done_ms"] - r["t_submit_ms"] for r in recs]
+    queue = [r["t_start_ms"] - r["t_submit_ms"] for r in recs]
+    svc = [r["t_done_ms"] - r["t_start_ms"] for r in recs]
+    span_ms = max(r["t_done_ms"] for r in recs) - min(r["t_submit_ms"] for r in recs)
+    value = len(recs) / (span_ms * 1e-3)
+    # aggregate algorithmic bytes of every data pass (FP32 and BF16) over the replay
+    pass_bytes = 0
+    for q, r in zip(trace, recs):
+        nd = q.n * (q.dx + q.dy)
+        pass_bytes += r["info"]["pass_launches"] * nd * 4 + r["info"]["lowp_pass_launches"] * nd * 2
+    agg = pass_bytes / (span_ms * 1e-3) / 1e9
+    statuses, lowp_breakdowns, failures = {}, 0, []
+    for q, r in zip(trace, recs):
+        name = srp._lib.STATUS_NAMES.get(r["status"], r["status"])
+        statuses[name] = statuses.get(name, 0) + 1
+        lowp_breakdowns += int(r["info"]["lowp_status"] == srp.SRP_ENOTSPD)
+        if r["status"] not in (srp.SRP_OK, srp.SRP_ENOCONV) and len(failures) < 5:
+            failures.append({"rid": q.rid, "n": q.n, "dx": q.dx, "dy": q.dy, "k": q.k, "message": r["message"]})
+    out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1000.0 * sum(w for w, _ in replays) / len(replays),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16" if stage != srp.SRP_STAGE_NONE else "f32", "data": "synthetic",
+           "config": {"workload": f"serving-cca-{len(trace)}req-poisson{args.rate:g}", "requests": len(trace),
+                      "rate_per_s": args.rate, "n_range": [5000, 100000], "d_range": [64, 1024],
+                      "k_range": [2, 16], "lambda": lam, "sketch": "countsketch", "s": "4 max(dx, dy)",
+                      "tol": tol, "weights": "equal", "warm_start_iters": warm, "slots": args.slots,
+                      "pool_gib": args.pool_gib, "stage": args.stage, "parallelism": "single-gpu",
+                      "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
+                      "data_bytes_resident": data_bytes},
+           "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(np.mean(lat)),
+                          "max": float(np.max(lat))},
+           "queue_ms": {"p50": pct(queue, 50), "p99": pct(queue, 99)},
+           "service_ms": {"p50": pct(svc, 50), "p99": pct(svc, 99)},
+           "iterations": {"mean": float(np.mean([r["info"]["iterations"] for r in recs])),
+                          "p99": pct([r["info"]["iterations"] for r in recs], 99),
+                          "warm_mean": float(np.mean([r["info"]["warm_iterations"] for r in recs])),
+                          "bf16_phase_mean": float(np.mean([r["info"]["lowp_iterations"] for r in recs]))},
+           "engine": {"peak_running": st["peak_running"], "pool_peak_bytes": st["pool_peak"],
+                      "span_ms": span_ms, "statuses": statuses, "bf16_phase_breakdowns": lowp_breakdowns,
+                      "failures": failures},
+           "roofline": {"bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": agg / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "all data passes of the replay (algorithmic bytes / replay span)"}}
+    if not args.no_accuracy:
+        # oracle check on a seeded sample of the requests the host solves quickly
+        cost = np.array([q.n * (q.dx + q.dy) ** 2 for q in trace], dtype=np.float64)
+        cheap = np.array([i for i in np.flatnonzero(cost < 3e10)
+                          if recs[i]["status"] in (srp.SRP_OK, srp.SRP_ENOCONV)], dtype=np.int64)
+        rng = np.random.default_rng(7)
+        pick = sorted(rng.choice(cheap, size=min(6, len(cheap)), replace=False).tolist())
+        errs, conss = [], []
+        for i in pick:
+            X64 = data[i][0].double().cpu().numpy()
+            Y64 = data[i][1].double().cpu().numpy()
+            sig, _, _ = direct.cca_direct(X64, Y64, lam, lam)
+            U, V = outs[i][0].cpu().numpy(), outs[i][1].cpu().numpy()
+            errs.append(metrics.cca_rel_objective_error(U, V, X64, Y64, lam, lam, sig))
+            conss.append(max(metrics.constraint_residual(U, X64, lam), metrics.constraint_residual(V, Y64, lam)))
+        out["accuracy"] = {"rel_objective_error_max": max(errs), "constraint_residual_max": max(conss),
+                           "sampled_requests": pick, "reference": "FP64 oracle (direct closed form)"}
+    if not args.no_cpu_baseline:
+        # the oracle on the host, whole requests of the same trace in arrival order, ~10 s
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        t_all, reps = 0.0, 0
+        for i in range(len(trace)):
+            if t_all >= 10.0:
+                break
+            X64 = data[i][0].double().cpu().numpy()
+            Y64 = data[i][1].double().cpu().numpy()
+            t1 = time.perf_counter()
+            direct.cca_direct(X64, Y64, lam, lam)
+            t_all += time.perf_counter() - t1
+            reps += 1
+        out["cpu_baseline"] = {"value": reps / t_all, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+                               "sample": f"the first {reps} requests of the trace, solved one after another by "
+                                         f"the FP64 direct closed form (numpy/OpenBLAS), {t_all:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU row-sharded path is design-only.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving":
+        if args.steps == 5 and "--steps" not in sys.argv:
+            args.steps = 1
+        # one hardware queue per engine stream, so that the slots' kernels
+        # are not serialised behind each other (set before HIP starts)
+        hwq = args.hw_queues if args.hw_queues is not None else (args.slots if args.slots > 4 else None)
+        if hwq is not None:
+            os.environ["GPU_MAX_HW_QUEUES"] = str(max(1, min(16, hwq)))
+        serve(args)
+        return
     import torch
     import paper_2106_12060_amd as srp
 

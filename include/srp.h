@@ -124,6 +124,11 @@ typedef struct srp_info {
   double ms_lowp;         /* wall ms of the BF16 phase (inside ms_iterate)   */
   double lowp_pass_ms;    /* summed duration of its timed BF16 passes         */
   int lowp_pass_launches;
+  int lowp_status;        /* how the BF16 phase ended: SRP_OK, SRP_ENOCONV
+                             (its cap) or SRP_ENOTSPD (a retraction Gram from
+                             BF16 products was not positive definite; the
+                             iteration then continued on the main data from
+                             the phase's start point)                        */
 } srp_info;
 
 /* Fill *opt with the defaults listed above.  Returns SRP_EINVAL if NULL. */
@@ -132,9 +137,10 @@ int srp_default_options(srp_options* opt);
 /* Thread-local text of the last error in this thread ("" if none). */
 const char* srp_last_error(void);
 
-/* sizeof(srp_options) and sizeof(srp_info) as compiled into the library,
- * for bindings to check their layouts.  Host only. */
-int srp_abi_sizes(size_t* options_bytes, size_t* info_bytes);
+/* sizeof(srp_options), sizeof(srp_info), sizeof(srp_request) and
+ * sizeof(srp_result) as compiled into the library, for bindings to check
+ * their layouts.  Host only; any pointer may be NULL. */
+int srp_abi_sizes(size_t* options_bytes, size_t* info_bytes, size_t* request_bytes, size_t* result_bytes);
 
 /* ---- sketches (Section 3; Appendix A) ---------------------------------
  * out = S A for an s x n sketch S drawn from `seed`, A n x d of `dtype`.
@@ -197,7 +203,10 @@ int srp_sketch_factor(const void* SA, int dtype, int s, int d, double lambda,
  * retraction of Eq. gradCCA / Table 1 consume.  One read of the data.
  * compute = SRP_BF16 (BF16 data only): the products run on BF16 matrix
  *   cores with FP32 accumulation; W is rounded to BF16 and A_b W_b is
- *   rounded to BF16 before the second product.
+ *   rounded to BF16 before the second product.  A view narrower than 113
+ *   columns (or rows that are not 4-byte aligned) is outside that
+ *   kernel's row chunk: those shapes run the FP32-arithmetic pass on the
+ *   same BF16 data (W and A_b W_b unrounded).
  * Limits: k <= 16 with two blocks, k <= 32 with one (k <= 16 for BF16
  * arithmetic); d0 + d1 <= 2048 (F32 / BF16 data) or <= 896 (F64
  * arithmetic).
@@ -239,6 +248,106 @@ int lda_solve(const void* X, const int32_t* labels, int64_t n, int d,
               int n_classes, int k, double lambda, int sketch_size,
               double tol, int dtype, const srp_options* opt, void* stream,
               double* W, double* rho, srp_info* info);
+
+/* Device workspace, in bytes, that one cca_solve / lda_solve with these
+ * sizes allocates (sketches, R^-1 and M^-1, iterate and product buffers,
+ * pass partials).  sketch_input_dtype: the dtype the sketch reads (the data
+ * dtype, or srp_options.sketch_dtype when sketch_x is set).  Returns 0 for
+ * sizes the solver rejects. */
+size_t srp_cca_workspace_bytes(int64_t n, int dx, int dy, int k, int sketch_size, int dtype,
+                               int sketch_kind, int sketch_input_dtype);
+size_t srp_lda_workspace_bytes(int64_t n, int d, int n_classes, int k, int sketch_size, int dtype,
+                               int sketch_kind);
+
+/* ---- serving engine ----------------------------------------------------
+ * Continuous batching of solves.  Not part of the paper's method: it is the
+ * request loop around Algorithms CCAopt / LDAopt for a stream of problems
+ * of mixed n, d and k.
+ *
+ * An engine owns one device-memory pool of hbm_budget_bytes, carved by a
+ * first-fit allocator, and max_slots worker slots, each with its own HIP
+ * stream (default priority) and host thread.  Submitted requests wait in
+ * arrival (FIFO) order.  The head request is admitted as soon as a slot is
+ * idle and its footprint (srp_request_footprint) fits in the pool; its
+ * sketches, metric factor, iterate and product buffers (and staged copies)
+ * then stay resident in that block until the solve ends, and the block
+ * returns to the pool.  Admitted solves run concurrently, one per slot, so
+ * their kernels overlap on the device; a request that arrives while others
+ * run starts as soon as a slot and memory free up.
+ *
+ * Ownership: X, Y / labels, the outputs and any pointer inside req->opt
+ * are caller memory that must stay valid until the request completes
+ * (poll / wait returns its status).  Each solve gives the same result as
+ * the synchronous call with the same arguments (the second CCA view runs
+ * after the first on the slot's stream instead of on a side stream).
+ * The engine functions are thread-safe. */
+#define SRP_PROBLEM_CCA 0
+#define SRP_PROBLEM_LDA 1
+
+#define SRP_STAGE_NONE 0      /* solve on the data as given                   */
+#define SRP_STAGE_BF16 1      /* F32 CCA data: the engine writes BF16 copies in
+                                 its pool and runs the BF16 phase on them, then
+                                 refines on X, Y (srp_options.lowp_*)          */
+#define SRP_STAGE_BF16_FP8 2  /* as SRP_STAGE_BF16, and the sketch reads FP8
+                                 E4M3 copies with column scales                */
+
+typedef struct srp_request {
+  int problem;            /* SRP_PROBLEM_CCA or SRP_PROBLEM_LDA              */
+  const void* X;          /* device, n x dx (CCA) / n x d (FDA), `dtype`      */
+  const void* Y;          /* CCA: device n x dy, `dtype`; FDA: int32 labels   */
+  int64_t n;
+  int dx;                 /* FDA: d                                           */
+  int dy;                 /* FDA: number of classes                           */
+  int k;
+  double lambda_x;        /* FDA: lambda                                      */
+  double lambda_y;        /* FDA: unused                                      */
+  int sketch_size;
+  double tol;
+  int dtype;              /* SRP_F64, SRP_F32 or SRP_BF16                     */
+  int stage;              /* SRP_STAGE_*                                      */
+  srp_options opt;        /* by value; lowp_* and sketch_* are set by the
+                             engine when stage != SRP_STAGE_NONE              */
+  double* U;              /* device outputs as in cca_solve (FDA: W, rho in   */
+  double* V;              /* U and sigma; V unused)                           */
+  double* sigma;
+} srp_request;
+
+typedef struct srp_result {
+  int status;             /* the solve's status (SRP_OK, SRP_ENOCONV, ...)    */
+  int slot;               /* worker slot that ran it                          */
+  double t_submit_ms;     /* engine clock: ms since srp_engine_create          */
+  double t_start_ms;      /* admitted (workspace reserved)                    */
+  double t_done_ms;       /* outputs complete on the device                   */
+  size_t footprint_bytes;
+  srp_info info;
+  char message[160];      /* the solve's error message, "" on success         */
+} srp_result;
+
+typedef struct srp_engine srp_engine;
+
+/* Creates an engine on `device` with a pool of hbm_budget_bytes (allocated
+ * once, here) and 1 <= max_slots <= 16 slots. */
+int srp_engine_create(int device, size_t hbm_budget_bytes, int max_slots, srp_engine** out);
+/* Bytes of the engine pool a request needs: the solve's workspace plus the
+ * staged copies (stage).  0 if the request's sizes are invalid. */
+size_t srp_request_footprint(const srp_request* req);
+/* Queues a request (never blocks on the GPU).  *ticket identifies it.
+ * SRP_EREJECTED: its footprint exceeds the whole pool; SRP_EINVAL: bad
+ * sizes or null pointers; SRP_EBUSY: the engine is shutting down. */
+int srp_engine_submit(srp_engine* e, const srp_request* req, uint64_t* ticket);
+/* SRP_PENDING while the request is queued or running; otherwise fills *out
+ * (if not NULL), returns the solve's status and forgets the ticket.
+ * SRP_EINVAL for an unknown ticket. */
+int srp_engine_poll(srp_engine* e, uint64_t ticket, srp_result* out);
+/* Blocks until the request completes; then as srp_engine_poll. */
+int srp_engine_wait(srp_engine* e, uint64_t ticket, srp_result* out);
+/* Engine counters: requests queued now, running now, the largest number
+ * that ran at once, pool bytes in use now and at most.  Any may be NULL. */
+int srp_engine_stats(srp_engine* e, int* queued, int* running, int* peak_running, size_t* pool_used,
+                     size_t* pool_peak);
+/* Finishes every queued and running request, then frees the pool, the
+ * streams and the threads.  Results not yet collected are dropped. */
+int srp_engine_destroy(srp_engine* e);
 
 #ifdef __cplusplus
 }

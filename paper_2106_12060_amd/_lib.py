@@ -49,10 +49,31 @@ class SrpInfo(ctypes.Structure):
                 ("ms_iterate", ctypes.c_double), ("ms_total", ctypes.c_double),
                 ("pass_ms", ctypes.c_double), ("pass_launches", ctypes.c_int),
                 ("lowp_iterations", ctypes.c_int), ("ms_lowp", ctypes.c_double),
-                ("lowp_pass_ms", ctypes.c_double), ("lowp_pass_launches", ctypes.c_int)]
+                ("lowp_pass_ms", ctypes.c_double), ("lowp_pass_launches", ctypes.c_int),
+                ("lowp_status", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SrpRequest(ctypes.Structure):
+    _fields_ = [("problem", ctypes.c_int), ("X", ctypes.c_void_p), ("Y", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("dx", ctypes.c_int), ("dy", ctypes.c_int), ("k", ctypes.c_int),
+                ("lambda_x", ctypes.c_double), ("lambda_y", ctypes.c_double), ("sketch_size", ctypes.c_int),
+                ("tol", ctypes.c_double), ("dtype", ctypes.c_int), ("stage", ctypes.c_int),
+                ("opt", SrpOptions), ("U", ctypes.c_void_p), ("V", ctypes.c_void_p), ("sigma", ctypes.c_void_p)]
+
+
+class SrpResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("slot", ctypes.c_int), ("t_submit_ms", ctypes.c_double),
+                ("t_start_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_size_t), ("info", SrpInfo), ("message", ctypes.c_char * 160)]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_ if name not in ("info", "message")}
+        d["info"] = self.info.as_dict()
+        d["message"] = self.message.decode(errors="replace")
+        return d
 
 
 class SrpError(RuntimeError):
@@ -68,7 +89,20 @@ _P = ctypes.c_void_p
 _SIGS = {
     "srp_default_options": (ctypes.c_int, [ctypes.POINTER(SrpOptions)]),
     "srp_last_error": (ctypes.c_char_p, []),
-    "srp_abi_sizes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "srp_abi_sizes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_size_t)] * 4),
+    "srp_cca_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "srp_lda_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "srp_engine_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_P)]),
+    "srp_request_footprint": (ctypes.c_size_t, [ctypes.POINTER(SrpRequest)]),
+    "srp_engine_submit": (ctypes.c_int, [_P, ctypes.POINTER(SrpRequest), ctypes.POINTER(ctypes.c_uint64)]),
+    "srp_engine_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(SrpResult)]),
+    "srp_engine_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(SrpResult)]),
+    "srp_engine_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t),
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "srp_engine_destroy": (ctypes.c_int, [_P]),
     "srp_countsketch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_uint64, _P, _P]),
     "srp_srht": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
@@ -286,3 +320,143 @@ def lda_solve(X, labels, n_classes, k, lam, sketch_size, tol=1e-6, options: SrpO
     if rc != SRP_OK and not (rc == SRP_ENOCONV and not raise_on_noconv):
         _check("lda_solve", rc)
     return W, rho, info.as_dict()
+
+
+# ------------------------------------------------------------ serving engine
+SRP_PROBLEM_CCA, SRP_PROBLEM_LDA = 0, 1
+SRP_STAGE_NONE, SRP_STAGE_BF16, SRP_STAGE_BF16_FP8 = 0, 1, 2
+
+
+class Engine:
+    """Continuous-batching engine (``srp_engine_*`` in include/srp.h).
+
+    submit_* returns a ticket at once; poll / wait return the outputs and
+    the engine's record for it.  Inputs are read on the engine's own
+    streams, so submit first waits for torch's current stream (the inputs'
+    producer); the tensors a request uses are held here until it ends."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, device: int | None = None):
+        dev = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        _check("srp_engine_create", lib().srp_engine_create(dev, int(hbm_budget_bytes), int(max_slots),
+                                                             ctypes.byref(h)))
+        self._h = h
+        self.device = dev
+        self._keep = {}
+
+    def _submit(self, req, keep):
+        torch.cuda.current_stream().synchronize()
+        t = ctypes.c_uint64()
+        _check("srp_engine_submit", lib().srp_engine_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    @staticmethod
+    def _mu(opt, mu, k):
+        if mu is None:
+            return None
+        buf = (ctypes.c_double * k)(*[float(m) for m in mu])
+        opt.mu = ctypes.cast(buf, ctypes.POINTER(ctypes.c_double))
+        return buf
+
+    def cca_request(self, X, Y, k, lambda_x, lambda_y, sketch_size, tol=1e-6, options=None, mu=None,
+                    stage=SRP_STAGE_NONE):
+        """(SrpRequest, kept objects) for a CCA solve; outputs allocated here."""
+        _need_cuda(X, Y)
+        if X.dtype != Y.dtype:
+            raise TypeError("X and Y must share a dtype")
+        n, dx = X.shape
+        dy = Y.shape[1]
+        opt = options if options is not None else srp_default_options()
+        req = SrpRequest()
+        req.problem, req.X, req.Y, req.n, req.dx, req.dy, req.k = SRP_PROBLEM_CCA, X.data_ptr(), Y.data_ptr(), n, dx, dy, k
+        req.lambda_x, req.lambda_y, req.sketch_size, req.tol = lambda_x, lambda_y, sketch_size, tol
+        req.dtype, req.stage = _dtype(X), stage
+        mu_buf = self._mu(opt, mu, k)
+        req.opt = opt
+        U = torch.empty((dx, k), dtype=torch.float64, device=X.device)
+        V = torch.empty((dy, k), dtype=torch.float64, device=X.device)
+        sigma = torch.empty(k, dtype=torch.float64, device=X.device)
+        req.U, req.V, req.sigma = U.data_ptr(), V.data_ptr(), sigma.data_ptr()
+        return req, {"kind": "cca", "in": (X, Y, mu_buf), "out": (U, V, sigma)}
+
+    def lda_request(self, X, labels, n_classes, k, lam, sketch_size, tol=1e-6, options=None, mu=None):
+        _need_cuda(X, labels)
+        if labels.dtype != torch.int32:
+            raise TypeError("labels must be int32")
+        n, d = X.shape
+        opt = options if options is not None else srp_default_options()
+        req = SrpRequest()
+        req.problem, req.X, req.Y, req.n, req.dx, req.dy, req.k = (SRP_PROBLEM_LDA, X.data_ptr(), labels.data_ptr(),
+                                                                   n, d, n_classes, k)
+        req.lambda_x, req.lambda_y, req.sketch_size, req.tol = lam, 0.0, sketch_size, tol
+        req.dtype, req.stage = _dtype(X), SRP_STAGE_NONE
+        mu_buf = self._mu(opt, mu, k)
+        req.opt = opt
+        W = torch.empty((d, k), dtype=torch.float64, device=X.device)
+        rho = torch.empty(k, dtype=torch.float64, device=X.device)
+        req.U, req.V, req.sigma = W.data_ptr(), None, rho.data_ptr()
+        return req, {"kind": "lda", "in": (X, labels, mu_buf), "out": (W, rho)}
+
+    @staticmethod
+    def footprint(req) -> int:
+        return int(lib().srp_request_footprint(ctypes.byref(req)))
+
+    def submit_cca(self, *args, **kw) -> int:
+        req, keep = self.cca_request(*args, **kw)
+        return self._submit(req, keep)
+
+    def submit_lda(self, *args, **kw) -> int:
+        req, keep = self.lda_request(*args, **kw)
+        return self._submit(req, keep)
+
+    def _finish(self, ticket, rc, res, raise_on_error):
+        keep = self._keep.pop(ticket)
+        if raise_on_error and rc not in (SRP_OK, SRP_ENOCONV):
+            raise SrpError("engine request", rc, res.message.decode(errors="replace"))
+        return (*keep["out"], res.as_dict())
+
+    def poll(self, ticket: int, raise_on_error: bool = True):
+        """None while pending, else (outputs..., record).  A failed solve
+        raises SrpError unless raise_on_error is False (then the record's
+        status and message tell)."""
+        res = SrpResult()
+        rc = lib().srp_engine_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(res))
+        if rc == SRP_PENDING:
+            return None
+        if ticket not in self._keep:
+            _check("srp_engine_poll", rc)
+        return self._finish(ticket, rc, res, raise_on_error)
+
+    def wait(self, ticket: int, raise_on_error: bool = True):
+        res = SrpResult()
+        rc = lib().srp_engine_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(res))
+        if ticket not in self._keep:
+            _check("srp_engine_wait", rc)
+        return self._finish(ticket, rc, res, raise_on_error)
+
+    def stats(self):
+        q, r, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        u, pk = ctypes.c_size_t(), ctypes.c_size_t()
+        _check("srp_engine_stats", lib().srp_engine_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(p),
+                                                          ctypes.byref(u), ctypes.byref(pk)))
+        return {"queued": q.value, "running": r.value, "peak_running": p.value, "pool_used": u.value,
+                "pool_peak": pk.value}
+
+    def close(self):
+        if self._h:
+            lib().srp_engine_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

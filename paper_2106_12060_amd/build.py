@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libsrp.so")
 ARCH = os.environ.get("SRP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["sketch.hip", "factor.hip", "pass.hip", "solver_kernels.hip", "lda.hip",
-           "stage.hip", "driver.hip", "api.cpp"]
+           "stage.hip", "driver.hip", "api.cpp", "engine.cpp"]
 
 COMMON_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
@@ -50,7 +50,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{proc.stdout}\n{proc.stderr}")

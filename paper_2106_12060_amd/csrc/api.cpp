@@ -8,16 +8,6 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
-namespace srp {
-const char* last_error();
-int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int k, double lx, double ly, int s,
-                   double tol, int dtype, const srp_options* opt, hipStream_t st, double* U, double* V,
-                   double* sigma, srp_info* info);
-int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c, int k, double lam, int s,
-                   double tol, int dtype, const srp_options* opt, hipStream_t st, double* W, double* rho,
-                   srp_info* info);
-}  // namespace srp
-
 using namespace srp;
 
 namespace {
@@ -61,9 +51,27 @@ int srp_default_options(srp_options* o) {
 
 const char* srp_last_error(void) { return srp::last_error(); }
 
-int srp_abi_sizes(size_t* options_bytes, size_t* info_bytes) {
+size_t srp_cca_workspace_bytes(int64_t n, int dx, int dy, int k, int sketch_size, int dtype, int sketch_kind,
+                               int sketch_input_dtype) {
+  if (n < 1 || dx < 1 || dy < 1 || k < 1 || k > std::min(dx, dy) || sketch_size < std::max(dx, dy)) return 0;
+  if (dtype < SRP_F64 || dtype > SRP_BF16 || sketch_input_dtype < SRP_F64 || sketch_input_dtype > SRP_FP8E4M3)
+    return 0;
+  if (sketch_kind != SRP_COUNTSKETCH && sketch_kind != SRP_SRHT) return 0;
+  return cca_ws_bytes(n, dx, dy, k, sketch_size, dtype, sketch_kind, sketch_input_dtype);
+}
+
+size_t srp_lda_workspace_bytes(int64_t n, int d, int n_classes, int k, int sketch_size, int dtype, int sketch_kind) {
+  if (n < 2 || d < 1 || n_classes < 2 || k < 1 || k > std::min(n_classes - 1, d) || sketch_size < d) return 0;
+  if (dtype < SRP_F64 || dtype > SRP_BF16) return 0;
+  if (sketch_kind != SRP_COUNTSKETCH && sketch_kind != SRP_SRHT) return 0;
+  return lda_ws_bytes(n, d, n_classes, k, sketch_size, dtype, sketch_kind);
+}
+
+int srp_abi_sizes(size_t* options_bytes, size_t* info_bytes, size_t* request_bytes, size_t* result_bytes) {
   if (options_bytes) *options_bytes = sizeof(srp_options);
   if (info_bytes) *info_bytes = sizeof(srp_info);
+  if (request_bytes) *request_bytes = sizeof(srp_request);
+  if (result_bytes) *result_bytes = sizeof(srp_result);
   return SRP_OK;
 }
 

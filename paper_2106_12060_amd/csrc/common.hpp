@@ -151,5 +151,9 @@ template <class T> inline size_t bytes_of(size_t count) {
 int device_alloc(void** p, size_t bytes, hipStream_t s);
 int device_free(void* p, hipStream_t s);
 int num_cus();
+// Raises the dynamic-LDS limit of kernel `fn` on the current device to at
+// least `bytes`.  Thread-safe; the limit only grows, so launches made by
+// other threads with smaller requests stay valid.
+int allow_dynamic_lds(const void* fn, size_t bytes);
 
 }  // namespace srp

@@ -20,6 +20,8 @@
 #include <vector>
 #include <cstdarg>
 #include <cstring>
+#include <atomic>
+#include <map>
 #include <mutex>
 
 namespace srp {
@@ -37,27 +39,45 @@ void clear_error() { g_err[0] = 0; }
 const char* last_error() { return g_err; }
 
 int num_cus() {
-  static int cached = 0;
-  if (cached) return cached;
+  static std::atomic<int> cached{0};
+  int c = cached.load(std::memory_order_relaxed);
+  if (c) return c;
   int dev = 0, v = 0;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-    cached = v;
+    c = v;
   else
-    cached = 256;
-  return cached;
+    c = 256;
+  cached.store(c, std::memory_order_relaxed);
+  return c;
+}
+
+int allow_dynamic_lds(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> limits;
+  int dev = 0;
+  SRP_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = limits[{dev, fn}];
+  if (bytes > cur) {
+    SRP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    cur = bytes;
+  }
+  return SRP_OK;
 }
 
 int device_alloc(void** p, size_t bytes, hipStream_t s) {
-  static bool pool_tuned = false;
-  if (!pool_tuned) {
-    int dev = 0;
+  static std::mutex mu;
+  static bool tuned[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+    std::lock_guard<std::mutex> lock(mu);
     hipMemPool_t pool;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    if (!tuned[dev] && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
       uint64_t thr = UINT64_MAX;
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
-    pool_tuned = true;
+    tuned[dev] = true;
   }
   hipError_t e = hipMallocAsync(p, bytes, s);
   if (e != hipSuccess) {
@@ -121,9 +141,15 @@ struct SideFork {
     if (fork) (void)hipEventDestroy(fork);
     if (join) (void)hipEventDestroy(join);
   }
-  int begin(hipStream_t st) {
+  // ctx == null: the per-device side stream; ctx->side == null: no fork,
+  // the "side" work runs in order on st itself.
+  int begin(hipStream_t st, const SolveCtx* ctx = nullptr) {
     main = st;
-    side = side_stream();
+    if (ctx && !ctx->side) {
+      side = st;
+      return SRP_OK;
+    }
+    side = ctx ? ctx->side : side_stream();
     if (!side) { set_error("could not create a side stream"); return SRP_EDEVICE; }
     SRP_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
     SRP_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
@@ -133,6 +159,7 @@ struct SideFork {
     return SRP_OK;
   }
   int end(hipStream_t st) {
+    if (!open) return SRP_OK;
     open = false;
     SRP_HIP(hipEventRecord(join, side));
     SRP_HIP(hipStreamWaitEvent(st, join, 0));
@@ -467,10 +494,15 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
   }
   const double ms_warm = tm.lap_ms();
   // low-precision phase (CCA): BF16 data, BF16 matrix-core passes
-  int lowp_iters = 0;
+  int lowp_iters = 0, lowp_status = SRP_OK;
   double ms_lowp = 0.0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> lowp_events;
   if (ca.opt.lowp_x && full.nb == 2) {
+    if (start[0] != outW[0]) {   // keep the phase's start point (Z is scratch of rcg_run)
+      for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], start[s], (int64_t)full.d[s] * k, st));
+      start[0] = outW[0];
+      start[1] = outW[1];
+    }
     B.time_passes = ca.opt.time_passes != 0;
     B.events = &lowp_events;
     RcgProblem lp = full;
@@ -483,13 +515,17 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
                     std::max(1, ca.opt.check_every), ca.opt.refresh_every, false, false, nullptr, rl, st));
     B.time_passes = false;
     B.events = nullptr;
-    if (rl.status == SRP_ENOTSPD) {
-      set_error("Cholesky breakdown in the BF16 phase");
-      return SRP_ENOTSPD;
+    lowp_status = rl.status;
+    // A retraction Gram from BF16 products can lose definiteness when the
+    // data's columns span many decades (the products' rounding is relative
+    // to |A|^T |A W|, not to the Gram).  The phase only accelerates: on a
+    // breakdown the iteration continues on the main data from the point the
+    // phase started at (still in outW).
+    if (rl.status != SRP_ENOTSPD) {
+      for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
+      start[0] = outW[0];
+      start[1] = outW[1];
     }
-    for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
-    start[0] = outW[0];
-    start[1] = outW[1];
     lowp_iters = rl.iterations;
     ms_lowp = tm.lap_ms();
   }
@@ -550,6 +586,7 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
     info->ms_warm = ms_warm;
     info->ms_iterate = ms_iter;
     info->lowp_iterations = lowp_iters;
+    info->lowp_status = lowp_status;
     info->ms_lowp = ms_lowp;
   }
   return r.status;
@@ -575,9 +612,63 @@ static int setup_mu(const srp_options& o, int k, double* mu_dev, hipStream_t st)
   return SRP_OK;
 }
 
+// Scratch of one CCA view's sketch and factor.  Both views get the larger
+// of the two needs: the factor's split-K partials do not grow monotonically
+// with d (fewer upper tiles take a deeper split).
+static size_t cca_view_scratch(int64_t n, int dx, int dy, int s, int dtype, int sketch_kind) {
+  return std::max({sketch_ws(sketch_kind, n, dx, s, dtype), sketch_ws(sketch_kind, n, dy, s, dtype),
+                   factor_ws_bytes(s, dx), factor_ws_bytes(s, dy)});
+}
+
+size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sketch_kind, int skin_dtype) {
+  const int sk_dtype = skin_dtype == SRP_F64 ? SRP_F64 : SRP_F32;
+  const size_t ssz = dtype_size(sk_dtype);
+  const int dd[2] = {dx, dy};
+  size_t bytes = 0;
+  bytes += 2 * (((size_t)s * std::max(dx, dy) * ssz + 255) & ~size_t(255));  // SX, SY
+  bytes += 2 * bytes_of<double>((size_t)dx * dx) + 2 * bytes_of<double>((size_t)dy * dy);  // R, Minv (x) ...
+  bytes += 2 * bytes_of<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
+  bytes += bytes_of<int>(4);
+  const size_t scratch = cca_view_scratch(n, dx, dy, s, dtype, sketch_kind);
+  bytes += rcg_buffers_bytes(2, k, std::max<int64_t>(n, s), dd, dtype);
+  bytes += 2 * ((scratch + 255) & ~size_t(255)) + 4096;   // one scratch per view (the views run concurrently)
+  return bytes;
+}
+
+size_t lda_ws_bytes(int64_t n, int d, int c, int k, int s, int dtype, int sketch_kind) {
+  const int sk_dtype = dtype == SRP_F64 ? SRP_F64 : SRP_F32;
+  const size_t esz = dtype_size(dtype), ssz = dtype_size(sk_dtype);
+  const int dd[2] = {d, 0};
+  size_t bytes = 0;
+  bytes += (((size_t)n * d * esz + 255) & ~size_t(255));          // Xhat
+  bytes += (((size_t)s * d * ssz + 255) & ~size_t(255));          // sketch
+  bytes += 3 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv
+  bytes += bytes_of<double>((size_t)c * d) + bytes_of<int>(c) + bytes_of<int>(4);
+  const size_t scratch = std::max({sketch_ws(sketch_kind, n, d, s, dtype), factor_ws_bytes(s, d),
+                                   lda_center_ws_bytes(n, d, c)});
+  bytes += rcg_buffers_bytes(1, k, std::max<int64_t>(n, s), dd, dtype, c);
+  bytes += scratch + 4096;
+  return bytes;
+}
+
+// The solve's workspace: the context's buffer when it has one (it must be
+// large enough), else a stream-ordered allocation released on return.
+static int take_workspace(Workspace& W, size_t bytes, const SolveCtx* ctx, hipStream_t st, void** base) {
+  if (ctx && ctx->ws) {
+    SRP_REQUIRE(ctx->ws_bytes >= bytes, "workspace of %zu bytes is smaller than the %zu needed", ctx->ws_bytes,
+                bytes);
+    *base = ctx->ws;
+    return SRP_OK;
+  }
+  W.st = st;
+  SRP_TRY(device_alloc(&W.base, bytes, st));
+  *base = W.base;
+  return SRP_OK;
+}
+
 int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int k, double lx, double ly, int s,
                    double tol, int dtype, const srp_options* optp, hipStream_t st, double* U, double* V,
-                   double* sigma, srp_info* info) {
+                   double* sigma, srp_info* info, const SolveCtx* ctx) {
   clear_error();
   srp_options opt;
   srp_default_options(&opt);
@@ -624,18 +715,12 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   // workspace
   const size_t ssz = dtype_size(sk_dtype);
   const int dd[2] = {dx, dy};
-  size_t bytes = 0;
-  bytes += 2 * (((size_t)s * std::max(dx, dy) * ssz + 255) & ~size_t(255));  // SX, SY
-  bytes += 2 * bytes_of<double>((size_t)dx * dx) + 2 * bytes_of<double>((size_t)dy * dy);  // R, Minv (x) ...
-  bytes += 2 * bytes_of<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
-  bytes += bytes_of<int>(4);
-  const size_t scratch = std::max({sketch_ws(opt.sketch, n, std::max(dx, dy), s, dtype), factor_ws_bytes(s, std::max(dx, dy))});
-  bytes += rcg_buffers_bytes(2, k, std::max<int64_t>(n, s), dd, dtype);
-  bytes += 2 * ((scratch + 255) & ~size_t(255)) + 4096;   // one scratch per view (the views run concurrently)
+  const size_t bytes = cca_ws_bytes(n, dx, dy, k, s, dtype, opt.sketch, skin_dtype);
+  const size_t scratch = cca_view_scratch(n, dx, dy, s, dtype, opt.sketch);
   Workspace W;
-  W.st = st;
-  SRP_TRY(device_alloc(&W.base, bytes, st));
-  Arena ar{(char*)W.base, bytes, 0};
+  void* wbase = nullptr;
+  SRP_TRY(take_workspace(W, bytes, ctx, st, &wbase));
+  Arena ar{(char*)wbase, bytes, 0};
   void* SX = ar.take<char>((size_t)s * dx * ssz);
   void* SY = ar.take<char>((size_t)s * dy * ssz);
   double* Rx = ar.take<double>((size_t)dx * dx);
@@ -659,7 +744,7 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   Arena sy{ar.base + ar.used + scr, scr, 0};
   if (ar.used + 2 * scr > ar.cap) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
   SideFork fk;
-  SRP_TRY(fk.begin(st));
+  SRP_TRY(fk.begin(st, ctx));
   SRP_TRY(sketch_any(opt.sketch, skin_y, skin_dtype, n, dy, s, opt.seed, SY, sy, fk.side));
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SY, s, dy, opt.sketch_scale_y, fk.side));
   {
@@ -714,7 +799,7 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
 
 int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c, int k, double lam, int s,
                    double tol, int dtype, const srp_options* optp, hipStream_t st, double* Wout, double* rho,
-                   srp_info* info) {
+                   srp_info* info, const SolveCtx* ctx) {
   clear_error();
   srp_options opt;
   srp_default_options(&opt);
@@ -740,19 +825,11 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   PhaseTimer tm(st);
   const size_t esz = dtype_size(dtype), ssz = dtype_size(sk_dtype);
   const int dd[2] = {d, 0};
-  size_t bytes = 0;
-  bytes += (((size_t)n * d * esz + 255) & ~size_t(255));          // Xhat
-  bytes += (((size_t)s * d * ssz + 255) & ~size_t(255));          // sketch
-  bytes += 3 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv
-  bytes += bytes_of<double>((size_t)c * d) + bytes_of<int>(c) + bytes_of<int>(4);
-  const size_t scratch = std::max({sketch_ws(opt.sketch, n, d, s, dtype), factor_ws_bytes(s, d),
-                                   lda_center_ws_bytes(n, d, c)});
-  bytes += rcg_buffers_bytes(1, k, std::max<int64_t>(n, s), dd, dtype, c);
-  bytes += scratch + 4096;
+  const size_t bytes = lda_ws_bytes(n, d, c, k, s, dtype, opt.sketch);
   Workspace Wk;
-  Wk.st = st;
-  SRP_TRY(device_alloc(&Wk.base, bytes, st));
-  Arena ar{(char*)Wk.base, bytes, 0};
+  void* wbase = nullptr;
+  SRP_TRY(take_workspace(Wk, bytes, ctx, st, &wbase));
+  Arena ar{(char*)wbase, bytes, 0};
   void* Xhat = ar.take<char>((size_t)n * d * esz);
   void* SXh = ar.take<char>((size_t)s * d * ssz);
   double* R = ar.take<double>((size_t)d * d);

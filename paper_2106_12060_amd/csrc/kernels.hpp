@@ -82,4 +82,24 @@ int stage_fp8_run(const void* X, int dtype, int64_t n, int d, uint8_t* out, doub
 // A (rows x d, FP32) column j times scales[j] (powers of two: exact).
 int scale_cols_run(float* A, int64_t rows, int d, const double* scales, hipStream_t st);
 
+// --------------------------------------------------------- solves
+// Execution context of one solve.  side: stream for the second CCA view
+// (null = both views in order on the main stream); ws / ws_bytes: a
+// workspace the solve carves its buffers from (null = allocate from the
+// stream-ordered pool and release on return).
+struct SolveCtx {
+  hipStream_t side = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sketch_kind, int skin_dtype);
+size_t lda_ws_bytes(int64_t n, int d, int c, int k, int s, int dtype, int sketch_kind);
+int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int k, double lx, double ly, int s,
+                   double tol, int dtype, const srp_options* opt, hipStream_t st, double* U, double* V,
+                   double* sigma, srp_info* info, const SolveCtx* ctx = nullptr);
+int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c, int k, double lam, int s,
+                   double tol, int dtype, const srp_options* opt, hipStream_t st, double* W, double* rho,
+                   srp_info* info, const SolveCtx* ctx = nullptr);
+const char* last_error();
+
 }  // namespace srp

@@ -842,12 +842,7 @@ static int pass_launch_bf(const unsigned short* A0, const unsigned short* A1, in
                      k);
   SRP_LAUNCH_CHECK();
   const size_t lds = bf_lds_bytes(d0, NB == 2 ? d1 : 0, NB);
-  static bool attr_done = false;
-  if (!attr_done) {
-    SRP_HIP(hipFuncSetAttribute((const void*)k_pass_bf<NB, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kPassLds + 8 * 1024));
-    attr_done = true;
-  }
+  SRP_TRY(allow_dynamic_lds((const void*)k_pass_bf<NB, VEC>, kPassLds + 8 * 1024));
   if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
   hipLaunchKernelGGL((k_pass_bf<NB, VEC>), dim3(grid), dim3(kDmaThreads), lds, st, A0, A1, n, d0, NB == 2 ? d1 : 0,
                      k, Wp0, Wp1, nrb, part, done);
@@ -876,7 +871,9 @@ int pass_limits_ok(int dtype, int compute, int d0, int d1, int k, int nblocks) {
   if (compute == SRP_BF16) {
     if (dtype != SRP_BF16 || k > 16) return 0;
     const BfGeom G = bf_geom(d0, nblocks == 2 ? d1 : 0);
-    return G.TTp <= kDmaMaxTiles && bf_lds_bytes(d0, nblocks == 2 ? d1 : 0, nblocks) <= (size_t)kPassLds + 8 * 1024;
+    if (G.TTp <= kDmaMaxTiles && bf_lds_bytes(d0, nblocks == 2 ? d1 : 0, nblocks) <= (size_t)kPassLds + 8 * 1024)
+      return 1;
+    return pass_limits_ok(SRP_BF16, SRP_F32, d0, d1, k, nblocks);   // the FP32-arithmetic pass takes it
   }
   const int D = d0 + (nblocks == 2 ? d1 : 0);
   const bool f64 = (compute == SRP_F64);
@@ -929,12 +926,7 @@ static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, in
   SRP_TRY(pack_dirs<CT>(W0, d0, dp0, Wp0, W1, d1, dp1, Wp1, k, KP, st));
   const int nrb = (int)((n + 15) / 16);
   const size_t lds = pass_lds_bytes<CT>(Dtot, NB * KT);
-  static bool attr_done = false;   // per template instance
-  if (!attr_done) {
-    SRP_HIP(hipFuncSetAttribute((const void*)k_pass<DT, CT, NB, KT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kPassLds));
-    attr_done = true;
-  }
+  SRP_TRY(allow_dynamic_lds((const void*)k_pass<DT, CT, NB, KT>, kPassLds));
   if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
   hipLaunchKernelGGL((k_pass<DT, CT, NB, KT>), dim3(grid), dim3(kPassThreads), lds, st, A0, A1, n, d0,
                      NB == 2 ? d1 : 0, k, Wp0, Wp1, nrb, part, done);
@@ -963,12 +955,7 @@ static int pass_launch_dma(const float* A0, const float* A1, int64_t n, int d0, 
   if (!Wp0 || !part || (NB == 2 && !Wp1)) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
   SRP_TRY(pack_dirs<float>(W0, d0, dp0, Wp0, W1, d1, dp1, Wp1, k, KP, st));
   const size_t lds = dma_lds_bytes(d0, NB == 2 ? d1 : 0, NB * KT);
-  static bool attr_done = false;   // per template instance
-  if (!attr_done) {
-    SRP_HIP(hipFuncSetAttribute((const void*)k_pass_dma<NB, KT, VEC>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kPassLds + 8 * 1024));
-    attr_done = true;
-  }
+  SRP_TRY(allow_dynamic_lds((const void*)k_pass_dma<NB, KT, VEC>, kPassLds + 8 * 1024));
   if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
   hipLaunchKernelGGL((k_pass_dma<NB, KT, VEC>), dim3(grid), dim3(kDmaThreads), lds, st, A0, A1, n, d0,
                      NB == 2 ? d1 : 0, k, Wp0, Wp1, nrb, part, done);
@@ -1011,12 +998,17 @@ int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_
     return SRP_EINVAL;
   }
   if (compute == SRP_BF16) {   // BF16 matrix-core products: BF16 data only
-    if (dtype != SRP_BF16 || !bf_fits(d0, nb == 2 ? d1 : 0, k, nb, bf_vec(A0, A1, d0, d1))) {
-      set_error("gram_pass: BF16 products need BF16 data, k <= 16 and a supported shape");
+    if (dtype != SRP_BF16) {
+      set_error("gram_pass: BF16 products need BF16 data");
       return SRP_EINVAL;
     }
-    return pass_dispatch_bf((const unsigned short*)A0, (const unsigned short*)A1, n, d0, d1, k, W0, W1, J0, J1, done,
-                            ws, st, before_pass, after_pass);
+    if (bf_fits(d0, nb == 2 ? d1 : 0, k, nb, bf_vec(A0, A1, d0, d1)))
+      return pass_dispatch_bf((const unsigned short*)A0, (const unsigned short*)A1, n, d0, d1, k, W0, W1, J0, J1,
+                              done, ws, st, before_pass, after_pass);
+    // views narrower than one 64-lane row chunk (or rows not 4-byte
+    // aligned): the FP32-arithmetic pass reads the same BF16 data
+    return pass_dispatch_k<bf16, float>((const bf16*)A0, (const bf16*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st,
+                                        before_pass, after_pass);
   }
   if (compute == SRP_F64) {
     switch (dtype) {

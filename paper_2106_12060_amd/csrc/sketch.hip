@@ -522,12 +522,7 @@ static int srht_levels(const T* A, int64_t n, int d, int s, uint64_t seed, const
     const int CW = 16384 >> logB;
     dim3 grid1(g.A_eff, (d + CW - 1) / CW);
     const size_t lds = (size_t)(16384 + 1024) * sizeof(Acc);
-    static bool attr = false;
-    if (!attr) {
-      SRP_HIP(hipFuncSetAttribute((const void*)k_srht_level1_reg<T, Acc>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-      attr = true;
-    }
+    SRP_TRY(allow_dynamic_lds((const void*)k_srht_level1_reg<T, Acc>, lds));
     hipLaunchKernelGGL((k_srht_level1_reg<T, Acc>), grid1, dim3(256), lds, st, A, n, d, logB,
                        seed ^ kSrhtSignSalt, Tbuf);
   } else {

@@ -565,11 +565,7 @@ static int launch_ctrl_ls_t(const ProbView& p, hipStream_t st) {
     return SRP_EINVAL;
   }
   const size_t lds = coef_bytes + (size_t)ntr * per_wave;
-  static size_t attr_set = 0;
-  if (lds > attr_set) {
-    SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_ls<KC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set = lds;
-  }
+  SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_ls<KC>, lds));
   hipLaunchKernelGGL(k_ctrl_ls<KC>, dim3(1), dim3(kLsThreads), lds, st, p, ntr);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
@@ -966,11 +962,7 @@ static int launch_ctrl_dir_t(const ProbView& p, hipStream_t st) {
   const int k = p.k, n = (k + 1) & ~1;
   const size_t per_side = (size_t)(9 * k * k + 5 * n * n);
   const size_t lds = (size_t)p.nb * per_side * sizeof(double);
-  static size_t attr_set = 0;
-  if (lds > attr_set) {
-    SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_dir<KC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    attr_set = lds;
-  }
+  SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_dir<KC>, lds));
   hipLaunchKernelGGL(k_ctrl_dir<KC>, dim3(1), dim3(512), lds, st, p);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
@@ -1137,7 +1129,7 @@ int launch_ctrl_final(const ProbView& p, double* sigma_out, hipStream_t st) {
   const int k = p.k;
   const int m = p.lda_cost ? ((k + 1) & ~1) : 2 * k;
   const size_t lds = (size_t)(8 * k * k + 4 * m * m) * sizeof(double);
-  SRP_HIP(hipFuncSetAttribute((const void*)k_ctrl_final, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_final, lds));
   hipLaunchKernelGGL(k_ctrl_final, dim3(1), dim3(64), lds, st, p, sigma_out);
   SRP_LAUNCH_CHECK();
   return SRP_OK;

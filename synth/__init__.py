@@ -20,7 +20,11 @@ rows (Section 2, Section 4 problem statement, Section 5 problem statement):
 * Planted CCA: matrices whose canonical correlations are known exactly,
   used to pin the oracle.
 
-All draws use ``numpy.random.default_rng(seed)`` (PCG64).
+All draws use ``numpy.random.default_rng(seed)`` (PCG64), except
+``cca_latent_device``: the same latent recipe drawn directly in device
+memory with torch's device generator (for the serving trace, whose 512
+requests hold about 1e11 bytes of data; the host could not draw them in
+reasonable time).
 """
 from __future__ import annotations
 
@@ -29,7 +33,7 @@ import dataclasses
 import numpy as np
 
 __all__ = [
-    "column_scales", "cca_latent", "lda_classes", "planted_cca",
+    "column_scales", "cca_latent", "cca_latent_device", "lda_classes", "planted_cca",
     "Workload", "workload", "serving_trace", "WORKLOADS",
 ]
 
@@ -66,6 +70,28 @@ def cca_latent(n: int, dx: int, dy: int, *, r: int, noise: float = 0.1,
         Y *= column_scales(dy, y_decades, inclusive_end)[None, :]
     return (np.ascontiguousarray(X, dtype=dtype),
             np.ascontiguousarray(Y, dtype=dtype))
+
+
+def cca_latent_device(n: int, dx: int, dy: int, *, r: int, noise: float = 0.1,
+                      x_decades: float = 0.0, y_decades: float = 0.0,
+                      inclusive_end: bool = True, seed: int = 0, device="cuda"):
+    """``cca_latent``'s recipe drawn on the device in FP32 (torch's
+    device generator seeded with ``seed``; a different stream from the
+    host version, same distribution)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f32 = torch.float32
+    Z = torch.randn((n, r), generator=g, device=device, dtype=f32)
+    out = []
+    for d, dec in ((dx, x_decades), (dy, y_decades)):
+        W = torch.randn((r, d), generator=g, device=device, dtype=f32)
+        A = torch.randn((n, d), generator=g, device=device, dtype=f32)
+        A.mul_(noise).addmm_(Z, W)
+        if dec:
+            A.mul_(torch.from_numpy(column_scales(d, dec, inclusive_end)).to(device=device, dtype=f32)[None, :])
+        out.append(A.contiguous())
+    return out[0], out[1]
 
 
 def haar_orthogonal(d: int, rng: np.random.Generator) -> np.ndarray:

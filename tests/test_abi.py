@@ -52,7 +52,41 @@ def test_default_options_host_only():
 def test_struct_layouts_match_library():
     import paper_2106_12060_amd as srp
     from paper_2106_12060_amd import _lib
-    a, b = ctypes.c_size_t(), ctypes.c_size_t()
-    assert srp.lib().srp_abi_sizes(ctypes.byref(a), ctypes.byref(b)) == 0
+    a, b, c, d = (ctypes.c_size_t() for _ in range(4))
+    assert srp.lib().srp_abi_sizes(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)) == 0
     assert a.value == ctypes.sizeof(_lib.SrpOptions)
     assert b.value == ctypes.sizeof(_lib.SrpInfo)
+    assert c.value == ctypes.sizeof(_lib.SrpRequest)
+    assert d.value == ctypes.sizeof(_lib.SrpResult)
+
+
+def test_request_footprint_host_only():
+    """srp_request_footprint is host arithmetic: the solve workspace plus the
+    staged copies, 0 for invalid sizes."""
+    import paper_2106_12060_amd as srp
+    from paper_2106_12060_amd import _lib
+    L = srp.lib()
+    req = _lib.SrpRequest()
+    req.problem, req.n, req.dx, req.dy, req.k, req.sketch_size = srp.SRP_PROBLEM_CCA, 50000, 300, 200, 8, 1200
+    req.lambda_x = req.lambda_y = 1e-3
+    req.dtype = srp.SRP_F32
+    srp.lib().srp_default_options(ctypes.byref(req.opt))
+    ws = L.srp_cca_workspace_bytes(50000, 300, 200, 8, 1200, srp.SRP_F32, srp.SRP_COUNTSKETCH, srp.SRP_F32)
+    assert ws > 0
+    req.stage = srp.SRP_STAGE_NONE
+    assert L.srp_request_footprint(ctypes.byref(req)) == ws
+    req.stage = srp.SRP_STAGE_BF16
+    f1 = L.srp_request_footprint(ctypes.byref(req))
+    def al(b):   # the library places every buffer on a 256-byte boundary
+        return (b + 255) // 256 * 256
+    assert f1 - ws == al(2 * 50000 * 300) + al(2 * 50000 * 200)
+    req.stage = srp.SRP_STAGE_BF16_FP8
+    f2 = L.srp_request_footprint(ctypes.byref(req))
+    ws8 = L.srp_cca_workspace_bytes(50000, 300, 200, 8, 1200, srp.SRP_F32, srp.SRP_COUNTSKETCH, srp.SRP_FP8E4M3)
+    assert f2 == (al(2 * 50000 * 300) + al(2 * 50000 * 200) + al(50000 * 300) + al(50000 * 200)
+                  + al(8 * 300) + al(8 * 200) + ws8)
+    req.sketch_size = 100   # smaller than max(dx, dy)
+    assert L.srp_request_footprint(ctypes.byref(req)) == 0
+    assert L.srp_cca_workspace_bytes(50000, 300, 200, 8, 100, srp.SRP_F32, 0, srp.SRP_F32) == 0
+    assert L.srp_lda_workspace_bytes(50000, 300, 10, 9, 1200, srp.SRP_F32, 0) > 0
+    assert L.srp_lda_workspace_bytes(50000, 300, 10, 10, 1200, srp.SRP_F32, 0) == 0

@@ -1,0 +1,206 @@
+"""Serving engine (srp_engine_*, through the C ABI): each request's result
+is the same alone (synchronous cca_solve / lda_solve) and in a mix of
+concurrently running solves, within the FP32-path tolerance, and matches
+the FP64 oracle; admission follows the memory footprint; the error paths
+report their status."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, metrics
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda"
+GiB = 1 << 30
+
+
+def _srp():
+    import paper_2106_12060_amd as srp
+    return srp
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+# Mixed sizes in the serving recipe (two latent-factor views, X columns
+# scaled over three decades, lambda = 1e-3, CountSketch s = 4 max(dx, dy)),
+# scaled down so that the oracle solves each in well under a second.
+MIX = [  # (n, dx, dy, k, seed)
+    (6000, 48, 40, 4, 1), (20000, 120, 96, 8, 2), (3000, 30, 64, 3, 3),
+    (12000, 200, 150, 12, 4), (8000, 64, 64, 6, 5), (16000, 90, 160, 16, 6),
+]
+LAM = 1e-3
+
+
+def make(n, dx, dy, seed):
+    return synth.cca_latent(n, dx, dy, r=8, noise=0.1, x_decades=3.0, seed=seed, dtype=np.float32)
+
+
+def opts(srp, **kw):
+    base = dict(warm_start_iters=40, max_iter=1000)
+    base.update(kw)
+    return srp.srp_default_options(**base)
+
+
+def objective_error(U, V, X, Y, sig_true):
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    err = metrics.cca_rel_objective_error(Uh, Vh, X64, Y64, LAM, LAM, sig_true)
+    cons = max(metrics.constraint_residual(Uh, X64, LAM), metrics.constraint_residual(Vh, Y64, LAM))
+    return err, cons
+
+
+def test_alone_and_in_the_mix_agree():
+    srp = _srp()
+    data = [make(n, dx, dy, seed) for n, dx, dy, _, seed in MIX]
+    dev_data = [(dev(X), dev(Y)) for X, Y in data]
+    alone = []
+    for (n, dx, dy, k, _), (Xd, Yd) in zip(MIX, dev_data):
+        s = 4 * max(dx, dy)
+        alone.append(srp.cca_solve(Xd, Yd, k, LAM, LAM, s, tol=1e-6, options=opts(srp), mu=[1.0] * k))
+    with srp.Engine(4 * GiB, max_slots=3) as eng:
+        tickets = [eng.submit_cca(Xd, Yd, k, LAM, LAM, 4 * max(dx, dy), tol=1e-6, options=opts(srp), mu=[1.0] * k)
+                   for (n, dx, dy, k, _), (Xd, Yd) in zip(MIX, dev_data)]
+        mixed = [eng.wait(t) for t in tickets]
+        st = eng.stats()
+    print("engine stats", st)
+    assert st["peak_running"] >= 2, "admitted solves should overlap"
+    assert st["queued"] == 0 and st["running"] == 0 and st["pool_used"] == 0
+    for (n, dx, dy, k, _), (X, Y), a, m in zip(MIX, data, alone, mixed):
+        sig_true, _, _ = direct.cca_direct(X, Y, LAM, LAM)
+        Ua, Va, sa, ia = a
+        Um, Vm, sm, rec = m
+        ea, ca = objective_error(Ua, Va, X, Y, sig_true)
+        em, cm = objective_error(Um, Vm, X, Y, sig_true)
+        print(f"n={n} dx={dx} dy={dy} k={k}: alone err={ea:.2e} cons={ca:.1e} it={ia['iterations']}; "
+              f"mix err={em:.2e} cons={cm:.1e} it={rec['info']['iterations']} slot={rec['slot']} "
+              f"latency={rec['t_done_ms'] - rec['t_submit_ms']:.1f} ms")
+        assert rec["status"] in (srp.SRP_OK, srp.SRP_ENOCONV)
+        assert ea < 1e-6 and em < 1e-6
+        assert ca < 1e-6 and cm < 1e-6
+        # same result alone and in the mix
+        sa_h, sm_h = sa.cpu().numpy(), sm.cpu().numpy()
+        assert abs(sa_h.sum() - sm_h.sum()) <= 1e-6 * sa_h.sum()
+        np.testing.assert_allclose(sm_h, sa_h, rtol=0, atol=1e-6)
+        assert rec["t_submit_ms"] <= rec["t_start_ms"] <= rec["t_done_ms"]
+
+
+def test_admission_by_footprint_serialises_when_memory_is_short():
+    """A pool that holds one request at a time admits them one by one, in
+    order, and every result is still right."""
+    srp = _srp()
+    sizes = [(8000, 64, 64, 6, seed) for seed in (5, 7, 9)]   # equal footprints
+    data = [make(n, dx, dy, seed) for n, dx, dy, _, seed in sizes]
+    dev_data = [(dev(X), dev(Y)) for X, Y in data]
+    probe = srp.Engine(1 * GiB, max_slots=1)
+    fps = []
+    for (n, dx, dy, k, _), (Xd, Yd) in zip(sizes, dev_data):
+        req, _ = probe.cca_request(Xd, Yd, k, LAM, LAM, 4 * max(dx, dy), options=opts(srp))
+        fps.append(probe.footprint(req))
+    probe.close()
+    assert len(set(fps)) == 1
+    budget = fps[0] + fps[0] // 2          # never two at once
+    with srp.Engine(budget, max_slots=3) as eng:
+        tickets = [eng.submit_cca(Xd, Yd, k, LAM, LAM, 4 * max(dx, dy), tol=1e-6, options=opts(srp), mu=[1.0] * k)
+                   for (n, dx, dy, k, _), (Xd, Yd) in zip(sizes, dev_data)]
+        res = [eng.wait(t) for t in tickets]
+        st = eng.stats()
+    print("footprints", fps, "budget", budget, "stats", st)
+    assert st["pool_peak"] <= budget
+    assert st["peak_running"] == 1
+    starts = [r[3]["t_start_ms"] for r in res]
+    assert starts == sorted(starts), "FIFO admission"
+    for (n, dx, dy, k, _), (X, Y), (U, V, s, rec) in zip(sizes, data, res):
+        sig_true, _, _ = direct.cca_direct(X, Y, LAM, LAM)
+        err, cons = objective_error(U, V, X, Y, sig_true)
+        assert err < 1e-6 and cons < 1e-6
+
+
+def test_staged_bf16_fp8_request_refines_to_fp32_tolerance():
+    """SRP_STAGE_BF16_FP8: the engine writes BF16 and FP8 copies into its
+    pool, sketches the FP8 codes, runs the BF16 phase and refines on the
+    FP32 data; the footprint counts the copies."""
+    srp = _srp()
+    n, dx, dy, k, seed = 20000, 120, 96, 8, 11
+    X, Y = make(n, dx, dy, seed)
+    Xd, Yd = dev(X), dev(Y)
+    s = 4 * max(dx, dy)
+    with srp.Engine(2 * GiB, max_slots=2) as eng:
+        r0, _ = eng.cca_request(Xd, Yd, k, LAM, LAM, s, options=opts(srp))
+        r1, _ = eng.cca_request(Xd, Yd, k, LAM, LAM, s, options=opts(srp), stage=srp.SRP_STAGE_BF16)
+        r2, _ = eng.cca_request(Xd, Yd, k, LAM, LAM, s, options=opts(srp), stage=srp.SRP_STAGE_BF16_FP8)
+        f0, f1, f2 = eng.footprint(r0), eng.footprint(r1), eng.footprint(r2)
+        assert f0 > 0
+        assert f1 - f0 >= 2 * n * (dx + dy)
+        assert f2 - f1 >= n * (dx + dy)
+        t = eng.submit_cca(Xd, Yd, k, LAM, LAM, s, tol=1e-6, options=opts(srp), mu=[1.0] * k,
+                           stage=srp.SRP_STAGE_BF16_FP8)
+        U, V, sig, rec = eng.wait(t)
+    print("staged", rec)
+    assert rec["footprint_bytes"] == f2
+    assert rec["info"]["lowp_iterations"] >= 1
+    sig_true, _, _ = direct.cca_direct(X, Y, LAM, LAM)
+    err, cons = objective_error(U, V, X, Y, sig_true)
+    assert err < 1e-6 and cons < 1e-6
+
+
+def test_lda_and_cca_requests_share_the_engine():
+    srp = _srp()
+    wl = synth.workload("lda-f32").scaled(n=8000, dx=100, s=400)
+    Xl, yl = wl.generate()
+    laml = wl.lam_value
+    X, Y = make(6000, 48, 40, 21)
+    with srp.Engine(2 * GiB, max_slots=2) as eng:
+        tl = eng.submit_lda(dev(Xl), dev(yl.astype(np.int32)), wl.c, 5, laml, wl.s, tol=1e-6,
+                            options=opts(srp), mu=[1.0] * 5)
+        tc = eng.submit_cca(dev(X), dev(Y), 4, LAM, LAM, 160, tol=1e-6, options=opts(srp), mu=[1.0] * 4)
+        # poll until done (poll never blocks)
+        out = {}
+        import time
+        t0 = time.time()
+        while len(out) < 2 and time.time() - t0 < 60:
+            for t in (tl, tc):
+                if t not in out:
+                    r = eng.poll(t)
+                    if r is not None:
+                        out[t] = r
+            time.sleep(0.002)
+    assert len(out) == 2
+    W, rho, rec = out[tl]
+    rho_true, _ = direct.lda_direct(Xl, yl, wl.c, laml, k=5)
+    _, _, _, Xh, Yh = direct.lda_scatter(Xl, yl, wl.c)
+    err = metrics.lda_rel_objective_error(W.cpu().numpy(), Xh, Yh, laml, rho_true)
+    print("lda in engine", rec["info"]["iterations"], err)
+    assert err < 1e-6
+    U, V, sig, rec = out[tc]
+    sig_true, _, _ = direct.cca_direct(X, Y, LAM, LAM)
+    err, cons = objective_error(U, V, X, Y, sig_true)
+    assert err < 1e-6 and cons < 1e-6
+
+
+def test_engine_rejects_and_reports():
+    srp = _srp()
+    X, Y = make(4000, 40, 40, 31)
+    Xd, Yd = dev(X), dev(Y)
+    with srp.Engine(1 << 20, max_slots=1) as eng:   # 1 MiB pool: too small for anything real
+        with pytest.raises(srp.SrpError) as ei:
+            eng.submit_cca(Xd, Yd, 4, LAM, LAM, 160, options=opts(srp))
+        assert ei.value.code == srp.SRP_EREJECTED
+        with pytest.raises(srp.SrpError) as ei:
+            eng.submit_cca(Xd, Yd, 4, LAM, LAM, 20, options=opts(srp))   # sketch smaller than d
+        assert ei.value.code == srp.SRP_EINVAL
+    with srp.Engine(1 * GiB, max_slots=1) as eng:
+        # accepted, but the solve itself rejects k > min(dx, dy): the
+        # status and message come back through wait
+        t = eng.submit_cca(Xd, Yd, 41, LAM, LAM, 160, options=opts(srp))
+        with pytest.raises(srp.SrpError) as ei:
+            eng.wait(t)
+        assert ei.value.code == srp.SRP_EINVAL
+        with pytest.raises(srp.SrpError) as ei:
+            eng.poll(t + 100)   # unknown ticket
+        assert ei.value.code == srp.SRP_EINVAL
+    with pytest.raises(srp.SrpError):
+        srp.Engine(1 << 20, max_slots=0)

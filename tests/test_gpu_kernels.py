@@ -130,8 +130,12 @@ def test_sketch_factor_reports_not_spd():
                                                (3333, 2000, 0, 19, "f32", "f32"), (1500, 90, 60, 5, "bf16", "f32"),
                                                (1003, 1000, 0, 10, "f32", "f32"), (777, 260, 516, 16, "f32", "f32"),
                                                (130, 66, 70, 3, "f32", "f32"), (5, 64, 0, 4, "f32", "f32"),
-                                               (40001, 2000, 0, 12, "f32", "f32")])
+                                               (40001, 2000, 0, 12, "f32", "f32"),
+                                               (3000, 120, 96, 8, "bf16", "bf16"), (999, 40, 0, 5, "bf16", "bf16")])
 def test_gram_pass_matches_products(n, d0, d1, k, dt, comp):
+    """Fused pass against the FP64 products of the same (quantised) data.
+    compute="bf16" on views narrower than the matrix-core pass's row chunk
+    runs the FP32-arithmetic pass on the BF16 data, hence the FP32 bound."""
     srp = _srp()
     rng = np.random.default_rng(n + d0)
     A0, A0q = quantised(rand_data(n, d0, n), dt)

@@ -246,3 +246,18 @@ def test_cca_staged_sketch_inputs(fmt):
     err, cons = cca_errors(U, V, X.astype(np.float64), Y.astype(np.float64), lam, sig_true)
     print(fmt, info, err, cons)
     assert err < 1e-6 and cons < 1e-6
+
+
+def test_cca_views_whose_factor_splits_differ():
+    """dx = 383 (6 tiles of 64) and dy = 399 (7 tiles): the narrower view's
+    Gram takes the deeper split-K and the larger factor scratch, so each
+    view's scratch must cover the larger need of the two."""
+    srp = _srp()
+    X, Y = synth.cca_latent(3000, 383, 399, r=8, noise=0.1, x_decades=3.0, seed=97)
+    lam = 1e-3
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    U, V, sig, info = srp.cca_solve(dev(X, torch.float32), dev(Y, torch.float32), 2, lam, lam, 1596, tol=1e-6,
+                                    options=srp.srp_default_options(max_iter=1000), mu=[1.0, 1.0])
+    err, cons = cca_errors(U, V, X, Y, lam, sig_true)
+    print("split views", info["iterations"], err, cons)
+    assert err < 1e-6 and cons < 1e-6
