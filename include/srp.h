@@ -119,11 +119,16 @@ typedef struct srp_info {
   double ms_iterate;
   double ms_total;
   double pass_ms;         /* summed duration of the timed fused passes       */
-  int pass_launches;      /* number of timed fused passes                    */
+  int pass_launches;      /* timed passes that did the work: a pass launched
+                             in the iterations that follow convergence (the
+                             host polls every check_every) returns at once;
+                             its few microseconds stay in pass_ms, so
+                             pass_ms / pass_launches slightly overstates the
+                             duration of a working pass                      */
   int lowp_iterations;    /* iterations of the BF16 phase                    */
   double ms_lowp;         /* wall ms of the BF16 phase (inside ms_iterate)   */
   double lowp_pass_ms;    /* summed duration of its timed BF16 passes         */
-  int lowp_pass_launches;
+  int lowp_pass_launches; /* BF16 passes that did the work (as above)       */
   int lowp_status;        /* how the BF16 phase ended: SRP_OK, SRP_ENOCONV
                              (its cap) or SRP_ENOTSPD (a retraction Gram from
                              BF16 products was not positive definite; the

@@ -195,10 +195,18 @@ struct RcgBuffers {
   double* mu;
   char* pass_ws;
   size_t pass_ws_bytes;
-  // optional timing of the fused passes over the full data
+  // optional timing of the fused passes over the full data; *ran counts
+  // the timed launches that did the work (a launch that finds the
+  // converged flag set returns at once)
   bool time_passes = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr;
+  int* ran_all = nullptr;   // two counters: main passes, BF16-phase passes
+  int* ran = nullptr;
 };
+
+__global__ void k_count_pass(const int* __restrict__ done, int* __restrict__ ran) {
+  if (!(done && *done)) ++*ran;
+}
 
 static size_t kk_bytes() { return bytes_of<double>((size_t)(2 * KK_NSLOTS + 9) * KK_STRIDE); }
 
@@ -223,7 +231,7 @@ static size_t rcg_buffers_bytes(int nb, int k, int64_t nmax, const int* d, int d
     b += 6 * bytes_of<double>(dk) + bytes_of<double>((size_t)d[s] * nb * k) + 2 * bytes_of<double>(2 * dk);
   }
   b += bytes_of<SolverCtrl>(1) + kk_bytes() + partial_bytes(k, std::max(d[0], nb == 2 ? d[1] : 0)) +
-       bytes_of<double>(KMAX);
+       bytes_of<double>(KMAX) + bytes_of<int>(2);
   const size_t pw = std::max(pass_ws_bytes(nmax, d[0], nb == 2 ? d[1] : 0, k, SRP_F64),
                              pass_ws_bytes(nmax, d[0], nb == 2 ? d[1] : 0, k, SRP_F32));
   b += (pw + 255) & ~size_t(255);
@@ -259,13 +267,15 @@ static int rcg_buffers_take(RcgBuffers& B, Arena& ar, int nb, int k, int64_t nma
   B.kk = (double*)ar.take<char>(kk_bytes());
   B.part = (double*)ar.take<char>(partial_bytes(k, std::max(d[0], nb == 2 ? d[1] : 0)));
   B.mu = ar.take<double>(KMAX);
+  B.ran_all = ar.take<int>(2);
   B.pass_ws_bytes = std::max(pass_ws_bytes(nmax, d[0], nb == 2 ? d[1] : 0, k, SRP_F64),
                              pass_ws_bytes(nmax, d[0], nb == 2 ? d[1] : 0, k, SRP_F32));
   B.pass_ws = ar.take<char>(B.pass_ws_bytes);
   B.ksplit = twopass_ksplit(nmax);
   B.Pn = ar.take<double>((size_t)nmax * nb * k);
   B.parts = ar.take<double>((size_t)B.ksplit * std::max(d[0], nb == 2 ? d[1] : 0) * nb * k);
-  if (!B.ctrl || !B.kk || !B.part || !B.mu || !B.pass_ws || !B.Pn || !B.parts || !B.skw || !B.Tc) return SRP_ENOMEM;
+  if (!B.ctrl || !B.kk || !B.part || !B.mu || !B.pass_ws || !B.Pn || !B.parts || !B.skw || !B.Tc || !B.ran_all)
+    return SRP_ENOMEM;
   return SRP_OK;
 }
 
@@ -344,7 +354,13 @@ static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int c
     }
     SRP_TRY(gram_pass_run(P.A[0], P.nb == 2 ? P.A[1] : nullptr, P.dtype, compute, P.n, P.d[0], P.d[1], P.k, W[0],
                           P.nb == 2 ? W[1] : nullptr, B.J[0], P.nb == 2 ? B.J[1] : nullptr, done, pw, st, e0, e1));
-    if (e0) B.events->push_back({e0, e1});
+    if (e0) {
+      B.events->push_back({e0, e1});
+      if (B.ran) {
+        hipLaunchKernelGGL(k_count_pass, dim3(1), dim3(1), 0, st, done, B.ran);
+        SRP_LAUNCH_CHECK();
+      }
+    }
   }
   if (P.lda_cost) {   // S_B W = Yhat^T (Yhat W): c-row factor instead of the d x d matrix
     SRP_TRY(gemm_skinny_f64(P.c, P.d[0], P.k, P.Yhat, P.d[0], false, W[0], P.k, B.Tc, P.k, B.skw, B.skw_bytes, st));
@@ -493,6 +509,7 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
     start[1] = nb == 2 ? outW[1] : nullptr;
   }
   const double ms_warm = tm.lap_ms();
+  if (ca.opt.time_passes) SRP_TRY(fill_i32(B.ran_all, 2, 0, st));
   // low-precision phase (CCA): BF16 data, BF16 matrix-core passes
   int lowp_iters = 0, lowp_status = SRP_OK;
   double ms_lowp = 0.0;
@@ -505,6 +522,7 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
     }
     B.time_passes = ca.opt.time_passes != 0;
     B.events = &lowp_events;
+    B.ran = B.ran_all + 1;
     RcgProblem lp = full;
     lp.A[0] = ca.opt.lowp_x;
     lp.A[1] = ca.opt.lowp_y;
@@ -515,6 +533,7 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
                     std::max(1, ca.opt.check_every), ca.opt.refresh_every, false, false, nullptr, rl, st));
     B.time_passes = false;
     B.events = nullptr;
+    B.ran = nullptr;
     lowp_status = rl.status;
     // A retraction Gram from BF16 products can lose definiteness when the
     // data's columns span many decades (the products' rounding is relative
@@ -533,6 +552,7 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   B.time_passes = ca.opt.time_passes != 0;
   B.events = &events;
+  B.ran = B.ran_all;
   // final_f64 > 0 with lower-precision passes: close with that many
   // iterations whose data products run in FP64 arithmetic, from the point
   // the FP32 (or BF16) iteration reached; the finishing pass is FP64 too.
@@ -565,6 +585,12 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
   }
   B.time_passes = false;
   B.events = nullptr;
+  B.ran = nullptr;
+  int ran_h[2] = {0, 0};
+  if (ca.opt.time_passes) {
+    SRP_HIP(hipMemcpyAsync(ran_h, B.ran_all, sizeof(ran_h), hipMemcpyDeviceToHost, st));
+    SRP_HIP(hipStreamSynchronize(st));
+  }
   double lowp_pass_ms = 0.0;
   for (auto& e : lowp_events) {
     float ms = 0.f;
@@ -574,9 +600,9 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
   }
   if (info) {
     info->lowp_pass_ms = lowp_pass_ms;
-    info->lowp_pass_launches = (int)lowp_events.size();
+    info->lowp_pass_launches = ran_h[1];
     info->pass_ms = pass_ms;
-    info->pass_launches = (int)events.size();
+    info->pass_launches = ran_h[0];
     info->status = r.status;
     info->iterations = r.iterations;
     info->warm_iterations = warm_iters;

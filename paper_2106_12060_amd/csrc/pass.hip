@@ -332,12 +332,18 @@ __global__ void __launch_bounds__(kPassThreads) k_pass(const DT* __restrict__ A0
 // floats of one row; the last chunk of each block is shifted back to end
 // on the block's last tile (it rewrites identical values), so no chunk
 // spills into the other block's columns.  The row pitch is 4 mod 32 floats
-// (bank-conflict free for both operand patterns).  P tiles use MFMA rows
-// 0-7 only (rows 8-15 repeat them).
+// (bank-conflict free for both operand patterns).  The 16 MFMA rows of the
+// P products hold the block's 8 rows twice: rows 0-7 accumulate A_0 W_0 and
+// rows 8-15 A_1 W_1 (each lane zeroes the operand of the other view), so
+// one accumulator serves both views and the tile loop has no view branch.
 constexpr int kDmaRows = 8;
 constexpr int kDmaWaves = 8;
 constexpr int kDmaThreads = 64 * kDmaWaves;
 constexpr int kDmaMaxTiles = 128;   // 2048 columns of [A_0 | A_1]
+// The FP32 pass runs 16 waves (4 per SIMD, 128 registers each): a wave
+// holds the direction operands and the J accumulators of at most 8 tiles.
+constexpr int kF32Waves = 16;
+constexpr int kF32Threads = 64 * kF32Waves;
 
 __device__ __forceinline__ void lds_only_barrier() {
   // LDS traffic of this wave done, then the workgroup barrier; in-flight
@@ -355,8 +361,8 @@ __device__ __forceinline__ void dma_row_chunk(__amdgpu_buffer_rsrc_t r, float* l
 
 __host__ __device__ constexpr int dma_pitch(int TT) { return ((TT * 16 + 31) / 32) * 32 + 4; }
 
-template <int NB, int KT, int VEC>
-__global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restrict__ A0, const float* __restrict__ A1,
+template <int NB, int TPB, int VEC>
+__global__ void __launch_bounds__(kF32Threads) k_pass_dma(const float* __restrict__ A0, const float* __restrict__ A1,
                                                           int64_t n, int d0, int d1, int k,
                                                           const float* __restrict__ Wp0,
                                                           const float* __restrict__ Wp1, int nrb,
@@ -364,9 +370,7 @@ __global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restric
   if (done && *done) return;
   constexpr int R = kDmaRows;
   constexpr int CH = 64 * VEC;
-  constexpr int NT = NB * KT;
-  constexpr int KP = KT * 16;
-  constexpr int TPB = (kDmaMaxTiles + kDmaWaves - 1) / kDmaWaves;
+  constexpr int NT = NB;                                        // [P_0 | P_1] tiles of the J phase
   using acc_t = f32x4;
   extern __shared__ float dsm[];
   const int T0 = (d0 + 15) >> 4;
@@ -374,56 +378,72 @@ __global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restric
   const int TT = T0 + T1;
   const int nch0 = (T0 * 16 + CH - 1) / CH, nch1 = NB == 2 ? (T1 * 16 + CH - 1) / CH : 0;
   const int nch = nch0 + nch1;
-  const int pitch = dma_pitch(TT);
-  float* red = dsm + 2 * R * pitch;              // [waves][NT][R x 16]
-  float* pfull = red + kDmaWaves * NT * R * 16;  // [NT][R][17]
+  const int pitch = dma_pitch(kF32Waves * TPB);
+  float* red = dsm + 2 * R * pitch;              // [waves][16 x 16]
+  float* pfull = red + kF32Waves * 256;          // [NB][R][17]
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, l16 = lane & 15;
-  const __amdgpu_buffer_rsrc_t wr0 = make_rsrc(Wp0, (int64_t)T0 * 16 * KP * 4);
-  const __amdgpu_buffer_rsrc_t wr1 = make_rsrc(NB == 2 ? Wp1 : Wp0, (int64_t)(NB == 2 ? T1 : T0) * 16 * KP * 4);
-  const int wvoff = (g * KP + l16) * 4;
+  const __amdgpu_buffer_rsrc_t wr0 = make_rsrc(Wp0, (int64_t)T0 * 16 * 16 * 4);
+  const __amdgpu_buffer_rsrc_t wr1 = make_rsrc(NB == 2 ? Wp1 : Wp0, (int64_t)(NB == 2 ? T1 : T0) * 16 * 16 * 4);
+  const int wvoff = (g * 16 + l16) * 4;
 
-  float wreg[TPB][4][KT];
+  // Slot i of wave w is tile t = w + 16 i (TPB >= the tiles / 16); slots past
+  // the last tile have a zero direction operand and read zero LDS columns,
+  // so every wave runs the same branch-free instruction stream.  keep[i]
+  // zeroes, in the P products, the lanes of MFMA rows that belong to the
+  // other view (rows 0-7: A_0, rows 8-15: A_1).
+  float wreg[TPB][4];
+  float keep[TPB];
   acc_t acc[TPB][NT];
 #pragma unroll
   for (int i = 0; i < TPB; ++i) {
-    const int t = w + kDmaWaves * i;
+    const int t = w + kF32Waves * i;
     const bool b1 = (NB == 2) && (t >= T0);
+    keep[i] = (NB == 1 || (l16 >> 3) == (int)b1) ? 1.f : 0.f;
     const int ct = b1 ? t - T0 : t;
 #pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-      for (int kt = 0; kt < KT; ++kt) {
-        const int soff = ((ct * 16 + 4 * s2) * KP + kt * 16) * 4;
-        float v = 0.f;
-        if (t < TT) v = b1 ? buf_load<float>(wr1, wvoff + soff, 0) : buf_load<float>(wr0, wvoff + soff, 0);
-        wreg[i][s2][kt] = v;
-      }
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int soff = (ct * 16 + 4 * s2) * 16 * 4;
+      float v = 0.f;
+      if (t < TT) v = b1 ? buf_load<float>(wr1, wvoff + soff, 0) : buf_load<float>(wr0, wvoff + soff, 0);
+      wreg[i][s2] = v;
+    }
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
   }
+  // The columns of the slots past the last tile are never loaded: zero both
+  // row buffers once.
+  for (int e = tid; e < 2 * R * pitch; e += kF32Threads) dsm[e] = 0.f;
+  __syncthreads();
 
-  // Issue the loads of row block rbk into buffer xb: instruction q covers
-  // row q / nch, chunk q % nch; waves take instructions round-robin.
+  // Loads of row block rbk into buffer xb: wave w moves chunks j = w, w + 16,
+  // ... of every row.  One buffer resource per view and block; rows past n
+  // lie past its num_records and read as zero.  A chunk's tail past the
+  // view's last column reads the next row's leading values (finite; they
+  // meet zero direction rows in P and land in J rows that are not stored).
   auto issue_block = [&](int rbk, float* xb) __attribute__((always_inline)) {
-    const int nq = R * nch;
-    for (int q = w; q < nq; q += kDmaWaves) {
-      const int r = q / nch, j = q - r * nch;
-      const int64_t row = (int64_t)rbk * R + r;
+    const int64_t row0 = (int64_t)rbk * R;
+    const int rows = (int)(n - row0 < R ? n - row0 : R);
+    const __amdgpu_buffer_rsrc_t r0 = make_rsrc(A0 + row0 * d0, (int64_t)rows * d0 * 4);
+    const __amdgpu_buffer_rsrc_t r1 =
+        NB == 2 ? make_rsrc(A1 + row0 * d1, (int64_t)rows * d1 * 4) : r0;
+    for (int j = w; j < nch; j += kF32Waves) {
       const bool s1 = (NB == 2) && (j >= nch0);
       const int jj = s1 ? j - nch0 : j;
       const int span = (s1 ? T1 : T0) * 16;
       const int o = min(jj * CH, span - CH);
-      float* dst = xb + r * pitch + (s1 ? T0 * 16 : 0) + o;
-      const int voff = (o + lane * VEC) * 4;
-      if (s1) dma_row_chunk<VEC>(make_rsrc(A1 + row * d1, row < n ? (int64_t)d1 * 4 : 0), dst, voff);
-      else dma_row_chunk<VEC>(make_rsrc(A0 + row * d0, row < n ? (int64_t)d0 * 4 : 0), dst, voff);
+      const int db4 = (s1 ? d1 : d0) * 4;
+      float* dst = xb + (s1 ? T0 * 16 : 0) + o;
+      const int vbase = (o + lane * VEC) * 4;
+      const __amdgpu_buffer_rsrc_t rs = s1 ? r1 : r0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dma_row_chunk<VEC>(rs, dst + r * pitch, vbase + r * db4);
     }
   };
 
-  // per-lane operand bases (floats); tile i adds 16 (w + 8 i)
+  // per-lane operand bases (floats); slot i adds 16 (w + 16 i)
   const int base_b = (l16 & (R - 1)) * pitch + g + 16 * w;   // P phase: row l16 mod 8, column 4 s2 + g
   const int base_d = g * pitch + l16 + 16 * w;               // J phase: row g + 4 s, column l16
   const int pf_b = g * 17 + l16;                              // pfull row g + 4 s (as the J-phase A operand)
@@ -432,52 +452,37 @@ __global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restric
   int boff = 0;   // float offset of the current buffer
   if (rb < nrb) issue_block(rb, dsm);
   for (; rb < nrb; rb += gridDim.x) {
-    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the block (and W) have landed
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the block have landed
     __syncthreads();                 // ... and every wave's; the other buffer is free
     const float* xs = dsm + boff;
     if (rb + (int)gridDim.x < nrb) issue_block(rb + gridDim.x, dsm + (R * pitch - boff));
-    // (b) P_b partials over this wave's tiles
-    acc_t pacc[NB][KT];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int kt = 0; kt < KT; ++kt) pacc[b][kt] = acc_t{0, 0, 0, 0};
+    // (b) P partials over this wave's slots.  Both views share one
+    // accumulator: MFMA rows 0-7 take A_0 W_0 (the lanes of rows 8-15 read
+    // zero on A_0 tiles) and rows 8-15 take A_1 W_1; two accumulators
+    // alternate to break the dependence chain.
+    acc_t pacc[2] = {acc_t{0, 0, 0, 0}, acc_t{0, 0, 0, 0}};
 #pragma unroll
     for (int i = 0; i < TPB; ++i) {
-      const int t = w + kDmaWaves * i;
-      if (t < TT) {
-        const bool b1 = (NB == 2) && (t >= T0);
 #pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) {
-          const float a = xs[base_b + 16 * kDmaWaves * i + 4 * s2];
-#pragma unroll
-          for (int kt = 0; kt < KT; ++kt) {
-            if (b1) pacc[NB - 1][kt] = mfma16x16x4(a, wreg[i][s2][kt], pacc[NB - 1][kt]);
-            else pacc[0][kt] = mfma16x16x4(a, wreg[i][s2][kt], pacc[0][kt]);
-          }
-        }
+      for (int s2 = 0; s2 < 4; ++s2) {
+        float a = xs[base_b + 16 * kF32Waves * i + 4 * s2];
+        if (NB == 2) a *= keep[i];
+        pacc[i & 1] = mfma16x16x4(a, wreg[i][s2], pacc[i & 1]);
       }
     }
-    // (c) reduce P over waves (MFMA rows 0-7 live in lanes 0-31)
-    if (lane < 32) {
+    // (c) sum P over the waves
 #pragma unroll
-      for (int b = 0; b < NB; ++b)
-#pragma unroll
-        for (int kt = 0; kt < KT; ++kt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            red[(w * NT + b * KT + kt) * (R * 16) + (4 * g + r) * 16 + l16] = pacc[b][kt][r];
-    }
+    for (int r = 0; r < 4; ++r) red[w * 256 + (4 * g + r) * 16 + l16] = pacc[0][r] + pacc[1][r];
     lds_only_barrier();
-    for (int e = tid; e < NT * R * 16; e += kDmaThreads) {
-      const int nt = e / (R * 16), q = e - nt * (R * 16);
+    if (tid < NB * R * 16) {
       float v = 0.f;
 #pragma unroll
-      for (int ww = 0; ww < kDmaWaves; ++ww) v += red[(ww * NT + nt) * (R * 16) + q];
-      pfull[nt * (R * 17) + (q >> 4) * 17 + (q & 15)] = v;
+      for (int ww = 0; ww < kF32Waves; ++ww) v += red[ww * 256 + tid];
+      const int row = tid >> 4, col = tid & 15;
+      pfull[(row >> 3) * (R * 17) + (row & 7) * 17 + col] = v;
     }
     lds_only_barrier();
-    // (d) A_b^T [P_0 | P_1] for this wave's tiles
+    // (d) A_b^T [P_0 | P_1] for this wave's slots
     float pb[R / 4][NT];
 #pragma unroll
     for (int s = 0; s < R / 4; ++s)
@@ -485,14 +490,11 @@ __global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restric
       for (int nt = 0; nt < NT; ++nt) pb[s][nt] = pfull[nt * (R * 17) + pf_b + 4 * s * 17];
 #pragma unroll
     for (int i = 0; i < TPB; ++i) {
-      const int t = w + kDmaWaves * i;
-      if (t < TT) {
 #pragma unroll
-        for (int s = 0; s < R / 4; ++s) {
-          const float a = xs[base_d + 4 * s * pitch + 16 * kDmaWaves * i];
+      for (int s = 0; s < R / 4; ++s) {
+        const float a = xs[base_d + 4 * s * pitch + 16 * kF32Waves * i];
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mfma16x16x4(a, pb[s][nt], acc[i][nt]);
-        }
+        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = mfma16x16x4(a, pb[s][nt], acc[i][nt]);
       }
     }
     boff = R * pitch - boff;
@@ -503,7 +505,7 @@ __global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restric
   float* out = partial + (int64_t)blockIdx.x * D * W_out;
 #pragma unroll
   for (int i = 0; i < TPB; ++i) {
-    const int t = w + kDmaWaves * i;
+    const int t = w + kF32Waves * i;
     if (t < TT) {
       const bool b1 = (NB == 2) && (t >= T0);
       const int db = b1 ? d1 : d0;
@@ -511,13 +513,12 @@ __global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restric
       const int rowbase = b1 ? d0 : 0;
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const int bsrc = nt / KT, kt = nt % KT;
-        const int col = kt * 16 + l16;
+        const int col = l16;
         if (col < k) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int c = ct * 16 + acc_row<float>(lane, r);
-            if (c < db) out[(int64_t)(rowbase + c) * W_out + bsrc * k + col] = acc[i][nt][r];
+            if (c < db) out[(int64_t)(rowbase + c) * W_out + nt * k + col] = acc[i][nt][r];
           }
         }
       }
@@ -525,10 +526,17 @@ __global__ void __launch_bounds__(kDmaThreads) k_pass_dma(const float* __restric
   }
 }
 
-static size_t dma_lds_bytes(int d0, int d1, int NT) {
+// Tile slots per wave: the smallest instance (2, 4, 6 or 8) covering
+// the tiles of [A_0 | A_1].
+static int dma_slots(int d0, int d1) {
   const int TT = (d0 + 15) / 16 + (d1 > 0 ? (d1 + 15) / 16 : 0);
-  const size_t pitch = (size_t)dma_pitch(TT);
-  return (2 * kDmaRows * pitch + (size_t)kDmaWaves * NT * kDmaRows * 16 + (size_t)NT * kDmaRows * 17) * sizeof(float);
+  const int need = (TT + kF32Waves - 1) / kF32Waves;
+  return need <= 2 ? 2 : need <= 4 ? 4 : need <= 6 ? 6 : 8;
+}
+
+static size_t dma_lds_bytes(int d0, int d1, int NT) {
+  const size_t pitch = (size_t)dma_pitch(kF32Waves * dma_slots(d0, d1));
+  return (2 * kDmaRows * pitch + (size_t)kF32Waves * 256 + (size_t)NT * kDmaRows * 17) * sizeof(float);
 }
 
 // 16-byte loads need rows that start on 16-byte boundaries and blocks of
@@ -939,12 +947,12 @@ static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, in
   return SRP_OK;
 }
 
-template <int NB, int KT, int VEC>
+template <int NB, int TPB, int VEC>
 static int pass_launch_dma(const float* A0, const float* A1, int64_t n, int d0, int d1, int k, const double* W0,
                            const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
                            hipEvent_t before_pass, hipEvent_t after_pass) {
   const int dp0 = (d0 + 15) / 16 * 16, dp1 = NB == 2 ? (d1 + 15) / 16 * 16 : 0;
-  const int KP = KT * 16;
+  const int KP = 16;
   float* Wp0 = ws.take<float>((size_t)dp0 * KP);
   float* Wp1 = NB == 2 ? ws.take<float>((size_t)dp1 * KP) : nullptr;
   const int nrb = (int)((n + kDmaRows - 1) / kDmaRows);
@@ -954,10 +962,10 @@ static int pass_launch_dma(const float* A0, const float* A1, int64_t n, int d0, 
   float* part = ws.take<float>((size_t)grid * Dtot * NB * k);
   if (!Wp0 || !part || (NB == 2 && !Wp1)) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
   SRP_TRY(pack_dirs<float>(W0, d0, dp0, Wp0, W1, d1, dp1, Wp1, k, KP, st));
-  const size_t lds = dma_lds_bytes(d0, NB == 2 ? d1 : 0, NB * KT);
-  SRP_TRY(allow_dynamic_lds((const void*)k_pass_dma<NB, KT, VEC>, kPassLds + 8 * 1024));
+  const size_t lds = dma_lds_bytes(d0, NB == 2 ? d1 : 0, NB);
+  SRP_TRY(allow_dynamic_lds((const void*)k_pass_dma<NB, TPB, VEC>, kPassLds + 8 * 1024));
   if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
-  hipLaunchKernelGGL((k_pass_dma<NB, KT, VEC>), dim3(grid), dim3(kDmaThreads), lds, st, A0, A1, n, d0,
+  hipLaunchKernelGGL((k_pass_dma<NB, TPB, VEC>), dim3(grid), dim3(kF32Threads), lds, st, A0, A1, n, d0,
                      NB == 2 ? d1 : 0, k, Wp0, Wp1, nrb, part, done);
   SRP_LAUNCH_CHECK();
   if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
@@ -972,12 +980,20 @@ static int pass_dispatch_dma(const float* A0, const float* A1, int64_t n, int d0
                              const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
                              hipEvent_t ev0, hipEvent_t ev) {
   const int vec = dma_vec(A0, A1, d0, d1);
+  const int slots = dma_slots(d0, A1 ? d1 : 0);
+#define SRP_DMA_CASE(NB_, TPB_)                                                                             \
+  if (slots == TPB_)                                                                                        \
+    return vec == 4 ? pass_launch_dma<NB_, TPB_, 4>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev) \
+                    : pass_launch_dma<NB_, TPB_, 1>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
   if (A1) {
-    if (vec == 4) return pass_launch_dma<2, 1, 4>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
-    return pass_launch_dma<2, 1, 1>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+    SRP_DMA_CASE(2, 2) SRP_DMA_CASE(2, 4) SRP_DMA_CASE(2, 6) SRP_DMA_CASE(2, 8)
+  } else {
+    d1 = 0;
+    SRP_DMA_CASE(1, 2) SRP_DMA_CASE(1, 4) SRP_DMA_CASE(1, 6) SRP_DMA_CASE(1, 8)
   }
-  if (vec == 4) return pass_launch_dma<1, 1, 4>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
-  return pass_launch_dma<1, 1, 1>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+#undef SRP_DMA_CASE
+  set_error("gram_pass: no DMA pass instance for %d tile slots", slots);
+  return SRP_EINVAL;
 }
 
 template <class DT, class CT>
