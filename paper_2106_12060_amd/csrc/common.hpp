@@ -129,6 +129,27 @@ template <class CT> __device__ __forceinline__ int acc_row(int lane, int r);
 template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
 template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
 
+// Buffer loads: a scalar base (the row block) plus a 32-bit lane offset;
+// offsets at or past num_records read as zero, which pads the last row
+// block and masked lanes without branches.
+constexpr uint32_t kBufDword3 = 0x00020000u;   // raw buffer, gfx9 family
+constexpr int kOob = 0x40000000;                 // lane offset that always reads zero
+
+template <class T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <> __device__ __forceinline__ bf16 buf_load<bf16>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(bf16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const int nrec = (int)(bytes < 0x7ffff000ll ? bytes : 0x7ffff000ll);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, (int)kBufDword3);
+}
+
 // ------------------------------------------------------------ workspace
 // Bump allocator over one stream-ordered allocation.
 struct Arena {

@@ -200,19 +200,39 @@ __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
   f64x4 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int l0 = lbeg; l0 < lend; l0 += 32) {
+  // Operands of 32 contraction steps in registers, by buffer loads: a
+  // masked element takes an offset past the resource (it reads zero), so
+  // every load issues unconditionally and a stage's loads are in flight
+  // together; the next stage's loads overlap this stage's products.
+  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(A, (int64_t)(pr.ta ? kk : m) * lda * 8);
+  const __amdgpu_buffer_rsrc_t brsrc = make_rsrc(B, (int64_t)kk * ldb * 8);
+  double ra[8], rb[8];
+  auto fetch = [&](int l0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = tid + 256 * q;
       int rr, ll;
       if (pr.ta) { ll = e >> 6; rr = e & 63; } else { rr = e >> 5; ll = e & 31; }
       const int gr = r0 + rr, gl = l0 + ll;
-      As[ll][rr] = (gr < m && gl < lend) ? (pr.ta ? A[(int64_t)gl * lda + gr] : A[(int64_t)gr * lda + gl]) : 0.0;
+      const int oa = pr.ta ? (gl * (int)lda + gr) : (gr * (int)lda + gl);
+      ra[q] = buf_load<double>(arsrc, (gr < m && gl < lend) ? oa * 8 : kOob, 0);
       const int bl = e >> 6, bj = e & 63;
       const int gbl = l0 + bl;
-      Bs[bl][bj] = (bj < nc && gbl < lend) ? B[(int64_t)gbl * ldb + bj] : 0.0;
+      rb[q] = buf_load<double>(brsrc, (bj < nc && gbl < lend) ? (gbl * (int)ldb + bj) * 8 : kOob, 0);
+    }
+  };
+  fetch(lbeg);
+  for (int l0 = lbeg; l0 < lend; l0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + 256 * q;
+      int rr, ll;
+      if (pr.ta) { ll = e >> 6; rr = e & 63; } else { rr = e >> 5; ll = e & 31; }
+      As[ll][rr] = ra[q];
+      Bs[e >> 6][e & 63] = rb[q];
     }
     __syncthreads();
+    if (l0 + 32 < lend) fetch(l0 + 32);
 #pragma unroll
     for (int s4 = 0; s4 < 8; ++s4) {
       const int kl = 4 * s4 + (lane >> 4);
@@ -263,8 +283,10 @@ int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_
   int gx = 1, gy = 1, sx = 1;
   for (int q = 0; q < nprob; ++q) {
     const SkinnyProb& p = probs[q];
-    if (p.nc > 64 || p.nc < 1 || p.m < 1 || p.kk < 1) {
-      set_error("gemm_skinny: bad shape m=%d kk=%d nc=%d", p.m, p.kk, p.nc);
+    if (p.nc > 64 || p.nc < 1 || p.m < 1 || p.kk < 1 ||
+        (int64_t)(p.ta ? p.kk : p.m) * p.lda * 8 >= (int64_t(1) << 31) ||
+        (int64_t)p.kk * p.ldb * 8 >= (int64_t(1) << 31)) {
+      set_error("gemm_skinny: bad shape m=%d kk=%d nc=%d (operands must stay under 2 GiB)", p.m, p.kk, p.nc);
       return SRP_EINVAL;
     }
     bt.p[q] = p;

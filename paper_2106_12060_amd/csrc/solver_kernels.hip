@@ -65,48 +65,108 @@ struct PartialArgs {
 constexpr int kPartRows = 16;
 constexpr int kMaxSlices = 16;   // row-slice partials per side
 
+// One row slice of a side: the (nl k) x (nr k) products L^T R over the
+// slice's rows on FP64 matrix cores (16x16 output tiles, 4 rows per step).
+// Rows are staged 16 at a time by buffer loads, one operand block (a d x k
+// array) per step: a masked element takes an offset past the resource and
+// reads zero, so the loads issue unconditionally and a stage's loads are in
+// flight together; the next stage's loads overlap this stage's products.
 __global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
   if (a.ctrl && a.ctrl->done) return;
   const PartialSide& ps = a.side[blockIdx.y];
   const int k = a.k, z = blockIdx.x;
   const int NL = ps.nl * k, NR = ps.nr * k;
+  const int MT = (NL + 15) >> 4, NT = (NR + 15) >> 4;
   __shared__ double ls[kPartRows][2 * KMAX];
   __shared__ double rs[kPartRows][6 * KMAX];
-  constexpr int PER = (2 * KMAX * 6 * KMAX + 255) / 256;
-  double acc[PER];
+  constexpr int EL = (kPartRows * KMAX + 255) / 256;   // elements of one operand block per thread
+  constexpr int MAXT = ((2 * KMAX / 16) * (6 * KMAX / 16) + 3) / 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ntiles = MT * NT;
+  // the staged columns past NL / NR are read by the edge tiles: zero them
+  for (int e = tid; e < kPartRows * 2 * KMAX; e += 256) (&ls[0][0])[e] = 0.0;
+  for (int e = tid; e < kPartRows * 6 * KMAX; e += 256) (&rs[0][0])[e] = 0.0;
+  f64x4 acc[MAXT];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) acc[q] = 0.0;
-  const int nout = NL * NR;
-  for (int r0 = z * kPartRows; r0 < ps.d; r0 += a.slices * kPartRows) {
-    for (int e = threadIdx.x; e < kPartRows * NL; e += 256) {
-      const int rr = sdiv(e, NL), c = e - rr * NL, blk = sdiv(c, k), j = c - blk * k;
-      const int r = r0 + rr;
-      ls[rr][c] = (r < ps.d) ? ps.lp[blk][(int64_t)r * ps.lld[blk] + j] : 0.0;
+  for (int q = 0; q < MAXT; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // element q of a block for this thread: row rr[q], column jj[q] (-1: none)
+  int rr[EL], jj[EL];
+#pragma unroll
+  for (int q = 0; q < EL; ++q) {
+    const int e = tid + 256 * q;
+    const int r = sdiv(e, k);
+    rr[q] = r;
+    jj[q] = (e < kPartRows * k) ? e - r * k : -1;
+  }
+  double vl[2][EL], vr[6][EL];
+  auto fetch = [&](int r0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (b < ps.nl) {
+        const __amdgpu_buffer_rsrc_t rs_b = make_rsrc(ps.lp[b], (int64_t)ps.d * ps.lld[b] * 8);
+#pragma unroll
+        for (int q = 0; q < EL; ++q) {
+          const int r = r0 + rr[q];
+          vl[b][q] = buf_load<double>(rs_b, (jj[q] >= 0 && r < ps.d) ? (r * ps.lld[b] + jj[q]) * 8 : kOob, 0);
+        }
+      }
     }
-    for (int e = threadIdx.x; e < kPartRows * NR; e += 256) {
-      const int rr = sdiv(e, NR), c = e - rr * NR, blk = sdiv(c, k), j = c - blk * k;
-      const int r = r0 + rr;
-      rs[rr][c] = (r < ps.d) ? ps.rp[blk][(int64_t)r * ps.rld[blk] + j] : 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+      if (b < ps.nr) {
+        const __amdgpu_buffer_rsrc_t rs_b = make_rsrc(ps.rp[b], (int64_t)ps.d * ps.rld[b] * 8);
+#pragma unroll
+        for (int q = 0; q < EL; ++q) {
+          const int r = r0 + rr[q];
+          vr[b][q] = buf_load<double>(rs_b, (jj[q] >= 0 && r < ps.d) ? (r * ps.rld[b] + jj[q]) * 8 : kOob, 0);
+        }
+      }
+    }
+  };
+  const int step = a.slices * kPartRows;
+  int r0 = z * kPartRows;
+  if (r0 < ps.d) fetch(r0);
+  __syncthreads();   // zeroed staging visible before the first stores
+  for (; r0 < ps.d; r0 += step) {
+#pragma unroll
+    for (int q = 0; q < EL; ++q) {
+      if (jj[q] >= 0) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          if (b < ps.nl) ls[rr[q]][b * k + jj[q]] = vl[b][q];
+#pragma unroll
+        for (int b = 0; b < 6; ++b)
+          if (b < ps.nr) rs[rr[q]][b * k + jj[q]] = vr[b][q];
+      }
     }
     __syncthreads();
+    if (r0 + step < ps.d) fetch(r0 + step);
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int o = threadIdx.x + q * 256;
-      if (o < nout) {
-        const int i = sdiv(o, NR), j = o - i * NR;
-        double s = acc[q];
+    for (int q = 0; q < MAXT; ++q) {
+      const int tt = w + 4 * q;
+      if (tt < ntiles) {
+        const int mt = sdiv(tt, NT), nt = tt - mt * NT;
 #pragma unroll
-        for (int rr = 0; rr < kPartRows; ++rr) s += ls[rr][i] * rs[rr][j];
-        acc[q] = s;
+        for (int s4 = 0; s4 < kPartRows / 4; ++s4) {
+          const int row = 4 * s4 + (lane >> 4);
+          acc[q] = mfma16x16x4(ls[row][16 * mt + (lane & 15)], rs[row][16 * nt + (lane & 15)], acc[q]);
+        }
       }
     }
     __syncthreads();
   }
-  double* out = a.out + blockIdx.y * a.side_stride + (int64_t)z * nout;
+  double* out = a.out + blockIdx.y * a.side_stride + (int64_t)z * NL * NR;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int o = threadIdx.x + q * 256;
-    if (o < nout) out[o] = acc[q];
+  for (int q = 0; q < MAXT; ++q) {
+    const int tt = w + 4 * q;
+    if (tt < ntiles) {
+      const int mt = sdiv(tt, NT), nt = tt - mt * NT;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * mt + acc_row<double>(lane, r), j = 16 * nt + (lane & 15);
+        if (i < NL && j < NR) out[(int64_t)i * NR + j] = acc[q][r];
+      }
+    }
   }
 }
 
