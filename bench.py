@@ -37,7 +37,7 @@ def parse():
                     help="serving: HIP hardware queues for this process (GPU_MAX_HW_QUEUES, <= 16; "
                          "default: the number of slots when above HIP's default of 4)")
     ap.add_argument("--pool-gib", type=float, default=64.0, help="serving: engine pool (HBM budget) in GiB")
-    ap.add_argument("--stage", choices=["none", "bf16", "bf16fp8"], default="bf16",
+    ap.add_argument("--stage", choices=["none", "bf16", "bf16fp8"], default="none",
                     help="serving: staged copies per request (BF16 phase + FP32 refinement, FP8 sketch input)")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rate", type=float, default=200.0, help="serving: Poisson arrival rate (requests/s)")
@@ -339,7 +339,9 @@ def main():
             else f"k_pass_{wl.problem}-{wl.dtype}-n{wl.n}-d{wl.dx}-k{wl.k}.md")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(prof),
-                "kernel": "k_pass_bf (BF16 data pass)" if lowp_form else "k_pass_dma (fused data pass)",
+                "kernel": ("k_pass_bf (BF16 data pass)" if lowp_form else
+                           "k_pass_dma (fused FP32 data pass)" if wl.k <= 16 and wl.dtype == "f32" else
+                           "k_pass (fused data pass, register-staged rows)"),
                 "bytes_per_launch": bytes_per_launch,
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "tflops": flops_per_pass / (avg_ms * 1e-3) / 1e12 if launches else 0.0}

@@ -172,7 +172,7 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
 // matching rows of B, and writes a partial; a second kernel adds the
 // partials in slice order (deterministic).  Thread (r, jg) keeps the
 // columns jg, jg + 16, ... of row r.
-constexpr int kSkSlice = 128;
+constexpr int kSkSlice = 64;
 
 // Up to two independent problems per launch (blockIdx.z), e.g. both views.
 struct SkinnyBatch {
