@@ -47,6 +47,9 @@ def parse():
                     help="N = I (unweighted trace, ordered by the closing Rayleigh-Ritz step; it optimises the "
                          "reported objective sum sigma_i) or N = diag(k, ..., 1)")
     ap.add_argument("--warm", type=int, default=None, help="warm-start iterations on the sketched problem")
+    ap.add_argument("--final-f64", type=int, default=None,
+                    help="FP64 closing iterations after the FP32 iteration (< 0: FP64 finishing pass only); "
+                         "default: -1 for FDA, 0 for CCA")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -113,7 +116,9 @@ def serve(args):
     trace = synth.serving_trace(args.requests, args.rate)
     print(f"bench: serving trace of {len(trace)} requests at {args.rate}/s; drawing the data on the device",
           file=sys.stderr, flush=True)
-    data = [synth.cca_latent_device(q.n, q.dx, q.dy, r=8, noise=0.1, x_decades=3.0, seed=q.seed) for q in trace]
+    w0 = synth.workload("cca-f64-small")   # the per-request recipe
+    data = [synth.cca_latent_device(q.n, q.dx, q.dy, r=w0.r, noise=w0.noise, factor_decades=w0.factor_decades,
+                                    x_decades=w0.x_decades, seed=q.seed) for q in trace]
     torch.cuda.synchronize()
     data_bytes = sum(X.numel() * 4 + Y.numel() * 4 for X, Y in data)
     stage = {"none": srp.SRP_STAGE_NONE, "bf16": srp.SRP_STAGE_BF16, "bf16fp8": srp.SRP_STAGE_BF16_FP8}[args.stage]
@@ -273,10 +278,18 @@ def main():
         print(json.dumps({"copy_probe_bytes": src.numel() * esize, "launches": 3}), flush=True)
         return
     lam = wl.lam_value
-    tol = args.tol if args.tol is not None else (1e-9 if wl.dtype == "f64" else 1e-5)
+    # gradient tolerance giving the 1e-6 relative objective error with a
+    # margin on these spectra (top-k correlations 3e-4 to 5e-3 apart)
+    tol = args.tol if args.tol is not None else (1e-9 if wl.dtype == "f64" else 1e-4)
     mu = [1.0] * wl.k if args.weights == "equal" else None
-    warm = args.warm if args.warm is not None else 60
+    warm = args.warm if args.warm is not None else 100
     extra = {"warm_start_iters": warm}
+    if args.final_f64 is not None:
+        extra["final_f64"] = args.final_f64
+    elif wl.problem == "lda":
+        # within-class covariance over 6 decades: the finishing retraction
+        # takes its Gram from an FP64 pass (constraint residual ~1e-6 otherwise)
+        extra["final_f64"] = -1
     sketch = srp.SRP_SRHT if wl.sketch == "srht" else srp.SRP_COUNTSKETCH
     staging = None
     lowp = sketch_input = None
@@ -353,6 +366,7 @@ def main():
                       "k": wl.k, "lambda": lam, "sketch": wl.sketch, "s": wl.s, "tol": tol,
                       "weights": args.weights,
                       "warm_start_iters": warm,
+                      "final_f64": extra.get("final_f64", 0),
                       "parallelism": "single-gpu"},
            "roofline": roofline,
            "solve": {key: infos[-1][key] for key in ("status", "iterations", "warm_iterations", "passes",

@@ -78,8 +78,10 @@ typedef struct srp_options {
                              iterations whose data products use FP64
                              arithmetic (two GEMM reads of the data where the
                              fused pass has no FP64 instance); the finishing
-                             pass is FP64 too.  Needs F32 or F64 data.
-                             0 = none (default)                              */
+                             pass is FP64 too.  < 0: only the finishing pass
+                             (the Gram of the final retraction and the
+                             Rayleigh-Ritz products) in FP64.  Needs F32 or
+                             F64 data.  0 = none (default)                   */
   const double* mu;       /* HOST pointer to k weights mu_1 >= ... >= mu_k > 0
                              (N = diag(mu)); NULL = k, k-1, ..., 1.  Equal
                              weights (N = I) optimise the unweighted trace;

@@ -556,6 +556,7 @@ static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const Com
   // final_f64 > 0 with lower-precision passes: close with that many
   // iterations whose data products run in FP64 arithmetic, from the point
   // the FP32 (or BF16) iteration reached; the finishing pass is FP64 too.
+  // final_f64 < 0: only the finishing pass runs in FP64.
   const bool refine = ca.opt.final_f64 > 0 && full.compute != SRP_F64;
   SRP_TRY(rcg_run(full, B, start, ca.opt.max_iter, ca.tol, std::max(1, ca.opt.check_every),
                   ca.opt.refresh_every, !refine, ca.opt.final_f64 != 0, sigma_out, r, st));

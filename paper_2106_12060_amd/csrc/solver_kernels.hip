@@ -342,51 +342,71 @@ __device__ bool group_chol(double* A, int k, int gl, int gsize) {
 }
 
 // X = L^-1 for lower L (ld k): lane c of the group forward-substitutes
-// column c (no cross-lane dependence); each row's dot product is unrolled
-// to KC so its loads issue together.
+// column c of X in registers (no cross-lane dependence, no LDS round trip
+// inside the chain).  Row r of L arrives as broadcast loads and the
+// diagonal through its reciprocal, so a step of the chain is the dot
+// product of the row with the finished entries and one multiply.  An empty
+// asm statement with a memory clobber keeps each row's loads in its own
+// step (hoisting all of them ahead of the chain would exhaust registers).
 template <int KC>
 __device__ void group_lower_inv(const double* L, double* X, int k, int gl) {
   if (gl < k) {
     const int c = gl;
-    for (int r = 0; r < k; ++r) {
+    double x[KC];
+#pragma unroll
+    for (int r = 0; r < KC; ++r) {
       double v = 0.0;
-      if (r >= c) {
+      if (r < k) {
+        asm volatile("" ::: "memory");
+        const double rinv = 1.0 / L[r * k + r];
         double acc4[4] = {0.0, 0.0, 0.0, 0.0};   // four short chains instead of one long one
 #pragma unroll
-        for (int l = 0; l < KC; ++l) {
-          const int lc = l < k ? l : 0;
-          const double prod = L[r * k + lc] * X[lc * k + c];
-          acc4[l & 3] += (l >= c && l < r) ? prod : 0.0;
-        }
+        for (int l = 0; l < r; ++l) acc4[l & 3] += L[r * k + l] * x[l];   // x[l] = 0 for l < c
         const double s = ((r == c) ? 1.0 : 0.0) - ((acc4[0] + acc4[1]) + (acc4[2] + acc4[3]));
-        v = s / L[r * k + r];
+        v = (r >= c) ? s * rinv : 0.0;
       }
-      X[r * k + c] = v;
+      x[r] = v;
     }
+#pragma unroll
+    for (int r = 0; r < KC; ++r)
+      if (r < k) X[r * k + c] = x[r];
   }
   wave_sync();
 }
 
 // sum_i mu_i (Lx^-1 C Ly^-T)_ii with Xx = Lx^-1, Xy = Ly^-1 (lower, ld k):
-// lane i forms row i; reduced over the wave.
+// lane i holds row i of Xy in registers, contracts it with each row of C
+// (broadcast loads, one row per step as above) and weights the result by
+// row i of Xx; reduced over the wave.
 template <int KC>
 __device__ double trial_cost(const double* C, const double* Xx, const double* Xy, const double* mu, int k,
                              int lane) {
   double part = 0.0;
   if (lane < k) {
     const int i = lane;
-    double fii = 0.0;
-    for (int a = 0; a <= i; ++a) {
-      double r4[4] = {0.0, 0.0, 0.0, 0.0};
+    double xy[KC];
 #pragma unroll
-      for (int b = 0; b < KC; ++b) {
-        const int bc = b < k ? b : 0;
-        const double prod = C[a * k + bc] * Xy[i * k + bc];
-        r4[b & 3] += (b <= i) ? prod : 0.0;
-      }
-      fii += Xx[i * k + a] * ((r4[0] + r4[1]) + (r4[2] + r4[3]));
+    for (int b = 0; b < KC; ++b) {
+      const int bc = b < k ? b : 0;
+      const double vy = Xy[i * k + bc];
+      xy[b] = (b < k && b <= i) ? vy : 0.0;
     }
-    part = mu[i] * fii;
+    double f4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < KC; ++a) {
+      if (a < k) {
+        asm volatile("" ::: "memory");
+        double u4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < KC; ++b) {
+          const int bc = b < k ? b : 0;
+          u4[b & 3] += C[a * k + bc] * xy[b];
+        }
+        const double xxa = (a <= i) ? Xx[i * k + a] : 0.0;
+        f4[a & 3] += xxa * ((u4[0] + u4[1]) + (u4[2] + u4[3]));
+      }
+    }
+    part = mu[i] * ((f4[0] + f4[1]) + (f4[2] + f4[3]));
   }
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
   return part;
@@ -402,7 +422,7 @@ __device__ __forceinline__ const double* coefp(const double* base, int k, int id
 // two Grams in the two half-waves; Lm holds nb k x k factors, Li their
 // inverses; C(t) is staged into Lm once the factors have been inverted.
 template <int KC>
-__device__ double eval_trial(const ProbView& p, const double* coef, const double* mu, double t, double* Lm,
+__device__ __attribute__((noinline)) double eval_trial(const ProbView& p, const double* coef, const double* mu, double t, double* Lm,
                              double* Li, int lane, bool* ok) {
   const int k = p.k, nb = p.nb, kk2 = k * k;
   const int gsize = nb == 2 ? 32 : 64;
@@ -787,23 +807,34 @@ __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, Wa
 }
 
 // ------------------------------------------------------- direction
-// C = op(A) op(B) for k x k blocks by one wave; element (i, j) per lane,
-// the contraction unrolled to KC so its loads issue together.
-// A(i, l) = A[i * lda + l] (or A[l * lda + i] when ta); likewise B.
+// C = op(A) op(B) for k x k blocks (k <= KC) by one wave on FP64 matrix
+// cores: 16x16 output tiles, 4 contraction steps per instruction; operands
+// past k read as zero.  A(i, l) = A[i * lda + l] (or A[l * lda + i] when
+// ta); likewise B.  C must not alias A or B.
 template <int KC>
 __device__ __forceinline__ void wave_mm_t(const double* A, int lda, bool ta, const double* B, int ldb, bool tb,
                                           double* C, int ldc, int k, int lane) {
-  for (int e = lane; e < k * k; e += 64) {
-    const int i = sdiv(e, k), j = e - i * k;
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  constexpr int T = (KC + 15) / 16;
+  const int m16 = lane & 15, q = lane >> 4;
 #pragma unroll
-    for (int l = 0; l < KC; ++l) {
-      const int lc = l < k ? l : 0;
-      const double prod = (ta ? A[lc * lda + i] : A[i * lda + lc]) * (tb ? B[j * ldb + lc] : B[lc * ldb + j]);
-      s4[l & 3] += (l < k) ? prod : 0.0;
+  for (int ti = 0; ti < T; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < T; ++tj) {
+      f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kb = 0; kb < (KC + 3) / 4; ++kb) {
+        const int i = 16 * ti + m16, l = 4 * kb + q, j = 16 * tj + m16;
+        const int ic = i < k ? i : k - 1, lc = l < k ? l : k - 1, jc = j < k ? j : k - 1;
+        const double av = ta ? A[lc * lda + ic] : A[ic * lda + lc];
+        const double bv = tb ? B[jc * ldb + lc] : B[lc * ldb + jc];
+        acc = mfma16x16x4((i < k && l < k) ? av : 0.0, (l < k && j < k) ? bv : 0.0, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ti + acc_row<double>(lane, r), col = 16 * tj + m16;
+        if (row < k && col < k) C[row * ldc + col] = acc[r];
+      }
     }
-    C[i * ldc + j] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-  }
   wave_sync();
 }
 
@@ -897,54 +928,23 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
       const double* C = srcs[m];
       for (int e = lane; e < kk2; e += 64) {
         const int i = sdiv(e, k), j = e - i * k;
-        double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int l = 0; l < KC; ++l) {
-          const int lc = l < k ? l : 0;
-          const double prod = (C[i * k + lc] + C[lc * k + i]) * JV[lc * n + j];
-          s4[l & 3] += (l < k) ? prod : 0.0;
-        }
-        const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-        W1[e] = s;
+        W2[e] = C[i * k + j] + C[j * k + i];
       }
       wave_sync();
+      wave_mm_t<KC>(W2, k, false, JV, n, false, W1, k, k, lane);   // (C + C^T) V
+      wave_mm_t<KC>(JV, n, true, W1, k, false, W2, k, k, lane);    // V^T (C + C^T) V
       for (int e = lane; e < kk2; e += 64) {
         const int i = sdiv(e, k), j = e - i * k;
-        double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int l = 0; l < KC; ++l) {
-          const int lc = l < k ? l : 0;
-          const double prod = JV[lc * n + i] * W1[lc * k + j];
-          s4[l & 3] += (l < k) ? prod : 0.0;
-        }
-        const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-        W2[e] = s / (JA[i * n + i] + JA[j * n + j]);
+        W2[e] /= (JA[i * n + i] + JA[j * n + j]);
       }
       wave_sync();
+      wave_mm_t<KC>(JV, n, false, W2, k, false, W1, k, k, lane);   // V (...)
+      wave_mm_t<KC>(W1, k, false, JV, n, true, W2, k, k, lane);    // ... V^T
+      // the solution is symmetric: keep it so (its two triangles are
+      // rounded along different sums)
       for (int e = lane; e < kk2; e += 64) {
         const int i = sdiv(e, k), j = e - i * k;
-        double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int l = 0; l < KC; ++l) {
-          const int lc = l < k ? l : 0;
-          const double prod = JV[i * n + lc] * W2[lc * k + j];
-          s4[l & 3] += (l < k) ? prod : 0.0;
-        }
-        const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-        W1[e] = s;
-      }
-      wave_sync();
-      for (int e = lane; e < kk2; e += 64) {
-        const int i = sdiv(e, k), j = e - i * k;
-        double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int l = 0; l < KC; ++l) {
-          const int lc = l < k ? l : 0;
-          const double prod = W1[i * k + lc] * JV[j * n + lc];
-          s4[l & 3] += (l < k) ? prod : 0.0;
-        }
-        const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-        dsts[m][e] = s;
+        dsts[m][e] = 0.5 * (W2[i * k + j] + W2[j * k + i]);
       }
       wave_sync();
     }

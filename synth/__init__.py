@@ -9,10 +9,13 @@ Workload shapes follow the paper's setting of tall data with samples in
 rows (Section 2, Section 4 problem statement, Section 5 problem statement):
 
 * CCA: ``X`` (n x dx) and ``Y`` (n x dy) share a Gaussian latent factor
-  ``Z`` (n x r); ``X = (Z Wx + noise*E) diag(cx)``, ``Y = (Z Wy + noise*E')
-  diag(cy)`` with geometric column scales ``c_j = 10^(-decades*j/(d-1))``
-  (or ``10^(-decades*j/d)``) that make ``X^T X`` ill conditioned the way
-  the paper's synthetic experiment asks for (Section 6.2).
+  ``Z`` (n x r) whose columns have strengths ``a_j = 10^(-fdec*j/r)``;
+  ``X = (Z diag(a) Wx + noise*E) diag(cx)``, ``Y = (Z diag(a) Wy +
+  noise*E') diag(cy)`` with geometric column scales
+  ``c_j = 10^(-decades*j/(d-1))`` (or ``10^(-decades*j/d)``) that make
+  ``X^T X`` ill conditioned the way the paper's synthetic experiment asks
+  for (Section 6.2).  Spread strengths separate the canonical correlations;
+  equal strengths with little noise cluster them near 1.
 * FDA: ``c`` classes with exactly ``n/c`` samples each (shuffled), class
   means drawn from ``N(0, mean_std^2 I)``, and a shared within-class
   covariance ``Q diag(lam) Q^T`` with ``lam_j = 10^(-decades*j/d)`` and a
@@ -54,10 +57,12 @@ def column_scales(d: int, decades: float, inclusive_end: bool) -> np.ndarray:
 def cca_latent(n: int, dx: int, dy: int, *, r: int, noise: float = 0.1,
                x_decades: float = 0.0, y_decades: float = 0.0,
                inclusive_end: bool = True, seed: int = 0,
-               dtype=np.float64):
+               dtype=np.float64, factor_decades: float = 0.0):
     """Two views of one Gaussian latent factor (rows are samples)."""
     rng = np.random.default_rng(seed)
     Z = rng.standard_normal((n, r))
+    if factor_decades:
+        Z *= 10.0 ** (-factor_decades * np.arange(r) / r)[None, :]
     Wx = rng.standard_normal((r, dx))
     Wy = rng.standard_normal((r, dy))
     X = Z @ Wx
@@ -74,7 +79,8 @@ def cca_latent(n: int, dx: int, dy: int, *, r: int, noise: float = 0.1,
 
 def cca_latent_device(n: int, dx: int, dy: int, *, r: int, noise: float = 0.1,
                       x_decades: float = 0.0, y_decades: float = 0.0,
-                      inclusive_end: bool = True, seed: int = 0, device="cuda"):
+                      inclusive_end: bool = True, seed: int = 0, device="cuda",
+                      factor_decades: float = 0.0):
     """``cca_latent``'s recipe drawn on the device in FP32 (torch's
     device generator seeded with ``seed``; a different stream from the
     host version, same distribution)."""
@@ -83,6 +89,8 @@ def cca_latent_device(n: int, dx: int, dy: int, *, r: int, noise: float = 0.1,
     g.manual_seed(int(seed))
     f32 = torch.float32
     Z = torch.randn((n, r), generator=g, device=device, dtype=f32)
+    if factor_decades:
+        Z.mul_(torch.from_numpy(10.0 ** (-factor_decades * np.arange(r) / r)).to(device=device, dtype=f32)[None, :])
     out = []
     for d, dec in ((dx, x_decades), (dy, y_decades)):
         W = torch.randn((r, d), generator=g, device=device, dtype=f32)
@@ -166,6 +174,8 @@ class Workload:
     y_decades: float = 0.0
     inclusive_end: bool = True
     c: int = 0            # classes (LDA)
+    noise: float = 0.1    # CCA noise level
+    factor_decades: float = 0.0   # CCA latent strengths 10^(-fdec j / r)
 
     @property
     def lam_value(self) -> float:
@@ -177,7 +187,8 @@ class Workload:
     def generate(self):
         np_dtype = np.float64 if self.dtype == "f64" else np.float32
         if self.problem == "cca":
-            return cca_latent(self.n, self.dx, self.dy, r=self.r, noise=0.1,
+            return cca_latent(self.n, self.dx, self.dy, r=self.r, noise=self.noise,
+                              factor_decades=self.factor_decades,
                               x_decades=self.x_decades,
                               y_decades=self.y_decades,
                               inclusive_end=self.inclusive_end,
@@ -196,15 +207,19 @@ class Workload:
 
 
 WORKLOADS = {
-    # FP64 CCA, CountSketch s = 4 dx, X columns scaled 1 -> 1e-3.
+    # FP64 CCA, CountSketch s = 4 dx, X columns scaled 1 -> 1e-3; latent
+    # strengths over one decade (top correlations 2-10 % apart).
     "cca-f64-small": Workload("cca-f64-small", "cca", 2000, 60, 40, 5, 1e-3,
                               "countsketch", 240, "f64", 12060 + 0, r=8,
-                              x_decades=3.0, inclusive_end=True),
-    # FP32 CCA, SRHT s = 4000, both views scaled 10^(-4j/d).
+                              x_decades=3.0, inclusive_end=True,
+                              noise=1.0, factor_decades=1.0),
+    # FP32 CCA, SRHT s = 4000, both views scaled 10^(-4j/d); latent
+    # strengths over two decades (top-10 correlations 3e-4 to 5e-3 apart).
     "cca-f32-srht": Workload("cca-f32-srht", "cca", 200_000, 1000, 1000, 10,
                              1e-4, "srht", 4000, "f32", 12060 + 1, r=32,
                              x_decades=4.0, y_decades=4.0,
-                             inclusive_end=False),
+                             inclusive_end=False, noise=1.0,
+                             factor_decades=2.0),
     # FP32 FDA, CountSketch s = 8000 of the centred data, 20 classes.
     "lda-f32": Workload("lda-f32", "lda", 100_000, 2000, 0, 19, float("nan"),
                         "countsketch", 8000, "f32", 12060 + 2, c=20),
@@ -212,7 +227,8 @@ WORKLOADS = {
     "cca-bf16-srht": Workload("cca-bf16-srht", "cca", 200_000, 1000, 1000, 10,
                               1e-4, "srht", 4000, "bf16", 12060 + 1, r=32,
                               x_decades=4.0, y_decades=4.0,
-                              inclusive_end=False),
+                              inclusive_end=False, noise=1.0,
+                              factor_decades=2.0),
 }
 
 
