@@ -145,6 +145,31 @@ template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_r
 template <> __device__ __forceinline__ bf16 buf_load<bf16>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
   return __builtin_bit_cast(bf16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
 }
+// An element of type T at byte offset off of a buffer, converted to Acc
+// (offsets past the resource read as zero).
+template <class Acc, class T> __device__ __forceinline__ Acc buf_load_as(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ float buf_load_as<float, float>(__amdgpu_buffer_rsrc_t r, int off) {
+  return buf_load<float>(r, off, 0);
+}
+template <> __device__ __forceinline__ double buf_load_as<double, double>(__amdgpu_buffer_rsrc_t r, int off) {
+  return buf_load<double>(r, off, 0);
+}
+template <> __device__ __forceinline__ double buf_load_as<double, float>(__amdgpu_buffer_rsrc_t r, int off) {
+  return (double)buf_load<float>(r, off, 0);
+}
+template <> __device__ __forceinline__ float buf_load_as<float, bf16>(__amdgpu_buffer_rsrc_t r, int off) {
+  return to_f32(buf_load<bf16>(r, off, 0));
+}
+template <> __device__ __forceinline__ double buf_load_as<double, bf16>(__amdgpu_buffer_rsrc_t r, int off) {
+  return to_f64(buf_load<bf16>(r, off, 0));
+}
+template <> __device__ __forceinline__ float buf_load_as<float, fp8e4m3>(__amdgpu_buffer_rsrc_t r, int off) {
+  return fp8_to_f32(fp8e4m3{(uint8_t)__builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0)});
+}
+template <> __device__ __forceinline__ double buf_load_as<double, fp8e4m3>(__amdgpu_buffer_rsrc_t r, int off) {
+  return (double)buf_load_as<float, fp8e4m3>(r, off);
+}
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
   const int nrec = (int)(bytes < 0x7ffff000ll ? bytes : 0x7ffff000ll);
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, (int)kBufDword3);

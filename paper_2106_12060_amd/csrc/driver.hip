@@ -306,6 +306,9 @@ static ProbView make_view(const RcgProblem& P, RcgBuffers& B) {
   v.kk = B.kk;
   v.part = B.part;
   v.part_slices = partial_slices(std::max(P.d[0], P.nb == 2 ? P.d[1] : 0));
+  // eigenvectors of the projection's k x k system to relative off-diagonal
+  // 1e-15 (a looser stop for FP32 passes stalled clustered problems)
+  v.eig_tol2 = 1e-30;
   return v;
 }
 

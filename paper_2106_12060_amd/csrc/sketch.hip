@@ -350,8 +350,8 @@ __global__ void __launch_bounds__(256) k_srht_level1(const T* __restrict__ A, in
                                                      int CW, uint64_t seedD, Acc* __restrict__ Tbuf) {
   extern __shared__ unsigned char smem_raw[];
   Acc* tile = reinterpret_cast<Acc*>(smem_raw);
-  const int a = blockIdx.x;
-  const int c0 = blockIdx.y * CW;
+  const int a = blockIdx.y;          // column chunks of one row block run side by side
+  const int c0 = blockIdx.x * CW;
   const int cw = min(CW, d - c0);
   const int tot = B * CW;
   for (int e = threadIdx.x; e < tot; e += 256) {
@@ -399,8 +399,10 @@ __global__ void __launch_bounds__(256) k_srht_level1_reg(const T* __restrict__ A
   const int B = 1 << logB;
   const int logCW = 14 - logB, CW = 1 << logCW;
   const int logG = 8 - logCW, G = 1 << logG;
-  const int a = blockIdx.x;
-  const int c0 = blockIdx.y * CW;
+  // the column chunks of one row block are consecutive workgroups, so the
+  // rows they read and write stream through HBM together
+  const int a = blockIdx.y;
+  const int c0 = blockIdx.x * CW;
   const int c = threadIdx.x & (CW - 1), g = threadIdx.x >> logCW;
   const bool col_ok = c0 + c < d;
   // the block's signs D_i, one hash per row (after the tile)
@@ -408,14 +410,18 @@ __global__ void __launch_bounds__(256) k_srht_level1_reg(const T* __restrict__ A
   for (int r = threadIdx.x; r < B; r += 256)
     sgn[r] = (splitmix64(seedD, (uint64_t)((int64_t)a * B + r)) & 1ull) ? Acc(-1) : Acc(1);
   __syncthreads();
+  // one buffer resource for the block's rows: rows past n lie past it and
+  // read zero, columns past d take an offset past it; every load issues
+  // unconditionally, so all 64 of a thread are in flight together
+  const int64_t row0 = (int64_t)a * B;
+  const int64_t rows_here = n - row0 < B ? n - row0 : B;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(A + row0 * d, rows_here * d * (int64_t)sizeof(T));
   Acc v[64];
 #pragma unroll
   for (int i = 0; i < 64; ++i) {
     const int r = g + G * i;
-    const int64_t row = (int64_t)a * B + r;
-    Acc x = Acc(0);
-    if (col_ok && row < n) x = load_as<Acc>(A + row * d + c0 + c) * sgn[r];
-    v[i] = x;
+    const int off = col_ok ? (r * d + c0 + c) * (int)sizeof(T) : kOob;
+    v[i] = buf_load_as<Acc, T>(rs, off) * sgn[r];
   }
 #pragma unroll
   for (int h = 1; h < 64; h <<= 1)
@@ -464,8 +470,8 @@ __global__ void __launch_bounds__(256) k_srht_level2(const Acc* __restrict__ Tbu
                                                      const int* __restrict__ goff, const int* __restrict__ galpha,
                                                      const int* __restrict__ gslot, Acc scale, Acc* __restrict__ out) {
   constexpr int G = 16;
-  const int beta = blockIdx.x;
-  const int c = blockIdx.y * 256 + threadIdx.x;
+  const int beta = blockIdx.y;   // the column chunks of one beta are consecutive workgroups
+  const int c = blockIdx.x * 256 + threadIdx.x;
   const int beg = goff[beta], cnt = goff[beta + 1] - beg;
   for (int g0 = 0; g0 < cnt; g0 += G) {
     const int gn = min(G, cnt - g0);
@@ -477,6 +483,8 @@ __global__ void __launch_bounds__(256) k_srht_level2(const Acc* __restrict__ Tbu
       acc[j] = Acc(0);
     }
     if (c < d) {
+      // eight blocks' loads in flight at a time
+#pragma unroll 8
       for (int a = 0; a < A_eff; ++a) {
         const Acc v = Tbuf[((int64_t)a * B + beta) * d + c];
 #pragma unroll
@@ -520,20 +528,20 @@ static int srht_levels(const T* A, int64_t n, int d, int s, uint64_t seed, const
   const int logB = (g.m + 1) / 2;
   if (logB >= 6 && logB <= 10) {
     const int CW = 16384 >> logB;
-    dim3 grid1(g.A_eff, (d + CW - 1) / CW);
+    dim3 grid1((d + CW - 1) / CW, g.A_eff);
     const size_t lds = (size_t)(16384 + 1024) * sizeof(Acc);
     SRP_TRY(allow_dynamic_lds((const void*)k_srht_level1_reg<T, Acc>, lds));
     hipLaunchKernelGGL((k_srht_level1_reg<T, Acc>), grid1, dim3(256), lds, st, A, n, d, logB,
                        seed ^ kSrhtSignSalt, Tbuf);
   } else {
     const int CW = srht_chunk_cols(g.B, (int)sizeof(Acc));
-    dim3 grid1(g.A_eff, (d + CW - 1) / CW);
+    dim3 grid1((d + CW - 1) / CW, g.A_eff);
     const size_t lds = (size_t)g.B * CW * sizeof(Acc);
     hipLaunchKernelGGL((k_srht_level1<T, Acc>), grid1, dim3(256), lds, st, A, n, d, g.B, logB, CW,
                        seed ^ kSrhtSignSalt, Tbuf);
   }
   SRP_LAUNCH_CHECK();
-  dim3 grid2(g.B, (d + 255) / 256);
+  dim3 grid2((d + 255) / 256, g.B);
   hipLaunchKernelGGL((k_srht_level2<Acc>), grid2, dim3(256), 0, st, Tbuf, d, g.B, g.A_eff, goff, galpha,
                      gslot, (Acc)(1.0 / std::sqrt((double)s)), out);
   SRP_LAUNCH_CHECK();

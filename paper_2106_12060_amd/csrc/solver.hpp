@@ -56,6 +56,7 @@ struct ProbView {
   double* kk;         // [2][KK_NSLOTS][KMAX*KMAX]
   double* part;       // partial k x k products
   int part_slices;    // row-slice workgroups per side used for partials
+  double eig_tol2;    // Jacobi stop of the direction step: off^2 <= eig_tol2 diag^2
 };
 
 // Launchers (solver_kernels.hip).

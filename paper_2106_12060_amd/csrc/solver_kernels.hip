@@ -753,7 +753,8 @@ struct WaveJacobiScratch {
   double rs[64];
 };
 
-__device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, WaveJacobiScratch& w) {
+__device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, WaveJacobiScratch& w,
+                            double tol2 = 1e-30) {
   const int nn = n * n;
   for (int e = lane; e < nn; e += 64) V[e] = (e == sdiv(e, n) * (n + 1)) ? 1.0 : 0.0;
   wave_sync();
@@ -767,7 +768,7 @@ __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, Wa
       off += __shfl_xor(off, o, 64);
       dia += __shfl_xor(dia, o, 64);
     }
-    if (off <= 1e-30 * (dia + 1e-300)) break;
+    if (off <= tol2 * (dia + 1e-300)) break;
     for (int round = 0; round < n - 1; ++round) {
       if (lane < n) w.pos[lane] = (lane == 0) ? 0 : 1 + ((lane - 1 + round) % (n - 1));
       wave_sync();
@@ -914,7 +915,7 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
       for (int e = lane; e < nn; e += 64) JA[e] = JT[e];
     }
     wave_sync();
-    wave_jacobi(JA, JV, JT, n, lane, jsc[b]);
+    wave_jacobi(JA, JV, JT, n, lane, jsc[b], p.eig_tol2);
     if (warm) {
       wave_mm_t<KC>(V0, n, false, JV, n, false, JT, n, n, lane);   // V = V0 J
       for (int e = lane; e < nn; e += 64) JV[e] = JT[e];
