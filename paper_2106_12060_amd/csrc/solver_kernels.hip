@@ -313,11 +313,37 @@ __device__ void wave_lower_inv(const double* L, double* X, int k, int lane) {
   wave_sync();
 }
 
+// The trial evaluations run out of line (their register use stays apart
+// from the line search's); their operands are LDS arrays, typed as such so
+// that the accesses compile to LDS instructions rather than generic ones.
+typedef __attribute__((address_space(3))) double lds_f64;
+
 // Lower Cholesky in place (ld k) by a group of gsize lanes (gl = lane in
 // the group); all lanes of the wave run the same loop, so two groups of 32
 // factor two matrices side by side.  A non-positive pivot is replaced by 1
 // to keep the loop uniform and reported through the return value.
-__device__ bool group_chol(double* A, int k, int gl, int gsize) {
+//
+// Right-looking and unscaled: step j subtracts A[r][j] A[c][j] / A[j][j]
+// from the trailing lower triangle (r >= c > j), whose entries the lanes
+// own in NS fixed slots (no index arithmetic per step, one barrier per
+// step); column j is final after step j, and all columns are scaled by
+// 1 / sqrt(pivot) at the end.  Every slot loads (slots past the triangle
+// read element (0, 0)), so a step's loads issue together; only the stores
+// are masked.
+template <int NS>
+__device__ bool chol_slots(lds_f64* A, int k, int gl, int gsize) {
+  const int ntri = k * (k + 1) / 2;
+  int sr[NS], sc[NS];
+  bool sv[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    const int e = gl + gsize * m;
+    int r = 0;
+    while ((r + 1) * (r + 2) / 2 <= e) ++r;   // row of element e of the row-major lower triangle
+    sv[m] = e < ntri;
+    sr[m] = sv[m] ? r : 0;
+    sc[m] = sv[m] ? e - r * (r + 1) / 2 : 0;
+  }
   bool ok = true;
   for (int j = 0; j < k; ++j) {
     wave_sync();
@@ -326,19 +352,51 @@ __device__ bool group_chol(double* A, int k, int gl, int gsize) {
       ok = false;
       piv = 1.0;
     }
-    const double dj = sqrt(piv);
-    wave_sync();
-    if (gl == 0) A[j * k + j] = dj;
-    for (int i = j + 1 + gl; i < k; i += gsize) A[i * k + j] /= dj;
-    wave_sync();
-    const int w = k - j - 1;
-    for (int e = gl; e < w * w; e += gsize) {
-      const int q = sdiv(e, w), r = j + 1 + q, c = j + 1 + (e - q * w);
-      if (c <= r) A[r * k + c] -= A[r * k + j] * A[c * k + j];
+    const double rp = 1.0 / piv;
+    double nv[NS];
+#pragma unroll
+    for (int m = 0; m < NS; ++m) {
+      const int r = sr[m], c = sc[m];
+      nv[m] = A[r * k + c] - A[r * k + j] * A[c * k + j] * rp;
     }
+#pragma unroll
+    for (int m = 0; m < NS; ++m)
+      if (sv[m] && sc[m] > j) A[sr[m] * k + sc[m]] = nv[m];
   }
   wave_sync();
+  // L[r][c] = A[r][c] / sqrt(A[c][c]) (the pivots are final)
+  double lv[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) {
+    const int r = sr[m], c = sc[m];
+    const double pc = A[c * k + c];
+    lv[m] = A[r * k + c] / sqrt((pc > 0.0 && isfinite(pc)) ? pc : 1.0);
+  }
+  wave_sync();
+#pragma unroll
+  for (int m = 0; m < NS; ++m)
+    if (sv[m]) A[sr[m] * k + sc[m]] = lv[m];
+  wave_sync();
   return ok;
+}
+
+// Picks the slot count ceil(k (k + 1) / 2 / gsize) (uniform over the wave),
+// so a small k in a large instance loads no more than it needs.
+template <int NS, int MAXS>
+__device__ __forceinline__ bool chol_dispatch(int ns, lds_f64* A, int k, int gl, int gsize) {
+  if constexpr (NS >= MAXS) {
+    return chol_slots<MAXS>(A, k, gl, gsize);
+  } else {
+    if (ns <= NS) return chol_slots<NS>(A, k, gl, gsize);
+    return chol_dispatch<NS + 1, MAXS>(ns, A, k, gl, gsize);
+  }
+}
+
+template <int KC>
+__device__ bool group_chol(lds_f64* A, int k, int gl, int gsize) {
+  constexpr int MAXS = (KC * (KC + 1) / 2 + 31) / 32;
+  const int ns = (k * (k + 1) / 2 + gsize - 1) / gsize;
+  return chol_dispatch<1, MAXS>(ns, A, k, gl, gsize);
 }
 
 // X = L^-1 for lower L (ld k): lane c of the group forward-substitutes
@@ -349,7 +407,7 @@ __device__ bool group_chol(double* A, int k, int gl, int gsize) {
 // asm statement with a memory clobber keeps each row's loads in its own
 // step (hoisting all of them ahead of the chain would exhaust registers).
 template <int KC>
-__device__ void group_lower_inv(const double* L, double* X, int k, int gl) {
+__device__ void group_lower_inv(const lds_f64* L, lds_f64* X, int k, int gl) {
   if (gl < k) {
     const int c = gl;
     double x[KC];
@@ -374,40 +432,38 @@ __device__ void group_lower_inv(const double* L, double* X, int k, int gl) {
   wave_sync();
 }
 
-// sum_i mu_i (Lx^-1 C Ly^-T)_ii with Xx = Lx^-1, Xy = Ly^-1 (lower, ld k):
-// lane i holds row i of Xy in registers, contracts it with each row of C
-// (broadcast loads, one row per step as above) and weights the result by
-// row i of Xx; reduced over the wave.
+// sum_i mu_i (Lx^-1 C Ly^-T)_ii with Xx = Lx^-1, Xy = Ly^-1 (lower, ld k),
+// by one wave: M = C Xy^T on FP64 matrix cores (16x16 tiles), then each
+// lane weighs the entries M[a][i] it holds by mu_i Xx[i][a]; reduced over
+// the wave.
 template <int KC>
-__device__ double trial_cost(const double* C, const double* Xx, const double* Xy, const double* mu, int k,
+__device__ double trial_cost(const lds_f64* C, const lds_f64* Xx, const lds_f64* Xy, const lds_f64* mu, int k,
                              int lane) {
+  constexpr int T = (KC + 15) / 16;
+  const int m16 = lane & 15, q = lane >> 4;
   double part = 0.0;
-  if (lane < k) {
-    const int i = lane;
-    double xy[KC];
 #pragma unroll
-    for (int b = 0; b < KC; ++b) {
-      const int bc = b < k ? b : 0;
-      const double vy = Xy[i * k + bc];
-      xy[b] = (b < k && b <= i) ? vy : 0.0;
-    }
-    double f4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int ta = 0; ta < T; ++ta)
 #pragma unroll
-    for (int a = 0; a < KC; ++a) {
-      if (a < k) {
-        asm volatile("" ::: "memory");
-        double u4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int ti = 0; ti < T; ++ti) {
+      if (16 * ta >= k || 16 * ti >= k) continue;   // uniform: tiles past k are zero
+      f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = 0; b < KC; ++b) {
-          const int bc = b < k ? b : 0;
-          u4[b & 3] += C[a * k + bc] * xy[b];
-        }
-        const double xxa = (a <= i) ? Xx[i * k + a] : 0.0;
-        f4[a & 3] += xxa * ((u4[0] + u4[1]) + (u4[2] + u4[3]));
+      for (int kb = 0; kb < (KC + 3) / 4; ++kb) {
+        if (4 * kb >= k) break;   // uniform: blocks past k contribute nothing
+        const int a = 16 * ta + m16, b = 4 * kb + q, i = 16 * ti + m16;
+        const int ac = a < k ? a : k - 1, bc = b < k ? b : k - 1, ic = i < k ? i : k - 1;
+        const double cv = C[ac * k + bc], yv = Xy[ic * k + bc];
+        acc = mfma16x16x4((a < k && b < k) ? cv : 0.0, (b < k && i < k) ? yv : 0.0, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * ta + acc_row<double>(lane, r), i = 16 * ti + m16;
+        const int ac = a < k ? a : 0, ic = i < k ? i : 0;
+        const double w = mu[ic] * Xx[ic * k + ac];
+        part += (a < k && i < k) ? w * acc[r] : 0.0;
       }
     }
-    part = mu[i] * ((f4[0] + f4[1]) + (f4[2] + f4[3]));
-  }
   for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
   return part;
 }
@@ -417,33 +473,36 @@ __device__ double trial_cost(const double* C, const double* Xx, const double* Xy
 __device__ __forceinline__ const double* coefp(const double* base, int k, int idx) {
   return base + (size_t)idx * k * k;
 }
+__device__ __forceinline__ const lds_f64* coefp(const lds_f64* base, int k, int idx) {
+  return base + idx * k * k;
+}
 
 // Cost along the curve at step t, evaluated by one wave.  CCA factors the
 // two Grams in the two half-waves; Lm holds nb k x k factors, Li their
 // inverses; C(t) is staged into Lm once the factors have been inverted.
 template <int KC>
-__device__ __attribute__((noinline)) double eval_trial(const ProbView& p, const double* coef, const double* mu, double t, double* Lm,
-                             double* Li, int lane, bool* ok) {
+__device__ __attribute__((noinline)) double eval_trial(const ProbView& p, const lds_f64* coef, const lds_f64* mu, double t,
+                                                      lds_f64* Lm, lds_f64* Li, int lane, bool* ok) {
   const int k = p.k, nb = p.nb, kk2 = k * k;
   const int gsize = nb == 2 ? 32 : 64;
   const int grp = nb == 2 ? (lane >> 5) : 0;
   const int gl = nb == 2 ? (lane & 31) : lane;
   const double t2 = t * t;
   {
-    double* L = Lm + grp * kk2;
-    const double* G0 = coefp(coef, k, 3 * grp + 0);
-    const double* G1 = coefp(coef, k, 3 * grp + 1);
-    const double* G2 = coefp(coef, k, 3 * grp + 2);
+    lds_f64* L = Lm + grp * kk2;
+    const lds_f64* G0 = coefp(coef, k, 3 * grp + 0);
+    const lds_f64* G1 = coefp(coef, k, 3 * grp + 1);
+    const lds_f64* G2 = coefp(coef, k, 3 * grp + 2);
     for (int e = gl; e < kk2; e += gsize) L[e] = G0[e] + t * G1[e] + t2 * G2[e];
-    const bool good = group_chol(L, k, gl, gsize);
+    const bool good = group_chol<KC>(L, k, gl, gsize);
     *ok = __all(good ? 1 : 0) != 0;
     group_lower_inv<KC>(L, Li + grp * kk2, k, gl);
   }
   if (!*ok) return INFINITY;
-  const double* C0 = coefp(coef, k, 3 * nb + 0);
-  const double* C1 = coefp(coef, k, 3 * nb + 1);
-  const double* C2 = coefp(coef, k, 3 * nb + 2);
-  double* Ct = Lm;
+  const lds_f64* C0 = coefp(coef, k, 3 * nb + 0);
+  const lds_f64* C1 = coefp(coef, k, 3 * nb + 1);
+  const lds_f64* C2 = coefp(coef, k, 3 * nb + 2);
+  lds_f64* Ct = Lm;
   for (int e = lane; e < kk2; e += 64) Ct[e] = C0[e] + t * C1[e] + t2 * C2[e];
   wave_sync();
   const double s = trial_cost<KC>(Ct, Li, Li + (nb == 2 ? kk2 : 0), mu, k, lane);
@@ -546,7 +605,7 @@ __global__ void __launch_bounds__(kLsThreads) k_ctrl_ls(ProbView p, int ntr) {
         const double x = (ntr > 1) ? (2.0 * w / (ntr - 1) - 1.0) : 0.0;
         const double t = centre * exp2(H * x);
         bool ok;
-        const double f = eval_trial<KC>(p, coef, mu, t, Lm, Li, lane, &ok);
+        const double f = eval_trial<KC>(p, (const lds_f64*)coef, (const lds_f64*)mu, t, (lds_f64*)Lm, (lds_f64*)Li, lane, &ok);
         if (lane == 0) { fbest[w] = f; tbest[w] = t; }
       }
       __syncthreads();
@@ -597,7 +656,7 @@ __global__ void __launch_bounds__(kLsThreads) k_ctrl_ls(ProbView p, int ntr) {
     double f;
     bool ok = true;
     if (winner >= 0) f = fbest[63];
-    else f = eval_trial<KC>(p, coef, mu, t_acc, Lm, Li, lane, &ok);
+    else f = eval_trial<KC>(p, (const lds_f64*)coef, (const lds_f64*)mu, t_acc, (lds_f64*)Lm, (lds_f64*)Li, lane, &ok);
     if (lane == 0) { fbest[62] = f; okflag[0] = ok ? 1 : 0; }
     wave_sync();
     for (int b = 0; b < nb; ++b) {
