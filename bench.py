@@ -349,14 +349,17 @@ def main():
     avg_ms = pass_ms / max(launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else 0.0
     flops_per_pass = (6 if wl.problem == "cca" else 4) * wl.k * dsum * wl.n
-    prof = (f"{'k_pass_bf' if lowp_form else 'k_pass_dma'}_{wl.problem}-{'bf16' if lowp_form else wl.dtype}"
+    kname = srp.srp_gram_pass_kernel("bf16" if lowp_form else wl.dtype, "bf16" if lowp_form else wl.dtype,
+                                     wl.dx, wl.dy if wl.problem == "cca" else 0, wl.k)
+    prof = (f"{kname}_{wl.problem}-{'bf16' if lowp_form else wl.dtype}"
             f"-n{wl.n}-d{wl.dx}x{wl.dy}-k{wl.k}.md" if wl.problem == "cca"
-            else f"k_pass_{wl.problem}-{wl.dtype}-n{wl.n}-d{wl.dx}-k{wl.k}.md")
+            else f"{kname}_{wl.problem}-{wl.dtype}-n{wl.n}-d{wl.dx}-k{wl.k}.md")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(prof),
-                "kernel": ("k_pass_bf (BF16 data pass)" if lowp_form else
-                           "k_pass_dma (fused FP32 data pass)" if wl.k <= 16 and wl.dtype == "f32" else
-                           "k_pass (fused data pass, register-staged rows)"),
+                "kernel": kname + {"k_pass_bf": " (BF16 data pass)",
+                                   "k_pass_quad": " (fused FP32 data pass, 4x4 matrix-core blocks)",
+                                   "k_pass_dma": " (fused FP32 data pass)",
+                                   "k_pass": " (fused data pass, register-staged rows)"}.get(kname, ""),
                 "bytes_per_launch": bytes_per_launch,
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "tflops": flops_per_pass / (avg_ms * 1e-3) / 1e12 if launches else 0.0}

@@ -224,6 +224,16 @@ int srp_gram_pass(const void* A0, const void* A1, int dtype, int compute,
                   int64_t n, int d0, int d1, int k, const double* W0,
                   const double* W1, double* J0, double* J1, void* stream);
 
+/* Name of the kernel srp_gram_pass (and the solvers' iterations) run for
+ * this shape, when the rows start on 16-byte boundaries (alignment only
+ * changes the load width): "k_pass_quad" (FP32, two views of at most 1024
+ * columns, 4x4 matrix-core blocks for the narrow products), "k_pass_dma"
+ * (FP32, rows streamed into LDS), "k_pass_bf" (BF16 matrix cores) or
+ * "k_pass" (register-staged rows).  Static string; NULL outside the limits
+ * above.  No device work.
+ */
+const char* srp_gram_pass_kernel(int dtype, int compute, int d0, int d1, int k);
+
 /* ---- solvers ----------------------------------------------------------
  * cca_solve: top-k (lambda_x, lambda_y)-canonical correlations of X (n x dx)
  * and Y (n x dy) (Definition of regularised CCA, Section 4), by Algorithm

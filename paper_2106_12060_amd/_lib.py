@@ -112,6 +112,7 @@ _SIGS = {
     "srp_stage_fp8": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _P, _P, _P]),
     "srp_sketch_factor": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                          _P, _P, _P]),
+    "srp_gram_pass_kernel": (ctypes.c_char_p, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "srp_gram_pass": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P]),
     "cca_solve": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -251,6 +252,15 @@ def srp_gram_pass(A0, W0, A1=None, W1=None, compute: str = "f32"):
     _check("srp_gram_pass", lib().srp_gram_pass(_ptr(A0), _ptr(A1), _dtype(A0), comp, n, d0, d1, k,
                                                 _ptr(W0), _ptr(W1), _ptr(J0), _ptr(J1), _stream()))
     return J0, J1
+
+
+def srp_gram_pass_kernel(dtype: str, compute: str, d0: int, d1: int, k: int):
+    """Name of the pass kernel the library runs for this shape (rows on
+    16-byte boundaries), or None outside its limits."""
+    dt = {"f64": SRP_F64, "f32": SRP_F32, "bf16": SRP_BF16}[dtype]
+    comp = {"f64": SRP_F64, "f32": SRP_F32, "bf16": SRP_BF16}[compute]
+    name = lib().srp_gram_pass_kernel(dt, comp, d0, d1, k)
+    return name.decode() if name else None
 
 
 def _attach_staged(opt, lowp, sketch_input):

@@ -192,6 +192,10 @@ int srp_gram_pass(const void* A0, const void* A1, int dtype, int compute, int64_
   return finish(st);
 }
 
+const char* srp_gram_pass_kernel(int dtype, int compute, int d0, int d1, int k) {
+  return gram_pass_kernel_name(dtype, compute, d0, d1, k);
+}
+
 int cca_solve(const void* X, const void* Y, int64_t n, int dx, int dy, int k, double lambda_x, double lambda_y,
               int sketch_size, double tol, int dtype, const srp_options* opt, void* stream, double* U, double* V,
               double* sigma, srp_info* info) {

@@ -62,6 +62,7 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
 // J_b = A_b^T [A_0 W_0 | A_1 W_1] (see srp_gram_pass).  Arithmetic in
 // `compute` (SRP_F64 / SRP_F32).
 size_t pass_ws_bytes(int64_t n, int d0, int d1, int k, int compute);
+const char* gram_pass_kernel_name(int dtype, int compute, int d0, int d1, int k);
 int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1,
                   int k, const double* W0, const double* W1, double* J0, double* J1, const int* done,
                   Arena& ws, hipStream_t st, hipEvent_t before_pass = nullptr,

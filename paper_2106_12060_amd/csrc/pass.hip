@@ -506,6 +506,311 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_dma(const float* __restric
   }
 }
 
+// ------------------------------------------------------------------
+// FP32, two views: the DMA-fed pass above with the narrow products on 4x4
+// matrix-core blocks (v_mfma_f32_4x4x1f32: sixteen independent 4 x 4 outer
+// products per instruction), which removes most of the zero padding that
+// 16 x 16 tiles carry for 8-row blocks and k <= 12:
+//   * P_b = A_b W_b (8 rows x k): waves 0-7 work on view 0, waves 8-15 on
+//     view 1.  A block is 4 rows x 4 direction columns of one tile over one
+//     of every four of its columns: the four 16-lane rows take four tiles,
+//     the four blocks of a row the four column phases (summed by two DPP
+//     rotations), rows 0-3 and 4-7 are separate instructions.  The four
+//     tiles' partials are added in the cross-wave sum.
+//   * J_b = A_b^T [P_0 | P_1]: whole 16-column tiles of [P_0 | P_1] on the
+//     16 x 16 x 4 products; the remaining 4-column groups on 4x4 blocks,
+//     one row of the block per instruction over four tiles at once (the
+//     16-lane rows take the tiles, the blocks of a row 4 of its columns).
+// [P_0 | P_1] is packed tight (2k columns; C4 = ceil(k / 2) groups of 4).
+// In the P products wave w takes tiles w % 8 + 8 (4 G + row) of view w / 8
+// (G < SV / 2); in the J products it owns SV tiles of each view (slot
+// i < SV: tile w + 16 i of view 0, slot SV + i: tile w + 16 i of view 1).
+// Tiles past a view's last have a zero direction operand and their J rows
+// are not stored.  The row-block stream (DMA loads, double buffer,
+// barriers) is that of k_pass_dma.
+template <int N>
+__device__ __forceinline__ float dpp_row_ror(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x120 + N, 0xF, 0xF, false));
+}
+__device__ __forceinline__ f32x4 mfma4x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 0, 0, 0);
+}
+
+// Row pitch of the 4x4-block pass: 16 mod 64 floats, so that four rows of
+// 16 consecutive columns (the J-phase operand) fall on 64 distinct banks,
+// as do the P operands' column quadruples of one 16-lane row.
+__host__ __device__ constexpr int quad_pitch(int TPB) { return ((16 * 16 * TPB + 63) / 64) * 64 + 16; }
+
+template <int SV, int C4>
+struct QuadShape {
+  static constexpr int TPB = 2 * SV;        // tile slots per wave
+  static constexpr int KG = (C4 + 1) / 2;   // 4-column groups of one view's P
+  static constexpr int JQ = C4 / 4;         // whole 16-column tiles of [P_0 | P_1]
+  static constexpr int JR = C4 % 4;         // remaining 4-column groups
+  static constexpr int NG = TPB / 4;        // 4-slot groups of the remainder products
+  static constexpr int PP = 4 * C4 + 1;     // row pitch of [P_0 | P_1] in LDS
+  static constexpr int PG = SV / 2;        // 4-tile groups of a wave's P products
+  static constexpr int RED = kDmaRows * 4 * KG;   // one P partial (8 rows x 4 KG)
+};
+
+// Per-block work of k_pass_quad.  The LDS regions arrive as separate
+// restrict pointers: the inlined accesses then carry alias scopes, and the
+// compiler's wait insertion can see that the reads of the current block,
+// the P partials and [P_0 | P_1] are disjoint from the next block's
+// in-flight DMA (without that it waits for the DMA before the first LDS
+// read, and the double buffer overlaps nothing).  The next block's DMA is
+// issued here when next_row0 >= 0.
+template <int SV, int C4, int VEC>
+__device__ __forceinline__ void quad_step(const float* __restrict__ xs, float* __restrict__ xnext,
+                                          float* __restrict__ red, float* __restrict__ pfull, int64_t next_row0,
+                                          const float* A0, const float* A1, int64_t n, int d0, int d1, int k,
+                                          int T0, int T1, int nch0, int nch, int pitch, int w, int lane,
+                                          const float (&wreg)[QuadShape<SV, C4>::PG][4][QuadShape<SV, C4>::KG],
+                                          const int (&pcol)[QuadShape<SV, C4>::PG],
+                                          const int (&rbase)[QuadShape<SV, C4>::NG],
+                                          f32x4 (&acc)[QuadShape<SV, C4>::TPB][QuadShape<SV, C4>::JQ > 0 ? QuadShape<SV, C4>::JQ : 1],
+                                          f32x4 (&accr)[QuadShape<SV, C4>::NG][QuadShape<SV, C4>::JR > 0 ? QuadShape<SV, C4>::JR : 1],
+                                          bool dma_only) {
+  using Q = QuadShape<SV, C4>;
+  constexpr int R = kDmaRows;
+  constexpr int CH = 64 * VEC;
+  constexpr int TPB = Q::TPB, KG = Q::KG, JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG;
+  constexpr int RED = Q::RED;
+  const int tid = threadIdx.x;
+  const int g = lane >> 4, l16 = lane & 15, cs = (lane >> 2) & 3, q4 = lane & 3;
+  if (next_row0 >= 0) {
+    // wave w moves chunks j = w, w + 16, ... of every row; one buffer
+    // resource per view, rows past n read as zero
+    const int rows = (int)(n - next_row0 < R ? n - next_row0 : R);
+    const __amdgpu_buffer_rsrc_t r0 = make_rsrc(A0 + next_row0 * d0, (int64_t)rows * d0 * 4);
+    const __amdgpu_buffer_rsrc_t r1 = make_rsrc(A1 + next_row0 * d1, (int64_t)rows * d1 * 4);
+    for (int j = w; j < nch; j += kF32Waves) {
+      const bool s1 = j >= nch0;
+      const int jj = s1 ? j - nch0 : j;
+      const int span = (s1 ? T1 : T0) * 16;
+      const int o = min(jj * CH, span - CH);
+      const int db4 = (s1 ? d1 : d0) * 4;
+      float* dst = xnext + (s1 ? T0 * 16 : 0) + o;
+      const int vbase = (o + lane * VEC) * 4;
+      const __amdgpu_buffer_rsrc_t rs = s1 ? r1 : r0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dma_row_chunk<VEC>(rs, dst + r * pitch, vbase + r * db4);
+    }
+  }
+  if (dma_only) return;
+  // (b) P partials of this wave's view over its tiles: rows 4 rg + q4,
+  // columns 4 cs .. 4 cs + 3 of each tile
+  {
+    f32x4 pacc[2][KG];
+#pragma unroll
+    for (int rg = 0; rg < 2; ++rg)
+#pragma unroll
+      for (int kg = 0; kg < KG; ++kg) pacc[rg][kg] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int G = 0; G < PG; ++G)
+#pragma unroll
+      for (int rg = 0; rg < 2; ++rg) {
+        const float4 a = *reinterpret_cast<const float4*>(xs + (4 * rg + q4) * pitch + pcol[G]);
+        const float av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int kg = 0; kg < KG; ++kg) pacc[rg][kg] = mfma4x4(av[s], wreg[G][s][kg], pacc[rg][kg]);
+      }
+    float* rw = red + (w * 4 + g) * RED + q4;
+#pragma unroll
+    for (int rg = 0; rg < 2; ++rg)
+#pragma unroll
+      for (int kg = 0; kg < KG; ++kg)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float x = pacc[rg][kg][r];
+          x += dpp_row_ror<4>(x);
+          x += dpp_row_ror<8>(x);
+          if (cs == 0) rw[(4 * rg + r) * (4 * KG) + 4 * kg] = x;
+        }
+  }
+  lds_only_barrier();
+  if (tid < 2 * RED) {
+    // sum over a view's 32 (wave, 16-lane row) partials, in a fixed order.
+    // The indexes are recomputed per block (an opaque copy of tid):
+    // hoisted out of the loop they would stay live through the whole block
+    // and be spilled.
+    int t = tid;
+    asm volatile("" : "+v"(t));
+    const int v = t / RED, e = t - v * RED, row = e / (4 * KG), col = e - row * (4 * KG);
+    float sum = 0.f;
+#pragma unroll 8
+    for (int h = 0; h < 2 * kF32Waves; ++h) sum += red[(v * 2 * kF32Waves + h) * RED + e];
+    if (col < k) pfull[row * PP + v * k + col] = sum;
+  }
+  lds_only_barrier();
+  // (d) J = A_b^T [P_0 | P_1]
+  if constexpr (JQ > 0) {
+    float pb[2][JQ];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int jq = 0; jq < JQ; ++jq) pb[s][jq] = pfull[(g + 4 * s) * PP + 16 * jq + l16];
+#pragma unroll
+    for (int i = 0; i < TPB; ++i) {
+      const int col = 16 * (i < SV ? w + 16 * i : T0 + w + 16 * (i - SV));
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const float a = xs[(g + 4 * s) * pitch + col + l16];
+#pragma unroll
+        for (int jq = 0; jq < JQ; ++jq) acc[i][jq] = mfma16x16x4(a, pb[s][jq], acc[i][jq]);
+      }
+    }
+  }
+  if constexpr (JR > 0) {
+    // step rho: lane row g takes block row (rho + g) mod 8 (the four tiles
+    // of an instruction then read different banks)
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) {
+      const int row = (rho + g) & (R - 1);
+      float b[JR];
+#pragma unroll
+      for (int jr = 0; jr < JR; ++jr) b[jr] = pfull[row * PP + 16 * JQ + 4 * jr + q4];
+#pragma unroll
+      for (int G = 0; G < NG; ++G) {
+        const float a = xs[row * pitch + rbase[G]];
+#pragma unroll
+        for (int jr = 0; jr < JR; ++jr) accr[G][jr] = mfma4x4(a, b[jr], accr[G][jr]);
+      }
+    }
+  }
+}
+
+template <int SV, int C4, int VEC>
+__global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restrict__ A0, const float* __restrict__ A1,
+                                                           int64_t n, int d0, int d1, int k,
+                                                           const float* __restrict__ Wp0,
+                                                           const float* __restrict__ Wp1, int nrb,
+                                                           float* __restrict__ partial, const int* __restrict__ done) {
+  if (done && *done) return;
+  using Q = QuadShape<SV, C4>;
+  constexpr int R = kDmaRows;
+  constexpr int CH = 64 * VEC;
+  constexpr int TPB = Q::TPB, KG = Q::KG, JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG;
+  constexpr int RED = Q::RED;
+  extern __shared__ float dsm[];
+  const int T0 = (d0 + 15) >> 4, T1 = (d1 + 15) >> 4;
+  const int nch0 = (T0 * 16 + CH - 1) / CH, nch1 = (T1 * 16 + CH - 1) / CH;
+  const int nch = nch0 + nch1;
+  const int pitch = quad_pitch(TPB);
+  float* red = dsm + 2 * R * pitch;                 // [wave][16-lane row][R][4 KG]
+  float* pfull = red + kF32Waves * 4 * RED;         // [R][PP]
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  const int cs = (lane >> 2) & 3, q4 = lane & 3;
+  const int pv = w >> 3;   // view of this wave's P products (wave-uniform)
+
+  // direction operands of the P blocks: group G, tile tv = w % 8 + 8 (4 G +
+  // g) of view pv, its column 4 cs + s, direction column 4 kg + q4
+  const __amdgpu_buffer_rsrc_t wrs = make_rsrc(pv ? Wp1 : Wp0, (int64_t)(pv ? T1 : T0) * 16 * 16 * 4);
+  float wreg[PG][4][KG];
+  int pcol[PG];   // LDS column of the tile's phase-cs quadruple
+#pragma unroll
+  for (int G = 0; G < PG; ++G) {
+    const int tv = (w & 7) + 8 * (4 * G + g);
+    const bool ok = tv < (pv ? T1 : T0);
+    pcol[G] = 16 * (pv ? T0 + tv : tv) + 4 * cs;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int kg = 0; kg < KG; ++kg) {
+        const int off = ok ? ((16 * tv + 4 * cs + s) * 16 + 4 * kg + q4) * 4 : kOob;
+        wreg[G][s][kg] = buf_load<float>(wrs, off, 0);
+      }
+  }
+  f32x4 acc[TPB][JQ > 0 ? JQ : 1];
+  f32x4 accr[NG][JR > 0 ? JR : 1];
+#pragma unroll
+  for (int i = 0; i < TPB; ++i)
+#pragma unroll
+    for (int j = 0; j < (JQ > 0 ? JQ : 1); ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int G = 0; G < NG; ++G)
+#pragma unroll
+    for (int j = 0; j < (JR > 0 ? JR : 1); ++j) accr[G][j] = f32x4{0, 0, 0, 0};
+  int rbase[NG];   // remainder blocks: slot 4 G + g, column l16
+#pragma unroll
+  for (int G = 0; G < NG; ++G) {
+    const int i = 4 * G + g;
+    rbase[G] = 16 * (i < SV ? w + 16 * i : T0 + w + 16 * (i - SV)) + l16;
+  }
+  // Columns past the last tile are never loaded and the padding columns of
+  // [P_0 | P_1] never written: zero both row buffers and pfull once.
+  for (int e = tid; e < 2 * R * pitch; e += kF32Threads) dsm[e] = 0.f;
+  for (int e = tid; e < R * PP; e += kF32Threads) pfull[e] = 0.f;
+  __syncthreads();
+
+  int rb = blockIdx.x;
+  int boff = 0;
+  if (rb < nrb)
+    quad_step<SV, C4, VEC>(dsm + R * pitch, dsm, red, pfull, (int64_t)rb * R, A0, A1, n, d0, d1, k, T0, T1, nch0,
+                           nch, pitch, w, lane, wreg, pcol, rbase, acc, accr, true);
+  for (; rb < nrb; rb += gridDim.x) {
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the block have landed
+    __syncthreads();                 // ... and every wave's; the other buffer is free
+    const int64_t nxt = rb + (int)gridDim.x < nrb ? (int64_t)(rb + gridDim.x) * R : -1;
+    quad_step<SV, C4, VEC>(dsm + boff, dsm + (R * pitch - boff), red, pfull, nxt, A0, A1, n, d0, d1, k, T0, T1,
+                           nch0, nch, pitch, w, lane, wreg, pcol, rbase, acc, accr, false);
+    boff = R * pitch - boff;
+  }
+  // epilogue: this workgroup's partial (rows = concatenated columns of A,
+  // columns = [P_0 | P_1])
+  const int W_out = 2 * k;
+  const int D = d0 + d1;
+  float* out = partial + (int64_t)blockIdx.x * D * W_out;
+  if constexpr (JQ > 0) {
+#pragma unroll
+    for (int i = 0; i < TPB; ++i) {
+      const int v = i < SV ? 0 : 1;
+      const int tv = w + 16 * (i - v * SV);
+      if (tv < (v ? T1 : T0)) {
+        const int db = v ? d1 : d0, rowbase = v ? d0 : 0;
+#pragma unroll
+        for (int jq = 0; jq < JQ; ++jq) {
+          const int c = 16 * jq + l16;
+          if (c < W_out) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * tv + acc_row<float>(lane, r);
+              if (row < db) out[(int64_t)(rowbase + row) * W_out + c] = acc[i][jq][r];
+            }
+          }
+        }
+      }
+    }
+  }
+  if constexpr (JR > 0) {
+#pragma unroll
+    for (int G = 0; G < NG; ++G) {
+      const int i = 4 * G + g;
+      const int v = i < SV ? 0 : 1;
+      const int tv = w + 16 * (i - v * SV);
+      if (tv < (v ? T1 : T0)) {
+        const int db = v ? d1 : d0, rowbase = v ? d0 : 0;
+#pragma unroll
+        for (int jr = 0; jr < JR; ++jr) {
+          const int c = 16 * JQ + 4 * jr + q4;
+          if (c < W_out) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * tv + 4 * cs + r;
+              if (row < db) out[(int64_t)(rowbase + row) * W_out + c] = accr[G][jr][r];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // Tile slots per wave: the smallest instance (2, 4, 6 or 8) covering
 // the tiles of [A_0 | A_1].
 static int dma_slots(int d0, int d1) {
@@ -976,6 +1281,79 @@ static int pass_dispatch_dma(const float* A0, const float* A1, int64_t n, int d0
   return SRP_EINVAL;
 }
 
+// The 4x4-block pass: two views, each of at most 64 tiles (1024 columns);
+// SV = 2 tile slots per view and wave up to 32 tiles, else 4.  k <= 10
+// with 4 slots (beyond that the registers no longer hold the accumulators
+// and operands of a block without spilling inside the row loop), k <= 16
+// with 2.
+static int quad_sv(int d0, int d1) {
+  const int tmax = std::max((d0 + 15) / 16, (d1 + 15) / 16);
+  return tmax <= 32 ? 2 : tmax <= 64 ? 4 : 0;
+}
+
+static size_t quad_lds_bytes(int sv, int c4) {
+  const size_t pitch = (size_t)quad_pitch(2 * sv);
+  const size_t kg = (size_t)(c4 + 1) / 2;
+  return (2 * kDmaRows * pitch + (size_t)kF32Waves * 4 * kDmaRows * 4 * kg + (size_t)kDmaRows * (4 * c4 + 1)) *
+         sizeof(float);
+}
+
+static bool quad_fits(int d0, int d1, int k, int nb, int vec) {
+  if (nb != 2 || vec == 0 || k < 1) return false;
+  const int sv = quad_sv(d0, d1);
+  const int c4 = (k + 1) / 2;
+  if (sv == 0 || c4 > (sv == 4 ? 5 : 8)) return false;
+  return quad_lds_bytes(sv, c4) <= (size_t)kPassLds + 8 * 1024;
+}
+
+template <int SV, int C4, int VEC>
+static int pass_launch_quad(const float* A0, const float* A1, int64_t n, int d0, int d1, int k, const double* W0,
+                            const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
+                            hipEvent_t before_pass, hipEvent_t after_pass) {
+  const int dp0 = (d0 + 15) / 16 * 16, dp1 = (d1 + 15) / 16 * 16;
+  const int KP = 16;
+  float* Wp0 = ws.take<float>((size_t)dp0 * KP);
+  float* Wp1 = ws.take<float>((size_t)dp1 * KP);
+  const int nrb = (int)((n + kDmaRows - 1) / kDmaRows);
+  // at least 4 blocks per workgroup (fewer partials to add for short data)
+  const int grid = std::max(1, std::min(num_cus(), (nrb + 3) / 4));
+  const int Dtot = d0 + d1;
+  float* part = ws.take<float>((size_t)grid * Dtot * 2 * k);
+  if (!Wp0 || !Wp1 || !part) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
+  SRP_TRY(pack_dirs<float>(W0, d0, dp0, Wp0, W1, d1, dp1, Wp1, k, KP, st));
+  const size_t lds = quad_lds_bytes(SV, C4);
+  SRP_TRY(allow_dynamic_lds((const void*)k_pass_quad<SV, C4, VEC>, kPassLds + 8 * 1024));
+  if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
+  hipLaunchKernelGGL((k_pass_quad<SV, C4, VEC>), dim3(grid), dim3(kF32Threads), lds, st, A0, A1, n, d0, d1, k, Wp0,
+                     Wp1, nrb, part, done);
+  SRP_LAUNCH_CHECK();
+  if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
+  const int64_t count = (int64_t)Dtot * 2 * k;
+  hipLaunchKernelGGL((k_pass_reduce<float>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, grid, d0,
+                     d1, 2 * k, J0, J1, done);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+static int pass_dispatch_quad(const float* A0, const float* A1, int64_t n, int d0, int d1, int k, const double* W0,
+                              const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
+                              hipEvent_t ev0, hipEvent_t ev) {
+  const int vec = dma_vec(A0, A1, d0, d1);
+  const int sv = quad_sv(d0, d1);
+  const int c4 = (k + 1) / 2;
+#define SRP_QUAD_CASE(SV_, C4_)                                                                                     \
+  if (sv == SV_ && c4 == C4_)                                                                                       \
+    return vec == 4 ? pass_launch_quad<SV_, C4_, 4>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev) \
+                    : pass_launch_quad<SV_, C4_, 1>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+  SRP_QUAD_CASE(2, 1) SRP_QUAD_CASE(2, 2) SRP_QUAD_CASE(2, 3) SRP_QUAD_CASE(2, 4)
+  SRP_QUAD_CASE(2, 5) SRP_QUAD_CASE(2, 6) SRP_QUAD_CASE(2, 7) SRP_QUAD_CASE(2, 8)
+  SRP_QUAD_CASE(4, 1) SRP_QUAD_CASE(4, 2) SRP_QUAD_CASE(4, 3) SRP_QUAD_CASE(4, 4)
+  SRP_QUAD_CASE(4, 5)
+#undef SRP_QUAD_CASE
+  set_error("gram_pass: no 4x4-block pass instance for %d slots, k = %d", sv, k);
+  return SRP_EINVAL;
+}
+
 template <class DT, class CT>
 static int pass_dispatch_k(const DT* A0, const DT* A1, int64_t n, int d0, int d1, int k, const double* W0,
                            const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
@@ -983,6 +1361,28 @@ static int pass_dispatch_k(const DT* A0, const DT* A1, int64_t n, int d0, int d1
   if (A1) return pass_launch<DT, CT, 2, 1>(A0, A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
   if (k <= 16) return pass_launch<DT, CT, 1, 1>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
   return pass_launch<DT, CT, 1, 2>(A0, A1, n, d0, 0, k, W0, W1, J0, J1, done, ws, st, ev0, ev);
+}
+
+// Name of the pass kernel gram_pass_run launches for a shape, for rows
+// that start on 16-byte boundaries (the row alignment only changes the
+// load width), or nullptr outside the limits.
+const char* gram_pass_kernel_name(int dtype, int compute, int d0, int d1, int k) {
+  const int nb = d1 > 0 ? 2 : 1;
+  if (nb == 1) d1 = 0;
+  if (!pass_limits_ok(dtype, compute, d0, d1, k, nb)) return nullptr;
+  const int T0 = (d0 + 15) / 16, T1 = nb == 2 ? (d1 + 15) / 16 : 0;
+  const bool al = d0 % 4 == 0 && (nb == 1 || d1 % 4 == 0);
+  if (compute == SRP_BF16) {
+    if (dtype != SRP_BF16) return nullptr;
+    const int bvec = ((d0 * 2) % 4 == 0 && (nb == 1 || (d1 * 2) % 4 == 0)) ? 1 : 0;
+    return bf_fits(d0, d1, k, nb, bvec ? 1 : 0) ? "k_pass_bf" : "k_pass";
+  }
+  if (compute == SRP_F32 && dtype == SRP_F32) {
+    const int vec = (al && T0 >= 16 && (nb == 1 || T1 >= 16)) ? 4 : (T0 >= 4 && (nb == 1 || T1 >= 4)) ? 1 : 0;
+    if (quad_fits(d0, d1, k, nb, vec)) return "k_pass_quad";
+    if (dma_fits(d0, d1, k, nb, vec)) return "k_pass_dma";
+  }
+  return "k_pass";
 }
 
 int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1, int k,
@@ -1015,6 +1415,9 @@ int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_
   } else {
     switch (dtype) {
       case SRP_F32:
+        if (quad_fits(d0, nb == 2 ? d1 : 0, k, nb, dma_vec(A0, A1, d0, d1)))
+          return pass_dispatch_quad((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st,
+                                    before_pass, after_pass);
         if (dma_fits(d0, nb == 2 ? d1 : 0, k, nb, dma_vec(A0, A1, d0, d1)))
           return pass_dispatch_dma((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st,
                                    before_pass, after_pass);

@@ -90,3 +90,21 @@ def test_request_footprint_host_only():
     assert L.srp_cca_workspace_bytes(50000, 300, 200, 8, 100, srp.SRP_F32, 0, srp.SRP_F32) == 0
     assert L.srp_lda_workspace_bytes(50000, 300, 10, 9, 1200, srp.SRP_F32, 0) > 0
     assert L.srp_lda_workspace_bytes(50000, 300, 10, 10, 1200, srp.SRP_F32, 0) == 0
+
+
+def test_pass_kernel_choice_by_shape():
+    """Host-side query of the pass kernel a shape takes (no device work):
+    two FP32 views up to 1024 columns take the 4x4-block pass (k <= 10, or
+    k <= 16 up to 512 columns), other FP32 shapes within the LDS budget the
+    streamed pass, the rest the register-staged one; out of limits: None."""
+    srp = pytest.importorskip("paper_2106_12060_amd")
+    q = srp.srp_gram_pass_kernel
+    assert q("f32", "f32", 1000, 1000, 10) == "k_pass_quad"
+    assert q("f32", "f32", 512, 500, 16) == "k_pass_quad"
+    assert q("f32", "f32", 1000, 1000, 12) == "k_pass_dma"     # 4 slots: k <= 10
+    assert q("f32", "f32", 2000, 0, 12) == "k_pass_dma"        # one view
+    assert q("f32", "f32", 1000, 0, 19) == "k_pass"            # k > 16
+    assert q("f32", "f32", 40, 30, 4) == "k_pass"              # views under 4 tiles
+    assert q("f64", "f64", 300, 200, 8) == "k_pass"
+    assert q("bf16", "bf16", 1000, 1000, 10) == "k_pass_bf"
+    assert q("f32", "f32", 3000, 0, 4) is None                 # past the column limit

@@ -158,6 +158,32 @@ def test_gram_pass_matches_products(n, d0, d1, k, dt, comp):
         assert np.all(np.abs(g - ref) <= bound), np.max(np.abs(g - ref) / bound)
 
 
+# Two FP32 views of at most 1024 columns each take the 4x4-block pass: every
+# tile-slot count (at most 32 / 64 tiles per view), every k class
+# (ceil(k / 2) = 1 .. 8 with 2 slots, .. 6 with 4), 16-byte and 4-byte row
+# loads (columns not a multiple of 4), views of unequal width (tiles without
+# work), fewer rows than one block, ragged last blocks.
+@pytest.mark.parametrize("n,d0,d1,k", [(3001, 512, 500, 1), (3001, 512, 500, 3), (3001, 512, 500, 5),
+                                       (3001, 512, 500, 8), (3001, 512, 500, 9), (3001, 512, 500, 12),
+                                       (3001, 512, 500, 13), (3001, 512, 500, 16),
+                                       (2500, 1000, 1024, 2), (2500, 1000, 1024, 7), (2500, 1000, 1024, 10),
+                                       (2500, 1000, 1024, 11), (1777, 1001, 333, 10), (7, 300, 200, 6),
+                                       (4099, 64, 1000, 11), (513, 70, 90, 4)])
+def test_gram_pass_4x4_blocks(n, d0, d1, k):
+    srp = _srp()
+    rng = np.random.default_rng(7 * n + k)
+    A0, A0q = quantised(rand_data(n, d0, n + k), "f32")
+    A1, A1q = quantised(rand_data(n, d1, n + k + 1), "f32")
+    W0 = rng.standard_normal((d0, k))
+    W1 = rng.standard_normal((d1, k))
+    J, Jabs = stiefel.data_products(A0q, W0, A1q, W1)
+    G0, G1 = srp.srp_gram_pass(A0, torch.from_numpy(W0).to(DEV), A1, torch.from_numpy(W1).to(DEV), compute="f32")
+    for g, ref, mag in zip([G0.cpu().numpy(), G1.cpu().numpy()], J, Jabs):
+        assert g.shape == ref.shape
+        bound = (d0 + d1 + n + 2) * U32 * mag + 1e-300
+        assert np.all(np.abs(g - ref) <= bound), np.max(np.abs(g - ref) / bound)
+
+
 # ---------------------------------------------------------- staging
 def test_stage_bf16_bit_exact():
     from oracle import quant
