@@ -932,6 +932,90 @@ __global__ void k_pack_dir_bf(const double* __restrict__ W0, int d0, int dp0, un
   Wp[i] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
+// Per-block work of k_pass_bf; the LDS regions arrive as separate restrict
+// pointers so that the reads of the current block, the partials and P carry
+// alias scopes disjoint from the next block's in-flight DMA (see quad_step).
+template <int NB, int VEC>
+__device__ __forceinline__ void bf_step(const unsigned short* __restrict__ xs, unsigned short* __restrict__ xnext,
+                                        float* __restrict__ red, unsigned short* __restrict__ pb, int next_rb,
+                                        const unsigned short* A0, const unsigned short* A1, int64_t n, int d0,
+                                        int d1, const BfGeom& G, int nch0, int nch, int w, int lane,
+                                        const bf16x8_t (&wreg)[(kDmaMaxTiles / 2 + kDmaWaves - 1) / kDmaWaves],
+                                        f32x4 (&acc)[(kDmaMaxTiles + kDmaWaves - 1) / kDmaWaves][NB], bool dma_only) {
+  constexpr int R = kBfRows;
+  constexpr int CH = 64 * VEC;
+  constexpr int NT = NB;
+  constexpr int TPB32 = (kDmaMaxTiles / 2 + kDmaWaves - 1) / kDmaWaves;
+  constexpr int TPB = (kDmaMaxTiles + kDmaWaves - 1) / kDmaWaves;
+  const int tid = threadIdx.x;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int pitch = G.pitch;
+  if (next_rb >= 0) {
+    const int nq = R * nch;
+    for (int q = w; q < nq; q += kDmaWaves) {
+      const int r = q / nch, j = q - r * nch;
+      const int64_t row = (int64_t)next_rb * R + r;
+      const bool s1 = (NB == 2) && (j >= nch0);
+      const int jj = s1 ? j - nch0 : j;
+      const int span = (s1 ? G.T1 : G.T0) * 16;
+      const int o = min(jj * CH, span - CH);
+      unsigned short* dst = xnext + r * pitch + (s1 ? G.T0p * 16 : 0) + o;
+      const int voff = (o + lane * VEC) * 2;
+      if (s1) dma_row_chunk_bf<VEC>(make_rsrc(A1 + row * d1, row < n ? (int64_t)d1 * 2 : 0), dst, voff);
+      else dma_row_chunk_bf<VEC>(make_rsrc(A0 + row * d0, row < n ? (int64_t)d0 * 2 : 0), dst, voff);
+    }
+  }
+  if (dma_only) return;
+  const int base_b = l16 * pitch + 8 * g + 32 * w;    // P phase: row l16, columns 32 T + 8 g .. + 7
+  const int base_d = (4 * g) * pitch + l16 + 16 * w;  // J phase: rows 4 g .. 4 g + 3, column 16 t + l16
+  // (b)
+  f32x4 pacc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) pacc[b] = f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < TPB32; ++i) {
+    const int T = w + kDmaWaves * i;
+    if (2 * T < G.TTp) {
+      const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(xs + base_b + 32 * kDmaWaves * i);
+      if (NB == 2 && 2 * T >= G.T0p) pacc[NB - 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[i], pacc[NB - 1], 0, 0, 0);
+      else pacc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[i], pacc[0], 0, 0, 0);
+    }
+  }
+  // (c)
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[(w * NT + b) * 256 + (4 * g + r) * 16 + l16] = pacc[b][r];
+  lds_only_barrier();
+  for (int e = tid; e < NT * 256; e += kDmaThreads) {
+    const int nt = e >> 8, q = e & 255;   // q = row * 16 + pcol
+    float v = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < kDmaWaves; ++ww) v += red[(ww * NT + nt) * 256 + q];
+    const uint32_t u = __float_as_uint(v);
+    pb[nt * 256 + (q & 15) * 16 + (q >> 4)] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  }
+  lds_only_barrier();
+  // (d)
+  s16x4_t bop[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) bop[nt] = *reinterpret_cast<const s16x4_t*>(pb + nt * 256 + l16 * 16 + 4 * g);
+#pragma unroll
+  for (int i = 0; i < TPB; ++i) {
+    const int t = w + kDmaWaves * i;
+    if (t < G.TTp) {
+      const unsigned short* xp = xs + base_d + 16 * kDmaWaves * i;
+      s16x4_t a;
+      a[0] = (short)xp[0];
+      a[1] = (short)xp[pitch];
+      a[2] = (short)xp[2 * pitch];
+      a[3] = (short)xp[3 * pitch];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bop[nt], acc[i][nt], 0, 0, 0);
+    }
+  }
+}
+
 template <int NB, int VEC>
 __global__ void __launch_bounds__(kDmaThreads) k_pass_bf(const unsigned short* __restrict__ A0,
                                                          const unsigned short* __restrict__ A1, int64_t n, int d0,
@@ -988,78 +1072,16 @@ __global__ void __launch_bounds__(kDmaThreads) k_pass_bf(const unsigned short* _
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
 
-  auto issue_block = [&](int rbk, unsigned short* xb) __attribute__((always_inline)) {
-    const int nq = R * nch;
-    for (int q = w; q < nq; q += kDmaWaves) {
-      const int r = q / nch, j = q - r * nch;
-      const int64_t row = (int64_t)rbk * R + r;
-      const bool s1 = (NB == 2) && (j >= nch0);
-      const int jj = s1 ? j - nch0 : j;
-      const int span = (s1 ? G.T1 : G.T0) * 16;
-      const int o = min(jj * CH, span - CH);
-      unsigned short* dst = xb + r * pitch + (s1 ? G.T0p * 16 : 0) + o;
-      const int voff = (o + lane * VEC) * 2;
-      if (s1) dma_row_chunk_bf<VEC>(make_rsrc(A1 + row * d1, row < n ? (int64_t)d1 * 2 : 0), dst, voff);
-      else dma_row_chunk_bf<VEC>(make_rsrc(A0 + row * d0, row < n ? (int64_t)d0 * 2 : 0), dst, voff);
-    }
-  };
-
-  const int base_b = l16 * pitch + 8 * g + 32 * w;    // P phase: row l16, columns 32 T + 8 g .. + 7
-  const int base_d = (4 * g) * pitch + l16 + 16 * w;  // J phase: rows 4 g .. 4 g + 3, column 16 t + l16
   int rb = blockIdx.x;
   int boff = 0;
-  if (rb < nrb) issue_block(rb, bsm);
+  if (rb < nrb)
+    bf_step<NB, VEC>(bsm + R * pitch, bsm, red, pb, rb, A0, A1, n, d0, d1, G, nch0, nch, w, lane, wreg, acc, true);
   for (; rb < nrb; rb += gridDim.x) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    const unsigned short* xs = bsm + boff;
-    if (rb + (int)gridDim.x < nrb) issue_block(rb + gridDim.x, bsm + (R * pitch - boff));
-    // (b)
-    f32x4 pacc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) pacc[b] = f32x4{0, 0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < TPB32; ++i) {
-      const int T = w + kDmaWaves * i;
-      if (2 * T < G.TTp) {
-        const bf16x8_t a = *reinterpret_cast<const bf16x8_t*>(xs + base_b + 32 * kDmaWaves * i);
-        if (NB == 2 && 2 * T >= G.T0p) pacc[NB - 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[i], pacc[NB - 1], 0, 0, 0);
-        else pacc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wreg[i], pacc[0], 0, 0, 0);
-      }
-    }
-    // (c)
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) red[(w * NT + b) * 256 + (4 * g + r) * 16 + l16] = pacc[b][r];
-    lds_only_barrier();
-    for (int e = tid; e < NT * 256; e += kDmaThreads) {
-      const int nt = e >> 8, q = e & 255;   // q = row * 16 + pcol
-      float v = 0.f;
-#pragma unroll
-      for (int ww = 0; ww < kDmaWaves; ++ww) v += red[(ww * NT + nt) * 256 + q];
-      const uint32_t u = __float_as_uint(v);
-      pb[nt * 256 + (q & 15) * 16 + (q >> 4)] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
-    }
-    lds_only_barrier();
-    // (d)
-    s16x4_t bop[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) bop[nt] = *reinterpret_cast<const s16x4_t*>(pb + nt * 256 + l16 * 16 + 4 * g);
-#pragma unroll
-    for (int i = 0; i < TPB; ++i) {
-      const int t = w + kDmaWaves * i;
-      if (t < G.TTp) {
-        const unsigned short* xp = xs + base_d + 16 * kDmaWaves * i;
-        s16x4_t a;
-        a[0] = (short)xp[0];
-        a[1] = (short)xp[pitch];
-        a[2] = (short)xp[2 * pitch];
-        a[3] = (short)xp[3 * pitch];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[i][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bop[nt], acc[i][nt], 0, 0, 0);
-      }
-    }
+    const int nxt = rb + (int)gridDim.x < nrb ? rb + (int)gridDim.x : -1;
+    bf_step<NB, VEC>(bsm + boff, bsm + (R * pitch - boff), red, pb, nxt, A0, A1, n, d0, d1, G, nch0, nch, w, lane,
+                     wreg, acc, false);
     boff = R * pitch - boff;
   }
   // epilogue: tile t of the padded space -> block and tile, pads skipped
