@@ -227,7 +227,8 @@ int srp_gram_pass(const void* A0, const void* A1, int dtype, int compute,
 /* Name of the kernel srp_gram_pass (and the solvers' iterations) run for
  * this shape, when the rows start on 16-byte boundaries (alignment only
  * changes the load width): "k_pass_quad" (FP32, two views of at most 1024
- * columns, 4x4 matrix-core blocks for the narrow products), "k_pass_dma"
+ * columns, 4x4 matrix-core blocks for the narrow products), "k_pass_quad1"
+ * (FP32, one view, k <= 20, the same blocks), "k_pass_dma"
  * (FP32, rows streamed into LDS), "k_pass_bf" (BF16 matrix cores) or
  * "k_pass" (register-staged rows).  Static string; NULL outside the limits
  * above.  No device work.

@@ -811,6 +811,257 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restri
   }
 }
 
+// ------------------------------------------------------------------
+// FP32, one view (FDA: J = A^T (A W), k <= 20): the same row stream with
+// the narrow products on 4x4 blocks.
+//   * P = A W (8 rows x k): wave w takes tiles w + 16 (4 G + g) (the four
+//     16-lane rows g of an instruction take four tiles); a block is 4 rows
+//     x 4 direction columns over one column in four; rows 0-3 and 4-7 are
+//     done one after the other (20 accumulator registers at k = 20).  The
+//     column phases are summed by two DPP rotations and the four tiles of
+//     an instruction by two lane-row swaps (v_permlane16_swap,
+//     v_permlane32_swap), so each wave publishes one 8 x 4 KG partial.
+//   * J = A^T P: whole 16-column tiles of P on 16x16x4, the remaining
+//     4-column groups on 4x4 blocks over four tiles at once, as above.
+// Wave w owns J slots w + 16 i (i < TPB); slots and P tiles past the last
+// tile have zero directions and their rows are not stored.
+__device__ __forceinline__ float lane_rows_sum(float x) {
+  // Sum over the four 16-lane rows, in every lane: v_permlane16_swap on two
+  // copies of x leaves rows (1, 0, 3, 2) in one and (0, 1, 2, 3) in the
+  // other, so their sum holds rows 0 + 1 and 2 + 3; v_permlane32_swap then
+  // adds the halves.  Written as asm with both registers read and written:
+  // the compiler's builtin for these swaps drops the second result.  The
+  // s_nop pairs give the VALU-write / permlane wait states.
+  float a = x, b = x;
+  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+  float c = a + b, d = a + b;
+  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(c), "+v"(d));
+  return c + d;
+}
+
+template <int TPB, int KG>
+struct Quad1Shape {
+  static constexpr int PG = TPB / 4;        // 4-tile groups of a wave's P products
+  static constexpr int JQ = KG / 4;         // whole 16-column tiles of P
+  static constexpr int JR = KG % 4;         // remaining 4-column groups
+  static constexpr int NG = TPB / 4;        // 4-slot groups of the remainder products
+  static constexpr int PP = 4 * KG + 1;     // row pitch of P in LDS
+  static constexpr int RED = kDmaRows * 4 * KG;
+};
+
+template <int TPB, int KG, int VEC>
+__device__ __forceinline__ void quad1_step(const float* __restrict__ xs, float* __restrict__ xnext,
+                                           float* __restrict__ red, float* __restrict__ pfull, int64_t next_row0,
+                                           const float* A0, int64_t n, int d0, int k, int T0, int nch0, int pitch,
+                                           int w, int lane, const float (&wreg)[TPB / 4][4][KG],
+                                           f32x4 (&acc)[TPB][Quad1Shape<TPB, KG>::JQ > 0 ? Quad1Shape<TPB, KG>::JQ : 1],
+                                           f32x4 (&accr)[TPB / 4][Quad1Shape<TPB, KG>::JR > 0 ? Quad1Shape<TPB, KG>::JR : 1],
+                                           bool dma_only) {
+  using Q = Quad1Shape<TPB, KG>;
+  constexpr int R = kDmaRows;
+  constexpr int CH = 64 * VEC;
+  constexpr int JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG, RED = Q::RED;
+  const int tid = threadIdx.x;
+  const int g = lane >> 4, l16 = lane & 15, cs = (lane >> 2) & 3, q4 = lane & 3;
+  if (next_row0 >= 0) {
+    const int rows = (int)(n - next_row0 < R ? n - next_row0 : R);
+    const __amdgpu_buffer_rsrc_t r0 = make_rsrc(A0 + next_row0 * d0, (int64_t)rows * d0 * 4);
+    const int span = T0 * 16;
+    const int db4 = d0 * 4;
+    for (int j = w; j < nch0; j += kF32Waves) {
+      const int o = min(j * CH, span - CH);
+      float* dst = xnext + o;
+      const int vbase = (o + lane * VEC) * 4;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dma_row_chunk<VEC>(r0, dst + r * pitch, vbase + r * db4);
+    }
+  }
+  if (dma_only) return;
+  // (b) P partial of this wave: rows 4 rg + q4, one half at a time; with
+  // five direction-column groups also in two passes over the groups (the
+  // accumulators of all five would not fit beside the J accumulators)
+  constexpr int KH = KG >= 5 ? (KG + 1) / 2 : KG;
+#pragma unroll
+  for (int rg = 0; rg < 2; ++rg)
+#pragma unroll
+  for (int k0 = 0; k0 < KG; k0 += KH) {
+    f32x4 pacc[KH];
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) pacc[kk] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int G = 0; G < PG; ++G) {
+      const int col = 16 * (w + 16 * (4 * G + g)) + 4 * cs;
+      const float4 a = *reinterpret_cast<const float4*>(xs + (4 * rg + q4) * pitch + col);
+      const float av[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int kk = 0; kk < KH; ++kk)
+          if (k0 + kk < KG) pacc[kk] = mfma4x4(av[s], wreg[G][s][k0 + kk], pacc[kk]);
+    }
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (k0 + kk >= KG) continue;
+        float x = pacc[kk][r];
+        x += dpp_row_ror<4>(x);
+        x += dpp_row_ror<8>(x);
+        x = lane_rows_sum(x);
+        if (lane < 4) red[w * RED + (4 * rg + r) * (4 * KG) + 4 * (k0 + kk) + q4] = x;
+      }
+  }
+  lds_only_barrier();
+  if (tid < RED) {   // sum over the 16 waves, in a fixed order
+    int t = tid;
+    asm volatile("" : "+v"(t));
+    const int row = t / (4 * KG), col = t - row * (4 * KG);
+    float sum = 0.f;
+#pragma unroll
+    for (int h = 0; h < kF32Waves; ++h) sum += red[h * RED + t];
+    if (col < k) pfull[row * PP + col] = sum;
+  }
+  lds_only_barrier();
+  // (d) J = A^T P
+  if constexpr (JQ > 0) {
+    float pb[2][JQ];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int jq = 0; jq < JQ; ++jq) pb[s][jq] = pfull[(g + 4 * s) * PP + 16 * jq + l16];
+#pragma unroll
+    for (int i = 0; i < TPB; ++i) {
+      const int col = 16 * (w + 16 * i);
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const float a = xs[(g + 4 * s) * pitch + col + l16];
+#pragma unroll
+        for (int jq = 0; jq < JQ; ++jq) acc[i][jq] = mfma16x16x4(a, pb[s][jq], acc[i][jq]);
+      }
+    }
+  }
+  if constexpr (JR > 0) {
+#pragma unroll
+    for (int rho = 0; rho < R; ++rho) {
+      const int row = (rho + g) & (R - 1);
+      float b[JR];
+#pragma unroll
+      for (int jr = 0; jr < JR; ++jr) b[jr] = pfull[row * PP + 16 * JQ + 4 * jr + q4];
+#pragma unroll
+      for (int G = 0; G < NG; ++G) {
+        const float a = xs[row * pitch + 16 * (w + 16 * (4 * G + g)) + l16];
+#pragma unroll
+        for (int jr = 0; jr < JR; ++jr) accr[G][jr] = mfma4x4(a, b[jr], accr[G][jr]);
+      }
+    }
+  }
+}
+
+template <int TPB, int KG, int VEC>
+__global__ void __launch_bounds__(kF32Threads) k_pass_quad1(const float* __restrict__ A0, int64_t n, int d0, int k,
+                                                            const float* __restrict__ Wp0, int nrb,
+                                                            float* __restrict__ partial, const int* __restrict__ done) {
+  if (done && *done) return;
+  using Q = Quad1Shape<TPB, KG>;
+  constexpr int R = kDmaRows;
+  constexpr int CH = 64 * VEC;
+  constexpr int JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG, RED = Q::RED;
+  extern __shared__ float dsm[];
+  const int T0 = (d0 + 15) >> 4;
+  const int nch0 = (T0 * 16 + CH - 1) / CH;
+  const int pitch = quad_pitch(TPB);
+  float* red = dsm + 2 * R * pitch;          // [wave][R][4 KG]
+  float* pfull = red + kF32Waves * RED;      // [R][PP]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, l16 = lane & 15, cs = (lane >> 2) & 3, q4 = lane & 3;
+
+  // direction operands of the P blocks: tile w + 16 (4 G + g), its column
+  // 4 cs + s, direction column 4 kg + q4 (the packed directions are 4 KG
+  // columns wide)
+  const __amdgpu_buffer_rsrc_t wrs = make_rsrc(Wp0, (int64_t)T0 * 16 * (4 * KG) * 4);
+  float wreg[PG][4][KG];
+#pragma unroll
+  for (int G = 0; G < PG; ++G) {
+    const int tv = w + 16 * (4 * G + g);
+    const bool ok = tv < T0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int kg = 0; kg < KG; ++kg) {
+        const int off = ok ? ((16 * tv + 4 * cs + s) * (4 * KG) + 4 * kg + q4) * 4 : kOob;
+        wreg[G][s][kg] = buf_load<float>(wrs, off, 0);
+      }
+  }
+  f32x4 acc[TPB][JQ > 0 ? JQ : 1];
+  f32x4 accr[NG][JR > 0 ? JR : 1];
+#pragma unroll
+  for (int i = 0; i < TPB; ++i)
+#pragma unroll
+    for (int j = 0; j < (JQ > 0 ? JQ : 1); ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int G = 0; G < NG; ++G)
+#pragma unroll
+    for (int j = 0; j < (JR > 0 ? JR : 1); ++j) accr[G][j] = f32x4{0, 0, 0, 0};
+  for (int e = tid; e < 2 * R * pitch; e += kF32Threads) dsm[e] = 0.f;
+  for (int e = tid; e < R * PP; e += kF32Threads) pfull[e] = 0.f;
+  __syncthreads();
+
+  int rb = blockIdx.x;
+  int boff = 0;
+  if (rb < nrb)
+    quad1_step<TPB, KG, VEC>(dsm + R * pitch, dsm, red, pfull, (int64_t)rb * R, A0, n, d0, k, T0, nch0, pitch, w,
+                             lane, wreg, acc, accr, true);
+  for (; rb < nrb; rb += gridDim.x) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int64_t nxt = rb + (int)gridDim.x < nrb ? (int64_t)(rb + gridDim.x) * R : -1;
+    quad1_step<TPB, KG, VEC>(dsm + boff, dsm + (R * pitch - boff), red, pfull, nxt, A0, n, d0, k, T0, nch0, pitch,
+                             w, lane, wreg, acc, accr, false);
+    boff = R * pitch - boff;
+  }
+  // epilogue: this workgroup's partial (d0 x k)
+  float* out = partial + (int64_t)blockIdx.x * d0 * k;
+  if constexpr (JQ > 0) {
+#pragma unroll
+    for (int i = 0; i < TPB; ++i) {
+      const int tv = w + 16 * i;
+      if (tv < T0) {
+#pragma unroll
+        for (int jq = 0; jq < JQ; ++jq) {
+          const int c = 16 * jq + l16;
+          if (c < k) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * tv + acc_row<float>(lane, r);
+              if (row < d0) out[(int64_t)row * k + c] = acc[i][jq][r];
+            }
+          }
+        }
+      }
+    }
+  }
+  if constexpr (JR > 0) {
+#pragma unroll
+    for (int G = 0; G < NG; ++G) {
+      const int tv = w + 16 * (4 * G + g);
+      if (tv < T0) {
+#pragma unroll
+        for (int jr = 0; jr < JR; ++jr) {
+          const int c = 16 * JQ + 4 * jr + q4;
+          if (c < k) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * tv + 4 * cs + r;
+              if (row < d0) out[(int64_t)row * k + c] = accr[G][jr][r];
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
 // Tile slots per wave: the smallest instance (2, 4, 6 or 8) covering
 // the tiles of [A_0 | A_1].
 static int dma_slots(int d0, int d1) {
@@ -1376,6 +1627,67 @@ static int pass_dispatch_quad(const float* A0, const float* A1, int64_t n, int d
   return SRP_EINVAL;
 }
 
+// The one-view 4x4-block pass: k <= 20, at most 128 tiles (2048 columns);
+// 4 J slots per wave up to 64 tiles, else 8.
+static int quad1_tpb(int d0) {
+  const int T0 = (d0 + 15) / 16;
+  return T0 <= 64 ? 4 : T0 <= 128 ? 8 : 0;
+}
+
+static size_t quad1_lds_bytes(int tpb, int kg) {
+  return (2 * kDmaRows * (size_t)quad_pitch(tpb) + (size_t)kF32Waves * kDmaRows * 4 * kg +
+          (size_t)kDmaRows * (4 * kg + 1)) * sizeof(float);
+}
+
+static bool quad1_fits(int d0, int k, int nb, int vec) {
+  if (nb != 1 || vec == 0 || k < 1 || k > 20) return false;
+  const int tpb = quad1_tpb(d0);
+  if (tpb == 0) return false;
+  return quad1_lds_bytes(tpb, (k + 3) / 4) <= (size_t)kPassLds + 8 * 1024;
+}
+
+template <int TPB, int KG, int VEC>
+static int pass_launch_quad1(const float* A0, int64_t n, int d0, int k, const double* W0, double* J0,
+                             const int* done, Arena& ws, hipStream_t st, hipEvent_t before_pass,
+                             hipEvent_t after_pass) {
+  const int dp0 = (d0 + 15) / 16 * 16;
+  const int KP = 4 * KG;
+  float* Wp0 = ws.take<float>((size_t)dp0 * KP);
+  const int nrb = (int)((n + kDmaRows - 1) / kDmaRows);
+  const int grid = std::max(1, std::min(num_cus(), (nrb + 3) / 4));
+  float* part = ws.take<float>((size_t)grid * d0 * k);
+  if (!Wp0 || !part) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
+  SRP_TRY(pack_dirs<float>(W0, d0, dp0, Wp0, nullptr, 0, 0, nullptr, k, KP, st));
+  const size_t lds = quad1_lds_bytes(TPB, KG);
+  SRP_TRY(allow_dynamic_lds((const void*)k_pass_quad1<TPB, KG, VEC>, kPassLds + 8 * 1024));
+  if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
+  hipLaunchKernelGGL((k_pass_quad1<TPB, KG, VEC>), dim3(grid), dim3(kF32Threads), lds, st, A0, n, d0, k, Wp0, nrb,
+                     part, done);
+  SRP_LAUNCH_CHECK();
+  if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
+  const int64_t count = (int64_t)d0 * k;
+  hipLaunchKernelGGL((k_pass_reduce<float>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, grid, d0,
+                     0, k, J0, (double*)nullptr, done);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+static int pass_dispatch_quad1(const float* A0, int64_t n, int d0, int k, const double* W0, double* J0,
+                               const int* done, Arena& ws, hipStream_t st, hipEvent_t ev0, hipEvent_t ev) {
+  const int vec = dma_vec(A0, nullptr, d0, 0);
+  const int tpb = quad1_tpb(d0);
+  const int kg = (k + 3) / 4;
+#define SRP_QUAD1_CASE(TPB_, KG_)                                                                              \
+  if (tpb == TPB_ && kg == KG_)                                                                                \
+    return vec == 4 ? pass_launch_quad1<TPB_, KG_, 4>(A0, n, d0, k, W0, J0, done, ws, st, ev0, ev)            \
+                    : pass_launch_quad1<TPB_, KG_, 1>(A0, n, d0, k, W0, J0, done, ws, st, ev0, ev);
+  SRP_QUAD1_CASE(4, 1) SRP_QUAD1_CASE(4, 2) SRP_QUAD1_CASE(4, 3) SRP_QUAD1_CASE(4, 4) SRP_QUAD1_CASE(4, 5)
+  SRP_QUAD1_CASE(8, 1) SRP_QUAD1_CASE(8, 2) SRP_QUAD1_CASE(8, 3) SRP_QUAD1_CASE(8, 4) SRP_QUAD1_CASE(8, 5)
+#undef SRP_QUAD1_CASE
+  set_error("gram_pass: no one-view 4x4-block pass instance for %d slots, k = %d", tpb, k);
+  return SRP_EINVAL;
+}
+
 template <class DT, class CT>
 static int pass_dispatch_k(const DT* A0, const DT* A1, int64_t n, int d0, int d1, int k, const double* W0,
                            const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
@@ -1401,6 +1713,7 @@ const char* gram_pass_kernel_name(int dtype, int compute, int d0, int d1, int k)
   }
   if (compute == SRP_F32 && dtype == SRP_F32) {
     const int vec = (al && T0 >= 16 && (nb == 1 || T1 >= 16)) ? 4 : (T0 >= 4 && (nb == 1 || T1 >= 4)) ? 1 : 0;
+    if (quad1_fits(d0, k, nb, vec)) return "k_pass_quad1";
     if (quad_fits(d0, d1, k, nb, vec)) return "k_pass_quad";
     if (dma_fits(d0, d1, k, nb, vec)) return "k_pass_dma";
   }
@@ -1437,6 +1750,8 @@ int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_
   } else {
     switch (dtype) {
       case SRP_F32:
+        if (quad1_fits(d0, k, nb, dma_vec(A0, A1, d0, d1)))
+          return pass_dispatch_quad1((const float*)A0, n, d0, k, W0, J0, done, ws, st, before_pass, after_pass);
         if (quad_fits(d0, nb == 2 ? d1 : 0, k, nb, dma_vec(A0, A1, d0, d1)))
           return pass_dispatch_quad((const float*)A0, (const float*)A1, n, d0, d1, k, W0, W1, J0, J1, done, ws, st,
                                     before_pass, after_pass);

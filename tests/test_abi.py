@@ -95,15 +95,17 @@ def test_request_footprint_host_only():
 def test_pass_kernel_choice_by_shape():
     """Host-side query of the pass kernel a shape takes (no device work):
     two FP32 views up to 1024 columns take the 4x4-block pass (k <= 10, or
-    k <= 16 up to 512 columns), other FP32 shapes within the LDS budget the
-    streamed pass, the rest the register-staged one; out of limits: None."""
+    k <= 16 up to 512 columns), one FP32 view with k <= 20 the one-view
+    4x4-block pass, other FP32 shapes within the LDS budget the streamed
+    pass, the rest the register-staged one; out of limits: None."""
     srp = pytest.importorskip("paper_2106_12060_amd")
     q = srp.srp_gram_pass_kernel
     assert q("f32", "f32", 1000, 1000, 10) == "k_pass_quad"
     assert q("f32", "f32", 512, 500, 16) == "k_pass_quad"
     assert q("f32", "f32", 1000, 1000, 12) == "k_pass_dma"     # 4 slots: k <= 10
-    assert q("f32", "f32", 2000, 0, 12) == "k_pass_dma"        # one view
-    assert q("f32", "f32", 1000, 0, 19) == "k_pass"            # k > 16
+    assert q("f32", "f32", 2000, 0, 12) == "k_pass_quad1"      # one view
+    assert q("f32", "f32", 2000, 0, 19) == "k_pass_quad1"
+    assert q("f32", "f32", 2000, 0, 24) == "k_pass"            # one view, k > 20
     assert q("f32", "f32", 40, 30, 4) == "k_pass"              # views under 4 tiles
     assert q("f64", "f64", 300, 200, 8) == "k_pass"
     assert q("bf16", "bf16", 1000, 1000, 10) == "k_pass_bf"

@@ -184,6 +184,27 @@ def test_gram_pass_4x4_blocks(n, d0, d1, k):
         assert np.all(np.abs(g - ref) <= bound), np.max(np.abs(g - ref) / bound)
 
 
+# One FP32 view of at most 2048 columns with k <= 20 takes the one-view
+# 4x4-block pass: 4 and 8 tile slots, one to five direction-column groups
+# (whole 16-column P tiles and 4-column remainders), 4-byte row loads,
+# fewer rows than one block, the widest view.
+@pytest.mark.parametrize("n,d,k", [(3001, 1000, 1), (3001, 1000, 4), (3001, 1000, 7), (3001, 1000, 12),
+                                   (3001, 1000, 16), (3001, 1000, 19), (3001, 1000, 20), (2500, 2000, 3),
+                                   (2500, 2000, 9), (2500, 2000, 13), (2500, 2000, 19), (2500, 2000, 20),
+                                   (1777, 1001, 10), (7, 300, 6), (4099, 2048, 17), (513, 70, 5)])
+def test_gram_pass_4x4_blocks_one_view(n, d, k):
+    srp = _srp()
+    rng = np.random.default_rng(11 * n + k)
+    A, Aq = quantised(rand_data(n, d, n + 3 * k), "f32")
+    W = rng.standard_normal((d, k))
+    J, Jabs = stiefel.data_products(Aq, W)
+    G, _ = srp.srp_gram_pass(A, torch.from_numpy(W).to(DEV), compute="f32")
+    g, ref, mag = G.cpu().numpy(), J[0], Jabs[0]
+    assert g.shape == ref.shape
+    bound = (d + n + 2) * U32 * mag + 1e-300
+    assert np.all(np.abs(g - ref) <= bound), np.max(np.abs(g - ref) / bound)
+
+
 # ---------------------------------------------------------- staging
 def test_stage_bf16_bit_exact():
     from oracle import quant
