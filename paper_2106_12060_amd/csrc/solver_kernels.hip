@@ -803,67 +803,89 @@ int launch_update(const ProbView& p, int refresh, hipStream_t st) {
 // Parallel cyclic Jacobi (round-robin pairs) on a symmetric n x n matrix
 // (n even, <= 64) by ONE wave: A is overwritten by the (near) diagonal
 // matrix and V accumulates the rotations, A_in = V D V^T.  Scratch: T
-// (2 n x n), and per-index tables of n entries.
+// (2 n x n; A and V alternate with it round by round) and the rotation
+// of each index.  Round r pairs the indices in slots i and n - 1 - i,
+// slot 0 holding index 0 and slot s > 0 index 1 + (s - 1 + r) mod (n - 1);
+// a lane finds the partner of an index from that rule, so a round reads
+// the rotations and the matrix entries in one batch.
 struct WaveJacobiScratch {
-  int pos[64];
-  int partner[64];
-  int isp[64];
-  double rc[64];
-  double rs[64];
+  double rc[64];   // cosine of the rotation of index i
+  double rs[64];   // signed sine: -s for the first index of a pair, +s for the second
 };
+
+__device__ __forceinline__ int jac_index(int slot, int round, int n1) {
+  if (slot == 0) return 0;
+  int x = slot - 1 + round;
+  if (x >= n1) x -= n1;
+  return 1 + x;
+}
+__device__ __forceinline__ int jac_partner(int idx, int round, int n) {
+  const int n1 = n - 1;
+  int slot = 0;
+  if (idx != 0) {
+    int x = idx - 1 - round;
+    if (x < 0) x += n1;
+    slot = 1 + x;
+  }
+  return jac_index(n1 - slot, round, n1);
+}
 
 __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, WaveJacobiScratch& w,
                             double tol2 = 1e-30) {
-  const int nn = n * n;
+  const int nn = n * n, n1 = n - 1;
+  double* a = A;
+  double* v = V;
+  double* a2 = T;
+  double* v2 = T + nn;
   for (int e = lane; e < nn; e += 64) V[e] = (e == sdiv(e, n) * (n + 1)) ? 1.0 : 0.0;
   wave_sync();
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off = 0.0, dia = 0.0;
     for (int e = lane; e < nn; e += 64) {
-      const double v = A[e];
-      if (e == sdiv(e, n) * (n + 1)) dia += v * v; else off += v * v;
+      const double x = a[e];
+      if (e == sdiv(e, n) * (n + 1)) dia += x * x; else off += x * x;
     }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_xor(off, o, 64);
       dia += __shfl_xor(dia, o, 64);
     }
     if (off <= tol2 * (dia + 1e-300)) break;
-    for (int round = 0; round < n - 1; ++round) {
-      if (lane < n) w.pos[lane] = (lane == 0) ? 0 : 1 + ((lane - 1 + round) % (n - 1));
-      wave_sync();
+    for (int round = 0; round < n1; ++round) {
       if (lane < n / 2) {
-        int pp = w.pos[lane], qq = w.pos[n - 1 - lane];
+        int pp = jac_index(lane, round, n1), qq = jac_index(n1 - lane, round, n1);
         if (pp > qq) { const int tmp = pp; pp = qq; qq = tmp; }
-        const double apq = A[pp * n + qq];
+        const double apq = a[pp * n + qq], app = a[pp * n + pp], aqq = a[qq * n + qq];
         double cth = 1.0, sth = 0.0;
         if (apq != 0.0) {
-          const double theta = (A[qq * n + qq] - A[pp * n + pp]) / (2.0 * apq);
+          const double theta = (aqq - app) / (2.0 * apq);
           const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
           cth = 1.0 / sqrt(tt * tt + 1.0);
           sth = tt * cth;
         }
-        w.rc[pp] = cth; w.rs[pp] = sth; w.rc[qq] = cth; w.rs[qq] = sth;
-        w.partner[pp] = qq; w.partner[qq] = pp;
-        w.isp[pp] = 1; w.isp[qq] = 0;
+        w.rc[pp] = cth; w.rs[pp] = -sth;
+        w.rc[qq] = cth; w.rs[qq] = sth;
       }
       wave_sync();
-      // A' = J^T A J, V' = V J with J[p][p]=c, J[p][q]=s, J[q][p]=-s, J[q][q]=c
+      // A' = J^T A J, V' = V J with J[p][p] = c, J[p][q] = s, J[q][p] = -s, J[q][q] = c
       for (int e = lane; e < nn; e += 64) {
         const int r = sdiv(e, n), col = e - r * n;
-        const int pr = w.partner[r], pc = w.partner[col];
-        const double jrr = w.rc[r], jpr = w.isp[r] ? -w.rs[r] : w.rs[r];
-        const double jcc = w.rc[col], jpc = w.isp[col] ? -w.rs[col] : w.rs[col];
-        T[e] = jrr * (jcc * A[r * n + col] + jpc * A[r * n + pc]) + jpr * (jcc * A[pr * n + col] + jpc * A[pr * n + pc]);
-        T[nn + e] = V[r * n + col] * jcc + V[r * n + pc] * jpc;
+        const int pr = jac_partner(r, round, n), pc = jac_partner(col, round, n);
+        const double cr = w.rc[r], sr = w.rs[r], cc = w.rc[col], sc = w.rs[col];
+        a2[e] = cr * (cc * a[r * n + col] + sc * a[r * n + pc]) + sr * (cc * a[pr * n + col] + sc * a[pr * n + pc]);
+        v2[e] = v[r * n + col] * cc + v[r * n + pc] * sc;
       }
       wave_sync();
-      for (int e = lane; e < nn; e += 64) {
-        A[e] = T[e];
-        V[e] = T[nn + e];
-      }
-      wave_sync();
+      double* t = a; a = a2; a2 = t;
+      t = v; v = v2; v2 = t;
     }
   }
+  if (a != A) {
+    for (int e = lane; e < nn; e += 64) {
+      A[e] = a[e];
+      V[e] = v[e];
+    }
+  }
+  wave_sync();
 }
 
 // ------------------------------------------------------- direction
