@@ -116,8 +116,12 @@ def serve(args):
     trace = synth.serving_trace(args.requests, args.rate)
     print(f"bench: serving trace of {len(trace)} requests at {args.rate}/s; drawing the data on the device",
           file=sys.stderr, flush=True)
-    w0 = synth.workload("cca-f64-small")   # the per-request recipe
-    data = [synth.cca_latent_device(q.n, q.dx, q.dy, r=w0.r, noise=w0.noise, factor_decades=w0.factor_decades,
+    # the per-request recipe: that of the FP64 workload with as many latent
+    # factors as the largest k of the trace, so that every request's top k
+    # correlations come from the factors rather than from the noise
+    w0 = synth.workload("cca-f64-small")
+    r_serve = max(max(q.k for q in trace), w0.r)
+    data = [synth.cca_latent_device(q.n, q.dx, q.dy, r=r_serve, noise=w0.noise, factor_decades=w0.factor_decades,
                                     x_decades=w0.x_decades, seed=q.seed) for q in trace]
     torch.cuda.synchronize()
     data_bytes = sum(X.numel() * 4 + Y.numel() * 4 for X, Y in data)
@@ -182,7 +186,7 @@ def serve(args):
            "config": {"workload": f"serving-cca-{len(trace)}req-poisson{args.rate:g}", "requests": len(trace),
                       "rate_per_s": args.rate, "n_range": [5000, 100000], "d_range": [64, 1024],
                       "k_range": [2, 16], "lambda": lam, "sketch": "countsketch", "s": "4 max(dx, dy)",
-                      "tol": tol, "weights": "equal", "warm_start_iters": warm, "slots": args.slots,
+                      "tol": tol, "weights": "equal", "latent_factors": r_serve, "warm_start_iters": warm, "slots": args.slots,
                       "pool_gib": args.pool_gib, "stage": args.stage, "parallelism": "single-gpu",
                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
                       "data_bytes_resident": data_bytes},
