@@ -888,6 +888,93 @@ __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, Wa
   wave_sync();
 }
 
+// The same rotations by a whole workgroup, one group of waves per matrix:
+// nv symmetric n x n matrices (n even, <= 64; nv <= 2), matrix v handled
+// by the threads with tid % nv == v (gt = tid / nv in the group, GW =
+// blockDim / nv of them).  Every thread of the block calls it; the rounds
+// are separated by block barriers, and a matrix that has converged stops
+// rotating (its group only takes the barriers) while the others go on, so
+// each matrix gets the same sweeps as alone.  (Further sweeps of a
+// converged matrix would rotate freely inside nearly equal eigenvalues.)
+// psum holds one (off, dia) pair per wave; the group sums read it in wave
+// order, so every thread takes the same decisions.
+__device__ void block_jacobi(double* const* Av, double* const* Vv, double* const* Tv, WaveJacobiScratch* w,
+                             double (*psum)[2], int nv, int n, double tol2) {
+  const int tid = threadIdx.x, nt = blockDim.x, nwaves = nt >> 6;
+  const int v = tid % nv, gt = tid / nv, GW = nt / nv;
+  const int nn = n * n, n1 = n - 1;
+  double* a = Av[v];
+  double* vv = Vv[v];
+  double* a2 = Tv[v];
+  double* v2 = Tv[v] + nn;
+  for (int e = gt; e < nn; e += GW) vv[e] = (e == sdiv(e, n) * (n + 1)) ? 1.0 : 0.0;
+  int flips = 0;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = gt; e < nn; e += GW) {
+      const double x = a[e];
+      if (e == sdiv(e, n) * (n + 1)) dia += x * x; else off += x * x;
+    }
+    // per wave: lanes of one wave alternate between the matrices when nv = 2,
+    // so reduce the lanes of each parity separately
+    for (int o = 32; o >= nv; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
+    }
+    if ((tid & 63) < nv) { psum[(tid >> 6) * nv + v][0] = off; psum[(tid >> 6) * nv + v][1] = dia; }
+    __syncthreads();
+    bool all = true, act = false;
+    for (int m = 0; m < nv; ++m) {
+      double so = 0.0, sd = 0.0;
+      for (int q = 0; q < nwaves; ++q) { so += psum[q * nv + m][0]; sd += psum[q * nv + m][1]; }
+      const bool cm = so <= tol2 * (sd + 1e-300);
+      all = all && cm;
+      if (m == v) act = !cm;
+    }
+    __syncthreads();
+    if (all) break;
+    for (int round = 0; round < n1; ++round) {
+      if (act && gt < n / 2) {
+        int pp = jac_index(gt, round, n1), qq = jac_index(n1 - gt, round, n1);
+        if (pp > qq) { const int tmp = pp; pp = qq; qq = tmp; }
+        const double apq = a[pp * n + qq], app = a[pp * n + pp], aqq = a[qq * n + qq];
+        double cth = 1.0, sth = 0.0;
+        if (apq != 0.0) {
+          const double theta = (aqq - app) / (2.0 * apq);
+          const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          cth = 1.0 / sqrt(tt * tt + 1.0);
+          sth = tt * cth;
+        }
+        w[v].rc[pp] = cth; w[v].rs[pp] = -sth;
+        w[v].rc[qq] = cth; w[v].rs[qq] = sth;
+      }
+      __syncthreads();
+      if (act) {
+        for (int e = gt; e < nn; e += GW) {
+          const int r = sdiv(e, n), col = e - r * n;
+          const int pr = jac_partner(r, round, n), pc = jac_partner(col, round, n);
+          const double cr = w[v].rc[r], sr = w[v].rs[r], cc = w[v].rc[col], sc = w[v].rs[col];
+          a2[e] = cr * (cc * a[r * n + col] + sc * a[r * n + pc]) + sr * (cc * a[pr * n + col] + sc * a[pr * n + pc]);
+          v2[e] = vv[r * n + col] * cc + vv[r * n + pc] * sc;
+        }
+      }
+      __syncthreads();
+      if (act) {
+        double* t = a; a = a2; a2 = t;
+        t = vv; vv = v2; v2 = t;
+        ++flips;
+      }
+    }
+  }
+  if (flips & 1) {   // the result sits in the scratch: copy it back (group-uniform)
+    for (int e = gt; e < nn; e += GW) {
+      Av[v][e] = a[e];
+      Vv[v][e] = vv[e];
+    }
+  }
+  __syncthreads();
+}
+
 // ------------------------------------------------------- direction
 // C = op(A) op(B) for k x k blocks (k <= KC) by one wave on FP64 matrix
 // cores: 16x16 output tiles, 4 contraction steps per instruction; operands
@@ -933,6 +1020,7 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
   if (c->done) return;
   extern __shared__ double sm[];
   __shared__ WaveJacobiScratch jsc[2];
+  __shared__ double jpsum[16][2];
   __shared__ double terms[2][12];
   __shared__ double trv[2][3][KC];
   __shared__ double beta_sh;
@@ -969,8 +1057,8 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
   double* JV = JA + nn;
   double* JT = JV + nn;   // 2 nn
   double* V0 = JT + 2 * nn;
+  double tr3[3] = {0.0, 0.0, 0.0};
   if (b < nb) {
-    double tr3[3] = {0.0, 0.0, 0.0};
     for (int i = lane; i < k; i += 64) {
       tr3[0] += trv[b][0][i];
       tr3[1] += trv[b][1][i];
@@ -996,7 +1084,27 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
       for (int e = lane; e < nn; e += 64) JA[e] = JT[e];
     }
     wave_sync();
-    wave_jacobi(JA, JV, JT, n, lane, jsc[b], p.eig_tol2);
+  }
+  // Eigenvectors of P: one wave per block for small k (a round is a few
+  // instructions per lane and block barriers would cost more), the whole
+  // workgroup from n = 16 (FDA's k = 19: 400 entries per round).
+  if (n < 16) {
+    if (b < nb) wave_jacobi(JA, JV, JT, n, lane, jsc[b], p.eig_tol2);
+  } else {
+    __syncthreads();
+    double* Av[2];
+    double* Vv[2];
+    double* Tv[2];
+    for (int s2 = 0; s2 < 2; ++s2) {
+      double* base = sm + (s2 < nb ? s2 : 0) * per_side + 9 * kk2;
+      Av[s2] = base;
+      Vv[s2] = base + nn;
+      Tv[s2] = base + 2 * nn;
+    }
+    block_jacobi(Av, Vv, Tv, jsc, jpsum, nb, n, p.eig_tol2);
+  }
+  if (b < nb) {
+    double* Vst = kkslot(p, b, KK_EIG);
     if (warm) {
       wave_mm_t<KC>(V0, n, false, JV, n, false, JT, n, n, lane);   // V = V0 J
       for (int e = lane; e < nn; e += 64) JV[e] = JT[e];
