@@ -313,6 +313,24 @@ __device__ void wave_lower_inv(const double* L, double* X, int k, int lane) {
   wave_sync();
 }
 
+// 1 / x and 1 / sqrt(x) for positive normal x: the hardware estimates
+// refined by two Newton steps (within an ulp of the correctly rounded
+// values; the divide sequence's scaling for denormal and infinite operands
+// is not needed for the pivots these serve).
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ __forceinline__ double fast_rsq(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+
 // The trial evaluations run out of line (their register use stays apart
 // from the line search's); their operands are LDS arrays, typed as such so
 // that the accesses compile to LDS instructions rather than generic ones.
@@ -327,9 +345,8 @@ typedef __attribute__((address_space(3))) double lds_f64;
 // from the trailing lower triangle (r >= c > j), whose entries the lanes
 // own in NS fixed slots (no index arithmetic per step, one barrier per
 // step); column j is final after step j, and all columns are scaled by
-// 1 / sqrt(pivot) at the end.  Every slot loads (slots past the triangle
-// read element (0, 0)), so a step's loads issue together; only the stores
-// are masked.
+// 1 / sqrt(pivot) at the end.  The diagonal of the result holds
+// 1 / L[i][i] (the only use of the factor is its inverse below).
 template <int NS>
 __device__ bool chol_slots(lds_f64* A, int k, int gl, int gsize) {
   const int ntri = k * (k + 1) / 2;
@@ -352,30 +369,42 @@ __device__ bool chol_slots(lds_f64* A, int k, int gl, int gsize) {
       ok = false;
       piv = 1.0;
     }
-    const double rp = 1.0 / piv;
+    const double rp = fast_rcp(piv);
+    // Every slot loads and stores each step (a slot not updated at this
+    // step writes back the value it read; each entry of the triangle has
+    // one owner, and the clamped slots past the triangle all rewrite entry
+    // (0, 0), which no step changes), so no load sits under a branch.
     double nv[NS];
 #pragma unroll
     for (int m = 0; m < NS; ++m) {
       const int r = sr[m], c = sc[m];
-      nv[m] = A[r * k + c] - A[r * k + j] * A[c * k + j] * rp;
+      const double old = A[r * k + c];
+      const double upd = old - A[r * k + j] * A[c * k + j] * rp;
+      nv[m] = (sc[m] > j) ? upd : old;
     }
 #pragma unroll
-    for (int m = 0; m < NS; ++m)
-      if (sv[m] && sc[m] > j) A[sr[m] * k + sc[m]] = nv[m];
+    for (int m = 0; m < NS; ++m) A[sr[m] * k + sc[m]] = nv[m];
   }
   wave_sync();
-  // L[r][c] = A[r][c] / sqrt(A[c][c]) (the pivots are final)
+  // Final scaling: the diagonal entries become 1 / sqrt(pivot) (the lower
+  // inverse multiplies by them), then L[r][c] = A[r][c] / sqrt(A[c][c]) for
+  // r > c as a product with that reciprocal.
+  if (gl < k) {
+    const double pc = A[gl * k + gl];
+    A[gl * k + gl] = fast_rsq((pc > 0.0 && isfinite(pc)) ? pc : 1.0);
+  }
+  wave_sync();
   double lv[NS];
 #pragma unroll
   for (int m = 0; m < NS; ++m) {
     const int r = sr[m], c = sc[m];
-    const double pc = A[c * k + c];
-    lv[m] = A[r * k + c] / sqrt((pc > 0.0 && isfinite(pc)) ? pc : 1.0);
+    const double x = A[r * k + c];
+    lv[m] = (r > c) ? x * A[c * k + c] : x;
   }
   wave_sync();
 #pragma unroll
   for (int m = 0; m < NS; ++m)
-    if (sv[m]) A[sr[m] * k + sc[m]] = lv[m];
+    if (sv[m] && sr[m] > sc[m]) A[sr[m] * k + sc[m]] = lv[m];
   wave_sync();
   return ok;
 }
@@ -399,11 +428,11 @@ __device__ bool group_chol(lds_f64* A, int k, int gl, int gsize) {
   return chol_dispatch<1, MAXS>(ns, A, k, gl, gsize);
 }
 
-// X = L^-1 for lower L (ld k): lane c of the group forward-substitutes
-// column c of X in registers (no cross-lane dependence, no LDS round trip
-// inside the chain).  Row r of L arrives as broadcast loads and the
-// diagonal through its reciprocal, so a step of the chain is the dot
-// product of the row with the finished entries and one multiply.  An empty
+// X = L^-1 for lower L (ld k) whose diagonal holds 1 / L[i][i] (as
+// group_chol leaves it): lane c of the group forward-substitutes column c
+// of X in registers (no cross-lane dependence, no LDS round trip inside the
+// chain).  Row r of L arrives as broadcast loads, so a step of the chain is
+// the dot product of the row with the finished entries and one multiply.  An empty
 // asm statement with a memory clobber keeps each row's loads in its own
 // step (hoisting all of them ahead of the chain would exhaust registers).
 template <int KC>
@@ -416,7 +445,7 @@ __device__ void group_lower_inv(const lds_f64* L, lds_f64* X, int k, int gl) {
       double v = 0.0;
       if (r < k) {
         asm volatile("" ::: "memory");
-        const double rinv = 1.0 / L[r * k + r];
+        const double rinv = L[r * k + r];   // the factor's diagonal holds 1 / L[r][r]
         double acc4[4] = {0.0, 0.0, 0.0, 0.0};   // four short chains instead of one long one
 #pragma unroll
         for (int l = 0; l < r; ++l) acc4[l & 3] += L[r * k + l] * x[l];   // x[l] = 0 for l < c
