@@ -319,13 +319,12 @@ int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta
 // its inverse into Dinv (64 x 64, upper, identity-padded).  Sets *flag on a
 // non-positive pivot.
 //
-// Right-looking with one barrier per column: step j updates the trailing
-// triangle with the unscaled row j (a[r][c] -= a[j][r] a[j][c] / a[j][j])
-// and scales row j - 1 into its final form, so no thread reads a row that
-// another thread of the same step writes.  The inverse is back-substituted
-// by four lanes per column (one wave per 16 columns): the four partial dot
-// products of a row are combined with lane shuffles, so the only
-// dependence between rows is inside a wave.
+// Right-looking with one barrier per column: the trailing triangle stays in
+// registers (each thread owns fixed entries), step j subtracts
+// a[j][r] a[j][c] / a[j][j] from the entries j < r <= c using row j as its
+// owners publish it in LDS, and row j is stored in its final form (scaled
+// by 1 / sqrt(pivot)) as soon as it is complete.  The inverse follows by
+// 16 x 16 blocks (see below).
 __device__ __forceinline__ void wave_fence_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -338,80 +337,122 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
   __shared__ double a[64][65];
   __shared__ double x[64][65];
   __shared__ double piv[64];
+  __shared__ double row[2][65];   // unscaled row j of the trailing matrix, double-buffered by step parity
+  __shared__ double rdiag[64];    // 1 / R[j][j]
+  __shared__ double tsc[3][16][17];   // per-wave 16 x 16 scratch of the blocked inverse
   const int t = threadIdx.x;
-  for (int e = t; e < 4096; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    double v;
-    if (r < nb && c < nb) {
-      const int lo = min(r, c), hi = max(r, c);
-      v = G[(int64_t)(k0 + lo) * ld + k0 + hi];
-    } else {
-      v = (r == c) ? 1.0 : 0.0;
+  // Thread t owns the entries e = t + 256 m of the row-major upper
+  // triangle (2080 entries, 9 slots) in registers for the whole
+  // factorisation.  Step j: the owners of row j publish it, one barrier,
+  // then every owner of an entry (r, c) with j < r <= c subtracts
+  // row[r] row[c] / row[j]; the owners of row j store it scaled by
+  // 1 / sqrt(pivot) (its final form).  Rows past nb are the identity.
+  constexpr int kSlots = 9;
+  int sr[kSlots], sc[kSlots];
+  double v[kSlots];
+#pragma unroll
+  for (int m = 0; m < kSlots; ++m) {
+    const int e = t + 256 * m;
+    int r = 0, rowlen = 64;
+    int rem = e < 2080 ? e : 0;
+    while (rem >= rowlen) { rem -= rowlen; ++r; --rowlen; }
+    const int c = r + rem;
+    sr[m] = e < 2080 ? r : 64;   // 64: no entry
+    sc[m] = c;
+    double val = 0.0;
+    if (e < 2080) {
+      if (r < nb && c < nb) val = G[(int64_t)(k0 + r) * ld + k0 + c];
+      else val = (r == c) ? 1.0 : 0.0;
     }
-    a[r][c] = v;
+    v[m] = val;
   }
-  __syncthreads();
   for (int j = 0; j < 64; ++j) {
-    double p = a[j][j];
-    if (!(p > 0.0)) p = 1.0;
-    const double rp = 1.0 / p;
+    double* rw = row[j & 1];
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m)
+      if (sr[m] == j) rw[sc[m]] = v[m];
+    __syncthreads();
+    double p = rw[j];
+    const bool bad = !(p > 0.0) || !isfinite(p);
+    if (bad) p = 1.0;
     if (t == 0) {
-      if (!(a[j][j] > 0.0)) atomicOr(flag, 1);
+      if (bad) atomicOr(flag, 1);
       piv[j] = p;
     }
-    if (j > 0) {   // final form of row j - 1
-      const double dj = sqrt(piv[j - 1]);
-      for (int c = j - 1 + t; c < 64; c += 256) a[j - 1][c] = (c == j - 1) ? dj : a[j - 1][c] / dj;
-    }
-    {   // trailing triangle j < r <= c: thread (r0, c) takes rows j + 1 + r0 + 4 m;
-        // all loads of the step issue before the first store
-      const int c = t & 63, r0 = j + 1 + (t >> 6);
-      const double ajc = a[j][c] * rp;
-      double arc[16], ajr[16];
+    const double rp = __builtin_amdgcn_rcp(p);
+    const double rpp = rp * fma(-p, rp, 2.0);
+    const double rinv = rpp * fma(-p, rpp, 2.0);      // 1 / p (two Newton steps)
+    double rs = __builtin_amdgcn_rsq(p);
+    rs = rs * fma(-0.5 * p * rs, rs, 1.5);
+    rs = rs * fma(-0.5 * p * rs, rs, 1.5);           // 1 / sqrt(p)
+    if (t == 0) rdiag[j] = rs;
+    // every slot reads its two row entries (row[64] for empty slots), so the
+    // loads issue together and no load sits under a branch
+    double fr[kSlots], fc[kSlots];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {   // unconditional loads (clamped rows) so they issue together
-        const int r = min(r0 + 4 * m, 63);
-        arc[m] = a[r][c];
-        ajr[m] = a[j][r];
-      }
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int r = r0 + 4 * m;
-        if (r <= c) a[r][c] = arc[m] - ajr[m] * ajc;
-      }
+    for (int m = 0; m < kSlots; ++m) {
+      fr[m] = rw[sr[m]];
+      fc[m] = rw[sc[m]];
     }
-    __syncthreads();
-  }
-  {
-    const double d63 = sqrt(piv[63]);
-    if (t == 0) a[63][63] = d63;
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) {
+      const int r = sr[m], c = sc[m];
+      const double upd = v[m] - fr[m] * fc[m] * rinv;
+      if (r == j) a[j][c] = (c == j) ? p * rs : v[m] * rs;   // sqrt(p) on the diagonal
+      v[m] = (r > j && r < 64) ? upd : v[m];
+    }
   }
   __syncthreads();
-  // x = a^-1 (upper): lanes 4c .. 4c + 3 own column c
-  if (t < 64) piv[t] = 1.0 / a[t][t];
+  // x = a^-1 (upper) by 16 x 16 blocks: the four diagonal blocks by
+  // back-substitution (wave w inverts block w; four lanes per column),
+  // then the blocks at distance d = 1, 2, 3 from the diagonal as
+  // X_ij = -X_ii sum_{i < l <= j} R_il X_lj on FP64 matrix cores (a level
+  // needs only blocks closer to the diagonal).
+  for (int e = t; e < 4096; e += 256) x[e >> 6][e & 63] = 0.0;
   __syncthreads();
+  const int wv = t >> 6, ln = t & 63;
   {
-    const int c = t >> 2, q = t & 3;
-    for (int r = 0; r < 64; ++r) x[r][c] = 0.0;   // (each of the 4 lanes writes the same zeros)
-    wave_fence_sync();
-    if (q == 0) x[c][c] = piv[c];
-    wave_fence_sync();
-    for (int r = 62; r >= 0; --r) {
-      double s = 0.0;
+    const int c = ln >> 2, q = ln & 3, o = 16 * wv;
+    for (int r = 15; r >= 0; --r) {
+      double sum = 0.0;
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {   // unconditional loads (clamped index), masked products
+      for (int m = 0; m < 4; ++m) {   // unconditional loads (clamped index), masked products
         const int l = r + 1 + q + 4 * m;
-        const int lc = min(l, 63);
-        const double prod = a[r][lc] * x[lc][c];
-        s += (l <= c) ? prod : 0.0;
+        const int lc = min(l, 15);
+        const double prod = a[o + r][o + lc] * x[o + lc][o + c];
+        sum += (l <= c) ? prod : 0.0;
       }
-      s += __shfl_xor(s, 1, 64);
-      s += __shfl_xor(s, 2, 64);
-      if (r < c && q == 0) x[r][c] = -s * piv[r];
+      sum += __shfl_xor(sum, 1, 64);
+      sum += __shfl_xor(sum, 2, 64);
+      if (q == 0 && r <= c) x[o + r][o + c] = ((r == c) ? 1.0 : -sum) * rdiag[o + r];
       wave_fence_sync();
     }
   }
   __syncthreads();
+  {
+    const int m16 = ln & 15, kq = ln >> 4;
+    for (int d = 1; d <= 3; ++d) {
+      if (wv < 4 - d) {
+        const int i = wv, j = wv + d;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int l = i + 1; l <= j; ++l) {
+#pragma unroll
+          for (int kb = 0; kb < 4; ++kb)
+            acc = mfma16x16x4(a[16 * i + m16][16 * l + 4 * kb + kq], x[16 * l + 4 * kb + kq][16 * j + m16], acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tsc[wv][acc_row<double>(ln, r)][m16] = acc[r];
+        wave_fence_sync();
+        f64x4 acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+          acc2 = mfma16x16x4(x[16 * i + m16][16 * i + 4 * kb + kq], tsc[wv][4 * kb + kq][m16], acc2);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[16 * i + acc_row<double>(ln, r)][16 * j + m16] = -acc2[r];
+      }
+      __syncthreads();
+    }
+  }
   for (int e = t; e < 4096; e += 256) {
     const int r = e >> 6, c = e & 63;
     Dinv[e] = x[r][c];
