@@ -179,10 +179,30 @@ size_t partial_bytes(int k, int dmax) {
   return bytes_of<double>((size_t)2 * partial_slices(dmax) * (4 * k) * (6 * k));
 }
 
+// Sum of the row-slice partials in slice order, in place into slice 0 (one
+// thread per entry): the single-workgroup controllers then read one slice
+// instead of pulling every slice through one compute unit.
+__global__ void __launch_bounds__(256) k_part_reduce(double* __restrict__ part, int slices, int64_t side_stride,
+                                                     int64_t nlnr, const SolverCtrl* __restrict__ ctrl) {
+  if (ctrl && ctrl->done) return;
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e >= nlnr) return;
+  double* base = part + blockIdx.y * side_stride + e;
+  double s = 0.0;
+  for (int z = 0; z < slices; ++z) s += base[z * nlnr];
+  base[0] = s;
+}
+
 static int run_partials(PartialArgs& a, int nb, hipStream_t st) {
   a.side_stride = (int64_t)a.slices * (4 * a.k) * (6 * a.k);
   hipLaunchKernelGGL(k_partials, dim3(a.slices, nb), dim3(256), 0, st, a);
   SRP_LAUNCH_CHECK();
+  if (a.slices > 1) {
+    const int64_t nlnr = (int64_t)a.side[0].nl * a.k * a.side[0].nr * a.k;
+    hipLaunchKernelGGL(k_part_reduce, dim3((unsigned)((nlnr + 255) / 256), nb), dim3(256), 0, st, a.out, a.slices,
+                       a.side_stride, nlnr, a.ctrl);
+    SRP_LAUNCH_CHECK();
+  }
   return SRP_OK;
 }
 
@@ -256,10 +276,13 @@ int launch_final_partials(const ProbView& p, hipStream_t st) {
 
 // ------------------------------------------------- small dense helpers
 // Sum over the row-slice partials of up to four entries with weights:
-// sum_z sum_q w_q part[z * zs + i_q] (q < nq).  The partials were written
-// by workgroups on other XCDs, so each load is a trip beyond this XCD's L2:
-// all of them are issued before the first is used (unrolled to the slice
-// cap), and the sum runs in a fixed order (deterministic).
+// sum_z sum_q w_q part[z * zs + i_q] (q < nq, z < slices <= MAXZ).  The
+// partials were written by workgroups on other XCDs, so each load is a
+// trip beyond this XCD's L2: all of them are issued before the first is
+// used (unrolled to MAXZ), and the sum runs in a fixed order
+// (deterministic).  The controllers read the slice sums k_part_reduce
+// leaves in slice 0 (MAXZ = 1).
+template <int MAXZ = 1>
 __device__ __forceinline__ double slice_sum(const double* __restrict__ part, int slices, int64_t zs, int nq,
                                             int64_t i0, int64_t i1, int64_t i2, int64_t i3, double w0,
                                             double w1, double w2, double w3) {
@@ -269,7 +292,7 @@ __device__ __forceinline__ double slice_sum(const double* __restrict__ part, int
   const double u1 = nq > 1 ? w1 : 0.0, u2 = nq > 2 ? w2 : 0.0, u3 = nq > 3 ? w3 : 0.0;
   double s = 0.0;
 #pragma unroll
-  for (int z = 0; z < kMaxSlices; ++z) {
+  for (int z = 0; z < MAXZ; ++z) {
     const bool on = z < slices;
     const double* pz = part + (int64_t)(on ? z : 0) * zs;
     const double t = (w0 * pz[i0] + u1 * pz[j1]) + (u2 * pz[j2] + u3 * pz[j3]);
@@ -558,10 +581,10 @@ __global__ void __launch_bounds__(kLsThreads) k_ctrl_ls(ProbView p, int ntr) {
   __shared__ double mu[KC];
   const int k = p.k, nb = p.nb, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int kk2 = k * k;
-  const int slices = p.part_slices;
+  const int slices = 1;   // k_part_reduce left the slice sums in slice 0
   const int NR = 6 * k;
   const int64_t zs = (int64_t)(2 * k) * NR;
-  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);   // as laid out by run_partials
+  const int64_t side_stride = (int64_t)p.part_slices * (4 * k) * (6 * k);   // as laid out by run_partials
   double* coef = sm;                                 // (3 nb + 3) k x k
   const int ncoef = 3 * nb + 3;
   // coefficients (ls partial layout: left [U, xi], right [Ks, Js, U, xi, Kc, Jc])
@@ -1056,10 +1079,10 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
   const int k = p.k, nb = p.nb, tid = threadIdx.x, lane = tid & 63, b = tid >> 6;
   const int n = (k + 1) & ~1;
   const int kk2 = k * k, nn = n * n;
-  const int slices = p.part_slices;
+  const int slices = 1;   // k_part_reduce left the slice sums in slice 0
   const int NR = 4 * k;
   const int64_t zs = (int64_t)(2 * k) * NR;
-  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);   // as laid out by run_partials
+  const int64_t side_stride = (int64_t)p.part_slices * (4 * k) * (6 * k);   // as laid out by run_partials
   const int per_side = 9 * kk2 + 5 * nn;
   for (int e = tid; e < nb * 4 * kk2; e += 512) {
     const int sd = sdiv(e, 4 * kk2), r = e - sd * 4 * kk2, blk = sdiv(r, kk2), q = r - blk * kk2, i = sdiv(q, k), j = q - i * k;
@@ -1306,8 +1329,8 @@ __global__ void __launch_bounds__(64) k_ctrl_final(ProbView p, double* sigma_out
   __shared__ int order[64];
   const int k = p.k, nb = p.nb, lane = threadIdx.x;
   const int kk2 = k * k;
-  const int slices = p.part_slices;
-  const int64_t side_stride = (int64_t)slices * (4 * k) * (6 * k);
+  const int slices = 1;   // k_part_reduce left the slice sums in slice 0
+  const int64_t side_stride = (int64_t)p.part_slices * (4 * k) * (6 * k);
   double* G[2] = {sm, sm + 3 * kk2};
   double* Li[2] = {sm + kk2, sm + 4 * kk2};
   double* Cu[2] = {sm + 2 * kk2, sm + 5 * kk2};
