@@ -685,8 +685,8 @@ __device__ __forceinline__ void quad_step(const float* __restrict__ xs, float* _
 template <int SV, int C4, int VEC>
 __global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restrict__ A0, const float* __restrict__ A1,
                                                            int64_t n, int d0, int d1, int k,
-                                                           const float* __restrict__ Wp0,
-                                                           const float* __restrict__ Wp1, int nrb,
+                                                           const double* __restrict__ W0,
+                                                           const double* __restrict__ W1, int nrb,
                                                            float* __restrict__ partial, const int* __restrict__ done) {
   if (done && *done) return;
   using Q = QuadShape<SV, C4>;
@@ -709,8 +709,10 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restri
   const int pv = w >> 3;   // view of this wave's P products (wave-uniform)
 
   // direction operands of the P blocks: group G, tile tv = w % 8 + 8 (4 G +
-  // g) of view pv, its column 4 cs + s, direction column 4 kg + q4
-  const __amdgpu_buffer_rsrc_t wrs = make_rsrc(pv ? Wp1 : Wp0, (int64_t)(pv ? T1 : T0) * 16 * 16 * 4);
+  // g) of view pv, its column 4 cs + s, direction column 4 kg + q4, read
+  // from the FP64 directions (d x k row-major; rows past d lie past the
+  // resource and read zero, columns past k take the zero offset)
+  const __amdgpu_buffer_rsrc_t wrs = make_rsrc(pv ? W1 : W0, (int64_t)(pv ? d1 : d0) * k * 8);
   float wreg[PG][4][KG];
   int pcol[PG];   // LDS column of the tile's phase-cs quadruple
 #pragma unroll
@@ -722,8 +724,9 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restri
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int kg = 0; kg < KG; ++kg) {
-        const int off = ok ? ((16 * tv + 4 * cs + s) * 16 + 4 * kg + q4) * 4 : kOob;
-        wreg[G][s][kg] = buf_load<float>(wrs, off, 0);
+        const int col = 4 * kg + q4;
+        const int off = (ok && col < k) ? ((16 * tv + 4 * cs + s) * k + col) * 8 : kOob;
+        wreg[G][s][kg] = (float)buf_load<double>(wrs, off, 0);
       }
   }
   f32x4 acc[TPB][JQ > 0 ? JQ : 1];
@@ -977,8 +980,9 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad1(const float* __restr
   const int g = lane >> 4, l16 = lane & 15, cs = (lane >> 2) & 3, q4 = lane & 3;
 
   // direction operands of the P blocks: tile w + 16 (4 G + g), its column
-  // 4 cs + s, direction column 4 kg + q4 (the packed directions are 4 KG
-  // columns wide)
+  // 4 cs + s, direction column 4 kg + q4, from the directions packed to
+  // FP32 (4 KG columns, zero padded; every workgroup reads all of them, and
+  // at k = 19 the FP64 iterate would double that L2 traffic)
   const __amdgpu_buffer_rsrc_t wrs = make_rsrc(Wp0, (int64_t)T0 * 16 * (4 * KG) * 4);
   float wreg[PG][4][KG];
 #pragma unroll
@@ -1583,22 +1587,18 @@ template <int SV, int C4, int VEC>
 static int pass_launch_quad(const float* A0, const float* A1, int64_t n, int d0, int d1, int k, const double* W0,
                             const double* W1, double* J0, double* J1, const int* done, Arena& ws, hipStream_t st,
                             hipEvent_t before_pass, hipEvent_t after_pass) {
-  const int dp0 = (d0 + 15) / 16 * 16, dp1 = (d1 + 15) / 16 * 16;
-  const int KP = 16;
-  float* Wp0 = ws.take<float>((size_t)dp0 * KP);
-  float* Wp1 = ws.take<float>((size_t)dp1 * KP);
   const int nrb = (int)((n + kDmaRows - 1) / kDmaRows);
   // at least 4 blocks per workgroup (fewer partials to add for short data)
   const int grid = std::max(1, std::min(num_cus(), (nrb + 3) / 4));
   const int Dtot = d0 + d1;
   float* part = ws.take<float>((size_t)grid * Dtot * 2 * k);
-  if (!Wp0 || !Wp1 || !part) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
-  SRP_TRY(pack_dirs<float>(W0, d0, dp0, Wp0, W1, d1, dp1, Wp1, k, KP, st));
+  if (!part) { set_error("gram_pass: workspace too small"); return SRP_ENOMEM; }
+  if ((int64_t)std::max(d0, d1) * k * 8 >= 0x7ffff000ll) { set_error("gram_pass: directions too large"); return SRP_EINVAL; }
   const size_t lds = quad_lds_bytes(SV, C4);
   SRP_TRY(allow_dynamic_lds((const void*)k_pass_quad<SV, C4, VEC>, kPassLds + 8 * 1024));
   if (before_pass) SRP_HIP(hipEventRecord(before_pass, st));
-  hipLaunchKernelGGL((k_pass_quad<SV, C4, VEC>), dim3(grid), dim3(kF32Threads), lds, st, A0, A1, n, d0, d1, k, Wp0,
-                     Wp1, nrb, part, done);
+  hipLaunchKernelGGL((k_pass_quad<SV, C4, VEC>), dim3(grid), dim3(kF32Threads), lds, st, A0, A1, n, d0, d1, k, W0,
+                     W1, nrb, part, done);
   SRP_LAUNCH_CHECK();
   if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
   const int64_t count = (int64_t)Dtot * 2 * k;
