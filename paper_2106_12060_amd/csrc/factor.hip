@@ -261,13 +261,19 @@ __global__ void __launch_bounds__(256) k_skinny_sum(SkinnyBatch bt) {
   if (e >= cnt) return;
   const int nsl = (pr.kk + kSkSlice - 1) / kSkSlice;
   const double* part = bt.part[blockIdx.y];
+  // even slices into s0, odd into s1, in slice order; the loads of 16
+  // slices are in flight together
   double s0 = 0.0, s1 = 0.0;
-  int z = 0;
-  for (; z + 2 <= nsl; z += 2) {
-    s0 += part[(int64_t)z * cnt + e];
-    s1 += part[(int64_t)(z + 1) * cnt + e];
+  for (int z0 = 0; z0 < nsl; z0 += 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = part[(int64_t)(z0 + u < nsl ? z0 + u : 0) * cnt + e];
+#pragma unroll
+    for (int u = 0; u < 16; u += 2) {
+      if (z0 + u < nsl) s0 += t[u];
+      if (z0 + u + 1 < nsl) s1 += t[u + 1];
+    }
   }
-  if (z < nsl) s0 += part[(int64_t)z * cnt + e];
   const int64_t row = e / pr.nc, col = e - row * pr.nc;
   pr.C[row * pr.ldc + col] = s0 + s1;
 }

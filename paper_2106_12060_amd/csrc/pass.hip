@@ -1117,8 +1117,18 @@ __global__ void __launch_bounds__(256) k_pass_reduce(const CT* __restrict__ part
   const int per = (nparts + 3) / 4;
   const int z0 = grp * per, z1 = min(nparts, z0 + per);
   double v = 0.0;
-  if (i < count)
-    for (int z = z0; z < z1; ++z) v += (double)partial[(int64_t)z * count + i];
+  if (i < count) {
+    // loads in batches of 16 (all in flight together), added in z order
+    int z = z0;
+    for (; z + 16 <= z1; z += 16) {
+      CT t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t[u] = partial[(int64_t)(z + u) * count + i];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v += (double)t[u];
+    }
+    for (; z < z1; ++z) v += (double)partial[(int64_t)z * count + i];
+  }
   q4[grp][lanei] = v;
   __syncthreads();
   if (grp == 0 && i < count) {

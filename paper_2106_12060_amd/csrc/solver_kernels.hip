@@ -188,8 +188,14 @@ __global__ void __launch_bounds__(256) k_part_reduce(double* __restrict__ part, 
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   if (e >= nlnr) return;
   double* base = part + blockIdx.y * side_stride + e;
+  // all slices' loads in flight together (slices <= kMaxSlices), added in
+  // slice order
+  double t[kMaxSlices];
+#pragma unroll
+  for (int z = 0; z < kMaxSlices; ++z) t[z] = base[(z < slices ? z : 0) * nlnr];
   double s = 0.0;
-  for (int z = 0; z < slices; ++z) s += base[z * nlnr];
+#pragma unroll
+  for (int z = 0; z < kMaxSlices; ++z) s += (z < slices) ? t[z] : 0.0;
   base[0] = s;
 }
 
