@@ -63,7 +63,7 @@ struct PartialArgs {
 };
 
 constexpr int kPartRows = 16;
-constexpr int kMaxSlices = 16;   // row-slice partials per side
+constexpr int kMaxSlices = 64;   // row-slice partials per side (summed by k_part_reduce)
 
 // One row slice of a side: the (nl k) x (nr k) products L^T R over the
 // slice's rows on FP64 matrix cores (16x16 output tiles, 4 rows per step).
@@ -188,14 +188,15 @@ __global__ void __launch_bounds__(256) k_part_reduce(double* __restrict__ part, 
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   if (e >= nlnr) return;
   double* base = part + blockIdx.y * side_stride + e;
-  // all slices' loads in flight together (slices <= kMaxSlices), added in
-  // slice order
-  double t[kMaxSlices];
-#pragma unroll
-  for (int z = 0; z < kMaxSlices; ++z) t[z] = base[(z < slices ? z : 0) * nlnr];
+  // the loads of 16 slices in flight together, added in slice order
   double s = 0.0;
+  for (int z0 = 0; z0 < slices; z0 += 16) {
+    double t[16];
 #pragma unroll
-  for (int z = 0; z < kMaxSlices; ++z) s += (z < slices) ? t[z] : 0.0;
+    for (int u = 0; u < 16; ++u) t[u] = base[(z0 + u < slices ? z0 + u : 0) * nlnr];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += (z0 + u < slices) ? t[u] : 0.0;
+  }
   base[0] = s;
 }
 
