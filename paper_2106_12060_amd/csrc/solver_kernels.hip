@@ -889,6 +889,24 @@ __device__ __forceinline__ int jac_partner(int idx, int round, int n) {
   return jac_index(n1 - slot, round, n1);
 }
 
+// Cosine (returned) and sine of the rotation that zeroes the (p, q) entry,
+// t = sign(theta) / (|theta| + sqrt(theta^2 + 1)), c = 1 / sqrt(t^2 + 1):
+// the arguments of the square roots and reciprocals are >= 1, so the
+// Newton-refined hardware estimates serve (within an ulp). Past |theta| =
+// 1e150 (theta^2 would overflow) t is 1 / (2 theta) to working precision
+// (clamped at 1e300 so that an infinite theta gives t ~ 5e-301, c = 1).
+__device__ __forceinline__ double jac_rotation(double theta, double* sn) {
+  const double at = fabs(theta);
+  const bool big = at >= 1e150;
+  const double as = big ? 0.0 : at;
+  const double h = fma(as, as, 1.0);
+  const double den = big ? 2.0 * fmin(at, 1e300) : as + h * fast_rsq(h);
+  const double tt = (theta >= 0.0 ? 1.0 : -1.0) * fast_rcp(den);
+  const double cth = fast_rsq(fma(tt, tt, 1.0));
+  *sn = tt * cth;
+  return cth;
+}
+
 __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, WaveJacobiScratch& w,
                             double tol2 = 1e-30) {
   const int nn = n * n, n1 = n - 1;
@@ -917,9 +935,7 @@ __device__ void wave_jacobi(double* A, double* V, double* T, int n, int lane, Wa
         double cth = 1.0, sth = 0.0;
         if (apq != 0.0) {
           const double theta = (aqq - app) / (2.0 * apq);
-          const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          cth = 1.0 / sqrt(tt * tt + 1.0);
-          sth = tt * cth;
+          cth = jac_rotation(theta, &sth);
         }
         w.rc[pp] = cth; w.rs[pp] = -sth;
         w.rc[qq] = cth; w.rs[qq] = sth;
@@ -1000,9 +1016,7 @@ __device__ void block_jacobi(double* const* Av, double* const* Vv, double* const
         double cth = 1.0, sth = 0.0;
         if (apq != 0.0) {
           const double theta = (aqq - app) / (2.0 * apq);
-          const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          cth = 1.0 / sqrt(tt * tt + 1.0);
-          sth = tt * cth;
+          cth = jac_rotation(theta, &sth);
         }
         w[v].rc[pp] = cth; w[v].rs[pp] = -sth;
         w[v].rc[qq] = cth; w[v].rs[qq] = sth;
