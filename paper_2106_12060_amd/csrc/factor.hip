@@ -167,22 +167,24 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
 // --------------------------------------------------------- skinny GEMM
 // C (m x nc) = op(A) (m x kk) B (kk x nc), nc <= 64: the per-iteration
 // products with M^-1 and the FDA between-class factor.  The contraction is
-// split over blockIdx.y into slices of kSkSlice; a workgroup owns 16 rows of
-// op(A) in its slice and streams them once through LDS together with the
-// matching rows of B, and writes a partial; a second kernel adds the
-// partials in slice order (deterministic).  Thread (r, jg) keeps the
-// columns jg, jg + 16, ... of row r.
+// split over blockIdx.y into slices (kSkSlice for a transposed A,
+// kSkRowSlice otherwise); a workgroup writes the partial of its rows and
+// slice, and a second kernel adds the partials in slice order
+// (deterministic).
 constexpr int kSkSlice = 64;
+constexpr int kSkRowSlice = 128;
 
 // Up to two independent problems per launch (blockIdx.z), e.g. both views.
 struct SkinnyBatch {
   SkinnyProb p[2];
   double* part[2];
+  int slice;          // contraction length per partial
 };
 
-// FP64 matrix cores: a workgroup (4 waves) owns 64 rows x up to 64 columns
-// of one contraction slice; wave w computes rows 16w..16w+15 for every
-// 16-column tile.  Operands are staged 32 contraction steps at a time.
+// Transposed A (the FDA between-class factor): FP64 matrix cores, a
+// workgroup (4 waves) owns 64 rows x up to 64 columns of one contraction
+// slice; wave w computes rows 16w..16w+15 for every 16-column tile.
+// Operands are staged 32 contraction steps at a time.
 __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
   const SkinnyProb& pr = bt.p[blockIdx.z];
   const int m = pr.m, kk = pr.kk, nc = pr.nc;
@@ -254,12 +256,92 @@ __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
     }
 }
 
+// Row-major A (the M^-1 products): a workgroup owns 64 rows (16 per wave)
+// and a kSkRowSlice-long contraction slice.  A's rows go straight from HBM
+// into registers as matrix-core operands, the whole slice in flight at once
+// (lane (i, kq) of the wave holds A[row i][16 c + 4 kq + s], s = 0..3, for
+// chunk c: one 32-byte run per lane, as two 16-byte loads when VEC); the
+// slice of B is staged once in LDS.  Step s of chunk c multiplies over the
+// contraction indices 16 c + 4 kq + s (kq = 0..3, one per 16-lane row), so A
+// and B agree on the order and every index is taken once.
+constexpr int sk_bpitch(int nct) { return (nct & 1) ? 16 * nct : 16 * nct + 16; }
+template <int NCT, bool VEC>
+__global__ void __launch_bounds__(256) k_gemm_skinny_rows(SkinnyBatch bt) {
+  constexpr int KS = kSkRowSlice, NCH = KS / 16, P = sk_bpitch(NCT), NBC = 16 * NCT;
+  constexpr int NB = (KS * NBC + 255) / 256;
+  const SkinnyProb& pr = bt.p[blockIdx.z];
+  const int m = pr.m, kk = pr.kk, nc = pr.nc;
+  const int r0 = blockIdx.x * 64;
+  const int lbeg = blockIdx.y * KS;
+  if (r0 >= m || lbeg >= kk) return;
+  __shared__ double Bs[KS * P];   // [contraction][column], pitch P
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(pr.A, (int64_t)m * pr.lda * 8);
+  const __amdgpu_buffer_rsrc_t brsrc = make_rsrc(pr.B, (int64_t)kk * pr.ldb * 8);
+  double rb[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int e = tid + 256 * q;
+    const int bl = e / NBC, bj = e - bl * NBC, gl = lbeg + bl;
+    rb[q] = buf_load<double>(brsrc, (e < KS * NBC && bj < nc && gl < kk) ? (gl * (int)pr.ldb + bj) * 8 : kOob, 0);
+  }
+  const int row = r0 + 16 * w + i;
+  double av[NCH][4];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int col = lbeg + 16 * c + 4 * kq;
+    if (VEC) {   // kk % 4 == 0, even lda, 16-byte aligned A: col < kk covers col + 3
+      const int off = (row < m && col < kk) ? (row * (int)pr.lda + col) * 8 : kOob;
+      const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off, 0, 0);
+      const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off + 16, 0, 0);
+      av[c][0] = __builtin_bit_cast(double, (uint64_t)v0[0] | ((uint64_t)v0[1] << 32));
+      av[c][1] = __builtin_bit_cast(double, (uint64_t)v0[2] | ((uint64_t)v0[3] << 32));
+      av[c][2] = __builtin_bit_cast(double, (uint64_t)v1[0] | ((uint64_t)v1[1] << 32));
+      av[c][3] = __builtin_bit_cast(double, (uint64_t)v1[2] | ((uint64_t)v1[3] << 32));
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        av[c][s] = buf_load<double>(arsrc, (row < m && col + s < kk) ? (row * (int)pr.lda + col + s) * 8 : kOob, 0);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int e = tid + 256 * q;
+    if (e < KS * NBC) {
+      const int bl = e / NBC, bj = e - bl * NBC;
+      Bs[bl * P + bj] = rb[q];
+    }
+  }
+  __syncthreads();
+  f64x4 acc[NCT];
+#pragma unroll
+  for (int q = 0; q < NCT; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < NCH; ++c)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double* bp = &Bs[(16 * c + 4 * kq + s) * P + i];
+#pragma unroll
+      for (int q = 0; q < NCT; ++q) acc[q] = mfma16x16x4(av[c][s], bp[16 * q], acc[q]);
+    }
+  double* out = bt.part[blockIdx.z] + (int64_t)blockIdx.y * m * nc;
+#pragma unroll
+  for (int q = 0; q < NCT; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int orow = r0 + 16 * w + acc_row<double>(lane, r);
+      const int col = 16 * q + i;
+      if (orow < m && col < nc) out[(int64_t)orow * nc + col] = acc[q][r];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_skinny_sum(SkinnyBatch bt) {
   const SkinnyProb& pr = bt.p[blockIdx.y];
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   const int64_t cnt = (int64_t)pr.m * pr.nc;
   if (e >= cnt) return;
-  const int nsl = (pr.kk + kSkSlice - 1) / kSkSlice;
+  const int nsl = (pr.kk + bt.slice - 1) / bt.slice;
   const double* part = bt.part[blockIdx.y];
   // even slices into s0, odd into s1, in slice order; the loads of 16
   // slices are in flight together
@@ -306,7 +388,32 @@ int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_
     set_error("gemm_skinny: workspace too small");
     return SRP_ENOMEM;
   }
-  hipLaunchKernelGGL(k_gemm_skinny, dim3(gx, gy, nprob), dim3(256), 0, st, bt);
+  bool rows = true, vec = true;
+  int nct = 1;
+  for (int q = 0; q < nprob; ++q) {
+    const SkinnyProb& p = probs[q];
+    rows = rows && !p.ta;
+    vec = vec && p.kk % 4 == 0 && p.lda % 2 == 0 && ((uintptr_t)p.A & 15) == 0;
+    nct = std::max(nct, (p.nc + 15) / 16);
+  }
+  if (rows) {   // fewer, longer slices: the workspace sized for kSkSlice holds them
+    bt.slice = kSkRowSlice;
+    gy = 1;
+    for (int q = 0; q < nprob; ++q) gy = std::max(gy, (probs[q].kk + kSkRowSlice - 1) / kSkRowSlice);
+    const dim3 grid(gx, gy, nprob);
+#define SRP_SK_ROWS(N)                                                                       \
+    case N:                                                                                  \
+      if (vec) hipLaunchKernelGGL((k_gemm_skinny_rows<N, true>), grid, dim3(256), 0, st, bt);  \
+      else hipLaunchKernelGGL((k_gemm_skinny_rows<N, false>), grid, dim3(256), 0, st, bt);     \
+      break;
+    switch (nct) {
+      SRP_SK_ROWS(1) SRP_SK_ROWS(2) SRP_SK_ROWS(3) SRP_SK_ROWS(4)
+    }
+#undef SRP_SK_ROWS
+  } else {
+    bt.slice = kSkSlice;
+    hipLaunchKernelGGL(k_gemm_skinny, dim3(gx, gy, nprob), dim3(256), 0, st, bt);
+  }
   SRP_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_skinny_sum, dim3(sx, nprob), dim3(256), 0, st, bt);
   SRP_LAUNCH_CHECK();
