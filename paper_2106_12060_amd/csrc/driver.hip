@@ -401,6 +401,54 @@ static int read_ctrl(SolverCtrl* dev, SolverCtrl* host, hipStream_t st) {
   return SRP_OK;
 }
 
+// Convergence polls without draining the stream: the flag is copied into
+// pinned host memory behind an event, and the host reads it only after it
+// has queued the next batch of iterations (those return at once on the
+// device once the flag is set).  The pinned words are pooled: one per solve
+// running at a time, kept for reuse until the process ends.
+class FlagPoll {
+ public:
+  ~FlagPoll() {
+    if (pending_) (void)hipEventSynchronize(ev_);   // no copy in flight into a pooled word
+    if (ev_) (void)hipEventDestroy(ev_);
+    if (h_) {
+      std::lock_guard<std::mutex> g(mu());
+      pool().push_back(h_);
+    }
+  }
+  int init() {
+    {
+      std::lock_guard<std::mutex> g(mu());
+      if (!pool().empty()) { h_ = pool().back(); pool().pop_back(); }
+    }
+    if (!h_) SRP_HIP(hipHostMalloc((void**)&h_, 64, hipHostMallocDefault));
+    SRP_HIP(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+    return SRP_OK;
+  }
+  // Queue a copy of *done (device) taken after the work queued so far.
+  int post(const int* done, hipStream_t st) {
+    SRP_HIP(hipMemcpyAsync(h_, done, sizeof(int), hipMemcpyDeviceToHost, st));
+    SRP_HIP(hipEventRecord(ev_, st));
+    pending_ = true;
+    return SRP_OK;
+  }
+  // Wait for the last posted copy; *set = its value (false if none posted).
+  int read(bool* set) {
+    *set = false;
+    if (!pending_) return SRP_OK;
+    SRP_HIP(hipEventSynchronize(ev_));
+    pending_ = false;
+    *set = *h_ != 0;
+    return SRP_OK;
+  }
+ private:
+  static std::mutex& mu() { static std::mutex m; return m; }
+  static std::vector<int*>& pool() { static std::vector<int*> v; return v; }
+  int* h_ = nullptr;
+  hipEvent_t ev_ = nullptr;
+  bool pending_ = false;
+};
+
 // Runs Riemannian CG from qf_B(start).  On return B.U holds the final point.
 static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int max_iter, double tol,
                    int check_every, int refresh_every, bool finalize, bool final_f64, double* sigma_out,
@@ -426,6 +474,9 @@ static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int
   SRP_TRY(direction_step(P, B, v, st));
   const int* done = &B.ctrl->done;
   SolverCtrl hc{};
+  FlagPoll poll;
+  SRP_TRY(poll.init());
+  int passes_posted = passes;   // passes queued when the pending flag copy was
   for (int it = 1; it <= max_iter; ++it) {
     SRP_TRY(data_pass(P, B, B.xi, P.compute, done, st));
     ++passes;
@@ -439,8 +490,16 @@ static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int
     }
     SRP_TRY(direction_step(P, B, v, st));
     if (it % check_every == 0 || it == max_iter) {
-      SRP_TRY(read_ctrl(B.ctrl, &hc, st));
-      if (hc.done) break;
+      // the flag posted one batch ago: if set, this batch ran as no-ops
+      bool was_done = false;
+      const int prev = passes_posted;
+      SRP_TRY(poll.read(&was_done));
+      if (was_done) {
+        passes = prev;
+        break;
+      }
+      SRP_TRY(poll.post(done, st));
+      passes_posted = passes;
     }
   }
   SRP_TRY(read_ctrl(B.ctrl, &hc, st));
