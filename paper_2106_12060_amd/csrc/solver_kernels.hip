@@ -188,14 +188,21 @@ __global__ void __launch_bounds__(256) k_part_reduce(double* __restrict__ part, 
   const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   if (e >= nlnr) return;
   double* base = part + blockIdx.y * side_stride + e;
-  // the loads of 16 slices in flight together, added in slice order
+  // the loads of all slices (at most kMaxSlices) in flight together, added
+  // in slice order; one batch of 16 when there are no more
   double s = 0.0;
-  for (int z0 = 0; z0 < slices; z0 += 16) {
+  if (slices > 16) {
+    double t[kMaxSlices];
+#pragma unroll
+    for (int u = 0; u < kMaxSlices; ++u) t[u] = base[(u < slices ? u : 0) * nlnr];
+#pragma unroll
+    for (int u = 0; u < kMaxSlices; ++u) s += (u < slices) ? t[u] : 0.0;
+  } else {
     double t[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) t[u] = base[(z0 + u < slices ? z0 + u : 0) * nlnr];
+    for (int u = 0; u < 16; ++u) t[u] = base[(u < slices ? u : 0) * nlnr];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) s += (z0 + u < slices) ? t[u] : 0.0;
+    for (int u = 0; u < 16; ++u) s += (u < slices) ? t[u] : 0.0;
   }
   base[0] = s;
 }
@@ -1080,6 +1087,33 @@ __device__ __forceinline__ void wave_mm_t(const double* A, int lda, bool ta, con
   wave_sync();
 }
 
+// wave_mm_t shared by the G waves of a group: wave g of the group computes
+// the 16 x 16 output tiles t = g, g + G, ... (each tile as wave_mm_t
+// computes it); the caller synchronises the workgroup before C is read.
+template <int KC>
+__device__ __forceinline__ void group_mm_t(const double* A, int lda, bool ta, const double* B, int ldb, bool tb,
+                                           double* C, int ldc, int k, int lane, int g, int G) {
+  constexpr int T = (KC + 15) / 16;
+  const int m16 = lane & 15, q = lane >> 4;
+  for (int t = g; t < T * T; t += G) {
+    const int ti = t / T, tj = t - ti * T;
+    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kb = 0; kb < (KC + 3) / 4; ++kb) {
+      const int i = 16 * ti + m16, l = 4 * kb + q, j = 16 * tj + m16;
+      const int ic = i < k ? i : k - 1, lc = l < k ? l : k - 1, jc = j < k ? j : k - 1;
+      const double av = ta ? A[lc * lda + ic] : A[ic * lda + lc];
+      const double bv = tb ? B[jc * ldb + lc] : B[lc * ldb + jc];
+      acc = mfma16x16x4((i < k && l < k) ? av : 0.0, (l < k && j < k) ? bv : 0.0, acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * ti + acc_row<double>(lane, r), col = 16 * tj + m16;
+      if (row < k && col < k) C[row * ldc + col] = acc[r];
+    }
+  }
+}
+
 // All threads first reduce the row-slice partials (P = BU^T M^-1 BU,
 // Q = BU^T M^-1 E, BU^T xi, BU^T gold and three traces per side) into LDS;
 // one wave per manifold block then diagonalises P (Jacobi, started from
@@ -1139,24 +1173,43 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
     }
     for (int q = 0; q < 3; ++q)
       for (int o = 32; o > 0; o >>= 1) tr3[q] += __shfl_xor(tr3[q], o, 64);
-    for (int e = lane; e < nn; e += 64) {
+  }
+  // The k x k algebra of a side runs on a group of four waves (side b / 4,
+  // wave g = b % 4 of the group): products split by output tile, the three
+  // Sylvester solves one per wave; each output is computed as a single
+  // wave would compute it.
+  constexpr int G = 4;
+  const int sd = b / G, g = b - sd * G;
+  const bool grp = sd < nb;
+  const int gl = g * 64 + lane;          // lane within the group
+  double* Pg = sm + (grp ? sd : 0) * per_side;
+  double* JAg = Pg + 9 * kk2;
+  double* JVg = JAg + nn;
+  double* JTg = JVg + nn;
+  double* V0g = JTg + 2 * nn;
+  double* Vstg = kkslot(p, grp ? sd : 0, KK_EIG);
+  if (grp) {
+    for (int e = gl; e < nn; e += 64 * G) {
       const int i = sdiv(e, n), j = e - i * n;
-      JA[e] = (i < k && j < k) ? 0.5 * (P[i * k + j] + P[j * k + i]) : ((i == j) ? 1.0 : 0.0);
+      JAg[e] = (i < k && j < k) ? 0.5 * (Pg[i * k + j] + Pg[j * k + i]) : ((i == j) ? 1.0 : 0.0);
+      if (warm) V0g[e] = Vstg[e];
     }
-    double* Vst = kkslot(p, b, KK_EIG);
-    if (warm) {
-      for (int e = lane; e < nn; e += 64) V0[e] = Vst[e];
-      wave_sync();
-      wave_mm_t<KC>(JA, n, false, V0, n, false, JT, n, n, lane);   // JA V0
-      wave_mm_t<KC>(V0, n, true, JT, n, false, JA, n, n, lane);   // V0^T (JA V0)
-      for (int e = lane; e < nn; e += 64) {
+  }
+  __syncthreads();
+  if (warm) {
+    if (grp) group_mm_t<KC>(JAg, n, false, V0g, n, false, JTg, n, n, lane, g, G);   // JA V0
+    __syncthreads();
+    if (grp) group_mm_t<KC>(V0g, n, true, JTg, n, false, JAg, n, n, lane, g, G);   // V0^T (JA V0)
+    __syncthreads();
+    if (grp)
+      for (int e = gl; e < nn; e += 64 * G) {
         const int i = sdiv(e, n), j = e - i * n;
-        JT[e] = 0.5 * (JA[i * n + j] + JA[j * n + i]);
+        JTg[e] = 0.5 * (JAg[i * n + j] + JAg[j * n + i]);
       }
-      wave_sync();
-      for (int e = lane; e < nn; e += 64) JA[e] = JT[e];
-    }
-    wave_sync();
+    __syncthreads();
+    if (grp)
+      for (int e = gl; e < nn; e += 64 * G) JAg[e] = JTg[e];
+    __syncthreads();
   }
   // Eigenvectors of P: one wave per block for small k (a round is a few
   // instructions per lane and block barriers would cost more), the whole
@@ -1164,7 +1217,6 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
   if (n < 16) {
     if (b < nb) wave_jacobi(JA, JV, JT, n, lane, jsc[b], p.eig_tol2);
   } else {
-    __syncthreads();
     double* Av[2];
     double* Vv[2];
     double* Tv[2];
@@ -1176,41 +1228,46 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
     }
     block_jacobi(Av, Vv, Tv, jsc, jpsum, nb, n, p.eig_tol2);
   }
+  __syncthreads();
+  if (warm) {
+    if (grp) group_mm_t<KC>(V0g, n, false, JVg, n, false, JTg, n, n, lane, g, G);   // V = V0 J
+    __syncthreads();
+    if (grp)
+      for (int e = gl; e < nn; e += 64 * G) JVg[e] = JTg[e];
+    __syncthreads();
+  }
+  if (grp && g < 3) {
+    if (g == 0)
+      for (int e = lane; e < nn; e += 64) Vstg[e] = JVg[e];
+    // Sylvester: X = V ((V^T C V) ./ (w_i + w_j)) V^T for C = Z + Z^T, Z one
+    // of Q, cx, cg; Y is this wave's scratch (W1, W2, or the free JT)
+    double* Qg = Pg + kk2;
+    const double* C = Qg + g * kk2;                 // Q, cx, cg
+    double* X = Pg + (4 + g) * kk2;                 // S, Sx, Sg
+    double* Y = g == 0 ? Pg + 7 * kk2 : (g == 1 ? Pg + 8 * kk2 : JTg);
+    for (int e = lane; e < kk2; e += 64) {
+      const int i = sdiv(e, k), j = e - i * k;
+      Y[e] = C[i * k + j] + C[j * k + i];
+    }
+    wave_sync();
+    wave_mm_t<KC>(Y, k, false, JVg, n, false, X, k, k, lane);   // (C + C^T) V
+    wave_mm_t<KC>(JVg, n, true, X, k, false, Y, k, k, lane);    // V^T (C + C^T) V
+    for (int e = lane; e < kk2; e += 64) {
+      const int i = sdiv(e, k), j = e - i * k;
+      Y[e] /= (JAg[i * n + i] + JAg[j * n + j]);
+    }
+    wave_sync();
+    wave_mm_t<KC>(JVg, n, false, Y, k, false, X, k, k, lane);   // V (...)
+    wave_mm_t<KC>(X, k, false, JVg, n, true, Y, k, k, lane);    // ... V^T
+    // the solution is symmetric: keep it so (its two triangles are
+    // rounded along different sums)
+    for (int e = lane; e < kk2; e += 64) {
+      const int i = sdiv(e, k), j = e - i * k;
+      X[e] = 0.5 * (Y[i * k + j] + Y[j * k + i]);
+    }
+  }
+  __syncthreads();
   if (b < nb) {
-    double* Vst = kkslot(p, b, KK_EIG);
-    if (warm) {
-      wave_mm_t<KC>(V0, n, false, JV, n, false, JT, n, n, lane);   // V = V0 J
-      for (int e = lane; e < nn; e += 64) JV[e] = JT[e];
-      wave_sync();
-    }
-    for (int e = lane; e < nn; e += 64) Vst[e] = JV[e];
-    // Sylvester: S = V ((V^T C V) ./ (w_i + w_j)) V^T for C = X + X^T
-    const double* srcs[3] = {Q, cx, cg};
-    double* dsts[3] = {S, Sx, Sg};
-    for (int m = 0; m < 3; ++m) {
-      const double* C = srcs[m];
-      for (int e = lane; e < kk2; e += 64) {
-        const int i = sdiv(e, k), j = e - i * k;
-        W2[e] = C[i * k + j] + C[j * k + i];
-      }
-      wave_sync();
-      wave_mm_t<KC>(W2, k, false, JV, n, false, W1, k, k, lane);   // (C + C^T) V
-      wave_mm_t<KC>(JV, n, true, W1, k, false, W2, k, k, lane);    // V^T (C + C^T) V
-      for (int e = lane; e < kk2; e += 64) {
-        const int i = sdiv(e, k), j = e - i * k;
-        W2[e] /= (JA[i * n + i] + JA[j * n + j]);
-      }
-      wave_sync();
-      wave_mm_t<KC>(JV, n, false, W2, k, false, W1, k, k, lane);   // V (...)
-      wave_mm_t<KC>(W1, k, false, JV, n, true, W2, k, k, lane);    // ... V^T
-      // the solution is symmetric: keep it so (its two triangles are
-      // rounded along different sums)
-      for (int e = lane; e < kk2; e += 64) {
-        const int i = sdiv(e, k), j = e - i * k;
-        dsts[m][e] = 0.5 * (W2[i * k + j] + W2[j * k + i]);
-      }
-      wave_sync();
-    }
     wave_mm_t<KC>(P, k, false, S, k, false, W1, k, k, lane);   // W1 = P S
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int e = lane; e < kk2; e += 64) {
