@@ -286,9 +286,11 @@ def main():
     # margin on these spectra (top-k correlations 3e-4 to 5e-3 apart)
     tol = args.tol if args.tol is not None else (1e-9 if wl.dtype == "f64" else 1e-4)
     mu = [1.0] * wl.k if args.weights == "equal" else None
-    # warm-start iterations that minimise the solve time (measured: 100 for
-    # the CCA workload, 60 for FDA, whose k = 19 controllers cost more)
-    warm = args.warm if args.warm is not None else (60 if wl.problem == "lda" else 100)
+    # warm-start iterations (RCG on the sketched problem, the sketch-and-solve
+    # start point) that minimise the solve time, measured: for the CCA
+    # workload 110-130 give 32-36 full iterations (100: 44, 150: 33), so 120;
+    # for FDA 10 to 100 all give 19 full iterations (none: 21), so 10
+    warm = args.warm if args.warm is not None else (10 if wl.problem == "lda" else 120)
     extra = {"warm_start_iters": warm}
     if args.final_f64 is not None:
         extra["final_f64"] = args.final_f64
