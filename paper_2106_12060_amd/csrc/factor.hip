@@ -586,13 +586,21 @@ __global__ void k_place_diag_blocks(const double* __restrict__ Dinv, int d, doub
 
 constexpr int kInvSplit = 8;   // split of the contraction in the R^-1 block rows
 
-size_t factor_ws_bytes(int s, int d) {
+// Split of the sketch Gram over the s rows: about 2048 workgroups over the
+// upper tiles (several per compute unit, so one's loads overlap another's
+// products), each contraction at least 64 rows long.
+static int gram_ksplit(int s, int d) {
   const int tiles = (d + 63) / 64;
   const int nupper = tiles * (tiles + 1) / 2;
-  int ksplit = (512 + nupper - 1) / nupper;
+  int ksplit = (2048 + nupper - 1) / nupper;
   const int kmax = (s + 63) / 64;
   if (ksplit > kmax) ksplit = kmax;
-  if (ksplit < 1) ksplit = 1;
+  return ksplit < 1 ? 1 : ksplit;
+}
+
+size_t factor_ws_bytes(int s, int d) {
+  const int tiles = (d + 63) / 64;
+  const int ksplit = gram_ksplit(s, d);
   const size_t dd = (size_t)d * d;
   return bytes_of<double>(dd) * (ksplit > 1 ? ksplit + 1 : 1) + bytes_of<double>((size_t)tiles * 4096) +
          bytes_of<double>((size_t)64 * d) + bytes_of<double>(dd) + bytes_of<double>((size_t)kInvSplit * 64 * d);
@@ -601,11 +609,7 @@ size_t factor_ws_bytes(int s, int d) {
 int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
                       double* Minv, int* flag_dev, Arena& ws, hipStream_t st) {
   const int tiles = (d + 63) / 64;
-  const int nupper = tiles * (tiles + 1) / 2;
-  int ksplit = (512 + nupper - 1) / nupper;
-  const int kmax = (s + 63) / 64;
-  if (ksplit > kmax) ksplit = kmax;
-  if (ksplit < 1) ksplit = 1;
+  const int ksplit = gram_ksplit(s, d);
   const int64_t dd = (int64_t)d * d;
   double* G = ws.take<double>(dd);
   double* parts = ksplit > 1 ? ws.take<double>(dd * ksplit) : nullptr;
