@@ -13,12 +13,22 @@ namespace srp {
 constexpr int kCenterRows = 4096;
 constexpr int kCenterMaxC = 64;
 
-__global__ void k_lda_counts(const int32_t* __restrict__ y, int64_t n, int c, int* counts, int* bad) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int l = y[i];
-  if (l < 0 || l >= c) { atomicOr(bad, 1); return; }
-  atomicAdd(&counts[l], 1);
+// Class counts: a histogram per workgroup in LDS, then one atomic add per
+// class and workgroup (integer sums: the order does not matter).
+__global__ void __launch_bounds__(256) k_lda_counts(const int32_t* __restrict__ y, int64_t n, int c, int* counts,
+                                                    int* bad) {
+  __shared__ int hist[kCenterMaxC];
+  for (int q = threadIdx.x; q < c; q += 256) hist[q] = 0;
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int l = y[i];
+    if (l < 0 || l >= c) atomicOr(bad, 1);
+    else atomicAdd(&hist[l], 1);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < c; q += 256)
+    if (hist[q]) atomicAdd(&counts[q], hist[q]);
 }
 
 // partial[chunk][class][col] = sum of X[i][col] over rows of the chunk with label class.
@@ -32,7 +42,21 @@ __global__ void __launch_bounds__(256) k_lda_chunk_sums(const T* __restrict__ X,
   const int64_t r0 = (int64_t)chunk * kCenterRows;
   const int64_t r1 = min(n, r0 + kCenterRows);
   if (col < d) {
-    for (int64_t i = r0; i < r1; ++i) {
+    // 16 rows' labels and values loaded together, then added in row order
+    int64_t i = r0;
+    for (; i + 16 <= r1; i += 16) {
+      int l[16];
+      double x[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        l[u] = y[i + u];
+        x[u] = to_f64(X[(i + u) * d + col]);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (l[u] >= 0 && l[u] < c) acc[l[u]][threadIdx.x] += x[u];
+    }
+    for (; i < r1; ++i) {
       const int l = y[i];
       if (l >= 0 && l < c) acc[l][threadIdx.x] += to_f64(X[i * d + col]);
     }
@@ -62,14 +86,20 @@ template <> __device__ __forceinline__ double from_f64<double>(double v) { retur
 template <> __device__ __forceinline__ float from_f64<float>(double v) { return (float)v; }
 template <> __device__ __forceinline__ bf16 from_f64<bf16>(double v) { return __float2bfloat16((float)v); }
 
+// One workgroup per row: the row's label is read once, its class mean row
+// (in L2) is subtracted column by column.  A label out of range (already
+// flagged by k_lda_counts, which fails the solve) reads class 0's row.
 template <class T>
-__global__ void k_lda_center(const T* __restrict__ X, const int32_t* __restrict__ y, int64_t n, int d,
-                             const double* __restrict__ means, T* __restrict__ Xhat) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n * d) return;
-  const int64_t i = e / d;
-  const int col = (int)(e % d);
-  Xhat[e] = from_f64<T>(to_f64(X[e]) - means[(int64_t)y[i] * d + col]);
+__global__ void __launch_bounds__(256) k_lda_center(const T* __restrict__ X, const int32_t* __restrict__ y,
+                                                    int64_t n, int d, int c, const double* __restrict__ means,
+                                                    T* __restrict__ Xhat) {
+  const int64_t i = blockIdx.x;
+  if (i >= n) return;
+  const int l = y[i];
+  const double* __restrict__ mrow = means + (int64_t)((l >= 0 && l < c) ? l : 0) * d;
+  const T* __restrict__ xr = X + i * d;
+  T* __restrict__ hr = Xhat + i * d;
+  for (int col = threadIdx.x; col < d; col += 256) hr[col] = from_f64<T>(to_f64(xr[col]) - mrow[col]);
 }
 
 size_t lda_center_ws_bytes(int64_t n, int d, int c) {
@@ -80,6 +110,10 @@ size_t lda_center_ws_bytes(int64_t n, int d, int c) {
 template <class T>
 static int lda_center_t(const T* X, const int32_t* y, int64_t n, int d, int c, T* Xhat, double* Yhat,
                         int* counts, int* bad, Arena& ws, hipStream_t st) {
+  if (n > 0x7fffffffll) {
+    set_error("lda: at most 2^31 - 1 rows");
+    return SRP_EINVAL;
+  }
   const int nchunks = (int)((n + kCenterRows - 1) / kCenterRows);
   double* partial = ws.take<double>((size_t)nchunks * c * d);
   double* means = ws.take<double>((size_t)c * d);
@@ -93,8 +127,7 @@ static int lda_center_t(const T* X, const int32_t* y, int64_t n, int d, int c, T
   hipLaunchKernelGGL(k_lda_stats, dim3((d + 255) / 256), dim3(256), 0, st, partial, nchunks, counts, n, d, c, means,
                      Yhat);
   SRP_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_lda_center<T>), dim3((unsigned)((n * d + 255) / 256)), dim3(256), 0, st, X, y, n, d, means,
-                     Xhat);
+  hipLaunchKernelGGL((k_lda_center<T>), dim3((unsigned)n), dim3(256), 0, st, X, y, n, d, c, means, Xhat);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
