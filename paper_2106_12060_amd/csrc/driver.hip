@@ -179,6 +179,10 @@ struct RcgProblem {
   const double* Minv[2] = {nullptr, nullptr};
   const double* Yhat = nullptr;  // FDA: c x d rows sqrt(n_j)(m_j - m); S_B = Yhat^T Yhat
   int c = 0;
+  // Optional FP64 Gram blocks H[b][c] = A_b^T A_c (d_b x d_c, row-major):
+  // when set, the data products come from them instead of a pass over A
+  // (the sketched problem, whose Grams cost no more to read than its rows).
+  const double* H[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 struct RcgBuffers {
@@ -218,8 +222,11 @@ static int twopass_ksplit(int64_t n) {
 }
 
 static size_t skinny_bytes(int nb, int k, const int* d, int c) {
-  size_t b = 0;
+  size_t b = 0, g = 0;
   for (int s = 0; s < nb; ++s) b += skinny_ws_bytes(d[s], d[s], 2 * k) + 256;
+  for (int s = 0; s < nb; ++s)   // the Gram route's nb x nb products
+    for (int t = 0; t < nb; ++t) g += skinny_ws_bytes(d[s], d[t], k);
+  b = std::max(b, g);
   if (c > 0) b = std::max({b, skinny_ws_bytes(c, d[0], k), skinny_ws_bytes(d[0], c, k)});
   return b;
 }
@@ -343,10 +350,24 @@ static int twopass_f64(const RcgProblem& P, RcgBuffers& B, double* const* W, hip
   return SRP_OK;
 }
 
+// J_b = [H_b0 W_0 | H_b1 W_1] from the Gram blocks: the same products as
+// A_b^T [A_0 W_0 | A_1 W_1], in FP64.
+static int gram_products(const RcgProblem& P, RcgBuffers& B, double* const* W, hipStream_t st) {
+  const int k = P.k, nb = P.nb;
+  SkinnyProb pr[4];
+  int np = 0;
+  for (int b = 0; b < nb; ++b)
+    for (int c = 0; c < nb; ++c)
+      pr[np++] = SkinnyProb{P.d[b], P.d[c], k, P.H[b][c], P.d[c], false, W[c], k, B.J[b] + c * k, nb * k};
+  return gemm_skinny_batch(np, pr, B.skw, B.skw_bytes, st);
+}
+
 // Data products along directions W (d_b x k): fills J (and FDA's S_B W).
 static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int compute, const int* done,
                      hipStream_t st) {
-  if (compute == SRP_F64 && !pass_limits_ok(P.dtype, SRP_F64, P.d[0], P.d[1], P.k, P.nb)) {
+  if (P.H[0][0]) {
+    SRP_TRY(gram_products(P, B, W, st));
+  } else if (compute == SRP_F64 && !pass_limits_ok(P.dtype, SRP_F64, P.d[0], P.d[1], P.k, P.nb)) {
     SRP_TRY(twopass_f64(P, B, W, st));
   } else {
     Arena pw{B.pass_ws, B.pass_ws_bytes, 0};
@@ -718,6 +739,7 @@ size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sket
   bytes += 2 * bytes_of<double>((size_t)dx * dx) + 2 * bytes_of<double>((size_t)dy * dy);  // R, Minv (x) ...
   bytes += 2 * bytes_of<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
   bytes += bytes_of<int>(4);
+  bytes += 4 * bytes_of<double>((size_t)std::max(dx, dy) * std::max(dx, dy));   // Gram blocks of the sketch
   const size_t scratch = cca_view_scratch(n, dx, dy, s, dtype, sketch_kind);
   bytes += rcg_buffers_bytes(2, k, std::max<int64_t>(n, s), dd, dtype);
   bytes += 2 * ((scratch + 255) & ~size_t(255)) + 4096;   // one scratch per view (the views run concurrently)
@@ -731,7 +753,7 @@ size_t lda_ws_bytes(int64_t n, int d, int c, int k, int s, int dtype, int sketch
   size_t bytes = 0;
   bytes += (((size_t)n * d * esz + 255) & ~size_t(255));          // Xhat
   bytes += (((size_t)s * d * ssz + 255) & ~size_t(255));          // sketch
-  bytes += 3 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv
+  bytes += 4 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv, sketch Gram
   bytes += bytes_of<double>((size_t)c * d) + bytes_of<int>(c) + bytes_of<int>(4);
   const size_t scratch = std::max({sketch_ws(sketch_kind, n, d, s, dtype), factor_ws_bytes(s, d),
                                    lda_center_ws_bytes(n, d, c)});
@@ -819,8 +841,14 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   double* Rinv = ar.take<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
   double* Rinv2 = ar.take<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
   int* flag = ar.take<int>(4);
+  // Gram blocks of the sketch [S X | S Y] for the warm start
+  double* Hxx = ar.take<double>((size_t)dx * dx);
+  double* Hxy = ar.take<double>((size_t)dx * dy);
+  double* Hyx = ar.take<double>((size_t)dy * dx);
+  double* Hyy = ar.take<double>((size_t)dy * dy);
+  const bool gram_warm = opt.warm_start_iters > 0;
   RcgBuffers B{};
-  if (!flag || !Rinv2 || rcg_buffers_take(B, ar, 2, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
+  if (!flag || !Rinv2 || !Hyy || rcg_buffers_take(B, ar, 2, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
     set_error("workspace layout overflow");
     return SRP_ENOMEM;
   }
@@ -838,16 +866,30 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SY, s, dy, opt.sketch_scale_y, fk.side));
   {
     Arena sub{sy.base, sy.cap, 0};
-    SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side));
+    SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side, gram_warm ? Hyy : nullptr));
   }
   SRP_TRY(sketch_any(opt.sketch, skin_x, skin_dtype, n, dx, s, opt.seed, SX, sx, st));
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SX, s, dx, opt.sketch_scale_x, st));
   const double ms_sketch = tm.lap_ms();   // X view's sketch (Y's runs alongside)
   {
     Arena sub{sx.base, sx.cap, 0};
-    SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st));
+    SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st, gram_warm ? Hxx : nullptr));
   }
   SRP_TRY(fk.end(st));
+  if (gram_warm) {   // cross Gram (S X)^T (S Y), split over the s rows in the X view's scratch
+    const int64_t cnt = (int64_t)dx * dy;
+    int ks = gram_split(s, dx, dy);
+    ks = (int)std::max<int64_t>(1, std::min<int64_t>(ks, (int64_t)(scr / bytes_of<double>((size_t)cnt))));
+    double* parts = (double*)sx.base;
+    GemmArgs g{};
+    g.m = dx; g.n = dy; g.kk = s; g.alpha = 1.0; g.beta = 0.0;
+    g.A = SX; g.lda = dx; g.ta = true; g.a_f32 = sk_dtype != SRP_F64;
+    g.B = SY; g.ldb = dy; g.tb = false; g.b_f32 = sk_dtype != SRP_F64;
+    g.C = parts; g.ldc = dy; g.ksplit = ks; g.c_split_stride = cnt;
+    SRP_TRY(gemm_f64(g, st));
+    SRP_TRY(sum_parts_f64(parts, ks, cnt, cnt, Hxy, 0, 0.0, st));
+    SRP_TRY(transpose_f64(Hxy, dx, dy, Hyx, st));
+  }
   int hflag = 0;
   SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   SRP_HIP(hipStreamSynchronize(st));
@@ -865,6 +907,10 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   RcgProblem sk = full;
   sk.dtype = sk_dtype; sk.compute = (sk_dtype == SRP_F64) ? SRP_F64 : compute;
   sk.A[0] = SX; sk.A[1] = SY; sk.n = s;
+  if (gram_warm) {
+    sk.H[0][0] = Hxx; sk.H[0][1] = Hxy;
+    sk.H[1][0] = Hyx; sk.H[1][1] = Hyy;
+  }
   CommonArgs ca{k, tol, opt};
   double* outW[2] = {U, V};
   if (info) {
@@ -924,6 +970,8 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   double* R = ar.take<double>((size_t)d * d);
   double* Rinv = ar.take<double>((size_t)d * d);
   double* Minv = ar.take<double>((size_t)d * d);
+  double* Hs = ar.take<double>((size_t)d * d);   // Gram of the sketch, for the warm start
+  const bool gram_warm = opt.warm_start_iters > 0;
   double* Yhat = ar.take<double>((size_t)c * d);
   int* counts = ar.take<int>(c);
   int* flag = ar.take<int>(4);
@@ -951,7 +999,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   SRP_TRY(fill_i32(flag, 1, 0, st));
   {
     Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
-    SRP_TRY(sketch_factor_run(SXh, sk_dtype, s, d, lam, R, Rinv, Minv, flag, sub, st));
+    SRP_TRY(sketch_factor_run(SXh, sk_dtype, s, d, lam, R, Rinv, Minv, flag, sub, st, gram_warm ? Hs : nullptr));
   }
   int hflag = 0;
   SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -969,6 +1017,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   RcgProblem sk = full;
   sk.dtype = sk_dtype; sk.compute = (sk_dtype == SRP_F64) ? SRP_F64 : compute;
   sk.A[0] = SXh; sk.n = s;
+  if (gram_warm) sk.H[0][0] = Hs;
   CommonArgs ca{k, tol, opt};
   double* outW[2] = {Wout, nullptr};
   if (info) {

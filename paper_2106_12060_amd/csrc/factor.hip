@@ -174,10 +174,12 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
 constexpr int kSkSlice = 64;
 constexpr int kSkRowSlice = 128;
 
-// Up to two independent problems per launch (blockIdx.z), e.g. both views.
+// Up to four independent problems per launch (blockIdx.z): both views, or
+// the four blocks of a two-view Gram.
+constexpr int kSkMaxProbs = 4;
 struct SkinnyBatch {
-  SkinnyProb p[2];
-  double* part[2];
+  SkinnyProb p[kSkMaxProbs];
+  double* part[kSkMaxProbs];
   int slice;          // contraction length per partial
 };
 
@@ -369,6 +371,10 @@ int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_
   SkinnyBatch bt{};
   size_t used = 0;
   int gx = 1, gy = 1, sx = 1;
+  if (nprob < 1 || nprob > kSkMaxProbs) {
+    set_error("gemm_skinny: %d problems (1 to %d per launch)", nprob, kSkMaxProbs);
+    return SRP_EINVAL;
+  }
   for (int q = 0; q < nprob; ++q) {
     const SkinnyProb& p = probs[q];
     if (p.nc > 64 || p.nc < 1 || p.m < 1 || p.kk < 1 ||
@@ -602,22 +608,63 @@ size_t factor_ws_bytes(int s, int d) {
   const int tiles = (d + 63) / 64;
   const int ksplit = gram_ksplit(s, d);
   const size_t dd = (size_t)d * d;
-  return bytes_of<double>(dd) * (ksplit > 1 ? ksplit + 1 : 1) + bytes_of<double>((size_t)tiles * 4096) +
+  return bytes_of<double>(dd) * (ksplit + 1) + bytes_of<double>((size_t)tiles * 4096) +
          bytes_of<double>((size_t)64 * d) + bytes_of<double>(dd) + bytes_of<double>((size_t)kInvSplit * 64 * d);
 }
 
+// Full symmetric Gram from the upper-tile split partials: H[i][j] is the
+// partials' sum at (min(i, j), max(i, j)), added in split order (the same
+// sum as the factored Gram before lambda is added).
+__global__ void k_gram_full(const double* __restrict__ parts, int nparts, int64_t stride, int d,
+                            double* __restrict__ H) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d * d) return;
+  const int i = (int)(e / d), j = (int)(e - (int64_t)i * d);
+  const int64_t src = i <= j ? e : (int64_t)j * d + i;
+  double v = 0.0;
+  for (int z = 0; z < nparts; ++z) v += parts[z * stride + src];
+  H[e] = v;
+}
+
+__global__ void k_transpose_f64(const double* __restrict__ A, int rows, int cols, double* __restrict__ AT) {
+  __shared__ double t[32][33];
+  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 8 rows of 32
+  for (int r = ty; r < 32; r += 8)
+    if (r0 + r < rows && c0 + tx < cols) t[r][tx] = A[(int64_t)(r0 + r) * cols + c0 + tx];
+  __syncthreads();
+  for (int c = ty; c < 32; c += 8)
+    if (c0 + c < cols && r0 + tx < rows) AT[(int64_t)(c0 + c) * rows + r0 + tx] = t[tx][c];
+}
+
+int transpose_f64(const double* A, int rows, int cols, double* AT, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return SRP_OK;
+  hipLaunchKernelGGL(k_transpose_f64, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st, A, rows, cols, AT);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+int gram_split(int s, int d0, int d1) {
+  const int tiles = ((d0 + 63) / 64) * ((d1 + 63) / 64);
+  int ks = (2048 + tiles - 1) / tiles;
+  const int kmax = (s + 63) / 64;
+  if (ks > kmax) ks = kmax;
+  return ks < 1 ? 1 : ks;
+}
+
 int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
-                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st) {
+                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st, double* Hfull) {
   const int tiles = (d + 63) / 64;
   const int ksplit = gram_ksplit(s, d);
   const int64_t dd = (int64_t)d * d;
   double* G = ws.take<double>(dd);
-  double* parts = ksplit > 1 ? ws.take<double>(dd * ksplit) : nullptr;
+  const bool use_parts = ksplit > 1 || Hfull;
+  double* parts = use_parts ? ws.take<double>(dd * ksplit) : nullptr;
   double* Dinv = ws.take<double>((size_t)tiles * 4096);
   double* Tmp = ws.take<double>((size_t)64 * d);
   double* X = Rinv ? Rinv : ws.take<double>(dd);
   double* Tparts = ws.take<double>((size_t)kInvSplit * 64 * d);
-  if (!G || !Dinv || !Tmp || !X || !Tparts || (ksplit > 1 && !parts)) {
+  if (!G || !Dinv || !Tmp || !X || !Tparts || (use_parts && !parts)) {
     set_error("sketch_factor: workspace too small");
     return SRP_ENOMEM;
   }
@@ -628,11 +675,16 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
   g.A = SA; g.lda = d; g.ta = true; g.a_f32 = f32;
   g.B = SA; g.ldb = d; g.tb = false; g.b_f32 = f32;
   g.upper_only = true;
-  if (ksplit > 1) {
+  if (use_parts) {
     g.C = parts; g.ldc = d; g.ksplit = ksplit; g.c_split_stride = dd;
     SRP_TRY(fill_f64(parts, dd * ksplit, 0.0, st));
     SRP_TRY(gemm_f64(g, st));
     SRP_TRY(sum_parts_f64(parts, ksplit, dd, dd, G, d, lambda, st));
+    if (Hfull) {
+      hipLaunchKernelGGL(k_gram_full, dim3((unsigned)((dd + 255) / 256)), dim3(256), 0, st, parts, ksplit, dd, d,
+                         Hfull);
+      SRP_LAUNCH_CHECK();
+    }
   } else {
     g.C = G; g.ldc = d;
     SRP_TRY(fill_f64(G, dd, 0.0, st));

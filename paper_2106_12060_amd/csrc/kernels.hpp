@@ -44,7 +44,7 @@ struct SkinnyProb {
   const double* B; int64_t ldb;
   double* C; int64_t ldc;
 };
-// Up to two problems in one launch; ws holds skinny_ws_bytes of each, in order.
+// Up to four problems in one launch; ws holds skinny_ws_bytes of each, in order.
 int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_bytes, hipStream_t st);
 int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
                     double* C, int64_t ldc, double* ws, size_t ws_bytes, hipStream_t st);
@@ -54,9 +54,15 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
                   int d, double diag_add, hipStream_t st);
 
 // Gram of a sketch, Cholesky and inverse: R^T R = SA^T SA + lambda I.
+// Hfull (optional, d x d): the full symmetric Gram SA^T SA, without lambda.
 size_t factor_ws_bytes(int s, int d);
 int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
-                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st);
+                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st, double* Hfull = nullptr);
+// Split of an s-long Gram contraction over d0 x d1 outputs (about 2048
+// workgroups of 64 x 64 tiles).
+int gram_split(int s, int d0, int d1);
+// AT (cols x rows) = A^T for row-major A (rows x cols).
+int transpose_f64(const double* A, int rows, int cols, double* AT, hipStream_t st);
 
 // --------------------------------------------------------- data pass
 // J_b = A_b^T [A_0 W_0 | A_1 W_1] (see srp_gram_pass).  Arithmetic in
