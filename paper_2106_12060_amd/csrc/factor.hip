@@ -119,6 +119,101 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int kk, double a
       }
 }
 
+// Large A^T B (the sketch Grams): one workgroup = one 128 x 128 output
+// tile, each wave a 64 x 64 quadrant of 4 x 4 MFMA tiles (two products per
+// LDS operand read); the contraction runs in stages of 16 through two LDS
+// buffers, the next stage's global loads in flight during this stage's
+// products.
+constexpr int kGemmBigK = 16;
+template <class AT, class BT>
+__global__ void __launch_bounds__(256) k_gemm_f64_big(int m, int n, int kk, double alpha, const AT* __restrict__ A,
+                                                      int64_t lda, const BT* __restrict__ B, int64_t ldb, double beta,
+                                                      double* __restrict__ C, int64_t ldc, int upper_only, int kchunk,
+                                                      int64_t c_split_stride) {
+  constexpr int KS = kGemmBigK, P = 128 + 4, PER = KS * 128 / 256;
+  const int tj = blockIdx.x, ti = blockIdx.y, z = blockIdx.z;
+  if (upper_only && ti > tj) return;
+  const int i0 = ti * 128, j0 = tj * 128;
+  const int kbeg = z * kchunk;
+  const int kend = min(kk, kbeg + kchunk);
+  C += (int64_t)z * c_split_stride;
+  __shared__ double As[2][KS][P];   // [buffer][k][row]
+  __shared__ double Bs[2][KS][P];   // [buffer][k][col]
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wi = (w >> 1) * 64, wj = (w & 1) * 64;
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  AT ra[PER];
+  BT rb[PER];
+  auto load = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = t + q * 256;
+      const int kq = e >> 7, iq = e & 127;
+      const int gk = k0 + kq, gi = i0 + iq, gj = j0 + iq;
+      ra[q] = (gi < m && gk < kend) ? A[(int64_t)gk * lda + gi] : AT(0);
+      rb[q] = (gj < n && gk < kend) ? B[(int64_t)gk * ldb + gj] : BT(0);
+    }
+  };
+  auto store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = t + q * 256;
+      As[buf][e >> 7][e & 127] = (double)ra[q];
+      Bs[buf][e >> 7][e & 127] = (double)rb[q];
+    }
+  };
+  int buf = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = kbeg; k0 < kend; k0 += KS) {
+    const bool more = k0 + KS < kend;
+    if (more) load(k0 + KS);
+#pragma unroll
+    for (int s = 0; s < KS / 4; ++s) {
+      const int kl = 4 * s + (lane >> 4);
+      double av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[buf][kl][wi + 16 * a + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][kl][wj + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + wi + 16 * a + acc_row<double>(lane, r);
+        const int col = j0 + wj + 16 * b + (lane & 15);
+        if (row < m && col < n) {
+          double v = alpha * acc[a][b][r];
+          if (beta != 0.0) v += beta * C[(int64_t)row * ldc + col];
+          C[(int64_t)row * ldc + col] = v;
+        }
+      }
+}
+
+// The big-tile kernel takes A^T B with both output sides and the
+// contraction long enough to fill its tiles and stages.
+static bool gemm_big(const GemmArgs& g) {
+  return g.ta && !g.tb && g.m >= 256 && g.n >= 256 && g.kk >= 512;
+}
+
 template <class AT, class BT>
 static int gemm_dispatch_t(const GemmArgs& g, hipStream_t st) {
   dim3 grid((g.n + 63) / 64, (g.m + 63) / 64, g.ksplit);
@@ -126,6 +221,13 @@ static int gemm_dispatch_t(const GemmArgs& g, hipStream_t st) {
   if (g.ksplit > 1) kchunk = (((g.kk + g.ksplit - 1) / g.ksplit) + kGemmK - 1) / kGemmK * kGemmK;
   const AT* A = (const AT*)g.A;
   const BT* B = (const BT*)g.B;
+  if (gemm_big(g)) {   // kchunk is a multiple of kGemmK, hence of kGemmBigK
+    const dim3 gb((g.n + 127) / 128, (g.m + 127) / 128, g.ksplit);
+    hipLaunchKernelGGL((k_gemm_f64_big<AT, BT>), gb, dim3(256), 0, st, g.m, g.n, g.kk, g.alpha, A, g.lda, B, g.ldb,
+                       g.beta, g.C, g.ldc, (int)g.upper_only, kchunk, g.c_split_stride);
+    SRP_LAUNCH_CHECK();
+    return SRP_OK;
+  }
 #define SRP_GEMM_CASE(TA_, TB_)                                                                    \
   hipLaunchKernelGGL((k_gemm_f64<AT, BT, TA_, TB_>), grid, dim3(256), 0, st, g.m, g.n, g.kk, g.alpha, A, \
                      g.lda, B, g.ldb, g.beta, g.C, g.ldc, (int)g.upper_only, kchunk, g.c_split_stride)
@@ -592,14 +694,15 @@ __global__ void k_place_diag_blocks(const double* __restrict__ Dinv, int d, doub
 
 constexpr int kInvSplit = 8;   // split of the contraction in the R^-1 block rows
 
-// Split of the sketch Gram over the s rows: about 2048 workgroups over the
-// upper tiles (several per compute unit, so one's loads overlap another's
-// products), each contraction at least 64 rows long.
+// Split of the sketch Gram over the s rows: about 256 workgroups of the
+// big-tile kernel over the upper 128 x 128 tiles (measured best: d = 1000,
+// s = 4000 splits 8 ways, d = 2000, s = 8000 2 ways), each contraction at
+// least 512 rows long.
 static int gram_ksplit(int s, int d) {
-  const int tiles = (d + 63) / 64;
+  const int tiles = (d + 127) / 128;
   const int nupper = tiles * (tiles + 1) / 2;
-  int ksplit = (2048 + nupper - 1) / nupper;
-  const int kmax = (s + 63) / 64;
+  int ksplit = (256 + nupper - 1) / nupper;
+  const int kmax = (s + 511) / 512;
   if (ksplit > kmax) ksplit = kmax;
   return ksplit < 1 ? 1 : ksplit;
 }
@@ -645,9 +748,9 @@ int transpose_f64(const double* A, int rows, int cols, double* AT, hipStream_t s
 }
 
 int gram_split(int s, int d0, int d1) {
-  const int tiles = ((d0 + 63) / 64) * ((d1 + 63) / 64);
-  int ks = (2048 + tiles - 1) / tiles;
-  const int kmax = (s + 63) / 64;
+  const int tiles = ((d0 + 127) / 128) * ((d1 + 127) / 128);
+  int ks = (256 + tiles - 1) / tiles;
+  const int kmax = (s + 511) / 512;
   if (ks > kmax) ks = kmax;
   return ks < 1 ? 1 : ks;
 }

@@ -58,8 +58,8 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
 size_t factor_ws_bytes(int s, int d);
 int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
                       double* Minv, int* flag_dev, Arena& ws, hipStream_t st, double* Hfull = nullptr);
-// Split of an s-long Gram contraction over d0 x d1 outputs (about 2048
-// workgroups of 64 x 64 tiles).
+// Split of an s-long Gram contraction over d0 x d1 outputs (about 256
+// workgroups of 128 x 128 tiles).
 int gram_split(int s, int d0, int d1);
 // AT (cols x rows) = A^T for row-major A (rows x cols).
 int transpose_f64(const double* A, int rows, int cols, double* AT, hipStream_t st);

@@ -49,6 +49,29 @@ def test_cca_f64_small_workload():
     assert np.all(np.diff(sig.cpu().numpy()) <= 0)
 
 
+@pytest.mark.parametrize("dt,tol,bar", [("f32", 1e-6, 1e-6), ("f64", 1e-12, 1e-10)])
+def test_cca_unequal_wide_views(dt, tol, bar):
+    """dx = 300, dy = 264 (views wider than one 256-wide Gram tile pair, of
+    different widths), n = 8000, k = 6, lambda = 1e-3, s = 1200: the sketch
+    Grams and the cross Gram of the warm start take the 128 x 128-tile GEMM
+    with ragged edges and a split contraction.  Latent strengths span one
+    decade and the noise is twice the factor scale, so the top correlations
+    run from 0.99 down to 0.82 with sigma_7 = 0.72 (with little noise they
+    cluster near 1 and the k-th gap all but closes)."""
+    srp = _srp()
+    X, Y = synth.cca_latent(8000, 300, 264, r=8, noise=2.0, x_decades=1.0, factor_decades=1.0, seed=41,
+                            dtype=np.float32 if dt == "f32" else np.float64)
+    lam, k = 1e-3, 6
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), k, lam, lam, 1200, tol=tol, mu=[1.0] * k,
+                                    options=srp.srp_default_options(max_iter=3000, warm_start_iters=40))
+    err, cons = cca_errors(U, V, X, Y, lam, sig_true)
+    print("unequal wide views", dt, info, err, cons)
+    assert info["warm_iterations"] > 0
+    assert err < bar and cons < bar
+    np.testing.assert_allclose(sig.cpu().numpy(), sig_true[:k], rtol=0, atol=10 * bar)
+
+
 def test_cca_planted_vectors_pinned():
     """lambda = 0, planted distinct correlations: the weights are pinned
     (A^-1, B^-1 columns) and sigma = rho.  The solve ends when the cost
