@@ -319,9 +319,11 @@ static ProbView make_view(const RcgProblem& P, RcgBuffers& B) {
   return v;
 }
 
-// J_b = A_b^T [A_0 W_0 | A_1 W_1] with FP64 arithmetic through the generic
-// GEMM (two reads of the data); used where the fused pass has no FP64
-// instance for the shape.
+// J_b = A_b^T [A_0 W_0 | A_1 W_1] with FP64 arithmetic in two reads of the
+// data; used where the fused pass has no FP64 instance for the shape.  The
+// skinny products take it when A fits their 32-bit offsets: P = A W row
+// blocks over the whole contraction (no partials), then A^T P split over
+// the rows into at most ksplit partials; else the generic GEMM.
 static int twopass_f64(const RcgProblem& P, RcgBuffers& B, double* const* W, hipStream_t st) {
   const int k = P.k, nb = P.nb, ldp = nb * k;
   if (P.dtype == SRP_BF16) {
@@ -329,6 +331,26 @@ static int twopass_f64(const RcgProblem& P, RcgBuffers& B, double* const* W, hip
     return SRP_EINVAL;
   }
   const bool f32 = (P.dtype == SRP_F32);
+  const int64_t esz = f32 ? 4 : 8;
+  bool skinny = ldp <= 64 && P.n * ldp * 8 < (int64_t(1) << 31);
+  for (int s = 0; s < nb; ++s) skinny = skinny && P.n * P.d[s] * esz < (int64_t(1) << 31);
+  if (skinny) {
+    SkinnyProb pr[2];
+    for (int s = 0; s < nb; ++s) {
+      pr[s] = SkinnyProb{(int)P.n, P.d[s], k, P.A[s], P.d[s], false, W[s], k, B.Pn + s * k, ldp};
+      pr[s].a_f32 = f32;
+    }
+    SRP_TRY(gemm_skinny_batch(nb, pr, nullptr, 0, st, std::max(P.d[0], nb == 2 ? P.d[1] : 0)));
+    const int64_t rows_per = (P.n + B.ksplit - 1) / B.ksplit;
+    const int slice = (int)((rows_per + 31) / 32 * 32);
+    const size_t ws = bytes_of<double>((size_t)B.ksplit * std::max(P.d[0], nb == 2 ? P.d[1] : 0) * ldp);
+    for (int s = 0; s < nb; ++s) {
+      SkinnyProb q{P.d[s], (int)P.n, ldp, P.A[s], P.d[s], true, B.Pn, ldp, B.J[s], ldp};
+      q.a_f32 = f32;
+      SRP_TRY(gemm_skinny_batch(1, &q, B.parts, ws, st, slice));
+    }
+    return SRP_OK;
+  }
   for (int s = 0; s < nb; ++s) {
     GemmArgs g{};
     g.m = (int)P.n; g.n = k; g.kk = P.d[s]; g.alpha = 1.0; g.beta = 0.0;

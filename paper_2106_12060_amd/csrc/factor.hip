@@ -283,22 +283,35 @@ struct SkinnyBatch {
   SkinnyProb p[kSkMaxProbs];
   double* part[kSkMaxProbs];
   int slice;          // contraction length per partial
+  int direct;         // one slice covers every contraction: write C itself
 };
 
-// Transposed A (the FDA between-class factor): FP64 matrix cores, a
-// workgroup (4 waves) owns 64 rows x up to 64 columns of one contraction
-// slice; wave w computes rows 16w..16w+15 for every 16-column tile.
-// Operands are staged 32 contraction steps at a time.
+// Output of a workgroup: its slice's partial, or C itself when one slice
+// covers the contraction.
+__device__ __forceinline__ double* sk_out(const SkinnyBatch& bt, const SkinnyProb& pr, int64_t* ld) {
+  if (bt.direct) {
+    *ld = pr.ldc;
+    return pr.C;
+  }
+  *ld = pr.nc;
+  return bt.part[blockIdx.z] + (int64_t)blockIdx.y * pr.m * pr.nc;
+}
+
+// Transposed A (the FDA between-class factor, X^T P of the two-read data
+// products): FP64 matrix cores, a workgroup (4 waves) owns 64 rows x up to
+// 64 columns of one contraction slice; wave w computes rows 16w..16w+15 for
+// every 16-column tile.  Operands are staged 32 contraction steps at a
+// time (FP32 elements of A converted on load).
+template <class AT>
 __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
   const SkinnyProb& pr = bt.p[blockIdx.z];
   const int m = pr.m, kk = pr.kk, nc = pr.nc;
-  const double* __restrict__ A = pr.A;
   const double* __restrict__ B = pr.B;
   const int64_t lda = pr.lda, ldb = pr.ldb;
   const int r0 = blockIdx.x * 64;
-  const int lbeg = blockIdx.y * kSkSlice;
+  const int lbeg = blockIdx.y * bt.slice;
   if (r0 >= m || lbeg >= kk) return;
-  const int lend = min(kk, lbeg + kSkSlice);
+  const int lend = min(kk, lbeg + bt.slice);
   const int nct = (nc + 15) >> 4;
   __shared__ double As[32][65];   // [k][row]
   __shared__ double Bs[32][65];   // [k][col]
@@ -310,7 +323,7 @@ __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
   // masked element takes an offset past the resource (it reads zero), so
   // every load issues unconditionally and a stage's loads are in flight
   // together; the next stage's loads overlap this stage's products.
-  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(A, (int64_t)(pr.ta ? kk : m) * lda * 8);
+  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(pr.A, (int64_t)(pr.ta ? kk : m) * lda * (int64_t)sizeof(AT));
   const __amdgpu_buffer_rsrc_t brsrc = make_rsrc(B, (int64_t)kk * ldb * 8);
   double ra[8], rb[8];
   auto fetch = [&](int l0) __attribute__((always_inline)) {
@@ -321,7 +334,7 @@ __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
       if (pr.ta) { ll = e >> 6; rr = e & 63; } else { rr = e >> 5; ll = e & 31; }
       const int gr = r0 + rr, gl = l0 + ll;
       const int oa = pr.ta ? (gl * (int)lda + gr) : (gr * (int)lda + gl);
-      ra[q] = buf_load<double>(arsrc, (gr < m && gl < lend) ? oa * 8 : kOob, 0);
+      ra[q] = (double)buf_load<AT>(arsrc, (gr < m && gl < lend) ? oa * (int)sizeof(AT) : kOob, 0);
       const int bl = e >> 6, bj = e & 63;
       const int gbl = l0 + bl;
       rb[q] = buf_load<double>(brsrc, (bj < nc && gbl < lend) ? (gbl * (int)ldb + bj) * 8 : kOob, 0);
@@ -349,64 +362,83 @@ __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
     }
     __syncthreads();
   }
-  double* out = bt.part[blockIdx.z] + (int64_t)blockIdx.y * m * nc;
+  int64_t ldo;
+  double* out = sk_out(bt, pr, &ldo);
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = r0 + 16 * w + acc_row<double>(lane, r);
       const int col = 16 * q + (lane & 15);
-      if (q < nct && row < m && col < nc) out[(int64_t)row * nc + col] = acc[q][r];
+      if (q < nct && row < m && col < nc) out[(int64_t)row * ldo + col] = acc[q][r];
     }
 }
 
-// Row-major A (the M^-1 products): a workgroup owns 64 rows (16 per wave)
-// and a kSkRowSlice-long contraction slice.  A's rows go straight from HBM
-// into registers as matrix-core operands, the whole slice in flight at once
-// (lane (i, kq) of the wave holds A[row i][16 c + 4 kq + s], s = 0..3, for
-// chunk c: one 32-byte run per lane, as two 16-byte loads when VEC); the
-// slice of B is staged once in LDS.  Step s of chunk c multiplies over the
-// contraction indices 16 c + 4 kq + s (kq = 0..3, one per 16-lane row), so A
-// and B agree on the order and every index is taken once.
+// Row-major A (the M^-1 products, the sketch Gram products, X W of the
+// two-read data products): a workgroup owns 64 rows (16 per wave) and a
+// slice of the contraction, taken kSkRowSlice at a time.  A's rows go
+// straight from HBM into registers as matrix-core operands, a whole
+// sub-slice in flight at once (lane (i, kq) of the wave holds
+// A[row i][16 c + 4 kq + s], s = 0..3, for chunk c: one 32-byte run per lane
+// as two 16-byte loads when VEC, 16 bytes as one load for FP32 A); each
+// sub-slice of B is staged once in LDS.  Step s of chunk c multiplies over
+// the contraction indices 16 c + 4 kq + s (kq = 0..3, one per 16-lane row),
+// so A and B agree on the order and every index is taken once.
+// LOOP: slices longer than one sub-slice (else the single-pass body, whose
+// accumulators need not stay live across a loop).
 constexpr int sk_bpitch(int nct) { return (nct & 1) ? 16 * nct : 16 * nct + 16; }
-template <int NCT, bool VEC>
+template <class AT, int NCT, bool VEC, bool LOOP>
 __global__ void __launch_bounds__(256) k_gemm_skinny_rows(SkinnyBatch bt) {
   constexpr int KS = kSkRowSlice, NCH = KS / 16, P = sk_bpitch(NCT), NBC = 16 * NCT;
   constexpr int NB = (KS * NBC + 255) / 256;
   const SkinnyProb& pr = bt.p[blockIdx.z];
   const int m = pr.m, kk = pr.kk, nc = pr.nc;
   const int r0 = blockIdx.x * 64;
-  const int lbeg = blockIdx.y * KS;
-  if (r0 >= m || lbeg >= kk) return;
+  const int zbeg = blockIdx.y * bt.slice;
+  if (r0 >= m || zbeg >= kk) return;
+  const int zend = min(kk, zbeg + bt.slice);
   __shared__ double Bs[KS * P];   // [contraction][column], pitch P
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int i = lane & 15, kq = lane >> 4;
-  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(pr.A, (int64_t)m * pr.lda * 8);
+  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(pr.A, (int64_t)m * pr.lda * (int64_t)sizeof(AT));
   const __amdgpu_buffer_rsrc_t brsrc = make_rsrc(pr.B, (int64_t)kk * pr.ldb * 8);
+  f64x4 acc[NCT];
+#pragma unroll
+  for (int q = 0; q < NCT; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int lbeg = zbeg; lbeg < zend; lbeg += KS) {
+  const int lend = LOOP ? min(zend, lbeg + KS) : zend;
   double rb[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int e = tid + 256 * q;
     const int bl = e / NBC, bj = e - bl * NBC, gl = lbeg + bl;
-    rb[q] = buf_load<double>(brsrc, (e < KS * NBC && bj < nc && gl < kk) ? (gl * (int)pr.ldb + bj) * 8 : kOob, 0);
+    rb[q] = buf_load<double>(brsrc, (e < KS * NBC && bj < nc && gl < lend) ? (gl * (int)pr.ldb + bj) * 8 : kOob, 0);
   }
   const int row = r0 + 16 * w + i;
   double av[NCH][4];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int col = lbeg + 16 * c + 4 * kq;
-    if (VEC) {   // kk % 4 == 0, even lda, 16-byte aligned A: col < kk covers col + 3
-      const int off = (row < m && col < kk) ? (row * (int)pr.lda + col) * 8 : kOob;
+    if (VEC && sizeof(AT) == 8) {   // kk % 4 == 0, even lda, 16-byte aligned A: col < kk covers col + 3
+      const int off = (row < m && col < lend) ? (row * (int)pr.lda + col) * 8 : kOob;
       const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off, 0, 0);
       const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off + 16, 0, 0);
       av[c][0] = __builtin_bit_cast(double, (uint64_t)v0[0] | ((uint64_t)v0[1] << 32));
       av[c][1] = __builtin_bit_cast(double, (uint64_t)v0[2] | ((uint64_t)v0[3] << 32));
       av[c][2] = __builtin_bit_cast(double, (uint64_t)v1[0] | ((uint64_t)v1[1] << 32));
       av[c][3] = __builtin_bit_cast(double, (uint64_t)v1[2] | ((uint64_t)v1[3] << 32));
+    } else if (VEC) {               // FP32: kk % 4 == 0, lda % 4 == 0, 16-byte aligned A
+      const int off = (row < m && col < lend) ? (row * (int)pr.lda + col) * 4 : kOob;
+      const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(arsrc, off, 0, 0);
+      av[c][0] = (double)__builtin_bit_cast(float, (uint32_t)v0[0]);
+      av[c][1] = (double)__builtin_bit_cast(float, (uint32_t)v0[1]);
+      av[c][2] = (double)__builtin_bit_cast(float, (uint32_t)v0[2]);
+      av[c][3] = (double)__builtin_bit_cast(float, (uint32_t)v0[3]);
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        av[c][s] = buf_load<double>(arsrc, (row < m && col + s < kk) ? (row * (int)pr.lda + col + s) * 8 : kOob, 0);
+        av[c][s] = (double)buf_load<AT>(arsrc, (row < m && col + s < lend)
+                                                   ? (row * (int)pr.lda + col + s) * (int)sizeof(AT) : kOob, 0);
     }
   }
 #pragma unroll
@@ -418,9 +450,6 @@ __global__ void __launch_bounds__(256) k_gemm_skinny_rows(SkinnyBatch bt) {
     }
   }
   __syncthreads();
-  f64x4 acc[NCT];
-#pragma unroll
-  for (int q = 0; q < NCT; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -429,14 +458,18 @@ __global__ void __launch_bounds__(256) k_gemm_skinny_rows(SkinnyBatch bt) {
 #pragma unroll
       for (int q = 0; q < NCT; ++q) acc[q] = mfma16x16x4(av[c][s], bp[16 * q], acc[q]);
     }
-  double* out = bt.part[blockIdx.z] + (int64_t)blockIdx.y * m * nc;
+  if (!LOOP) break;
+  __syncthreads();   // the next sub-slice overwrites Bs
+  }
+  int64_t ldo;
+  double* out = sk_out(bt, pr, &ldo);
 #pragma unroll
   for (int q = 0; q < NCT; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int orow = r0 + 16 * w + acc_row<double>(lane, r);
       const int col = 16 * q + i;
-      if (orow < m && col < nc) out[(int64_t)orow * nc + col] = acc[q][r];
+      if (orow < m && col < nc) out[(int64_t)orow * ldo + col] = acc[q][r];
     }
 }
 
@@ -469,62 +502,78 @@ size_t skinny_ws_bytes(int m, int kk, int nc) {
   return bytes_of<double>(nsl * (size_t)m * nc);
 }
 
-int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_bytes, hipStream_t st) {
+int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_bytes, hipStream_t st,
+                      int slice) {
   SkinnyBatch bt{};
-  size_t used = 0;
-  int gx = 1, gy = 1, sx = 1;
   if (nprob < 1 || nprob > kSkMaxProbs) {
     set_error("gemm_skinny: %d problems (1 to %d per launch)", nprob, kSkMaxProbs);
     return SRP_EINVAL;
   }
+  const bool rows = !probs[0].ta, f32 = probs[0].a_f32;
+  const int64_t esz = f32 ? 4 : 8;
+  bool vec = true;
+  int nct = 1, gx = 1, kmax = 1, sx = 1;
   for (int q = 0; q < nprob; ++q) {
     const SkinnyProb& p = probs[q];
-    if (p.nc > 64 || p.nc < 1 || p.m < 1 || p.kk < 1 ||
-        (int64_t)(p.ta ? p.kk : p.m) * p.lda * 8 >= (int64_t(1) << 31) ||
+    if (p.ta != probs[0].ta || p.a_f32 != f32 || p.nc > 64 || p.nc < 1 || p.m < 1 || p.kk < 1 ||
+        (int64_t)(p.ta ? p.kk : p.m) * p.lda * esz >= (int64_t(1) << 31) ||
         (int64_t)p.kk * p.ldb * 8 >= (int64_t(1) << 31)) {
-      set_error("gemm_skinny: bad shape m=%d kk=%d nc=%d (operands must stay under 2 GiB)", p.m, p.kk, p.nc);
+      set_error("gemm_skinny: bad shape m=%d kk=%d nc=%d (one A type and layout per batch; operands under 2 GiB)",
+                p.m, p.kk, p.nc);
       return SRP_EINVAL;
     }
-    bt.p[q] = p;
-    bt.part[q] = (double*)((char*)ws + used);
-    used += skinny_ws_bytes(p.m, p.kk, p.nc);
+    vec = vec && p.kk % 4 == 0 && p.lda % (f32 ? 4 : 2) == 0 && ((uintptr_t)p.A & 15) == 0;
+    nct = std::max(nct, (p.nc + 15) / 16);
     gx = std::max(gx, (p.m + 63) / 64);
-    gy = std::max(gy, (p.kk + kSkSlice - 1) / kSkSlice);
+    kmax = std::max(kmax, p.kk);
     sx = std::max(sx, (int)(((int64_t)p.m * p.nc + 255) / 256));
   }
-  if (!ws || used > ws_bytes) {
+  // contraction per partial: whole sub-slices for the row kernel (the
+  // default, kSkRowSlice, needs no more workspace than kSkSlice)
+  int sl = slice > 0 ? slice : (rows ? kSkRowSlice : kSkSlice);
+  if (rows) sl = (sl + kSkRowSlice - 1) / kSkRowSlice * kSkRowSlice;
+  const int gy = (kmax + sl - 1) / sl;
+  bt.slice = sl;
+  bt.direct = gy == 1 ? 1 : 0;
+  size_t used = 0;
+  for (int q = 0; q < nprob; ++q) {
+    bt.p[q] = probs[q];
+    bt.part[q] = (double*)((char*)ws + used);
+    if (!bt.direct) used += bytes_of<double>((size_t)((probs[q].kk + sl - 1) / sl) * probs[q].m * probs[q].nc);
+  }
+  if (used > 0 && (!ws || used > ws_bytes)) {
     set_error("gemm_skinny: workspace too small");
     return SRP_ENOMEM;
   }
-  bool rows = true, vec = true;
-  int nct = 1;
-  for (int q = 0; q < nprob; ++q) {
-    const SkinnyProb& p = probs[q];
-    rows = rows && !p.ta;
-    vec = vec && p.kk % 4 == 0 && p.lda % 2 == 0 && ((uintptr_t)p.A & 15) == 0;
-    nct = std::max(nct, (p.nc + 15) / 16);
-  }
-  if (rows) {   // fewer, longer slices: the workspace sized for kSkSlice holds them
-    bt.slice = kSkRowSlice;
-    gy = 1;
-    for (int q = 0; q < nprob; ++q) gy = std::max(gy, (probs[q].kk + kSkRowSlice - 1) / kSkRowSlice);
-    const dim3 grid(gx, gy, nprob);
-#define SRP_SK_ROWS(N)                                                                       \
-    case N:                                                                                  \
-      if (vec) hipLaunchKernelGGL((k_gemm_skinny_rows<N, true>), grid, dim3(256), 0, st, bt);  \
-      else hipLaunchKernelGGL((k_gemm_skinny_rows<N, false>), grid, dim3(256), 0, st, bt);     \
+  const dim3 grid(gx, gy, nprob);
+  if (rows) {
+#define SRP_SK_ROWS_T(AT, N, V)                                                                         \
+      if (loop) hipLaunchKernelGGL((k_gemm_skinny_rows<AT, N, V, true>), grid, dim3(256), 0, st, bt);   \
+      else hipLaunchKernelGGL((k_gemm_skinny_rows<AT, N, V, false>), grid, dim3(256), 0, st, bt);
+#define SRP_SK_ROWS(N)                                                                                  \
+    case N:                                                                                             \
+      if (f32) {                                                                                        \
+        if (vec) { SRP_SK_ROWS_T(float, N, true) } else { SRP_SK_ROWS_T(float, N, false) }              \
+      } else {                                                                                          \
+        if (vec) { SRP_SK_ROWS_T(double, N, true) } else { SRP_SK_ROWS_T(double, N, false) }            \
+      }                                                                                                 \
       break;
+    const bool loop = sl > kSkRowSlice;
     switch (nct) {
       SRP_SK_ROWS(1) SRP_SK_ROWS(2) SRP_SK_ROWS(3) SRP_SK_ROWS(4)
     }
 #undef SRP_SK_ROWS
+#undef SRP_SK_ROWS_T
+  } else if (f32) {
+    hipLaunchKernelGGL(k_gemm_skinny<float>, grid, dim3(256), 0, st, bt);
   } else {
-    bt.slice = kSkSlice;
-    hipLaunchKernelGGL(k_gemm_skinny, dim3(gx, gy, nprob), dim3(256), 0, st, bt);
+    hipLaunchKernelGGL(k_gemm_skinny<double>, grid, dim3(256), 0, st, bt);
   }
   SRP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_skinny_sum, dim3(sx, nprob), dim3(256), 0, st, bt);
-  SRP_LAUNCH_CHECK();
+  if (!bt.direct) {
+    hipLaunchKernelGGL(k_skinny_sum, dim3(sx, nprob), dim3(256), 0, st, bt);
+    SRP_LAUNCH_CHECK();
+  }
   return SRP_OK;
 }
 

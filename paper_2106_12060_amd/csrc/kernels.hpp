@@ -34,18 +34,24 @@ struct GemmArgs {
   int64_t c_split_stride = 0;
 };
 int gemm_f64(const GemmArgs& g, hipStream_t st);
-// C (m x nc) = op(A) (m x kk) B (kk x nc) for nc <= 64 (row-major, FP64;
-// op(A) = A^T when ta, A then kk x m).  ws holds the split-K partials
-// (skinny_ws_bytes).
+// C (m x nc) = op(A) (m x kk) B (kk x nc) for nc <= 64 (row-major, FP64
+// arithmetic; op(A) = A^T when ta, A then kk x m; A FP64, or FP32 when
+// a_f32).  ws holds the split-K partials (skinny_ws_bytes with the default
+// slices).
 size_t skinny_ws_bytes(int m, int kk, int nc);
 struct SkinnyProb {
   int m, kk, nc;
-  const double* A; int64_t lda; bool ta;
+  const void* A; int64_t lda; bool ta;
   const double* B; int64_t ldb;
   double* C; int64_t ldc;
+  bool a_f32 = false;
 };
-// Up to four problems in one launch; ws holds skinny_ws_bytes of each, in order.
-int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_bytes, hipStream_t st);
+// Up to four problems in one launch (all with the same ta and A type); ws
+// holds the partials of each, in order.  slice: contraction length per
+// partial (0: the default); when one slice covers every problem's
+// contraction the products are written to C directly and ws may be null.
+int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_bytes, hipStream_t st,
+                      int slice = 0);
 int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* B, int64_t ldb,
                     double* C, int64_t ldc, double* ws, size_t ws_bytes, hipStream_t st);
 // out[i] = sum_z parts[z * stride + i] (+ diag_add on the diagonal of a

@@ -160,6 +160,29 @@ def test_lda_scaled_workload():
     assert cons < 1e-6
 
 
+@pytest.mark.parametrize("d", [1000, 1003])
+def test_lda_fp64_finish_two_reads(d):
+    """FP32 FDA with d past the fused FP64 pass (d = 1000, and 1003, whose
+    rows are not 16-byte multiples), n = 12000, 12 classes, k = 8,
+    CountSketch s = 4000: the finishing pass takes the two-read FP64 route
+    (P = X W, then X^T P split over the rows).  With the within-class
+    covariance over 6 decades its constraint residual is about 2e-7; wrong
+    products break the final retraction or leave residuals of order one."""
+    srp = _srp()
+    n, c, k = 12_000, 12, 8
+    X, y = synth.lda_classes(n, d, c, seed=17, dtype=np.float32)
+    lam = synth.lda_population_lambda(n, d)
+    rho_true, _ = direct.lda_direct(X, y, c, lam, k=k)
+    W, rho, info = srp.lda_solve(dev(X), dev(y), c, k, lam, 4000, tol=1e-5,
+                                 options=srp.srp_default_options(max_iter=1500, final_f64=-1))
+    _, _, _, Xh, Yh = direct.lda_scatter(X, y, c)
+    err = metrics.lda_rel_objective_error(W.cpu().numpy(), Xh, Yh, lam, rho_true)
+    cons = metrics.constraint_residual(W.cpu().numpy(), Xh, lam)
+    print("lda two-read FP64 finish", d, info, err, cons)
+    assert err < 1e-6
+    assert cons < 1e-6
+
+
 def test_lda_f64_two_classes_closed_form():
     srp = _srp()
     rng = np.random.default_rng(3)
