@@ -215,8 +215,8 @@ __global__ void k_count_pass(const int* __restrict__ done, int* __restrict__ ran
 static size_t kk_bytes() { return bytes_of<double>((size_t)(2 * KK_NSLOTS + 9) * KK_STRIDE); }
 
 static int twopass_ksplit(int64_t n) {
-  int64_t ks = (n + 4095) / 4096;
-  if (ks > 64) ks = 64;
+  int64_t ks = (n + 1023) / 1024;
+  if (ks > 128) ks = 128;
   if (ks < 1) ks = 1;
   return (int)ks;
 }

@@ -297,11 +297,12 @@ __device__ __forceinline__ double* sk_out(const SkinnyBatch& bt, const SkinnyPro
   return bt.part[blockIdx.z] + (int64_t)blockIdx.y * pr.m * pr.nc;
 }
 
-// Transposed A (the FDA between-class factor, X^T P of the two-read data
-// products): FP64 matrix cores, a workgroup (4 waves) owns 64 rows x up to
-// 64 columns of one contraction slice; wave w computes rows 16w..16w+15 for
-// every 16-column tile.  Operands are staged 32 contraction steps at a
-// time (FP32 elements of A converted on load).
+// Transposed A only (the FDA between-class factor, X^T P of the two-read
+// data products; row-major A takes k_gemm_skinny_rows): FP64 matrix cores,
+// a workgroup (4 waves) owns 64 rows x up to 64 columns of one contraction
+// slice; wave w computes rows 16w..16w+15 for every 16-column tile.
+// Operands are staged 32 contraction steps at a time (FP32 elements of A
+// converted on load).
 template <class AT>
 __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
   const SkinnyProb& pr = bt.p[blockIdx.z];
@@ -323,17 +324,16 @@ __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
   // masked element takes an offset past the resource (it reads zero), so
   // every load issues unconditionally and a stage's loads are in flight
   // together; the next stage's loads overlap this stage's products.
-  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(pr.A, (int64_t)(pr.ta ? kk : m) * lda * (int64_t)sizeof(AT));
+  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(pr.A, (int64_t)kk * lda * (int64_t)sizeof(AT));
   const __amdgpu_buffer_rsrc_t brsrc = make_rsrc(B, (int64_t)kk * ldb * 8);
   double ra[8], rb[8];
   auto fetch = [&](int l0) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = tid + 256 * q;
-      int rr, ll;
-      if (pr.ta) { ll = e >> 6; rr = e & 63; } else { rr = e >> 5; ll = e & 31; }
+      const int ll = e >> 6, rr = e & 63;   // A^T: 64 consecutive columns of one row of A
       const int gr = r0 + rr, gl = l0 + ll;
-      const int oa = pr.ta ? (gl * (int)lda + gr) : (gr * (int)lda + gl);
+      const int oa = gl * (int)lda + gr;
       ra[q] = (double)buf_load<AT>(arsrc, (gr < m && gl < lend) ? oa * (int)sizeof(AT) : kOob, 0);
       const int bl = e >> 6, bj = e & 63;
       const int gbl = l0 + bl;
@@ -341,13 +341,12 @@ __global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
     }
   };
   fetch(lbeg);
+#pragma unroll 1
   for (int l0 = lbeg; l0 < lend; l0 += 32) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int e = tid + 256 * q;
-      int rr, ll;
-      if (pr.ta) { ll = e >> 6; rr = e & 63; } else { rr = e >> 5; ll = e & 31; }
-      As[ll][rr] = ra[q];
+      As[e >> 6][e & 63] = ra[q];
       Bs[e >> 6][e & 63] = rb[q];
     }
     __syncthreads();
