@@ -297,80 +297,93 @@ __device__ __forceinline__ double* sk_out(const SkinnyBatch& bt, const SkinnyPro
   return bt.part[blockIdx.z] + (int64_t)blockIdx.y * pr.m * pr.nc;
 }
 
-// Transposed A only (the FDA between-class factor, X^T P of the two-read
-// data products; row-major A takes k_gemm_skinny_rows): FP64 matrix cores,
-// a workgroup (4 waves) owns 64 rows x up to 64 columns of one contraction
-// slice; wave w computes rows 16w..16w+15 for every 16-column tile.
-// Operands are staged 32 contraction steps at a time (FP32 elements of A
-// converted on load).
-template <class AT>
-__global__ void __launch_bounds__(256) k_gemm_skinny(SkinnyBatch bt) {
+// Transposed A (op(A) = A^T, A kk x m row-major: the FDA between-class
+// factor, X^T P of the two-read data products).  A workgroup owns 64
+// output rows (64 columns of A) and a slice of the contraction; every wave
+// covers all 64 rows (four 16-row tiles) and all columns of B, over the
+// 4-row steps w, w + 4, ... of the slice, so the four waves read 16
+// consecutive rows of A together.  Operands go straight from memory into
+// the FP64 matrix-core registers (lane (i, kq) holds A[l][c0 + 16 t + i]
+// and B[l][16 q + i] for its contraction row l), UG groups in flight at
+// once; the four waves' sums are added in wave order through LDS.
+template <class AT, int NCT>
+__global__ void __launch_bounds__(256) k_gemm_skinny_t(SkinnyBatch bt) {
+  constexpr int UG = 4;
   const SkinnyProb& pr = bt.p[blockIdx.z];
   const int m = pr.m, kk = pr.kk, nc = pr.nc;
-  const double* __restrict__ B = pr.B;
-  const int64_t lda = pr.lda, ldb = pr.ldb;
-  const int r0 = blockIdx.x * 64;
-  const int lbeg = blockIdx.y * bt.slice;
-  if (r0 >= m || lbeg >= kk) return;
-  const int lend = min(kk, lbeg + bt.slice);
-  const int nct = (nc + 15) >> 4;
-  __shared__ double As[32][65];   // [k][row]
-  __shared__ double Bs[32][65];   // [k][col]
+  const int c0 = blockIdx.x * 64;
+  const int zbeg = blockIdx.y * bt.slice;
+  if (c0 >= m || zbeg >= kk) return;
+  const int zend = min(kk, zbeg + bt.slice);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  f64x4 acc[4];
+  const int i = lane & 15, kq = lane >> 4;
+  const int lda = (int)pr.lda, ldb = (int)pr.ldb;
+  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(pr.A, (int64_t)kk * pr.lda * (int64_t)sizeof(AT));
+  const __amdgpu_buffer_rsrc_t brsrc = make_rsrc(pr.B, (int64_t)kk * pr.ldb * 8);
+  f64x4 acc[4][NCT];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // Operands of 32 contraction steps in registers, by buffer loads: a
-  // masked element takes an offset past the resource (it reads zero), so
-  // every load issues unconditionally and a stage's loads are in flight
-  // together; the next stage's loads overlap this stage's products.
-  const __amdgpu_buffer_rsrc_t arsrc = make_rsrc(pr.A, (int64_t)kk * lda * (int64_t)sizeof(AT));
-  const __amdgpu_buffer_rsrc_t brsrc = make_rsrc(B, (int64_t)kk * ldb * 8);
-  double ra[8], rb[8];
-  auto fetch = [&](int l0) __attribute__((always_inline)) {
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q;
-      const int ll = e >> 6, rr = e & 63;   // A^T: 64 consecutive columns of one row of A
-      const int gr = r0 + rr, gl = l0 + ll;
-      const int oa = gl * (int)lda + gr;
-      ra[q] = (double)buf_load<AT>(arsrc, (gr < m && gl < lend) ? oa * (int)sizeof(AT) : kOob, 0);
-      const int bl = e >> 6, bj = e & 63;
-      const int gbl = l0 + bl;
-      rb[q] = buf_load<double>(brsrc, (bj < nc && gbl < lend) ? (gbl * (int)ldb + bj) * 8 : kOob, 0);
+    for (int q = 0; q < NCT; ++q) acc[t][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int g0 = zbeg; g0 < zend; g0 += 16 * UG) {
+    AT a[UG][4];
+    double b[UG][NCT];
+#pragma unroll
+    for (int u = 0; u < UG; ++u) {
+      const int l = g0 + 16 * u + 4 * w + kq;   // this lane's contraction row
+      const bool lv = l < zend;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int col = c0 + 16 * t + i;
+        a[u][t] = buf_load<AT>(arsrc, (lv && col < m) ? (l * lda + col) * (int)sizeof(AT) : kOob, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < NCT; ++q) {
+        const int j = 16 * q + i;
+        b[u][q] = buf_load<double>(brsrc, (lv && j < nc) ? (l * ldb + j) * 8 : kOob, 0);
+      }
     }
-  };
-  fetch(lbeg);
-#pragma unroll 1
-  for (int l0 = lbeg; l0 < lend; l0 += 32) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q;
-      As[e >> 6][e & 63] = ra[q];
-      Bs[e >> 6][e & 63] = rb[q];
-    }
-    __syncthreads();
-    if (l0 + 32 < lend) fetch(l0 + 32);
+    for (int u = 0; u < UG; ++u)
 #pragma unroll
-    for (int s4 = 0; s4 < 8; ++s4) {
-      const int kl = 4 * s4 + (lane >> 4);
-      const double av = As[kl][16 * w + (lane & 15)];
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (q < nct) acc[q] = mfma16x16x4(av, Bs[kl][16 * q + (lane & 15)], acc[q]);
-    }
-    __syncthreads();
+        for (int q = 0; q < NCT; ++q) acc[t][q] = mfma16x16x4((double)a[u][t], b[u][q], acc[t][q]);
   }
+  // wave 0 adds waves 1, 2, 3 in order
+  __shared__ double red[4 * 4 * NCT][64];
+#pragma unroll 1
+  for (int src = 1; src < 4; ++src) {
+    __syncthreads();
+    if (w == src)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < NCT; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[(t * NCT + q) * 4 + r][lane] = acc[t][q][r];
+    __syncthreads();
+    if (w == 0)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < NCT; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[t][q][r] += red[(t * NCT + q) * 4 + r][lane];
+  }
+  if (w != 0) return;
   int64_t ldo;
   double* out = sk_out(bt, pr, &ldo);
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = r0 + 16 * w + acc_row<double>(lane, r);
-      const int col = 16 * q + (lane & 15);
-      if (q < nct && row < m && col < nc) out[(int64_t)row * ldo + col] = acc[q][r];
-    }
+    for (int q = 0; q < NCT; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = c0 + 16 * t + acc_row<double>(lane, r);
+        const int col = 16 * q + i;
+        if (row < m && col < nc) out[(int64_t)row * ldo + col] = acc[t][q][r];
+      }
 }
 
 // Row-major A (the M^-1 products, the sketch Gram products, X W of the
@@ -563,10 +576,16 @@ int gemm_skinny_batch(int nprob, const SkinnyProb* probs, double* ws, size_t ws_
     }
 #undef SRP_SK_ROWS
 #undef SRP_SK_ROWS_T
-  } else if (f32) {
-    hipLaunchKernelGGL(k_gemm_skinny<float>, grid, dim3(256), 0, st, bt);
   } else {
-    hipLaunchKernelGGL(k_gemm_skinny<double>, grid, dim3(256), 0, st, bt);
+#define SRP_SK_T(N)                                                                              \
+    case N:                                                                                      \
+      if (f32) hipLaunchKernelGGL((k_gemm_skinny_t<float, N>), grid, dim3(256), 0, st, bt);      \
+      else hipLaunchKernelGGL((k_gemm_skinny_t<double, N>), grid, dim3(256), 0, st, bt);         \
+      break;
+    switch (nct) {
+      SRP_SK_T(1) SRP_SK_T(2) SRP_SK_T(3) SRP_SK_T(4)
+    }
+#undef SRP_SK_T
   }
   SRP_LAUNCH_CHECK();
   if (!bt.direct) {
