@@ -268,11 +268,13 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
 
 // --------------------------------------------------------- skinny GEMM
 // C (m x nc) = op(A) (m x kk) B (kk x nc), nc <= 64: the per-iteration
-// products with M^-1 and the FDA between-class factor.  The contraction is
-// split over blockIdx.y into slices (kSkSlice for a transposed A,
-// kSkRowSlice otherwise); a workgroup writes the partial of its rows and
-// slice, and a second kernel adds the partials in slice order
-// (deterministic).
+// products with M^-1, the sketch Gram products of the warm start, the FDA
+// between-class factor and the two-read FP64 data products.  The
+// contraction is split over blockIdx.y into slices (by default kSkSlice
+// for a transposed A, kSkRowSlice otherwise; the caller may ask for longer
+// ones); a workgroup writes the partial of its rows and slice, and a
+// second kernel adds the partials in slice order (deterministic).  With a
+// single slice the workgroups write C directly.
 constexpr int kSkSlice = 64;
 constexpr int kSkRowSlice = 128;
 
