@@ -10,7 +10,7 @@
 
 namespace srp {
 
-constexpr int kCenterRows = 4096;
+constexpr int kCenterRows = 1024;
 constexpr int kCenterMaxC = 64;
 
 // Class counts: a histogram per workgroup in LDS, then one atomic add per
@@ -35,7 +35,8 @@ __global__ void __launch_bounds__(256) k_lda_counts(const int32_t* __restrict__ 
 template <class T>
 __global__ void __launch_bounds__(256) k_lda_chunk_sums(const T* __restrict__ X, const int32_t* __restrict__ y,
                                                         int64_t n, int d, int c, double* __restrict__ partial) {
-  __shared__ double acc[kCenterMaxC][256];
+  extern __shared__ double acc_raw[];   // c x 256: sized to the classes present
+  double (*acc)[256] = reinterpret_cast<double (*)[256]>(acc_raw);
   const int chunk = blockIdx.x;
   const int col = blockIdx.y * 256 + threadIdx.x;
   for (int q = 0; q < c; ++q) acc[q][threadIdx.x] = 0.0;
@@ -64,18 +65,35 @@ __global__ void __launch_bounds__(256) k_lda_chunk_sums(const T* __restrict__ X,
   }
 }
 
-// sums -> means, data mean, Yhat; one thread per column.
-__global__ void k_lda_stats(const double* __restrict__ partial, int nchunks, const int* __restrict__ counts,
-                            int64_t n, int d, int c, double* __restrict__ means, double* __restrict__ Yhat) {
+// Class sums over the chunks, in chunk order (16 chunks' loads in flight),
+// and class means; one thread per (class, column).  The sums go to Yhat,
+// which k_lda_yhat then overwrites.
+__global__ void __launch_bounds__(256) k_lda_class_sums(const double* __restrict__ partial, int nchunks,
+                                                        const int* __restrict__ counts, int d, int c,
+                                                        double* __restrict__ means, double* __restrict__ sums) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e >= (int64_t)c * d) return;
+  const int q = (int)(e / d);
+  double s = 0.0;
+  for (int z0 = 0; z0 < nchunks; z0 += 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = partial[(int64_t)(z0 + u < nchunks ? z0 + u : 0) * c * d + e];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (z0 + u < nchunks) s += t[u];
+  }
+  sums[e] = s;
+  means[e] = counts[q] > 0 ? s / counts[q] : 0.0;
+}
+
+// Data mean (class sums added in class order) and Yhat; one thread per column.
+__global__ void k_lda_yhat(const int* __restrict__ counts, int64_t n, int d, int c, const double* __restrict__ means,
+                           double* __restrict__ Yhat) {
   const int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= d) return;
   double total = 0.0;
-  for (int q = 0; q < c; ++q) {
-    double s = 0.0;
-    for (int z = 0; z < nchunks; ++z) s += partial[((int64_t)z * c + q) * d + col];
-    total += s;
-    means[(int64_t)q * d + col] = counts[q] > 0 ? s / counts[q] : 0.0;
-  }
+  for (int q = 0; q < c; ++q) total += Yhat[(int64_t)q * d + col];
   const double m = total / (double)n;
   for (int q = 0; q < c; ++q)
     Yhat[(int64_t)q * d + col] = sqrt((double)counts[q]) * (means[(int64_t)q * d + col] - m);
@@ -122,10 +140,14 @@ static int lda_center_t(const T* X, const int32_t* y, int64_t n, int d, int c, T
   SRP_TRY(fill_i32(bad, 1, 0, st));
   hipLaunchKernelGGL(k_lda_counts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, y, n, c, counts, bad);
   SRP_LAUNCH_CHECK();
-  hipLaunchKernelGGL((k_lda_chunk_sums<T>), dim3(nchunks, (d + 255) / 256), dim3(256), 0, st, X, y, n, d, c, partial);
+  const size_t lds = (size_t)c * 256 * sizeof(double);
+  SRP_TRY(allow_dynamic_lds((const void*)k_lda_chunk_sums<T>, lds));
+  hipLaunchKernelGGL((k_lda_chunk_sums<T>), dim3(nchunks, (d + 255) / 256), dim3(256), lds, st, X, y, n, d, c, partial);
   SRP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_lda_stats, dim3((d + 255) / 256), dim3(256), 0, st, partial, nchunks, counts, n, d, c, means,
-                     Yhat);
+  hipLaunchKernelGGL(k_lda_class_sums, dim3((unsigned)(((int64_t)c * d + 255) / 256)), dim3(256), 0, st, partial,
+                     nchunks, counts, d, c, means, Yhat);
+  SRP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_lda_yhat, dim3((d + 255) / 256), dim3(256), 0, st, counts, n, d, c, means, Yhat);
   SRP_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_lda_center<T>), dim3((unsigned)n), dim3(256), 0, st, X, y, n, d, c, means, Xhat);
   SRP_LAUNCH_CHECK();
