@@ -72,6 +72,26 @@ def test_cca_unequal_wide_views(dt, tol, bar):
     np.testing.assert_allclose(sig.cpu().numpy(), sig_true[:k], rtol=0, atol=10 * bar)
 
 
+def test_poll_interval_does_not_change_the_result():
+    """The host reads the convergence flag of the previous batch after it
+    has queued the next one; iterations queued after convergence return at
+    once on the device.  So the poll interval changes neither the
+    iterations nor any output bit."""
+    srp = _srp()
+    wl = synth.workload("cca-f64-small")
+    X, Y = wl.generate()
+    lam = wl.lam_value
+    outs = []
+    for ce in (1, 3, 4):
+        U, V, sig, info = srp.cca_solve(dev(X), dev(Y), wl.k, lam, lam, wl.s, tol=1e-10,
+                                        options=srp.srp_default_options(max_iter=2000, check_every=ce))
+        outs.append((U.cpu().numpy(), V.cpu().numpy(), sig.cpu().numpy(), info["iterations"]))
+    for U, V, sig, it in outs[1:]:
+        assert it == outs[0][3]
+        assert np.array_equal(U, outs[0][0]) and np.array_equal(V, outs[0][1])
+        assert np.array_equal(sig, outs[0][2])
+
+
 def test_cca_planted_vectors_pinned():
     """lambda = 0, planted distinct correlations: the weights are pinned
     (A^-1, B^-1 columns) and sigma = rho.  The solve ends when the cost
