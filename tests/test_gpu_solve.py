@@ -72,6 +72,23 @@ def test_cca_unequal_wide_views(dt, tol, bar):
     np.testing.assert_allclose(sig.cpu().numpy(), sig_true[:k], rtol=0, atol=10 * bar)
 
 
+def test_cca_f64_two_reads_every_iteration():
+    """FP64 CCA with dx + dy = 960, past the fused FP64 pass: every data
+    product takes the two-read FP64 route (X W by row blocks over the whole
+    contraction, then X^T P split over the rows), n = 6000, k = 4,
+    lambda = 1e-3, s = 2000; the iteration reaches the closed form."""
+    srp = _srp()
+    X, Y = synth.cca_latent(6000, 500, 460, r=6, noise=2.0, factor_decades=1.0, seed=23, dtype=np.float64)
+    lam, k = 1e-3, 4
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), k, lam, lam, 2000, tol=1e-11, mu=[1.0] * k,
+                                    options=srp.srp_default_options(max_iter=3000))
+    err, cons = cca_errors(U, V, X, Y, lam, sig_true)
+    print("f64 two reads", info, err, cons)
+    assert err < 1e-10 and cons < 1e-10
+    np.testing.assert_allclose(sig.cpu().numpy(), sig_true[:k], rtol=0, atol=1e-8)
+
+
 def test_poll_interval_does_not_change_the_result():
     """The host reads the convergence flag of the previous batch after it
     has queued the next one; iterations queued after convergence return at
