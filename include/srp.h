@@ -69,8 +69,9 @@ typedef struct srp_options {
                              from qf of a seeded Gaussian point              */
   int refresh_every;      /* recompute the data products B*U from the data
                              every this many iterations (default 25)         */
-  int check_every;        /* host polls the convergence flag every this many
-                             iterations (default 4)                          */
+  int check_every;        /* host reads the convergence flag every this many
+                             iterations, one batch behind the queued work
+                             (default 2; the result does not depend on it)   */
   int pass_compute;       /* arithmetic of the data passes: SRP_F64 or
                              SRP_F32 (default: F64 for F64 data, F32 else)   */
   int final_f64;          /* > 0 with F32 / BF16 passes: after the iteration

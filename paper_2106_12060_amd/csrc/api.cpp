@@ -39,7 +39,7 @@ int srp_default_options(srp_options* o) {
   o->max_iter = 1000;
   o->warm_start_iters = 40;
   o->refresh_every = 25;
-  o->check_every = 4;
+  o->check_every = 2;
   o->pass_compute = -1;
   o->final_f64 = 0;
   o->mu = nullptr;
