@@ -260,8 +260,8 @@ int cca_solve(const void* X, const void* Y, int64_t n, int dx, int dy, int k,
  * warm start, Riemannian CG on St_{S_w + lambda I} for Eq. lda_riemannian.
  * Outputs: W (d x k, double) with W^T (S_w + lambda I) W = I and
  * W^T S_B W = diag(rho); rho (k) descending.
- * Requires 1 <= k <= min(n_classes - 1, d), k <= 32, every class
- * non-empty, sketch_size >= d, lambda >= 0.
+ * Requires 2 <= n_classes <= 64, 1 <= k <= min(n_classes - 1, d),
+ * k <= 32, every class non-empty, sketch_size >= d, lambda >= 0.
  */
 int lda_solve(const void* X, const int32_t* labels, int64_t n, int d,
               int n_classes, int k, double lambda, int sketch_size,

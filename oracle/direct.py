@@ -4,7 +4,10 @@ Parity status: pinned.  ``tests/test_oracle_pins.py`` checks these against
 a dense generalized symmetric eigensolve, the Y = X closed form, planted
 correlations, invariance under invertible column transforms (lambda = 0),
 the two-class FDA closed form, and the constraint / diagonality conditions
-of the definitions.
+of the definitions.  The Hessian spectra and kappa* are pinned to the
+eigenvalues of the dense Riemannian Hessian operator (``stiefel``) at the
+optimum; the statistical dimension to a linear solve and its closed forms
+(rank at lambda -> 0, d / (1 + lambda) for orthonormal columns).
 """
 from __future__ import annotations
 
@@ -134,8 +137,49 @@ def lda_direct(X, labels, c: int, lam: float, k: int | None = None):
     return rho, W
 
 
+def cca_hessian_spectrum(sigma, mu, dx: int, dy: int) -> np.ndarray:
+    """Eigenvalues of the Riemannian Hessian at the CCA optimum with the
+    metric M = Sigma (proof of Theorem CCAHessiantheorem, Appendix B), for
+    sigma_1 > ... > sigma_p > sigma_{p+1} >= ... the min(dx, dy) canonical
+    correlations and N = diag(mu):
+    mu_j (sigma_j + sigma_i) and mu_j (sigma_j - sigma_i) for j <= p < i;
+    mu_j sigma_j, |dx - dy| times each; and for j < i <= p the pair
+    (mu_j + mu_i)(sigma_j + sigma_i) / 2, (mu_j - mu_i)(sigma_j - sigma_i) / 2.
+    Sorted ascending; p d - p (p + 1) values in all (d = dx + dy)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    s = np.asarray(sigma, dtype=np.float64)
+    p = len(mu)
+    q = min(dx, dy)
+    ev = []
+    for j in range(p):
+        for i in range(p, q):
+            ev += [mu[j] * (s[j] + s[i]), mu[j] * (s[j] - s[i])]
+        ev += [mu[j] * s[j]] * abs(dx - dy)
+        for i in range(j + 1, p):
+            ev += [0.5 * (mu[j] + mu[i]) * (s[j] + s[i]), 0.5 * (mu[j] - mu[i]) * (s[j] - s[i])]
+    return np.sort(np.array(ev))
+
+
+def lda_hessian_spectrum(rho, mu) -> np.ndarray:
+    """Eigenvalues of the Riemannian Hessian at the FDA optimum with the
+    metric M = S_w + lam I (proof of Theorem LDAHessiantheorem, Appendix C),
+    for rho the d generalized eigenvalues in descending order:
+    mu_j (rho_j - rho_i) for j <= p < i <= d, and
+    (mu_j - mu_i)(rho_j - rho_i) / 2 for j < i <= p.  Sorted ascending;
+    p d - p (p + 1) / 2 values."""
+    mu = np.asarray(mu, dtype=np.float64)
+    r = np.asarray(rho, dtype=np.float64)
+    p, d = len(mu), len(r)
+    ev = []
+    for j in range(p):
+        ev += [mu[j] * (r[j] - r[i]) for i in range(p, d)]
+        ev += [0.5 * (mu[j] - mu[i]) * (r[j] - r[i]) for i in range(j + 1, p)]
+    return np.sort(np.array(ev))
+
+
 def kappa_star_cca(sigma, mu) -> float:
-    """kappa*_CCA of Theorem CCAHessiantheorem (needs sigma_1..sigma_{p+1})."""
+    """kappa*_CCA of Theorem CCAHessiantheorem: the largest over the
+    smallest value of the spectrum above (needs sigma_1..sigma_{p+1})."""
     p = len(mu)
     s = np.asarray(sigma, dtype=np.float64)
     num = mu[0] * (s[0] + s[p])

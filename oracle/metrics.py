@@ -9,8 +9,13 @@
   sum mu_i sigma_i (Section 6.1);
 * principal angles between subspaces.
 
-Parity status: these are definitions used by tests; pinned indirectly by
-the oracle pins (they must read zero on the oracle's own solution).
+Parity status: pinned.  Besides reading zero at the oracle's solution,
+tests check that they flag wrong answers by the amounts the definitions
+fix: a point scaled by (1 + eps) has constraint residual 2 eps + eps^2; a
+column rotated by theta towards the next canonical pair loses exactly
+sin^2 theta (sigma_k - sigma_{k+1}) of the objective (CCA and FDA); random
+feasible points score below sum sigma_i (Ky Fan) with positive weighted
+sub-optimality; principal angles of a plane rotation equal its angle.
 """
 from __future__ import annotations
 

@@ -4,8 +4,10 @@ The low-precision forms of the method store the tall data in BF16, or in
 FP8 E4M3 with one power-of-two scale per column, before the sketch and the
 data products read it.  These are plain definitions of those encodings:
 
-* BF16: the upper 16 bits of an IEEE binary32 value after rounding to
-  nearest, ties to even, on the discarded 16 bits.
+* BF16: the float32 values with zero low 16 bits; encoding picks the
+  nearer of the two neighbouring BF16 values by exact comparison, ties to
+  the even significand, overflowing to infinity as IEEE round-to-nearest
+  does; a NaN keeps its sign and upper payload with the quiet bit set.
 * FP8 E4M3 (the OCP 8-bit format with 4 exponent bits, bias 7, 3 mantissa
   bits, no infinities, the all-ones pattern is NaN): the finite values are
   (-1)^s (m/8) 2^-6 for e = 0 and (-1)^s (1 + m/8) 2^(e-7) for e = 1..15
@@ -17,6 +19,11 @@ data products read it.  These are plain definitions of those encodings:
 
 The FP8 rounding is done by brute force over the table of all finite
 values, so it can be read against the definition directly.
+
+Parity status: pinned.  Tests check hand-worked ties, the unit roundoff
+bounds, subnormals, saturation, the largest values, NaN and infinities,
+and (BF16) an exhaustive sweep of neighbouring float32 patterns against a
+brute-force search over the ordered BF16 values.
 """
 from __future__ import annotations
 
@@ -26,11 +33,41 @@ FP8_MAX = 448.0
 
 
 def bf16_round(x) -> np.ndarray:
-    """float32 -> nearest BF16 (ties to even), returned as float32."""
-    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
-    bias = 0x7FFF + ((u >> 16) & 1)
-    r = ((u + bias) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32)
+    """float32 -> nearest BF16 value (ties to the even significand), returned
+    as float32, by exact comparison with the two neighbouring BF16 values.
+
+    BF16 values are the float32 values whose low 16 bits are zero.  For a
+    finite x the neighbours are lo (x with its low 16 bits cleared: the next
+    BF16 value towards zero) and hi (the next BF16 value away from zero).
+    Both distances are computed exactly in float64; the nearer one wins, a
+    tie goes to the neighbour whose last significand bit is 0.  Past the
+    largest finite BF16 value (2 - 2^-7) 2^127 the upper neighbour is
+    infinity, taken at 2^128 for the comparison (IEEE overflow of
+    round-to-nearest).  +-0 and +-inf are kept.  A NaN stays a NaN: its upper
+    16 bits with the quiet bit (bit 6 of the BF16 significand) set, so the
+    sign and the high payload bits are kept."""
+    x32 = np.ascontiguousarray(x, dtype=np.float32)
+    u = x32.view(np.uint32).astype(np.uint64)
+    sign = u & np.uint64(0x80000000)
+    mag = u & np.uint64(0x7FFFFFFF)
+    out = np.empty_like(u)
+    nan = mag > np.uint64(0x7F800000)
+    out[nan] = ((u[nan] >> np.uint64(16)) | np.uint64(0x40)) << np.uint64(16)
+    fin = ~nan
+    lo_bits = mag[fin] & np.uint64(0xFFFF0000)
+    hi_bits = lo_bits + np.uint64(0x10000)
+    v = np.abs(x32[fin].astype(np.float64))
+    lo = lo_bits.astype(np.uint32).view(np.float32).astype(np.float64)
+    hi = np.where(hi_bits >= np.uint64(0x7F800000), 2.0 ** 128,
+                  np.minimum(hi_bits, np.uint64(0x7F7FFFFF)).astype(np.uint32).view(np.float32).astype(np.float64))
+    with np.errstate(invalid="ignore"):
+        dlo = v - lo
+        dhi = hi - v
+    even_hi = ((hi_bits >> np.uint64(16)) & np.uint64(1)) == 0
+    pick_hi = np.isfinite(v) & ((dhi < dlo) | ((dhi == dlo) & even_hi))
+    res = np.where(pick_hi, np.minimum(hi_bits, np.uint64(0x7F800000)), lo_bits)
+    out[fin] = res | sign[fin]
+    return out.astype(np.uint32).view(np.float32)
 
 
 def fp8_e4m3_table():

@@ -12,7 +12,12 @@ M-self-adjointness of the projection, that the Sylvester solve reduces to
 S = sym(X^T B xi) when M = B (Appendix B), that the Cholesky form of the QR
 retraction equals B^-1/2 qf(B^1/2 (X + xi)) literally, that the retraction
 lands on the manifold, and that the Riemannian gradient reproduces finite
-differences of the cost along retraction curves.
+differences of the cost along retraction curves.  The Riemannian Hessians
+are pinned to the closed-form spectra at the optimum with M = B (proofs of
+Theorems CCAHessiantheorem and LDAHessiantheorem, Appendices B and C), to
+central differences of the extended gradient field projected on the
+tangent space (the Levi-Civita connection of a Riemannian submanifold of
+the constant-metric ambient space), and to self-adjointness in the metric.
 """
 from __future__ import annotations
 
@@ -83,6 +88,35 @@ def qf_B(X, B):
     return retract_qr(X, np.zeros_like(X), B)
 
 
+def rhess(X, B, M, egrad, ehess_eta, rgrad, eta):
+    """Riemannian Hessian applied to a tangent vector (Table 1):
+    Pi_X(M^-1 (D^2 f[eta] - B eta (X^T grad_E f - X^T M grad f))), with the
+    Euclidean gradient ``egrad``, the Euclidean Hessian applied to eta
+    ``ehess_eta`` and the Riemannian gradient ``rgrad`` at X.  Valid for a
+    constant metric M, the case of the sketched preconditioner."""
+    inner_kk = X.T @ egrad - X.T @ M @ rgrad
+    return project(X, B, M, np.linalg.solve(M, ehess_eta - B @ eta @ inner_kk))
+
+
+def tangent_basis(X, B, M):
+    """M-orthonormal basis (list of d x p matrices) of T_X St_B(p, d), of
+    dimension p d - p (p + 1) / 2: the projections of the canonical basis,
+    orthonormalised in the metric tr(xi^T M eta) (Table 1)."""
+    d, p = X.shape
+    cols = []
+    for i in range(d):
+        for j in range(p):
+            E = np.zeros((d, p))
+            E[i, j] = 1.0
+            cols.append(project(X, B, M, E).reshape(-1))
+    A = np.array(cols).T                      # (d p) x (d p) spanning set
+    G = A.T @ np.kron(M, np.eye(p)) @ A       # metric Gram of the set
+    w, Q = np.linalg.eigh(G)
+    keep = w > 1e-10 * w.max()
+    Bas = A @ (Q[:, keep] / np.sqrt(w[keep]))
+    return [Bas[:, i].reshape(d, p) for i in range(Bas.shape[1])]
+
+
 # --------------------------------------------------------------- CCA ---
 def cca_blocks(X, Y, lam_x, lam_y):
     X = np.asarray(X, dtype=np.float64)
@@ -113,6 +147,20 @@ def cca_rgrad(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu):
             project(V, Syy, Myy, np.linalg.solve(Myy, gv)))
 
 
+def cca_rhess(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu, xu, xv):
+    """Riemannian Hessian of the CCA cost applied to (xu, xv), Eq. HessCCA:
+    Pi_Z(M^-1 [-Sigma_cca xi N + Sigma (xi_U U^T Sxy V N ; xi_V V^T Sxy^T U N)
+    + Sigma (xi_U U^T ; xi_V V^T) M grad f]), block by block on the product
+    manifold (the Table 1 formula with grad_E f = -[Sxy V N; Sxy^T U N] and
+    D^2 f[xi] = -[Sxy xi_V N; Sxy^T xi_U N])."""
+    N = np.diag(mu)
+    gu, gv = cca_rgrad(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu)
+    eu, ev = cca_egrad(U, V, Sxy, mu)
+    hu = rhess(U, Sxx, Mxx, eu, -(Sxy @ xv @ N), gu, xu)
+    hv = rhess(V, Syy, Myy, ev, -(Sxy.T @ xu @ N), gv, xv)
+    return hu, hv
+
+
 # --------------------------------------------------------------- FDA ---
 def lda_cost(W, SB, mu) -> float:
     """f_FDA(W) = -1/2 tr(W^T S_B W N) (Eq. lda_riemannian)."""
@@ -129,6 +177,16 @@ def lda_rgrad(W, B, SB, M, mu):
     cost; Eq. LDAgrad read as grad = Pi(M^-1 (-S_B W N)), its printed
     second term being the first written out)."""
     return project(W, B, M, np.linalg.solve(M, lda_egrad(W, SB, mu)))
+
+
+def lda_rhess(W, B, SB, M, mu, xi):
+    """Riemannian Hessian of the FDA cost applied to xi, Eq. LDAhess:
+    Pi_W(M^-1 [-S_B xi N + B xi (W^T S_B W N + W^T M grad f)]).  The printed
+    equation adds grad f (d x p) to a p x p matrix; it is read as W^T M grad f,
+    the term of the Table 1 formula with grad_E f = -S_B W N."""
+    N = np.diag(mu)
+    g = lda_rgrad(W, B, SB, M, mu)
+    return rhess(W, B, M, lda_egrad(W, SB, mu), -(SB @ xi @ N), g, xi)
 
 
 # ----------------------------------------------------- data products ---

@@ -70,6 +70,17 @@ template <> __device__ __forceinline__ float load_as<float, float>(const float* 
 template <> __device__ __forceinline__ float load_as<float, bf16>(const bf16* p) { return to_f32(*p); }
 template <> __device__ __forceinline__ float load_as<float, double>(const double* p) { return (float)*p; }
 
+// BF16 bits of v: round to nearest, ties to even, on the 16 discarded bits
+// (adding 0x7FFF plus the kept lowest bit carries into the kept bits exactly
+// when the discarded part is above half, or at half with an odd kept part;
+// a carry out of the largest finite value gives the infinity pattern).  A
+// NaN keeps its sign and upper payload with the quiet bit set.
+__device__ __forceinline__ uint16_t bf16_rne_bits(float v) {
+  const uint32_t u = __float_as_uint(v);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
 // FP8 E4M3 code (OCP: bias 7, 3 mantissa bits, no infinities).
 struct fp8e4m3 {
   uint8_t v;

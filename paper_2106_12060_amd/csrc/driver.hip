@@ -965,7 +965,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   SRP_REQUIRE(X && labels && Wout && rho, "null pointer argument");
   SRP_REQUIRE(dtype == SRP_F64 || dtype == SRP_F32 || dtype == SRP_BF16, "bad dtype %d", dtype);
   SRP_REQUIRE(n >= 2 && n < (int64_t(1) << 31), "n out of range");
-  SRP_REQUIRE(c >= 2 && d >= 1, "need >= 2 classes and d >= 1");
+  SRP_REQUIRE(c >= 2 && c <= kLdaMaxClasses && d >= 1, "need 2 <= n_classes <= %d and d >= 1", kLdaMaxClasses);
   SRP_REQUIRE(k >= 1 && k <= std::min(c - 1, d) && k <= KMAX, "need 1 <= k <= min(c-1, d), k <= 32");
   SRP_REQUIRE(s >= d, "sketch_size must be >= d");
   SRP_REQUIRE(lam >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
@@ -1008,13 +1008,13 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
     Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
     SRP_TRY(lda_center_run(X, labels, dtype, n, d, c, Xhat, Yhat, counts, flag + 1, sub, st));
   }
-  int hc[64];
+  int hc[kLdaMaxClasses];
   int hbad = 0;
   SRP_HIP(hipMemcpyAsync(&hbad, flag + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-  SRP_HIP(hipMemcpyAsync(hc, counts, sizeof(int) * std::min(c, 64), hipMemcpyDeviceToHost, st));
+  SRP_HIP(hipMemcpyAsync(hc, counts, sizeof(int) * c, hipMemcpyDeviceToHost, st));
   SRP_HIP(hipStreamSynchronize(st));
   SRP_REQUIRE(!hbad, "label out of range [0, %d)", c);
-  for (int q = 0; q < std::min(c, 64); ++q) SRP_REQUIRE(hc[q] > 0, "class %d is empty", q);
+  for (int q = 0; q < c; ++q) SRP_REQUIRE(hc[q] > 0, "class %d is empty", q);
   // 2. sketch of Xhat and metric factor
   SRP_TRY(sketch_any(opt.sketch, Xhat, dtype, n, d, s, opt.seed, SXh, ar, st));
   const double ms_sketch = tm.lap_ms();

@@ -82,6 +82,9 @@ int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_
 // FDA centring (Section 5.1): class counts and FP64 sums, Yhat rows
 // sqrt(n_k)(m_k - m), and the materialised Xhat = X - m_{y_i} in the data
 // type.  Returns SRP_EINVAL (via *bad) for labels out of range.
+// Largest number of FDA classes: the centring kernels keep one LDS
+// histogram bin and one 256-column accumulator row per class.
+constexpr int kLdaMaxClasses = 64;
 size_t lda_center_ws_bytes(int64_t n, int d, int c);
 int lda_center_run(const void* X, const int32_t* labels, int dtype, int64_t n, int d, int c, void* Xhat,
                    double* Yhat, int* counts, int* bad, Arena& ws, hipStream_t st);

@@ -11,7 +11,7 @@
 namespace srp {
 
 constexpr int kCenterRows = 1024;
-constexpr int kCenterMaxC = 64;
+constexpr int kCenterMaxC = kLdaMaxClasses;
 
 // Class counts: a histogram per workgroup in LDS, then one atomic add per
 // class and workgroup (integer sums: the order does not matter).

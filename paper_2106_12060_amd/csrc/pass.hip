@@ -1193,8 +1193,7 @@ __global__ void k_pack_dir_bf(const double* __restrict__ W0, int d0, int dp0, un
   }
   const int r = i >> 4, c = i & 15;
   const float v = (r < d && c < k) ? (float)W[(int64_t)r * k + c] : 0.0f;
-  const uint32_t u = __float_as_uint(v);
-  Wp[i] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  Wp[i] = bf16_rne_bits(v);
 }
 
 // Per-block work of k_pass_bf; the LDS regions arrive as separate restrict
@@ -1257,8 +1256,7 @@ __device__ __forceinline__ void bf_step(const unsigned short* __restrict__ xs, u
     float v = 0.f;
 #pragma unroll
     for (int ww = 0; ww < kDmaWaves; ++ww) v += red[(ww * NT + nt) * 256 + q];
-    const uint32_t u = __float_as_uint(v);
-    pb[nt * 256 + (q & 15) * 16 + (q >> 4)] = (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    pb[nt * 256 + (q & 15) * 16 + (q >> 4)] = bf16_rne_bits(v);
   }
   lds_only_barrier();
   // (d)

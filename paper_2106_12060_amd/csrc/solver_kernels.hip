@@ -1578,8 +1578,12 @@ __global__ void __launch_bounds__(256) k_sign_fix(ProbView p) {
     }
     __syncthreads();
   }
-  const bool flip = s0.U[(int64_t)bi[0] * k + j] < 0.0;
-  if (!flip) return;
+  // One thread reads the winning entry's sign; every thread waits for it
+  // before any write to the column (the thread that owns that row negates it).
+  __shared__ int flip_sh;
+  if (threadIdx.x == 0) flip_sh = s0.U[(int64_t)bi[0] * k + j] < 0.0;
+  __syncthreads();
+  if (!flip_sh) return;
   for (int b = 0; b < p.nb; ++b) {
     const SideView& s = p.s[b];
     for (int i = threadIdx.x; i < s.d; i += 256) s.U[(int64_t)i * k + j] = -s.U[(int64_t)i * k + j];

@@ -1,7 +1,8 @@
 // Reduced-precision staging of the tall data: the BF16 and FP8 E4M3 copies
 // that the low-precision forms of the sketch and of the data passes read.
 //
-//  * BF16: round to nearest even on the 16 discarded bits of the FP32 value.
+//  * BF16: round to nearest even on the 16 discarded bits of the FP32 value;
+//    a NaN stays a quiet NaN with its sign and upper payload.
 //  * FP8 E4M3 (OCP; bias 7, 3 mantissa bits, no infinities, 448 largest):
 //    each column j is scaled by the smallest power of two 2^e_j with
 //    max_i |x_ij| <= 448 2^e_j (exact comparisons), then every entry is
@@ -19,9 +20,7 @@ namespace srp {
 __global__ void k_stage_bf16(const float* __restrict__ X, int64_t count, uint16_t* __restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= count) return;
-  const uint32_t u = __float_as_uint(X[i]);
-  const uint32_t r = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
-  out[i] = (uint16_t)r;
+  out[i] = bf16_rne_bits(X[i]);
 }
 
 // Column maxima of |x|: non-negative floats order like their bit patterns,

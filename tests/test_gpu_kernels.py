@@ -117,6 +117,28 @@ def test_sketch_factor_matches_cholesky(s, d, dt, lam):
     np.testing.assert_allclose(Rinv @ R, np.eye(d), atol=1e-13 * np.sqrt(kappa) * d)
 
 
+@pytest.mark.parametrize("s,d", [(4000, 1000), (8000, 2000)])
+def test_sketch_factor_at_solver_sizes(s, d):
+    """The factor at the sizes the solvers use (16 and 32 diagonal blocks of
+    64 columns, 128 x 128 Gram tiles over a split contraction): R^T R equals
+    the sketched Gram plus lambda I to FP64 rounding, and R^-1 R = I."""
+    srp = _srp()
+    SA, SAq = quantised(rand_data(s, d, 300 + d, decades=2.0), "f32")
+    lam = 1e-4
+    R, Rinv = srp.srp_sketch_factor(SA, lam)
+    R = R.cpu().numpy()
+    Rinv = Rinv.cpu().numpy()
+    assert np.allclose(np.tril(R, -1), 0.0) and np.all(np.diag(R) > 0)
+    assert np.allclose(np.tril(Rinv, -1), 0.0)
+    G = SAq.T @ SAq + lam * np.eye(d)
+    assert np.max(np.abs(R.T @ R - G)) <= 1e-13 * d * np.max(np.abs(G))
+    ref = osk.sketch_factor(SAq, lam)
+    w = np.linalg.eigvalsh(G)
+    kappa = w[-1] / w[0]
+    assert np.max(np.abs(R - ref)) <= 1e-14 * kappa * np.max(np.abs(ref))
+    np.testing.assert_allclose(Rinv @ R, np.eye(d), atol=1e-13 * np.sqrt(kappa) * d)
+
+
 def test_sketch_factor_reports_not_spd():
     srp = _srp()
     SA = torch.zeros((40, 8), dtype=torch.float64, device=DEV)
@@ -214,6 +236,13 @@ def test_stage_bf16_bit_exact():
     rng = np.random.default_rng(11)
     X = (rng.standard_normal((1037, 129)) * np.exp(rng.uniform(-20, 20, (1037, 129)))).astype(np.float32)
     X[0, :5] = [0.0, -0.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -3.0e38]
+    # infinities, NaNs whose payload sits only in the low 16 bits (they must
+    # stay NaN), FLT_MAX (overflows to inf), ties at the largest BF16 values
+    # and subnormal ties
+    special = np.array([0x7F800000, 0xFF800000, 0x7F800001, 0xFF80FFFF, 0x7FC00000, 0x7F7FFFFF,
+                        0x7F7F7FFF, 0x7F7F8000, 0x7F7E8000, 0x00008000, 0x00018000, 0x80000001],
+                       dtype=np.uint32).view(np.float32)
+    X[1, :special.size] = special
     got = srp.srp_stage_bf16(torch.from_numpy(X).to(DEV)).float().cpu().numpy()
     np.testing.assert_array_equal(got.view(np.uint32), quant.bf16_round(X).view(np.uint32))
 

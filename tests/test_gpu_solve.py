@@ -351,3 +351,64 @@ def test_cca_views_whose_factor_splits_differ():
     err, cons = cca_errors(U, V, X, Y, lam, sig_true)
     print("split views", info["iterations"], err, cons)
     assert err < 1e-6 and cons < 1e-6
+
+
+def test_cca_sign_convention_with_largest_entries_past_row_256():
+    """The sign convention flips a column pair when the largest |entry| of
+    the U column is negative.  Here every U column has its largest entry at
+    a row past 256 (the columns of X are scaled over three decades, so the
+    weights peak at the small-scale columns): the workgroup thread that owns
+    that row negates it while the others decide whether to flip, so the
+    decision must be taken once and shared before any write.  Two seeds give
+    different signs before the fix; every column must end with a positive
+    largest entry and the constraints intact."""
+    srp = _srp()
+    X, Y = synth.cca_latent(20000, 600, 520, r=8, noise=1.0, x_decades=3.0, factor_decades=1.0, seed=61,
+                            dtype=np.float32)
+    lam, k = 1e-3, 6
+    sig_true, U_true, _ = direct.cca_direct(X, Y, lam, lam, k=k)
+    assert np.all(np.argmax(np.abs(U_true), axis=0) >= 256)
+    for seed in (3, 4):
+        U, V, sig, info = srp.cca_solve(dev(X), dev(Y), k, lam, lam, 2400, tol=1e-6,
+                                        options=srp.srp_default_options(max_iter=500, seed=seed))
+        err, cons = cca_errors(U, V, X.astype(np.float64), Y.astype(np.float64), lam, sig_true)
+        Uh = U.cpu().numpy()
+        print("sign fix", seed, info, err, cons)
+        j = np.argmax(np.abs(Uh), axis=0)
+        assert np.all(Uh[j, np.arange(k)] > 0)
+        assert cons < 1e-6 and err < 1e-6
+        # same phase: u_i^T Sxy v_i >= 0 for every pair
+        XU = X.astype(np.float64) @ Uh
+        YV = Y.astype(np.float64) @ V.cpu().numpy()
+        assert np.all(np.sum(XU * YV, axis=0) > 0)
+
+
+@pytest.mark.parametrize("c,k", [(22, 21), (33, 32)])
+def test_lda_more_than_twenty_directions(c, k):
+    """FDA with k = 21 and k = 32 (the ABI's limit): the one-view pass past
+    the 4x4-block instance (register-staged rows) and the controllers'
+    largest k x k instances.  k = c - 1 takes every between-class
+    direction, a subspace separated from the null space of S_B, so equal
+    weights converge quickly; the closing Rayleigh-Ritz step orders it."""
+    srp = _srp()
+    n, d = c * 600, 200
+    X, y = synth.lda_classes(n, d, c, decades=2.0, seed=70 + c, dtype=np.float32)
+    lam = synth.lda_population_lambda(n, d)
+    rho_true, _ = direct.lda_direct(X, y, c, lam, k=k)
+    W, rho, info = srp.lda_solve(dev(X), dev(y), c, k, lam, 800, tol=1e-7, mu=[1.0] * k,
+                                 options=srp.srp_default_options(max_iter=1000, final_f64=-1))
+    _, _, _, Xh, Yh = direct.lda_scatter(X, y, c)
+    err = metrics.lda_rel_objective_error(W.cpu().numpy(), Xh, Yh, lam, rho_true)
+    cons = metrics.constraint_residual(W.cpu().numpy(), Xh, lam)
+    print("lda k", k, info, err, cons)
+    assert err < 1e-6 and cons < 1e-6
+    np.testing.assert_allclose(rho.cpu().numpy(), rho_true[:k], rtol=1e-5)
+
+
+def test_lda_rejects_too_many_classes():
+    srp = _srp()
+    X = torch.zeros((650, 8), dtype=torch.float32, device=DEV)
+    y = torch.arange(650, dtype=torch.int32, device=DEV) % 65
+    with pytest.raises(srp.SrpError) as e:
+        srp.lda_solve(X, y, 65, 2, 0.1, 16)
+    assert e.value.code == srp.SRP_EINVAL

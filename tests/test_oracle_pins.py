@@ -501,3 +501,282 @@ def test_fp8_column_scales_are_powers_of_two_and_exact():
     back = quant.fp8_unstage(codes, sc2)
     ok = np.abs(X) >= 2.0 ** -6 * sc2[None, :]
     assert np.all(np.abs(back - X)[ok] <= 2.0 ** -4 * np.abs(X)[ok])
+
+
+def test_bf16_round_special_values():
+    """Infinities, signed zeros, NaN (quiet, sign kept), the largest finite
+    BF16 value, and overflow: FLT_MAX lies past the midpoint between the
+    largest BF16 value and 2^128, so round-to-nearest overflows to inf."""
+    from oracle import quant
+    bits = np.array([0x7F800000, 0xFF800000, 0x00000000, 0x80000000, 0x7F800001, 0xFF800001,
+                     0x7FC00000, 0xFFFFFFFF, 0x7F7F0000, 0x7F7FFFFF, 0x7F7F7FFF, 0x7F7F8000,
+                     0x7F7E8000, 0x00000001, 0x00008000, 0x00018000], dtype=np.uint32)
+    expect = np.array([0x7F80, 0xFF80, 0x0000, 0x8000, 0x7FC0, 0xFFC0,
+                       0x7FC0, 0xFFFF, 0x7F7F, 0x7F80, 0x7F7F, 0x7F80,
+                       0x7F7E, 0x0000, 0x0000, 0x0002], dtype=np.uint32)
+    got = quant.bf16_round(bits.view(np.float32)).view(np.uint32)
+    np.testing.assert_array_equal(got >> 16, expect)
+    np.testing.assert_array_equal(got & 0xFFFF, 0)
+
+
+def test_bf16_round_matches_search_over_all_values():
+    """Nearest BF16 value found by searching the ordered list of every finite
+    non-negative BF16 value (2^128 standing in for the overflow to inf),
+    ties to the even code: an independent route to the same rounding."""
+    from oracle import quant
+    codes = np.arange(0x0000, 0x7F80, dtype=np.uint32)          # every finite magnitude
+    vals = (codes << 16).view(np.float32).astype(np.float64)
+    vals = np.append(vals, 2.0 ** 128)
+    codes = np.append(codes, 0x7F80)
+    rng = np.random.default_rng(3)
+    # random patterns over the whole finite range plus dense sweeps at ties
+    u = rng.integers(0, 0x7F800000, size=200_000, dtype=np.uint32)
+    ties = (rng.integers(0, 0x7F7F, size=20_000, dtype=np.uint32) << 16) | 0x8000
+    u = np.concatenate([u, ties, ties + 1, ties - 1])
+    x = u.view(np.float32).astype(np.float64)
+    hi = np.searchsorted(vals, x, side="left")
+    lo = np.maximum(hi - 1, 0)
+    dlo, dhi = x - vals[lo], vals[hi] - x
+    pick = np.where((dhi < dlo) | ((dhi == dlo) & (codes[hi] % 2 == 0)), hi, lo)
+    pick = np.where(vals[hi] == x, hi, pick)
+    ref = codes[pick]
+    sgn = rng.integers(0, 2, size=u.size).astype(np.uint32)
+    got = quant.bf16_round((u | (sgn << 31)).view(np.float32)).view(np.uint32)
+    np.testing.assert_array_equal(got >> 16, ref | (sgn << 15))
+
+
+def test_splitmix64_published_reference_outputs():
+    """The first outputs of the published splitmix64.c generator seeded with
+    0 (the reference sequence of the generator's public test vectors)."""
+    ref = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F,
+           0xF88BB8A8724C81EC, 0x1B39896A51A8749B]
+    assert [int(v) for v in sketch.splitmix64(0, np.arange(5, dtype=np.uint64))] == ref
+
+
+# ------------------------------------------------------ statistical dimension
+def test_statistical_dimension_definition_and_limits():
+    """s_lambda(Z) = tr((Z^T Z + lambda I)^-1 Z^T Z) (Lemma sketching): equal
+    to a linear solve, to rank(Z) as lambda -> 0, to d / (1 + lambda) for
+    orthonormal columns, and decreasing in lambda."""
+    rng = np.random.default_rng(40)
+    Z = rng.standard_normal((50, 6)) * np.array([5, 2, 1, .5, .1, .01])
+    G = Z.T @ Z
+    for lam in [1e-3, 0.3, 7.0, 400.0]:
+        ref = np.trace(np.linalg.solve(G + lam * np.eye(6), G))
+        assert abs(direct.statistical_dimension(Z, lam) - ref) < 1e-12 * 6
+    Q, _ = np.linalg.qr(rng.standard_normal((30, 5)))
+    assert abs(direct.statistical_dimension(Q, 0.25) - 5 / 1.25) < 1e-12
+    Zr = rng.standard_normal((40, 3)) @ rng.standard_normal((3, 7))      # rank 3
+    assert abs(direct.statistical_dimension(Zr, 1e-6) - 3.0) < 1e-5
+    vals = [direct.statistical_dimension(Z, lam) for lam in [0.01, 0.1, 1, 10]]
+    assert np.all(np.diff(vals) < 0)
+
+
+# ------------------------------------------------------------ Hessians
+def _dense_cca_hessian(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu):
+    bu = stiefel.tangent_basis(U, Sxx, Mxx)
+    bv = stiefel.tangent_basis(V, Syy, Myy)
+    basis = [(b, np.zeros_like(V)) for b in bu] + [(np.zeros_like(U), b) for b in bv]
+    m = len(basis)
+    H = np.zeros((m, m))
+    for a in range(m):
+        hu, hv = stiefel.cca_rhess(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu, *basis[a])
+        for b in range(m):
+            H[b, a] = stiefel.inner(basis[b][0], hu, Mxx) + stiefel.inner(basis[b][1], hv, Myy)
+    return H
+
+
+@pytest.mark.parametrize("dx,dy,p", [(5, 4, 2), (4, 6, 3), (5, 5, 1)])
+def test_cca_hessian_spectrum_at_optimum(dx, dy, p):
+    """With M = Sigma the Riemannian Hessian (Eq. HessCCA) at the optimum has
+    exactly the spectrum of the proof of Theorem CCAHessiantheorem, and its
+    condition number is kappa*_CCA."""
+    X, Y = synth.cca_latent(90, dx, dy, r=3, noise=0.3, x_decades=1.0, seed=41 + dx + dy)
+    lam = 0.05
+    Sxx, Syy, Sxy = stiefel.cca_blocks(X, Y, lam, lam)
+    mu = np.arange(p, 0, -1, dtype=float) * 1.5
+    sig, U, V = direct.cca_direct(X, Y, lam, lam, k=p)
+    H = _dense_cca_hessian(U, V, Sxx, Syy, Sxy, Sxx, Syy, mu)
+    assert H.shape[0] == p * (dx + dy) - p * (p + 1)
+    np.testing.assert_allclose(H, H.T, atol=1e-12 * np.abs(H).max())
+    ev = np.sort(np.linalg.eigvalsh(0.5 * (H + H.T)))
+    cf = direct.cca_hessian_spectrum(sig, mu, dx, dy)
+    np.testing.assert_allclose(ev, cf, rtol=1e-9, atol=1e-12)
+    assert ev[0] > 0
+    assert abs(ev[-1] / ev[0] - direct.kappa_star_cca(sig, mu)) < 1e-8 * ev[-1] / ev[0]
+
+
+def test_cca_hessian_condition_bound_with_sketched_metric():
+    """Theorem CCAHessiantheorem: kappa(Hess) <= kappa*_CCA kappa(Sigma, M)
+    for another SPD metric M (here the sketched one)."""
+    X, Y = synth.cca_latent(400, 5, 4, r=3, noise=0.3, x_decades=2.0, seed=44)
+    lam = 0.05
+    Sxx, Syy, Sxy = stiefel.cca_blocks(X, Y, lam, lam)
+    mu = np.array([2.0, 1.0])
+    sig, U, V = direct.cca_direct(X, Y, lam, lam, k=2)
+    SX = sketch.sketch(X, "countsketch", 60, 45)
+    SY = sketch.sketch(Y, "countsketch", 60, 45)
+    Mxx = SX.T @ SX + lam * np.eye(5)
+    Myy = SY.T @ SY + lam * np.eye(4)
+    H = _dense_cca_hessian(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu)
+    ev = np.linalg.eigvalsh(0.5 * (H + H.T))
+    gx = sla.eigh(Sxx, Mxx, eigvals_only=True)
+    gy = sla.eigh(Syy, Myy, eigvals_only=True)
+    kap_m = max(gx.max(), gy.max()) / min(gx.min(), gy.min())
+    assert ev.min() > 0
+    assert ev.max() / ev.min() <= direct.kappa_star_cca(sig, mu) * kap_m * (1 + 1e-9)
+
+
+def test_lda_hessian_spectrum_at_optimum():
+    """With M = S_w + lam I the Riemannian Hessian (Eq. LDAhess) at the
+    optimum has the spectrum of the proof of Theorem LDAHessiantheorem and
+    condition number kappa*_FDA."""
+    X, y = synth.lda_classes(152, 6, 4, decades=1.0, seed=46)
+    lam = 0.2
+    mu = np.array([3.0, 2.0, 1.0])
+    rho, W = direct.lda_direct(X, y, 4, lam, k=3)
+    _, _, _, Xh, Yh = direct.lda_scatter(X, y, 4)
+    B = Xh.T @ Xh + lam * np.eye(6)
+    SB = Yh.T @ Yh
+    bas = stiefel.tangent_basis(W, B, B)
+    m = len(bas)
+    assert m == 3 * 6 - 6
+    H = np.zeros((m, m))
+    for a in range(m):
+        h = stiefel.lda_rhess(W, B, SB, B, mu, bas[a])
+        for b in range(m):
+            H[b, a] = stiefel.inner(bas[b], h, B)
+    np.testing.assert_allclose(H, H.T, atol=1e-12 * np.abs(H).max())
+    ev = np.sort(np.linalg.eigvalsh(0.5 * (H + H.T)))
+    rho_all = np.concatenate([rho, np.zeros(6 - len(rho))])    # rank S_B <= c - 1
+    np.testing.assert_allclose(ev, direct.lda_hessian_spectrum(rho_all, mu), rtol=1e-9,
+                               atol=1e-12 * rho[0])
+    assert abs(ev[-1] / ev[0] - direct.kappa_star_fda(rho_all, mu)) < 1e-8 * ev[-1] / ev[0]
+
+
+def _fd_hessian(grad_field, X, xi, h=1e-5):
+    """Central difference of the extended gradient field Y -> grad(Y) along xi
+    (projected on T_X by the caller): the Levi-Civita derivative on a
+    Riemannian submanifold of the constant-metric ambient space."""
+    return (grad_field(X + h * xi) - grad_field(X - h * xi)) / (2 * h)
+
+
+def test_cca_hessian_matches_differentiated_gradient_field():
+    """Away from critical points, with a non-trivial metric: Hess f[xi] =
+    Pi_Z(D grad f[xi]) for the extension of the gradient formula off the
+    manifold, and the Hessian is self-adjoint in the metric."""
+    X, Y = synth.cca_latent(90, 5, 4, r=3, noise=0.3, x_decades=1.0, seed=47)
+    lam = 0.1
+    Sxx, Syy, Sxy = stiefel.cca_blocks(X, Y, lam, lam)
+    rng = np.random.default_rng(48)
+    Mxx, Myy = _spd(5, rng, 5) * 40, _spd(4, rng, 5) * 40
+    mu = np.array([3.0, 2.0])
+    U = _point(5, 2, Sxx, rng)
+    V = _point(4, 2, Syy, rng)
+    xu = stiefel.project(U, Sxx, Mxx, rng.standard_normal((5, 2)))
+    xv = stiefel.project(V, Syy, Myy, rng.standard_normal((4, 2)))
+    hu, hv = stiefel.cca_rhess(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu, xu, xv)
+    h = 1e-5
+    gp = stiefel.cca_rgrad(U + h * xu, V + h * xv, Sxx, Syy, Sxy, Mxx, Myy, mu)
+    gm = stiefel.cca_rgrad(U - h * xu, V - h * xv, Sxx, Syy, Sxy, Mxx, Myy, mu)
+    fu = stiefel.project(U, Sxx, Mxx, (gp[0] - gm[0]) / (2 * h))
+    fv = stiefel.project(V, Syy, Myy, (gp[1] - gm[1]) / (2 * h))
+    scale = np.linalg.norm(hu) + np.linalg.norm(hv)
+    assert np.linalg.norm(fu - hu) + np.linalg.norm(fv - hv) < 1e-7 * scale
+    eu = stiefel.project(U, Sxx, Mxx, rng.standard_normal((5, 2)))
+    ev = stiefel.project(V, Syy, Myy, rng.standard_normal((4, 2)))
+    ku, kv = stiefel.cca_rhess(U, V, Sxx, Syy, Sxy, Mxx, Myy, mu, eu, ev)
+    a = stiefel.inner(eu, hu, Mxx) + stiefel.inner(ev, hv, Myy)
+    b = stiefel.inner(xu, ku, Mxx) + stiefel.inner(xv, kv, Myy)
+    assert abs(a - b) < 1e-10 * max(1.0, abs(a))
+
+
+def test_lda_hessian_matches_differentiated_gradient_field():
+    X, y = synth.lda_classes(100, 6, 4, decades=1.0, seed=49)
+    _, _, _, Xh, Yh = direct.lda_scatter(X, y, 4)
+    lam = 0.5
+    B = Xh.T @ Xh + lam * np.eye(6)
+    SB = Yh.T @ Yh
+    rng = np.random.default_rng(50)
+    M = _spd(6, rng, 8) * 30
+    mu = np.array([3.0, 2.0, 1.0])
+    W = _point(6, 3, B, rng)
+    xi = stiefel.project(W, B, M, rng.standard_normal((6, 3)))
+    hx = stiefel.lda_rhess(W, B, SB, M, mu, xi)
+    fd = stiefel.project(W, B, M, _fd_hessian(lambda Z: stiefel.lda_rgrad(Z, B, SB, M, mu), W, xi))
+    assert np.linalg.norm(fd - hx) < 1e-7 * np.linalg.norm(hx)
+    eta = stiefel.project(W, B, M, rng.standard_normal((6, 3)))
+    he = stiefel.lda_rhess(W, B, SB, M, mu, eta)
+    assert abs(stiefel.inner(eta, hx, M) - stiefel.inner(xi, he, M)) < 1e-10 * np.linalg.norm(hx) ** 2
+
+
+# ------------------------------------------------------- metrics: negatives
+def test_constraint_residual_flags_a_scaled_point():
+    """U scaled by (1 + eps) has U^T Sxx U = (1 + eps)^2 I: residual 2 eps + eps^2."""
+    X, Y = _rand_cca(seed=51)
+    lam = 0.05
+    _, U, V = direct.cca_direct(X, Y, lam, lam, k=3)
+    for eps in [1e-7, 1e-4, 0.1]:
+        r = metrics.constraint_residual((1 + eps) * U, X, lam)
+        assert abs(r - (2 * eps + eps * eps)) < 1e-12 + 1e-9 * eps
+
+
+def test_objective_error_of_a_rotated_point_is_closed_form():
+    """Rotating the last column of the optimum towards the next canonical
+    pair by theta (u_k -> cos u_k + sin u_{k+1}, same for v) keeps the
+    constraints and, since u_i^T Sxy v_j = sigma_i delta_ij, lowers the
+    objective by sin^2 theta (sigma_k - sigma_{k+1}): the metric must report
+    exactly that."""
+    X, Y = _rand_cca(n=120, dx=6, dy=5, seed=52)
+    lam = 0.05
+    sig, U, V = direct.cca_direct(X, Y, lam, lam, k=3)
+    for th in [1e-3, 0.1, 0.7]:
+        U2, V2 = U[:, :2].copy(), V[:, :2].copy()
+        U2[:, 1] = np.cos(th) * U[:, 1] + np.sin(th) * U[:, 2]
+        V2[:, 1] = np.cos(th) * V[:, 1] + np.sin(th) * V[:, 2]
+        err = metrics.cca_rel_objective_error(U2, V2, X, Y, lam, lam, sig)
+        # tr(U2^T Sxy V2) = sigma_1 + cos^2 sigma_2 + sin^2 sigma_3
+        expect = (sig[1] - (np.cos(th) ** 2 * sig[1] + np.sin(th) ** 2 * sig[2])) / (sig[0] + sig[1])
+        assert abs(err - expect) < 1e-12 + 1e-9 * expect
+        assert metrics.constraint_residual(U2, X, lam) < 1e-10
+
+
+def test_objective_error_of_random_feasible_points_is_positive():
+    """Any feasible point scores at most sum sigma_i (von Neumann / Ky Fan):
+    random qf points score strictly below it, and their weighted
+    sub-optimality is positive."""
+    X, Y = _rand_cca(n=100, dx=6, dy=5, seed=53)
+    lam = 0.05
+    sig, _, _ = direct.cca_direct(X, Y, lam, lam, k=2)
+    Sxx, Syy, Sxy = stiefel.cca_blocks(X, Y, lam, lam)
+    rng = np.random.default_rng(54)
+    mu = np.array([2.0, 1.0])
+    for _ in range(20):
+        U = stiefel.qf_B(rng.standard_normal((6, 2)), Sxx)
+        V = stiefel.qf_B(rng.standard_normal((5, 2)), Syy)
+        assert metrics.cca_objective(U, V, X, Y, lam, lam) < sig[0] + sig[1]
+        assert metrics.cca_rel_objective_error(U, V, X, Y, lam, lam, sig) > 1e-6
+        assert metrics.weighted_suboptimality(sig, stiefel.cca_cost(U, V, Sxy, mu), mu) > 1e-6
+
+
+def test_lda_objective_error_of_a_rotated_point_is_closed_form():
+    X, y = synth.lda_classes(150, 6, 5, decades=1.0, seed=55)
+    lam = 0.2
+    rho, W = direct.lda_direct(X, y, 5, lam, k=3)
+    _, _, _, Xh, Yh = direct.lda_scatter(X, y, 5)
+    th = 0.3
+    W2 = W[:, :2].copy()
+    W2[:, 1] = np.cos(th) * W[:, 1] + np.sin(th) * W[:, 2]
+    err = metrics.lda_rel_objective_error(W2, Xh, Yh, lam, rho)
+    expect = (rho[1] - (np.cos(th) ** 2 * rho[1] + np.sin(th) ** 2 * rho[2])) / (rho[0] + rho[1])
+    assert abs(err - expect) < 1e-12 + 1e-9 * expect
+
+
+def test_principal_angles_of_a_plane_rotation():
+    th = 0.37
+    A = np.array([[1.0], [0.0], [0.0]])
+    B = np.array([[np.cos(th)], [np.sin(th)], [0.0]])
+    assert abs(metrics.principal_angles(A, B)[0] - th) < 1e-14
+    S = np.diag([4.0, 1.0, 1.0])     # S-inner product of e_1 and (1, 2, 0)
+    a = metrics.principal_angles(A, np.array([[1.0], [2.0], [0.0]]), S)[0]
+    assert abs(np.cos(a) - 4.0 / (2.0 * np.sqrt(8.0))) < 1e-14   # <A,B>_S / (|A|_S |B|_S)
