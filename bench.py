@@ -49,7 +49,9 @@ def parse():
     ap.add_argument("--weights", choices=["equal", "descending"], default="equal",
                     help="N = I (unweighted trace, ordered by the closing Rayleigh-Ritz step; it optimises the "
                          "reported objective sum sigma_i) or N = diag(k, ..., 1)")
-    ap.add_argument("--warm", type=int, default=None, help="warm-start iterations on the sketched problem")
+    ap.add_argument("--warm", type=int, default=None,
+                    help="block subspace iterations of the exact sketched solve that gives the start point "
+                         "(CCA; FDA's is one eigensolve); 0 = Gaussian start")
     ap.add_argument("--final-f64", type=int, default=None,
                     help="FP64 closing iterations after the FP32 iteration (< 0: FP64 finishing pass only); "
                          "default: -1 for FDA, 0 for CCA")
@@ -130,7 +132,7 @@ def serve(args):
     data_bytes = sum(X.numel() * 4 + Y.numel() * 4 for X, Y in data)
     stage = {"none": srp.SRP_STAGE_NONE, "bf16": srp.SRP_STAGE_BF16, "bf16fp8": srp.SRP_STAGE_BF16_FP8}[args.stage]
     tol = args.tol if args.tol is not None else 1e-5
-    warm = args.warm if args.warm is not None else 40
+    warm = args.warm if args.warm is not None else 48
 
     def opt():
         return srp.srp_default_options(sketch=srp.SRP_COUNTSKETCH, max_iter=args.max_iter,
@@ -289,11 +291,9 @@ def main():
     # margin on these spectra (top-k correlations 3e-4 to 5e-3 apart)
     tol = args.tol if args.tol is not None else (1e-9 if wl.dtype == "f64" else 1e-4)
     mu = [1.0] * wl.k if args.weights == "equal" else None
-    # warm-start iterations (RCG on the sketched problem, the sketch-and-solve
-    # start point) that minimise the solve time, measured: for the CCA
-    # workload 110-130 give 32-36 full iterations (100: 44, 150: 33), so 120;
-    # for FDA 10 to 100 all give 19 full iterations (none: 21), so 10
-    warm = args.warm if args.warm is not None else (10 if wl.problem == "lda" else 120)
+    # start point: the exact solution of the sketched problem (block subspace
+    # iterations with Rayleigh-Ritz for CCA, one eigensolve for FDA)
+    warm = args.warm if args.warm is not None else 48
     extra = {"warm_start_iters": warm}
     if args.final_f64 is not None:
         extra["final_f64"] = args.final_f64

@@ -63,10 +63,16 @@ typedef struct srp_options {
   int sketch;             /* SRP_COUNTSKETCH or SRP_SRHT                      */
   uint64_t seed;          /* seed of the sketch randomness (SplitMix64)       */
   int max_iter;           /* Riemannian CG iteration cap (default 1000)       */
-  int warm_start_iters;   /* RCG iterations on the sketched problem that give
-                             the start point (exact-cca / exact-fda of the
-                             sketch, Algorithms CCAopt / LDAopt); 0 = start
-                             from qf of a seeded Gaussian point              */
+  int warm_start_iters;   /* > 0: start from the exact solution of the
+                             sketched problem (exact-cca(SX, SY) /
+                             exact-fda(SX), Algorithms CCAopt / LDAopt).
+                             CCA: this many block subspace iterations on
+                             C^T C (block of min(64, dx, dy) columns,
+                             rounded up to a multiple of 4: each product
+                             applies (C^T C)^4), then a Rayleigh-Ritz step;
+                             one when the block spans min(dx, dy) columns.
+                             FDA: one c x c eigensolve, exact.  Default 48.
+                             0 = start from qf of a seeded Gaussian point    */
   int refresh_every;      /* recompute the data products B*U from the data
                              every this many iterations (default 25)         */
   int check_every;        /* host reads the convergence flag every this many
@@ -111,7 +117,8 @@ typedef struct srp_options {
 typedef struct srp_info {
   int status;             /* same as the return value                        */
   int iterations;         /* Riemannian CG iterations on the full data       */
-  int warm_iterations;    /* iterations spent on the sketched problem        */
+  int warm_iterations;    /* subspace iterations of the warm start (FDA: 1);
+                             0 when it fell back to the Gaussian start        */
   int passes;             /* data passes over the full n rows                */
   double f;               /* final weighted cost f(Z) = -sum mu_i sigma_i    */
   double objective;       /* sum of the returned sigma (or rho)              */

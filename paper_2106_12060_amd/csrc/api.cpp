@@ -37,7 +37,7 @@ int srp_default_options(srp_options* o) {
   o->sketch = SRP_COUNTSKETCH;
   o->seed = 12060;
   o->max_iter = 1000;
-  o->warm_start_iters = 40;
+  o->warm_start_iters = 48;
   o->refresh_every = 25;
   o->check_every = 2;
   o->pass_compute = -1;

@@ -2,8 +2,9 @@
 //
 //   sketch (CountSketch / SRHT, one S for X and Y)
 //   -> M_b = (S A_b)^T (S A_b) + lam_b I, R_b, M_b^-1 = R_b^-1 R_b^-T (FP64)
-//   -> warm start: Riemannian CG on the sketched problem (exact-cca /
-//      exact-fda of the sketch; its exact metric is M itself)
+//   -> warm start: the exact solution of the sketched problem (exact-cca /
+//      exact-fda of the sketch): block subspace iteration with Rayleigh-Ritz
+//      (CCA), one small eigensolve (FDA)
 //   -> qf_B of the warm start, then Riemannian CG on the full data with the
 //      metric M (one fused data pass per iteration)
 //   -> FP64 retraction, Rayleigh-Ritz rotation of the k x k block, sign
@@ -179,10 +180,6 @@ struct RcgProblem {
   const double* Minv[2] = {nullptr, nullptr};
   const double* Yhat = nullptr;  // FDA: c x d rows sqrt(n_j)(m_j - m); S_B = Yhat^T Yhat
   int c = 0;
-  // Optional FP64 Gram blocks H[b][c] = A_b^T A_c (d_b x d_c, row-major):
-  // when set, the data products come from them instead of a pass over A
-  // (the sketched problem, whose Grams cost no more to read than its rows).
-  const double* H[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 };
 
 struct RcgBuffers {
@@ -222,11 +219,8 @@ static int twopass_ksplit(int64_t n) {
 }
 
 static size_t skinny_bytes(int nb, int k, const int* d, int c) {
-  size_t b = 0, g = 0;
+  size_t b = 0;
   for (int s = 0; s < nb; ++s) b += skinny_ws_bytes(d[s], d[s], 2 * k) + 256;
-  for (int s = 0; s < nb; ++s)   // the Gram route's nb x nb products
-    for (int t = 0; t < nb; ++t) g += skinny_ws_bytes(d[s], d[t], k);
-  b = std::max(b, g);
   if (c > 0) b = std::max({b, skinny_ws_bytes(c, d[0], k), skinny_ws_bytes(d[0], c, k)});
   return b;
 }
@@ -372,24 +366,10 @@ static int twopass_f64(const RcgProblem& P, RcgBuffers& B, double* const* W, hip
   return SRP_OK;
 }
 
-// J_b = [H_b0 W_0 | H_b1 W_1] from the Gram blocks: the same products as
-// A_b^T [A_0 W_0 | A_1 W_1], in FP64.
-static int gram_products(const RcgProblem& P, RcgBuffers& B, double* const* W, hipStream_t st) {
-  const int k = P.k, nb = P.nb;
-  SkinnyProb pr[4];
-  int np = 0;
-  for (int b = 0; b < nb; ++b)
-    for (int c = 0; c < nb; ++c)
-      pr[np++] = SkinnyProb{P.d[b], P.d[c], k, P.H[b][c], P.d[c], false, W[c], k, B.J[b] + c * k, nb * k};
-  return gemm_skinny_batch(np, pr, B.skw, B.skw_bytes, st);
-}
-
 // Data products along directions W (d_b x k): fills J (and FDA's S_B W).
 static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int compute, const int* done,
                      hipStream_t st) {
-  if (P.H[0][0]) {
-    SRP_TRY(gram_products(P, B, W, st));
-  } else if (compute == SRP_F64 && !pass_limits_ok(P.dtype, SRP_F64, P.d[0], P.d[1], P.k, P.nb)) {
+  if (compute == SRP_F64 && !pass_limits_ok(P.dtype, SRP_F64, P.d[0], P.d[1], P.k, P.nb)) {
     SRP_TRY(twopass_f64(P, B, W, st));
   } else {
     Arena pw{B.pass_ws, B.pass_ws_bytes, 0};
@@ -593,26 +573,185 @@ static size_t sketch_ws(int kind, int64_t n, int d, int s, int dtype) {
   return kind == SRP_SRHT ? srht_ws_bytes(n, d, s, dtype) : countsketch_ws_bytes(n, s);
 }
 
-// Shared tail of both solvers once the data, sketches and metric exist.
-static int solve_tail(RcgProblem& full, RcgProblem& sk, RcgBuffers& B, const CommonArgs& ca, double* const* outW,
-                      double* sigma_out, srp_info* info, PhaseTimer& tm, hipStream_t st) {
-  const int k = full.k, nb = full.nb;
-  // start point for the sketched problem: qf of a seeded Gaussian matrix
-  double* start[2] = {B.Z[0], nb == 2 ? B.Z[1] : nullptr};
-  for (int s = 0; s < nb; ++s)
-    SRP_TRY(launch_gauss_fill(start[s], (int64_t)full.d[s] * k, ca.opt.seed ^ (0x5741524D53544152ull + s), st));
-  int warm_iters = 0;
-  if (ca.opt.warm_start_iters > 0) {
-    RcgResult wr;
-    // The warm start runs on the sketch; B.U then holds exact-cca(S X, S Y).
-    // Its start lives in Z, which rcg_run overwrites only after the copy.
-    SRP_TRY(rcg_run(sk, B, start, ca.opt.warm_start_iters, 1e-9, ca.opt.warm_start_iters + 1, 0, false, false,
-                    nullptr, wr, st));
-    warm_iters = wr.iterations;
-    for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
-    start[0] = outW[0];
-    start[1] = nb == 2 ? outW[1] : nullptr;
+// ------------------------------------------------------- warm start
+// The exact solution of the sketched problem: Algorithms CCAopt and LDAopt
+// start from exact-cca(SX, SY) / exact-fda(SX) (sketch-and-solve), then
+// qf_B of it.  M_b = (S A_b)^T (S A_b) + lam_b I and M_b^-1 are at hand.
+struct WarmStart {
+  int kind = 0;                  // 0: none (Gaussian start), 1: CCA, 2: FDA
+  int iters = 0;                 // CCA: block subspace iterations
+  const double* Hxy = nullptr;   // CCA: (S X)^T (S Y), dx x dy
+  const double* Rinv[2] = {nullptr, nullptr};   // CCA: R_x^-1, R_y^-1 (upper)
+  const double* Yhat = nullptr;  // FDA: c x d between-class factor
+  int c = 0;
+  char* ws = nullptr;            // scratch (warm_ws_bytes)
+  size_t ws_bytes = 0;
+};
+
+// Block width of the CCA subspace iteration: 64 columns (the spectrum of the
+// sketched problem is flat past its leading correlations, so a wide block
+// converges in a few iterations), at most min(dx, dy).
+static int warm_block(int dx, int dy, int k) { return std::max(k, std::min(64, std::min(dx, dy))); }
+// Subspace iterations per product: the block is multiplied by (C^T C)^4.
+constexpr int kWarmPower = 4;
+
+static int warm_cca_iters(int dx, int dy, int k, int iters) {
+  if (warm_block(dx, dy, k) == std::min(dx, dy)) return 1;   // the block spans C^T C's range
+  return (std::max(1, iters) + kWarmPower - 1) / kWarmPower * kWarmPower;
+}
+
+// C = op(A)... : out (m x n) = A^T B for A kk x m, B kk x n (FP64), split
+// over the contraction into `parts` (the big-tile GEMM), summed in order.
+static int gemm_atb(int m, int n, int kk, const double* A, int64_t lda, const double* Bm, int64_t ldb, double* out,
+                    double* parts, size_t parts_bytes, hipStream_t st) {
+  const int64_t cnt = (int64_t)m * n;
+  int ks = gram_split(kk, m, n);
+  ks = (int)std::max<int64_t>(1, std::min<int64_t>(ks, (int64_t)(parts_bytes / bytes_of<double>((size_t)cnt))));
+  GemmArgs g{};
+  g.m = m; g.n = n; g.kk = kk; g.alpha = 1.0; g.beta = 0.0;
+  g.A = A; g.lda = lda; g.ta = true; g.a_f32 = false;
+  g.B = Bm; g.ldb = ldb; g.tb = false; g.b_f32 = false;
+  if (ks == 1) {
+    g.C = out; g.ldc = n;
+    return gemm_f64(g, st);
   }
+  g.C = parts; g.ldc = n; g.ksplit = ks; g.c_split_stride = cnt;
+  SRP_TRY(gemm_f64(g, st));
+  return sum_parts_f64(parts, ks, cnt, cnt, out, 0, 0.0, st);
+}
+
+static size_t warm_ws_bytes(int nb, int k, const int* d, int c) {
+  if (nb == 2) {
+    const int dx = d[0], dy = d[1], q = warm_block(dx, dy, k), dm = std::max(dx, dy);
+    const size_t dense = 3 * bytes_of<double>((size_t)dm * dm) + 2 * bytes_of<double>((size_t)dm * dm);  // E, B1, B2, parts
+    return dense + bytes_of<double>((size_t)(3 * dy + 2 * dx) * q + 64 * 64 + q * q + q * k + 64) +
+           bytes_of<int>(4) + skinny_ws_bytes(dm, dm, q) + 16 * 256;
+  }
+  const int dd = d[0];
+  return bytes_of<double>((size_t)2 * dd * c + c * c + c * k + 64) + bytes_of<int>(4) +
+         skinny_ws_bytes(std::max(dd, c), dd, c) + 8 * 256;
+}
+
+// CCA.  The sketched correlations are the singular values of
+// C = R_x^-T H_xy R_y^-1 (H_xy = (SX)^T (SY), R^T R = M), and the
+// sketched weights are U = R_x^-1 P_k, V = R_y^-1 W_k for the singular
+// pairs (P, W) of C.  The dense FP64 products are all of the A^T B form
+// of the big-tile GEMM:
+//   E = (R_x^-1)^T H_xy,  F = E^T E,  K^T = F^T R_y^-1,  S = (R_y^-1)^T K^T
+// so S = C^T C (symmetric, eigenvalues sigma^2), then S^2 and S^4 by
+// squaring.  Block subspace iteration W <- qf(S^4 W) (Cholesky-QR) then
+// advances four iterations per product.  Rayleigh-Ritz on the block: with
+// V = R_y^-1 W and P = E V = C W, the q x q matrix P^T P = W^T S W has
+// eigenvectors Q, and V Q_k, R_x^-1 P Q_k are the right and left weights
+// (up to positive column scales, which the qf start point removes).
+static int warm_cca(const RcgProblem& P, const WarmStart& w, double* const* out, int* flag, uint64_t seed,
+                    const double* Rix, const double* Riy, hipStream_t st) {
+  const int dx = P.d[0], dy = P.d[1], k = P.k, q = warm_block(dx, dy, k), dm = std::max(dx, dy);
+  const int ldq = cholqr_block(q);
+  Arena a{w.ws, w.ws_bytes, 0};
+  double* E = a.take<double>((size_t)dm * dm);
+  double* B1 = a.take<double>((size_t)dm * dm);
+  double* B2 = a.take<double>((size_t)dm * dm);
+  const size_t parts_bytes = 2 * bytes_of<double>((size_t)dm * dm);
+  double* parts = (double*)a.take<char>(parts_bytes);
+  double* W = a.take<double>((size_t)dy * q);
+  double* Wn = a.take<double>((size_t)dy * q);
+  double* V = a.take<double>((size_t)dy * q);
+  double* Pm = a.take<double>((size_t)dx * q);
+  double* PQ = a.take<double>((size_t)dx * q);
+  double* G = a.take<double>((size_t)q * q);
+  double* Bm = a.take<double>((size_t)64 * 64);
+  double* Q = a.take<double>((size_t)q * k);
+  double* ev = a.take<double>(64);
+  const size_t skb = skinny_ws_bytes(dm, dm, q);
+  double* skw = (double*)a.take<char>(skb);
+  if (!skw) { set_error("warm start: workspace too small"); return SRP_ENOMEM; }
+  auto mm = [&](int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* Bp, int64_t ldb,
+                double* C) { return gemm_skinny_f64(m, kk, nc, A, lda, ta, Bp, ldb, C, nc, skw, skb, st); };
+  // dense products
+  SRP_TRY(gemm_atb(dx, dy, dx, Rix, dx, w.Hxy, dy, E, parts, parts_bytes, st));    // R_x^-T H_xy
+  SRP_TRY(gemm_atb(dy, dy, dx, E, dy, E, dy, B1, parts, parts_bytes, st));         // F = E^T E
+  SRP_TRY(gemm_atb(dy, dy, dy, B1, dy, Riy, dy, B2, parts, parts_bytes, st));      // K^T = F R_y^-1
+  SRP_TRY(gemm_atb(dy, dy, dy, Riy, dy, B2, dy, B1, parts, parts_bytes, st));      // S = R_y^-T K^T
+  const int iters = warm_cca_iters(dx, dy, k, w.iters);
+  const double* Sp = B1;
+  if (iters >= kWarmPower) {
+    SRP_TRY(gemm_atb(dy, dy, dy, B1, dy, B1, dy, B2, parts, parts_bytes, st));     // S^2
+    SRP_TRY(gemm_atb(dy, dy, dy, B2, dy, B2, dy, B1, parts, parts_bytes, st));     // S^4
+  }
+  const int steps = iters >= kWarmPower ? iters / kWarmPower : iters;
+  // W = qf(G0) for a seeded Gaussian G0, then W <- qf(S^p W)
+  SRP_TRY(launch_gauss_fill(Wn, (int64_t)dy * q, seed ^ 0x5741524D53544152ull, st));
+  for (int it = 0; it <= steps; ++it) {
+    if (it > 0) SRP_TRY(mm(dy, dy, q, Sp, dy, false, W, q, Wn));
+    SRP_TRY(mm(q, dy, q, Wn, q, true, Wn, q, G));
+    SRP_TRY(launch_cholqr_factor(G, q, Bm, flag, st));
+    SRP_TRY(gemm_skinny_f64(dy, q, q, Wn, q, false, Bm, ldq, W, q, skw, skb, st));
+  }
+  // Rayleigh-Ritz on the block
+  SRP_TRY(mm(dy, dy, q, Riy, dy, false, W, q, V));       // V = R_y^-1 W
+  SRP_TRY(mm(dx, dy, q, E, dy, false, V, q, Pm));        // P = E V = C W
+  SRP_TRY(mm(q, dx, q, Pm, q, true, Pm, q, G));          // P^T P = W^T S W
+  SRP_TRY(launch_rr_eig(G, q, k, Q, ev, st));
+  SRP_TRY(gemm_skinny_f64(dx, q, k, Pm, q, false, Q, k, PQ, k, skw, skb, st));
+  SRP_TRY(gemm_skinny_f64(dx, dx, k, Rix, dx, false, PQ, k, out[0], k, skw, skb, st));
+  SRP_TRY(gemm_skinny_f64(dy, q, k, V, q, false, Q, k, out[1], k, skw, skb, st));
+  return SRP_OK;
+}
+
+// FDA.  The sketched problem S_B w = rho M w with S_B = Yhat^T Yhat has its
+// solutions in the range of M^-1 Yhat^T: w = M^-1 Yhat^T p with
+// (Yhat M^-1 Yhat^T) p = rho p, a c x c eigenproblem.
+static int warm_lda(const RcgProblem& P, const WarmStart& w, double* const* out, hipStream_t st) {
+  const int d = P.d[0], k = P.k, c = w.c;
+  Arena a{w.ws, w.ws_bytes, 0};
+  double* Yt = a.take<double>((size_t)d * c);
+  double* T = a.take<double>((size_t)d * c);
+  double* K = a.take<double>((size_t)c * c);
+  double* Q = a.take<double>((size_t)c * k);
+  double* ev = a.take<double>(64);
+  const size_t skb = skinny_ws_bytes(std::max(d, c), d, c);
+  double* skw = (double*)a.take<char>(skb);
+  if (!skw) { set_error("warm start: workspace too small"); return SRP_ENOMEM; }
+  SRP_TRY(transpose_f64(w.Yhat, c, d, Yt, st));
+  SRP_TRY(gemm_skinny_f64(d, d, c, P.Minv[0], d, false, Yt, c, T, c, skw, skb, st));   // M^-1 Yhat^T
+  SRP_TRY(gemm_skinny_f64(c, d, c, w.Yhat, d, false, T, c, K, c, skw, skb, st));        // Yhat M^-1 Yhat^T
+  SRP_TRY(launch_rr_eig(K, c, k, Q, ev, st));
+  SRP_TRY(gemm_skinny_f64(d, c, k, T, c, false, Q, k, out[0], k, skw, skb, st));
+  return SRP_OK;
+}
+
+// Shared tail of both solvers once the data, sketches and metric exist.
+static int solve_tail(RcgProblem& full, const WarmStart& warm, RcgBuffers& B, const CommonArgs& ca,
+                      double* const* outW, double* sigma_out, srp_info* info, PhaseTimer& tm, hipStream_t st) {
+  const int k = full.k, nb = full.nb;
+  // start point: the exact solution of the sketched problem, or (no warm
+  // start, or its block factor broke down) a seeded Gaussian matrix; the
+  // iteration begins at qf_B of it
+  double* start[2] = {outW[0], nb == 2 ? outW[1] : nullptr};
+  int warm_iters = 0;
+  bool gauss = warm.kind == 0;
+  if (!gauss) {
+    int* wflag = B.ran_all;   // not yet in use: cleared before the timed passes
+    SRP_TRY(fill_i32(wflag, 1, 0, st));
+    if (warm.kind == 1) {
+      SRP_TRY(warm_cca(full, warm, outW, wflag, ca.opt.seed, warm.Rinv[0], warm.Rinv[1], st));
+      warm_iters = warm_cca_iters(full.d[0], full.d[1], k, warm.iters);
+    } else {
+      SRP_TRY(warm_lda(full, warm, outW, st));
+      warm_iters = 1;
+    }
+    int hflag = 0;
+    SRP_HIP(hipMemcpyAsync(&hflag, wflag, sizeof(int), hipMemcpyDeviceToHost, st));
+    SRP_HIP(hipStreamSynchronize(st));
+    if (hflag) {   // a singular sketched block (e.g. zero cross-covariance): Gaussian start
+      gauss = true;
+      warm_iters = 0;
+    }
+  }
+  if (gauss)
+    for (int s = 0; s < nb; ++s)
+      SRP_TRY(launch_gauss_fill(start[s], (int64_t)full.d[s] * k, ca.opt.seed ^ (0x5741524D53544152ull + s), st));
   const double ms_warm = tm.lap_ms();
   if (ca.opt.time_passes) SRP_TRY(fill_i32(B.ran_all, 2, 0, st));
   // low-precision phase (CCA): BF16 data, BF16 matrix-core passes
@@ -747,9 +886,10 @@ static int setup_mu(const srp_options& o, int k, double* mu_dev, hipStream_t st)
 // Scratch of one CCA view's sketch and factor.  Both views get the larger
 // of the two needs: the factor's split-K partials do not grow monotonically
 // with d (fewer upper tiles take a deeper split).
-static size_t cca_view_scratch(int64_t n, int dx, int dy, int s, int dtype, int sketch_kind) {
+static size_t cca_view_scratch(int64_t n, int dx, int dy, int k, int s, int dtype, int sketch_kind) {
+  const int dd[2] = {dx, dy};
   return std::max({sketch_ws(sketch_kind, n, dx, s, dtype), sketch_ws(sketch_kind, n, dy, s, dtype),
-                   factor_ws_bytes(s, dx), factor_ws_bytes(s, dy)});
+                   factor_ws_bytes(s, dx), factor_ws_bytes(s, dy), warm_ws_bytes(2, k, dd, 0)});
 }
 
 size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sketch_kind, int skin_dtype) {
@@ -761,8 +901,8 @@ size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sket
   bytes += 2 * bytes_of<double>((size_t)dx * dx) + 2 * bytes_of<double>((size_t)dy * dy);  // R, Minv (x) ...
   bytes += 2 * bytes_of<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
   bytes += bytes_of<int>(4);
-  bytes += 4 * bytes_of<double>((size_t)std::max(dx, dy) * std::max(dx, dy));   // Gram blocks of the sketch
-  const size_t scratch = cca_view_scratch(n, dx, dy, s, dtype, sketch_kind);
+  bytes += bytes_of<double>((size_t)dx * dy);   // cross Gram of the sketches
+  const size_t scratch = cca_view_scratch(n, dx, dy, k, s, dtype, sketch_kind);
   bytes += rcg_buffers_bytes(2, k, std::max<int64_t>(n, s), dd, dtype);
   bytes += 2 * ((scratch + 255) & ~size_t(255)) + 4096;   // one scratch per view (the views run concurrently)
   return bytes;
@@ -775,10 +915,10 @@ size_t lda_ws_bytes(int64_t n, int d, int c, int k, int s, int dtype, int sketch
   size_t bytes = 0;
   bytes += (((size_t)n * d * esz + 255) & ~size_t(255));          // Xhat
   bytes += (((size_t)s * d * ssz + 255) & ~size_t(255));          // sketch
-  bytes += 4 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv, sketch Gram
+  bytes += 3 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv
   bytes += bytes_of<double>((size_t)c * d) + bytes_of<int>(c) + bytes_of<int>(4);
   const size_t scratch = std::max({sketch_ws(sketch_kind, n, d, s, dtype), factor_ws_bytes(s, d),
-                                   lda_center_ws_bytes(n, d, c)});
+                                   lda_center_ws_bytes(n, d, c), warm_ws_bytes(1, k, dd, c)});
   bytes += rcg_buffers_bytes(1, k, std::max<int64_t>(n, s), dd, dtype, c);
   bytes += scratch + 4096;
   return bytes;
@@ -849,7 +989,7 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   const size_t ssz = dtype_size(sk_dtype);
   const int dd[2] = {dx, dy};
   const size_t bytes = cca_ws_bytes(n, dx, dy, k, s, dtype, opt.sketch, skin_dtype);
-  const size_t scratch = cca_view_scratch(n, dx, dy, s, dtype, opt.sketch);
+  const size_t scratch = cca_view_scratch(n, dx, dy, k, s, dtype, opt.sketch);
   Workspace W;
   void* wbase = nullptr;
   SRP_TRY(take_workspace(W, bytes, ctx, st, &wbase));
@@ -863,14 +1003,11 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   double* Rinv = ar.take<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
   double* Rinv2 = ar.take<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
   int* flag = ar.take<int>(4);
-  // Gram blocks of the sketch [S X | S Y] for the warm start
-  double* Hxx = ar.take<double>((size_t)dx * dx);
+  // cross Gram (S X)^T (S Y) of the sketches, for the warm start
   double* Hxy = ar.take<double>((size_t)dx * dy);
-  double* Hyx = ar.take<double>((size_t)dy * dx);
-  double* Hyy = ar.take<double>((size_t)dy * dy);
-  const bool gram_warm = opt.warm_start_iters > 0;
+  const bool warm = opt.warm_start_iters > 0;
   RcgBuffers B{};
-  if (!flag || !Rinv2 || !Hyy || rcg_buffers_take(B, ar, 2, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
+  if (!flag || !Rinv2 || !Hxy || rcg_buffers_take(B, ar, 2, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
     set_error("workspace layout overflow");
     return SRP_ENOMEM;
   }
@@ -888,17 +1025,17 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SY, s, dy, opt.sketch_scale_y, fk.side));
   {
     Arena sub{sy.base, sy.cap, 0};
-    SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side, gram_warm ? Hyy : nullptr));
+    SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side));
   }
   SRP_TRY(sketch_any(opt.sketch, skin_x, skin_dtype, n, dx, s, opt.seed, SX, sx, st));
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SX, s, dx, opt.sketch_scale_x, st));
   const double ms_sketch = tm.lap_ms();   // X view's sketch (Y's runs alongside)
   {
     Arena sub{sx.base, sx.cap, 0};
-    SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st, gram_warm ? Hxx : nullptr));
+    SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st));
   }
   SRP_TRY(fk.end(st));
-  if (gram_warm) {   // cross Gram (S X)^T (S Y), split over the s rows in the X view's scratch
+  if (warm) {   // cross Gram (S X)^T (S Y), split over the s rows in the X view's scratch
     const int64_t cnt = (int64_t)dx * dy;
     int ks = gram_split(s, dx, dy);
     ks = (int)std::max<int64_t>(1, std::min<int64_t>(ks, (int64_t)(scr / bytes_of<double>((size_t)cnt))));
@@ -910,7 +1047,6 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
     g.C = parts; g.ldc = dy; g.ksplit = ks; g.c_split_stride = cnt;
     SRP_TRY(gemm_f64(g, st));
     SRP_TRY(sum_parts_f64(parts, ks, cnt, cnt, Hxy, 0, 0.0, st));
-    SRP_TRY(transpose_f64(Hxy, dx, dy, Hyx, st));
   }
   int hflag = 0;
   SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -926,12 +1062,10 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   full.nb = 2; full.k = k; full.lda_cost = 0; full.dtype = dtype; full.compute = compute;
   full.A[0] = X; full.A[1] = Y; full.n = n; full.d[0] = dx; full.d[1] = dy;
   full.lam[0] = lx; full.lam[1] = ly; full.Minv[0] = Mx; full.Minv[1] = My;
-  RcgProblem sk = full;
-  sk.dtype = sk_dtype; sk.compute = (sk_dtype == SRP_F64) ? SRP_F64 : compute;
-  sk.A[0] = SX; sk.A[1] = SY; sk.n = s;
-  if (gram_warm) {
-    sk.H[0][0] = Hxx; sk.H[0][1] = Hxy;
-    sk.H[1][0] = Hyx; sk.H[1][1] = Hyy;
+  WarmStart ws;
+  if (warm) {   // the X view's scratch is free once the cross Gram is summed
+    ws.kind = 1; ws.iters = opt.warm_start_iters; ws.Hxy = Hxy; ws.Rinv[0] = Rinv; ws.Rinv[1] = Rinv2;
+    ws.ws = sx.base; ws.ws_bytes = sx.cap;
   }
   CommonArgs ca{k, tol, opt};
   double* outW[2] = {U, V};
@@ -940,7 +1074,7 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
     info->ms_sketch = ms_sketch;
     info->ms_factor = ms_factor;
   }
-  int rc = solve_tail(full, sk, B, ca, outW, sigma, info, tm, st);
+  int rc = solve_tail(full, ws, B, ca, outW, sigma, info, tm, st);
   SRP_HIP(hipStreamSynchronize(st));
   if (info) {
     info->status = rc;
@@ -992,8 +1126,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   double* R = ar.take<double>((size_t)d * d);
   double* Rinv = ar.take<double>((size_t)d * d);
   double* Minv = ar.take<double>((size_t)d * d);
-  double* Hs = ar.take<double>((size_t)d * d);   // Gram of the sketch, for the warm start
-  const bool gram_warm = opt.warm_start_iters > 0;
+  const bool warm = opt.warm_start_iters > 0;
   double* Yhat = ar.take<double>((size_t)c * d);
   int* counts = ar.take<int>(c);
   int* flag = ar.take<int>(4);
@@ -1021,7 +1154,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   SRP_TRY(fill_i32(flag, 1, 0, st));
   {
     Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
-    SRP_TRY(sketch_factor_run(SXh, sk_dtype, s, d, lam, R, Rinv, Minv, flag, sub, st, gram_warm ? Hs : nullptr));
+    SRP_TRY(sketch_factor_run(SXh, sk_dtype, s, d, lam, R, Rinv, Minv, flag, sub, st));
   }
   int hflag = 0;
   SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1036,10 +1169,11 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   full.nb = 1; full.k = k; full.lda_cost = 1; full.dtype = dtype; full.compute = compute;
   full.A[0] = Xhat; full.n = n; full.d[0] = d; full.lam[0] = lam; full.Minv[0] = Minv; full.Yhat = Yhat;
   full.c = c;
-  RcgProblem sk = full;
-  sk.dtype = sk_dtype; sk.compute = (sk_dtype == SRP_F64) ? SRP_F64 : compute;
-  sk.A[0] = SXh; sk.n = s;
-  if (gram_warm) sk.H[0][0] = Hs;
+  WarmStart ws;
+  if (warm) {   // scratch past the solve's buffers (the sketch's and factor's, now free)
+    ws.kind = 2; ws.Yhat = Yhat; ws.c = c;
+    ws.ws = ar.base + ar.used; ws.ws_bytes = ar.cap - ar.used;
+  }
   CommonArgs ca{k, tol, opt};
   double* outW[2] = {Wout, nullptr};
   if (info) {
@@ -1047,7 +1181,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
     info->ms_sketch = ms_sketch;
     info->ms_factor = ms_factor;
   }
-  int rc = solve_tail(full, sk, B, ca, outW, rho, info, tm, st);
+  int rc = solve_tail(full, ws, B, ca, outW, rho, info, tm, st);
   SRP_HIP(hipStreamSynchronize(st));
   if (info) {
     info->status = rc;

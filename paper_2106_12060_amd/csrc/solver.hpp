@@ -74,6 +74,13 @@ int launch_gauss_fill(double* p, int64_t count, uint64_t seed, hipStream_t st);
 int launch_ctrl_init(SolverCtrl* c, double tol, int max_iter, hipStream_t st);
 int launch_set_fixed_step(SolverCtrl* c, int on, hipStream_t st);
 size_t partial_bytes(int k, int dmax);
+// Exact sketched solves (warm start): Cholesky-QR factor B = L^-T of a
+// q x q block Gram (q <= 64; *flag = 1 on breakdown), written with leading
+// dimension cholqr_block(q) (16, 32 or 64; B must hold its square), and the
+// Rayleigh-Ritz eigenvectors of a symmetric q x q block (top k, descending).
+int cholqr_block(int q);
+int launch_cholqr_factor(const double* G, int q, double* B, int* flag, hipStream_t st);
+int launch_rr_eig(const double* G, int q, int k, double* Q, double* ev, hipStream_t st);
 int partial_slices(int dmax);
 
 }  // namespace srp

@@ -1458,12 +1458,20 @@ __global__ void __launch_bounds__(64) k_ctrl_final(ProbView p, double* sigma_out
   double* JA = Tm + kk2;
   double* JV = JA + m * m;
   double* JT = JV + m * m;
+  // FDA with odd k pads one decoupled row and column whose diagonal lies
+  // below every eigenvalue (-(1 + ||Cw||_F)), so it sorts last; a finite
+  // value of the matrix's own scale keeps the sweeps' convergence test (off
+  // against the diagonal norm) meaningful.
+  double fro = 0.0;
+  for (int e = lane; e < kk2; e += 64) fro += Cw[e] * Cw[e];
+  for (int o = 32; o > 0; o >>= 1) fro += __shfl_xor(fro, o, 64);
+  const double pad = -(1.0 + sqrt(fro));
   for (int e = lane; e < m * m; e += 64) {
     const int i = sdiv(e, m), j = e - i * m;
     double v = 0.0;
     if (p.lda_cost) {
       if (i < k && j < k) v = 0.5 * (Cw[i * k + j] + Cw[j * k + i]);
-      else v = (i == j) ? -1e300 : 0.0;   // padding sorts last
+      else v = (i == j) ? pad : 0.0;
     } else {
       if (i < k && j >= k) v = Cw[i * k + (j - k)];
       else if (i >= k && j < k) v = Cw[j * k + (i - k)];
@@ -1592,6 +1600,204 @@ __global__ void __launch_bounds__(256) k_sign_fix(ProbView p) {
 
 int launch_sign_fix(const ProbView& p, hipStream_t st) {
   hipLaunchKernelGGL(k_sign_fix, dim3(p.k), dim3(256), 0, st, p);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// ------------------------------------------------ exact sketched solves
+// Small dense steps of the warm start (the exact CCA / FDA solution of the
+// sketched problem, Algorithms CCAopt and LDAopt): the Cholesky-QR factor of
+// a block Gram and the Rayleigh-Ritz eigensolve of a q x q block.
+
+// B = L^-T for L L^T = G + delta I (G q x q symmetric, only its lower
+// triangle read; q <= Q <= 64; delta = 1e-14 tr(G) / q keeps a numerically
+// singular block factorable, and the next iteration re-orthonormalises
+// anyway), written as a Q x Q row-major matrix (ld Q) whose rows and
+// columns past q are those of the identity.  W B then has orthonormal
+// columns in the inner product G was taken in.  *flag = 1 when the factor
+// breaks down (non-finite or non-positive pivot).  One wave, registers:
+// for the factor lane i keeps row i of the trailing matrix (the shift is
+// added to each pivot as it is used) and the pivot column goes through
+// LDS; for the inverse lane c builds column c of L^-1 by forward
+// substitution against L in LDS (uniform addresses: every read is a
+// broadcast).  The scheduling barrier per step keeps the compiler from
+// hoisting later steps' LDS reads, and the stores are unconditional: both
+// keep the wave within its registers.
+template <int Q>
+__global__ void __launch_bounds__(64) k_cholqr_factor(const double* __restrict__ G, int q, double* __restrict__ B,
+                                                      int* __restrict__ flag) {
+  __shared__ double Lm[Q * Q];
+  __shared__ double col[64];
+  const int i = threadIdx.x;
+  double tr = (i < q) ? G[i * q + i] : 0.0;
+  for (int o = 32; o > 0; o >>= 1) tr += __shfl_xor(tr, o, 64);
+  const double delta = 1e-14 * tr / q;
+  bool ok = true;
+  {
+    double a[Q];
+#pragma unroll
+    for (int c = 0; c < Q; ++c) a[c] = (i < q && c < q) ? G[i * q + c] : (c == i ? 1.0 : 0.0);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const double piv = __shfl(a[j], j, 64) + (j < q ? delta : 0.0);
+      ok = ok && piv > 0.0;
+      const double inv = 1.0 / sqrt(piv);
+      const double lij = (i == j) ? piv * inv : a[j] * inv;   // L[i][j] for i >= j
+      a[j] = lij;
+      col[i] = lij;
+      wave_sync();
+#pragma unroll
+      for (int c = j + 1; c < Q; ++c) a[c] -= lij * col[c];
+      wave_sync();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (i < Q) {
+#pragma unroll
+      for (int c = 0; c < Q; ++c) Lm[i * Q + c] = (c <= i) ? a[c] : 0.0;
+    }
+  }
+  wave_sync();
+  if (i < Q) {
+    // column i of L^-1: x[r] = (delta_ri - sum_{l < r} L[r][l] x[l]) / L[r][r]
+    double x[Q];
+#pragma unroll
+    for (int r = 0; r < Q; ++r) {
+      double sacc = (r == i) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = 0; l < r; ++l) sacc -= Lm[r * Q + l] * x[l];
+      x[r] = sacc / Lm[r * Q + r];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = 0; r < Q; ++r) B[i * Q + r] = x[r];    // B = L^-T: B[i][r] = (L^-1)[r][i]
+  }
+  if (i == 0 && !ok) *flag = 1;
+}
+
+int cholqr_block(int q) { return q <= 16 ? 16 : (q <= 32 ? 32 : 64); }
+
+int launch_cholqr_factor(const double* G, int q, double* B, int* flag, hipStream_t st) {
+  if (q < 1 || q > 64) {
+    set_error("cholqr: block of %d columns (1 to 64)", q);
+    return SRP_EINVAL;
+  }
+  switch (cholqr_block(q)) {
+    case 16: hipLaunchKernelGGL((k_cholqr_factor<16>), dim3(1), dim3(64), 0, st, G, q, B, flag); break;
+    case 32: hipLaunchKernelGGL((k_cholqr_factor<32>), dim3(1), dim3(64), 0, st, G, q, B, flag); break;
+    default: hipLaunchKernelGGL((k_cholqr_factor<64>), dim3(1), dim3(64), 0, st, G, q, B, flag); break;
+  }
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+// Rayleigh-Ritz: eigenvectors of the symmetric q x q G (q <= 64), ordered by
+// eigenvalue, descending; the first k go to Q (q x k, row-major) and their
+// eigenvalues to ev.  An odd q is padded with one decoupled row and column
+// whose diagonal -(1 + ||G||_F) lies below every eigenvalue.  One
+// workgroup, cyclic Jacobi in parallel rounds (the round-robin pairing of
+// the controllers' eigensolver): per round the pair threads compute the
+// rotations into LDS tables, then every thread rotates whole 2 x 2 blocks
+// (a row pair against a column pair) in place, and rows of V against
+// column pairs; two barriers per round, no scratch copy.  Sweeps stop at
+// off-diagonal norm <= 1e-13 of the diagonal norm.
+__global__ void __launch_bounds__(256) k_rr_eig(const double* __restrict__ G, int q, int k, double* __restrict__ Q,
+                                                double* __restrict__ ev) {
+  __shared__ double A[64 * 64];
+  __shared__ double V[64 * 64];
+  __shared__ double rc[32], rs[32];
+  __shared__ int rp[32], rq[32];
+  __shared__ double red[4][2];
+  __shared__ int order[64];
+  const int n = (q + 1) & ~1, P = n / 2, n1 = n - 1, tid = threadIdx.x;
+  double fro = 0.0;
+  for (int e = tid; e < q * q; e += 256) fro += G[e] * G[e];
+  for (int o = 32; o > 0; o >>= 1) fro += __shfl_xor(fro, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6][0] = fro;
+  __syncthreads();
+  const double pad = -(1.0 + sqrt(red[0][0] + red[1][0] + red[2][0] + red[3][0]));
+  for (int e = tid; e < n * n; e += 256) {
+    const int i = e / n, j = e - i * n;
+    A[i * 64 + j] = (i < q && j < q) ? 0.5 * (G[i * q + j] + G[j * q + i]) : (i == j ? pad : 0.0);
+    V[i * 64 + j] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    __syncthreads();
+    double off = 0.0, dia = 0.0;
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e / n, j = e - i * n;
+      const double x = A[i * 64 + j];
+      if (i == j) dia += x * x; else off += x * x;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
+    }
+    if ((tid & 63) == 0) { red[tid >> 6][0] = off; red[tid >> 6][1] = dia; }
+    __syncthreads();
+    const double so = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    const double sd = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+    if (so <= 1e-26 * (sd + 1e-300)) break;   // uniform
+    for (int round = 0; round < n1; ++round) {
+      if (tid < P) {
+        int pp = jac_index(tid, round, n1), qq = jac_index(n1 - tid, round, n1);
+        if (pp > qq) { const int t = pp; pp = qq; qq = t; }
+        const double apq = A[pp * 64 + qq];
+        double cth = 1.0, sth = 0.0;
+        if (apq != 0.0) cth = jac_rotation((A[qq * 64 + qq] - A[pp * 64 + pp]) / (2.0 * apq), &sth);
+        rc[tid] = cth; rs[tid] = sth; rp[tid] = pp; rq[tid] = qq;
+      }
+      __syncthreads();
+      // A <- J^T A J: new row p = c row_p - s row_q, new row q = s row_p + c row_q (likewise columns)
+      for (int e = tid; e < P * P; e += 256) {
+        const int m1 = e / P, m2 = e - m1 * P;
+        const int p1 = rp[m1], q1 = rq[m1], p2 = rp[m2], q2 = rq[m2];
+        const double c1 = rc[m1], s1 = rs[m1], c2 = rc[m2], s2 = rs[m2];
+        const double b00 = A[p1 * 64 + p2], b01 = A[p1 * 64 + q2], b10 = A[q1 * 64 + p2], b11 = A[q1 * 64 + q2];
+        const double t00 = c1 * b00 - s1 * b10, t01 = c1 * b01 - s1 * b11;
+        const double t10 = s1 * b00 + c1 * b10, t11 = s1 * b01 + c1 * b11;
+        double n01 = s2 * t00 + c2 * t01, n10 = c2 * t10 - s2 * t11;
+        if (m1 == m2) { n01 = 0.0; n10 = 0.0; }   // the rotated pair's coupling
+        A[p1 * 64 + p2] = c2 * t00 - s2 * t01;
+        A[p1 * 64 + q2] = n01;
+        A[q1 * 64 + p2] = n10;
+        A[q1 * 64 + q2] = s2 * t10 + c2 * t11;
+      }
+      // V <- V J
+      for (int e = tid; e < n * P; e += 256) {
+        const int r = e / P, m = e - r * P;
+        const int pp = rp[m], qq = rq[m];
+        const double cm = rc[m], sm = rs[m];
+        const double vp = V[r * 64 + pp], vq = V[r * 64 + qq];
+        V[r * 64 + pp] = cm * vp - sm * vq;
+        V[r * 64 + qq] = sm * vp + cm * vq;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (tid < n) {
+    const double vi = A[tid * 64 + tid];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double vj = A[j * 64 + j];
+      rank += (vj > vi) || (vj == vi && j < tid);
+    }
+    order[rank] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; e < q * k; e += 256) {
+    const int i = e / k, j = e - i * k;
+    Q[e] = V[i * 64 + order[j]];
+  }
+  if (tid < k) ev[tid] = A[order[tid] * 64 + order[tid]];
+}
+
+int launch_rr_eig(const double* G, int q, int k, double* Q, double* ev, hipStream_t st) {
+  if (q < 1 || q > 64 || k < 1 || k > q) {
+    set_error("rayleigh-ritz: block of %d columns, %d wanted (1 <= k <= q <= 64)", q, k);
+    return SRP_EINVAL;
+  }
+  hipLaunchKernelGGL(k_rr_eig, dim3(1), dim3(256), 0, st, G, q, k, Q, ev);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }

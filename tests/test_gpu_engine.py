@@ -40,7 +40,7 @@ def make(n, dx, dy, seed):
 
 
 def opts(srp, **kw):
-    base = dict(warm_start_iters=40, max_iter=1000)
+    base = dict(warm_start_iters=12, max_iter=1000)
     base.update(kw)
     return srp.srp_default_options(**base)
 

@@ -64,7 +64,7 @@ def test_cca_unequal_wide_views(dt, tol, bar):
     lam, k = 1e-3, 6
     sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
     U, V, sig, info = srp.cca_solve(dev(X), dev(Y), k, lam, lam, 1200, tol=tol, mu=[1.0] * k,
-                                    options=srp.srp_default_options(max_iter=3000, warm_start_iters=40))
+                                    options=srp.srp_default_options(max_iter=3000, warm_start_iters=12))
     err, cons = cca_errors(U, V, X, Y, lam, sig_true)
     print("unequal wide views", dt, info, err, cons)
     assert info["warm_iterations"] > 0
@@ -195,6 +195,9 @@ def test_lda_scaled_workload():
     print("lda", info, err, cons)
     assert err < 1e-6
     assert cons < 1e-6
+    # k = 19 is odd: the closing Rayleigh-Ritz eigensolve pads one row; the
+    # returned rho are the Ritz values, ordered
+    np.testing.assert_allclose(rho.cpu().numpy(), rho_true[:k], rtol=1e-5)
 
 
 @pytest.mark.parametrize("d", [1000, 1003])
@@ -412,3 +415,69 @@ def test_lda_rejects_too_many_classes():
     with pytest.raises(srp.SrpError) as e:
         srp.lda_solve(X, y, 65, 2, 0.1, 16)
     assert e.value.code == srp.SRP_EINVAL
+
+
+def _sin_max_angle(A, B):
+    """Sine of the largest principal angle between span(A) and span(B):
+    the norm of the part of B's orthonormal basis outside span(A) (accurate
+    for small angles, unlike sqrt(1 - cos^2))."""
+    Qa, _ = np.linalg.qr(A)
+    Qb, _ = np.linalg.qr(B)
+    return float(np.linalg.norm(Qb - Qa @ (Qa.T @ Qb), 2))
+
+
+@pytest.mark.parametrize("n,dx,dy,k,s,dt,sketch,iters,bar", [
+    # block = min(dx, dy) columns: one product spans C^T C's range, exact
+    (3000, 50, 40, 5, 200, "f64", "countsketch", 12, 1e-9),
+    # 64-column block inside dmin = 200; the sketched correlations past the
+    # block sit near 0.75 against 0.95 for the sixth, so the error falls
+    # about 0.6x per iteration: 40 iterations reach the floor set by the
+    # FP32 sketch (its rounding moves the sketched subspace by ~1e-6)
+    (20000, 300, 200, 6, 1200, "f32", "srht", 40, 1e-5)])
+def test_cca_warm_start_is_the_exact_sketched_solution(n, dx, dy, k, s, dt, sketch, iters, bar):
+    """Algorithm CCAopt starts from exact-cca(SX, SY).  With max_iter = 0
+    the solver returns that start point (after qf in the full metric and the
+    closing Rayleigh-Ritz rotation, which keep its span): its span must be
+    the span of the oracle's CCA of the sketched data, sketched with the
+    same seed."""
+    from oracle import sketch as osk
+    srp = _srp()
+    X, Y = synth.cca_latent(n, dx, dy, r=k, noise=0.5, factor_decades=0.5, seed=80 + dx,
+                            dtype=np.float64 if dt == "f64" else np.float32)
+    lam, seed = 1e-3, 17
+    opt = srp.srp_default_options(sketch=sketch, seed=seed, max_iter=0, warm_start_iters=iters)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), k, lam, lam, s, tol=1e-9, options=opt)
+    assert info["warm_iterations"] >= 1
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    SX = osk.sketch(X64, sketch, s, seed)
+    SY = osk.sketch(Y64, sketch, s, seed)
+    sig_s, Us, Vs = direct.cca_direct(SX, SY, lam, lam, k=k)
+    assert sig_s[k - 1] - sig_s[k] > 0.05          # the sketched top-k block is separated
+    su = _sin_max_angle(U.cpu().numpy(), Us)
+    sv = _sin_max_angle(V.cpu().numpy(), Vs)
+    print("warm start", info, su, sv)
+    assert su < bar and sv < bar
+
+
+def test_lda_warm_start_is_the_exact_sketched_solution():
+    """Algorithm LDAopt starts from exact-fda(SX): the leading generalized
+    eigenvectors of (S_B, M) with M the sketched within-class Gram plus
+    lambda I; k < c - 1 so the span is pinned by the eigengap, not by the
+    range of S_B alone."""
+    from oracle import sketch as osk
+    srp = _srp()
+    c, k, d, n, s = 10, 4, 120, 6000, 480
+    X, y = synth.lda_classes(n, d, c, decades=2.0, seed=90, dtype=np.float64)
+    lam, seed = 0.1, 5
+    opt = srp.srp_default_options(seed=seed, max_iter=0, warm_start_iters=1)
+    W, rho, info = srp.lda_solve(dev(X), dev(y), c, k, lam, s, tol=1e-9, options=opt)
+    _, _, _, Xh, Yh = direct.lda_scatter(X, y, c)
+    SXh = osk.sketch(Xh, "countsketch", s, seed)
+    M = SXh.T @ SXh + lam * np.eye(d)
+    import scipy.linalg as sla
+    ev, Vg = sla.eigh(Yh.T @ Yh, M)
+    ev, Vg = ev[::-1], Vg[:, ::-1]
+    assert (ev[k - 1] - ev[k]) > 0.02 * ev[0]
+    sw = _sin_max_angle(W.cpu().numpy(), Vg[:, :k])
+    print("lda warm start", info, sw)
+    assert sw < 1e-9
