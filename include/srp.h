@@ -178,6 +178,21 @@ int srp_countsketch(const void* A, int dtype, int64_t n, int d, int s,
                     uint64_t seed, void* out, void* stream);
 int srp_srht(const void* A, int dtype, int64_t n, int d, int s,
              uint64_t seed, void* out, void* stream);
+/* srp_countsketch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and the same output bits as
+ * srp_countsketch, with no allocation of any kind.  Its scratch is a
+ * library-owned device array of 44 MiB per GPU (held from the first launch
+ * on that GPU until the process ends), which limits it to
+ * n <= 4194304 rows and s <= 1048576 buckets (SRP_EINVAL beyond, before any
+ * device work).  Stream-ordered and asynchronous: it returns once the work
+ * is enqueued on `stream` (the output is ready when the stream reaches that
+ * point) and does not synchronise.  Every call on one GPU shares that GPU's
+ * array: calls on one stream run in order, but calls that overlap on one
+ * GPU (other streams, other host threads) race on the scratch and give
+ * undefined results.  Errors: as srp_countsketch, plus the limits above. */
+int srp_countsketch_noalloc(const void* A, int dtype, int64_t n, int d, int s,
+                            uint64_t seed, void* out, void* stream);
 /* The s sampled SRHT rows (int64, ascending) for n rows and `seed`. */
 int srp_srht_rows(int64_t n, int s, uint64_t seed, int64_t* rows,
                   void* stream);

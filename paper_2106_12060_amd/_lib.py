@@ -105,6 +105,8 @@ _SIGS = {
     "srp_engine_destroy": (ctypes.c_int, [_P]),
     "srp_countsketch": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_uint64, _P, _P]),
+    "srp_countsketch_noalloc": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_uint64, _P, _P]),
     "srp_srht": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_uint64, _P, _P]),
     "srp_srht_rows": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, _P, _P]),
@@ -193,6 +195,16 @@ def srp_countsketch(A: torch.Tensor, s: int, seed: int) -> torch.Tensor:
     out = _sketch_out(A, s)
     _check("srp_countsketch", lib().srp_countsketch(_ptr(A), _dtype(A), A.shape[0], A.shape[1], s,
                                                     seed, _ptr(out), _stream()))
+    return out
+
+
+def srp_countsketch_noalloc(A: torch.Tensor, s: int, seed: int, out: torch.Tensor) -> torch.Tensor:
+    """The allocation-free CountSketch: the caller passes the output (s x d,
+    float64 for float64 input, float32 otherwise); the call is enqueued on
+    torch's current stream and returns without synchronising."""
+    _need_cuda(A, out)
+    _check("srp_countsketch_noalloc", lib().srp_countsketch_noalloc(_ptr(A), _dtype(A), A.shape[0], A.shape[1], s,
+                                                                    seed, _ptr(out), _stream()))
     return out
 
 
