@@ -37,7 +37,7 @@ import numpy as np
 
 __all__ = [
     "column_scales", "cca_latent", "cca_latent_device", "lda_classes", "planted_cca",
-    "Workload", "workload", "serving_trace", "WORKLOADS",
+    "Workload", "workload", "serving_trace", "WORKLOADS", "sparse_signs",
 ]
 
 
@@ -131,6 +131,21 @@ def lda_classes(n: int, d: int, c: int, *, mean_std: float = 2.0,
     X = G @ Q.T
     X += means[labels]
     return np.ascontiguousarray(X, dtype=dtype), labels
+
+
+def sparse_signs(n: int, d: int, per_row: int, *, seed: int = 0, cols=None,
+                 dtype=np.float32) -> np.ndarray:
+    """n x d matrix with ``per_row`` entries of +-1 per row at random
+    columns (drawn from ``cols`` when given; a repeated column adds up), the
+    rest zero: small integers, so that every sum of products with small
+    integers is exact in FP32."""
+    rng = np.random.default_rng(seed)
+    cols = np.arange(d) if cols is None else np.asarray(cols)
+    idx = cols[rng.integers(0, len(cols), size=(n, per_row))]
+    vals = rng.choice(np.array([-1.0, 1.0]), size=(n, per_row))
+    X = np.zeros((n, d), dtype=np.float64)
+    np.add.at(X, (np.repeat(np.arange(n), per_row), idx.reshape(-1)), vals.reshape(-1))
+    return X.astype(dtype)
 
 
 def planted_cca(n: int, r: int, rho, *, seed: int = 0, dtype=np.float64):
