@@ -563,9 +563,12 @@ struct CommonArgs {
 };
 
 static int sketch_any(int kind, const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out,
-                      Arena& ar, hipStream_t st) {
+                      Arena& ar, hipStream_t st, const SrhtPlan* plan = nullptr) {
   Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
-  if (kind == SRP_SRHT) return srht_run(A, dtype, n, d, s, seed, out, sub, st);
+  if (kind == SRP_SRHT) {
+    if (plan) return srht_apply_run(*plan, A, dtype, d, out, sub, st);
+    return srht_run(A, dtype, n, d, s, seed, out, sub, st);
+  }
   return countsketch_run(A, dtype, n, d, s, seed, out, sub, st);
 }
 
@@ -902,6 +905,7 @@ size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sket
   bytes += 2 * bytes_of<double>((size_t)std::max(dx, dy) * std::max(dx, dy));
   bytes += bytes_of<int>(4);
   bytes += bytes_of<double>((size_t)dx * dy);   // cross Gram of the sketches
+  if (sketch_kind == SRP_SRHT) bytes += srht_plan_bytes(n, s) + 1024;   // shared sampled rows
   const size_t scratch = cca_view_scratch(n, dx, dy, k, s, dtype, sketch_kind);
   bytes += rcg_buffers_bytes(2, k, std::max<int64_t>(n, s), dd, dtype);
   bytes += 2 * ((scratch + 255) & ~size_t(255)) + 4096;   // one scratch per view (the views run concurrently)
@@ -1019,15 +1023,24 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   Arena sx{ar.base + ar.used, scr, 0};
   Arena sy{ar.base + ar.used + scr, scr, 0};
   if (ar.used + 2 * scr > ar.cap) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+  // SRHT: the sampled rows (one S for both views) once, before the fork
+  SrhtPlan plan;
+  const SrhtPlan* planp = nullptr;
+  if (opt.sketch == SRP_SRHT) {
+    Arena keep{ar.base + ar.used + 2 * scr, ar.cap - ar.used - 2 * scr, 0};
+    Arena tmp{sx.base, sx.cap, 0};
+    SRP_TRY(srht_plan_run(n, s, opt.seed, &plan, keep, tmp, st));
+    planp = &plan;
+  }
   SideFork fk;
   SRP_TRY(fk.begin(st, ctx));
-  SRP_TRY(sketch_any(opt.sketch, skin_y, skin_dtype, n, dy, s, opt.seed, SY, sy, fk.side));
+  SRP_TRY(sketch_any(opt.sketch, skin_y, skin_dtype, n, dy, s, opt.seed, SY, sy, fk.side, planp));
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SY, s, dy, opt.sketch_scale_y, fk.side));
   {
     Arena sub{sy.base, sy.cap, 0};
     SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side));
   }
-  SRP_TRY(sketch_any(opt.sketch, skin_x, skin_dtype, n, dx, s, opt.seed, SX, sx, st));
+  SRP_TRY(sketch_any(opt.sketch, skin_x, skin_dtype, n, dx, s, opt.seed, SX, sx, st, planp));
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SX, s, dx, opt.sketch_scale_x, st));
   const double ms_sketch = tm.lap_ms();   // X view's sketch (Y's runs alongside)
   {

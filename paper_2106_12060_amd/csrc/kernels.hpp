@@ -16,6 +16,20 @@ size_t srht_ws_bytes(int64_t n, int d, int s, int dtype);
 int srht_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, Arena& ws,
              hipStream_t st);
 int srht_rows_run(int64_t n, int s, uint64_t seed, int64_t* rows, Arena& ws, hipStream_t st);
+// The sampled rows of an SRHT and their grouping by low bits depend only on
+// (n, s, seed): a plan computes them once (its arrays from `keep`, the
+// selection's temporaries from `scratch`) and serves every matrix sketched
+// with that S (both CCA views).
+struct SrhtPlan {
+  int64_t n = 0;
+  int s = 0;
+  uint64_t seed = 0;
+  int64_t* rows = nullptr;
+  int *goff = nullptr, *galpha = nullptr, *gslot = nullptr;
+};
+size_t srht_plan_bytes(int64_t n, int s);
+int srht_plan_run(int64_t n, int s, uint64_t seed, SrhtPlan* plan, Arena& keep, Arena& scratch, hipStream_t st);
+int srht_apply_run(const SrhtPlan& plan, const void* A, int dtype, int d, void* out, Arena& ws, hipStream_t st);
 
 // ---------------------------------------------------- FP64 dense blocks
 // C = alpha * op(A) op(B) + beta * C on row-major double matrices (A may be

@@ -272,15 +272,30 @@ __global__ void __launch_bounds__(256) k_sel_write(int64_t n_pad, uint64_t seed,
 
 struct SrhtGeom {
   int64_t n_pad;
-  int m, A, B, A_eff;
+  int m, A, B, A_eff, logB;
 };
 
-static SrhtGeom srht_geom(int64_t n) {
+// H_{n'} = H_A (x) H_B with row index a B + b: level 1 transforms blocks of
+// B rows, level 2 combines the A blocks for the sampled rows only.  B is
+// chosen so that about 16 to 32 sampled rows share each low part b: level
+// 2's matrix-core work, s A d products, falls as B grows while level 1's
+// rows coalesce better as it shrinks (groups of 16 rows), within
+// 2^6 .. 2^10 (level 1 holds
+// 64 rows per lane and at most 16 row groups across lanes), and at least
+// 2^ceil(m / 2) when s is too small to decide (few samples per b).
+static SrhtGeom srht_geom(int64_t n, int s = 0) {
   SrhtGeom g;
   g.m = 1;
   while ((int64_t(1) << g.m) < n) ++g.m;
   g.n_pad = int64_t(1) << g.m;
-  const int mb = (g.m + 1) / 2;
+  int mb = (g.m + 1) / 2;
+  if (s >= 1024) {
+    mb = 0;
+    while ((int64_t(16) << (mb + 1)) <= s) ++mb;   // floor(log2(s / 16))
+    mb = std::max(6, std::min(10, mb));
+  }
+  mb = std::min(mb, g.m);
+  g.logB = mb;
   g.B = 1 << mb;
   g.A = 1 << (g.m - mb);
   g.A_eff = (int)((n + g.B - 1) / g.B);
@@ -464,6 +479,63 @@ __global__ void __launch_bounds__(256) k_srht_level1_reg(const T* __restrict__ A
   }
 }
 
+// Level 1 for 2^LR <= B <= 1024 without an LDS tile: lane (c, g) of a wave
+// holds rows g + G i (i < R = 2^LR) of column c, G = B / R row groups and
+// 64 / G columns per wave (256 / G per block).  The butterflies over the
+// LR high row bits run in registers, those over the log2 G low bits
+// between lanes (lane shuffles); LDS holds only the block's signs, so
+// occupancy is set by registers.  Rows past n read zero through the
+// buffer resource, columns past d take an offset past it.
+template <class T, class Acc, int LR>
+__global__ void __launch_bounds__(256) k_srht_level1_lane(const T* __restrict__ A, int64_t n, int d, int logB,
+                                                          uint64_t seedD, Acc* __restrict__ Tbuf) {
+  constexpr int R = 1 << LR;
+  __shared__ Acc sgn[1024];
+  const int B = 1 << logB;
+  const int logG = logB - LR, G = 1 << logG;
+  const int logCW = 6 - logG, CW = 1 << logCW;          // columns per wave
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a = blockIdx.y;
+  const int c = (blockIdx.x * 4 + w) * CW + (lane & (CW - 1));
+  const int g = lane >> logCW;
+  for (int r = threadIdx.x; r < B; r += 256)
+    sgn[r] = (splitmix64(seedD, (uint64_t)((int64_t)a * B + r)) & 1ull) ? Acc(-1) : Acc(1);
+  __syncthreads();
+  const bool col_ok = c < d;
+  const int64_t row0 = (int64_t)a * B;
+  const int64_t rows_here = n - row0 < B ? n - row0 : B;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(A + row0 * d, rows_here * d * (int64_t)sizeof(T));
+  Acc v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int r = g + G * i;
+    const int off = col_ok ? (r * d + c) * (int)sizeof(T) : kOob;
+    v[i] = buf_load_as<Acc, T>(rs, off) * sgn[r];
+  }
+#pragma unroll
+  for (int h = 1; h < R; h <<= 1)
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if ((i & h) == 0) {
+        const Acc x = v[i], y = v[i + h];
+        v[i] = x + y;
+        v[i + h] = x - y;
+      }
+  for (int lb = 0; lb < logG; ++lb) {
+    const int sh = CW << lb;
+    const bool hi = (g >> lb) & 1;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const Acc p = __shfl_xor(v[i], sh, 64);
+      v[i] = hi ? p - v[i] : v[i] + p;
+    }
+  }
+  if (col_ok) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) Tbuf[(row0 + g + G * i) * d + c] = v[i];
+  }
+}
+
 // Level 2: out[slot] = s^-1/2 * sum_a (-1)^popcount(alpha & a) T[a B + beta].
 template <class Acc>
 __global__ void __launch_bounds__(256) k_srht_level2(const Acc* __restrict__ Tbuf, int d, int B, int A_eff,
@@ -495,6 +567,90 @@ __global__ void __launch_bounds__(256) k_srht_level2(const Acc* __restrict__ Tbu
   }
 }
 
+// Level 2 on FP32 matrix cores: for the sampled rows whose low bits are
+// beta, out_beta = S T_beta with S[j][a] = (-1)^popcount(alpha_j & a) (the
+// rows of H_A the samples pick) and T_beta the rows a B + beta of the
+// level-1 output.  Up to NG groups of 16 sampled rows are the A operands
+// of one pass over T_beta (each lane forms its +-1 entries from alpha_j and
+// a; padding rows are 0); four rows a of T per step are the B operand.  A
+// wave owns NT 16-column tiles (the block four waves side by side) and
+// walks the a range in runs of four steps (16 rows of T), the next run's
+// loads in flight during this run's products.  Each element of T is read
+// once (a beta with more than 16 NG samples takes further passes).
+template <int NT, int NG>
+__global__ void __launch_bounds__(256) k_srht_level2_mfma(const float* __restrict__ Tbuf, int d, int B, int A_eff,
+                                                          const int* __restrict__ goff,
+                                                          const int* __restrict__ galpha,
+                                                          const int* __restrict__ gslot, float scale,
+                                                          float* __restrict__ out) {
+  const int beta = blockIdx.y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const int c0 = (blockIdx.x * 4 + w) * NT * 16;
+  if (c0 >= d) return;
+  const int beg = goff[beta], cnt = goff[beta + 1] - beg;
+  const float* __restrict__ Tb = Tbuf + (int64_t)beta * d;
+  const int64_t rstride = (int64_t)B * d;
+  const int nss = (A_eff + 15) / 16;
+  for (int g0 = 0; g0 < cnt; g0 += 16 * NG) {
+    bool jok[NG];
+    int alpha[NG];
+    f32x4 acc[NG][NT];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      jok[q] = g0 + 16 * q + m < cnt;
+      alpha[q] = jok[q] ? galpha[beg + g0 + 16 * q + m] : 0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[q][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    const int ng = min(NG, (cnt - g0 + 15) / 16);   // groups with samples in this pass
+    auto load = [&](int ss, float (&bv)[4][NT]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int a = 16 * ss + 4 * u + kq;
+        const bool aok = a < A_eff;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int col = c0 + 16 * t + m;
+          bv[u][t] = (aok && col < d) ? Tb[(int64_t)a * rstride + col] : 0.f;
+        }
+      }
+    };
+    float cur[4][NT], nxt[4][NT];
+    load(0, cur);
+    for (int ss = 0; ss < nss; ++ss) {
+      load(ss + 1, nxt);
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        if (q < ng) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int a = 16 * ss + 4 * u + kq;
+            const float sg = (jok[q] && a < A_eff) ? ((__popc(alpha[q] & a) & 1) ? -1.f : 1.f) : 0.f;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[q][t] = mfma16x16x4(sg, cur[u][t], acc[q][t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) cur[u][t] = nxt[u][t];
+    }
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int col = c0 + 16 * t + m;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = g0 + 16 * q + 4 * kq + r;   // accumulator row
+          if (j < cnt && col < d) out[(int64_t)gslot[beg + j] * d + col] = acc[q][t][r] * scale;
+        }
+      }
+  }
+}
+
 static int srht_chunk_cols(int B, int acc_bytes) {
   // LDS tile of B x CW elements, at most 64 KiB.
   int cw = (64 * 1024) / (B * acc_bytes);
@@ -504,7 +660,7 @@ static int srht_chunk_cols(int B, int acc_bytes) {
 }
 
 size_t srht_ws_bytes(int64_t n, int d, int s, int dtype) {
-  SrhtGeom g = srht_geom(n);
+  SrhtGeom g = srht_geom(n, s);
   const size_t acc = dtype == SRP_F64 ? 8 : 4;
   const int chunks = (int)((g.n_pad + kSelChunk - 1) / kSelChunk);
   return bytes_of<int>(65536) + bytes_of<SelectState>(1) + 2 * bytes_of<int>(chunks + 1) +
@@ -525,7 +681,41 @@ template <class T, class Acc>
 static int srht_levels(const T* A, int64_t n, int d, int s, uint64_t seed, const SrhtGeom& g,
                        const int* goff, const int* galpha, const int* gslot, Acc* Tbuf, Acc* out,
                        hipStream_t st) {
-  const int logB = (g.m + 1) / 2;
+  const int logB = g.logB;
+  if constexpr (sizeof(Acc) == 4) {
+    if (logB >= 6 && logB <= 10) {
+      // FP32: level 1 in registers and lane shuffles, level 2 on matrix
+      // cores.  Groups of 16 per pass: the expected
+      // samples per class plus four standard deviations, so that nearly
+      // every class reads its rows once.
+      const int CWB = 256 >> (logB - 6);   // columns per block
+      dim3 grid1((d + CWB - 1) / CWB, g.A_eff);
+      hipLaunchKernelGGL((k_srht_level1_lane<T, Acc, 6>), grid1, dim3(256), 0, st, A, n, d, logB,
+                         seed ^ kSrhtSignSalt, Tbuf);
+      SRP_LAUNCH_CHECK();
+      constexpr int NT = 2;
+      const double mean = (double)s / g.B;
+      const int want = (int)std::ceil((mean + 4.0 * std::sqrt(mean) + 1.0) / 16.0);
+      dim3 grid2((d + 4 * NT * 16 - 1) / (4 * NT * 16), g.B);
+      const float sc = (float)(1.0 / std::sqrt((double)s));
+      const float* Tf = (const float*)Tbuf;
+      float* of = (float*)out;
+      if (want <= 2)
+        hipLaunchKernelGGL((k_srht_level2_mfma<NT, 2>), grid2, dim3(256), 0, st, Tf, d, g.B, g.A_eff, goff, galpha,
+                           gslot, sc, of);
+      else if (want <= 4)
+        hipLaunchKernelGGL((k_srht_level2_mfma<NT, 4>), grid2, dim3(256), 0, st, Tf, d, g.B, g.A_eff, goff, galpha,
+                           gslot, sc, of);
+      else
+        hipLaunchKernelGGL((k_srht_level2_mfma<NT, 6>), grid2, dim3(256), 0, st, Tf, d, g.B, g.A_eff, goff, galpha,
+                           gslot, sc, of);
+      SRP_LAUNCH_CHECK();
+      return SRP_OK;
+    }
+  }
+  // FP64, and blocks outside 2^6 .. 2^10: level 1 through an LDS tile
+  // (registers for the 64 high row bits when B >= 64), block-major output;
+  // level 2 on the vector units.
   if (logB >= 6 && logB <= 10) {
     const int CW = 16384 >> logB;
     dim3 grid1((d + CW - 1) / CW, g.A_eff);
@@ -548,39 +738,64 @@ static int srht_levels(const T* A, int64_t n, int d, int s, uint64_t seed, const
   return SRP_OK;
 }
 
-int srht_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, Arena& ws,
-             hipStream_t st) {
-  SrhtGeom g = srht_geom(n);
+size_t srht_plan_bytes(int64_t n, int s) {
+  const SrhtGeom g = srht_geom(n, s);
+  return bytes_of<int64_t>(s) + bytes_of<int>(g.B + 1) + 2 * bytes_of<int>(s);
+}
+
+int srht_plan_run(int64_t n, int s, uint64_t seed, SrhtPlan* plan, Arena& keep, Arena& scratch, hipStream_t st) {
+  SrhtGeom g = srht_geom(n, s);
   if ((int64_t)s > g.n_pad || g.m > 20) {
     set_error("srht: need s <= n' <= 2^20 (n=%lld, s=%d)", (long long)n, s);
     return SRP_EINVAL;
   }
-  int64_t* rows = ws.take<int64_t>(s);
-  int* goff = ws.take<int>(g.B + 1);
-  int* galpha = ws.take<int>(s);
-  int* gslot = ws.take<int>(s);
-  if (!gslot) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
-  SRP_TRY(srht_select_rows(g.n_pad, s, seed, rows, ws, st));
-  int logB = 0;
-  while ((1 << logB) < g.B) ++logB;
-  hipLaunchKernelGGL(k_srht_group, dim3(1), dim3(1024), 0, st, rows, s, g.B, logB, goff, galpha, gslot);
+  plan->n = n;
+  plan->s = s;
+  plan->seed = seed;
+  plan->rows = keep.take<int64_t>(s);
+  plan->goff = keep.take<int>(g.B + 1);
+  plan->galpha = keep.take<int>(s);
+  plan->gslot = keep.take<int>(s);
+  if (!plan->gslot) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
+  SRP_TRY(srht_select_rows(g.n_pad, s, seed, plan->rows, scratch, st));
+  hipLaunchKernelGGL(k_srht_group, dim3(1), dim3(1024), 0, st, plan->rows, s, g.B, g.logB, plan->goff,
+                     plan->galpha, plan->gslot);
   SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+int srht_apply_run(const SrhtPlan& plan, const void* A, int dtype, int d, void* out, Arena& ws, hipStream_t st) {
+  const int64_t n = plan.n;
+  const int s = plan.s;
+  const uint64_t seed = plan.seed;
+  SrhtGeom g = srht_geom(n, s);
   const size_t tcount = (size_t)g.A_eff * g.B * d;
   if (dtype == SRP_F64) {
     double* Tbuf = ws.take<double>(tcount);
     if (!Tbuf) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
-    return srht_levels((const double*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (double*)out, st);
+    return srht_levels((const double*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, Tbuf, (double*)out,
+                       st);
   }
   float* Tbuf = ws.take<float>(tcount);
   if (!Tbuf) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
   if (dtype == SRP_F32)
-    return srht_levels((const float*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (float*)out, st);
+    return srht_levels((const float*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, Tbuf, (float*)out,
+                       st);
   if (dtype == SRP_BF16)
-    return srht_levels((const bf16*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (float*)out, st);
+    return srht_levels((const bf16*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, Tbuf, (float*)out,
+                       st);
   if (dtype == SRP_FP8E4M3)
-    return srht_levels((const fp8e4m3*)A, n, d, s, seed, g, goff, galpha, gslot, Tbuf, (float*)out, st);
+    return srht_levels((const fp8e4m3*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, Tbuf,
+                       (float*)out, st);
   set_error("srht: bad dtype %d", dtype);
   return SRP_EINVAL;
+}
+
+int srht_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, Arena& ws,
+             hipStream_t st) {
+  SrhtPlan plan;
+  SRP_TRY(srht_plan_run(n, s, seed, &plan, ws, ws, st));
+  return srht_apply_run(plan, A, dtype, d, out, ws, st);
 }
 
 }  // namespace srp
