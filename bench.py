@@ -23,6 +23,7 @@ import synth  # noqa: E402
 
 METRIC = "CCA solves/sec + TFLOP/s at 1e-6 rel obj err vs FP64; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 # the metric's accuracy: relative objective error and constraint residual
 # against the FP64 oracle (FP32 paths, and BF16 / FP8 after refinement)
 ACCURACY_BAR = 1e-6
@@ -100,9 +101,74 @@ def cpu_baseline(wl, X, Y_or_labels, min_seconds=10.0, max_reps=20):
         t_all += time.perf_counter() - t0
         reps += 1
     rec = {"value": reps / t_all, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+           "cpu_model": cpu_model(),
            "sample": f"{reps} full FP64 direct solves of the {wl.name} workload "
                      f"(Gram, Cholesky, whitened SVD; numpy/OpenBLAS), {t_all:.1f} s in total"}
+    # the same oracle on one thread: one whole solve
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        if wl.problem == "cca":
+            direct.cca_direct(X, Y_or_labels, wl.lam_value, wl.lam_value)
+        else:
+            direct.lda_direct(X, Y_or_labels, wl.c, wl.lam_value, k=wl.k)
+        t1 = time.perf_counter() - t0
+    rec["one_thread"] = {"value": 1.0 / t1, "unit": "solves/s", "cores": 1,
+                         "sample": f"one full solve on one thread, {t1:.1f} s"}
     return rec, vals
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def stream_time_ms(fn, reps=5):
+    """Average GPU time of fn() over reps calls, from HIP events recorded on
+    torch's current stream (the stream the library enqueues on)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def sketch_and_factor_rooflines(srp, wl, Ad):
+    """The sketch of one view (the whole srp_srht / srp_countsketch call:
+    row selection, both levels) against the HBM roofline, with algorithmic
+    bytes = the view read once plus the s x d sketch written once; and the
+    FP64 metric factor of that sketch (srp_sketch_factor) against the FP64
+    matrix-core peak, with algorithmic flops = s d^2 (the symmetric Gram) +
+    d^3 / 3 (Cholesky) + d^3 / 3 (R^-1) + d^3 / 3 (M^-1 = R^-1 R^-T)."""
+    esize = Ad.element_size()
+    n, d = Ad.shape
+    s = wl.s
+    sk = srp.srp_srht if wl.sketch == "srht" else srp.srp_countsketch
+    ms = stream_time_ms(lambda: sk(Ad, s, 12060))
+    nbytes = n * d * esize + s * d * 4
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    SA = sk(Ad, s, 12060)
+    lam = wl.lam_value
+    msf = stream_time_ms(lambda: srp.srp_sketch_factor(SA, lam))
+    flops = s * d * d + d ** 3
+    tf = flops / (msf * 1e-3) / 1e12
+    return ({"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+             "traffic": None, "kernel": f"{wl.sketch} of one {n} x {d} view (s = {s}), whole call",
+             "bytes_per_call": nbytes, "avg_call_ms": ms},
+            {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": tf / FP64_PEAK_TFS,
+             "traffic": None, "kernel": f"FP64 metric factor of the {s} x {d} sketch (Gram, Cholesky, R^-1, M^-1)",
+             "flops_per_call": flops, "avg_call_ms": msf})
 
 
 def pct(a, q):
@@ -373,6 +439,7 @@ def main():
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "tflops": flops_per_pass / (avg_ms * 1e-3) / 1e12 if launches else 0.0}
 
+    sketch_rl, factor_rl = sketch_and_factor_rooflines(srp, wl, Ad)
     out = {"metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": DTYPE_NAMES[wl.dtype], "data": "synthetic",
@@ -383,6 +450,8 @@ def main():
                       "final_f64": extra.get("final_f64", 0),
                       "parallelism": "single-gpu"},
            "roofline": roofline,
+           "sketch_roofline": sketch_rl,
+           "factor_roofline": factor_rl,
            "solve": {key: infos[-1][key] for key in ("status", "iterations", "warm_iterations", "passes",
                                                      "ms_sketch", "ms_factor", "ms_warm", "ms_iterate",
                                                      "ms_total", "lowp_iterations", "ms_lowp")}}

@@ -235,6 +235,14 @@ WORKLOADS = {
                              x_decades=4.0, y_decades=4.0,
                              inclusive_end=False, noise=1.0,
                              factor_decades=2.0),
+    # The same shape with the recipe exactly as the FP32 CCA configuration
+    # states it: latent Z ~ N(0, 1) of rank 32 with equal strengths, noise
+    # 0.1 (the top 32 correlations then sit within ~1e-5 of 1).
+    "cca-f32-srht-cfg1": Workload("cca-f32-srht-cfg1", "cca", 200_000, 1000, 1000, 10,
+                                  1e-4, "srht", 4000, "f32", 12060 + 1, r=32,
+                                  x_decades=4.0, y_decades=4.0,
+                                  inclusive_end=False, noise=0.1,
+                                  factor_decades=0.0),
     # FP32 FDA, CountSketch s = 8000 of the centred data, 20 classes.
     "lda-f32": Workload("lda-f32", "lda", 100_000, 2000, 0, 19, float("nan"),
                         "countsketch", 8000, "f32", 12060 + 2, c=20),
