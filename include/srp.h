@@ -54,6 +54,10 @@ extern "C" {
 #define SRP_BF16 2
 #define SRP_FP8E4M3 3     /* sketch input only: OCP E4M3 codes (see srp_stage_fp8) */
 
+/* ---- Riemannian optimisation methods ---------------------------------- */
+#define SRP_RCG 0         /* Riemannian conjugate gradient (the default)      */
+#define SRP_RTR 1         /* Riemannian trust region with truncated CG        */
+
 /* ---- sketch kinds ----------------------------------------------------- */
 #define SRP_COUNTSKETCH 0 /* Section 3                                       */
 #define SRP_SRHT 1        /* Appendix A, Definition SRHT                      */
@@ -111,6 +115,13 @@ typedef struct srp_options {
   int sketch_dtype;       /* SRP_F32, SRP_BF16 or SRP_FP8E4M3                  */
   const double* sketch_scale_x;   /* FP8: device column scales (srp_stage_fp8) */
   const double* sketch_scale_y;
+  /* SRP_RCG, or SRP_RTR: the Riemannian trust-region method (Section 2.2
+     names it among the Riemannian algorithms the Table 1 components serve)
+     with a truncated CG inner solver; its Hessian-vector products are
+     Table 1's formula (Eq. HessCCA, Eq. LDAhess), one fused data pass each.
+     max_iter then caps the outer iterations.  Needs k <= 16; no BF16 phase. */
+  int method;
+  int rtr_max_inner;      /* inner (truncated CG) iterations per outer one (50) */
 } srp_options;
 
 /* Per-solve report. */
@@ -144,6 +155,8 @@ typedef struct srp_info {
                              BF16 products was not positive definite; the
                              iteration then continued on the main data from
                              the phase's start point)                        */
+  int inner_iterations;   /* SRP_RTR: truncated CG iterations in all (one
+                             data pass each)                                 */
 } srp_info;
 
 /* Fill *opt with the defaults listed above.  Returns SRP_EINVAL if NULL. */

@@ -20,6 +20,7 @@ SRP_OK, SRP_EINVAL, SRP_ENOTSPD, SRP_ENOCONV, SRP_ENOMEM, SRP_EDEVICE = 0, 1, 2,
 SRP_EBUSY, SRP_EREJECTED, SRP_PENDING = 6, 7, 8
 SRP_F64, SRP_F32, SRP_BF16, SRP_FP8E4M3 = 0, 1, 2, 3
 SRP_COUNTSKETCH, SRP_SRHT = 0, 1
+SRP_RCG, SRP_RTR = 0, 1
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTSPD", 3: "ENOCONV", 4: "ENOMEM",
                 5: "EDEVICE", 6: "EBUSY", 7: "EREJECTED", 8: "PENDING"}
@@ -37,7 +38,7 @@ class SrpOptions(ctypes.Structure):
                 ("lowp_x", ctypes.c_void_p), ("lowp_y", ctypes.c_void_p), ("lowp_tol", ctypes.c_double),
                 ("lowp_max_iter", ctypes.c_int), ("sketch_x", ctypes.c_void_p), ("sketch_y", ctypes.c_void_p),
                 ("sketch_dtype", ctypes.c_int), ("sketch_scale_x", ctypes.c_void_p),
-                ("sketch_scale_y", ctypes.c_void_p)]
+                ("sketch_scale_y", ctypes.c_void_p), ("method", ctypes.c_int), ("rtr_max_inner", ctypes.c_int)]
 
 
 class SrpInfo(ctypes.Structure):
@@ -50,7 +51,7 @@ class SrpInfo(ctypes.Structure):
                 ("pass_ms", ctypes.c_double), ("pass_launches", ctypes.c_int),
                 ("lowp_iterations", ctypes.c_int), ("ms_lowp", ctypes.c_double),
                 ("lowp_pass_ms", ctypes.c_double), ("lowp_pass_launches", ctypes.c_int),
-                ("lowp_status", ctypes.c_int)]
+                ("lowp_status", ctypes.c_int), ("inner_iterations", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -181,6 +182,8 @@ def srp_default_options(**overrides) -> SrpOptions:
             val = {"countsketch": SRP_COUNTSKETCH, "srht": SRP_SRHT}[val]
         if key == "pass_compute" and isinstance(val, str):
             val = {"f64": SRP_F64, "f32": SRP_F32}[val]
+        if key == "method" and isinstance(val, str):
+            val = {"rcg": SRP_RCG, "rtr": SRP_RTR}[val]
         setattr(o, key, val)
     return o
 

@@ -38,6 +38,8 @@ int srp_default_options(srp_options* o) {
   o->seed = 12060;
   o->max_iter = 1000;
   o->warm_start_iters = 48;
+  o->method = SRP_RCG;
+  o->rtr_max_inner = 50;
   o->refresh_every = 25;
   o->check_every = 2;
   o->pass_compute = -1;

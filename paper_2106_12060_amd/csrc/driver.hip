@@ -14,6 +14,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 #include "solver.hpp"
+#include "rtr.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -203,6 +204,8 @@ struct RcgBuffers {
   std::vector<std::pair<hipEvent_t, hipEvent_t>>* events = nullptr;
   int* ran_all = nullptr;   // two counters: main passes, BF16-phase passes
   int* ran = nullptr;
+  char* rtr_ws = nullptr;   // the trust-region solver's vectors
+  size_t rtr_ws_bytes = 0;
 };
 
 __global__ void k_count_pass(const int* __restrict__ done, int* __restrict__ ran) {
@@ -225,6 +228,8 @@ static size_t skinny_bytes(int nb, int k, const int* d, int c) {
   return b;
 }
 
+static size_t rtr_ws_bytes(int nb, int k, const int* d);
+
 static size_t rcg_buffers_bytes(int nb, int k, int64_t nmax, const int* d, int dtype, int c = 0) {
   size_t b = skinny_bytes(nb, k, d, c) + bytes_of<double>((size_t)std::max(c, 1) * k);
   for (int s = 0; s < nb; ++s) {
@@ -240,6 +245,7 @@ static size_t rcg_buffers_bytes(int nb, int k, int64_t nmax, const int* d, int d
   const int ks = twopass_ksplit(nmax);
   b += bytes_of<double>((size_t)nmax * nb * k);
   b += bytes_of<double>((size_t)ks * std::max(d[0], nb == 2 ? d[1] : 0) * nb * k);
+  b += rtr_ws_bytes(nb, std::min(k, kRtrK), d);
   (void)dtype;
   return b;
 }
@@ -275,7 +281,10 @@ static int rcg_buffers_take(RcgBuffers& B, Arena& ar, int nb, int k, int64_t nma
   B.ksplit = twopass_ksplit(nmax);
   B.Pn = ar.take<double>((size_t)nmax * nb * k);
   B.parts = ar.take<double>((size_t)B.ksplit * std::max(d[0], nb == 2 ? d[1] : 0) * nb * k);
-  if (!B.ctrl || !B.kk || !B.part || !B.mu || !B.pass_ws || !B.Pn || !B.parts || !B.skw || !B.Tc || !B.ran_all)
+  B.rtr_ws_bytes = rtr_ws_bytes(nb, std::min(k, kRtrK), d);
+  B.rtr_ws = ar.take<char>(B.rtr_ws_bytes);
+  if (!B.ctrl || !B.kk || !B.part || !B.mu || !B.pass_ws || !B.Pn || !B.parts || !B.skw || !B.Tc || !B.ran_all ||
+      !B.rtr_ws)
     return SRP_ENOMEM;
   return SRP_OK;
 }
@@ -555,6 +564,288 @@ static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int
   return SRP_OK;
 }
 
+// ------------------------------------------------- trust region
+// Riemannian trust-region with a truncated CG inner solver (Steihaug-Toint),
+// in the metric g(xi, eta) = tr(xi^T M eta) of Table 1.  The Hessian of
+// Table 1 applied to a tangent vector reads, with S_g the symmetric solution
+// of the gradient's projection (X^T grad_E f - X^T M grad f = S_g),
+//   Hess f[d] = Pi_Z(M^-1 (D^2 f[d] - B d S_g)),
+// which for CCA is Eq. HessCCA (D^2 f[d] = -[Sxy d_V N; Sxy^T d_U N]) and
+// for FDA Eq. LDAhess (D^2 f[d] = -S_B d N).  One fused data pass along d
+// gives B d and the cross product; the projection reuses P = (BZ)^T M^-1 BZ,
+// factored once per outer iteration.  Every tangent vector v is carried
+// with its image M v (M Pi(M^-1 h) = h - BZ S_h), so the metric's inner
+// products are plain traces.  The trial point's retraction Gram and cost
+// come from products accumulated along the inner iterations (B eta and the
+// cross product of eta are sums of the passes along the CG directions): no
+// extra data pass.
+struct RtrState {
+  double *BZ[2], *MiK[2], *e[2], *w[2], *grad[2], *Mg[2], *r[2], *Mr[2], *dl[2], *Mdl[2];
+  double *eta[2], *Meta[2], *Beta[2], *Ceta[2], *MHeta[2], *h[2], *wh[2], *Hd[2], *MHd[2], *Bd[2], *Cd[2], *tmp[2];
+  double *P[2], *Q[2], *lam[2], *Sg[2], *Cg[2], *Sh[2], *Ch[2], *E[2], *F[2], *Lit[2], *X0[4], *Nm;
+  double* dots;     // device scalars
+  double* hdots;    // pinned host copy
+};
+
+static size_t rtr_ws_bytes(int nb, int k, const int* d) {
+  size_t b = 0;
+  for (int s = 0; s < nb; ++s) b += 22 * bytes_of<double>((size_t)d[s] * k);
+  b += (2 * 11 + 5) * bytes_of<double>((size_t)kRtrK * kRtrK) + bytes_of<double>(16);
+  return b + 64 * 256;
+}
+
+static int rtr_take(RtrState& R, Arena& a, int nb, int k, const int* d) {
+  for (int s = 0; s < 2; ++s) {
+    double** vecs[] = {&R.BZ[s], &R.MiK[s], &R.e[s], &R.w[s], &R.grad[s], &R.Mg[s], &R.r[s], &R.Mr[s], &R.dl[s],
+                       &R.Mdl[s], &R.eta[s], &R.Meta[s], &R.Beta[s], &R.Ceta[s], &R.MHeta[s], &R.h[s], &R.wh[s],
+                       &R.Hd[s], &R.MHd[s], &R.Bd[s], &R.Cd[s], &R.tmp[s]};
+    for (double** v : vecs) *v = s < nb ? a.take<double>((size_t)d[s] * k) : nullptr;
+    double** mats[] = {&R.P[s], &R.Q[s], &R.lam[s], &R.Sg[s], &R.Cg[s], &R.Sh[s], &R.Ch[s], &R.E[s], &R.F[s],
+                       &R.Lit[s]};
+    for (double** m : mats) *m = s < nb ? a.take<double>((size_t)kRtrK * kRtrK) : nullptr;
+  }
+  for (int q = 0; q < 4; ++q) R.X0[q] = a.take<double>((size_t)kRtrK * kRtrK);
+  R.Nm = a.take<double>((size_t)kRtrK * kRtrK);
+  R.dots = a.take<double>(16);
+  if (!R.dots || !R.tmp[nb - 1]) { set_error("trust region: workspace too small"); return SRP_ENOMEM; }
+  return SRP_OK;
+}
+
+struct RtrResult {
+  int status = SRP_OK, outer = 0, inner = 0, passes = 0;
+  double f = 0.0, gg = 0.0;
+};
+
+static int rtr_run(const RcgProblem& P, RcgBuffers& B, RtrState& R, const double* mu_host, int max_outer,
+                   int max_inner, double tol, int refresh_every, RtrResult& res, hipStream_t st) {
+  const int k = P.k, nb = P.nb;
+  const int* d = P.d;
+  const double cs = P.lda_cost ? 0.5 : 1.0;   // f = cs tr(Z_0^T e_0)
+  auto lin = [&](double* const* out, double a, double* const* A, double c, double* const* C,
+                 double* const* K) -> int {
+    RtrLinArgs la{};
+    la.k = k;
+    for (int b = 0; b < nb; ++b) {
+      la.side[b] = RtrLinSide{out[b], A ? A[b] : nullptr, a, C ? C[b] : nullptr, c, K ? K[b] : nullptr, d[b]};
+    }
+    return rtr_lin(la, nb, st);
+  };
+  // C_b = op(X_b)^T Y_b (k x k) for both blocks, one launch
+  auto gram = [&](double* const* X, double* const* Y, double* const* Cout) -> int {
+    SkinnyProb pr[2];
+    for (int b = 0; b < nb; ++b) pr[b] = SkinnyProb{k, d[b], k, X[b], k, true, Y[b], k, Cout[b], k};
+    return gemm_skinny_batch(nb, pr, B.skw, B.skw_bytes, st);
+  };
+  auto minv = [&](double* const* X, double* const* Out) -> int {
+    SkinnyProb pr[2];
+    for (int b = 0; b < nb; ++b) pr[b] = SkinnyProb{d[b], d[b], k, P.Minv[b], d[b], false, X[b], k, Out[b], k};
+    return gemm_skinny_batch(nb, pr, B.skw, B.skw_bytes, st);
+  };
+  auto dots = [&](int np, double* const* X0, double* const* Y0, double* const* X1, double* const* Y1,
+                  double* const* X2, double* const* Y2, double* const* X3, double* const* Y3, int nbp = 0) -> int {
+    RtrDotArgs da{};
+    da.k = k; da.nb = nbp ? nbp : nb; da.np = np; da.out = R.dots;
+    da.d[0] = d[0]; da.d[1] = nb == 2 ? d[1] : 0;
+    double* const* xs[4] = {X0, X1, X2, X3};
+    double* const* ys[4] = {Y0, Y1, Y2, Y3};
+    for (int p = 0; p < np; ++p)
+      for (int b = 0; b < da.nb; ++b) { da.X[p][b] = xs[p][b]; da.Y[p][b] = ys[p][b]; }
+    SRP_TRY(rtr_dots(da, st));
+    SRP_HIP(hipMemcpyAsync(R.hdots, R.dots, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+    SRP_HIP(hipStreamSynchronize(st));
+    return SRP_OK;
+  };
+  // the pass along dirs: B dirs (with lambda) into Bout, cross products into Cout
+  auto pass = [&](double* const* dirs, double* const* Bout, double* const* Cout) -> int {
+    SRP_TRY(data_pass(P, B, dirs, P.compute, nullptr, st));
+    ++res.passes;
+    // J_b = A_b^T [A_0 d_0 | A_1 d_1]: block b of it (plus lambda d_b) is
+    // B_b d_b, the other block the cross product (FDA: S_B d from Jc)
+    RtrLinArgs la{}, lc{};
+    la.k = lc.k = k;
+    for (int b = 0; b < nb; ++b) {
+      la.side[b] = RtrLinSide{Bout[b], B.J[b] + b * k, 1.0, dirs[b], P.lam[b], nullptr, d[b], nb * k, 0};
+      if (P.lda_cost) lc.side[b] = RtrLinSide{Cout[b], B.Jc[b], 1.0, nullptr, 0.0, nullptr, d[b], 0, 0};
+      else lc.side[b] = RtrLinSide{Cout[b], B.J[b] + (1 - b) * k, 1.0, nullptr, 0.0, nullptr, d[b], nb * k, 0};
+    }
+    SRP_TRY(rtr_lin(la, nb, st));
+    SRP_TRY(rtr_lin(lc, nb, st));
+    return SRP_OK;
+  };
+  // N as a diagonal matrix
+  {
+    double Nh[kRtrK * kRtrK] = {};
+    for (int i = 0; i < k; ++i) Nh[i * k + i] = mu_host[i];
+    SRP_HIP(hipMemcpyAsync(R.Nm, Nh, sizeof(double) * k * k, hipMemcpyHostToDevice, st));
+  }
+  double* Nm2[2] = {R.Nm, R.Nm};
+  const double Dbar = std::sqrt((double)k * nb), rho_prime = 0.1;
+  double Delta = Dbar / 8.0;
+  int accepted = 0;
+  double f = 0.0, gg = 0.0;
+  for (int outer = 0; outer <= max_outer; ++outer) {
+    // gradient at Z: BZ = Ks + lam Z, e = -Kc N, S_g, grad, M grad
+    for (int b = 0; b < nb; ++b) {
+      RtrLinArgs la{};
+      la.k = k;
+      la.side[0] = RtrLinSide{R.BZ[b], B.Ks[b], 1.0, B.U[b], P.lam[b], nullptr, d[b]};
+      SRP_TRY(rtr_lin(la, 1, st));
+    }
+    SRP_TRY(lin(R.e, 0.0, nullptr, -1.0, B.Kc, Nm2));
+    SRP_TRY(minv(R.BZ, R.MiK));
+    SRP_TRY(minv(R.e, R.w));
+    SRP_TRY(gram(R.BZ, R.MiK, R.P));
+    for (int b = 0; b < nb; ++b) SRP_TRY(launch_rr_eig(R.P[b], k, k, R.Q[b], R.lam[b], st));
+    SRP_TRY(gram(R.BZ, R.w, R.Cg));
+    {
+      RtrSylvArgs sa{};
+      sa.k = k;
+      for (int b = 0; b < nb; ++b) { sa.Q[b] = R.Q[b]; sa.lam[b] = R.lam[b]; sa.C[b] = R.Cg[b]; sa.S[b] = R.Sg[b]; }
+      SRP_TRY(rtr_sylv(sa, nb, st));
+    }
+    SRP_TRY(lin(R.grad, 1.0, R.w, -1.0, R.MiK, R.Sg));
+    SRP_TRY(lin(R.Mg, 1.0, R.e, -1.0, R.BZ, R.Sg));
+    // f needs block 0 only, ||grad||^2 both blocks
+    {
+      double* const* Z0 = B.U;
+      SRP_TRY(dots(1, Z0, R.e, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 1));
+      f = cs * R.hdots[0];
+    }
+    SRP_TRY(dots(1, R.grad, R.Mg, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
+    gg = R.hdots[0];
+    res.f = f;
+    res.gg = gg;
+    res.outer = outer;
+    if (!(std::isfinite(f) && std::isfinite(gg))) { res.status = SRP_ENOTSPD; return SRP_OK; }
+    if (std::sqrt(std::max(gg, 0.0)) <= tol * std::fabs(f)) { res.status = SRP_OK; return SRP_OK; }
+    if (outer == max_outer) { res.status = SRP_ENOCONV; return SRP_OK; }
+    // truncated CG on the model  f + <grad, eta> + 1/2 <eta, Hess eta>, ||eta|| <= Delta
+    SRP_TRY(lin(R.eta, 0.0, nullptr, 0.0, nullptr, nullptr));
+    SRP_TRY(lin(R.Meta, 0.0, nullptr, 0.0, nullptr, nullptr));
+    SRP_TRY(lin(R.Beta, 0.0, nullptr, 0.0, nullptr, nullptr));
+    SRP_TRY(lin(R.Ceta, 0.0, nullptr, 0.0, nullptr, nullptr));
+    SRP_TRY(lin(R.MHeta, 0.0, nullptr, 0.0, nullptr, nullptr));
+    SRP_TRY(lin(R.r, 1.0, R.grad, 0.0, nullptr, nullptr));
+    SRP_TRY(lin(R.Mr, 1.0, R.Mg, 0.0, nullptr, nullptr));
+    SRP_TRY(lin(R.dl, -1.0, R.grad, 0.0, nullptr, nullptr));
+    SRP_TRY(lin(R.Mdl, -1.0, R.Mg, 0.0, nullptr, nullptr));
+    double rr = gg, ee = 0.0, ed = 0.0, dd = gg;
+    const double r0 = std::sqrt(gg);
+    bool boundary = false;
+    for (int j = 0; j < max_inner; ++j) {
+      ++res.inner;
+      SRP_TRY(pass(R.dl, R.Bd, R.Cd));
+      // h = -Cd N - Bd S_g ; Hd = Pi(M^-1 h) ; M Hd = h - BZ S_h
+      SRP_TRY(lin(R.tmp, 0.0, nullptr, 1.0, R.Cd, Nm2));
+      SRP_TRY(lin(R.h, -1.0, R.tmp, -1.0, R.Bd, R.Sg));
+      SRP_TRY(minv(R.h, R.wh));
+      SRP_TRY(gram(R.BZ, R.wh, R.Ch));
+      {
+        RtrSylvArgs sa{};
+        sa.k = k;
+        for (int b = 0; b < nb; ++b) { sa.Q[b] = R.Q[b]; sa.lam[b] = R.lam[b]; sa.C[b] = R.Ch[b]; sa.S[b] = R.Sh[b]; }
+        SRP_TRY(rtr_sylv(sa, nb, st));
+      }
+      SRP_TRY(lin(R.Hd, 1.0, R.wh, -1.0, R.MiK, R.Sh));
+      SRP_TRY(lin(R.MHd, 1.0, R.h, -1.0, R.BZ, R.Sh));
+      SRP_TRY(dots(1, R.dl, R.MHd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr));
+      const double kappa = R.hdots[0];
+      const double alpha = rr / kappa;
+      double step = alpha;
+      bool stop_boundary = false;
+      if (!(kappa > 0.0) || ee + 2.0 * alpha * ed + alpha * alpha * dd >= Delta * Delta) {
+        // to the boundary: the positive root of ee + 2 t ed + t^2 dd = Delta^2
+        step = (-ed + std::sqrt(std::max(0.0, ed * ed + dd * (Delta * Delta - ee)))) / dd;
+        stop_boundary = true;
+      }
+      SRP_TRY(lin(R.eta, 1.0, R.eta, step, R.dl, nullptr));
+      SRP_TRY(lin(R.Meta, 1.0, R.Meta, step, R.Mdl, nullptr));
+      SRP_TRY(lin(R.Beta, 1.0, R.Beta, step, R.Bd, nullptr));
+      SRP_TRY(lin(R.Ceta, 1.0, R.Ceta, step, R.Cd, nullptr));
+      SRP_TRY(lin(R.MHeta, 1.0, R.MHeta, step, R.MHd, nullptr));
+      if (stop_boundary) { boundary = true; break; }
+      SRP_TRY(lin(R.r, 1.0, R.r, alpha, R.Hd, nullptr));
+      SRP_TRY(lin(R.Mr, 1.0, R.Mr, alpha, R.MHd, nullptr));
+      SRP_TRY(dots(4, R.r, R.Mr, R.eta, R.Meta, R.eta, R.Mr, R.r, R.Mdl));
+      const double rr_new = R.hdots[0], ee_new = R.hdots[1], er = R.hdots[2], rd_old = R.hdots[3];
+      if (std::sqrt(std::max(rr_new, 0.0)) <= r0 * std::min(r0, 0.1)) break;   // theta = 1, kappa = 0.1
+      const double beta = rr_new / rr;
+      const double ed_old = ed + alpha * dd;   // <eta_new, d_old>
+      ed = -er + beta * ed_old;
+      dd = rr_new - 2.0 * beta * rd_old + beta * beta * dd;
+      ee = ee_new;
+      rr = rr_new;
+      SRP_TRY(lin(R.dl, -1.0, R.r, beta, R.dl, nullptr));
+      SRP_TRY(lin(R.Mdl, -1.0, R.Mr, beta, R.Mdl, nullptr));
+    }
+    // model decrease and the trial point
+    SRP_TRY(dots(2, R.eta, R.Mg, R.eta, R.MHeta, nullptr, nullptr, nullptr, nullptr));
+    const double mdec = -(R.hdots[0] + 0.5 * R.hdots[1]);
+    // Gram of Z + eta from the carried products, the current Z^T B Z
+    // included (not taken as I), so rounding in the constraint does not
+    // accumulate over accepted steps
+    SRP_TRY(lin(R.tmp, 0.5, B.U, 1.0, R.eta, nullptr));
+    SRP_TRY(gram(R.BZ, R.tmp, R.E));
+    SRP_TRY(gram(R.eta, R.Beta, R.F));
+    {
+      SkinnyProb pr[4];
+      pr[0] = SkinnyProb{k, d[0], k, B.U[0], k, true, B.Kc[0], k, R.X0[0], k};
+      pr[1] = SkinnyProb{k, d[0], k, B.U[0], k, true, R.Ceta[0], k, R.X0[1], k};
+      pr[2] = SkinnyProb{k, d[0], k, R.eta[0], k, true, B.Kc[0], k, R.X0[2], k};
+      pr[3] = SkinnyProb{k, d[0], k, R.eta[0], k, true, R.Ceta[0], k, R.X0[3], k};
+      SRP_TRY(gemm_skinny_batch(4, pr, B.skw, B.skw_bytes, st));
+    }
+    {
+      RtrTrialArgs ta{};
+      ta.k = k; ta.nb = nb; ta.mu = B.mu; ta.cost_scale = cs; ta.out = R.dots;
+      for (int b = 0; b < nb; ++b) { ta.E[b] = R.E[b]; ta.F[b] = R.F[b]; ta.Lit[b] = R.Lit[b]; }
+      for (int q = 0; q < 4; ++q) ta.X0[q] = R.X0[q];
+      SRP_TRY(rtr_trial(ta, st));
+      SRP_HIP(hipMemcpyAsync(R.hdots, R.dots, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+      SRP_HIP(hipStreamSynchronize(st));
+    }
+    const double fplus = R.hdots[0];
+    const bool breakdown = R.hdots[1] != 0.0;
+    // near the solution both decreases fall to the rounding level of f: a
+    // shift of a few hundred ulps of |f| on both makes the ratio tend to 1
+    // there instead of to noise (the regularised ratio of Absil, Baker and
+    // Gallivan's trust-region code)
+    const double reg = 1e3 * 2.220446049250313e-16 * std::max(1.0, std::fabs(f));
+    const double rho = breakdown ? -1.0 : (f - fplus + reg) / (mdec + reg);
+    if (rho < 0.25) Delta *= 0.25;
+    else if (rho > 0.75 && boundary) Delta = std::min(2.0 * Delta, Dbar);
+    if (rho > rho_prime && !breakdown) {
+      // accept: Z <- (Z + eta) L^-T; Ks <- (Ks + B eta - lam eta) L^-T;
+      // Kc_b <- (Kc_b + Ceta_b) L_o^-T (o: the other block; FDA: itself)
+      SRP_TRY(lin(R.tmp, 1.0, B.U, 1.0, R.eta, nullptr));
+      SRP_TRY(lin(B.U, 0.0, nullptr, 1.0, R.tmp, R.Lit));
+      for (int b = 0; b < nb; ++b) {
+        RtrLinArgs la{};
+        la.k = k;
+        la.side[0] = RtrLinSide{R.tmp[b], B.Ks[b], 1.0, R.Beta[b], 1.0, nullptr, d[b]};
+        SRP_TRY(rtr_lin(la, 1, st));
+        la.side[0] = RtrLinSide{R.tmp[b], R.tmp[b], 1.0, R.eta[b], -P.lam[b], nullptr, d[b]};
+        SRP_TRY(rtr_lin(la, 1, st));
+      }
+      SRP_TRY(lin(B.Ks, 0.0, nullptr, 1.0, R.tmp, R.Lit));
+      SRP_TRY(lin(R.tmp, 1.0, B.Kc, 1.0, R.Ceta, nullptr));
+      double* Lo[2] = {R.Lit[nb == 2 ? 1 : 0], R.Lit[0]};
+      SRP_TRY(lin(B.Kc, 0.0, nullptr, 1.0, R.tmp, Lo));
+      ++accepted;
+      if (refresh_every > 0 && accepted % refresh_every == 0) {   // products from the data again
+        SRP_TRY(pass(B.U, R.Bd, B.Kc));
+        for (int b = 0; b < nb; ++b) {
+          RtrLinArgs la{};
+          la.k = k;
+          la.side[0] = RtrLinSide{B.Ks[b], R.Bd[b], 1.0, B.U[b], -P.lam[b], nullptr, d[b]};
+          SRP_TRY(rtr_lin(la, 1, st));
+        }
+      }
+    }
+  }
+  return SRP_OK;
+}
+
 // --------------------------------------------------------- CCA / FDA
 struct CommonArgs {
   int k;
@@ -724,6 +1015,48 @@ static int warm_lda(const RcgProblem& P, const WarmStart& w, double* const* out,
   return SRP_OK;
 }
 
+// The trust-region tail: qf_B of the start point (a data pass, step t = 1),
+// trust-region iterations to tol, then the finish of the CG tail (FP64
+// Rayleigh-Ritz rotation and sign convention from a pass along the point).
+static int rtr_tail(RcgProblem& full, RcgBuffers& B, const CommonArgs& ca, double* const* start,
+                    double* const* outW, double* sigma_out, srp_info* info, double ms_warm, int warm_iters,
+                    PhaseTimer& tm, hipStream_t st) {
+  const int k = full.k, nb = full.nb;
+  RcgResult r0;
+  SRP_TRY(rcg_run(full, B, start, 0, ca.tol, 1, 0, false, false, nullptr, r0, st));
+  if (r0.status == SRP_ENOTSPD) return SRP_ENOTSPD;
+  RtrState R{};
+  Arena a{B.rtr_ws, B.rtr_ws_bytes, 0};
+  SRP_TRY(rtr_take(R, a, nb, k, full.d));
+  SRP_HIP(hipHostMalloc((void**)&R.hdots, 16 * sizeof(double), hipHostMallocDefault));
+  struct Pinned { double* p; ~Pinned() { if (p) (void)hipHostFree(p); } } pin{R.hdots};
+  double mu_h[KMAX];
+  for (int i = 0; i < k; ++i) mu_h[i] = ca.opt.mu ? ca.opt.mu[i] : (double)(k - i);
+  RtrResult rr;
+  SRP_TRY(rtr_run(full, B, R, mu_h, ca.opt.max_iter, std::max(1, ca.opt.rtr_max_inner), ca.tol, ca.opt.refresh_every,
+                  rr, st));
+  for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
+  RcgResult rf;
+  const bool f64_finish = ca.opt.final_f64 != 0;
+  SRP_TRY(rcg_run(full, B, outW, 0, ca.tol, 1, 0, true, f64_finish, sigma_out, rf, st));
+  for (int s = 0; s < nb; ++s) SRP_TRY(copy_f64(outW[s], B.U[s], (int64_t)full.d[s] * k, st));
+  const double ms_iter = tm.lap_ms();
+  int status = rr.status;
+  if (rf.status == SRP_ENOTSPD) status = SRP_ENOTSPD;
+  if (info) {
+    info->status = status;
+    info->iterations = rr.outer;
+    info->inner_iterations = rr.inner;
+    info->warm_iterations = warm_iters;
+    info->passes = rr.passes + r0.passes + rf.passes;
+    info->f = rf.f;
+    info->grad_norm = rr.gg > 0 ? std::sqrt(rr.gg) : 0.0;
+    info->ms_warm = ms_warm;
+    info->ms_iterate = ms_iter;
+  }
+  return status;
+}
+
 // Shared tail of both solvers once the data, sketches and metric exist.
 static int solve_tail(RcgProblem& full, const WarmStart& warm, RcgBuffers& B, const CommonArgs& ca,
                       double* const* outW, double* sigma_out, srp_info* info, PhaseTimer& tm, hipStream_t st) {
@@ -795,6 +1128,8 @@ static int solve_tail(RcgProblem& full, const WarmStart& warm, RcgBuffers& B, co
     lowp_iters = rl.iterations;
     ms_lowp = tm.lap_ms();
   }
+  if (ca.opt.method == SRP_RTR) return rtr_tail(full, B, ca, start, outW, sigma_out, info, ms_warm, warm_iters,
+                                                 tm, st);
   RcgResult r;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   B.time_passes = ca.opt.time_passes != 0;
@@ -871,6 +1206,8 @@ static int check_options(const srp_options& o) {
   SRP_REQUIRE(o.max_iter >= 0 && o.warm_start_iters >= 0 && o.refresh_every >= 0, "negative iteration option");
   SRP_REQUIRE(o.pass_compute == SRP_F64 || o.pass_compute == SRP_F32 || o.pass_compute == -1,
               "pass_compute must be SRP_F64 or SRP_F32");
+  SRP_REQUIRE(o.method == SRP_RCG || o.method == SRP_RTR, "unknown method %d", o.method);
+  SRP_REQUIRE(o.method == SRP_RCG || o.lowp_x == nullptr, "the trust-region method has no BF16 phase");
   return SRP_OK;
 }
 
@@ -1114,6 +1451,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   SRP_REQUIRE(n >= 2 && n < (int64_t(1) << 31), "n out of range");
   SRP_REQUIRE(c >= 2 && c <= kLdaMaxClasses && d >= 1, "need 2 <= n_classes <= %d and d >= 1", kLdaMaxClasses);
   SRP_REQUIRE(k >= 1 && k <= std::min(c - 1, d) && k <= KMAX, "need 1 <= k <= min(c-1, d), k <= 32");
+  SRP_REQUIRE(opt.method != SRP_RTR || k <= kRtrK, "the trust-region method needs k <= %d", kRtrK);
   SRP_REQUIRE(s >= d, "sketch_size must be >= d");
   SRP_REQUIRE(lam >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
   int compute = opt.pass_compute == -1 ? (dtype == SRP_F64 ? SRP_F64 : SRP_F32) : opt.pass_compute;

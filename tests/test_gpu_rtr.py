@@ -1,0 +1,106 @@
+"""The Riemannian trust-region method (method = SRP_RTR) through the C ABI
+against the FP64 oracle's closed forms.  Its Hessian-vector products are
+Table 1's formula (Eq. HessCCA / Eq. LDAhess) on the fused data pass; the
+fixed point is the same exact solution as the CG method's (the method is
+Las Vegas: every Riemannian algorithm converging to the optimum returns the
+closed form)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, metrics
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda"
+
+
+def _srp():
+    import paper_2106_12060_amd as srp
+    return srp
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def test_rtr_cca_f64_small_workload():
+    srp = _srp()
+    wl = synth.workload("cca-f64-small")
+    X, Y = wl.generate()
+    lam = wl.lam_value
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    opt = srp.srp_default_options(method="rtr", max_iter=200)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), wl.k, lam, lam, wl.s, tol=1e-12, options=opt)
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    err = metrics.cca_rel_objective_error(Uh, Vh, X, Y, lam, lam, sig_true)
+    cons = max(metrics.constraint_residual(Uh, X, lam), metrics.constraint_residual(Vh, Y, lam))
+    print("rtr f64", info, err, cons)
+    assert info["status"] == 0
+    assert info["inner_iterations"] >= info["iterations"] >= 1
+    assert err < 1e-10 and cons < 1e-12
+    np.testing.assert_allclose(sig.cpu().numpy(), sig_true[:wl.k], rtol=0, atol=1e-8)
+
+
+@pytest.mark.parametrize("sketch", ["srht", "countsketch"])
+def test_rtr_cca_f32_scaled_workload(sketch):
+    import dataclasses
+    srp = _srp()
+    wl = dataclasses.replace(synth.workload("cca-f32-srht").scaled(n=30_000, dx=200, dy=160, s=800), r=10,
+                             noise=0.1, factor_decades=0.0)
+    X, Y = wl.generate()
+    lam = wl.lam_value
+    sig_true, _, _ = direct.cca_direct(X, Y, lam, lam)
+    opt = srp.srp_default_options(sketch=sketch, method="rtr", max_iter=100)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), wl.k, lam, lam, wl.s, tol=1e-5, options=opt)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    err = metrics.cca_rel_objective_error(Uh, Vh, X64, Y64, lam, lam, sig_true)
+    cons = max(metrics.constraint_residual(Uh, X64, lam), metrics.constraint_residual(Vh, Y64, lam))
+    print("rtr f32", sketch, info, err, cons)
+    assert err < 1e-6 and cons < 1e-6
+
+
+def test_rtr_cca_planted_vectors_and_weighted_cost():
+    """Distinct planted correlations, lambda = 0, N = diag(k..1) (the
+    weighted cost whose minimiser is the ordered vectors themselves)."""
+    srp = _srp()
+    rho = np.array([0.95, 0.85, 0.7, 0.5, 0.3, 0.1])
+    X, Y, A, B = synth.planted_cca(4000, 6, rho, seed=5)
+    k = 4
+    opt = srp.srp_default_options(method="rtr", max_iter=200)
+    U, V, sig, info = srp.cca_solve(dev(X), dev(Y), k, 0.0, 0.0, 24, tol=1e-12, options=opt)
+    print("rtr planted", info)
+    np.testing.assert_allclose(sig.cpu().numpy(), rho[:k], atol=1e-9)
+    Uh = U.cpu().numpy()
+    Ai = np.linalg.inv(A)
+    for i in range(k):
+        j = np.argmax(np.abs(Ai[:, i]))
+        np.testing.assert_allclose(Uh[:, i], np.sign(Ai[j, i]) * Ai[:, i], atol=3e-7 * np.abs(Ai).max())
+
+
+def test_rtr_lda_scaled_workload():
+    srp = _srp()
+    wl = synth.workload("lda-f32")
+    n, d, c, k = 19_992, 200, 12, 11
+    X, y = synth.lda_classes(n, d, c, seed=wl.seed, dtype=np.float32)
+    lam = synth.lda_population_lambda(n, d)
+    rho_true, _ = direct.lda_direct(X, y, c, lam, k=k)
+    opt = srp.srp_default_options(method="rtr", max_iter=200, final_f64=-1)
+    W, rho, info = srp.lda_solve(dev(X), dev(y), c, k, lam, 800, tol=1e-7, options=opt)
+    _, _, _, Xh, Yh = direct.lda_scatter(X, y, c)
+    err = metrics.lda_rel_objective_error(W.cpu().numpy(), Xh, Yh, lam, rho_true)
+    cons = metrics.constraint_residual(W.cpu().numpy(), Xh, lam)
+    print("rtr lda", info, err, cons)
+    assert err < 1e-6 and cons < 1e-6
+    np.testing.assert_allclose(rho.cpu().numpy(), rho_true[:k], rtol=1e-5)
+
+
+def test_rtr_rejects_large_k_and_bf16_phase():
+    srp = _srp()
+    X = torch.zeros((400, 40), dtype=torch.float32, device=DEV)
+    y = (torch.arange(400, device=DEV) % 40).to(torch.int32)
+    with pytest.raises(srp.SrpError) as e:
+        srp.lda_solve(X, y, 40, 20, 0.1, 80, options=srp.srp_default_options(method="rtr"))
+    assert e.value.code == srp.SRP_EINVAL
