@@ -303,6 +303,63 @@ int lda_solve(const void* X, const int32_t* labels, int64_t n, int d,
               double tol, int dtype, const srp_options* opt, void* stream,
               double* W, double* rho, srp_info* info);
 
+/* ---- sparse (CSR) data ----------------------------------------------
+ * The paper states its costs in terms of nnz(X) and nnz(Y) (Section 3,
+ * Table costs; the cost remarks of Sections 4.5 and 5.5): with the
+ * CountSketch the preprocessing is O(nnz) and every data product is
+ * O(nnz k).  These entry points take X (and Y) in CSR form.
+ *
+ * srp_csr: device arrays owned by the caller, unchanged until the call
+ * returns.  row_ptr (int64, n_rows + 1, row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n_rows] = nnz); col_idx (int32, nnz; in [0, n_cols) and strictly
+ * increasing within each row: sorted, no duplicates); values (nnz, dtype
+ * SRP_F32 or SRP_F64).  Limits: 1 <= n_rows < 2^31, 1 <= n_cols <= 8192,
+ * nnz < 2^31.  Every entry point checks the structure on the device first
+ * and returns SRP_EINVAL for a malformed matrix.  All arithmetic on the
+ * data is FP64 (the F32 values are widened).  The library builds a
+ * column-major copy of each matrix for the products A^T P (nnz index and
+ * value words, from its workspace).
+ */
+typedef struct srp_csr {
+  int64_t n_rows;
+  int n_cols;
+  int dtype;
+  int64_t nnz;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const void* values;
+} srp_csr;
+
+/* CountSketch (Section 3) of a CSR matrix: out (s x n_cols, double,
+ * row-major) = S A with the h, g of srp_countsketch for `seed`; each
+ * bucket's rows are summed in ascending row order, as srp_countsketch sums
+ * the dense rows (zero entries add nothing).  O(nnz + n + s n_cols).
+ * Errors: SRP_EINVAL for bad sizes or a malformed matrix. */
+int srp_countsketch_csr(const srp_csr* A, int s, uint64_t seed, double* out, void* stream);
+
+/* The data pass of srp_gram_pass for CSR blocks, FP64 arithmetic:
+ * J0 = A0^T [A0 W0 | A1 W1] (n_cols0 x 2k), J1 = A1^T [A0 W0 | A1 W1]
+ * (with A1 == NULL: J0 = A0^T A0 W0, n_cols0 x k).  The sums over a row
+ * take its entries in column order, those over a column take its rows in
+ * ascending order.  Requires (blocks x k) <= 64 and equal row counts.
+ * O(nnz k). */
+int srp_gram_pass_csr(const srp_csr* A0, const srp_csr* A1, int k, const double* W0, const double* W1,
+                      double* J0, double* J1, void* stream);
+
+/* cca_solve and lda_solve for CSR data (same outputs, conventions and
+ * limits otherwise).  The sketch must be SRP_COUNTSKETCH (an SRHT mixes
+ * every row, which is not O(nnz)), and the staged-sketch and BF16-phase
+ * options are not available (SRP_EINVAL).  lda_solve_csr never forms the
+ * centred Xhat: Xhat W = X W - (C W)[labels] row by row (C the class
+ * means), Xhat^T (Xhat W) = X^T (Xhat W) since the class sums of Xhat's
+ * rows vanish, and S Xhat = S X - (S E) C for the one-hot labels E. */
+int cca_solve_csr(const srp_csr* X, const srp_csr* Y, int k, double lambda_x, double lambda_y,
+                  int sketch_size, double tol, const srp_options* opt, void* stream, double* U,
+                  double* V, double* sigma, srp_info* info);
+int lda_solve_csr(const srp_csr* X, const int32_t* labels, int n_classes, int k, double lambda,
+                  int sketch_size, double tol, const srp_options* opt, void* stream, double* W,
+                  double* rho, srp_info* info);
+
 /* Device workspace, in bytes, that one cca_solve / lda_solve with these
  * sizes allocates (sketches, R^-1 and M^-1, iterate and product buffers,
  * pass partials).  sketch_input_dtype: the dtype the sketch reads (the data

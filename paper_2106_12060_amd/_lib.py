@@ -77,6 +77,12 @@ class SrpResult(ctypes.Structure):
         return d
 
 
+class SrpCsr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p),
+                ("values", ctypes.c_void_p)]
+
+
 class SrpError(RuntimeError):
     def __init__(self, fn, code, msg):
         super().__init__(f"{fn} failed: {STATUS_NAMES.get(code, code)} ({msg})")
@@ -118,6 +124,15 @@ _SIGS = {
     "srp_gram_pass_kernel": (ctypes.c_char_p, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "srp_gram_pass": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P]),
+    "srp_countsketch_csr": (ctypes.c_int, [ctypes.POINTER(SrpCsr), ctypes.c_int, ctypes.c_uint64, _P, _P]),
+    "srp_gram_pass_csr": (ctypes.c_int, [ctypes.POINTER(SrpCsr), ctypes.POINTER(SrpCsr), ctypes.c_int, _P, _P,
+                                         _P, _P, _P]),
+    "cca_solve_csr": (ctypes.c_int, [ctypes.POINTER(SrpCsr), ctypes.POINTER(SrpCsr), ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                     ctypes.POINTER(SrpOptions), _P, _P, _P, _P, ctypes.POINTER(SrpInfo)]),
+    "lda_solve_csr": (ctypes.c_int, [ctypes.POINTER(SrpCsr), _P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_double, ctypes.POINTER(SrpOptions), _P, _P, _P,
+                                     ctypes.POINTER(SrpInfo)]),
     "cca_solve": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_int, ctypes.POINTER(SrpOptions), _P, _P, _P, _P,
@@ -344,6 +359,98 @@ def lda_solve(X, labels, n_classes, k, lam, sketch_size, tol=1e-6, options: SrpO
                          ctypes.byref(opt), _stream(), _ptr(W), _ptr(rho), ctypes.byref(info))
     if rc != SRP_OK and not (rc == SRP_ENOCONV and not raise_on_noconv):
         _check("lda_solve", rc)
+    return W, rho, info.as_dict()
+
+
+# ------------------------------------------------------------ CSR data
+class Csr:
+    """A CSR matrix on the HIP device: row_ptr (int64, n + 1), col_idx
+    (int32, strictly increasing within each row), values (float32 or
+    float64) and the column count.  The tensors must stay alive while a
+    call that takes the matrix runs."""
+
+    def __init__(self, row_ptr, col_idx, values, n_cols):
+        _need_cuda(row_ptr, col_idx, values)
+        if row_ptr.dtype != torch.int64 or col_idx.dtype != torch.int32:
+            raise TypeError("row_ptr must be int64 and col_idx int32")
+        if values.dtype not in (torch.float32, torch.float64):
+            raise TypeError("values must be float32 or float64")
+        self.row_ptr, self.col_idx, self.values = row_ptr, col_idx, values
+        self.shape = (row_ptr.numel() - 1, int(n_cols))
+
+    @classmethod
+    def from_torch(cls, A):
+        """From a torch sparse CSR tensor (indices are converted)."""
+        return cls(A.crow_indices().to(torch.int64).contiguous(), A.col_indices().to(torch.int32).contiguous(),
+                   A.values().contiguous(), A.shape[1])
+
+    def struct(self) -> SrpCsr:
+        return SrpCsr(self.shape[0], self.shape[1], _dtype(self.values), self.values.numel(),
+                      self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.values.data_ptr())
+
+
+def srp_countsketch_csr(A: Csr, s: int, seed: int) -> torch.Tensor:
+    out = torch.empty((s, A.shape[1]), dtype=torch.float64, device=A.values.device)
+    a = A.struct()
+    _check("srp_countsketch_csr", lib().srp_countsketch_csr(ctypes.byref(a), s, seed, _ptr(out), _stream()))
+    return out
+
+
+def srp_gram_pass_csr(A0: Csr, W0, A1: Csr | None = None, W1=None):
+    _need_cuda(W0, W1)
+    k = W0.shape[1]
+    nb = 2 if A1 is not None else 1
+    dev = A0.values.device
+    J0 = torch.empty((A0.shape[1], nb * k), dtype=torch.float64, device=dev)
+    J1 = torch.empty((A1.shape[1], nb * k), dtype=torch.float64, device=dev) if A1 is not None else None
+    a0 = A0.struct()
+    a1 = A1.struct() if A1 is not None else None
+    _check("srp_gram_pass_csr", lib().srp_gram_pass_csr(ctypes.byref(a0), ctypes.byref(a1) if a1 else None, k,
+                                                        _ptr(W0), _ptr(W1), _ptr(J0), _ptr(J1), _stream()))
+    return J0, J1
+
+
+def cca_solve_csr(X: Csr, Y: Csr, k, lambda_x, lambda_y, sketch_size, tol=1e-6,
+                  options: SrpOptions | None = None, mu=None, raise_on_noconv: bool = False):
+    """cca_solve for CSR data.  Returns (U, V, sigma, info_dict)."""
+    opt = options if options is not None else srp_default_options()
+    mu_buf = None
+    if mu is not None:
+        mu_buf = (ctypes.c_double * k)(*[float(m) for m in mu])
+        opt.mu = ctypes.cast(mu_buf, ctypes.POINTER(ctypes.c_double))
+    dev = X.values.device
+    U = torch.empty((X.shape[1], k), dtype=torch.float64, device=dev)
+    V = torch.empty((Y.shape[1], k), dtype=torch.float64, device=dev)
+    sigma = torch.empty(k, dtype=torch.float64, device=dev)
+    info = SrpInfo()
+    x, y = X.struct(), Y.struct()
+    rc = lib().cca_solve_csr(ctypes.byref(x), ctypes.byref(y), k, lambda_x, lambda_y, sketch_size, tol,
+                             ctypes.byref(opt), _stream(), _ptr(U), _ptr(V), _ptr(sigma), ctypes.byref(info))
+    if rc != SRP_OK and not (rc == SRP_ENOCONV and not raise_on_noconv):
+        _check("cca_solve_csr", rc)
+    return U, V, sigma, info.as_dict()
+
+
+def lda_solve_csr(X: Csr, labels, n_classes, k, lam, sketch_size, tol=1e-6, options: SrpOptions | None = None,
+                  mu=None, raise_on_noconv: bool = False):
+    """lda_solve for CSR data.  Returns (W, rho, info_dict)."""
+    _need_cuda(labels)
+    if labels.dtype != torch.int32:
+        raise TypeError("labels must be int32")
+    opt = options if options is not None else srp_default_options()
+    mu_buf = None
+    if mu is not None:
+        mu_buf = (ctypes.c_double * k)(*[float(m) for m in mu])
+        opt.mu = ctypes.cast(mu_buf, ctypes.POINTER(ctypes.c_double))
+    dev = X.values.device
+    W = torch.empty((X.shape[1], k), dtype=torch.float64, device=dev)
+    rho = torch.empty(k, dtype=torch.float64, device=dev)
+    info = SrpInfo()
+    x = X.struct()
+    rc = lib().lda_solve_csr(ctypes.byref(x), _ptr(labels), n_classes, k, lam, sketch_size, tol,
+                             ctypes.byref(opt), _stream(), _ptr(W), _ptr(rho), ctypes.byref(info))
+    if rc != SRP_OK and not (rc == SRP_ENOCONV and not raise_on_noconv):
+        _check("lda_solve_csr", rc)
     return W, rho, info.as_dict()
 
 

@@ -19,7 +19,8 @@ LIB = os.path.join(HERE, "libsrp.so")
 ARCH = os.environ.get("SRP_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["sketch.hip", "factor.hip", "pass.hip", "solver_kernels.hip", "lda.hip",
-           "stage.hip", "driver.hip", "api.cpp", "engine.cpp", "noalloc.hip", "rtr_kernels.hip"]
+           "stage.hip", "driver.hip", "api.cpp", "engine.cpp", "noalloc.hip", "rtr_kernels.hip",
+           "sparse.hip"]
 
 COMMON_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

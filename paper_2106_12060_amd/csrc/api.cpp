@@ -27,6 +27,18 @@ int finish(hipStream_t st) {
   SRP_HIP(hipStreamSynchronize(st));
   return SRP_OK;
 }
+
+CsrView csr_view(const srp_csr& a) {
+  CsrView v;
+  v.n = a.n_rows;
+  v.d = a.n_cols;
+  v.nnz = a.nnz;
+  v.ptr = a.row_ptr;
+  v.idx = a.col_idx;
+  v.val = a.values;
+  v.dtype = a.dtype;
+  return v;
+}
 }  // namespace
 
 extern "C" {
@@ -194,6 +206,66 @@ int srp_gram_pass(const void* A0, const void* A1, int dtype, int compute, int64_
   return finish(st);
 }
 
+int srp_countsketch_csr(const srp_csr* A, int s, uint64_t seed, double* out, void* stream) {
+  clear_error();
+  SRP_REQUIRE(A && out, "null pointer argument");
+  SRP_REQUIRE(s >= 1, "bad sizes");
+  hipStream_t st = (hipStream_t)stream;
+  const CsrView v = csr_view(*A);
+  Scratch ws(st);
+  const size_t bytes = countsketch_csr_ws_bytes(std::max<int64_t>(v.n, 1), s) + bytes_of<int>(4) + 1024;
+  SRP_TRY(device_alloc(&ws.p, bytes, st));
+  Arena ar{(char*)ws.p, bytes, 0};
+  int* bad = ar.take<int>(4);
+  SRP_TRY(csr_check(v, "A", bad, st));
+  SRP_TRY(countsketch_csr_run(v, s, seed, out, nullptr, 0, nullptr, ar, st));
+  return finish(st);
+}
+
+int srp_gram_pass_csr(const srp_csr* A0, const srp_csr* A1, int k, const double* W0, const double* W1, double* J0,
+                      double* J1, void* stream) {
+  clear_error();
+  SRP_REQUIRE(A0 && W0 && J0, "null pointer argument");
+  SRP_REQUIRE(!A1 || (W1 && J1), "second block needs W1 and J1");
+  const int nb = A1 ? 2 : 1;
+  SRP_REQUIRE(k >= 1 && nb * k <= 64, "need 1 <= k and (blocks x k) <= 64");
+  hipStream_t st = (hipStream_t)stream;
+  CsrView v[2] = {csr_view(*A0), A1 ? csr_view(*A1) : CsrView{}};
+  SRP_REQUIRE(!A1 || v[1].n == v[0].n, "A0 and A1 must have the same number of rows");
+  const int ldp = nb * k;
+  Scratch ws(st);
+  size_t bytes = bytes_of<int>(4) + bytes_of<double>((size_t)std::max<int64_t>(v[0].n, 1) * ldp) + 2048;
+  size_t scr = 0;
+  for (int b = 0; b < nb; ++b) {
+    SRP_REQUIRE(v[b].n >= 1 && v[b].d >= 1, "bad sizes");
+    bytes += csc_bytes(v[b]) + csc_partial_bytes(v[b], ldp);
+    scr = std::max(scr, csc_scratch_bytes(v[b]));
+  }
+  bytes += scr;
+  SRP_TRY(device_alloc(&ws.p, bytes, st));
+  Arena ar{(char*)ws.p, bytes, 0};
+  int* bad = ar.take<int>(4);
+  SRP_TRY(csr_check(v[0], "A0", bad, st));
+  if (A1) SRP_TRY(csr_check(v[1], "A1", bad, st));
+  double* P = ar.take<double>((size_t)v[0].n * ldp);
+  CscView c[2];
+  char* sbase = ar.base + ar.used;
+  ar.used += (scr + 255) & ~size_t(255);
+  double* part[2] = {nullptr, nullptr};
+  for (int b = 0; b < nb; ++b) {
+    Arena t{sbase, scr, 0};
+    SRP_TRY(csc_build(v[b], &c[b], ar, t, st));
+    part[b] = (double*)ar.take<char>(csc_partial_bytes(v[b], ldp));
+    if (!part[b]) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+  }
+  const double* Wb[2] = {W0, W1};
+  double* Jb[2] = {J0, J1};
+  for (int b = 0; b < nb; ++b)
+    SRP_TRY(csr_times_dense(v[b], Wb[b], k, k, P + b * k, ldp, nullptr, nullptr, nullptr, st));
+  for (int b = 0; b < nb; ++b) SRP_TRY(csc_times_dense(c[b], P, ldp, ldp, Jb[b], ldp, part[b], nullptr, st));
+  return finish(st);
+}
+
 const char* srp_gram_pass_kernel(int dtype, int compute, int d0, int d1, int k) {
   return gram_pass_kernel_name(dtype, compute, d0, d1, k);
 }
@@ -210,6 +282,23 @@ int lda_solve(const void* X, const int32_t* labels, int64_t n, int d, int n_clas
               srp_info* info) {
   return lda_solve_impl(X, labels, n, d, n_classes, k, lambda, sketch_size, tol, dtype, opt, (hipStream_t)stream, W,
                         rho, info);
+}
+
+int cca_solve_csr(const srp_csr* X, const srp_csr* Y, int k, double lambda_x, double lambda_y, int sketch_size,
+                  double tol, const srp_options* opt, void* stream, double* U, double* V, double* sigma,
+                  srp_info* info) {
+  clear_error();
+  SRP_REQUIRE(X && Y, "null pointer argument");
+  return cca_solve_csr_impl(csr_view(*X), csr_view(*Y), k, lambda_x, lambda_y, sketch_size, tol, opt,
+                            (hipStream_t)stream, U, V, sigma, info);
+}
+
+int lda_solve_csr(const srp_csr* X, const int32_t* labels, int n_classes, int k, double lambda, int sketch_size,
+                  double tol, const srp_options* opt, void* stream, double* W, double* rho, srp_info* info) {
+  clear_error();
+  SRP_REQUIRE(X, "null pointer argument");
+  return lda_solve_csr_impl(csr_view(*X), labels, n_classes, k, lambda, sketch_size, tol, opt, (hipStream_t)stream, W,
+                            rho, info);
 }
 
 }  // extern "C"

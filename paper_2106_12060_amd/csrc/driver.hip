@@ -181,6 +181,18 @@ struct RcgProblem {
   const double* Minv[2] = {nullptr, nullptr};
   const double* Yhat = nullptr;  // FDA: c x d rows sqrt(n_j)(m_j - m); S_B = Yhat^T Yhat
   int c = 0;
+  const struct SparseData* sp = nullptr;   // CSR data (A unused): products in FP64 from the sparse forms
+};
+
+// Sparse data of a solve: the CSR views and their CSC copies; FDA adds the
+// labels and the class means, whose products give the centred ones.
+struct SparseData {
+  CsrView csr[2];
+  CscView csc[2];
+  const int32_t* labels = nullptr;
+  const double* means = nullptr;   // c x d class means
+  double* T = nullptr;             // c x k: means W
+  double* partial[2] = {nullptr, nullptr};   // per-segment partials of A_b^T P
 };
 
 struct RcgBuffers {
@@ -375,10 +387,48 @@ static int twopass_f64(const RcgProblem& P, RcgBuffers& B, double* const* W, hip
   return SRP_OK;
 }
 
+// Products of CSR data, FP64: P_b = A_b W_b (n x k each, side by side in
+// B.Pn), then J_b = A_b^T [P_0 | P_1] from the CSC copies.  FDA: the rows
+// of Xhat = X - E C (E the one-hot labels, C the class means) give
+// Xhat W = X W - (C W)[labels] per row, and Xhat^T (Xhat W) = X^T (Xhat W)
+// because the class sums of the rows of Xhat vanish (E^T Xhat = 0): the
+// centred products cost nnz(X) k + c d k, without an n x d Xhat.
+static int sparse_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, const int* done, hipStream_t st) {
+  const SparseData& S = *P.sp;
+  const int k = P.k, nb = P.nb, ldp = nb * k;
+  for (int b = 0; b < nb; ++b) {
+    const double* sub = nullptr;
+    if (S.labels) {
+      SRP_TRY(gemm_skinny_f64(P.c, P.d[0], k, S.means, P.d[0], false, W[0], k, S.T, k, B.skw, B.skw_bytes, st));
+      sub = S.T;
+    }
+    SRP_TRY(csr_times_dense(S.csr[b], W[b], k, k, B.Pn + b * k, ldp, sub, S.labels, done, st));
+  }
+  for (int b = 0; b < nb; ++b)
+    SRP_TRY(csc_times_dense(S.csc[b], B.Pn, ldp, ldp, B.J[b], ldp, S.partial[b], done, st));
+  return SRP_OK;
+}
+
 // Data products along directions W (d_b x k): fills J (and FDA's S_B W).
 static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int compute, const int* done,
                      hipStream_t st) {
-  if (compute == SRP_F64 && !pass_limits_ok(P.dtype, SRP_F64, P.d[0], P.d[1], P.k, P.nb)) {
+  if (P.sp) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (B.time_passes && B.events) {
+      SRP_HIP(hipEventCreate(&e0));
+      SRP_HIP(hipEventCreate(&e1));
+      SRP_HIP(hipEventRecord(e0, st));
+    }
+    SRP_TRY(sparse_pass(P, B, W, done, st));
+    if (e0) {
+      SRP_HIP(hipEventRecord(e1, st));
+      B.events->push_back({e0, e1});
+      if (B.ran) {
+        hipLaunchKernelGGL(k_count_pass, dim3(1), dim3(1), 0, st, done, B.ran);
+        SRP_LAUNCH_CHECK();
+      }
+    }
+  } else if (compute == SRP_F64 && !pass_limits_ok(P.dtype, SRP_F64, P.d[0], P.d[1], P.k, P.nb)) {
     SRP_TRY(twopass_f64(P, B, W, st));
   } else {
     Arena pw{B.pass_ws, B.pass_ws_bytes, 0};
@@ -1542,6 +1592,299 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
       for (int i = 0; i < k; ++i) sum += hs[i];
     info->objective = sum;
   }
+  if (rc == SRP_ENOCONV) set_error("max_iter reached before the gradient tolerance");
+  return rc;
+}
+
+// ------------------------------------------------------- CSR inputs
+// The sparse forms of Algorithms CCAopt and LDAopt: the CountSketch reads
+// nnz entries (an SRHT would mix every row: it is not offered), the data
+// products are the O(nnz k) sparse-times-skinny products, and the rest of
+// the solve (factor, warm start, iteration, finish) is the dense one.  All
+// data arithmetic is FP64.
+static int csr_common_checks(const srp_options& opt) {
+  SRP_REQUIRE(opt.sketch == SRP_COUNTSKETCH, "CSR input takes the CountSketch (an SRHT touches every row)");
+  SRP_REQUIRE(!opt.sketch_x && !opt.lowp_x, "CSR input has no staged sketch input or BF16 phase");
+  return SRP_OK;
+}
+
+static size_t csr_scratch(const CsrView* A, int nv, int s, int k, int c) {
+  size_t m = 0;
+  int dd[2] = {A[0].d, nv == 2 ? A[1].d : 0};
+  for (int b = 0; b < nv; ++b)
+    m = std::max({m, csc_scratch_bytes(A[b]), countsketch_csr_ws_bytes(A[b].n, s), factor_ws_bytes(s, A[b].d)});
+  m = std::max(m, warm_ws_bytes(nv, k, dd, c));
+  if (nv == 2) m = std::max(m, bytes_of<double>((size_t)dd[0] * dd[1]));
+  return m + 4096;
+}
+
+size_t cca_csr_ws_bytes(const CsrView& X, const CsrView& Y, int k, int s) {
+  const int dx = X.d, dy = Y.d, dm = std::max(dx, dy);
+  const int dd[2] = {dx, dy};
+  const CsrView v[2] = {X, Y};
+  size_t b = bytes_of<double>((size_t)s * dx) + bytes_of<double>((size_t)s * dy);
+  b += 2 * bytes_of<double>((size_t)dx * dx) + 2 * bytes_of<double>((size_t)dy * dy);   // R, M^-1
+  b += 2 * bytes_of<double>((size_t)dm * dm) + bytes_of<int>(4) + bytes_of<double>((size_t)dx * dy);
+  b += csc_bytes(X) + csc_bytes(Y) + csc_partial_bytes(X, 2 * k) + csc_partial_bytes(Y, 2 * k);
+  b += rcg_buffers_bytes(2, k, std::max<int64_t>(X.n, s), dd, SRP_F64);
+  return b + csr_scratch(v, 2, s, k, 0) + 4096;
+}
+
+size_t lda_csr_ws_bytes(const CsrView& X, int c, int k, int s) {
+  const int d = X.d;
+  const int dd[2] = {d, 0};
+  size_t b = bytes_of<double>((size_t)s * d) + bytes_of<double>((size_t)s * c);
+  b += 3 * bytes_of<double>((size_t)d * d) + 3 * bytes_of<double>((size_t)c * d) + bytes_of<double>((size_t)c * k);
+  b += bytes_of<int>(c) + bytes_of<int>(4) + csc_bytes(X) + csc_partial_bytes(X, k);
+  b += rcg_buffers_bytes(1, k, std::max<int64_t>(X.n, s), dd, SRP_F64, c);
+  return b + csr_scratch(&X, 1, s, k, c) + 4096;
+}
+
+static void finish_info(srp_info* info, int rc, const double* vals, int k) {
+  if (!info) return;
+  info->status = rc;
+  info->ms_total = info->ms_sketch + info->ms_factor + info->ms_warm + info->ms_iterate;
+  double sum = 0.0, hs[KMAX];
+  if (hipMemcpy(hs, vals, sizeof(double) * k, hipMemcpyDeviceToHost) == hipSuccess)
+    for (int i = 0; i < k; ++i) sum += hs[i];
+  info->objective = sum;
+}
+
+int cca_solve_csr_impl(const CsrView& X, const CsrView& Y, int k, double lx, double ly, int s, double tol,
+                       const srp_options* optp, hipStream_t st, double* U, double* V, double* sigma, srp_info* info,
+                       const SolveCtx* ctx) {
+  clear_error();
+  srp_options opt;
+  srp_default_options(&opt);
+  if (optp) opt = *optp;
+  SRP_TRY(check_options(opt));
+  SRP_TRY(csr_common_checks(opt));
+  SRP_REQUIRE(U && V && sigma, "null pointer argument");
+  SRP_REQUIRE(X.n == Y.n, "X and Y must have the same number of rows");
+  const int64_t n = X.n;
+  const int dx = X.d, dy = Y.d;
+  SRP_REQUIRE(k >= 1 && k <= std::min(dx, dy) && k <= 16, "need 1 <= k <= min(dx, dy), k <= 16");
+  SRP_REQUIRE(s >= std::max(dx, dy), "sketch_size must be >= max(dx, dy)");
+  SRP_REQUIRE(lx >= 0.0 && ly >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
+  PhaseTimer tm(st);
+  const size_t bytes = cca_csr_ws_bytes(X, Y, k, s);
+  const CsrView views[2] = {X, Y};
+  const size_t scr = csr_scratch(views, 2, s, k, 0);
+  Workspace W;
+  void* wbase = nullptr;
+  SRP_TRY(take_workspace(W, bytes, ctx, st, &wbase));
+  Arena ar{(char*)wbase, bytes, 0};
+  int* flag = ar.take<int>(4);
+  SRP_TRY(csr_check(X, "X", flag, st));
+  SRP_TRY(csr_check(Y, "Y", flag, st));
+  const int dd[2] = {dx, dy}, dm = std::max(dx, dy);
+  double* SX = ar.take<double>((size_t)s * dx);
+  double* SY = ar.take<double>((size_t)s * dy);
+  double* Rx = ar.take<double>((size_t)dx * dx);
+  double* Ry = ar.take<double>((size_t)dy * dy);
+  double* Mx = ar.take<double>((size_t)dx * dx);
+  double* My = ar.take<double>((size_t)dy * dy);
+  double* Rinv = ar.take<double>((size_t)dm * dm);
+  double* Rinv2 = ar.take<double>((size_t)dm * dm);
+  double* Hxy = ar.take<double>((size_t)dx * dy);
+  SparseData sd;
+  sd.csr[0] = X;
+  sd.csr[1] = Y;
+  RcgBuffers B{};
+  if (!Hxy || rcg_buffers_take(B, ar, 2, k, std::max<int64_t>(n, s), dd) != SRP_OK) {
+    set_error("workspace layout overflow");
+    return SRP_ENOMEM;
+  }
+  SRP_TRY(setup_mu(opt, k, B.mu, st));
+  if (ar.used + scr > ar.cap) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+  Arena keep{ar.base + ar.used, ar.cap - ar.used - scr, 0};
+  char* scratch_base = ar.base + ar.cap - scr;
+  // CSC copies, sketches (one S for both views) and metric factors; the
+  // steps share one scratch area in stream order
+  for (int b = 0; b < 2; ++b) {
+    Arena t{scratch_base, scr, 0};
+    SRP_TRY(csc_build(views[b], &sd.csc[b], keep, t, st));
+    sd.partial[b] = (double*)keep.take<char>(csc_partial_bytes(views[b], 2 * k));
+  }
+  if (!sd.partial[1]) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+  SRP_TRY(fill_i32(flag, 1, 0, st));
+  for (int b = 0; b < 2; ++b) {
+    Arena t{scratch_base, scr, 0};
+    SRP_TRY(countsketch_csr_run(views[b], s, opt.seed, b ? SY : SX, nullptr, 0, nullptr, t, st));
+  }
+  const double ms_sketch = tm.lap_ms();
+  {
+    Arena t{scratch_base, scr, 0};
+    SRP_TRY(sketch_factor_run(SX, SRP_F64, s, dx, lx, Rx, Rinv, Mx, flag, t, st));
+  }
+  {
+    Arena t{scratch_base, scr, 0};
+    SRP_TRY(sketch_factor_run(SY, SRP_F64, s, dy, ly, Ry, Rinv2, My, flag, t, st));
+  }
+  const bool warm = opt.warm_start_iters > 0;
+  if (warm) {
+    const int64_t cnt = (int64_t)dx * dy;
+    int ks = gram_split(s, dx, dy);
+    ks = (int)std::max<int64_t>(1, std::min<int64_t>(ks, (int64_t)(scr / bytes_of<double>((size_t)cnt))));
+    double* parts = (double*)scratch_base;
+    GemmArgs g{};
+    g.m = dx; g.n = dy; g.kk = s; g.alpha = 1.0; g.beta = 0.0;
+    g.A = SX; g.lda = dx; g.ta = true; g.a_f32 = false;
+    g.B = SY; g.ldb = dy; g.tb = false; g.b_f32 = false;
+    g.C = parts; g.ldc = dy; g.ksplit = ks; g.c_split_stride = cnt;
+    SRP_TRY(gemm_f64(g, st));
+    SRP_TRY(sum_parts_f64(parts, ks, cnt, cnt, Hxy, 0, 0.0, st));
+  }
+  int hflag = 0;
+  SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SRP_HIP(hipStreamSynchronize(st));
+  if (hflag) {
+    set_error("sketched Gram is not positive definite (lambda = 0 with rank-deficient data?)");
+    if (info) info->status = SRP_ENOTSPD;
+    return SRP_ENOTSPD;
+  }
+  const double ms_factor = tm.lap_ms();
+  RcgProblem full;
+  full.nb = 2; full.k = k; full.lda_cost = 0; full.dtype = SRP_F64; full.compute = SRP_F64;
+  full.n = n; full.d[0] = dx; full.d[1] = dy;
+  full.lam[0] = lx; full.lam[1] = ly; full.Minv[0] = Mx; full.Minv[1] = My;
+  full.sp = &sd;
+  WarmStart ws;
+  if (warm) {
+    ws.kind = 1; ws.iters = opt.warm_start_iters; ws.Hxy = Hxy; ws.Rinv[0] = Rinv; ws.Rinv[1] = Rinv2;
+    ws.ws = scratch_base; ws.ws_bytes = scr;
+  }
+  CommonArgs ca{k, tol, opt};
+  double* outW[2] = {U, V};
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->ms_sketch = ms_sketch;
+    info->ms_factor = ms_factor;
+  }
+  int rc = solve_tail(full, ws, B, ca, outW, sigma, info, tm, st);
+  SRP_HIP(hipStreamSynchronize(st));
+  finish_info(info, rc, sigma, k);
+  if (rc == SRP_ENOCONV) set_error("max_iter reached before the gradient tolerance");
+  return rc;
+}
+
+int lda_solve_csr_impl(const CsrView& X, const int32_t* labels, int c, int k, double lam, int s, double tol,
+                       const srp_options* optp, hipStream_t st, double* Wout, double* rho, srp_info* info,
+                       const SolveCtx* ctx) {
+  clear_error();
+  srp_options opt;
+  srp_default_options(&opt);
+  if (optp) opt = *optp;
+  SRP_TRY(check_options(opt));
+  SRP_TRY(csr_common_checks(opt));
+  SRP_REQUIRE(labels && Wout && rho, "null pointer argument");
+  const int64_t n = X.n;
+  const int d = X.d;
+  SRP_REQUIRE(n >= 2, "n out of range");
+  SRP_REQUIRE(c >= 2 && c <= kLdaMaxClasses, "need 2 <= n_classes <= %d", kLdaMaxClasses);
+  SRP_REQUIRE(k >= 1 && k <= std::min(c - 1, d) && k <= KMAX, "need 1 <= k <= min(c-1, d), k <= 32");
+  SRP_REQUIRE(opt.method != SRP_RTR || k <= kRtrK, "the trust-region method needs k <= %d", kRtrK);
+  SRP_REQUIRE(s >= d, "sketch_size must be >= d");
+  SRP_REQUIRE(lam >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
+  PhaseTimer tm(st);
+  const size_t bytes = lda_csr_ws_bytes(X, c, k, s);
+  const size_t scr = csr_scratch(&X, 1, s, k, c);
+  Workspace Wk;
+  void* wbase = nullptr;
+  SRP_TRY(take_workspace(Wk, bytes, ctx, st, &wbase));
+  Arena ar{(char*)wbase, bytes, 0};
+  int* flag = ar.take<int>(4);
+  SRP_TRY(csr_check(X, "X", flag, st));
+  int* counts = ar.take<int>(c);
+  SRP_TRY(fill_i32(flag + 1, 1, 0, st));
+  SRP_TRY(label_counts_run(n, c, labels, counts, flag + 1, st));
+  {
+    int hc[kLdaMaxClasses];
+    int hbad = 0;
+    SRP_HIP(hipMemcpyAsync(&hbad, flag + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    SRP_HIP(hipMemcpyAsync(hc, counts, sizeof(int) * c, hipMemcpyDeviceToHost, st));
+    SRP_HIP(hipStreamSynchronize(st));
+    SRP_REQUIRE(!hbad, "label out of range [0, %d)", c);
+    for (int q = 0; q < c; ++q) SRP_REQUIRE(hc[q] > 0, "class %d is empty", q);
+  }
+  const int dd[2] = {d, 0};
+  double* SXh = ar.take<double>((size_t)s * d);
+  double* SE = ar.take<double>((size_t)s * c);
+  double* R = ar.take<double>((size_t)d * d);
+  double* Rinv = ar.take<double>((size_t)d * d);
+  double* Minv = ar.take<double>((size_t)d * d);
+  double* sums = ar.take<double>((size_t)c * d);
+  double* means = ar.take<double>((size_t)c * d);
+  double* Yhat = ar.take<double>((size_t)c * d);
+  double* T = ar.take<double>((size_t)c * k);
+  RcgBuffers B{};
+  if (!T || rcg_buffers_take(B, ar, 1, k, std::max<int64_t>(n, s), dd, c) != SRP_OK) {
+    set_error("workspace layout overflow");
+    return SRP_ENOMEM;
+  }
+  SRP_TRY(setup_mu(opt, k, B.mu, st));
+  if (ar.used + scr > ar.cap) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+  Arena keep{ar.base + ar.used, ar.cap - ar.used - scr, 0};
+  char* scratch_base = ar.base + ar.cap - scr;
+  SparseData sd;
+  sd.csr[0] = X;
+  sd.labels = labels;
+  sd.means = means;
+  sd.T = T;
+  {
+    Arena t{scratch_base, scr, 0};
+    SRP_TRY(csc_build(X, &sd.csc[0], keep, t, st));
+    sd.partial[0] = (double*)keep.take<char>(csc_partial_bytes(X, k));
+  }
+  if (!sd.partial[0]) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+  // class statistics; the sketch of Xhat = X - E C is S X - (S E) C
+  SRP_TRY(fda_csr_stats_run(sd.csc[0], n, c, labels, counts, sums, means, Yhat, st));
+  {
+    Arena t{scratch_base, scr, 0};
+    SRP_TRY(countsketch_csr_run(X, s, opt.seed, SXh, labels, c, SE, t, st));
+  }
+  {
+    GemmArgs g{};
+    g.m = s; g.n = d; g.kk = c; g.alpha = -1.0; g.beta = 1.0;
+    g.A = SE; g.lda = c; g.ta = false; g.a_f32 = false;
+    g.B = means; g.ldb = d; g.tb = false; g.b_f32 = false;
+    g.C = SXh; g.ldc = d;
+    SRP_TRY(gemm_f64(g, st));
+  }
+  const double ms_sketch = tm.lap_ms();
+  SRP_TRY(fill_i32(flag, 1, 0, st));
+  {
+    Arena t{scratch_base, scr, 0};
+    SRP_TRY(sketch_factor_run(SXh, SRP_F64, s, d, lam, R, Rinv, Minv, flag, t, st));
+  }
+  int hflag = 0;
+  SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SRP_HIP(hipStreamSynchronize(st));
+  if (hflag) {
+    set_error("sketched Gram is not positive definite (lambda = 0 with rank-deficient data?)");
+    if (info) info->status = SRP_ENOTSPD;
+    return SRP_ENOTSPD;
+  }
+  const double ms_factor = tm.lap_ms();
+  RcgProblem full;
+  full.nb = 1; full.k = k; full.lda_cost = 1; full.dtype = SRP_F64; full.compute = SRP_F64;
+  full.n = n; full.d[0] = d; full.lam[0] = lam; full.Minv[0] = Minv; full.Yhat = Yhat; full.c = c;
+  full.sp = &sd;
+  WarmStart ws;
+  if (opt.warm_start_iters > 0) {
+    ws.kind = 2; ws.Yhat = Yhat; ws.c = c;
+    ws.ws = scratch_base; ws.ws_bytes = scr;
+  }
+  CommonArgs ca{k, tol, opt};
+  double* outW[2] = {Wout, nullptr};
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->ms_sketch = ms_sketch;
+    info->ms_factor = ms_factor;
+  }
+  int rc = solve_tail(full, ws, B, ca, outW, rho, info, tm, st);
+  SRP_HIP(hipStreamSynchronize(st));
+  finish_info(info, rc, rho, k);
   if (rc == SRP_ENOCONV) set_error("max_iter reached before the gradient tolerance");
   return rc;
 }

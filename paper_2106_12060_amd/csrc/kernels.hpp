@@ -12,6 +12,12 @@ int copy_f64(double* dst, const double* src, int64_t count, hipStream_t st);
 size_t countsketch_ws_bytes(int64_t n, int s);
 int countsketch_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out,
                     Arena& ws, hipStream_t st);
+// Rows grouped by bucket (offsets[b] .. offsets[b+1] into sorted, rows
+// ascending inside a bucket), from ws.
+int countsketch_buckets(int64_t n, int s, uint64_t seed, Arena& ws, const int** offsets, const int** sorted,
+                        hipStream_t st);
+// offsets[0..count] = exclusive scan of in[0..count) (offsets[count] = total).
+int scan_excl_i32(const int* in, int count, int* offsets, hipStream_t st);
 size_t srht_ws_bytes(int64_t n, int d, int s, int dtype);
 int srht_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out, Arena& ws,
              hipStream_t st);
@@ -104,6 +110,65 @@ int lda_center_run(const void* X, const int32_t* labels, int dtype, int64_t n, i
                    double* Yhat, int* counts, int* bad, Arena& ws, hipStream_t st);
 int pass_limits_ok(int dtype, int compute, int d0, int d1, int k, int nblocks);
 
+// --------------------------------------------------------- sparse data
+// CSR matrix in device memory (row pointers int64, n + 1 of them; column
+// indices int32, strictly increasing within a row; values F32 or F64).
+struct CsrView {
+  int64_t n = 0;
+  int d = 0;
+  int64_t nnz = 0;
+  const int64_t* ptr = nullptr;
+  const int32_t* idx = nullptr;
+  const void* val = nullptr;
+  int dtype = SRP_F32;
+};
+// Its column-major copy: column j's rows (ascending) at ptr[j] .. ptr[j+1].
+struct CscView {
+  int d = 0;
+  int64_t nnz = 0;
+  int* ptr = nullptr;
+  int32_t* idx = nullptr;
+  void* val = nullptr;
+  int dtype = SRP_F32;
+  // the columns cut into segments of a fixed number of entries: segments
+  // segptr[j] .. segptr[j+1] belong to column j, segcol[q] is q's column
+  int nseg = 0;
+  int* segptr = nullptr;
+  int* segcol = nullptr;
+};
+// Widest CSR input: the CountSketch keeps one bucket's row of d doubles in
+// LDS.
+constexpr int kCsrMaxCols = 8192;
+// Sets *bad (device) to 1 if A is not a well-formed CSR matrix.
+int csr_validate(const CsrView& A, int* bad, hipStream_t st);
+// Size and pointer checks, then csr_validate (bad: one device int);
+// synchronises st; SRP_EINVAL naming `name` on failure.
+int csr_check(const CsrView& A, const char* name, int* bad, hipStream_t st);
+size_t csc_bytes(const CsrView& A);
+size_t csc_scratch_bytes(const CsrView& A);
+int csc_build(const CsrView& A, CscView* out, Arena& keep, Arena& scratch, hipStream_t st);
+// out (rows x w, leading dimension ldo) = A D for D with leading dimension
+// ldd, w <= 64; CSR form optionally minus sub[labels[r]] per row r.
+// A set *done makes the launch a no-op.
+int csr_times_dense(const CsrView& A, const double* D, int ldd, int w, double* out, int ldo, const double* sub,
+                    const int32_t* labels, const int* done, hipStream_t st);
+// The columns' products go through per-segment partials (partial:
+// csc_partial_bytes(A, w) bytes), summed per column in segment order.
+int64_t csc_max_segments(const CsrView& A);
+size_t csc_partial_bytes(const CsrView& A, int w);
+int csc_times_dense(const CscView& A, const double* D, int ldd, int w, double* out, int ldo, double* partial,
+                    const int* done, hipStream_t st);
+size_t countsketch_csr_ws_bytes(int64_t n, int s);
+// out (s x d, FP64) = S A; with labels, se (s x c) = S E for the one-hot
+// class matrix E (labels must be in range).
+int countsketch_csr_run(const CsrView& A, int s, uint64_t seed, double* out, const int32_t* labels, int c,
+                        double* se, Arena& ws, hipStream_t st);
+int label_counts_run(int64_t n, int c, const int32_t* labels, int* counts, int* bad, hipStream_t st);
+// sums (c x d) = class sums of A's rows, means (c x d) = class means and
+// Yhat (c x d) rows sqrt(n_q)(m_q - m).
+int fda_csr_stats_run(const CscView& A, int64_t n, int c, const int32_t* labels, const int* counts, double* sums,
+                      double* means, double* Yhat, hipStream_t st);
+
 // --------------------------------------------------------- staging
 int stage_bf16_run(const float* X, int64_t n, int d, uint16_t* out, hipStream_t st);
 size_t stage_fp8_ws_bytes(int d);
@@ -124,6 +189,14 @@ struct SolveCtx {
 };
 size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sketch_kind, int skin_dtype);
 size_t lda_ws_bytes(int64_t n, int d, int c, int k, int s, int dtype, int sketch_kind);
+size_t cca_csr_ws_bytes(const CsrView& X, const CsrView& Y, int k, int s);
+size_t lda_csr_ws_bytes(const CsrView& X, int c, int k, int s);
+int cca_solve_csr_impl(const CsrView& X, const CsrView& Y, int k, double lx, double ly, int s, double tol,
+                       const srp_options* opt, hipStream_t st, double* U, double* V, double* sigma, srp_info* info,
+                       const SolveCtx* ctx = nullptr);
+int lda_solve_csr_impl(const CsrView& X, const int32_t* labels, int c, int k, double lam, int s, double tol,
+                       const srp_options* opt, hipStream_t st, double* W, double* rho, srp_info* info,
+                       const SolveCtx* ctx = nullptr);
 int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int k, double lx, double ly, int s,
                    double tol, int dtype, const srp_options* opt, hipStream_t st, double* U, double* V,
                    double* sigma, srp_info* info, const SolveCtx* ctx = nullptr);

@@ -136,8 +136,14 @@ static int cs_gather_launch(const T* A, int d, int s, uint64_t seed, const int* 
   return SRP_OK;
 }
 
-int countsketch_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out,
-                    Arena& ws, hipStream_t st) {
+int scan_excl_i32(const int* in, int count, int* offsets, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, in, count, offsets, (int*)nullptr);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+int countsketch_buckets(int64_t n, int s, uint64_t seed, Arena& ws, const int** offsets_out,
+                        const int** sorted_out, hipStream_t st) {
   int* counts = ws.take<int>(s + 1);
   int* offsets = ws.take<int>(s + 1);
   int* cursor = ws.take<int>(s + 1);
@@ -154,6 +160,16 @@ int countsketch_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t 
   SRP_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_cs_sort, dim3(s), dim3(64), 0, st, offsets, list, sorted);
   SRP_LAUNCH_CHECK();
+  *offsets_out = offsets;
+  *sorted_out = sorted;
+  return SRP_OK;
+}
+
+int countsketch_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t seed, void* out,
+                    Arena& ws, hipStream_t st) {
+  const int* offsets = nullptr;
+  const int* sorted = nullptr;
+  SRP_TRY(countsketch_buckets(n, s, seed, ws, &offsets, &sorted, st));
   switch (dtype) {
     case SRP_F64:
       return cs_gather_launch((const double*)A, d, s, seed, offsets, sorted, (double*)out, st);

@@ -38,6 +38,7 @@ import numpy as np
 __all__ = [
     "column_scales", "cca_latent", "cca_latent_device", "lda_classes", "planted_cca",
     "Workload", "workload", "serving_trace", "WORKLOADS", "sparse_signs",
+    "CsrArrays", "sparse_pattern", "cca_sparse", "lda_sparse",
 ]
 
 
@@ -146,6 +147,85 @@ def sparse_signs(n: int, d: int, per_row: int, *, seed: int = 0, cols=None,
     X = np.zeros((n, d), dtype=np.float64)
     np.add.at(X, (np.repeat(np.arange(n), per_row), idx.reshape(-1)), vals.reshape(-1))
     return X.astype(dtype)
+
+
+@dataclasses.dataclass
+class CsrArrays:
+    """A CSR matrix as host arrays: row_ptr (int64, n + 1), col_idx (int32,
+    strictly increasing within a row), values, and the column count."""
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    values: np.ndarray
+    n_cols: int
+
+    @property
+    def shape(self):
+        return (len(self.row_ptr) - 1, self.n_cols)
+
+    @property
+    def nnz(self):
+        return len(self.col_idx)
+
+
+def sparse_pattern(n: int, d: int, per_row: float, rng: np.random.Generator, *, alpha: float = 0.7,
+                   empty_frac: float = 0.02):
+    """Sparsity pattern of a bag-of-words-like matrix: row i draws about
+    ``per_row`` columns (Poisson count) from a Zipf-like popularity
+    p_j ~ (j + 1)^-alpha, duplicates merged; a fraction ``empty_frac`` of the
+    rows is left empty.  Returns (row_ptr int64, col_idx int32, row of each
+    entry int64), entries in row order with ascending columns."""
+    counts = rng.poisson(per_row, n)
+    counts[rng.random(n) < empty_frac] = 0
+    p = (np.arange(d) + 1.0) ** -alpha
+    p /= p.sum()
+    rows = np.repeat(np.arange(n, dtype=np.int64), counts)
+    cols = rng.choice(d, size=rows.size, p=p)
+    key = np.unique(rows * d + cols)
+    rows, cols = key // d, key % d
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    return row_ptr, cols.astype(np.int32), rows
+
+
+def cca_sparse(n: int, dx: int, dy: int, *, per_row: float = 16, r: int = 8, noise: float = 0.5,
+               seed: int = 0, dtype=np.float32, integer: bool = False):
+    """Two sparse views of one Gaussian latent factor: both views share the
+    rows' latent z_i (r-dimensional); an entry (i, j) of view X, at a
+    sparse position, holds z_i . a_j + noise * e with a_j ~ N(0, I_r) per
+    column, so the views correlate through z on their supports.  With
+    ``integer`` the values are instead drawn from {-2, -1, 1, 2} (exact in
+    any summation order).  Returns (X, Y) as CsrArrays."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((n, r))
+    out = []
+    for d in (dx, dy):
+        row_ptr, cols, rows = sparse_pattern(n, d, per_row, rng)
+        if integer:
+            vals = rng.choice(np.array([-2.0, -1.0, 1.0, 2.0]), size=cols.size)
+        else:
+            A = rng.standard_normal((d, r))
+            vals = np.empty(cols.size)
+            for b0 in range(0, cols.size, 1 << 22):
+                b1 = min(cols.size, b0 + (1 << 22))
+                vals[b0:b1] = np.einsum("ij,ij->i", Z[rows[b0:b1]], A[cols[b0:b1]])
+            vals += noise * rng.standard_normal(cols.size)
+        out.append(CsrArrays(row_ptr, cols, vals.astype(dtype), d))
+    return out[0], out[1]
+
+
+def lda_sparse(n: int, d: int, c: int, *, per_row: float = 24, mean_std: float = 1.0, noise: float = 0.5,
+               seed: int = 0, dtype=np.float32):
+    """Sparse labelled samples: labels uniform over c classes (every class
+    present); an entry (i, j) at a sparse position holds mu[y_i, j] +
+    noise * e, with class means mu ~ N(0, mean_std^2).  Returns
+    (X as CsrArrays, labels int32)."""
+    rng = np.random.default_rng(seed)
+    labels = rng.integers(0, c, size=n).astype(np.int32)
+    labels[:c] = np.arange(c, dtype=np.int32)
+    means = mean_std * rng.standard_normal((c, d))
+    row_ptr, cols, rows = sparse_pattern(n, d, per_row, rng)
+    vals = means[labels[rows], cols] + noise * rng.standard_normal(cols.size)
+    return CsrArrays(row_ptr, cols, vals.astype(dtype), d), labels
 
 
 def planted_cca(n: int, r: int, rho, *, seed: int = 0, dtype=np.float64):

@@ -1,0 +1,171 @@
+"""CSR inputs through the C ABI against the FP64 oracle: the O(nnz)
+CountSketch (Section 3) and data products (Table costs), then whole CCA /
+FDA solves on sparse data against the closed forms of the densified
+matrices (the method's fixed point does not depend on the data format)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import direct, metrics, sketch
+from oracle import sparse as osp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda"
+
+
+def _srp():
+    import paper_2106_12060_amd as srp
+    return srp
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def to_dev(M):
+    return _srp().Csr(dev(M.row_ptr), dev(M.col_idx), dev(M.values), M.n_cols)
+
+
+def dense(M):
+    return osp.csr_to_dense(M.row_ptr, M.col_idx, M.values, M.n_cols)
+
+
+def blk(M):
+    return (M.row_ptr, M.col_idx, M.values, M.n_cols)
+
+
+@pytest.mark.parametrize("n,d,s,per_row,dt", [
+    (200_000, 1000, 4000, 32, np.float32),   # the CCA benchmark's sketch shape, exact values
+    (3001, 257, 300, 9, np.float64),         # ragged: several column tiles, a partial one
+    (1, 3, 2, 2, np.float32),                # one row
+])
+def test_countsketch_csr_bit_exact(n, d, s, per_row, dt):
+    """Entries in {-2, -1, 1, 2}: every bucket sum is an exact integer in
+    FP64, whatever the order, so the result must match bit for bit."""
+    srp = _srp()
+    X, _ = synth.cca_sparse(n, d, 2, per_row=per_row, seed=n % 97, dtype=dt, integer=True)
+    print("countsketch_csr", n, d, s, X.nnz, flush=True)
+    h, g = sketch.countsketch_hash(n, s, 12060)
+    want = osp.countsketch_csr(X.row_ptr, X.col_idx, X.values, d, h, g, s)
+    got = srp.srp_countsketch_csr(to_dev(X), s, 12060).cpu().numpy()
+    assert np.array_equal(got, want)
+
+
+def test_countsketch_csr_gaussian_bound():
+    srp = _srp()
+    n, d, s = 20_000, 300, 600
+    X, _ = synth.cca_sparse(n, d, 2, per_row=12, seed=5, dtype=np.float64)
+    h, g = sketch.countsketch_hash(n, s, 3)
+    want = osp.countsketch_csr(X.row_ptr, X.col_idx, X.values, d, h, g, s)
+    absum = osp.countsketch_csr(X.row_ptr, X.col_idx, np.abs(X.values), d, h, np.abs(g), s)
+    m = np.bincount(h, minlength=s).max()
+    got = srp.srp_countsketch_csr(to_dev(X), s, 3).cpu().numpy()
+    assert np.all(np.abs(got - want) <= m * 2.0 ** -53 * absum + 1e-300)
+
+
+def test_gram_pass_csr_exact_full_size():
+    """Integer entries and integer directions: A W and A^T (A W) are exact
+    integers far below 2^53, so the two-block pass must match bit for bit
+    at the benchmark's sparse shape."""
+    srp = _srp()
+    n, d0, d1, k = 200_000, 1000, 800, 10
+    X, Y = synth.cca_sparse(n, d0, d1, per_row=24, seed=8, integer=True)
+    rng = np.random.default_rng(1)
+    W0 = rng.integers(-3, 4, size=(d0, k)).astype(np.float64)
+    W1 = rng.integers(-3, 4, size=(d1, k)).astype(np.float64)
+    print("gram_pass_csr exact", X.nnz, Y.nnz, flush=True)
+    J0w, J1w = osp.pass_csr([blk(X), blk(Y)], [W0, W1])
+    J0, J1 = srp.srp_gram_pass_csr(to_dev(X), dev(W0), to_dev(Y), dev(W1))
+    assert np.array_equal(J0.cpu().numpy(), J0w)
+    assert np.array_equal(J1.cpu().numpy(), J1w)
+
+
+@pytest.mark.parametrize("nb,k", [(2, 7), (1, 20), (1, 1)])
+def test_gram_pass_csr_gaussian(nb, k):
+    srp = _srp()
+    n = 9000
+    X, Y = synth.cca_sparse(n, 300, 130, per_row=10, seed=k, dtype=np.float32)
+    rng = np.random.default_rng(k)
+    W0, W1 = rng.standard_normal((300, k)), rng.standard_normal((130, k))
+    blocks = [blk(X), blk(Y)][:nb]
+    Ws = [W0, W1][:nb]
+    want = osp.pass_csr(blocks, Ws)
+    # bound: |fl(sum) - sum| <= gamma_m sum |terms|, products of |.|
+    absb = [(b[0], b[1], np.abs(b[2]), b[3]) for b in blocks]
+    bound = osp.pass_csr(absb, [np.abs(W) for W in Ws])
+    m = n + max(b[3] for b in blocks)
+    if nb == 2:
+        J0, J1 = srp.srp_gram_pass_csr(to_dev(X), dev(W0), to_dev(Y), dev(W1))
+        got = [J0.cpu().numpy(), J1.cpu().numpy()]
+    else:
+        J0, _ = srp.srp_gram_pass_csr(to_dev(X), dev(W0))
+        got = [J0.cpu().numpy()]
+    for g, w, b in zip(got, want, bound):
+        assert np.all(np.abs(g - w) <= 2 * m * 2.0 ** -53 * b + 1e-300)
+
+
+@pytest.mark.parametrize("method", ["rcg", "rtr"])
+def test_cca_solve_csr_against_closed_form(method):
+    srp = _srp()
+    n, dx, dy, k, s, lam = 30_000, 300, 200, 5, 900, 1e-3
+    X, Y = synth.cca_sparse(n, dx, dy, per_row=14, r=8, seed=21, dtype=np.float32)
+    Xd, Yd = dense(X), dense(Y)
+    sig_true, _, _ = direct.cca_direct(Xd, Yd, lam, lam)
+    opt = srp.srp_default_options(method=method, max_iter=500)
+    U, V, sig, info = srp.cca_solve_csr(to_dev(X), to_dev(Y), k, lam, lam, s, tol=1e-11, options=opt)
+    Uh, Vh = U.cpu().numpy(), V.cpu().numpy()
+    err = metrics.cca_rel_objective_error(Uh, Vh, Xd, Yd, lam, lam, sig_true)
+    cons = max(metrics.constraint_residual(Uh, Xd, lam), metrics.constraint_residual(Vh, Yd, lam))
+    print("cca csr", method, info, err, cons)
+    assert info["status"] == 0
+    assert err < 1e-10 and cons < 1e-11
+    np.testing.assert_allclose(sig.cpu().numpy(), sig_true[:k], rtol=0, atol=1e-8)
+
+
+@pytest.mark.parametrize("method", ["rcg", "rtr"])
+def test_lda_solve_csr_against_closed_form(method):
+    srp = _srp()
+    n, d, c, k, s = 20_000, 250, 8, 7, 750
+    X, y = synth.lda_sparse(n, d, c, per_row=20, seed=33, dtype=np.float32)
+    Xd = dense(X)
+    lam = 1e-3
+    rho_true, _ = direct.lda_direct(Xd, y, c, lam, k=k)
+    opt = srp.srp_default_options(method=method, max_iter=500)
+    W, rho, info = srp.lda_solve_csr(to_dev(X), dev(y), c, k, lam, s, tol=1e-11, options=opt)
+    _, _, _, Xh, Yh = direct.lda_scatter(Xd, y, c)
+    Wh = W.cpu().numpy()
+    err = metrics.lda_rel_objective_error(Wh, Xh, Yh, lam, rho_true)
+    cons = metrics.constraint_residual(Wh, Xh, lam)
+    print("lda csr", method, info, err, cons)
+    assert info["status"] == 0
+    assert err < 1e-10 and cons < 1e-11
+    np.testing.assert_allclose(rho.cpu().numpy(), rho_true[:k], rtol=1e-9)
+
+
+def test_csr_rejects_malformed_and_srht():
+    srp = _srp()
+    X, Y = synth.cca_sparse(500, 40, 30, per_row=5, seed=2)
+    # columns out of order in one row
+    bad = synth.CsrArrays(X.row_ptr.copy(), X.col_idx.copy(), X.values, X.n_cols)
+    r = int(np.argmax(np.diff(X.row_ptr) >= 2))
+    e = X.row_ptr[r]
+    bad.col_idx[e], bad.col_idx[e + 1] = bad.col_idx[e + 1], bad.col_idx[e]
+    # column out of range
+    oor = synth.CsrArrays(X.row_ptr, X.col_idx.copy(), X.values, X.n_cols)
+    oor.col_idx[-1] = X.n_cols
+    # last row pointer past nnz
+    ptr = synth.CsrArrays(X.row_ptr.copy(), X.col_idx, X.values, X.n_cols)
+    ptr.row_ptr[-1] = X.nnz + 5
+    for M in (bad, oor, ptr):
+        with pytest.raises(srp.SrpError) as ei:
+            srp.srp_countsketch_csr(to_dev(M), 64, 1)
+        assert ei.value.code == srp.SRP_EINVAL
+        with pytest.raises(srp.SrpError) as ei:
+            srp.cca_solve_csr(to_dev(M), to_dev(Y), 2, 1e-3, 1e-3, 64)
+        assert ei.value.code == srp.SRP_EINVAL
+    with pytest.raises(srp.SrpError) as ei:
+        srp.cca_solve_csr(to_dev(X), to_dev(Y), 2, 1e-3, 1e-3, 64,
+                          options=srp.srp_default_options(sketch="srht"))
+    assert ei.value.code == srp.SRP_EINVAL

@@ -780,3 +780,51 @@ def test_principal_angles_of_a_plane_rotation():
     S = np.diag([4.0, 1.0, 1.0])     # S-inner product of e_1 and (1, 2, 0)
     a = metrics.principal_angles(A, np.array([[1.0], [2.0], [0.0]]), S)[0]
     assert abs(np.cos(a) - 4.0 / (2.0 * np.sqrt(8.0))) < 1e-14   # <A,B>_S / (|A|_S |B|_S)
+
+
+# ----------------------------------------------------------- CSR oracle
+def _csr_case(n, d, per_row, seed):
+    X, _ = synth.cca_sparse(n, d, 3, per_row=per_row, seed=seed, dtype=np.float64)
+    return X
+
+
+def test_csr_to_dense_matches_loop_and_scipy():
+    import scipy.sparse as sp
+    from oracle import sparse as osp
+    X = _csr_case(300, 40, 6, 3)
+    A = osp.csr_to_dense(X.row_ptr, X.col_idx, X.values, X.n_cols)
+    L = np.zeros_like(A)
+    for i in range(X.shape[0]):
+        for e in range(X.row_ptr[i], X.row_ptr[i + 1]):
+            L[i, X.col_idx[e]] += X.values[e]
+    assert np.array_equal(A, L)
+    S = sp.csr_matrix((X.values, X.col_idx, X.row_ptr), shape=X.shape).toarray()
+    assert np.array_equal(A, S)
+    assert np.any(np.diff(X.row_ptr) == 0)   # the pattern holds empty rows
+
+
+@pytest.mark.parametrize("n,d,s", [(500, 30, 64), (1, 5, 3), (200, 1, 16)])
+def test_csr_countsketch_matches_dense_definition(n, d, s):
+    from oracle import sparse as osp
+    X = _csr_case(n, d, 4, 11)
+    A = osp.csr_to_dense(X.row_ptr, X.col_idx, X.values, X.n_cols)
+    h, g = sketch.countsketch_hash(n, s, 7)
+    got = osp.countsketch_csr(X.row_ptr, X.col_idx, X.values, X.n_cols, h, g, s)
+    np.testing.assert_allclose(got, sketch.countsketch_apply(A, h, g, s), rtol=1e-14, atol=1e-13)
+    np.testing.assert_allclose(got, sketch.countsketch_matrix(h, g, s) @ A, rtol=1e-14, atol=1e-13)
+
+
+def test_csr_pass_matches_dense_products():
+    from oracle import sparse as osp
+    X, Y = synth.cca_sparse(400, 30, 20, per_row=5, seed=4, dtype=np.float64)
+    rng = np.random.default_rng(0)
+    W0, W1 = rng.standard_normal((30, 3)), rng.standard_normal((20, 3))
+    A0 = osp.csr_to_dense(X.row_ptr, X.col_idx, X.values, X.n_cols)
+    A1 = osp.csr_to_dense(Y.row_ptr, Y.col_idx, Y.values, Y.n_cols)
+    blocks = [(X.row_ptr, X.col_idx, X.values, X.n_cols), (Y.row_ptr, Y.col_idx, Y.values, Y.n_cols)]
+    J0, J1 = osp.pass_csr(blocks, [W0, W1])
+    P = np.hstack([A0 @ W0, A1 @ W1])
+    np.testing.assert_allclose(J0, A0.T @ P, rtol=1e-12, atol=1e-11)
+    np.testing.assert_allclose(J1, A1.T @ P, rtol=1e-12, atol=1e-11)
+    (J,) = osp.pass_csr(blocks[:1], [W0])
+    np.testing.assert_allclose(J, A0.T @ (A0 @ W0), rtol=1e-12, atol=1e-11)
