@@ -12,11 +12,22 @@ optimum; the statistical dimension to a linear solve and its closed forms
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
 from scipy.linalg import solve_triangular
 
 
 def _f64(a):
+    """FP64 view of a matrix; a scipy sparse matrix stays sparse (its
+    products below are sparse products, made dense)."""
+    if sp.issparse(a):
+        return sp.csr_matrix(a, dtype=np.float64)
     return np.asarray(a, dtype=np.float64)
+
+
+def _gram(A, B):
+    """A^T B as a dense FP64 array (A, B dense or scipy sparse)."""
+    G = A.T @ B
+    return G.toarray() if sp.issparse(G) else np.asarray(G)
 
 
 def sign_normalize(U: np.ndarray, V: np.ndarray | None = None):
@@ -56,9 +67,9 @@ def cca_direct(X, Y, lam_x: float, lam_y: float, k: int | None = None):
     dx, dy = X.shape[1], Y.shape[1]
     if k is None:
         k = min(dx, dy)
-    Sxx = X.T @ X + lam_x * np.eye(dx)
-    Syy = Y.T @ Y + lam_y * np.eye(dy)
-    Sxy = X.T @ Y
+    Sxx = _gram(X, X) + lam_x * np.eye(dx)
+    Syy = _gram(Y, Y) + lam_y * np.eye(dy)
+    Sxy = _gram(X, Y)
     Lx = np.linalg.cholesky(Sxx)
     Ly = np.linalg.cholesky(Syy)
     C = solve_triangular(Lx, Sxy, lower=True)               # Lx^-1 Sxy

@@ -20,6 +20,13 @@ sub-optimality; principal angles of a plane rotation equal its angle.
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
+
+
+def _mat(Z):
+    """FP64 data matrix; scipy sparse matrices stay sparse (Z @ U is then
+    a sparse product with a dense result)."""
+    return sp.csr_matrix(Z, dtype=np.float64) if sp.issparse(Z) else np.asarray(Z, dtype=np.float64)
 
 
 def _qf(U, S):
@@ -29,7 +36,7 @@ def _qf(U, S):
 
 def constraint_residual(U, Z, lam) -> float:
     U = np.asarray(U, dtype=np.float64)
-    Z = np.asarray(Z, dtype=np.float64)
+    Z = _mat(Z)
     ZU = Z @ U
     G = ZU.T @ ZU + lam * (U.T @ U)
     return float(np.max(np.abs(G - np.eye(U.shape[1]))))
@@ -39,8 +46,8 @@ def cca_objective(U, V, X, Y, lam_x, lam_y, reorth: bool = True) -> float:
     """tr(U^T X^T Y V), optionally after FP64 qf re-orthonormalisation."""
     U = np.asarray(U, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
-    X = np.asarray(X, dtype=np.float64)
-    Y = np.asarray(Y, dtype=np.float64)
+    X = _mat(X)
+    Y = _mat(Y)
     XU = X @ U
     YV = Y @ V
     if reorth:

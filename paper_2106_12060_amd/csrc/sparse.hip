@@ -250,16 +250,28 @@ __global__ void __launch_bounds__(256) k_spmm_segs(int nseg, const int* __restri
   if (c < w) partial[q * w + c] = acc;
 }
 
-// Stage 2: out[j][c] = sum of column j's segment partials, in order.
-__global__ void k_spmm_seg_sum(int d, int w, const int* __restrict__ segptr, const double* __restrict__ partial,
-                               double* __restrict__ out, int ldo, const int* __restrict__ done) {
+// Stage 2: out[j][c] = sum of column j's segment partials.  One workgroup
+// per column: W lanes per slice (W >= w), 256 / W slices; slice l adds
+// segments l, l + 256/W, ... in order, then slice 0 adds the slices'
+// sums in slice order (a fixed order: bitwise reproducible).
+template <int W>
+__global__ void __launch_bounds__(256) k_spmm_seg_sum(int w, const int* __restrict__ segptr,
+                                                      const double* __restrict__ partial, double* __restrict__ out,
+                                                      int ldo, const int* __restrict__ done) {
   if (done && *done) return;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)d * w) return;
-  const int j = (int)(t / w), c = (int)(t - (int64_t)j * w);
+  constexpr int SL = 256 / W;
+  __shared__ double red[SL][W];
+  const int j = blockIdx.x, c = threadIdx.x % W, l = threadIdx.x / W;
   double acc = 0.0;
-  for (int q = segptr[j]; q < segptr[j + 1]; ++q) acc += partial[(int64_t)q * w + c];
-  out[(int64_t)j * ldo + c] = acc;
+  if (c < w)
+    for (int q = segptr[j] + l; q < segptr[j + 1]; q += SL) acc += partial[(int64_t)q * w + c];
+  red[l][c] = acc;
+  __syncthreads();
+  if (l == 0 && c < w) {
+    double s = 0.0;
+    for (int t = 0; t < SL; ++t) s += red[t][c];
+    out[(int64_t)j * ldo + c] = s;
+  }
 }
 
 template <class T>
@@ -317,9 +329,12 @@ int csc_times_dense(const CscView& A, const double* D, int ldd, int w, double* o
     if (A.dtype == SRP_F64) SRP_TRY(spmm_segs_launch(A, (const double*)A.val, D, ldd, w, partial, done, st));
     else SRP_TRY(spmm_segs_launch(A, (const float*)A.val, D, ldd, w, partial, done, st));
   }
-  const int64_t t = (int64_t)A.d * w;
-  hipLaunchKernelGGL(k_spmm_seg_sum, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, A.d, w, A.segptr, partial,
-                     out, ldo, done);
+  if (w <= 8) hipLaunchKernelGGL(k_spmm_seg_sum<8>, dim3(A.d), dim3(256), 0, st, w, A.segptr, partial, out, ldo, done);
+  else if (w <= 16) hipLaunchKernelGGL(k_spmm_seg_sum<16>, dim3(A.d), dim3(256), 0, st, w, A.segptr, partial, out, ldo,
+                                       done);
+  else if (w <= 32) hipLaunchKernelGGL(k_spmm_seg_sum<32>, dim3(A.d), dim3(256), 0, st, w, A.segptr, partial, out, ldo,
+                                       done);
+  else hipLaunchKernelGGL(k_spmm_seg_sum<64>, dim3(A.d), dim3(256), 0, st, w, A.segptr, partial, out, ldo, done);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }

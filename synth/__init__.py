@@ -38,7 +38,7 @@ import numpy as np
 __all__ = [
     "column_scales", "cca_latent", "cca_latent_device", "lda_classes", "planted_cca",
     "Workload", "workload", "serving_trace", "WORKLOADS", "sparse_signs",
-    "CsrArrays", "sparse_pattern", "cca_sparse", "lda_sparse",
+    "CsrArrays", "sparse_pattern", "cca_sparse", "lda_sparse", "SparseWorkload", "SPARSE_WORKLOADS",
 ]
 
 
@@ -332,6 +332,38 @@ WORKLOADS = {
                               x_decades=4.0, y_decades=4.0,
                               inclusive_end=False, noise=1.0,
                               factor_decades=2.0),
+}
+
+
+@dataclasses.dataclass(frozen=True)
+class SparseWorkload:
+    """A CSR CCA workload (``cca_sparse`` recipe, CountSketch, FP32 values)."""
+    name: str
+    n: int
+    dx: int
+    dy: int
+    k: int
+    lam: float
+    s: int
+    per_row: float
+    r: int = 8
+    noise: float = 0.5
+    seed: int = 0
+    problem: str = "cca"
+    sketch: str = "countsketch"
+    dtype: str = "f32"
+
+    def generate(self):
+        return cca_sparse(self.n, self.dx, self.dy, per_row=self.per_row, r=self.r, noise=self.noise,
+                          seed=self.seed, dtype=np.float32)
+
+
+# Bag-of-words-like sparse views (the regime the paper states its costs
+# for: nnz(X), nnz(Y) << n d): one million rows, 1000 columns per view,
+# about 24 stored entries per row with Zipf-like column popularity; k = 8,
+# the latent rank (the 9th correlation is in the noise bulk, 10x lower).
+SPARSE_WORKLOADS = {
+    "cca-csr": SparseWorkload("cca-csr", 1_000_000, 1000, 1000, 8, 1e-3, 4000, 24, seed=12065),
 }
 
 

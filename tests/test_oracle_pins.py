@@ -828,3 +828,21 @@ def test_csr_pass_matches_dense_products():
     np.testing.assert_allclose(J1, A1.T @ P, rtol=1e-12, atol=1e-11)
     (J,) = osp.pass_csr(blocks[:1], [W0])
     np.testing.assert_allclose(J, A0.T @ (A0 @ W0), rtol=1e-12, atol=1e-11)
+
+
+def test_closed_form_and_metrics_take_sparse_matrices():
+    """The CCA closed form and the metrics on scipy sparse input equal
+    those on the same matrices made dense."""
+    import scipy.sparse as sps
+    from oracle import sparse as osp
+    X, Y = synth.cca_sparse(600, 25, 18, per_row=6, seed=9, dtype=np.float64)
+    Xs = sps.csr_matrix((X.values, X.col_idx, X.row_ptr), shape=X.shape)
+    Ys = sps.csr_matrix((Y.values, Y.col_idx, Y.row_ptr), shape=Y.shape)
+    Xd, Yd = Xs.toarray(), Ys.toarray()
+    s1, U1, V1 = direct.cca_direct(Xs, Ys, 1e-2, 1e-2, k=4)
+    s2, U2, V2 = direct.cca_direct(Xd, Yd, 1e-2, 1e-2, k=4)
+    np.testing.assert_allclose(s1, s2, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(U1, U2, rtol=1e-9, atol=1e-12)
+    assert metrics.constraint_residual(U1, Xs, 1e-2) == pytest.approx(metrics.constraint_residual(U1, Xd, 1e-2),
+                                                                       abs=1e-14)
+    assert metrics.cca_rel_objective_error(U1, V1, Xs, Ys, 1e-2, 1e-2, s2) < 1e-13
