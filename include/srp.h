@@ -281,8 +281,14 @@ const char* srp_gram_pass_kernel(int dtype, int compute, int d0, int d1, int k);
  * V^T Syy V = I, U^T Sxy V = diag(sigma); sigma (k) descending; column
  * pairs sign-normalised (largest |entry| of each U column positive).
  * tol: stop when ||grad f||_M <= tol * |f|.
- * Requires 1 <= k <= min(dx, dy), k <= 16, sketch_size >= max(dx, dy),
- * lambda >= 0.  Returns SRP_ENOCONV (with the last iterate) at max_iter.
+ * Requires 1 <= k <= min(dx, dy), k <= 16, lambda >= 0, sketch_size >= 1.
+ * A view with sketch_size < its width d (lambda > 0 required for it) keeps
+ * its metric in Woodbury form (closing remark after Table costs): the
+ * d x d M is neither formed nor factored; K = SA SA^T + lambda I_s is, and
+ * M^-1 V = (V - SA^T K^-1 SA V) / lambda, so the metric costs O(s^2 d)
+ * instead of O(s d^2); the warm start then iterates on the sketched
+ * problem's pencil (no R^-1 to whiten with).
+ * Returns SRP_ENOCONV (with the last iterate) at max_iter.
  */
 int cca_solve(const void* X, const void* Y, int64_t n, int dx, int dy, int k,
               double lambda_x, double lambda_y, int sketch_size, double tol,
@@ -296,7 +302,9 @@ int cca_solve(const void* X, const void* Y, int64_t n, int dx, int dy, int k,
  * Outputs: W (d x k, double) with W^T (S_w + lambda I) W = I and
  * W^T S_B W = diag(rho); rho (k) descending.
  * Requires 2 <= n_classes <= 64, 1 <= k <= min(n_classes - 1, d),
- * k <= 32, every class non-empty, sketch_size >= d, lambda >= 0.
+ * k <= 32, every class non-empty, lambda >= 0, sketch_size >= 1
+ * (sketch_size < d: the Woodbury form of M^-1 as for cca_solve, which
+ * needs lambda > 0).
  */
 int lda_solve(const void* X, const int32_t* labels, int64_t n, int d,
               int n_classes, int k, double lambda, int sketch_size,

@@ -67,7 +67,7 @@ const char* srp_last_error(void) { return srp::last_error(); }
 
 size_t srp_cca_workspace_bytes(int64_t n, int dx, int dy, int k, int sketch_size, int dtype, int sketch_kind,
                                int sketch_input_dtype) {
-  if (n < 1 || dx < 1 || dy < 1 || k < 1 || k > std::min(dx, dy) || sketch_size < std::max(dx, dy)) return 0;
+  if (n < 1 || dx < 1 || dy < 1 || k < 1 || k > std::min(dx, dy) || sketch_size < 1) return 0;
   if (dtype < SRP_F64 || dtype > SRP_BF16 || sketch_input_dtype < SRP_F64 || sketch_input_dtype > SRP_FP8E4M3)
     return 0;
   if (sketch_kind != SRP_COUNTSKETCH && sketch_kind != SRP_SRHT) return 0;
@@ -75,7 +75,7 @@ size_t srp_cca_workspace_bytes(int64_t n, int dx, int dy, int k, int sketch_size
 }
 
 size_t srp_lda_workspace_bytes(int64_t n, int d, int n_classes, int k, int sketch_size, int dtype, int sketch_kind) {
-  if (n < 2 || d < 1 || n_classes < 2 || k < 1 || k > std::min(n_classes - 1, d) || sketch_size < d) return 0;
+  if (n < 2 || d < 1 || n_classes < 2 || k < 1 || k > std::min(n_classes - 1, d) || sketch_size < 1) return 0;
   if (dtype < SRP_F64 || dtype > SRP_BF16) return 0;
   if (sketch_kind != SRP_COUNTSKETCH && sketch_kind != SRP_SRHT) return 0;
   return lda_ws_bytes(n, d, n_classes, k, sketch_size, dtype, sketch_kind);

@@ -182,7 +182,78 @@ struct RcgProblem {
   const double* Yhat = nullptr;  // FDA: c x d rows sqrt(n_j)(m_j - m); S_B = Yhat^T Yhat
   int c = 0;
   const struct SparseData* sp = nullptr;   // CSR data (A unused): products in FP64 from the sparse forms
+  const struct Woodbury* wb[2] = {nullptr, nullptr};   // block b's M^-1 in Woodbury form (Minv[b] unused)
 };
+
+// M^-1 for a sketch with fewer rows than columns (s < d, lambda > 0; the
+// closing remark after Table costs): M = SA^T SA + lam I (d x d) is never
+// formed or factored.  K = SA SA^T + lam I_s (s x s) is, in O(s^2 d + s^3),
+// and by the Sherman-Morrison-Woodbury identity
+//   M^-1 V = (V - SA^T K^-1 SA V) / lam,
+// O(s d w + s^2 w) for w columns.
+struct Woodbury {
+  const void* SA = nullptr;   // the sketch, s x d (FP64 or FP32)
+  bool f32 = false;
+  int s = 0, d = 0;
+  double lam = 0.0;
+  const double* Kinv = nullptr;   // s x s
+  double* t1 = nullptr;           // s x 64
+  double* t2 = nullptr;           // s x 64
+  double* skw = nullptr;          // split-K partials of its skinny products
+  size_t skw_bytes = 0;
+};
+
+// Workspace a Woodbury block keeps for the whole solve (t1, t2, partials).
+static size_t woodbury_keep_bytes(int s, int d) {
+  return 2 * bytes_of<double>((size_t)s * 64) +
+         std::max({skinny_ws_bytes(s, d, 64), skinny_ws_bytes(s, s, 64), skinny_ws_bytes(d, s, 64)}) + 1024;
+}
+// Scratch of its factorisation: SA^T in FP64 and the factor's own.
+static size_t woodbury_factor_scratch(int s, int d) {
+  return bytes_of<double>((size_t)d * s) + factor_ws_bytes(d, s) + 1024;
+}
+
+// K = SA SA^T + lam I_s is the Gram of SA^T (d x s) plus lam I: the sketch
+// factor of SA^T gives K's Cholesky factor (KR) and K^-1.
+static int woodbury_factor(const void* SA, int sk_dtype, int s, int d, double lam, double* KR, double* Kinv,
+                           int* flag, Arena& scratch, Arena& keep, Woodbury* W, hipStream_t st) {
+  double* SAt = scratch.take<double>((size_t)d * s);
+  if (!SAt) { set_error("Woodbury factor: workspace too small"); return SRP_ENOMEM; }
+  SRP_TRY(transpose_to_f64(SA, sk_dtype, s, d, SAt, st));
+  Arena sub{scratch.base + scratch.used, scratch.cap - scratch.used, 0};
+  SRP_TRY(sketch_factor_run(SAt, SRP_F64, d, s, lam, KR, nullptr, Kinv, flag, sub, st));
+  W->SA = SA;
+  W->f32 = sk_dtype != SRP_F64;
+  W->s = s;
+  W->d = d;
+  W->lam = lam;
+  W->Kinv = Kinv;
+  W->t1 = keep.take<double>((size_t)s * 64);
+  W->t2 = keep.take<double>((size_t)s * 64);
+  W->skw_bytes = std::max({skinny_ws_bytes(s, d, 64), skinny_ws_bytes(s, s, 64), skinny_ws_bytes(d, s, 64)});
+  W->skw = (double*)keep.take<char>(W->skw_bytes);
+  if (!W->skw) { set_error("Woodbury form: workspace too small"); return SRP_ENOMEM; }
+  return SRP_OK;
+}
+
+// out (d_b x w, row-major, w <= 64) = M_b^-1 V.
+static int minv_apply(const RcgProblem& P, int b, const double* V, int w, double* out, double* skw, size_t skw_bytes,
+                      hipStream_t st) {
+  const int d = P.d[b];
+  if (!P.wb[b]) return gemm_skinny_f64(d, d, w, P.Minv[b], d, false, V, w, out, w, skw, skw_bytes, st);
+  const Woodbury& W = *P.wb[b];
+  SkinnyProb p1{W.s, d, w, W.SA, d, false, V, w, W.t1, w};   // SA V
+  p1.a_f32 = W.f32;
+  SRP_TRY(gemm_skinny_batch(1, &p1, W.skw, W.skw_bytes, st));
+  SRP_TRY(gemm_skinny_f64(W.s, W.s, w, W.Kinv, W.s, false, W.t1, w, W.t2, w, W.skw, W.skw_bytes, st));
+  SkinnyProb p3{d, W.s, w, W.SA, d, true, W.t2, w, out, w};   // SA^T K^-1 SA V
+  p3.a_f32 = W.f32;
+  SRP_TRY(gemm_skinny_batch(1, &p3, W.skw, W.skw_bytes, st));
+  RtrLinArgs la{};
+  la.k = w;
+  la.side[0] = RtrLinSide{out, V, 1.0 / W.lam, out, -1.0 / W.lam, nullptr, d};
+  return rtr_lin(la, 1, st);
+}
 
 // Sparse data of a solve: the CSR views and their CSC copies; FDA adds the
 // labels and the class means, whose products give the centred ones.
@@ -455,6 +526,10 @@ static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int c
 }
 
 static int apply_minv(const RcgProblem& P, RcgBuffers& B, hipStream_t st) {
+  if (P.wb[0] || P.wb[1]) {
+    for (int b = 0; b < P.nb; ++b) SRP_TRY(minv_apply(P, b, B.Z[b], 2 * P.k, B.Wz[b], B.skw, B.skw_bytes, st));
+    return SRP_OK;
+  }
   SkinnyProb pr[2];
   for (int s = 0; s < P.nb; ++s)
     pr[s] = SkinnyProb{P.d[s], P.d[s], 2 * P.k, P.Minv[s], P.d[s], false, B.Z[s], 2 * P.k, B.Wz[s], 2 * P.k};
@@ -687,6 +762,10 @@ static int rtr_run(const RcgProblem& P, RcgBuffers& B, RtrState& R, const double
     return gemm_skinny_batch(nb, pr, B.skw, B.skw_bytes, st);
   };
   auto minv = [&](double* const* X, double* const* Out) -> int {
+    if (P.wb[0] || P.wb[1]) {
+      for (int b = 0; b < nb; ++b) SRP_TRY(minv_apply(P, b, X[b], k, Out[b], B.skw, B.skw_bytes, st));
+      return SRP_OK;
+    }
     SkinnyProb pr[2];
     for (int b = 0; b < nb; ++b) pr[b] = SkinnyProb{d[b], d[b], k, P.Minv[b], d[b], false, X[b], k, Out[b], k};
     return gemm_skinny_batch(nb, pr, B.skw, B.skw_bytes, st);
@@ -922,12 +1001,15 @@ static size_t sketch_ws(int kind, int64_t n, int d, int s, int dtype) {
 // start from exact-cca(SX, SY) / exact-fda(SX) (sketch-and-solve), then
 // qf_B of it.  M_b = (S A_b)^T (S A_b) + lam_b I and M_b^-1 are at hand.
 struct WarmStart {
-  int kind = 0;                  // 0: none (Gaussian start), 1: CCA, 2: FDA
+  int kind = 0;                  // 0: none (Gaussian start), 1: CCA, 2: FDA, 3: CCA with a Woodbury block
   int iters = 0;                 // CCA: block subspace iterations
   const double* Hxy = nullptr;   // CCA: (S X)^T (S Y), dx x dy
   const double* Rinv[2] = {nullptr, nullptr};   // CCA: R_x^-1, R_y^-1 (upper)
   const double* Yhat = nullptr;  // FDA: c x d between-class factor
   int c = 0;
+  const void* SA[2] = {nullptr, nullptr};   // CCA with a Woodbury block: the sketches S X, S Y
+  bool sa_f32 = false;
+  int s = 0;
   char* ws = nullptr;            // scratch (warm_ws_bytes)
   size_t ws_bytes = 0;
 };
@@ -1043,6 +1125,82 @@ static int warm_cca(const RcgProblem& P, const WarmStart& w, double* const* out,
   return SRP_OK;
 }
 
+// CCA when a block's metric is in Woodbury form (no R^-1 to whiten with).
+// The sketched weights solve H v = sigma M_x u, H^T u = sigma M_y v for
+// H = (S X)^T (S Y), so v is an eigenvector of A = M_y^-1 H^T M_x^-1 H,
+// which is self-adjoint in the M_y inner product.  Block subspace
+// iteration V <- qf_My(A V) (H and H^T applied as two skinny products
+// through the s x q middle, M^-1 by minv_apply), then Rayleigh-Ritz:
+// with U = M_x^-1 H V, V^T M_y A V = (H V)^T U (q x q), whose top
+// eigenvectors Q give V Q and U Q (U Q = M_x^-1 H V Q: the left weights up
+// to positive column scales, which the qf start removes).
+static int warm_cca_pencil(const RcgProblem& P, const WarmStart& w, double* const* out, int* flag, uint64_t seed,
+                           hipStream_t st) {
+  const int dx = P.d[0], dy = P.d[1], k = P.k, s = w.s, q = warm_block(dx, dy, k), dm = std::max(dx, dy);
+  const int ldq = cholqr_block(q);
+  Arena a{w.ws, w.ws_bytes, 0};
+  double* V = a.take<double>((size_t)dy * q);
+  double* Vn = a.take<double>((size_t)dy * q);
+  double* Z = a.take<double>((size_t)dy * q);
+  double* U = a.take<double>((size_t)dx * q);
+  double* H = a.take<double>((size_t)dx * q);
+  double* T = a.take<double>((size_t)s * q);
+  double* G = a.take<double>((size_t)q * q);
+  double* G2 = a.take<double>((size_t)q * q);
+  double* Bm = a.take<double>((size_t)64 * 64);
+  double* Q = a.take<double>((size_t)q * k);
+  double* ev = a.take<double>(64);
+  const size_t skb = std::max({skinny_ws_bytes(dm, dm, q), skinny_ws_bytes(s, dm, q), skinny_ws_bytes(dm, s, q),
+                               skinny_ws_bytes(q, dm, q), skinny_ws_bytes(q, s, q)});
+  double* skw = (double*)a.take<char>(skb);
+  if (!skw) { set_error("warm start: workspace too small"); return SRP_ENOMEM; }
+  const bool f32 = w.sa_f32;
+  // C (m x nc) = op(A) B for a sketch A (FP32 or FP64)
+  auto mmS = [&](int m, int kk, int nc, const void* A, int64_t lda, bool ta, const double* Bp, int64_t ldb,
+                 double* C) {
+    SkinnyProb pr{m, kk, nc, A, lda, ta, Bp, ldb, C, nc};
+    pr.a_f32 = f32;
+    return gemm_skinny_batch(1, &pr, skw, skb, st);
+  };
+  auto mm = [&](int m, int kk, int nc, const double* A, int64_t lda, bool ta, const double* Bp, int64_t ldb,
+                double* C) { return gemm_skinny_f64(m, kk, nc, A, lda, ta, Bp, ldb, C, nc, skw, skb, st); };
+  // Vout = qf_My(Vin): G = (S Y Vin)^T (S Y Vin) + lam_y Vin^T Vin, L^-T by Cholesky-QR
+  auto qf_y = [&](const double* Vin, double* Vout) -> int {
+    SRP_TRY(mmS(s, dy, q, w.SA[1], dy, false, Vin, q, T));
+    SRP_TRY(mm(q, s, q, T, q, true, T, q, G));
+    SRP_TRY(mm(q, dy, q, Vin, q, true, Vin, q, G2));
+    RtrLinArgs la{};
+    la.k = q;
+    la.side[0] = RtrLinSide{G, G, 1.0, G2, P.lam[1], nullptr, q};
+    SRP_TRY(rtr_lin(la, 1, st));
+    SRP_TRY(launch_cholqr_factor(G, q, Bm, flag, st));
+    return gemm_skinny_f64(dy, q, q, Vin, q, false, Bm, ldq, Vout, q, skw, skb, st);
+  };
+  // Hout = H V = (S X)^T (S Y V)
+  auto apply_h = [&](const double* Vin, double* Hout) -> int {
+    SRP_TRY(mmS(s, dy, q, w.SA[1], dy, false, Vin, q, T));
+    return mmS(dx, s, q, w.SA[0], dx, true, T, q, Hout);
+  };
+  SRP_TRY(launch_gauss_fill(Vn, (int64_t)dy * q, seed ^ 0x5741524D53544152ull, st));
+  SRP_TRY(qf_y(Vn, V));
+  const int iters = std::max(1, w.iters);
+  for (int it = 0; it < iters; ++it) {
+    SRP_TRY(apply_h(V, H));
+    SRP_TRY(minv_apply(P, 0, H, q, U, skw, skb, st));
+    SRP_TRY(mmS(s, dx, q, w.SA[0], dx, false, U, q, T));       // S X U
+    SRP_TRY(mmS(dy, s, q, w.SA[1], dy, true, T, q, Z));        // H^T U
+    SRP_TRY(minv_apply(P, 1, Z, q, Vn, skw, skb, st));
+    SRP_TRY(qf_y(Vn, V));
+  }
+  SRP_TRY(apply_h(V, H));
+  SRP_TRY(minv_apply(P, 0, H, q, U, skw, skb, st));
+  SRP_TRY(mm(q, dx, q, H, q, true, U, q, G));                  // (H V)^T M_x^-1 (H V)
+  SRP_TRY(launch_rr_eig(G, q, k, Q, ev, st));
+  SRP_TRY(gemm_skinny_f64(dx, q, k, U, q, false, Q, k, out[0], k, skw, skb, st));
+  SRP_TRY(gemm_skinny_f64(dy, q, k, V, q, false, Q, k, out[1], k, skw, skb, st));
+  return SRP_OK;
+}
+
 // FDA.  The sketched problem S_B w = rho M w with S_B = Yhat^T Yhat has its
 // solutions in the range of M^-1 Yhat^T: w = M^-1 Yhat^T p with
 // (Yhat M^-1 Yhat^T) p = rho p, a c x c eigenproblem.
@@ -1058,7 +1216,7 @@ static int warm_lda(const RcgProblem& P, const WarmStart& w, double* const* out,
   double* skw = (double*)a.take<char>(skb);
   if (!skw) { set_error("warm start: workspace too small"); return SRP_ENOMEM; }
   SRP_TRY(transpose_f64(w.Yhat, c, d, Yt, st));
-  SRP_TRY(gemm_skinny_f64(d, d, c, P.Minv[0], d, false, Yt, c, T, c, skw, skb, st));   // M^-1 Yhat^T
+  SRP_TRY(minv_apply(P, 0, Yt, c, T, skw, skb, st));                                  // M^-1 Yhat^T
   SRP_TRY(gemm_skinny_f64(c, d, c, w.Yhat, d, false, T, c, K, c, skw, skb, st));        // Yhat M^-1 Yhat^T
   SRP_TRY(launch_rr_eig(K, c, k, Q, ev, st));
   SRP_TRY(gemm_skinny_f64(d, c, k, T, c, false, Q, k, out[0], k, skw, skb, st));
@@ -1123,6 +1281,9 @@ static int solve_tail(RcgProblem& full, const WarmStart& warm, RcgBuffers& B, co
     if (warm.kind == 1) {
       SRP_TRY(warm_cca(full, warm, outW, wflag, ca.opt.seed, warm.Rinv[0], warm.Rinv[1], st));
       warm_iters = warm_cca_iters(full.d[0], full.d[1], k, warm.iters);
+    } else if (warm.kind == 3) {
+      SRP_TRY(warm_cca_pencil(full, warm, outW, wflag, ca.opt.seed, st));
+      warm_iters = std::max(1, warm.iters);
     } else {
       SRP_TRY(warm_lda(full, warm, outW, st));
       warm_iters = 1;
@@ -1278,8 +1439,11 @@ static int setup_mu(const srp_options& o, int k, double* mu_dev, hipStream_t st)
 // with d (fewer upper tiles take a deeper split).
 static size_t cca_view_scratch(int64_t n, int dx, int dy, int k, int s, int dtype, int sketch_kind) {
   const int dd[2] = {dx, dy};
-  return std::max({sketch_ws(sketch_kind, n, dx, s, dtype), sketch_ws(sketch_kind, n, dy, s, dtype),
-                   factor_ws_bytes(s, dx), factor_ws_bytes(s, dy), warm_ws_bytes(2, k, dd, 0)});
+  size_t m = std::max({sketch_ws(sketch_kind, n, dx, s, dtype), sketch_ws(sketch_kind, n, dy, s, dtype),
+                       factor_ws_bytes(s, dx), factor_ws_bytes(s, dy), warm_ws_bytes(2, k, dd, 0)});
+  for (int d : dd)
+    if (s < d) m = std::max(m, woodbury_factor_scratch(s, d));
+  return m;
 }
 
 size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sketch_kind, int skin_dtype) {
@@ -1296,6 +1460,8 @@ size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sket
   const size_t scratch = cca_view_scratch(n, dx, dy, k, s, dtype, sketch_kind);
   bytes += rcg_buffers_bytes(2, k, std::max<int64_t>(n, s), dd, dtype);
   bytes += 2 * ((scratch + 255) & ~size_t(255)) + 4096;   // one scratch per view (the views run concurrently)
+  for (int d : dd)
+    if (s < d) bytes += woodbury_keep_bytes(s, d);
   return bytes;
 }
 
@@ -1308,8 +1474,9 @@ size_t lda_ws_bytes(int64_t n, int d, int c, int k, int s, int dtype, int sketch
   bytes += (((size_t)s * d * ssz + 255) & ~size_t(255));          // sketch
   bytes += 3 * bytes_of<double>((size_t)d * d);                    // R, Rinv, Minv
   bytes += bytes_of<double>((size_t)c * d) + bytes_of<int>(c) + bytes_of<int>(4);
-  const size_t scratch = std::max({sketch_ws(sketch_kind, n, d, s, dtype), factor_ws_bytes(s, d),
-                                   lda_center_ws_bytes(n, d, c), warm_ws_bytes(1, k, dd, c)});
+  size_t scratch = std::max({sketch_ws(sketch_kind, n, d, s, dtype), factor_ws_bytes(s, d),
+                             lda_center_ws_bytes(n, d, c), warm_ws_bytes(1, k, dd, c)});
+  if (s < d) scratch = std::max(scratch, woodbury_factor_scratch(s, d)) + woodbury_keep_bytes(s, d);
   bytes += rcg_buffers_bytes(1, k, std::max<int64_t>(n, s), dd, dtype, c);
   bytes += scratch + 4096;
   return bytes;
@@ -1343,9 +1510,12 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   SRP_REQUIRE(n >= 1 && n < (int64_t(1) << 31), "n out of range");
   SRP_REQUIRE(dx >= 1 && dy >= 1, "dx, dy must be positive");
   SRP_REQUIRE(k >= 1 && k <= std::min(dx, dy) && k <= 16, "need 1 <= k <= min(dx, dy), k <= 16");
-  SRP_REQUIRE(s >= std::max(dx, dy), "sketch_size must be >= max(dx, dy)");
   SRP_REQUIRE(lx >= 0.0 && ly >= 0.0, "lambda must be >= 0");
   SRP_REQUIRE(tol >= 0.0, "tol must be >= 0");
+  // s < d: the view's metric in Woodbury form, which needs lambda > 0
+  const bool wbx = s < dx, wby = s < dy;
+  SRP_REQUIRE(s >= 1 && (!wbx || lx > 0.0) && (!wby || ly > 0.0),
+              "sketch_size < d needs lambda > 0 for that view (the Woodbury form of M^-1)");
   int compute = opt.pass_compute == -1 ? (dtype == SRP_F64 ? SRP_F64 : SRP_F32) : opt.pass_compute;
   // FP64 arithmetic falls back to two GEMM reads of the data where the fused pass has no instance
   const bool f64_ok = opt.final_f64 == 0 || dtype != SRP_BF16;
@@ -1402,6 +1572,14 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
     set_error("workspace layout overflow");
     return SRP_ENOMEM;
   }
+  Arena wkeep[2];
+  Woodbury wbs[2];
+  for (int b = 0; b < 2; ++b)
+    if (s < dd[b]) {
+      const size_t kb = woodbury_keep_bytes(s, dd[b]);
+      wkeep[b] = Arena{ar.take<char>(kb), kb, 0};
+      if (!wkeep[b].base) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+    }
   SRP_TRY(setup_mu(opt, k, B.mu, st));
   SRP_TRY(fill_i32(flag, 1, 0, st));
   // 1-2. sketches (same S for X and Y) and metric factors: the Y view on the
@@ -1425,17 +1603,20 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SY, s, dy, opt.sketch_scale_y, fk.side));
   {
     Arena sub{sy.base, sy.cap, 0};
-    SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side));
+    if (wby) SRP_TRY(woodbury_factor(SY, sk_dtype, s, dy, ly, Ry, My, flag, sub, wkeep[1], &wbs[1], fk.side));
+    else SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side));
   }
   SRP_TRY(sketch_any(opt.sketch, skin_x, skin_dtype, n, dx, s, opt.seed, SX, sx, st, planp));
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SX, s, dx, opt.sketch_scale_x, st));
   const double ms_sketch = tm.lap_ms();   // X view's sketch (Y's runs alongside)
   {
     Arena sub{sx.base, sx.cap, 0};
-    SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st));
+    if (wbx) SRP_TRY(woodbury_factor(SX, sk_dtype, s, dx, lx, Rx, Mx, flag, sub, wkeep[0], &wbs[0], st));
+    else SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st));
   }
   SRP_TRY(fk.end(st));
-  if (warm) {   // cross Gram (S X)^T (S Y), split over the s rows in the X view's scratch
+  const bool pencil = wbx || wby;   // no R^-1 for a Woodbury view: the warm start iterates on the pencil
+  if (warm && !pencil) {   // cross Gram (S X)^T (S Y), split over the s rows in the X view's scratch
     const int64_t cnt = (int64_t)dx * dy;
     int ks = gram_split(s, dx, dy);
     ks = (int)std::max<int64_t>(1, std::min<int64_t>(ks, (int64_t)(scr / bytes_of<double>((size_t)cnt))));
@@ -1462,8 +1643,13 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   full.nb = 2; full.k = k; full.lda_cost = 0; full.dtype = dtype; full.compute = compute;
   full.A[0] = X; full.A[1] = Y; full.n = n; full.d[0] = dx; full.d[1] = dy;
   full.lam[0] = lx; full.lam[1] = ly; full.Minv[0] = Mx; full.Minv[1] = My;
+  full.wb[0] = wbx ? &wbs[0] : nullptr;
+  full.wb[1] = wby ? &wbs[1] : nullptr;
   WarmStart ws;
-  if (warm) {   // the X view's scratch is free once the cross Gram is summed
+  if (warm && pencil) {
+    ws.kind = 3; ws.iters = opt.warm_start_iters; ws.SA[0] = SX; ws.SA[1] = SY; ws.sa_f32 = sk_dtype != SRP_F64;
+    ws.s = s; ws.ws = sx.base; ws.ws_bytes = sx.cap;
+  } else if (warm) {   // the X view's scratch is free once the cross Gram is summed
     ws.kind = 1; ws.iters = opt.warm_start_iters; ws.Hxy = Hxy; ws.Rinv[0] = Rinv; ws.Rinv[1] = Rinv2;
     ws.ws = sx.base; ws.ws_bytes = sx.cap;
   }
@@ -1502,8 +1688,9 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   SRP_REQUIRE(c >= 2 && c <= kLdaMaxClasses && d >= 1, "need 2 <= n_classes <= %d and d >= 1", kLdaMaxClasses);
   SRP_REQUIRE(k >= 1 && k <= std::min(c - 1, d) && k <= KMAX, "need 1 <= k <= min(c-1, d), k <= 32");
   SRP_REQUIRE(opt.method != SRP_RTR || k <= kRtrK, "the trust-region method needs k <= %d", kRtrK);
-  SRP_REQUIRE(s >= d, "sketch_size must be >= d");
   SRP_REQUIRE(lam >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
+  const bool wbm = s < d;   // the metric in Woodbury form
+  SRP_REQUIRE(s >= 1 && (!wbm || lam > 0.0), "sketch_size < d needs lambda > 0 (the Woodbury form of M^-1)");
   int compute = opt.pass_compute == -1 ? (dtype == SRP_F64 ? SRP_F64 : SRP_F32) : opt.pass_compute;
   SRP_REQUIRE(opt.final_f64 == 0 || dtype != SRP_BF16, "FP64 closing iterations need F32 or F64 data");
   SRP_REQUIRE(pass_limits_ok(dtype, compute, d, 0, k, 1) || (compute == SRP_F64 && dtype != SRP_BF16),
@@ -1553,7 +1740,14 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   SRP_TRY(sketch_any(opt.sketch, Xhat, dtype, n, d, s, opt.seed, SXh, ar, st));
   const double ms_sketch = tm.lap_ms();
   SRP_TRY(fill_i32(flag, 1, 0, st));
-  {
+  Woodbury wbs;
+  if (wbm) {
+    const size_t kb = woodbury_keep_bytes(s, d);
+    Arena keep{ar.take<char>(kb), kb, 0};
+    Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
+    if (!keep.base) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+    SRP_TRY(woodbury_factor(SXh, sk_dtype, s, d, lam, R, Minv, flag, sub, keep, &wbs, st));
+  } else {
     Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
     SRP_TRY(sketch_factor_run(SXh, sk_dtype, s, d, lam, R, Rinv, Minv, flag, sub, st));
   }
@@ -1570,6 +1764,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   full.nb = 1; full.k = k; full.lda_cost = 1; full.dtype = dtype; full.compute = compute;
   full.A[0] = Xhat; full.n = n; full.d[0] = d; full.lam[0] = lam; full.Minv[0] = Minv; full.Yhat = Yhat;
   full.c = c;
+  full.wb[0] = wbm ? &wbs : nullptr;
   WarmStart ws;
   if (warm) {   // scratch past the solve's buffers (the sketch's and factor's, now free)
     ws.kind = 2; ws.Yhat = Yhat; ws.c = c;
@@ -1611,8 +1806,10 @@ static int csr_common_checks(const srp_options& opt) {
 static size_t csr_scratch(const CsrView* A, int nv, int s, int k, int c) {
   size_t m = 0;
   int dd[2] = {A[0].d, nv == 2 ? A[1].d : 0};
-  for (int b = 0; b < nv; ++b)
+  for (int b = 0; b < nv; ++b) {
     m = std::max({m, csc_scratch_bytes(A[b]), countsketch_csr_ws_bytes(A[b].n, s), factor_ws_bytes(s, A[b].d)});
+    if (s < A[b].d) m = std::max(m, woodbury_factor_scratch(s, A[b].d));
+  }
   m = std::max(m, warm_ws_bytes(nv, k, dd, c));
   if (nv == 2) m = std::max(m, bytes_of<double>((size_t)dd[0] * dd[1]));
   return m + 4096;
@@ -1627,6 +1824,8 @@ size_t cca_csr_ws_bytes(const CsrView& X, const CsrView& Y, int k, int s) {
   b += 2 * bytes_of<double>((size_t)dm * dm) + bytes_of<int>(4) + bytes_of<double>((size_t)dx * dy);
   b += csc_bytes(X) + csc_bytes(Y) + csc_partial_bytes(X, 2 * k) + csc_partial_bytes(Y, 2 * k);
   b += rcg_buffers_bytes(2, k, std::max<int64_t>(X.n, s), dd, SRP_F64);
+  for (int q = 0; q < 2; ++q)
+    if (s < dd[q]) b += woodbury_keep_bytes(s, dd[q]);
   return b + csr_scratch(v, 2, s, k, 0) + 4096;
 }
 
@@ -1637,6 +1836,7 @@ size_t lda_csr_ws_bytes(const CsrView& X, int c, int k, int s) {
   b += 3 * bytes_of<double>((size_t)d * d) + 3 * bytes_of<double>((size_t)c * d) + bytes_of<double>((size_t)c * k);
   b += bytes_of<int>(c) + bytes_of<int>(4) + csc_bytes(X) + csc_partial_bytes(X, k);
   b += rcg_buffers_bytes(1, k, std::max<int64_t>(X.n, s), dd, SRP_F64, c);
+  if (s < d) b += woodbury_keep_bytes(s, d);
   return b + csr_scratch(&X, 1, s, k, c) + 4096;
 }
 
@@ -1664,8 +1864,10 @@ int cca_solve_csr_impl(const CsrView& X, const CsrView& Y, int k, double lx, dou
   const int64_t n = X.n;
   const int dx = X.d, dy = Y.d;
   SRP_REQUIRE(k >= 1 && k <= std::min(dx, dy) && k <= 16, "need 1 <= k <= min(dx, dy), k <= 16");
-  SRP_REQUIRE(s >= std::max(dx, dy), "sketch_size must be >= max(dx, dy)");
   SRP_REQUIRE(lx >= 0.0 && ly >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
+  const bool wbv[2] = {s < dx, s < dy};
+  SRP_REQUIRE(s >= 1 && (!wbv[0] || lx > 0.0) && (!wbv[1] || ly > 0.0),
+              "sketch_size < d needs lambda > 0 for that view (the Woodbury form of M^-1)");
   PhaseTimer tm(st);
   const size_t bytes = cca_csr_ws_bytes(X, Y, k, s);
   const CsrView views[2] = {X, Y};
@@ -1695,6 +1897,14 @@ int cca_solve_csr_impl(const CsrView& X, const CsrView& Y, int k, double lx, dou
     set_error("workspace layout overflow");
     return SRP_ENOMEM;
   }
+  Arena wkeep[2];
+  Woodbury wbs[2];
+  for (int b = 0; b < 2; ++b)
+    if (wbv[b]) {
+      const size_t kb = woodbury_keep_bytes(s, dd[b]);
+      wkeep[b] = Arena{ar.take<char>(kb), kb, 0};
+      if (!wkeep[b].base) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+    }
   SRP_TRY(setup_mu(opt, k, B.mu, st));
   if (ar.used + scr > ar.cap) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
   Arena keep{ar.base + ar.used, ar.cap - ar.used - scr, 0};
@@ -1715,14 +1925,17 @@ int cca_solve_csr_impl(const CsrView& X, const CsrView& Y, int k, double lx, dou
   const double ms_sketch = tm.lap_ms();
   {
     Arena t{scratch_base, scr, 0};
-    SRP_TRY(sketch_factor_run(SX, SRP_F64, s, dx, lx, Rx, Rinv, Mx, flag, t, st));
+    if (wbv[0]) SRP_TRY(woodbury_factor(SX, SRP_F64, s, dx, lx, Rx, Mx, flag, t, wkeep[0], &wbs[0], st));
+    else SRP_TRY(sketch_factor_run(SX, SRP_F64, s, dx, lx, Rx, Rinv, Mx, flag, t, st));
   }
   {
     Arena t{scratch_base, scr, 0};
-    SRP_TRY(sketch_factor_run(SY, SRP_F64, s, dy, ly, Ry, Rinv2, My, flag, t, st));
+    if (wbv[1]) SRP_TRY(woodbury_factor(SY, SRP_F64, s, dy, ly, Ry, My, flag, t, wkeep[1], &wbs[1], st));
+    else SRP_TRY(sketch_factor_run(SY, SRP_F64, s, dy, ly, Ry, Rinv2, My, flag, t, st));
   }
   const bool warm = opt.warm_start_iters > 0;
-  if (warm) {
+  const bool pencil = wbv[0] || wbv[1];
+  if (warm && !pencil) {
     const int64_t cnt = (int64_t)dx * dy;
     int ks = gram_split(s, dx, dy);
     ks = (int)std::max<int64_t>(1, std::min<int64_t>(ks, (int64_t)(scr / bytes_of<double>((size_t)cnt))));
@@ -1749,8 +1962,13 @@ int cca_solve_csr_impl(const CsrView& X, const CsrView& Y, int k, double lx, dou
   full.n = n; full.d[0] = dx; full.d[1] = dy;
   full.lam[0] = lx; full.lam[1] = ly; full.Minv[0] = Mx; full.Minv[1] = My;
   full.sp = &sd;
+  full.wb[0] = wbv[0] ? &wbs[0] : nullptr;
+  full.wb[1] = wbv[1] ? &wbs[1] : nullptr;
   WarmStart ws;
-  if (warm) {
+  if (warm && pencil) {
+    ws.kind = 3; ws.iters = opt.warm_start_iters; ws.SA[0] = SX; ws.SA[1] = SY; ws.sa_f32 = false; ws.s = s;
+    ws.ws = scratch_base; ws.ws_bytes = scr;
+  } else if (warm) {
     ws.kind = 1; ws.iters = opt.warm_start_iters; ws.Hxy = Hxy; ws.Rinv[0] = Rinv; ws.Rinv[1] = Rinv2;
     ws.ws = scratch_base; ws.ws_bytes = scr;
   }
@@ -1784,8 +2002,9 @@ int lda_solve_csr_impl(const CsrView& X, const int32_t* labels, int c, int k, do
   SRP_REQUIRE(c >= 2 && c <= kLdaMaxClasses, "need 2 <= n_classes <= %d", kLdaMaxClasses);
   SRP_REQUIRE(k >= 1 && k <= std::min(c - 1, d) && k <= KMAX, "need 1 <= k <= min(c-1, d), k <= 32");
   SRP_REQUIRE(opt.method != SRP_RTR || k <= kRtrK, "the trust-region method needs k <= %d", kRtrK);
-  SRP_REQUIRE(s >= d, "sketch_size must be >= d");
   SRP_REQUIRE(lam >= 0.0 && tol >= 0.0, "lambda and tol must be >= 0");
+  const bool wbm = s < d;
+  SRP_REQUIRE(s >= 1 && (!wbm || lam > 0.0), "sketch_size < d needs lambda > 0 (the Woodbury form of M^-1)");
   PhaseTimer tm(st);
   const size_t bytes = lda_csr_ws_bytes(X, c, k, s);
   const size_t scr = csr_scratch(&X, 1, s, k, c);
@@ -1853,9 +2072,17 @@ int lda_solve_csr_impl(const CsrView& X, const int32_t* labels, int c, int k, do
   }
   const double ms_sketch = tm.lap_ms();
   SRP_TRY(fill_i32(flag, 1, 0, st));
+  Woodbury wbs;
   {
     Arena t{scratch_base, scr, 0};
-    SRP_TRY(sketch_factor_run(SXh, SRP_F64, s, d, lam, R, Rinv, Minv, flag, t, st));
+    if (wbm) {
+      const size_t kb = woodbury_keep_bytes(s, d);
+      Arena wk{keep.take<char>(kb), kb, 0};
+      if (!wk.base) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
+      SRP_TRY(woodbury_factor(SXh, SRP_F64, s, d, lam, R, Minv, flag, t, wk, &wbs, st));
+    } else {
+      SRP_TRY(sketch_factor_run(SXh, SRP_F64, s, d, lam, R, Rinv, Minv, flag, t, st));
+    }
   }
   int hflag = 0;
   SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1870,6 +2097,7 @@ int lda_solve_csr_impl(const CsrView& X, const int32_t* labels, int c, int k, do
   full.nb = 1; full.k = k; full.lda_cost = 1; full.dtype = SRP_F64; full.compute = SRP_F64;
   full.n = n; full.d[0] = d; full.lam[0] = lam; full.Minv[0] = Minv; full.Yhat = Yhat; full.c = c;
   full.sp = &sd;
+  full.wb[0] = wbm ? &wbs : nullptr;
   WarmStart ws;
   if (opt.warm_start_iters > 0) {
     ws.kind = 2; ws.Yhat = Yhat; ws.c = c;

@@ -798,12 +798,13 @@ __global__ void k_gram_full(const double* __restrict__ parts, int nparts, int64_
   H[e] = v;
 }
 
-__global__ void k_transpose_f64(const double* __restrict__ A, int rows, int cols, double* __restrict__ AT) {
+template <class T>
+__global__ void k_transpose_f64(const T* __restrict__ A, int rows, int cols, double* __restrict__ AT) {
   __shared__ double t[32][33];
   const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 8 rows of 32
   for (int r = ty; r < 32; r += 8)
-    if (r0 + r < rows && c0 + tx < cols) t[r][tx] = A[(int64_t)(r0 + r) * cols + c0 + tx];
+    if (r0 + r < rows && c0 + tx < cols) t[r][tx] = to_f64(A[(int64_t)(r0 + r) * cols + c0 + tx]);
   __syncthreads();
   for (int c = ty; c < 32; c += 8)
     if (c0 + c < cols && r0 + tx < rows) AT[(int64_t)(c0 + c) * rows + r0 + tx] = t[tx][c];
@@ -811,7 +812,17 @@ __global__ void k_transpose_f64(const double* __restrict__ A, int rows, int cols
 
 int transpose_f64(const double* A, int rows, int cols, double* AT, hipStream_t st) {
   if (rows <= 0 || cols <= 0) return SRP_OK;
-  hipLaunchKernelGGL(k_transpose_f64, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st, A, rows, cols, AT);
+  hipLaunchKernelGGL(k_transpose_f64<double>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st, A, rows,
+                     cols, AT);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+int transpose_to_f64(const void* A, int dtype, int rows, int cols, double* AT, hipStream_t st) {
+  if (dtype == SRP_F64) return transpose_f64((const double*)A, rows, cols, AT, st);
+  if (rows <= 0 || cols <= 0) return SRP_OK;
+  hipLaunchKernelGGL(k_transpose_f64<float>, dim3((cols + 31) / 32, (rows + 31) / 32), dim3(256), 0, st,
+                     (const float*)A, rows, cols, AT);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }

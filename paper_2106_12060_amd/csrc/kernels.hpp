@@ -89,6 +89,8 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
 int gram_split(int s, int d0, int d1);
 // AT (cols x rows) = A^T for row-major A (rows x cols).
 int transpose_f64(const double* A, int rows, int cols, double* AT, hipStream_t st);
+// The same from an SRP_F64 or SRP_F32 matrix (FP32 entries widened).
+int transpose_to_f64(const void* A, int dtype, int rows, int cols, double* AT, hipStream_t st);
 
 // --------------------------------------------------------- data pass
 // J_b = A_b^T [A_0 W_0 | A_1 W_1] (see srp_gram_pass).  Arithmetic in
