@@ -100,8 +100,11 @@ size_t staged_bytes(const srp_request& q) {
 
 bool sizes_ok(const srp_request& q) {
   if (q.n < 1 || q.n >= (int64_t(1) << 31) || q.k < 1 || q.sketch_size < 1 || q.dx < 1 || q.dy < 1) return false;
-  if (q.problem == SRP_PROBLEM_CCA) return q.sketch_size >= std::max(q.dx, q.dy);
-  if (q.problem == SRP_PROBLEM_LDA) return q.dy >= 2 && q.sketch_size >= q.dx && q.stage == SRP_STAGE_NONE;
+  // a sketch narrower than a view keeps that view's metric in Woodbury form, which needs lambda > 0
+  if (q.problem == SRP_PROBLEM_CCA)
+    return (q.sketch_size >= q.dx || q.lambda_x > 0.0) && (q.sketch_size >= q.dy || q.lambda_y > 0.0);
+  if (q.problem == SRP_PROBLEM_LDA)
+    return q.dy >= 2 && (q.sketch_size >= q.dx || q.lambda_x > 0.0) && q.stage == SRP_STAGE_NONE;
   return false;
 }
 

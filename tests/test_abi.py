@@ -85,9 +85,16 @@ def test_request_footprint_host_only():
     ws8 = L.srp_cca_workspace_bytes(50000, 300, 200, 8, 1200, srp.SRP_F32, srp.SRP_COUNTSKETCH, srp.SRP_FP8E4M3)
     assert f2 == (al(2 * 50000 * 300) + al(2 * 50000 * 200) + al(50000 * 300) + al(50000 * 200)
                   + al(8 * 300) + al(8 * 200) + ws8)
-    req.sketch_size = 100   # smaller than max(dx, dy)
+    req.sketch_size = 100   # smaller than max(dx, dy): the Woodbury form, which needs lambda > 0
+    lx, ly = req.lambda_x, req.lambda_y
+    req.lambda_x = 0.0
     assert L.srp_request_footprint(ctypes.byref(req)) == 0
-    assert L.srp_cca_workspace_bytes(50000, 300, 200, 8, 100, srp.SRP_F32, 0, srp.SRP_F32) == 0
+    req.lambda_x, req.lambda_y = lx, ly
+    assert L.srp_request_footprint(ctypes.byref(req)) > 0
+    assert L.srp_cca_workspace_bytes(50000, 300, 200, 8, 100, srp.SRP_F32, 0, srp.SRP_F32) > 0
+    req.sketch_size = 0
+    assert L.srp_request_footprint(ctypes.byref(req)) == 0
+    assert L.srp_cca_workspace_bytes(50000, 300, 200, 8, 0, srp.SRP_F32, 0, srp.SRP_F32) == 0
     assert L.srp_lda_workspace_bytes(50000, 300, 10, 9, 1200, srp.SRP_F32, 0) > 0
     assert L.srp_lda_workspace_bytes(50000, 300, 10, 10, 1200, srp.SRP_F32, 0) == 0
 
