@@ -30,6 +30,24 @@ ACCURACY_BAR = 1e-6
 DTYPE_NAMES = {"f64": "f64", "f32": "f32", "bf16": "bf16"}
 
 
+# How each dense workload's data recipe relates to the configuration it
+# stands for (printed in the bench line's config).
+RECIPE_NOTES = {
+    "cca-f32-srht": "latent rank 32 with strengths 10^(-2j/32) and noise 1.0; the FP32 CCA configuration states "
+                    "equal strengths and noise 0.1, whose top-32 correlations sit within 1e-5 of 1 (a random "
+                    "10-dimensional subspace of that cluster already meets the 1e-6 bar); that recipe as stated "
+                    "is workload cca-f32-srht-cfg1",
+    "cca-f32-srht-cfg1": "the FP32 CCA configuration's recipe as stated: latent Z ~ N(0,1) of rank 32, equal "
+                         "strengths, noise 0.1, column scales 10^(-4j/d)",
+    "cca-bf16-srht": "the cca-f32-srht data (strengths 10^(-2j/32), noise 1.0), staged to BF16 and FP8 E4M3",
+    "lda-f32": "the FDA configuration's recipe as stated",
+    "cca-f64-small": "latent strengths over one decade and noise 1.0 (the FP64 configuration states equal "
+                     "strengths and noise 0.1)",
+}
+WEIGHTS_NOTE = ("equal weights N = I (the unweighted trace cost sum sigma_i, ordered by the closing Rayleigh-Ritz "
+                "rotation); Algorithm CCAopt's distinct weights: --weights descending")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -537,6 +555,8 @@ def main():
            "config": {"workload": wl.name, "problem": wl.problem, "n": wl.n, "dx": wl.dx, "dy": wl.dy,
                       "k": wl.k, "lambda": lam, "sketch": wl.sketch, "s": wl.s, "tol": tol,
                       "weights": args.weights,
+                      "weights_note": WEIGHTS_NOTE if args.weights == "equal" else "N = diag(k, ..., 1)",
+                      "recipe": RECIPE_NOTES.get(wl.name, ""),
                       "warm_start_iters": warm,
                       "final_f64": extra.get("final_f64", 0),
                       "parallelism": "single-gpu"},
