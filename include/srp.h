@@ -447,6 +447,22 @@ typedef struct srp_engine srp_engine;
 /* Creates an engine on `device` with a pool of hbm_budget_bytes (allocated
  * once, here) and 1 <= max_slots <= 16 slots. */
 int srp_engine_create(int device, size_t hbm_budget_bytes, int max_slots, srp_engine** out);
+/* As srp_engine_create, with flags:
+ * SRP_ENGINE_GROUPED: grouped ticks.  The Riemannian CG iterations of the
+ *   running solves advance together: each solve's data pass runs on its
+ *   slot's stream, and each small step of an iteration (the line search's
+ *   inner products, controller and update; M^-1 Z, the direction's inner
+ *   products, controller and combination) runs for every solve in the tick
+ *   as ONE launch (a grid dimension per solve) on the engine's own stream,
+ *   between stream-event joins.  A solve's arithmetic is the same as alone
+ *   (same kernels per solve, same order), so each result is the same as
+ *   from the synchronous call.  Solves that cannot join (Woodbury metric,
+ *   trust-region method) run their own launches.
+ * Errors: SRP_EINVAL for unknown flags, as srp_engine_create otherwise. */
+#define SRP_ENGINE_GROUPED 1
+int srp_engine_create2(int device, size_t hbm_budget_bytes, int max_slots, int flags, srp_engine** out);
+/* Grouped phases launched so far (0 without SRP_ENGINE_GROUPED). */
+int srp_engine_ticks(srp_engine* e, uint64_t* ticks);
 /* Bytes of the engine pool a request needs: the solve's workspace plus the
  * staged copies (stage).  0 if the request's sizes are invalid. */
 size_t srp_request_footprint(const srp_request* req);

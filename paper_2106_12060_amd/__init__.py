@@ -10,6 +10,6 @@ from ._lib import (  # noqa: F401
     srp_default_options, srp_countsketch, srp_countsketch_noalloc, srp_srht, srp_srht_rows,
     srp_sketch_factor, srp_gram_pass, srp_gram_pass_kernel, cca_solve, lda_solve, srp_stage_bf16, srp_stage_fp8,
     SRP_EBUSY, SRP_EREJECTED, SRP_PENDING, SRP_PROBLEM_CCA, SRP_PROBLEM_LDA,
-    SRP_STAGE_NONE, SRP_STAGE_BF16, SRP_STAGE_BF16_FP8, SrpRequest, SrpResult, Engine,
+    SRP_STAGE_NONE, SRP_STAGE_BF16, SRP_STAGE_BF16_FP8, SRP_ENGINE_GROUPED, SrpRequest, SrpResult, Engine,
     SrpCsr, Csr, srp_countsketch_csr, srp_gram_pass_csr, cca_solve_csr, lda_solve_csr,
 )

@@ -102,6 +102,9 @@ _SIGS = {
     "srp_lda_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                   ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "srp_engine_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_P)]),
+    "srp_engine_create2": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(_P)]),
+    "srp_engine_ticks": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64)]),
     "srp_request_footprint": (ctypes.c_size_t, [ctypes.POINTER(SrpRequest)]),
     "srp_engine_submit": (ctypes.c_int, [_P, ctypes.POINTER(SrpRequest), ctypes.POINTER(ctypes.c_uint64)]),
     "srp_engine_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(SrpResult)]),
@@ -456,6 +459,7 @@ def lda_solve_csr(X: Csr, labels, n_classes, k, lam, sketch_size, tol=1e-6, opti
 
 # ------------------------------------------------------------ serving engine
 SRP_PROBLEM_CCA, SRP_PROBLEM_LDA = 0, 1
+SRP_ENGINE_GROUPED = 1
 SRP_STAGE_NONE, SRP_STAGE_BF16, SRP_STAGE_BF16_FP8 = 0, 1, 2
 
 
@@ -467,11 +471,13 @@ class Engine:
     streams, so submit first waits for torch's current stream (the inputs'
     producer); the tensors a request uses are held here until it ends."""
 
-    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, device: int | None = None):
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 4, device: int | None = None,
+                 grouped: bool = False):
         dev = torch.cuda.current_device() if device is None else int(device)
         h = ctypes.c_void_p()
-        _check("srp_engine_create", lib().srp_engine_create(dev, int(hbm_budget_bytes), int(max_slots),
-                                                             ctypes.byref(h)))
+        flags = SRP_ENGINE_GROUPED if grouped else 0
+        _check("srp_engine_create2", lib().srp_engine_create2(dev, int(hbm_budget_bytes), int(max_slots), flags,
+                                                               ctypes.byref(h)))
         self._h = h
         self.device = dev
         self._keep = {}
@@ -572,8 +578,10 @@ class Engine:
         u, pk = ctypes.c_size_t(), ctypes.c_size_t()
         _check("srp_engine_stats", lib().srp_engine_stats(self._h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(p),
                                                           ctypes.byref(u), ctypes.byref(pk)))
+        t = ctypes.c_uint64()
+        _check("srp_engine_ticks", lib().srp_engine_ticks(self._h, ctypes.byref(t)))
         return {"queued": q.value, "running": r.value, "peak_running": p.value, "pool_used": u.value,
-                "pool_peak": pk.value}
+                "pool_peak": pk.value, "grouped_ticks": t.value}
 
     def close(self):
         if self._h:

@@ -25,6 +25,7 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <condition_variable>
 
 namespace srp {
 
@@ -289,6 +290,7 @@ struct RcgBuffers {
   int* ran = nullptr;
   char* rtr_ws = nullptr;   // the trust-region solver's vectors
   size_t rtr_ws_bytes = 0;
+  TickGroup* group[2] = {nullptr, nullptr};   // grouped ticks (engine), for k <= 16 / k <= 32
 };
 
 __global__ void k_count_pass(const int* __restrict__ done, int* __restrict__ ran) {
@@ -545,6 +547,197 @@ static int direction_step(const RcgProblem& P, RcgBuffers& B, const ProbView& v,
   return SRP_OK;
 }
 
+// ------------------------------------------------------ grouped ticks
+// The serving engine runs several solves at once.  Their data passes are
+// their own (each on its solve's stream), but the small kernels of an
+// iteration (the line search's partials and controller, the update; then
+// M^-1 Z, the direction's partials and controller, the combination) are
+// latency-bound, a few microseconds of work behind a launch each.  A tick
+// group runs each of those steps for every member as one launch on the
+// group's stream: an iteration is two phases, and a phase fires when every
+// member has posted it (its stream's work so far recorded as an event);
+// the group's stream waits for all of them, launches the grouped kernels
+// and each member's stream waits for that in turn.  Members join and leave
+// between iterations.  Each member's arithmetic is the same as alone.
+struct TickMember {
+  int slot = -1;
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  ProbView v{};
+  PartialArgs ls{}, dir{};
+  const RcgProblem* P = nullptr;
+  int ntr = 0;
+  size_t lds_ls = 0, lds_dir = 0;
+  int dmax = 0;
+  size_t skw_need = 0;   // the M^-1 Z products' partials
+};
+
+struct TickGroup {
+  explicit TickGroup(int kc) : kc_(kc) {}
+  ~TickGroup() {
+    if (st_) (void)hipStreamSynchronize(st_);
+    if (views_) (void)hipFree(views_);
+    if (ls_) (void)hipFree(ls_);
+    if (dir_) (void)hipFree(dir_);
+    if (skw_) (void)hipFree(skw_);
+    if (ev_) (void)hipEventDestroy(ev_);
+    if (st_) (void)hipStreamDestroy(st_);
+  }
+  int init() {
+    SRP_HIP(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
+    SRP_HIP(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+    SRP_HIP(hipMalloc((void**)&views_, sizeof(ProbView) * kGroupMax));
+    SRP_HIP(hipMalloc((void**)&ls_, sizeof(PartialArgs) * kGroupMax));
+    SRP_HIP(hipMalloc((void**)&dir_, sizeof(PartialArgs) * kGroupMax));
+    skw_bytes_ = size_t(64) << 20;
+    SRP_HIP(hipMalloc((void**)&skw_, skw_bytes_));
+    return SRP_OK;
+  }
+  // A solve can join when its M^-1 products fit the group's partials
+  // (two views per chunk of four problems).
+  bool fits(const TickMember& m) const { return m.skw_need * 2 <= skw_bytes_; }
+  int join(TickMember& m) {
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_.wait(lk, [&] { return phase_ == 0; });
+    int slot = -1;
+    for (int i = 0; i < kGroupMax && slot < 0; ++i)
+      if (!used_[i]) slot = i;
+    if (slot < 0) return SRP_EBUSY;
+    used_[slot] = true;
+    m.slot = slot;
+    SRP_HIP(hipMemcpyAsync(views_ + slot, &m.v, sizeof(ProbView), hipMemcpyHostToDevice, st_));
+    SRP_HIP(hipMemcpyAsync(ls_ + slot, &m.ls, sizeof(PartialArgs), hipMemcpyHostToDevice, st_));
+    SRP_HIP(hipMemcpyAsync(dir_ + slot, &m.dir, sizeof(PartialArgs), hipMemcpyHostToDevice, st_));
+    SRP_HIP(hipStreamSynchronize(st_));
+    members_.push_back(&m);
+    return SRP_OK;
+  }
+  // Leaves between iterations (or, on an error, in the middle of one: the
+  // phase the others have posted then fires without it).
+  int leave(TickMember& m) {
+    std::unique_lock<std::mutex> lk(mu_);
+    members_.erase(std::remove(members_.begin(), members_.end(), &m), members_.end());
+    used_[m.slot] = false;
+    m.slot = -1;
+    int rc = SRP_OK;
+    if (!members_.empty() && posted_.size() == members_.size()) rc = fire();
+    cv_.notify_all();
+    return rc != SRP_OK ? rc : err_;
+  }
+  // Post phase `ph` of the current iteration for m; returns once the
+  // grouped launches of that phase are queued (m's stream waits for them).
+  int post(TickMember& m, int ph) {
+    SRP_HIP(hipEventRecord(m.ev, m.st));
+    std::unique_lock<std::mutex> lk(mu_);
+    cv_.wait(lk, [&] { return phase_ == ph; });
+    posted_.push_back(&m);
+    const uint64_t g = gen_;
+    if (posted_.size() == members_.size()) {
+      const int rc = fire();
+      if (rc != SRP_OK) err_ = rc;
+      cv_.notify_all();
+    } else {
+      cv_.wait(lk, [&] { return gen_ != g; });
+    }
+    return err_;
+  }
+  uint64_t ticks() const { return gen_; }
+
+ private:
+  int fire() {
+    GroupSel sel{};
+    sel.n = (int)posted_.size();
+    int slices = 1, dmax = 1, kmax = 1;
+    size_t lds = 0;
+    for (int i = 0; i < sel.n; ++i) {
+      TickMember* m = posted_[i];
+      SRP_HIP(hipStreamWaitEvent(st_, m->ev, 0));
+      sel.idx[i] = m->slot;
+      sel.aux[i] = m->ntr;
+      slices = std::max(slices, m->v.part_slices);
+      dmax = std::max(dmax, m->dmax);
+      kmax = std::max(kmax, m->v.k);
+      lds = std::max(lds, phase_ == 0 ? m->lds_ls : m->lds_dir);
+    }
+    if (phase_ == 0) {
+      SRP_TRY(launch_partials_g(ls_, sel, slices, (int64_t)(2 * kmax) * (6 * kmax), st_));
+      SRP_TRY(launch_ctrl_ls_g(views_, sel, lds, kc_, st_));
+      SRP_TRY(launch_update_g(views_, sel, 0, dmax, kc_, st_));
+    } else {
+      // M^-1 Z of every member's views, four problems per launch
+      std::vector<SkinnyProb> pr;
+      for (int i = 0; i < sel.n; ++i) {
+        const RcgProblem& P = *posted_[i]->P;
+        for (int b = 0; b < P.nb; ++b)
+          pr.push_back(SkinnyProb{P.d[b], P.d[b], 2 * P.k, P.Minv[b], P.d[b], false, posted_[i]->v.s[b].Z,
+                                  2 * P.k, posted_[i]->v.s[b].Wz, 2 * P.k});
+      }
+      for (size_t q = 0; q < pr.size(); q += 4) {
+        const int np = (int)std::min<size_t>(4, pr.size() - q);
+        SRP_TRY(gemm_skinny_batch(np, pr.data() + q, skw_, skw_bytes_, st_));
+      }
+      SRP_TRY(launch_partials_g(dir_, sel, slices, (int64_t)(2 * kmax) * (4 * kmax), st_));
+      SRP_TRY(launch_ctrl_dir_g(views_, sel, lds, kc_, st_));
+      SRP_TRY(launch_combine_g(views_, sel, (int64_t)dmax * kmax, kc_, st_));
+    }
+    SRP_HIP(hipEventRecord(ev_, st_));
+    for (TickMember* m : posted_) SRP_HIP(hipStreamWaitEvent(m->st, ev_, 0));
+    posted_.clear();
+    phase_ = 1 - phase_;
+    ++gen_;
+    return SRP_OK;
+  }
+
+  std::mutex mu_;
+  std::condition_variable cv_;
+  int phase_ = 0;
+  uint64_t gen_ = 0;
+  int err_ = SRP_OK;
+  std::vector<TickMember*> members_, posted_;
+  bool used_[kGroupMax] = {};
+  hipStream_t st_ = nullptr;
+  hipEvent_t ev_ = nullptr;
+  ProbView* views_ = nullptr;
+  PartialArgs* ls_ = nullptr;
+  PartialArgs* dir_ = nullptr;
+  double* skw_ = nullptr;
+  size_t skw_bytes_ = 0;
+  int kc_;
+};
+
+TickGroup* tick_group_create(int kc, int* status) {
+  auto* g = new TickGroup(kc);
+  const int rc = g->init();
+  if (status) *status = rc;
+  if (rc != SRP_OK) {
+    delete g;
+    return nullptr;
+  }
+  return g;
+}
+
+void tick_group_destroy(TickGroup* g) { delete g; }
+
+uint64_t tick_group_ticks(const TickGroup* g) { return g ? g->ticks() : 0; }
+
+// The member record of a solve (its grouped-launch parameters), or false
+// when the solve cannot take part (Woodbury metric, too large).
+static bool tick_member(const RcgProblem& P, const ProbView& v, hipStream_t st, TickMember* m) {
+  if (P.wb[0] || P.wb[1]) return false;
+  m->st = st;
+  m->v = v;
+  m->P = &P;
+  fill_partial_args(v, 0, &m->ls);
+  fill_partial_args(v, 1, &m->dir);
+  m->ntr = ctrl_ls_shape(P.k, P.nb, &m->lds_ls);
+  if (m->ntr < 1) return false;
+  m->lds_dir = ctrl_dir_lds(P.k, P.nb);
+  m->dmax = std::max(P.d[0], P.nb == 2 ? P.d[1] : 0);
+  m->skw_need = 0;
+  for (int b = 0; b < P.nb; ++b) m->skw_need += skinny_ws_bytes(P.d[b], P.d[b], 2 * P.k) + 256;
+  return true;
+}
+
 struct RcgResult {
   int status = SRP_OK;
   int iterations = 0;
@@ -634,18 +827,43 @@ static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int
   FlagPoll poll;
   SRP_TRY(poll.init());
   int passes_posted = passes;   // passes queued when the pending flag copy was
+  // grouped ticks (serving engine): this solve's small kernels run in the
+  // group's launches
+  TickGroup* grp = B.group[k <= 16 ? 0 : 1];
+  TickMember mem;
+  struct Ev {
+    hipEvent_t e = nullptr;
+    ~Ev() { if (e) (void)hipEventDestroy(e); }
+  } mev;
+  bool grouped = false;
+  if (grp && max_iter > 0 && tick_member(P, v, st, &mem) && grp->fits(mem)) {
+    SRP_HIP(hipEventCreateWithFlags(&mev.e, hipEventDisableTiming));
+    mem.ev = mev.e;
+    SRP_TRY(grp->join(mem));
+    grouped = true;
+  }
+  struct Leave {
+    TickGroup* g = nullptr;
+    TickMember* m = nullptr;
+    ~Leave() { if (g) (void)g->leave(*m); }
+  } leave_guard{grouped ? grp : nullptr, &mem};
   for (int it = 1; it <= max_iter; ++it) {
     SRP_TRY(data_pass(P, B, B.xi, P.compute, done, st));
     ++passes;
-    SRP_TRY(launch_ls_partials(v, st));
-    SRP_TRY(launch_ctrl_ls(v, st));
-    SRP_TRY(launch_update(v, 0, st));
+    if (grouped) {
+      SRP_TRY(grp->post(mem, 0));
+    } else {
+      SRP_TRY(launch_ls_partials(v, st));
+      SRP_TRY(launch_ctrl_ls(v, st));
+      SRP_TRY(launch_update(v, 0, st));
+    }
     if (refresh_every > 0 && it % refresh_every == 0) {
       SRP_TRY(data_pass(P, B, B.U, P.compute, done, st));
       ++passes;
       SRP_TRY(launch_update(v, 1, st));
     }
-    SRP_TRY(direction_step(P, B, v, st));
+    if (grouped) SRP_TRY(grp->post(mem, 1));
+    else SRP_TRY(direction_step(P, B, v, st));
     if (it % check_every == 0 || it == max_iter) {
       // the flag posted one batch ago: if set, this batch ran as no-ops
       bool was_done = false;
@@ -658,6 +876,10 @@ static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int
       SRP_TRY(poll.post(done, st));
       passes_posted = passes;
     }
+  }
+  if (grouped) {   // leave before the finish, so the group's ticks do not wait for it
+    leave_guard.g = nullptr;
+    SRP_TRY(grp->leave(mem));
   }
   SRP_TRY(read_ctrl(B.ctrl, &hc, st));
   res.status = hc.status;
@@ -1572,6 +1794,10 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
     set_error("workspace layout overflow");
     return SRP_ENOMEM;
   }
+  if (ctx) {
+    B.group[0] = ctx->group[0];
+    B.group[1] = ctx->group[1];
+  }
   Arena wkeep[2];
   Woodbury wbs[2];
   for (int b = 0; b < 2; ++b)
@@ -1722,6 +1948,10 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
   if (!flag || rcg_buffers_take(B, ar, 1, k, std::max<int64_t>(n, s), dd, c) != SRP_OK) {
     set_error("workspace layout overflow");
     return SRP_ENOMEM;
+  }
+  if (ctx) {
+    B.group[0] = ctx->group[0];
+    B.group[1] = ctx->group[1];
   }
   SRP_TRY(setup_mu(opt, k, B.mu, st));
   // 1. centring; S_B = Yhat^T Yhat stays factored

@@ -136,6 +136,7 @@ struct srp_engine {
   int running = 0, peak_running = 0;
   std::vector<hipStream_t> streams;
   std::vector<std::thread> workers;
+  TickGroup* groups[2] = {nullptr, nullptr};   // grouped ticks (SRP_ENGINE_GROUPED)
   std::chrono::steady_clock::time_point t0;
 
   double now_ms() const {
@@ -146,7 +147,7 @@ struct srp_engine {
 namespace {
 
 // Stages (if asked) and solves one admitted request inside its pool block.
-int run_job(const Job& job, char* block, hipStream_t st, srp_result& r) {
+int run_job(srp_engine* e, const Job& job, char* block, hipStream_t st, srp_result& r) {
   const srp_request& q = job.req;
   srp_options opt = q.opt;
   Arena ar{block, job.footprint, 0};
@@ -183,6 +184,8 @@ int run_job(const Job& job, char* block, hipStream_t st, srp_result& r) {
   ctx.side = nullptr;   // one stream per slot: both views in order on it
   ctx.ws = ar.base + ar.used;
   ctx.ws_bytes = ar.cap - ar.used;
+  ctx.group[0] = e->groups[0];
+  ctx.group[1] = e->groups[1];
   if (q.problem == SRP_PROBLEM_CCA)
     return cca_solve_impl(q.X, q.Y, q.n, q.dx, q.dy, q.k, q.lambda_x, q.lambda_y, q.sketch_size, q.tol, q.dtype,
                           &opt, st, q.U, q.V, q.sigma, &r.info, &ctx);
@@ -219,7 +222,7 @@ void worker(srp_engine* e, int slot) {
     r.footprint_bytes = job.footprint;
     lk.unlock();
     clear_error();
-    int rc = run_job(job, e->pool_mem + off, st, r);
+    int rc = run_job(e, job, e->pool_mem + off, st, r);
     // outputs are complete once the stream drains (the solve synchronises
     // it on success; an early error return may leave work queued)
     (void)hipStreamSynchronize(st);
@@ -252,10 +255,15 @@ extern "C" {
 size_t srp_request_footprint(const srp_request* req) { return req ? footprint(*req) : 0; }
 
 int srp_engine_create(int device, size_t hbm_budget_bytes, int max_slots, srp_engine** out) {
+  return srp_engine_create2(device, hbm_budget_bytes, max_slots, 0, out);
+}
+
+int srp_engine_create2(int device, size_t hbm_budget_bytes, int max_slots, int flags, srp_engine** out) {
   clear_error();
   SRP_REQUIRE(out, "null pointer argument");
   *out = nullptr;
   SRP_REQUIRE(max_slots >= 1 && max_slots <= kMaxSlots, "max_slots must be in [1, %d]", kMaxSlots);
+  SRP_REQUIRE((flags & ~SRP_ENGINE_GROUPED) == 0, "unknown engine flags %d", flags);
   SRP_REQUIRE(hbm_budget_bytes >= kAlign, "hbm_budget_bytes too small");
   int prev = 0;
   SRP_HIP(hipGetDevice(&prev));
@@ -281,6 +289,20 @@ int srp_engine_create(int device, size_t hbm_budget_bytes, int max_slots, srp_en
       delete e;
       (void)hipSetDevice(prev);
       return SRP_EDEVICE;
+    }
+  }
+  if (flags & SRP_ENGINE_GROUPED) {
+    for (int g = 0; g < 2; ++g) {
+      int rc = SRP_OK;
+      e->groups[g] = tick_group_create(g == 0 ? 16 : 32, &rc);
+      if (!e->groups[g]) {
+        for (int j = 0; j < g; ++j) tick_group_destroy(e->groups[j]);
+        for (auto st : e->streams) (void)hipStreamDestroy(st);
+        (void)hipFree(e->pool_mem);
+        delete e;
+        (void)hipSetDevice(prev);
+        return rc;
+      }
     }
   }
   for (int i = 0; i < max_slots; ++i) e->workers.emplace_back(worker, e, i);
@@ -350,6 +372,13 @@ int srp_engine_stats(srp_engine* e, int* queued, int* running, int* peak_running
   return SRP_OK;
 }
 
+int srp_engine_ticks(srp_engine* e, uint64_t* ticks) {
+  clear_error();
+  SRP_REQUIRE(e && ticks, "null pointer argument");
+  *ticks = tick_group_ticks(e->groups[0]) + tick_group_ticks(e->groups[1]);
+  return SRP_OK;
+}
+
 int srp_engine_destroy(srp_engine* e) {
   clear_error();
   if (!e) return SRP_OK;
@@ -362,6 +391,7 @@ int srp_engine_destroy(srp_engine* e) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(e->device);
+  for (auto& g : e->groups) tick_group_destroy(g);
   for (auto s : e->streams) (void)hipStreamDestroy(s);
   (void)hipFree(e->pool_mem);
   (void)hipSetDevice(prev);

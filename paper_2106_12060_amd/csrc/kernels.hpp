@@ -184,11 +184,21 @@ int scale_cols_run(float* A, int64_t rows, int d, const double* scales, hipStrea
 // (null = both views in order on the main stream); ws / ws_bytes: a
 // workspace the solve carves its buffers from (null = allocate from the
 // stream-ordered pool and release on return).
+struct TickGroup;
 struct SolveCtx {
   hipStream_t side = nullptr;
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  // the serving engine's grouped ticks (k <= 16 and k <= 32 solves): the
+  // iteration's small kernels of every solve in a group run as one launch
+  TickGroup* group[2] = {nullptr, nullptr};
 };
+// Groups of solves whose per-iteration small kernels run as grouped
+// launches (driver.hip).  kc: 16 or 32 (the kernels' k bound).
+TickGroup* tick_group_create(int kc, int* status);
+void tick_group_destroy(TickGroup* g);
+// Grouped ticks so far (the number of grouped phases launched).
+uint64_t tick_group_ticks(const TickGroup* g);
 size_t cca_ws_bytes(int64_t n, int dx, int dy, int k, int s, int dtype, int sketch_kind, int skin_dtype);
 size_t lda_ws_bytes(int64_t n, int d, int c, int k, int s, int dtype, int sketch_kind);
 size_t cca_csr_ws_bytes(const CsrView& X, const CsrView& Y, int k, int s);

@@ -59,6 +59,43 @@ struct ProbView {
   double eig_tol2;    // Jacobi stop of the direction step: off^2 <= eig_tol2 diag^2
 };
 
+// k-wide inner products over row slices:
+// out[y][z][a*k+i][b*k+j] = sum over rows r of slice z of L_a[r][i] R_b[r][j]
+// for side y.
+struct PartialSide {
+  int d, nl, nr;
+  const double* lp[4]; int lld[4];
+  const double* rp[6]; int rld[6];
+};
+struct PartialArgs {
+  int k, slices, nb;
+  PartialSide side[2];
+  double* out;            // [side][slices][nl*k][nr*k]
+  int64_t side_stride;
+  const SolverCtrl* ctrl;
+};
+// The partial products of a step for view p: kind 0 the line search's, 1
+// the direction's, 2 the finish's.
+void fill_partial_args(const ProbView& p, int kind, PartialArgs* a);
+
+// Grouped launches (the serving engine's ticks): one launch runs a step for
+// up to kGroupMax solves, each read from a device array of ProbView (or
+// PartialArgs) at index idx[z]; aux carries a per-solve launch parameter.
+constexpr int kGroupMax = 16;
+struct GroupSel {
+  int n;
+  int idx[kGroupMax];
+  int aux[kGroupMax];
+};
+int launch_partials_g(const PartialArgs* ga, const GroupSel& sel, int max_slices, int64_t max_nlnr,
+                      hipStream_t st);
+int ctrl_ls_shape(int k, int nb, size_t* lds);   // returns the trial count (< 1: k too large)
+size_t ctrl_dir_lds(int k, int nb);
+int launch_ctrl_ls_g(const ProbView* v, const GroupSel& sel, size_t lds, int kc, hipStream_t st);
+int launch_update_g(const ProbView* v, const GroupSel& sel, int refresh, int dmax, int kc, hipStream_t st);
+int launch_ctrl_dir_g(const ProbView* v, const GroupSel& sel, size_t lds, int kc, hipStream_t st);
+int launch_combine_g(const ProbView* v, const GroupSel& sel, int64_t max_dk, int kc, hipStream_t st);
+
 // Launchers (solver_kernels.hip).
 int launch_ls_partials(const ProbView& p, hipStream_t st);
 int launch_ctrl_ls(const ProbView& p, hipStream_t st);

@@ -48,19 +48,8 @@ __host__ __device__ __forceinline__ double* kkslot(const ProbView& p, int side, 
 }
 
 // ------------------------------------------------------------ partials
-// out[z][a*k+i][b*k+j] = sum over rows r in slice z of L_a[r][i] * R_b[r][j].
-struct PartialSide {
-  int d, nl, nr;
-  const double* lp[4]; int lld[4];
-  const double* rp[6]; int rld[6];
-};
-struct PartialArgs {
-  int k, slices;
-  PartialSide side[2];
-  double* out;            // [side][slices][nl*k][nr*k]
-  int64_t side_stride;
-  const SolverCtrl* ctrl;
-};
+// out[z][a*k+i][b*k+j] = sum over rows r in slice z of L_a[r][i] * R_b[r][j]
+// (PartialArgs in solver.hpp).
 
 constexpr int kPartRows = 16;
 constexpr int kMaxSlices = 64;   // row-slice partials per side (summed by k_part_reduce)
@@ -71,10 +60,10 @@ constexpr int kMaxSlices = 64;   // row-slice partials per side (summed by k_par
 // array) per step: a masked element takes an offset past the resource and
 // reads zero, so the loads issue unconditionally and a stage's loads are in
 // flight together; the next stage's loads overlap this stage's products.
-__global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
+__device__ __forceinline__ void partials_body(const PartialArgs& a, int z, int y) {
   if (a.ctrl && a.ctrl->done) return;
-  const PartialSide& ps = a.side[blockIdx.y];
-  const int k = a.k, z = blockIdx.x;
+  const PartialSide& ps = a.side[y];
+  const int k = a.k;
   const int NL = ps.nl * k, NR = ps.nr * k;
   const int MT = (NL + 15) >> 4, NT = (NR + 15) >> 4;
   __shared__ double ls[kPartRows][2 * KMAX];
@@ -155,7 +144,7 @@ __global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
     }
     __syncthreads();
   }
-  double* out = a.out + blockIdx.y * a.side_stride + (int64_t)z * NL * NR;
+  double* out = a.out + y * a.side_stride + (int64_t)z * NL * NR;
 #pragma unroll
   for (int q = 0; q < MAXT; ++q) {
     const int tt = w + 4 * q;
@@ -170,6 +159,16 @@ __global__ void __launch_bounds__(256) k_partials(PartialArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_partials(PartialArgs a) { partials_body(a, blockIdx.x, blockIdx.y); }
+
+// Grouped: blockIdx.z picks the solve (sel.idx), each with its own slices
+// and sides.
+__global__ void __launch_bounds__(256) k_partials_g(const PartialArgs* __restrict__ ga, GroupSel sel) {
+  const PartialArgs& a = ga[sel.idx[blockIdx.z]];
+  if ((int)blockIdx.x >= a.slices || (int)blockIdx.y >= a.nb) return;
+  partials_body(a, blockIdx.x, blockIdx.y);
+}
+
 int partial_slices(int dmax) {
   int s = (dmax + kPartRows - 1) / kPartRows;
   return s < kMaxSlices ? (s < 1 ? 1 : s) : kMaxSlices;
@@ -182,12 +181,12 @@ size_t partial_bytes(int k, int dmax) {
 // Sum of the row-slice partials in slice order, in place into slice 0 (one
 // thread per entry): the single-workgroup controllers then read one slice
 // instead of pulling every slice through one compute unit.
-__global__ void __launch_bounds__(256) k_part_reduce(double* __restrict__ part, int slices, int64_t side_stride,
-                                                     int64_t nlnr, const SolverCtrl* __restrict__ ctrl) {
+__device__ __forceinline__ void part_reduce_body(double* __restrict__ part, int slices, int64_t side_stride,
+                                                 int64_t nlnr, const SolverCtrl* __restrict__ ctrl, int64_t e,
+                                                 int y) {
   if (ctrl && ctrl->done) return;
-  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
   if (e >= nlnr) return;
-  double* base = part + blockIdx.y * side_stride + e;
+  double* base = part + y * side_stride + e;
   // the loads of all slices (at most kMaxSlices) in flight together, added
   // in slice order; one batch of 16 when there are no more
   double s = 0.0;
@@ -207,8 +206,21 @@ __global__ void __launch_bounds__(256) k_part_reduce(double* __restrict__ part, 
   base[0] = s;
 }
 
+__global__ void __launch_bounds__(256) k_part_reduce(double* __restrict__ part, int slices, int64_t side_stride,
+                                                     int64_t nlnr, const SolverCtrl* __restrict__ ctrl) {
+  part_reduce_body(part, slices, side_stride, nlnr, ctrl, blockIdx.x * 256ll + threadIdx.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(256) k_part_reduce_g(const PartialArgs* __restrict__ ga, GroupSel sel) {
+  const PartialArgs& a = ga[sel.idx[blockIdx.z]];
+  if (a.slices <= 1 || (int)blockIdx.y >= a.nb) return;
+  const int64_t nlnr = (int64_t)a.side[0].nl * a.k * a.side[0].nr * a.k;
+  part_reduce_body(a.out, a.slices, a.side_stride, nlnr, a.ctrl, blockIdx.x * 256ll + threadIdx.x, blockIdx.y);
+}
+
 static int run_partials(PartialArgs& a, int nb, hipStream_t st) {
   a.side_stride = (int64_t)a.slices * (4 * a.k) * (6 * a.k);
+  a.nb = nb;
   hipLaunchKernelGGL(k_partials, dim3(a.slices, nb), dim3(256), 0, st, a);
   SRP_LAUNCH_CHECK();
   if (a.slices > 1) {
@@ -233,59 +245,75 @@ __device__ void sum_block(const double* part, int slices, int nl, int nr, int k,
   }
 }
 
-int launch_ls_partials(const ProbView& p, hipStream_t st) {
-  PartialArgs a{};
-  a.k = p.k; a.slices = p.part_slices; a.out = p.part; a.ctrl = p.ctrl;
+void fill_partial_args(const ProbView& p, int kind, PartialArgs* out) {
+  PartialArgs& a = *out;
+  a = PartialArgs{};
+  a.k = p.k; a.slices = p.part_slices; a.out = p.part; a.ctrl = kind == 2 ? nullptr : p.ctrl;
+  a.nb = p.nb;
+  a.side_stride = (int64_t)a.slices * (4 * a.k) * (6 * a.k);
   const int k = p.k;
   for (int b = 0; b < p.nb; ++b) {
     const SideView& s = p.s[b];
     PartialSide& q = a.side[b];
-    q.d = s.d; q.nl = 2; q.nr = 6;
-    q.lp[0] = s.U; q.lld[0] = k;
-    q.lp[1] = s.xi; q.lld[1] = k;
-    q.rp[0] = s.Ks; q.rld[0] = k;
-    q.rp[1] = s.J + s.js_off; q.rld[1] = s.jld;
-    q.rp[2] = s.U; q.rld[2] = k;
-    q.rp[3] = s.xi; q.rld[3] = k;
-    q.rp[4] = s.Kc; q.rld[4] = k;
-    if (s.Jc_sep) { q.rp[5] = s.Jc_sep; q.rld[5] = k; }
-    else { q.rp[5] = s.J + s.jc_off; q.rld[5] = s.jld; }
+    q.d = s.d;
+    if (kind == 0) {   // line search: [U | xi]^T [Ks | Js | U | xi | Kc | Jc]
+      q.nl = 2; q.nr = 6;
+      q.lp[0] = s.U; q.lld[0] = k;
+      q.lp[1] = s.xi; q.lld[1] = k;
+      q.rp[0] = s.Ks; q.rld[0] = k;
+      q.rp[1] = s.J + s.js_off; q.rld[1] = s.jld;
+      q.rp[2] = s.U; q.rld[2] = k;
+      q.rp[3] = s.xi; q.rld[3] = k;
+      q.rp[4] = s.Kc; q.rld[4] = k;
+      if (s.Jc_sep) { q.rp[5] = s.Jc_sep; q.rld[5] = k; }
+      else { q.rp[5] = s.J + s.jc_off; q.rld[5] = s.jld; }
+    } else if (kind == 1) {   // direction: [B U | E]^T [M^-1 B U | M^-1 E | xi | gold]
+      q.nl = 2; q.nr = 4;
+      q.lp[0] = s.Z + k; q.lld[0] = 2 * k;
+      q.lp[1] = s.Z; q.lld[1] = 2 * k;
+      q.rp[0] = s.Wz + k; q.rld[0] = 2 * k;
+      q.rp[1] = s.Wz; q.rld[1] = 2 * k;
+      q.rp[2] = s.xi; q.rld[2] = k;
+      q.rp[3] = s.gold; q.rld[3] = k;
+    } else {   // finish: U^T [Ks | U | Kc]
+      q.nl = 1; q.nr = 3;
+      q.lp[0] = s.U; q.lld[0] = k;
+      q.rp[0] = s.Ks; q.rld[0] = k;
+      q.rp[1] = s.U; q.rld[1] = k;
+      q.rp[2] = s.Kc; q.rld[2] = k;
+    }
   }
+}
+
+int launch_ls_partials(const ProbView& p, hipStream_t st) {
+  PartialArgs a;
+  fill_partial_args(p, 0, &a);
   return run_partials(a, p.nb, st);
 }
 
 int launch_dir_partials(const ProbView& p, hipStream_t st) {
-  PartialArgs a{};
-  a.k = p.k; a.slices = p.part_slices; a.out = p.part; a.ctrl = p.ctrl;
-  const int k = p.k;
-  for (int b = 0; b < p.nb; ++b) {
-    const SideView& s = p.s[b];
-    PartialSide& q = a.side[b];
-    q.d = s.d; q.nl = 2; q.nr = 4;
-    q.lp[0] = s.Z + k; q.lld[0] = 2 * k;   // B U
-    q.lp[1] = s.Z; q.lld[1] = 2 * k;       // E
-    q.rp[0] = s.Wz + k; q.rld[0] = 2 * k;  // M^-1 B U
-    q.rp[1] = s.Wz; q.rld[1] = 2 * k;      // M^-1 E
-    q.rp[2] = s.xi; q.rld[2] = k;
-    q.rp[3] = s.gold; q.rld[3] = k;
-  }
+  PartialArgs a;
+  fill_partial_args(p, 1, &a);
   return run_partials(a, p.nb, st);
 }
 
 int launch_final_partials(const ProbView& p, hipStream_t st) {
-  PartialArgs a{};
-  a.k = p.k; a.slices = p.part_slices; a.out = p.part; a.ctrl = nullptr;
-  const int k = p.k;
-  for (int b = 0; b < p.nb; ++b) {
-    const SideView& s = p.s[b];
-    PartialSide& q = a.side[b];
-    q.d = s.d; q.nl = 1; q.nr = 3;
-    q.lp[0] = s.U; q.lld[0] = k;
-    q.rp[0] = s.Ks; q.rld[0] = k;
-    q.rp[1] = s.U; q.rld[1] = k;
-    q.rp[2] = s.Kc; q.rld[2] = k;
-  }
+  PartialArgs a;
+  fill_partial_args(p, 2, &a);
   return run_partials(a, p.nb, st);
+}
+
+int launch_partials_g(const PartialArgs* ga, const GroupSel& sel, int max_slices, int64_t max_nlnr,
+                      hipStream_t st) {
+  if (sel.n <= 0) return SRP_OK;
+  hipLaunchKernelGGL(k_partials_g, dim3(max_slices, 2, sel.n), dim3(256), 0, st, ga, sel);
+  SRP_LAUNCH_CHECK();
+  if (max_slices > 1) {
+    hipLaunchKernelGGL(k_part_reduce_g, dim3((unsigned)((max_nlnr + 255) / 256), 2, sel.n), dim3(256), 0, st, ga,
+                       sel);
+    SRP_LAUNCH_CHECK();
+  }
+  return SRP_OK;
 }
 
 // ------------------------------------------------- small dense helpers
@@ -585,7 +613,7 @@ __device__ __attribute__((noinline)) double eval_trial(const ProbView& p, const 
 constexpr int kLsThreads = 512;   // 8 trial steps per round
 
 template <int KC>
-__global__ void __launch_bounds__(kLsThreads) k_ctrl_ls(ProbView p, int ntr) {
+__device__ __forceinline__ void ctrl_ls_body(const ProbView& p, int ntr) {
   SolverCtrl* c = p.ctrl;
   if (c->done) return;
   extern __shared__ double sm[];
@@ -758,18 +786,33 @@ __global__ void __launch_bounds__(kLsThreads) k_ctrl_ls(ProbView p, int ntr) {
 }
 
 template <int KC>
-static int launch_ctrl_ls_t(const ProbView& p, hipStream_t st) {
-  const int k = p.k, nb = p.nb;
+__global__ void __launch_bounds__(kLsThreads) k_ctrl_ls(ProbView p, int ntr) { ctrl_ls_body<KC>(p, ntr); }
+
+// Grouped: one workgroup per solve, sel.aux holds each solve's trial count.
+template <int KC>
+__global__ void __launch_bounds__(kLsThreads) k_ctrl_ls_g(const ProbView* __restrict__ v, GroupSel sel) {
+  ctrl_ls_body<KC>(v[sel.idx[blockIdx.x]], sel.aux[blockIdx.x]);
+}
+
+int ctrl_ls_shape(int k, int nb, size_t* lds) {
   const size_t coef_bytes = (size_t)(3 * nb + 3) * k * k * sizeof(double);
   const size_t per_wave = (size_t)2 * nb * k * k * sizeof(double);
   const size_t budget = 156 * 1024;
   int ntr = (int)((budget - coef_bytes) / per_wave);
   if (ntr > kLsThreads / 64) ntr = kLsThreads / 64;
+  *lds = coef_bytes + (size_t)(ntr > 0 ? ntr : 0) * per_wave;
+  return ntr;
+}
+
+template <int KC>
+static int launch_ctrl_ls_t(const ProbView& p, hipStream_t st) {
+  const int k = p.k;
+  size_t lds = 0;
+  const int ntr = ctrl_ls_shape(k, p.nb, &lds);
   if (ntr < 1) {
     set_error("line search: k = %d too large for the LDS budget", k);
     return SRP_EINVAL;
   }
-  const size_t lds = coef_bytes + (size_t)ntr * per_wave;
   SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_ls<KC>, lds));
   hipLaunchKernelGGL(k_ctrl_ls<KC>, dim3(1), dim3(kLsThreads), lds, st, p, ntr);
   SRP_LAUNCH_CHECK();
@@ -781,6 +824,19 @@ int launch_ctrl_ls(const ProbView& p, hipStream_t st) {
   return launch_ctrl_ls_t<32>(p, st);
 }
 
+int launch_ctrl_ls_g(const ProbView* v, const GroupSel& sel, size_t lds, int kc, hipStream_t st) {
+  if (sel.n <= 0) return SRP_OK;
+  if (kc == 16) {
+    SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_ls_g<16>, lds));
+    hipLaunchKernelGGL(k_ctrl_ls_g<16>, dim3(sel.n), dim3(kLsThreads), lds, st, v, sel);
+  } else {
+    SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_ls_g<32>, lds));
+    hipLaunchKernelGGL(k_ctrl_ls_g<32>, dim3(sel.n), dim3(kLsThreads), lds, st, v, sel);
+  }
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
 // ------------------------------------------------------------- update
 // Per row: U+ = (U + t xi) Linv^T, Ks+ = (Ks + t Js) Linv^T,
 // Kc+ = (Kc + t Jc) Linv_o^T; then Z = [-Kc+ N | Ks+ + lam U+].
@@ -790,14 +846,13 @@ int launch_ctrl_ls(const ProbView& p, hipStream_t st) {
 constexpr int kUpdRows = 16;
 
 template <int KC>
-__global__ void __launch_bounds__(256) k_update(ProbView p, int refresh) {
+__device__ __forceinline__ void update_body(const ProbView& p, int refresh, int bx, int b) {
   const SolverCtrl* c = p.ctrl;
   if (c->done && refresh != 2) return;   // 2 = forced refresh after the loop
-  const int b = blockIdx.y;
   const SideView& s = p.s[b];
   const int o = (p.nb == 2) ? 1 - b : b;
   const int k = p.k;
-  const int r0 = blockIdx.x * kUpdRows;
+  const int r0 = bx * kUpdRows;
   if (r0 >= s.d) return;
   const int nr = min(kUpdRows, s.d - r0);
   __shared__ double LT[KMAX * KMAX], LTo[KMAX * KMAX], mu[KMAX];
@@ -854,6 +909,27 @@ __global__ void __launch_bounds__(256) k_update(ProbView p, int refresh) {
     Zi[j] = -kcn * mu[j];
     Zi[k + j] = ksn + s.lam * un;
   }
+}
+
+template <int KC>
+__global__ void __launch_bounds__(256) k_update(ProbView p, int refresh) {
+  update_body<KC>(p, refresh, blockIdx.x, blockIdx.y);
+}
+
+template <int KC>
+__global__ void __launch_bounds__(256) k_update_g(const ProbView* __restrict__ v, GroupSel sel, int refresh) {
+  const ProbView& p = v[sel.idx[blockIdx.z]];
+  if ((int)blockIdx.y >= p.nb) return;
+  update_body<KC>(p, refresh, blockIdx.x, blockIdx.y);
+}
+
+int launch_update_g(const ProbView* v, const GroupSel& sel, int refresh, int dmax, int kc, hipStream_t st) {
+  if (sel.n <= 0) return SRP_OK;
+  dim3 grid((dmax + kUpdRows - 1) / kUpdRows, 2, sel.n);
+  if (kc == 16) hipLaunchKernelGGL(k_update_g<16>, grid, dim3(256), 0, st, v, sel, refresh);
+  else hipLaunchKernelGGL(k_update_g<32>, grid, dim3(256), 0, st, v, sel, refresh);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
 }
 
 int launch_update(const ProbView& p, int refresh, hipStream_t st) {
@@ -1122,7 +1198,7 @@ __device__ __forceinline__ void group_mm_t(const double* A, int lda, bool ta, co
 // trace terms; thread 0 forms the Polak-Ribiere+ coefficient, the descent
 // test and the stopping test.
 template <int KC>
-__global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
+__device__ __forceinline__ void ctrl_dir_body(const ProbView& p) {
   SolverCtrl* c = p.ctrl;
   if (c->done) return;
   extern __shared__ double sm[];
@@ -1338,10 +1414,35 @@ __global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) {
 }
 
 template <int KC>
-static int launch_ctrl_dir_t(const ProbView& p, hipStream_t st) {
-  const int k = p.k, n = (k + 1) & ~1;
+__global__ void __launch_bounds__(512) k_ctrl_dir(ProbView p) { ctrl_dir_body<KC>(p); }
+
+template <int KC>
+__global__ void __launch_bounds__(512) k_ctrl_dir_g(const ProbView* __restrict__ v, GroupSel sel) {
+  ctrl_dir_body<KC>(v[sel.idx[blockIdx.x]]);
+}
+
+size_t ctrl_dir_lds(int k, int nb) {
+  const int n = (k + 1) & ~1;
   const size_t per_side = (size_t)(9 * k * k + 5 * n * n);
-  const size_t lds = (size_t)p.nb * per_side * sizeof(double);
+  return (size_t)nb * per_side * sizeof(double);
+}
+
+int launch_ctrl_dir_g(const ProbView* v, const GroupSel& sel, size_t lds, int kc, hipStream_t st) {
+  if (sel.n <= 0) return SRP_OK;
+  if (kc == 16) {
+    SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_dir_g<16>, lds));
+    hipLaunchKernelGGL(k_ctrl_dir_g<16>, dim3(sel.n), dim3(512), lds, st, v, sel);
+  } else {
+    SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_dir_g<32>, lds));
+    hipLaunchKernelGGL(k_ctrl_dir_g<32>, dim3(sel.n), dim3(512), lds, st, v, sel);
+  }
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
+}
+
+template <int KC>
+static int launch_ctrl_dir_t(const ProbView& p, hipStream_t st) {
+  const size_t lds = ctrl_dir_lds(p.k, p.nb);
   SRP_TRY(allow_dynamic_lds((const void*)k_ctrl_dir<KC>, lds));
   hipLaunchKernelGGL(k_ctrl_dir<KC>, dim3(1), dim3(512), lds, st, p);
   SRP_LAUNCH_CHECK();
@@ -1356,10 +1457,9 @@ int launch_ctrl_dir(const ProbView& p, hipStream_t st) {
 // ------------------------------------------------------------ combine
 // xi+ = -W_E + beta xi + W_B Phi ;  gold = W_E - W_B S   (element-wise).
 template <int KC>
-__global__ void __launch_bounds__(256) k_combine(ProbView p) {
+__device__ __forceinline__ void combine_body(const ProbView& p, int bx, int b) {
   const SolverCtrl* c = p.ctrl;
   if (c->done) return;
-  const int b = blockIdx.y;
   const SideView& s = p.s[b];
   const int k = p.k;
   __shared__ double S[KMAX * KMAX], Phi[KMAX * KMAX];
@@ -1367,7 +1467,7 @@ __global__ void __launch_bounds__(256) k_combine(ProbView p) {
   const double* gPhi = kkslot(p, b, KK_PHI);
   for (int e = threadIdx.x; e < k * k; e += 256) { S[e] = gS[e]; Phi[e] = gPhi[e]; }
   __syncthreads();
-  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t e = bx * 256ll + threadIdx.x;
   if (e >= (int64_t)s.d * k) return;
   const int i = sdiv((int)e, k), j = (int)e - i * k;
   const double* Wrow = s.Wz + (int64_t)i * 2 * k;   // [W_E | W_B]
@@ -1384,6 +1484,25 @@ __global__ void __launch_bounds__(256) k_combine(ProbView p) {
   const double beta = c->beta;
   s.xi[e] = -we + beta * s.xi[e] + wbphi;
   s.gold[e] = we - wbs;
+}
+
+template <int KC>
+__global__ void __launch_bounds__(256) k_combine(ProbView p) { combine_body<KC>(p, blockIdx.x, blockIdx.y); }
+
+template <int KC>
+__global__ void __launch_bounds__(256) k_combine_g(const ProbView* __restrict__ v, GroupSel sel) {
+  const ProbView& p = v[sel.idx[blockIdx.z]];
+  if ((int)blockIdx.y >= p.nb) return;
+  combine_body<KC>(p, blockIdx.x, blockIdx.y);
+}
+
+int launch_combine_g(const ProbView* v, const GroupSel& sel, int64_t max_dk, int kc, hipStream_t st) {
+  if (sel.n <= 0) return SRP_OK;
+  dim3 grid((unsigned)((max_dk + 255) / 256), 2, sel.n);
+  if (kc == 16) hipLaunchKernelGGL(k_combine_g<16>, grid, dim3(256), 0, st, v, sel);
+  else hipLaunchKernelGGL(k_combine_g<32>, grid, dim3(256), 0, st, v, sel);
+  SRP_LAUNCH_CHECK();
+  return SRP_OK;
 }
 
 int launch_combine(const ProbView& p, hipStream_t st) {

@@ -88,6 +88,72 @@ def test_alone_and_in_the_mix_agree():
         assert rec["t_submit_ms"] <= rec["t_start_ms"] <= rec["t_done_ms"]
 
 
+def test_grouped_ticks_match_alone():
+    """SRP_ENGINE_GROUPED: the running solves' small per-iteration kernels
+    run as one launch per step for all of them (grouped ticks); every
+    solve's arithmetic is the same as alone, so the outputs agree with the
+    synchronous call bit for bit, and with the oracle."""
+    srp = _srp()
+    data = [make(n, dx, dy, seed) for n, dx, dy, _, seed in MIX]
+    dev_data = [(dev(X), dev(Y)) for X, Y in data]
+    alone = []
+    for (n, dx, dy, k, _), (Xd, Yd) in zip(MIX, dev_data):
+        s = 4 * max(dx, dy)
+        alone.append(srp.cca_solve(Xd, Yd, k, LAM, LAM, s, tol=1e-6, options=opts(srp), mu=[1.0] * k))
+    with srp.Engine(4 * GiB, max_slots=4, grouped=True) as eng:
+        tickets = [eng.submit_cca(Xd, Yd, k, LAM, LAM, 4 * max(dx, dy), tol=1e-6, options=opts(srp), mu=[1.0] * k)
+                   for (n, dx, dy, k, _), (Xd, Yd) in zip(MIX, dev_data)]
+        mixed = [eng.wait(t) for t in tickets]
+        st = eng.stats()
+    print("grouped engine stats", st)
+    assert st["grouped_ticks"] > 0 and st["peak_running"] >= 2
+    for (n, dx, dy, k, _), (X, Y), a, m in zip(MIX, data, alone, mixed):
+        Ua, Va, sa, ia = a
+        Um, Vm, sm, rec = m
+        print(f"n={n} dx={dx} dy={dy} k={k}: it alone {ia['iterations']} grouped {rec['info']['iterations']}, "
+              f"latency {rec['t_done_ms'] - rec['t_submit_ms']:.1f} ms")
+        assert rec["status"] in (srp.SRP_OK, srp.SRP_ENOCONV)
+        assert rec["info"]["iterations"] == ia["iterations"]
+        assert torch.equal(sm, sa) and torch.equal(Um, Ua) and torch.equal(Vm, Va)
+        sig_true, _, _ = direct.cca_direct(X, Y, LAM, LAM)
+        em, cm = objective_error(Um, Vm, X, Y, sig_true)
+        assert em < 1e-6 and cm < 1e-6
+
+
+def test_grouped_ticks_with_fda_and_wide_k():
+    """Grouped ticks with FDA solves (one view) beside CCA solves, and an
+    FDA solve with k > 16 (its own group of the k <= 32 kernels)."""
+    srp = _srp()
+    jobs = []
+    X1, y1 = synth.lda_classes(9000, 80, 10, seed=3, dtype=np.float32)
+    X2, y2 = synth.lda_classes(8400, 120, 24, seed=4, dtype=np.float32)
+    lam = 1e-3 * float(np.mean(np.var(X1, axis=0)))
+    Xc, Yc = make(6000, 48, 40, 11)
+    with srp.Engine(4 * GiB, max_slots=3, grouped=True) as eng:
+        t1 = eng.submit_lda(dev(X1), dev(y1), 10, 9, lam, 320, tol=1e-6, options=opts(srp, final_f64=-1))
+        # equal weights: the top-20 subspace (rho_20 / rho_21 = 1.3) without
+        # resolving the close pairs inside it
+        t2 = eng.submit_lda(dev(X2), dev(y2), 24, 20, lam, 480, tol=1e-6, options=opts(srp, final_f64=-1),
+                            mu=[1.0] * 20)
+        t3 = eng.submit_cca(dev(Xc), dev(Yc), 4, LAM, LAM, 192, tol=1e-6, options=opts(srp), mu=[1.0] * 4)
+        r1, r2, r3 = eng.wait(t1), eng.wait(t2), eng.wait(t3)
+        st = eng.stats()
+    print("grouped engine stats", st)
+    assert st["grouped_ticks"] > 0
+    for (X, y, c, k), r in (((X1, y1, 10, 9), r1), ((X2, y2, 24, 20), r2)):
+        W, rho, rec = r
+        assert rec["status"] == srp.SRP_OK
+        rho_true, _ = direct.lda_direct(X, y, c, lam, k=k)
+        _, _, _, Xh, Yh = direct.lda_scatter(X, y, c)
+        err = metrics.lda_rel_objective_error(W.cpu().numpy(), Xh, Yh, lam, rho_true)
+        print("fda", c, k, rec["info"]["iterations"], err)
+        assert err < 1e-6
+    U, V, s, rec = r3
+    sig_true, _, _ = direct.cca_direct(Xc, Yc, LAM, LAM)
+    err, cons = objective_error(U, V, Xc, Yc, sig_true)
+    assert rec["status"] == srp.SRP_OK and err < 1e-6 and cons < 1e-6
+
+
 def test_admission_by_footprint_serialises_when_memory_is_short():
     """A pool that holds one request at a time admits them one by one, in
     order, and every result is still right."""
@@ -189,8 +255,8 @@ def test_engine_rejects_and_reports():
         with pytest.raises(srp.SrpError) as ei:
             eng.submit_cca(Xd, Yd, 4, LAM, LAM, 160, options=opts(srp))
         assert ei.value.code == srp.SRP_EREJECTED
-        with pytest.raises(srp.SrpError) as ei:
-            eng.submit_cca(Xd, Yd, 4, LAM, LAM, 20, options=opts(srp))   # sketch smaller than d
+        with pytest.raises(srp.SrpError) as ei:   # sketch smaller than d needs lambda > 0 (Woodbury form)
+            eng.submit_cca(Xd, Yd, 4, 0.0, LAM, 20, options=opts(srp))
         assert ei.value.code == srp.SRP_EINVAL
     with srp.Engine(1 * GiB, max_slots=1) as eng:
         # accepted, but the solve itself rejects k > min(dx, dy): the
