@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--workload", default="cca-f32-srht",
                     choices=sorted(synth.WORKLOADS) + sorted(synth.SPARSE_WORKLOADS) + ["serving"])
     ap.add_argument("--slots", type=int, default=4, help="serving: engine worker slots")
+    ap.add_argument("--grouped", type=int, default=0,
+                    help="serving: 1 = grouped ticks (the running solves' small kernels as one launch per step; "
+                         "0, the default, runs each solve's launches on its slot's stream, which measured faster "
+                         "on the mixed-size trace)")
     ap.add_argument("--hw-queues", type=int, default=None,
                     help="serving: HIP hardware queues for this process (GPU_MAX_HW_QUEUES, <= 16; "
                          "default: the number of slots when above HIP's default of 4)")
@@ -229,7 +233,7 @@ def serve(args):
         return eng.submit_cca(X, Y, q.k, lam, lam, 4 * max(q.dx, q.dy), tol=tol, options=opt(),
                               mu=[1.0] * q.k, stage=stage)
 
-    eng = srp.Engine(int(args.pool_gib * (1 << 30)), max_slots=args.slots)
+    eng = srp.Engine(int(args.pool_gib * (1 << 30)), max_slots=args.slots, grouped=bool(args.grouped))
     # untimed warm-up: a few requests (code objects, kernel attributes)
     for i in range(min(args.warmup * 4, len(trace))):
         eng.wait(submit(eng, i))
@@ -289,6 +293,7 @@ def serve(args):
                           "warm_mean": float(np.mean([r["info"]["warm_iterations"] for r in recs])),
                           "bf16_phase_mean": float(np.mean([r["info"]["lowp_iterations"] for r in recs]))},
            "engine": {"peak_running": st["peak_running"], "pool_peak_bytes": st["pool_peak"],
+                      "grouped": bool(args.grouped), "grouped_ticks": st["grouped_ticks"],
                       "span_ms": span_ms, "statuses": statuses, "bf16_phase_breakdowns": lowp_breakdowns,
                       "failures": failures},
            "roofline": {"bound": "hbm", "achieved": agg, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -553,12 +553,14 @@ static int direction_step(const RcgProblem& P, RcgBuffers& B, const ProbView& v,
 // iteration (the line search's partials and controller, the update; then
 // M^-1 Z, the direction's partials and controller, the combination) are
 // latency-bound, a few microseconds of work behind a launch each.  A tick
-// group runs each of those steps for every member as one launch on the
-// group's stream: an iteration is two phases, and a phase fires when every
-// member has posted it (its stream's work so far recorded as an event);
-// the group's stream waits for all of them, launches the grouped kernels
-// and each member's stream waits for that in turn.  Members join and leave
-// between iterations.  Each member's arithmetic is the same as alone.
+// group runs each of those steps for every member as one launch.  All of a
+// member's iteration work goes to the group's one stream while it is a
+// member (no cross-stream joins inside an iteration): an iteration is two
+// phases, a member queues its phase work (data pass; refresh) and posts
+// the phase, and the phase fires, queuing the grouped kernels behind every
+// member's work, when every member has posted it.  Members join and leave
+// between iterations (their own stream and the group's joined by events).
+// Each member's arithmetic is the same as alone.
 struct TickMember {
   int slot = -1;
   hipStream_t st = nullptr;
@@ -589,7 +591,7 @@ struct TickGroup {
     SRP_HIP(hipMalloc((void**)&views_, sizeof(ProbView) * kGroupMax));
     SRP_HIP(hipMalloc((void**)&ls_, sizeof(PartialArgs) * kGroupMax));
     SRP_HIP(hipMalloc((void**)&dir_, sizeof(PartialArgs) * kGroupMax));
-    skw_bytes_ = size_t(64) << 20;
+    skw_bytes_ = size_t(32) << 20;
     SRP_HIP(hipMalloc((void**)&skw_, skw_bytes_));
     return SRP_OK;
   }
@@ -624,10 +626,13 @@ struct TickGroup {
     cv_.notify_all();
     return rc != SRP_OK ? rc : err_;
   }
-  // Post phase `ph` of the current iteration for m; returns once the
-  // grouped launches of that phase are queued (m's stream waits for them).
+  // The group's stream: a member's iteration loop queues all its work
+  // (data passes, refreshes, polls) there while it is a member.
+  hipStream_t stream() const { return st_; }
+  // Post phase `ph` of the current iteration for m (its work for the phase
+  // already queued on the group's stream); returns once the grouped
+  // launches of that phase are queued behind it.
   int post(TickMember& m, int ph) {
-    SRP_HIP(hipEventRecord(m.ev, m.st));
     std::unique_lock<std::mutex> lk(mu_);
     cv_.wait(lk, [&] { return phase_ == ph; });
     posted_.push_back(&m);
@@ -651,7 +656,6 @@ struct TickGroup {
     size_t lds = 0;
     for (int i = 0; i < sel.n; ++i) {
       TickMember* m = posted_[i];
-      SRP_HIP(hipStreamWaitEvent(st_, m->ev, 0));
       sel.idx[i] = m->slot;
       sel.aux[i] = m->ntr;
       slices = std::max(slices, m->v.part_slices);
@@ -680,8 +684,6 @@ struct TickGroup {
       SRP_TRY(launch_ctrl_dir_g(views_, sel, lds, kc_, st_));
       SRP_TRY(launch_combine_g(views_, sel, (int64_t)dmax * kmax, kc_, st_));
     }
-    SRP_HIP(hipEventRecord(ev_, st_));
-    for (TickMember* m : posted_) SRP_HIP(hipStreamWaitEvent(m->st, ev_, 0));
     posted_.clear();
     phase_ = 1 - phase_;
     ++gen_;
@@ -836,17 +838,29 @@ static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int
     ~Ev() { if (e) (void)hipEventDestroy(e); }
   } mev;
   bool grouped = false;
+  const hipStream_t own = st;
   if (grp && max_iter > 0 && tick_member(P, v, st, &mem) && grp->fits(mem)) {
     SRP_HIP(hipEventCreateWithFlags(&mev.e, hipEventDisableTiming));
     mem.ev = mev.e;
     SRP_TRY(grp->join(mem));
     grouped = true;
+    // the loop's work goes to the group's stream, after this solve's own
+    SRP_HIP(hipEventRecord(mev.e, own));
+    SRP_HIP(hipStreamWaitEvent(grp->stream(), mev.e, 0));
+    st = grp->stream();
   }
+  // on an early return: leave, and make the solve's own stream wait for the
+  // work it queued on the group's stream (its buffers stay in use until then)
   struct Leave {
     TickGroup* g = nullptr;
     TickMember* m = nullptr;
-    ~Leave() { if (g) (void)g->leave(*m); }
-  } leave_guard{grouped ? grp : nullptr, &mem};
+    hipStream_t own = nullptr;
+    ~Leave() {
+      if (!g) return;
+      (void)g->leave(*m);
+      if (hipEventRecord(m->ev, g->stream()) == hipSuccess) (void)hipStreamWaitEvent(own, m->ev, 0);
+    }
+  } leave_guard{grouped ? grp : nullptr, &mem, own};
   for (int it = 1; it <= max_iter; ++it) {
     SRP_TRY(data_pass(P, B, B.xi, P.compute, done, st));
     ++passes;
@@ -880,6 +894,9 @@ static int rcg_run(const RcgProblem& P, RcgBuffers& B, double* const* start, int
   if (grouped) {   // leave before the finish, so the group's ticks do not wait for it
     leave_guard.g = nullptr;
     SRP_TRY(grp->leave(mem));
+    SRP_HIP(hipEventRecord(mev.e, st));
+    SRP_HIP(hipStreamWaitEvent(own, mev.e, 0));
+    st = own;
   }
   SRP_TRY(read_ctrl(B.ctrl, &hc, st));
   res.status = hc.status;

@@ -136,7 +136,11 @@ struct srp_engine {
   int running = 0, peak_running = 0;
   std::vector<hipStream_t> streams;
   std::vector<std::thread> workers;
-  TickGroup* groups[2] = {nullptr, nullptr};   // grouped ticks (SRP_ENGINE_GROUPED)
+  // grouped ticks (SRP_ENGINE_GROUPED): one group per (k bound, size
+  // class), so that the solves ticking together have passes of similar
+  // length (a tick waits for its slowest member's pass)
+  static constexpr int kSizeClasses = 5;
+  TickGroup* groups[2][kSizeClasses] = {};
   std::chrono::steady_clock::time_point t0;
 
   double now_ms() const {
@@ -184,8 +188,14 @@ int run_job(srp_engine* e, const Job& job, char* block, hipStream_t st, srp_resu
   ctx.side = nullptr;   // one stream per slot: both views in order on it
   ctx.ws = ar.base + ar.used;
   ctx.ws_bytes = ar.cap - ar.used;
-  ctx.group[0] = e->groups[0];
-  ctx.group[1] = e->groups[1];
+  {
+    // size class from the data read per pass, log4 steps from 2^20 elements
+    const double elems = (double)q.n * (q.dx + (q.problem == SRP_PROBLEM_CCA ? q.dy : 0));
+    int c = 0;
+    for (double t = double(1 << 20); elems >= t && c < srp_engine::kSizeClasses - 1; t *= 4.0) ++c;
+    ctx.group[0] = e->groups[0][c];
+    ctx.group[1] = e->groups[1][c];
+  }
   if (q.problem == SRP_PROBLEM_CCA)
     return cca_solve_impl(q.X, q.Y, q.n, q.dx, q.dy, q.k, q.lambda_x, q.lambda_y, q.sketch_size, q.tol, q.dtype,
                           &opt, st, q.U, q.V, q.sigma, &r.info, &ctx);
@@ -292,11 +302,16 @@ int srp_engine_create2(int device, size_t hbm_budget_bytes, int max_slots, int f
     }
   }
   if (flags & SRP_ENGINE_GROUPED) {
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < 2 * srp_engine::kSizeClasses; ++g) {
       int rc = SRP_OK;
-      e->groups[g] = tick_group_create(g == 0 ? 16 : 32, &rc);
-      if (!e->groups[g]) {
-        for (int j = 0; j < g; ++j) tick_group_destroy(e->groups[j]);
+      TickGroup*& slot = e->groups[g / srp_engine::kSizeClasses][g % srp_engine::kSizeClasses];
+      slot = tick_group_create(g < srp_engine::kSizeClasses ? 16 : 32, &rc);
+      if (!slot) {
+        for (auto& row : e->groups)
+          for (auto& t : row) {
+            tick_group_destroy(t);
+            t = nullptr;
+          }
         for (auto st : e->streams) (void)hipStreamDestroy(st);
         (void)hipFree(e->pool_mem);
         delete e;
@@ -375,7 +390,10 @@ int srp_engine_stats(srp_engine* e, int* queued, int* running, int* peak_running
 int srp_engine_ticks(srp_engine* e, uint64_t* ticks) {
   clear_error();
   SRP_REQUIRE(e && ticks, "null pointer argument");
-  *ticks = tick_group_ticks(e->groups[0]) + tick_group_ticks(e->groups[1]);
+  uint64_t t = 0;
+  for (auto& row : e->groups)
+    for (auto g : row) t += tick_group_ticks(g);
+  *ticks = t;
   return SRP_OK;
 }
 
@@ -391,7 +409,8 @@ int srp_engine_destroy(srp_engine* e) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(e->device);
-  for (auto& g : e->groups) tick_group_destroy(g);
+  for (auto& row : e->groups)
+    for (auto g : row) tick_group_destroy(g);
   for (auto s : e->streams) (void)hipStreamDestroy(s);
   (void)hipFree(e->pool_mem);
   (void)hipSetDevice(prev);
