@@ -1253,10 +1253,12 @@ struct WarmStart {
   size_t ws_bytes = 0;
 };
 
-// Block width of the CCA subspace iteration: 64 columns (the spectrum of the
-// sketched problem is flat past its leading correlations, so a wide block
-// converges in a few iterations), at most min(dx, dy).
-static int warm_block(int dx, int dy, int k) { return std::max(k, std::min(64, std::min(dx, dy))); }
+// Block width of the CCA subspace iteration: 32 columns for k <= 12, else
+// 64 (the spectrum of the sketched problem is flat past its leading
+// correlations, so a block a few times k wide converges in a few products;
+// the Rayleigh-Ritz eigensolve and the Cholesky-QR cost grow with the
+// block's square and cube), at most min(dx, dy).
+static int warm_block(int dx, int dy, int k) { return std::max(k, std::min(k <= 12 ? 32 : 64, std::min(dx, dy))); }
 // Subspace iterations per product: the block is multiplied by (C^T C)^4.
 constexpr int kWarmPower = 4;
 

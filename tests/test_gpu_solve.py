@@ -245,7 +245,7 @@ def test_cca_rejects_bad_arguments():
         srp.cca_solve(X, Y, 5, 0.1, 0.1, 20)          # k > min(dx, dy)
     assert e.value.code == srp.SRP_EINVAL
     with pytest.raises(srp.SrpError) as e:
-        srp.cca_solve(X, Y, 2, 0.1, 0.1, 5)           # s < max(dx, dy)
+        srp.cca_solve(X, Y, 2, 0.0, 0.1, 5)           # s < dx needs lambda_x > 0 (Woodbury form)
     assert e.value.code == srp.SRP_EINVAL
     with pytest.raises(srp.SrpError) as e:
         srp.cca_solve(X, Y, 2, -1.0, 0.1, 20)         # lambda < 0
