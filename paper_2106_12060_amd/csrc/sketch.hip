@@ -90,26 +90,61 @@ __global__ void k_cs_sort(const int* offsets, const int* list, int* sorted) {
   }
 }
 
-// One workgroup per bucket; each thread owns up to CPT columns.
+// One workgroup per bucket; each thread owns up to CPT columns.  The
+// bucket's row indices and signs are staged in LDS first, then the rows are
+// read four at a time (all their loads in flight together) and added in
+// ascending row order, one after the other.
 template <class T, class Acc, int CPT>
 __global__ void __launch_bounds__(256) k_cs_gather(const T* __restrict__ A, int d, uint64_t seed,
                                                    const int* __restrict__ offsets,
                                                    const int* __restrict__ sorted, Acc* __restrict__ out,
                                                    int col_base) {
+  constexpr int RB = 4;
+  __shared__ int rows_s[256];
+  __shared__ Acc sgn_s[256];
   const int b = blockIdx.x;
   const int beg = offsets[b], cnt = offsets[b + 1] - beg;
   const int c0 = col_base + threadIdx.x;
   Acc acc[CPT];
 #pragma unroll
   for (int j = 0; j < CPT; ++j) acc[j] = Acc(0);
-  for (int e = 0; e < cnt; ++e) {
-    const int row = sorted[beg + e];
-    const Acc g = (Acc)cs_sign(splitmix64(seed, (uint64_t)row));
-    const T* Ar = A + (int64_t)row * d;
+  const int nt = blockDim.x;   // <= 256: one index per thread and chunk
+  for (int base = 0; base < cnt; base += nt) {
+    const int m = min(nt, cnt - base);
+    __syncthreads();   // the previous chunk's indices are consumed
+    if ((int)threadIdx.x < m) {
+      const int row = sorted[beg + base + threadIdx.x];
+      rows_s[threadIdx.x] = row;
+      sgn_s[threadIdx.x] = (Acc)cs_sign(splitmix64(seed, (uint64_t)row));
+    }
+    __syncthreads();
+    int e = 0;
+    for (; e + RB <= m; e += RB) {
+      Acc v[RB][CPT];
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      const int c = c0 + j * (int)blockDim.x;
-      if (c < d) acc[j] += g * load_as<Acc>(Ar + c);
+      for (int r = 0; r < RB; ++r) {
+        const T* Ar = A + (int64_t)rows_s[e + r] * d;
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) {
+          const int c = c0 + j * (int)blockDim.x;
+          v[r][j] = c < d ? load_as<Acc>(Ar + c) : Acc(0);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const Acc g = sgn_s[e + r];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) acc[j] += g * v[r][j];
+      }
+    }
+    for (; e < m; ++e) {
+      const Acc g = sgn_s[e];
+      const T* Ar = A + (int64_t)rows_s[e] * d;
+#pragma unroll
+      for (int j = 0; j < CPT; ++j) {
+        const int c = c0 + j * (int)blockDim.x;
+        if (c < d) acc[j] += g * load_as<Acc>(Ar + c);
+      }
     }
   }
 #pragma unroll
