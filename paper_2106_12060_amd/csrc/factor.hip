@@ -631,68 +631,74 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
   __shared__ double rdiag[64];    // 1 / R[j][j]
   __shared__ double tsc[3][16][17];   // per-wave 16 x 16 scratch of the blocked inverse
   const int t = threadIdx.x;
-  // Thread t owns the entries e = t + 256 m of the row-major upper
-  // triangle (2080 entries, 9 slots) in registers for the whole
-  // factorisation.  Step j: the owners of row j publish it, one barrier,
-  // then every owner of an entry (r, c) with j < r <= c subtracts
-  // row[r] row[c] / row[j]; the owners of row j store it scaled by
-  // 1 / sqrt(pivot) (its final form).  Rows past nb are the identity.
-  constexpr int kSlots = 9;
-  int sr[kSlots], sc[kSlots];
-  double v[kSlots];
-#pragma unroll
-  for (int m = 0; m < kSlots; ++m) {
-    const int e = t + 256 * m;
-    int r = 0, rowlen = 64;
-    int rem = e < 2080 ? e : 0;
-    while (rem >= rowlen) { rem -= rowlen; ++r; --rowlen; }
-    const int c = r + rem;
-    sr[m] = e < 2080 ? r : 64;   // 64: no entry
-    sc[m] = c;
+  const int wv = t >> 6, ln = t & 63;
+  // The upper triangle of the block in LDS (rows past nb: the identity).
+  for (int e = t; e < 4096; e += 256) {
+    const int r = e >> 6, c = e & 63;
     double val = 0.0;
-    if (e < 2080) {
+    if (r <= c) {
       if (r < nb && c < nb) val = G[(int64_t)(k0 + r) * ld + k0 + c];
       else val = (r == c) ? 1.0 : 0.0;
     }
-    v[m] = val;
-  }
-  for (int j = 0; j < 64; ++j) {
-    double* rw = row[j & 1];
-#pragma unroll
-    for (int m = 0; m < kSlots; ++m)
-      if (sr[m] == j) rw[sc[m]] = v[m];
-    __syncthreads();
-    double p = rw[j];
-    const bool bad = !(p > 0.0) || !isfinite(p);
-    if (bad) p = 1.0;
-    if (t == 0) {
-      if (bad) atomicOr(flag, 1);
-      piv[j] = p;
-    }
-    const double rp = __builtin_amdgcn_rcp(p);
-    const double rpp = rp * fma(-p, rp, 2.0);
-    const double rinv = rpp * fma(-p, rpp, 2.0);      // 1 / p (two Newton steps)
-    double rs = __builtin_amdgcn_rsq(p);
-    rs = rs * fma(-0.5 * p * rs, rs, 1.5);
-    rs = rs * fma(-0.5 * p * rs, rs, 1.5);           // 1 / sqrt(p)
-    if (t == 0) rdiag[j] = rs;
-    // every slot reads its two row entries (row[64] for empty slots), so the
-    // loads issue together and no load sits under a branch
-    double fr[kSlots], fc[kSlots];
-#pragma unroll
-    for (int m = 0; m < kSlots; ++m) {
-      fr[m] = rw[sr[m]];
-      fc[m] = rw[sc[m]];
-    }
-#pragma unroll
-    for (int m = 0; m < kSlots; ++m) {
-      const int r = sr[m], c = sc[m];
-      const double upd = v[m] - fr[m] * fc[m] * rinv;
-      if (r == j) a[j][c] = (c == j) ? p * rs : v[m] * rs;   // sqrt(p) on the diagonal
-      v[m] = (r > j && r < 64) ? upd : v[m];
-    }
+    a[r][c] = val;
   }
   __syncthreads();
+  // Four panels of 16 rows, right-looking.  Wave 0 factors a panel alone
+  // with lane c holding rows p0 .. p0+15 of column c in registers: step j
+  // takes the pivot from lane p0+j, scales row j and subtracts its outer
+  // product from the rows below, the row-j entries of the other columns
+  // broadcast by readlane (no barrier inside the panel).  Then all waves
+  // subtract the panel's rows' products from the trailing triangle.
+  for (int p0 = 0; p0 < 64; p0 += 16) {
+    if (wv == 0) {
+      double pr[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) pr[i] = a[p0 + i][ln];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int pl = p0 + j;   // lane (column) of the pivot
+        double p = __shfl(pr[j], pl, 64);
+        const bool bad = !(p > 0.0) || !isfinite(p);
+        if (bad) p = 1.0;
+        double rs = __builtin_amdgcn_rsq(p);
+        rs = rs * fma(-0.5 * p * rs, rs, 1.5);
+        rs = rs * fma(-0.5 * p * rs, rs, 1.5);   // 1 / sqrt(p), two Newton steps
+        if (ln == 0) {
+          if (bad) atomicOr(flag, 1);
+          piv[pl] = p;
+          rdiag[pl] = rs;
+        }
+        const double rj = pr[j] * rs;   // row j of R in column ln (ln >= pl)
+#pragma unroll
+        for (int i = j + 1; i < 16; ++i) {
+          const double rji = __shfl(rj, p0 + i, 64);   // R[j][p0 + i]
+          pr[i] = fma(-rji, rj, pr[i]);
+        }
+        pr[j] = rj;
+      }
+      if (ln >= p0) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (p0 + i <= ln) a[p0 + i][ln] = pr[i];
+      }
+    }
+    __syncthreads();
+    const int q0 = p0 + 16;
+    if (q0 < 64) {
+      // a[r][c] -= sum_i R[p0+i][r] R[p0+i][c] for q0 <= r <= c < 64
+      const int m = 64 - q0;
+      for (int e = t; e < m * m; e += 256) {
+        const int r = q0 + e / m, c = q0 + e % m;
+        if (r <= c) {
+          double sacc = a[r][c];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) sacc = fma(-a[p0 + i][r], a[p0 + i][c], sacc);
+          a[r][c] = sacc;
+        }
+      }
+      __syncthreads();
+    }
+  }
   // x = a^-1 (upper) by 16 x 16 blocks: the four diagonal blocks by
   // back-substitution (wave w inverts block w; four lanes per column),
   // then the blocks at distance d = 1, 2, 3 from the diagonal as
@@ -700,7 +706,6 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
   // needs only blocks closer to the diagonal).
   for (int e = t; e < 4096; e += 256) x[e >> 6][e & 63] = 0.0;
   __syncthreads();
-  const int wv = t >> 6, ln = t & 63;
   {
     const int c = ln >> 2, q = ln & 3, o = 16 * wv;
     for (int r = 15; r >= 0; --r) {
