@@ -122,8 +122,8 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int m, int n, int kk, double a
 // Large A^T B (the sketch Grams): one workgroup = one 128 x 128 output
 // tile, each wave a 64 x 64 quadrant of 4 x 4 MFMA tiles (two products per
 // LDS operand read); the contraction runs in stages of 16 through two LDS
-// buffers, the next stage's global loads in flight during this stage's
-// products.
+// buffers, the global loads of the next two stages in flight during a
+// stage's products.
 constexpr int kGemmBigK = 16;
 template <class AT, class BT>
 __global__ void __launch_bounds__(256) k_gemm_f64_big(int m, int n, int kk, double alpha, const AT* __restrict__ A,
@@ -146,9 +146,12 @@ __global__ void __launch_bounds__(256) k_gemm_f64_big(int m, int n, int kk, doub
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  AT ra[PER];
-  BT rb[PER];
-  auto load = [&](int k0) __attribute__((always_inline)) {
+  // Two register sets of staged operands: the loads of the stages two and
+  // three ahead are in flight while a stage is multiplied (one stage of
+  // products is shorter than a load's latency from HBM).
+  AT ra0[PER], ra1[PER];
+  BT rb0[PER], rb1[PER];
+  auto load = [&](int k0, AT (&ra)[PER], BT (&rb)[PER]) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = t + q * 256;
@@ -158,7 +161,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64_big(int m, int n, int kk, doub
       rb[q] = (gj < n && gk < kend) ? B[(int64_t)gk * ldb + gj] : BT(0);
     }
   };
-  auto store = [&](int buf) __attribute__((always_inline)) {
+  auto store = [&](int buf, const AT (&ra)[PER], const BT (&rb)[PER]) __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int e = t + q * 256;
@@ -166,15 +169,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64_big(int m, int n, int kk, doub
       Bs[buf][e >> 7][e & 127] = (double)rb[q];
     }
   };
-  int buf = 0;
-  if (kbeg < kend) {
-    load(kbeg);
-    store(0);
-  }
-  __syncthreads();
-  for (int k0 = kbeg; k0 < kend; k0 += KS) {
-    const bool more = k0 + KS < kend;
-    if (more) load(k0 + KS);
+  auto compute = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < KS / 4; ++s) {
       const int kl = 4 * s + (lane >> 4);
@@ -188,9 +183,26 @@ __global__ void __launch_bounds__(256) k_gemm_f64_big(int m, int n, int kk, doub
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
     }
-    if (more) store(buf ^ 1);
+  };
+  if (kbeg < kend) {
+    load(kbeg, ra0, rb0);
+    store(0, ra0, rb0);
+    if (kbeg + KS < kend) load(kbeg + KS, ra0, rb0);
+    if (kbeg + 2 * KS < kend) load(kbeg + 2 * KS, ra1, rb1);
+  }
+  __syncthreads();
+  // even stages in buffer 0, odd ones in buffer 1; set 0 carries the
+  // stages 1, 3, ... ahead, set 1 the stages 2, 4, ...
+  for (int k0 = kbeg; k0 < kend; k0 += 2 * KS) {
+    compute(0);
+    if (k0 + KS < kend) store(1, ra0, rb0);
+    if (k0 + 3 * KS < kend) load(k0 + 3 * KS, ra0, rb0);
     __syncthreads();
-    buf ^= 1;
+    if (k0 + KS >= kend) break;
+    compute(1);
+    if (k0 + 2 * KS < kend) store(0, ra1, rb1);
+    if (k0 + 4 * KS < kend) load(k0 + 4 * KS, ra1, rb1);
+    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)
