@@ -1573,8 +1573,76 @@ __global__ void __launch_bounds__(64) k_ctrl_final(ProbView p, double* sigma_out
     Cw[e] = s;
   }
   wave_sync();
-  const int m = p.lda_cost ? ((k + 1) & ~1) : 2 * k;  // even Jacobi size
   double* JA = Tm + kk2;
+  if (!p.lda_cost) {
+    // CCA: the singular pairs of Cw from the eigenpairs of Cw^T Cw (k x k,
+    // even size, an odd k padded as in FDA below): v_j the eigenvectors,
+    // sigma_j = sqrt(lambda_j), u_j = Cw v_j / sigma_j (so u_j^T Cw v_j =
+    // sigma_j > 0).  When the smallest of the k is below 1e-6 of the
+    // largest, u_j would lose accuracy: the augmented 2k x 2k problem below
+    // is solved instead.
+    const int mg = (k + 1) & ~1;
+    double* GV = JA + mg * mg;
+    double* GT = GV + mg * mg;
+    double gf = 0.0;
+    for (int e = lane; e < kk2; e += 64) {
+      const int i = sdiv(e, k), j = e - i * k;
+      double sg = 0.0;
+      for (int l = 0; l < k; ++l) sg += Cw[l * k + i] * Cw[l * k + j];
+      Tm[e] = sg;
+      gf += sg * sg;
+    }
+    for (int o = 32; o > 0; o >>= 1) gf += __shfl_xor(gf, o, 64);
+    wave_sync();
+    const double gpad = -(1.0 + sqrt(gf));
+    for (int e = lane; e < mg * mg; e += 64) {
+      const int i = sdiv(e, mg), j = e - i * mg;
+      JA[e] = (i < k && j < k) ? 0.5 * (Tm[i * k + j] + Tm[j * k + i]) : (i == j ? gpad : 0.0);
+    }
+    wave_sync();
+    wave_jacobi(JA, GV, GT, mg, lane, jsc);
+    if (lane < mg) {
+      const double vi = JA[lane * mg + lane];
+      int rank = 0;
+      for (int j = 0; j < mg; ++j) {
+        const double vj = JA[j * mg + j];
+        rank += (vj > vi) || (vj == vi && j < lane);
+      }
+      order[rank] = lane;
+    }
+    wave_sync();
+    const double l0 = JA[order[0] * mg + order[0]], lk = JA[order[k - 1] * mg + order[k - 1]];
+    if (l0 > 0.0 && lk > 1e-12 * l0) {
+      // Tm = Cw V_k diag(1 / sigma)
+      for (int e = lane; e < kk2; e += 64) {
+        const int i = sdiv(e, k), j = e - i * k;
+        const int col = order[j];
+        double sg = 0.0;
+        for (int l = 0; l < k; ++l) sg += Cw[i * k + l] * GV[l * mg + col];
+        Tm[e] = sg / sqrt(JA[col * mg + col]);
+      }
+      wave_sync();
+      for (int b = 0; b < 2; ++b) {
+        double* R = kkslot(p, b, KK_ROT);
+        const double* Lb = Li[b];
+        for (int e = lane; e < kk2; e += 64) {
+          const int i = sdiv(e, k), j = e - i * k;
+          double sg = 0.0;
+          for (int l = i; l < k; ++l) sg += Lb[l * k + i] * (b == 0 ? Tm[l * k + j] : GV[l * mg + order[j]]);
+          R[e] = sg;
+        }
+      }
+      if (lane < k) sigma_out[lane] = sqrt(JA[order[lane] * mg + order[lane]]);
+      if (lane == 0) {
+        double f = 0.0;
+        for (int i = 0; i < k; ++i) f += p.mu[i] * sqrt(JA[order[i] * mg + order[i]]);
+        p.ctrl->f = -f;
+      }
+      return;
+    }
+    wave_sync();
+  }
+  const int m = p.lda_cost ? ((k + 1) & ~1) : 2 * k;  // even Jacobi size
   double* JV = JA + m * m;
   double* JT = JV + m * m;
   // FDA with odd k pads one decoupled row and column whose diagonal lies
