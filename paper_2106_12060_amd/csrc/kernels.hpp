@@ -32,6 +32,7 @@ struct SrhtPlan {
   uint64_t seed = 0;
   int64_t* rows = nullptr;
   int *goff = nullptr, *galpha = nullptr, *gslot = nullptr;
+  uint32_t* dbits = nullptr;   // signs of D, one bit per row (1 = negated)
 };
 size_t srht_plan_bytes(int64_t n, int s);
 int srht_plan_run(int64_t n, int s, uint64_t seed, SrhtPlan* plan, Arena& keep, Arena& scratch, hipStream_t st);

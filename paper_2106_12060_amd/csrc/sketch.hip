@@ -19,6 +19,7 @@
 #include "kernels.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace srp {
 
@@ -221,21 +222,22 @@ int countsketch_run(const void* A, int dtype, int64_t n, int d, int s, uint64_t 
 
 // --------------------------------------------------------------- SRHT
 struct SelectState {
-  uint64_t prefix;   // digits fixed so far
+  uint64_t prefix;   // digits fixed so far (all 64 bits once done)
   int need;          // how many keys still to take at or below the prefix
-  int pad;
+  int done;          // the threshold is final: a whole bucket was taken
 };
 
 __global__ void k_sel_init(SelectState* st, int s) {
   st->prefix = 0;
   st->need = s;
+  st->done = 0;
 }
 
 // Histogram of 16-bit digit `round` (0 = most significant) over keys whose
 // higher digits equal the prefix found so far.
 __global__ void k_sel_hist(int64_t n_pad, uint64_t seed, int round, const SelectState* st, int* hist) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n_pad) return;
+  if (i >= n_pad || st->done) return;
   const uint64_t key = splitmix64(seed, (uint64_t)i);
   if (round > 0 && (key >> (64 - 16 * round)) != st->prefix) return;
   const int digit = (int)((key >> (48 - 16 * round)) & 0xFFFFull);
@@ -243,35 +245,67 @@ __global__ void k_sel_hist(int64_t n_pad, uint64_t seed, int round, const Select
 }
 
 // Find the digit holding the need-th smallest remaining key; zero hist.
-__global__ void __launch_bounds__(1024) k_sel_pick(int* hist, SelectState* st) {
-  __shared__ int part[1024];
-  __shared__ int found_digit, found_before;
-  const int t = threadIdx.x;
+// Thread t owns digits 64 t .. 64 t + 63 (sixteen 16-byte loads in flight),
+// the counts are scanned by lane shuffles within a wave and the sixteen
+// wave totals through LDS.  When the need-th key closes its bucket (the
+// bucket is taken whole) the threshold is that bucket's prefix followed by
+// all ones, the same key set as finishing the remaining rounds, and they
+// are skipped.
+__global__ void __launch_bounds__(1024) k_sel_pick(int* hist, SelectState* st, int round) {
+  __shared__ int wsum[16];
+  __shared__ int found_digit, found_before, found_count;
+  if (st->done) return;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int4* h4 = reinterpret_cast<int4*>(hist) + 16 * t;
+  int4 v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = h4[j];
   int sum = 0;
-  for (int j = 0; j < 64; ++j) sum += hist[t * 64 + j];
-  part[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    int v = (t >= off) ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) sum += v[j].x + v[j].y + v[j].z + v[j].w;
+  int incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += u;
   }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  for (int k = 0; k < wv; ++k) incl += wsum[k];
   const int need = st->need;
-  const int before = (t == 0) ? 0 : part[t - 1];
-  if (before < need && need <= part[t]) {
+  const int before = incl - sum;
+  if (before < need && need <= incl) {
     int run = before;
-    for (int j = 0; j < 64; ++j) {
-      const int c = hist[t * 64 + j];
-      if (run + c >= need) { found_digit = t * 64 + j; found_before = run; break; }
-      run += c;
+    bool done = false;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int c4[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!done && run + c4[q] >= need) {
+          found_digit = 64 * t + 4 * j + q;
+          found_before = run;
+          found_count = c4[q];
+          done = true;
+        }
+        run += c4[q];
+      }
     }
   }
+#pragma unroll
+  for (int j = 0; j < 16; ++j) h4[j] = make_int4(0, 0, 0, 0);
   __syncthreads();
-  for (int j = 0; j < 64; ++j) hist[t * 64 + j] = 0;
   if (t == 0) {
-    st->prefix = (st->prefix << 16) | (uint64_t)found_digit;
-    st->need = need - found_before;
+    const uint64_t prefix = (st->prefix << 16) | (uint64_t)found_digit;
+    const int left = need - found_before;
+    const int rest = 16 * (3 - round);   // key bits below this digit
+    if (rest > 0 && left == found_count) {
+      st->prefix = (prefix << rest) | ((uint64_t(1) << rest) - 1);
+      st->done = 1;
+    } else {
+      st->prefix = prefix;
+    }
+    st->need = left;
   }
 }
 
@@ -368,7 +402,7 @@ static int srht_select_rows(int64_t n_pad, int s, uint64_t seed, int64_t* rows, 
   for (int round = 0; round < 4; ++round) {
     hipLaunchKernelGGL(k_sel_hist, dim3(nb), dim3(256), 0, st, n_pad, seedR, round, state, hist);
     SRP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1024), 0, st, hist, state);
+    hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(1024), 0, st, hist, state, round);
     SRP_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(k_sel_count, dim3(chunks), dim3(256), 0, st, n_pad, seedR, state, counts);
@@ -702,6 +736,375 @@ __global__ void __launch_bounds__(256) k_srht_level2_mfma(const float* __restric
   }
 }
 
+// ------------------------------------------------------ fused SRHT (FP32)
+// Both levels in one read of FP32 data, for B = 2^LB rows per block with
+// LB = 6 or 7 (s from 1024 to 4095).  A workgroup owns 16 columns, one half
+// of the low parts beta (the top bit of beta) and a run of steps of four
+// consecutive blocks.  The step's rows stream into an LDS ring four steps
+// deep (buffer loads to LDS, 16 B per lane; three steps in flight).  Four
+// producer waves (one per SIMD) take one block of a step each: the signs D
+// from the plan's bit table, the block's two halves combined for the
+// workgroup's beta half ((-1)^popcount(beta & b) splits into the top bits'
+// sign and the low bits'), then the remaining B/2-point Walsh-Hadamard
+// transform, the register bits in registers and the two lane bits by DPP
+// exchanges.  Twelve consumer waves each own up to 14 accumulator tiles,
+// one per group of at most 16 sampled rows with the same beta:
+// out_group += S T_beta on 16x16x4 FP32 matrix cores, the A operand the
+// signs (-1)^popcount(alpha_j & a) of the group's rows for the step's four
+// blocks a, the B operand the four blocks' level-1 row beta from the LDS
+// buffer T.  A step has two barriers: the producers transform step i in
+// registers while the consumers multiply step i - 1 out of T, then write
+// T.  Workgroups that read the same bytes (both beta halves of four
+// neighbouring column slices) get block indexes equal mod 8: they run on
+// one XCD and share its L2.  With several row ranges per column slice
+// each range writes a partial sketch and a second kernel adds them in
+// range order.
+constexpr int kFuWaves = 16;
+constexpr int kFuThreads = 64 * kFuWaves;
+constexpr int kFuProd = 4;                     // producer waves: 12 .. 15, one per SIMD
+constexpr int kFuCons = kFuWaves - kFuProd;    // consumer waves: 0 .. 11
+constexpr int kFuSlots = 14;                   // accumulator tiles per consumer wave and pass (168 groups)
+constexpr int kFuRing = 4;                     // steps of rows held in LDS (three in flight)
+constexpr int kFuCSG = 4;                      // column slices sharing an XCD
+constexpr int kFuMaxGroups = 320;              // 16-row groups of one beta half
+
+template <int LB>
+struct FuShape {
+  static constexpr int B = 1 << LB;
+  static constexpr int HB = B / 2;                              // betas per workgroup
+  static constexpr int R = B / 4;                               // rows per producer lane
+  static constexpr int STEP_ROWS = 4 * B;
+  static constexpr int STEP_F = STEP_ROWS * 16;                 // floats per step (16 columns)
+  static constexpr int DMA_W = STEP_ROWS / (16 * kFuWaves);     // 16-row loads per wave and step
+  static constexpr int TP = HB * 16 + 16;                       // T block pitch: the 4 blocks on distinct banks
+  static constexpr size_t lds_bytes() {
+    return (size_t)(kFuRing * STEP_F + 4 * TP + 3 * kFuMaxGroups + 4) * 4;
+  }
+};
+
+// s_waitcnt on the vector-memory counter only (gfx9 encoding: expcnt and
+// lgkmcnt at their maxima).
+template <int N>
+__device__ __forceinline__ void fu_wait_vm() {
+  static_assert(N >= 0 && N < 16, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt(N | (0x7 << 4) | (0xF << 8));
+}
+
+// Rows row0 .. row0 + 4B - 1 (past n: zero), columns c0 .. c0 + 15 (past d:
+// zero) into the ring slot dst, as [row][16 columns]: each 16-row load moves
+// 1 KB, lane l the 16 B of row l / 4, columns 4 (l % 4) .. + 3.
+template <int LB>
+__device__ __forceinline__ void fu_issue(const float* A, int64_t n, int d, int64_t row0, int c0, float* dst, int w,
+                                         int lane) {
+  using S = FuShape<LB>;
+  const int64_t left = n - row0;
+  const int64_t rows = left < S::STEP_ROWS ? (left > 0 ? left : 0) : S::STEP_ROWS;
+  const __amdgpu_buffer_rsrc_t r = make_rsrc(A + (rows > 0 ? row0 * d : 0), rows * d * 4);
+  const int col = c0 + 4 * (lane & 3);
+#pragma unroll
+  for (int j = 0; j < S::DMA_W; ++j) {
+    const int ins = w * S::DMA_W + j;
+    const int row = 16 * ins + (lane >> 2);
+    const int voff = col < d ? (row * d + col) * 4 : kOob;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)(dst + 256 * ins), 16,
+                                             voff, 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void fu_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// The end of a step: this wave's rows of the next step have landed (npend
+// later steps, 0 to 2, stay in flight), then the workgroup barrier.
+template <int LB>
+__device__ __forceinline__ void fu_end(int npend) {
+  constexpr int W = FuShape<LB>::DMA_W;
+  if (npend >= 2) fu_wait_vm<2 * W>();
+  else if (npend == 1) fu_wait_vm<W>();
+  else fu_wait_vm<0>();
+  fu_barrier();
+}
+
+template <int CTRL>
+__device__ __forceinline__ float fu_dpp(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+
+// Producer step it: the DMA of step it + 3 into rdma, level 1 of block a
+// (slot p of ring step rcur) for this workgroup's beta half q in registers
+// while the consumers use T; after the first barrier the result goes to T.
+// Lane (g = lane % 4, c = lane / 4) holds rows b = g + 4 i of column c;
+// after the transform it holds T[beta_lo = g + 4 i], i < R / 2.  The LDS
+// regions come in as separate restrict pointers, so the compiler's wait
+// insertion sees these reads and writes as disjoint from the DMA in flight.
+template <int LB>
+__device__ __forceinline__ void fu_produce(const float* __restrict__ rcur, float* __restrict__ rdma,
+                                           float* __restrict__ tw, const float* A, int64_t n, int d, int c0,
+                                           int64_t dma_row0, bool issue, bool work, int npend,
+                                           const uint32_t* __restrict__ dbits, int64_t a, int q, int p, int w,
+                                           int lane) {
+  using S = FuShape<LB>;
+  constexpr int R = S::R, H = R / 2, NW = S::B / 32;
+  if (issue) fu_issue<LB>(A, n, d, dma_row0, c0, rdma, w, lane);
+  const int g = lane & 3, c = lane >> 2;
+  float v[R];
+  if (work) {
+    uint32_t wv[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) wv[k] = dbits[a * NW + k] >> g;   // bit b of the block: row b negated
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const uint32_t x = __builtin_bit_cast(uint32_t, rcur[(p * S::B + g + 4 * i) * 16 + c]);
+      const uint32_t f = (wv[i >> 3] << (31 - 4 * (i & 7))) & 0x80000000u;
+      v[i] = __builtin_bit_cast(float, x ^ f);
+    }
+    // top bit of b against the top bit of beta (q)
+    const float sq = q ? -1.f : 1.f;
+#pragma unroll
+    for (int i = 0; i < H; ++i) v[i] = fmaf(sq, v[i + H], v[i]);
+#pragma unroll
+    for (int h = 1; h < H; h <<= 1)
+#pragma unroll
+      for (int i = 0; i < H; ++i)
+        if ((i & h) == 0) {
+          const float x = v[i], y = v[i + h];
+          v[i] = x + y;
+          v[i + h] = x - y;
+        }
+    // lane bits 0 and 1 of b: partner lanes g ^ 1 and g ^ 2 (quad permutes)
+    const float s1 = (g & 1) ? -1.f : 1.f, s2 = (g & 2) ? -1.f : 1.f;
+#pragma unroll
+    for (int i = 0; i < H; ++i) v[i] = fmaf(s1, v[i], fu_dpp<0xB1>(v[i]));
+#pragma unroll
+    for (int i = 0; i < H; ++i) v[i] = fmaf(s2, v[i], fu_dpp<0x4E>(v[i]));
+  }
+  fu_barrier();   // the consumers are done with T
+  if (work) {
+#pragma unroll
+    for (int i = 0; i < H; ++i) tw[p * S::TP + (g + 4 * i) * 16 + c] = v[i];
+  }
+  fu_end<LB>(npend);
+}
+
+// Consumer step it: the DMA of step it + 3 into rdma, then the products of
+// step it - 1 from tr (ak: the block of this lane's contraction index).
+template <int LB>
+__device__ __forceinline__ void fu_consume(float* __restrict__ rdma, const float* __restrict__ tr, const float* A,
+                                           int64_t n, int d, int c0, int64_t dma_row0, bool issue, bool work,
+                                           int npend, int ak, int nsl, const int (&alpha)[kFuSlots],
+                                           const int (&bl16)[kFuSlots], int lb, f32x4 (&acc)[kFuSlots], int w,
+                                           int lane) {
+  if (issue) fu_issue<LB>(A, n, d, dma_row0, c0, rdma, w, lane);
+  if (work) {
+    // T operands eight slots at a time, all loads in flight before the
+    // products (slots past nsl read a valid, unused address)
+#pragma unroll
+    for (int j0 = 0; j0 < kFuSlots; j0 += 8) {
+      float tv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j0 + j < kFuSlots) tv[j] = tr[lb + bl16[j0 + j]];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (j0 + j < kFuSlots && j0 + j < nsl) {
+          const float sg = __builtin_bit_cast(float, 0x3f800000u | ((uint32_t)__popc(alpha[j0 + j] & ak) << 31));
+          acc[j0 + j] = mfma16x16x4(sg, tv[j], acc[j0 + j]);
+        }
+    }
+  }
+  fu_barrier();   // T is free for the producers
+  fu_end<LB>(npend);
+}
+
+template <int LB>
+__global__ void __launch_bounds__(kFuThreads) k_srht_fused(const float* __restrict__ A, int64_t n, int d, int ncs,
+                                                          int ngrp, int rsp, int nsteps,
+                                                          const uint32_t* __restrict__ dbits,
+                                                          const int* __restrict__ goff,
+                                                          const int* __restrict__ galpha,
+                                                          const int* __restrict__ gslot, int s, float scale,
+                                                          float* __restrict__ out) {
+  using S = FuShape<LB>;
+  extern __shared__ float fsm[];
+  float* ring = fsm;
+  float* tbuf = ring + kFuRing * S::STEP_F;
+  int* gtab = reinterpret_cast<int*>(tbuf + 4 * S::TP);   // [group][beta_local, start, count]
+  int* gcount = gtab + 3 * kFuMaxGroups;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // block index -> (sharing group, member); members share blockIdx % 8
+  const int u = blockIdx.x, rest = u >> 3;
+  const int member = rest % (2 * kFuCSG);
+  const int grp = (rest / (2 * kFuCSG)) * 8 + (u & 7);
+  if (grp >= ngrp) return;
+  const int q = member & 1;
+  const int ncsg = (ncs + kFuCSG - 1) / kFuCSG;
+  const int rs = grp / ncsg;
+  const int cs = (grp - rs * ncsg) * kFuCSG + (member >> 1);
+  if (cs >= ncs) return;
+  const int c0 = 16 * cs;
+  const int st_beg = (int)((int64_t)rs * nsteps / rsp);
+  const int nst = (int)((int64_t)(rs + 1) * nsteps / rsp) - st_beg;
+  // the groups of this beta half: beta = q HB + lane, ceil(count / 16) each
+  if (w == 0) {
+    int start = 0, cnt = 0, ngb = 0;
+    if (lane < S::HB) {
+      const int beta = q * S::HB + lane;
+      start = goff[beta];
+      cnt = goff[beta + 1] - start;
+      ngb = (cnt + 15) >> 4;
+    }
+    int incl = ngb;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    const int excl = incl - ngb;
+    for (int j = 0; j < ngb; ++j) {
+      const int gi = excl + j;
+      if (gi < kFuMaxGroups) {
+        gtab[3 * gi] = lane;
+        gtab[3 * gi + 1] = start + 16 * j;
+        gtab[3 * gi + 2] = min(16, cnt - 16 * j);
+      }
+    }
+    if (lane == 63) *gcount = min(incl, kFuMaxGroups);
+  }
+  __syncthreads();
+  const int ng = *gcount;
+  float* dst = out + (rsp > 1 ? (int64_t)rs * s * d : 0);
+  const float sc = rsp > 1 ? 1.f : scale;
+  for (int pbase = 0; pbase < ng; pbase += kFuCons * kFuSlots) {
+    if (w >= kFuCons) {
+      const int p = w - kFuCons;
+      __builtin_amdgcn_s_waitcnt(0);   // nothing of an earlier pass in flight
+      for (int j = 0; j < 3 && j < nst; ++j)
+        fu_issue<LB>(A, n, d, (int64_t)(st_beg + j) * S::STEP_ROWS, c0, ring + j * S::STEP_F, w, lane);
+      fu_end<LB>(min(nst, 3) - 1);
+      for (int it = 0; it <= nst; ++it) {
+        fu_produce<LB>(ring + (it % kFuRing) * S::STEP_F, ring + ((it + 3) % kFuRing) * S::STEP_F, tbuf, A, n, d,
+                       c0, (int64_t)(st_beg + it + 3) * S::STEP_ROWS, it + 3 < nst, it < nst,
+                       (it + 2 < nst) + (it + 3 < nst), dbits, 4 * (int64_t)(st_beg + it) + p, q, p, w, lane);
+      }
+    } else {
+      int alpha[kFuSlots], bl16[kFuSlots];
+      f32x4 acc[kFuSlots];
+      const int left = ng - pbase - w;
+      const int nsl = left > 0 ? min(kFuSlots, (left + kFuCons - 1) / kFuCons) : 0;
+      const int m = lane & 15, lb = (lane >> 4) * S::TP + m;
+#pragma unroll
+      for (int j = 0; j < kFuSlots; ++j) {
+        acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        alpha[j] = 0;
+        bl16[j] = 0;
+        if (j < nsl) {
+          const int gi = pbase + w + kFuCons * j;
+          const int cn = gtab[3 * gi + 2];
+          // rows past the group's count are never stored: any alpha serves
+          alpha[j] = m < cn ? galpha[gtab[3 * gi + 1] + m] : 0;
+          bl16[j] = __builtin_amdgcn_readfirstlane(16 * gtab[3 * gi]);
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);   // the alpha loads have landed before the row stream starts
+      for (int j = 0; j < 3 && j < nst; ++j)
+        fu_issue<LB>(A, n, d, (int64_t)(st_beg + j) * S::STEP_ROWS, c0, ring + j * S::STEP_F, w, lane);
+      fu_end<LB>(min(nst, 3) - 1);
+      for (int it = 0; it <= nst; ++it) {
+        fu_consume<LB>(ring + ((it + 3) % kFuRing) * S::STEP_F, tbuf, A, n, d, c0,
+                       (int64_t)(st_beg + it + 3) * S::STEP_ROWS, it + 3 < nst, it > 0,
+                       (it + 2 < nst) + (it + 3 < nst), 4 * (st_beg + it - 1) + (lane >> 4), nsl, alpha, bl16, lb,
+                       acc, w, lane);
+      }
+      const int col = c0 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < kFuSlots; ++j)
+        if (j < nsl) {
+          const int gi = pbase + w + kFuCons * j;
+          const int start = gtab[3 * gi + 1], cn = gtab[3 * gi + 2];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = acc_row<float>(lane, r);
+            if (row < cn && col < d) dst[(int64_t)gslot[start + row] * d + col] = acc[j][r] * sc;
+          }
+        }
+    }
+    __syncthreads();   // the ring and T are reused by the next pass
+  }
+}
+
+// out = scale * (sum of the row-range partials, in range order)
+__global__ void __launch_bounds__(256) k_srht_fused_sum(const float* __restrict__ part, int rsp, int64_t count,
+                                                        float scale, float* __restrict__ out) {
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  if (e >= count) return;
+  float v = 0.f;
+  for (int r = 0; r < rsp; ++r) v += part[r * count + e];
+  out[e] = v * scale;
+}
+
+// Sign bits of D: bit i % 32 of word i / 32 set when row i is negated.
+__global__ void __launch_bounds__(256) k_srht_sign_bits(int64_t nwords, uint64_t seedD, uint32_t* __restrict__ bits) {
+  const int64_t r = blockIdx.x * 256ll + threadIdx.x;
+  const bool neg = r < nwords * 32 && (splitmix64(seedD, (uint64_t)r) & 1ull);
+  const uint64_t m = __ballot(neg);
+  const int lane = threadIdx.x & 63;
+  const int64_t word = (r - lane) / 32;
+  if (lane == 0 && word < nwords) bits[word] = (uint32_t)m;
+  if (lane == 32 && word + 1 < nwords) bits[word + 1] = (uint32_t)(m >> 32);
+}
+
+static int64_t srht_sign_words(const SrhtGeom& g) {
+  // four-block steps past the last block read signs too (their rows are zero)
+  const int64_t rows = (int64_t)((g.A_eff + 3) / 4) * 4 * g.B;
+  return ((rows + 63) / 64) * 2;
+}
+
+// Whether the fused kernel takes this FP32 view.
+static bool srht_fused_ok(const SrhtGeom& g, int s, int d, const void* A) {
+  return (g.logB == 6 || g.logB == 7) && d % 4 == 0 && d > 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+         s + 15 * (g.B / 2) <= 16 * kFuMaxGroups;
+}
+
+// The step loop counts its own loads (s_waitcnt on the vector-memory
+// counter): a register spill would add scratch loads to that count, so a
+// build whose kernel uses scratch memory keeps the two-level kernels.
+template <int LB>
+static bool srht_fused_clean() {
+  static const bool clean = [] {
+    hipFuncAttributes attr{};
+    return hipFuncGetAttributes(&attr, (const void*)k_srht_fused<LB>) == hipSuccess && attr.localSizeBytes == 0;
+  }();
+  return clean;
+}
+
+template <int LB>
+static int srht_fused_launch(const float* A, int64_t n, int d, int s, const SrhtGeom& g, const uint32_t* dbits,
+                             const int* goff, const int* galpha, const int* gslot, float* part, size_t part_floats,
+                             float* out, hipStream_t st) {
+  using S = FuShape<LB>;
+  const int ncs = (d + 15) / 16;
+  const int ncsg = (ncs + kFuCSG - 1) / kFuCSG;
+  const int nsteps = (g.A_eff + 3) / 4;
+  // about 256 workgroups: split the rows when the column slices are few
+  int rsp = std::max(1, 32 / ncsg);
+  rsp = std::min(rsp, nsteps);
+  while (rsp > 1 && (size_t)rsp * s * d > part_floats) --rsp;
+  const int ngrp = ncsg * rsp;
+  const unsigned grid = (unsigned)((ngrp + 7) / 8) * 8 * 2 * kFuCSG;
+  const float scale = (float)(1.0 / std::sqrt((double)s));
+  SRP_TRY(allow_dynamic_lds((const void*)k_srht_fused<LB>, S::lds_bytes()));
+  hipLaunchKernelGGL((k_srht_fused<LB>), dim3(grid), dim3(kFuThreads), S::lds_bytes(), st, A, n, d, ncs, ngrp, rsp,
+                     nsteps, dbits, goff, galpha, gslot, s, scale, rsp > 1 ? part : out);
+  SRP_LAUNCH_CHECK();
+  if (rsp > 1) {
+    const int64_t count = (int64_t)s * d;
+    hipLaunchKernelGGL(k_srht_fused_sum, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, part, rsp, count,
+                       scale, out);
+    SRP_LAUNCH_CHECK();
+  }
+  return SRP_OK;
+}
+
 static int srht_chunk_cols(int B, int acc_bytes) {
   // LDS tile of B x CW elements, at most 64 KiB.
   int cw = (64 * 1024) / (B * acc_bytes);
@@ -716,7 +1119,7 @@ size_t srht_ws_bytes(int64_t n, int d, int s, int dtype) {
   const int chunks = (int)((g.n_pad + kSelChunk - 1) / kSelChunk);
   return bytes_of<int>(65536) + bytes_of<SelectState>(1) + 2 * bytes_of<int>(chunks + 1) +
          bytes_of<int64_t>(s) + bytes_of<int>(g.B + 1) + 2 * bytes_of<int>(s) +
-         (((size_t)g.A_eff * g.B * d * acc + 255) & ~size_t(255));
+         bytes_of<uint32_t>((size_t)srht_sign_words(g)) + (((size_t)g.A_eff * g.B * d * acc + 255) & ~size_t(255));
 }
 
 int srht_rows_run(int64_t n, int s, uint64_t seed, int64_t* rows, Arena& ws, hipStream_t st) {
@@ -730,9 +1133,18 @@ int srht_rows_run(int64_t n, int s, uint64_t seed, int64_t* rows, Arena& ws, hip
 
 template <class T, class Acc>
 static int srht_levels(const T* A, int64_t n, int d, int s, uint64_t seed, const SrhtGeom& g,
-                       const int* goff, const int* galpha, const int* gslot, Acc* Tbuf, Acc* out,
-                       hipStream_t st) {
+                       const int* goff, const int* galpha, const int* gslot, const uint32_t* dbits, Acc* Tbuf,
+                       size_t tcount, Acc* out, hipStream_t st) {
   const int logB = g.logB;
+  if constexpr (std::is_same<T, float>::value) {
+    if (dbits && srht_fused_ok(g, s, d, A) && (logB == 6 ? srht_fused_clean<6>() : srht_fused_clean<7>())) {
+      // one read of the data, no level-1 intermediate (Tbuf holds the
+      // row-range partials)
+      if (logB == 6)
+        return srht_fused_launch<6>(A, n, d, s, g, dbits, goff, galpha, gslot, Tbuf, tcount, out, st);
+      return srht_fused_launch<7>(A, n, d, s, g, dbits, goff, galpha, gslot, Tbuf, tcount, out, st);
+    }
+  }
   if constexpr (sizeof(Acc) == 4) {
     if (logB >= 6 && logB <= 10) {
       // FP32: level 1 in registers and lane shuffles, level 2 on matrix
@@ -791,7 +1203,8 @@ static int srht_levels(const T* A, int64_t n, int d, int s, uint64_t seed, const
 
 size_t srht_plan_bytes(int64_t n, int s) {
   const SrhtGeom g = srht_geom(n, s);
-  return bytes_of<int64_t>(s) + bytes_of<int>(g.B + 1) + 2 * bytes_of<int>(s);
+  return bytes_of<int64_t>(s) + bytes_of<int>(g.B + 1) + 2 * bytes_of<int>(s) +
+         bytes_of<uint32_t>((size_t)srht_sign_words(g));
 }
 
 int srht_plan_run(int64_t n, int s, uint64_t seed, SrhtPlan* plan, Arena& keep, Arena& scratch, hipStream_t st) {
@@ -807,7 +1220,12 @@ int srht_plan_run(int64_t n, int s, uint64_t seed, SrhtPlan* plan, Arena& keep, 
   plan->goff = keep.take<int>(g.B + 1);
   plan->galpha = keep.take<int>(s);
   plan->gslot = keep.take<int>(s);
-  if (!plan->gslot) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
+  const int64_t words = srht_sign_words(g);
+  plan->dbits = keep.take<uint32_t>((size_t)words);
+  if (!plan->gslot || !plan->dbits) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
+  hipLaunchKernelGGL(k_srht_sign_bits, dim3((unsigned)((words * 32 + 255) / 256)), dim3(256), 0, st, words,
+                     seed ^ kSrhtSignSalt, plan->dbits);
+  SRP_LAUNCH_CHECK();
   SRP_TRY(srht_select_rows(g.n_pad, s, seed, plan->rows, scratch, st));
   hipLaunchKernelGGL(k_srht_group, dim3(1), dim3(1024), 0, st, plan->rows, s, g.B, g.logB, plan->goff,
                      plan->galpha, plan->gslot);
@@ -824,20 +1242,20 @@ int srht_apply_run(const SrhtPlan& plan, const void* A, int dtype, int d, void* 
   if (dtype == SRP_F64) {
     double* Tbuf = ws.take<double>(tcount);
     if (!Tbuf) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
-    return srht_levels((const double*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, Tbuf, (double*)out,
-                       st);
+    return srht_levels((const double*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, plan.dbits, Tbuf,
+                       tcount, (double*)out, st);
   }
   float* Tbuf = ws.take<float>(tcount);
   if (!Tbuf) { set_error("srht: workspace too small"); return SRP_ENOMEM; }
   if (dtype == SRP_F32)
-    return srht_levels((const float*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, Tbuf, (float*)out,
-                       st);
+    return srht_levels((const float*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, plan.dbits, Tbuf,
+                       tcount, (float*)out, st);
   if (dtype == SRP_BF16)
-    return srht_levels((const bf16*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, Tbuf, (float*)out,
-                       st);
+    return srht_levels((const bf16*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, plan.dbits, Tbuf,
+                       tcount, (float*)out, st);
   if (dtype == SRP_FP8E4M3)
-    return srht_levels((const fp8e4m3*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, Tbuf,
-                       (float*)out, st);
+    return srht_levels((const fp8e4m3*)A, n, d, s, seed, g, plan.goff, plan.galpha, plan.gslot, plan.dbits, Tbuf,
+                       tcount, (float*)out, st);
   set_error("srht: bad dtype %d", dtype);
   return SRP_EINVAL;
 }

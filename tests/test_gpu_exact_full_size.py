@@ -71,6 +71,38 @@ def test_srht_exact_at_benchmark_shape():
     assert not np.any(out[:, mask])
 
 
+@pytest.mark.parametrize("n,d,s,per_row,col_step", [
+    (200_000, 1000, 4000, 3, 7),   # the CCA benchmark sketch: B = 128, two row ranges per column slice
+    (200_000, 1000, 1024, 3, 7),   # B = 64 and 1/sqrt(s) = 2^-5: bit for bit
+    (50_000, 100, 3000, 4, 1),     # last column slice holds 4 of its 16 columns
+    (140_000, 36, 2000, 4, 1),     # B = 64, three column slices: many row ranges
+    (3_000, 12, 2500, 4, 1),       # n' = 4096, one column slice, one row range
+    (700, 16, 1024, 2, 1),         # under four blocks per row range
+])
+def test_srht_one_read_exact(n, d, s, per_row, col_step):
+    """The one-read SRHT (FP32 data, d a multiple of 4, B = 64 or 128, that
+    is s from 1024 to 4095) on +-1 data: every partial sum is an exact
+    integer, so the only rounding left is the final 1/sqrt(s) (none when s
+    is a power of 4).  Columns outside the chosen set must stay zero."""
+    srp = _srp()
+    seed = 900 + s + n
+    cols = np.arange(0, d, col_step)
+    X = synth.sparse_signs(n, d, per_row, seed=seed, cols=cols)
+    print("srht one-read exact", n, d, s, flush=True)
+    out = srp.srp_srht(torch.from_numpy(X).to(DEV), s, seed).double().cpu().numpy()
+    n_pad = osk.srht_padded_rows(n)
+    ref = osk.srht_apply(X[:, cols].astype(np.float64), osk.srht_signs(n_pad, seed),
+                         osk.srht_rows(n_pad, s, seed), s)
+    got = out[:, cols]
+    if (s & (s - 1)) == 0 and (s.bit_length() - 1) % 2 == 0:
+        np.testing.assert_array_equal(got, ref)
+    else:
+        assert np.all(np.abs(got - ref) <= 2.0 ** -22 * np.abs(ref))
+    mask = np.ones(d, bool)
+    mask[cols] = False
+    assert not np.any(out[:, mask])
+
+
 def test_countsketch_exact_at_benchmark_shape():
     srp = _srp()
     n, d, s, seed = 200_000, 1000, 4000, 12062
