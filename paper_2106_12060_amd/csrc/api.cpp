@@ -176,7 +176,8 @@ int srp_sketch_factor(const void* SA, int dtype, int s, int d, double lambda, do
   int* flag = ar.take<int>(4);
   double* X = Rinv ? Rinv : ar.take<double>((size_t)d * d);
   SRP_TRY(fill_i32(flag, 1, 0, st));
-  SRP_TRY(sketch_factor_run(SA, dtype, s, d, lambda, R, X, nullptr, flag, ar, st));
+  SRP_TRY(sketch_factor_run(SA, dtype, s, d, lambda, R, X, nullptr, flag, ar, st, nullptr,
+                            factor_aux_stream(0)));
   int h = 0;
   SRP_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   SRP_TRY(finish(st));

@@ -132,6 +132,24 @@ static hipStream_t side_stream() {
   return streams[dev];
 }
 
+// Two more streams per device (default priority) for the column blocks of
+// R^-1 that run alongside each view's Cholesky (sketch_factor_run).
+hipStream_t factor_aux_stream(int i) {
+  static std::mutex mu;
+  static hipStream_t streams[64][2] = {};
+  int dev = 0;
+  if (i < 0 || i > 1 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!streams[dev][i] && hipStreamCreateWithFlags(&streams[dev][i], hipStreamNonBlocking) != hipSuccess)
+    streams[dev][i] = nullptr;
+  return streams[dev][i];
+}
+
+// The factor's second stream for a solve: only when the solve may fork
+// (ctx == null: the synchronous entry points); a context without a side
+// stream (the serving engine) keeps every view's work on its own stream.
+static hipStream_t factor_aux(const SolveCtx* ctx, int i) { return ctx ? nullptr : factor_aux_stream(i); }
+
 // Fork/join of the side stream around a block of independent work.
 struct SideFork {
   hipEvent_t fork = nullptr, join = nullptr;
@@ -1849,7 +1867,8 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   {
     Arena sub{sy.base, sy.cap, 0};
     if (wby) SRP_TRY(woodbury_factor(SY, sk_dtype, s, dy, ly, Ry, My, flag, sub, wkeep[1], &wbs[1], fk.side));
-    else SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side));
+    else SRP_TRY(sketch_factor_run(SY, sk_dtype, s, dy, ly, Ry, Rinv2, My, flag, sub, fk.side, nullptr,
+                                   factor_aux(ctx, 1)));
   }
   SRP_TRY(sketch_any(opt.sketch, skin_x, skin_dtype, n, dx, s, opt.seed, SX, sx, st, planp));
   if (staged && skin_dtype == SRP_FP8E4M3) SRP_TRY(scale_cols_run((float*)SX, s, dx, opt.sketch_scale_x, st));
@@ -1857,7 +1876,7 @@ int cca_solve_impl(const void* X, const void* Y, int64_t n, int dx, int dy, int 
   {
     Arena sub{sx.base, sx.cap, 0};
     if (wbx) SRP_TRY(woodbury_factor(SX, sk_dtype, s, dx, lx, Rx, Mx, flag, sub, wkeep[0], &wbs[0], st));
-    else SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st));
+    else SRP_TRY(sketch_factor_run(SX, sk_dtype, s, dx, lx, Rx, Rinv, Mx, flag, sub, st, nullptr, factor_aux(ctx, 0)));
   }
   SRP_TRY(fk.end(st));
   const bool pencil = wbx || wby;   // no R^-1 for a Woodbury view: the warm start iterates on the pencil
@@ -1998,7 +2017,7 @@ int lda_solve_impl(const void* X, const int32_t* labels, int64_t n, int d, int c
     SRP_TRY(woodbury_factor(SXh, sk_dtype, s, d, lam, R, Minv, flag, sub, keep, &wbs, st));
   } else {
     Arena sub{ar.base + ar.used, ar.cap - ar.used, 0};
-    SRP_TRY(sketch_factor_run(SXh, sk_dtype, s, d, lam, R, Rinv, Minv, flag, sub, st));
+    SRP_TRY(sketch_factor_run(SXh, sk_dtype, s, d, lam, R, Rinv, Minv, flag, sub, st, nullptr, factor_aux(ctx, 0)));
   }
   int hflag = 0;
   SRP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));

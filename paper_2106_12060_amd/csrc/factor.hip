@@ -10,6 +10,8 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <vector>
+
 namespace srp {
 
 __global__ void k_fill_f64(double* p, int64_t count, double v) {
@@ -768,8 +770,8 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
 }
 
 // Copy 64x64 block inverses onto the diagonal of X (d x d).
-__global__ void k_place_diag_blocks(const double* __restrict__ Dinv, int d, double* __restrict__ X) {
-  const int kb = blockIdx.x;
+__global__ void k_place_diag_blocks(const double* __restrict__ Dinv, int d, double* __restrict__ X, int kb0) {
+  const int kb = kb0 + blockIdx.x;
   const int k0 = kb * 64;
   const int nb = min(64, d - k0);
   for (int e = threadIdx.x; e < 4096; e += blockDim.x) {
@@ -778,7 +780,7 @@ __global__ void k_place_diag_blocks(const double* __restrict__ Dinv, int d, doub
   }
 }
 
-constexpr int kInvSplit = 8;   // split of the contraction in the R^-1 block rows
+constexpr int kInvSplit = 8;   // split of the contraction in the R^-1 column blocks
 
 // Split of the sketch Gram over the s rows: about 256 workgroups of the
 // big-tile kernel over the upper 128 x 128 tiles (measured best: d = 1000,
@@ -852,8 +854,58 @@ int gram_split(int s, int d0, int d1) {
   return ks < 1 ? 1 : ks;
 }
 
+// Events of the calling thread on the current device, reused call after
+// call (a wait takes the event's state when it is issued).  Never freed.
+static int factor_events(int count, hipEvent_t** out) {
+  thread_local std::vector<hipEvent_t>* pools[64] = {};
+  int dev = 0;
+  SRP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) { set_error("factor: device %d out of range", dev); return SRP_EDEVICE; }
+  if (!pools[dev]) pools[dev] = new std::vector<hipEvent_t>();
+  std::vector<hipEvent_t>& pool = *pools[dev];
+  while ((int)pool.size() < count) {
+    hipEvent_t e = nullptr;
+    SRP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    pool.push_back(e);
+  }
+  *out = pool.data();
+  return SRP_OK;
+}
+
+// Column block kb of X = R^-1 (left to right): X_kk = R_kk^-1 (from the
+// diagonal block's factor) and X[0:k0, kb] = -X[0:k0, 0:k0] R[0:k0, kb] X_kk.
+// It needs only R's columns up to kb and X's earlier column blocks, so it
+// runs while the Cholesky works on the columns after kb.
+static int rinv_column(int kb, int d, const double* R, const double* Dinv, double* X, double* Tmp, double* Tparts,
+                       hipStream_t st) {
+  const int k0 = kb * 64, nb = std::min(64, d - k0);
+  hipLaunchKernelGGL(k_place_diag_blocks, dim3(1), dim3(256), 0, st, Dinv, d, X, kb);
+  SRP_LAUNCH_CHECK();
+  if (kb == 0) return SRP_OK;
+  const int rows = k0;
+  GemmArgs a{};
+  a.m = rows; a.n = nb; a.kk = rows; a.alpha = 1.0; a.beta = 0.0;
+  a.A = X; a.lda = d; a.ta = false;
+  a.B = R + k0; a.ldb = d; a.tb = false;
+  const int ks = std::min(kInvSplit, (rows + 127) / 128);
+  if (ks > 1) {   // rows x nb outputs are few tiles: split the contraction
+    a.C = Tparts; a.ldc = nb; a.ksplit = ks; a.c_split_stride = (int64_t)rows * nb;
+    SRP_TRY(gemm_f64(a, st));
+    SRP_TRY(sum_parts_f64(Tparts, ks, (int64_t)rows * nb, (int64_t)rows * nb, Tmp, 0, 0.0, st));
+  } else {
+    a.C = Tmp; a.ldc = nb;
+    SRP_TRY(gemm_f64(a, st));
+  }
+  GemmArgs b{};
+  b.m = rows; b.n = nb; b.kk = nb; b.alpha = -1.0; b.beta = 0.0;
+  b.A = Tmp; b.lda = nb; b.ta = false;
+  b.B = Dinv + (size_t)kb * 4096; b.ldb = 64; b.tb = false;
+  b.C = X + k0; b.ldc = d;
+  return gemm_f64(b, st);
+}
+
 int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
-                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st, double* Hfull) {
+                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st, double* Hfull, hipStream_t aux) {
   const int tiles = (d + 63) / 64;
   const int ksplit = gram_ksplit(s, d);
   const int64_t dd = (int64_t)d * d;
@@ -891,13 +943,37 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
     SRP_TRY(gemm_f64(g, st));
     SRP_TRY(sum_parts_f64(G, 1, dd, dd, G, d, lambda, st));
   }
-  // Right-looking blocked Cholesky, 64-wide panels.
+  // Right-looking blocked Cholesky, 64-wide panels; column block kb of
+  // X = R^-1 follows diagonal block kb, on the second stream when there is
+  // one (the same arithmetic either way, so the result does not depend on
+  // it).
+  const bool overlap = aux != nullptr && aux != st && tiles > 1;
+  hipEvent_t* ev = nullptr;
+  if (overlap) SRP_TRY(factor_events(tiles + 1, &ev));
+  // joins the second stream into st on every return (an error return too,
+  // so the caller's stream-ordered release of the workspace follows it)
+  struct Join {
+    hipStream_t st, aux;
+    hipEvent_t e;
+    ~Join() {
+      if (aux) {
+        (void)hipEventRecord(e, aux);
+        (void)hipStreamWaitEvent(st, e, 0);
+      }
+    }
+  } join{st, overlap ? aux : nullptr, overlap ? ev[tiles] : nullptr};
   SRP_TRY(fill_f64(R, dd, 0.0, st));
+  SRP_TRY(fill_f64(X, dd, 0.0, st));
   for (int kb = 0; kb < tiles; ++kb) {
     const int k0 = kb * 64, nb = min(64, d - k0);
     hipLaunchKernelGGL(k_potrf_block, dim3(1), dim3(256), 0, st, G, (int64_t)d, k0, nb, R,
                        Dinv + (size_t)kb * 4096, flag_dev);
     SRP_LAUNCH_CHECK();
+    if (overlap) {
+      SRP_HIP(hipEventRecord(ev[kb], st));
+      SRP_HIP(hipStreamWaitEvent(aux, ev[kb], 0));
+    }
+    SRP_TRY(rinv_column(kb, d, R, Dinv, X, Tmp, Tparts, overlap ? aux : st));
     const int rest = d - k0 - nb;
     if (rest <= 0) continue;
     GemmArgs t{};
@@ -914,31 +990,10 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
     u.upper_only = true;
     SRP_TRY(gemm_f64(u, st));
   }
-  // X = R^-1, block rows bottom-up: X_ij = -R_ii^-1 sum_{l>i} R_il X_lj.
-  SRP_TRY(fill_f64(X, dd, 0.0, st));
-  hipLaunchKernelGGL(k_place_diag_blocks, dim3(tiles), dim3(256), 0, st, Dinv, d, X);
-  SRP_LAUNCH_CHECK();
-  for (int ib = tiles - 2; ib >= 0; --ib) {
-    const int i0 = ib * 64, c1 = i0 + 64, rest = d - c1;
-    GemmArgs a{};
-    a.m = 64; a.n = rest; a.kk = rest; a.alpha = 1.0; a.beta = 0.0;
-    a.A = R + (int64_t)i0 * d + c1; a.lda = d; a.ta = false;
-    a.B = X + (int64_t)c1 * d + c1; a.ldb = d; a.tb = false;
-    const int ks = std::min(kInvSplit, (rest + 127) / 128);
-    if (ks > 1) {   // 64 x rest outputs are few tiles: split the contraction
-      a.C = Tparts; a.ldc = rest; a.ksplit = ks; a.c_split_stride = (int64_t)64 * rest;
-      SRP_TRY(gemm_f64(a, st));
-      SRP_TRY(sum_parts_f64(Tparts, ks, (int64_t)64 * rest, (int64_t)64 * rest, Tmp, 0, 0.0, st));
-    } else {
-      a.C = Tmp; a.ldc = rest;
-      SRP_TRY(gemm_f64(a, st));
-    }
-    GemmArgs b{};
-    b.m = 64; b.n = rest; b.kk = 64; b.alpha = -1.0; b.beta = 0.0;
-    b.A = Dinv + (size_t)ib * 4096; b.lda = 64; b.ta = false;
-    b.B = Tmp; b.ldb = rest; b.tb = false;
-    b.C = X + (int64_t)i0 * d + c1; b.ldc = d;
-    SRP_TRY(gemm_f64(b, st));
+  if (overlap) {   // R^-1 done on the second stream: join it
+    join.aux = nullptr;
+    SRP_HIP(hipEventRecord(ev[tiles], aux));
+    SRP_HIP(hipStreamWaitEvent(st, ev[tiles], 0));
   }
   if (Minv) {
     GemmArgs mm{};

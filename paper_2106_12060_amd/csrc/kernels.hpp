@@ -83,8 +83,14 @@ int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count
 // Gram of a sketch, Cholesky and inverse: R^T R = SA^T SA + lambda I.
 // Hfull (optional, d x d): the full symmetric Gram SA^T SA, without lambda.
 size_t factor_ws_bytes(int s, int d);
+// aux (optional, not st): a second stream on which the column blocks of
+// R^-1 run alongside the Cholesky (joined before return).
 int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, double* R, double* Rinv,
-                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st, double* Hfull = nullptr);
+                      double* Minv, int* flag_dev, Arena& ws, hipStream_t st, double* Hfull = nullptr,
+                      hipStream_t aux = nullptr);
+// Per-device second streams for sketch_factor_run's aux (i = 0, 1; null on
+// failure).
+hipStream_t factor_aux_stream(int i);
 // Split of an s-long Gram contraction over d0 x d1 outputs (about 256
 // workgroups of 128 x 128 tiles).
 int gram_split(int s, int d0, int d1);
