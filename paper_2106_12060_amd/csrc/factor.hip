@@ -623,16 +623,21 @@ int gemm_skinny_f64(int m, int kk, int nc, const double* A, int64_t lda, bool ta
 // its inverse into Dinv (64 x 64, upper, identity-padded).  Sets *flag on a
 // non-positive pivot.
 //
-// Right-looking with one barrier per column: the trailing triangle stays in
-// registers (each thread owns fixed entries), step j subtracts
-// a[j][r] a[j][c] / a[j][j] from the entries j < r <= c using row j as its
-// owners publish it in LDS, and row j is stored in its final form (scaled
-// by 1 / sqrt(pivot)) as soon as it is complete.  The inverse follows by
-// 16 x 16 blocks (see below).
+// The block is loaded into LDS once and factored right-looking in four
+// panels of 16 rows (details below); the inverse follows by 16 x 16
+// blocks.
 __device__ __forceinline__ void wave_fence_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// x from lane l (uniform l), as two 32-bit readlanes.
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ G, int64_t ld, int k0, int nb,
@@ -647,14 +652,22 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
   const int t = threadIdx.x;
   const int wv = t >> 6, ln = t & 63;
   // The upper triangle of the block in LDS (rows past nb: the identity).
-  for (int e = t; e < 4096; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    double val = 0.0;
-    if (r <= c) {
-      if (r < nb && c < nb) val = G[(int64_t)(k0 + r) * ld + k0 + c];
-      else val = (r == c) ? 1.0 : 0.0;
+  {
+    // all sixteen loads of a thread in flight together (masked entries read
+    // the block's first element and are replaced)
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u, r = e >> 6, c = e & 63;
+      const bool in = r <= c && r < nb && c < nb;
+      v[u] = G[in ? (int64_t)(k0 + r) * ld + k0 + c : (int64_t)k0 * ld + k0];
     }
-    a[r][c] = val;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = t + 256 * u, r = e >> 6, c = e & 63;
+      const bool in = r <= c && r < nb && c < nb;
+      a[r][c] = in ? v[u] : ((r == c) ? 1.0 : 0.0);
+    }
   }
   __syncthreads();
   // Four panels of 16 rows, right-looking.  Wave 0 factors a panel alone
@@ -662,7 +675,8 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
   // takes the pivot from lane p0+j, scales row j and subtracts its outer
   // product from the rows below, the row-j entries of the other columns
   // broadcast by readlane (no barrier inside the panel).  Then all waves
-  // subtract the panel's rows' products from the trailing triangle.
+  // subtract the panel's rows' products from the trailing triangle on FP64
+  // matrix cores.
   for (int p0 = 0; p0 < 64; p0 += 16) {
     if (wv == 0) {
       double pr[16];
@@ -671,7 +685,7 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int pl = p0 + j;   // lane (column) of the pivot
-        double p = __shfl(pr[j], pl, 64);
+        double p = readlane_f64(pr[j], pl);
         const bool bad = !(p > 0.0) || !isfinite(p);
         if (bad) p = 1.0;
         double rs = __builtin_amdgcn_rsq(p);
@@ -685,7 +699,7 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
         const double rj = pr[j] * rs;   // row j of R in column ln (ln >= pl)
 #pragma unroll
         for (int i = j + 1; i < 16; ++i) {
-          const double rji = __shfl(rj, p0 + i, 64);   // R[j][p0 + i]
+          const double rji = readlane_f64(rj, p0 + i);   // R[j][p0 + i]
           pr[i] = fma(-rji, rj, pr[i]);
         }
         pr[j] = rj;
@@ -699,17 +713,23 @@ __global__ void __launch_bounds__(256) k_potrf_block(const double* __restrict__ 
     __syncthreads();
     const int q0 = p0 + 16;
     if (q0 < 64) {
-      // a[r][c] -= sum_i R[p0+i][r] R[p0+i][c] for q0 <= r <= c < 64
-      const int m = 64 - q0;
-      for (int e = t; e < m * m; e += 256) {
-        const int r = q0 + e / m, c = q0 + e % m;
-        if (r <= c) {
-          double sacc = a[r][c];
+      // a[r][c] -= sum_i R[p0+i][r] R[p0+i][c] for q0 <= r <= c < 64: the
+      // upper 16 x 16 tiles of P^T P (P = the panel's rows, columns q0..63)
+      // on FP64 matrix cores, tile (ti, tj) by wave (ti + tj) % 4 (entries
+      // below the diagonal of a diagonal tile are updated too and never read)
+      const int nt = (64 - q0) >> 4;
+      const int m16 = ln & 15, kq = ln >> 4;
+      for (int ti = 0; ti < nt; ++ti)
+        for (int tj = ti; tj < nt; ++tj) {
+          if (((ti + tj) & 3) != wv) continue;
+          const int r0 = q0 + 16 * ti, c0 = q0 + 16 * tj;
+          f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int i = 0; i < 16; ++i) sacc = fma(-a[p0 + i][r], a[p0 + i][c], sacc);
-          a[r][c] = sacc;
+          for (int kb = 0; kb < 4; ++kb)
+            acc = mfma16x16x4(a[p0 + 4 * kb + kq][r0 + m16], a[p0 + 4 * kb + kq][c0 + m16], acc);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a[r0 + acc_row<double>(ln, r)][c0 + m16] -= acc[r];
         }
-      }
       __syncthreads();
     }
   }
