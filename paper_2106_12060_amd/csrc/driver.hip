@@ -2194,12 +2194,12 @@ int cca_solve_csr_impl(const CsrView& X, const CsrView& Y, int k, double lx, dou
   {
     Arena t{scratch_base, scr, 0};
     if (wbv[0]) SRP_TRY(woodbury_factor(SX, SRP_F64, s, dx, lx, Rx, Mx, flag, t, wkeep[0], &wbs[0], st));
-    else SRP_TRY(sketch_factor_run(SX, SRP_F64, s, dx, lx, Rx, Rinv, Mx, flag, t, st));
+    else SRP_TRY(sketch_factor_run(SX, SRP_F64, s, dx, lx, Rx, Rinv, Mx, flag, t, st, nullptr, factor_aux(ctx, 0)));
   }
   {
     Arena t{scratch_base, scr, 0};
     if (wbv[1]) SRP_TRY(woodbury_factor(SY, SRP_F64, s, dy, ly, Ry, My, flag, t, wkeep[1], &wbs[1], st));
-    else SRP_TRY(sketch_factor_run(SY, SRP_F64, s, dy, ly, Ry, Rinv2, My, flag, t, st));
+    else SRP_TRY(sketch_factor_run(SY, SRP_F64, s, dy, ly, Ry, Rinv2, My, flag, t, st, nullptr, factor_aux(ctx, 0)));
   }
   const bool warm = opt.warm_start_iters > 0;
   const bool pencil = wbv[0] || wbv[1];
@@ -2349,7 +2349,7 @@ int lda_solve_csr_impl(const CsrView& X, const int32_t* labels, int c, int k, do
       if (!wk.base) { set_error("workspace layout overflow"); return SRP_ENOMEM; }
       SRP_TRY(woodbury_factor(SXh, SRP_F64, s, d, lam, R, Minv, flag, t, wk, &wbs, st));
     } else {
-      SRP_TRY(sketch_factor_run(SXh, SRP_F64, s, d, lam, R, Rinv, Minv, flag, t, st));
+      SRP_TRY(sketch_factor_run(SXh, SRP_F64, s, d, lam, R, Rinv, Minv, flag, t, st, nullptr, factor_aux(ctx, 0)));
     }
   }
   int hflag = 0;

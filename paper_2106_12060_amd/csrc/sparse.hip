@@ -19,7 +19,7 @@
 
 namespace srp {
 
-constexpr int kCscChunkRows = 512;
+constexpr int kCscChunkMax = 4096;   // largest chunk of rows in the CSC build
 // Entries per segment of a column in the products A^T P.
 constexpr int kCscSeg = 256;
 
@@ -52,13 +52,14 @@ int csr_validate(const CsrView& A, int* bad, hipStream_t st) {
 }
 
 // ------------------------------------------------------- CSC build
-__global__ void __launch_bounds__(256) k_csc_chunk_count(int64_t n, int d, const int64_t* __restrict__ ptr,
+__global__ void __launch_bounds__(256) k_csc_chunk_count(int64_t n, int d, int chunk_rows,
+                                                         const int64_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx, int* chunk_cnt) {
   extern __shared__ int cnt[];
   const int ch = blockIdx.x;
   for (int j = threadIdx.x; j < d; j += blockDim.x) cnt[j] = 0;
   __syncthreads();
-  const int64_t r0 = (int64_t)ch * kCscChunkRows, r1 = min(n, r0 + kCscChunkRows);
+  const int64_t r0 = (int64_t)ch * chunk_rows, r1 = min(n, r0 + chunk_rows);
   const int64_t e0 = ptr[r0], e1 = ptr[r1];
   for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&cnt[idx[e]], 1);
   __syncthreads();
@@ -67,35 +68,83 @@ __global__ void __launch_bounds__(256) k_csc_chunk_count(int64_t n, int d, const
 
 // Per column: the chunk counts become offsets inside the column (exclusive
 // scan over the chunks, in chunk order); total[j] = entries of column j.
-__global__ void k_csc_col_scan(int nchunks, int d, int* chunk_cnt, int* total) {
+// Three levels over groups of kCscScanGroup chunks: the groups' sums (one
+// thread per group and column), their scan per column, then each group's
+// chunks from its offset; every level keeps sixteen loads in flight.
+constexpr int kCscScanGroup = 64;
+
+__global__ void k_csc_group_sums(int nchunks, int d, const int* __restrict__ chunk_cnt, int* __restrict__ gsum) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int ngroups = (nchunks + kCscScanGroup - 1) / kCscScanGroup;
+  if (t >= (int64_t)ngroups * d) return;
+  const int g = (int)(t / d), j = (int)(t - (int64_t)g * d);
+  const int c0 = g * kCscScanGroup, c1 = min(nchunks, c0 + kCscScanGroup);
+  int sum = 0;
+  for (int ch0 = c0; ch0 < c1; ch0 += 16) {
+    int v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = ch0 + u < c1 ? chunk_cnt[(int64_t)(ch0 + u) * d + j] : 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sum += v[u];
+  }
+  gsum[t] = sum;
+}
+
+__global__ void k_csc_group_scan(int ngroups, int d, int* __restrict__ gsum, int* __restrict__ total) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= d) return;
   int run = 0;
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int64_t o = (int64_t)ch * d + j;
-    const int t = chunk_cnt[o];
-    chunk_cnt[o] = run;
-    run += t;
+  for (int g0 = 0; g0 < ngroups; g0 += 16) {
+    int v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = g0 + u < ngroups ? gsum[(int64_t)(g0 + u) * d + j] : 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (g0 + u < ngroups) gsum[(int64_t)(g0 + u) * d + j] = run;
+      run += v[u];
+    }
   }
   total[j] = run;
 }
 
+__global__ void k_csc_chunk_offsets(int nchunks, int d, const int* __restrict__ gsum, int* __restrict__ chunk_cnt) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int ngroups = (nchunks + kCscScanGroup - 1) / kCscScanGroup;
+  if (t >= (int64_t)ngroups * d) return;
+  const int g = (int)(t / d), j = (int)(t - (int64_t)g * d);
+  const int c0 = g * kCscScanGroup, c1 = min(nchunks, c0 + kCscScanGroup);
+  int run = gsum[t];
+  for (int ch0 = c0; ch0 < c1; ch0 += 16) {
+    int v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = ch0 + u < c1 ? chunk_cnt[(int64_t)(ch0 + u) * d + j] : 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if (ch0 + u < c1) chunk_cnt[(int64_t)(ch0 + u) * d + j] = run;
+      run += v[u];
+    }
+  }
+}
+
 // One wave per chunk of rows, in row order: the entries of one row have
 // distinct columns, so its lanes bump distinct counters; the barrier after
-// each row orders the rows.
+// each row orders the rows.  The chunk's row pointers are staged in LDS
+// first, so a row waits only for its own entries.
 template <class T>
-__global__ void __launch_bounds__(64) k_csc_place(int64_t n, int d, const int64_t* __restrict__ ptr,
+__global__ void __launch_bounds__(64) k_csc_place(int64_t n, int d, int chunk_rows, const int64_t* __restrict__ ptr,
                                                   const int32_t* __restrict__ idx, const T* __restrict__ val,
                                                   const int* __restrict__ colptr, const int* __restrict__ chunk_off,
                                                   int32_t* __restrict__ rows_out, T* __restrict__ val_out) {
   extern __shared__ int off[];
+  int64_t* rp = reinterpret_cast<int64_t*>(off + ((d + 1) & ~1));   // chunk_rows + 1 row pointers
   const int ch = blockIdx.x;
+  const int64_t r0 = (int64_t)ch * chunk_rows, r1 = min(n, r0 + chunk_rows);
   for (int j = threadIdx.x; j < d; j += 64) off[j] = colptr[j] + chunk_off[(int64_t)ch * d + j];
+  for (int64_t r = r0 + threadIdx.x; r <= r1; r += 64) rp[r - r0] = ptr[r];
   __syncthreads();
-  const int64_t r0 = (int64_t)ch * kCscChunkRows, r1 = min(n, r0 + kCscChunkRows);
-  int64_t e0 = ptr[r0];
+  int64_t e0 = rp[0];
   for (int64_t r = r0; r < r1; ++r) {
-    const int64_t e1 = ptr[r + 1];
+    const int64_t e1 = rp[r + 1 - r0];
     for (int64_t e = e0 + threadIdx.x; e < e1; e += 64) {
       const int j = idx[e];
       const int pos = off[j];
@@ -108,7 +157,17 @@ __global__ void __launch_bounds__(64) k_csc_place(int64_t n, int d, const int64_
   }
 }
 
-static int csc_nchunks(int64_t n) { return (int)((n + kCscChunkRows - 1) / kCscChunkRows); }
+// Rows per chunk of the CSC build: 128, doubled while the per-chunk column
+// counters (chunks x d) would outnumber twice the entries.
+static int csc_chunk_rows(int64_t n, int d, int64_t nnz) {
+  int rows = 128;
+  while (rows < kCscChunkMax && ((n + rows - 1) / rows) * (int64_t)d > 2 * std::max<int64_t>(nnz, 1)) rows *= 2;
+  return rows;
+}
+static int csc_nchunks(const CsrView& A) {
+  const int rows = csc_chunk_rows(A.n, A.d, A.nnz);
+  return (int)((A.n + rows - 1) / rows);
+}
 
 // Segments of kCscSeg entries per column (a column of m entries has
 // ceil(m / kCscSeg) of them): at most nnz / kCscSeg + d in all.
@@ -130,7 +189,9 @@ size_t csc_bytes(const CsrView& A) {
 }
 
 size_t csc_scratch_bytes(const CsrView& A) {
-  return bytes_of<int>((size_t)csc_nchunks(A.n) * A.d) + bytes_of<int>((size_t)A.d + 1);
+  const int ngroups = (csc_nchunks(A) + kCscScanGroup - 1) / kCscScanGroup;
+  return bytes_of<int>((size_t)csc_nchunks(A) * A.d) + bytes_of<int>((size_t)ngroups * A.d) +
+         bytes_of<int>((size_t)A.d + 1);
 }
 
 int csc_build(const CsrView& A, CscView* out, Arena& keep, Arena& scratch, hipStream_t st) {
@@ -142,24 +203,33 @@ int csc_build(const CsrView& A, CscView* out, Arena& keep, Arena& scratch, hipSt
   out->val = keep.take<char>((size_t)A.nnz * dtype_size(A.dtype));
   out->segptr = keep.take<int>((size_t)A.d + 1);
   out->segcol = keep.take<int>((size_t)csc_max_segments(A));
-  const int nch = csc_nchunks(A.n);
+  const int crows = csc_chunk_rows(A.n, A.d, A.nnz);
+  const int nch = csc_nchunks(A);
+  const int ngroups = (nch + kCscScanGroup - 1) / kCscScanGroup;
   int* chunk = scratch.take<int>((size_t)nch * A.d);
+  int* gsum = scratch.take<int>((size_t)ngroups * A.d);
   int* total = scratch.take<int>((size_t)A.d + 1);
   if (!out->segcol || !total) { set_error("CSC copy: workspace too small"); return SRP_ENOMEM; }
   const size_t lds = sizeof(int) * (size_t)A.d;
+  const size_t lds_place = sizeof(int) * (size_t)((A.d + 1) & ~1) + sizeof(int64_t) * ((size_t)crows + 1);
   SRP_TRY(allow_dynamic_lds((const void*)k_csc_chunk_count, lds));
-  hipLaunchKernelGGL(k_csc_chunk_count, dim3(nch), dim3(256), lds, st, A.n, A.d, A.ptr, A.idx, chunk);
+  hipLaunchKernelGGL(k_csc_chunk_count, dim3(nch), dim3(256), lds, st, A.n, A.d, crows, A.ptr, A.idx, chunk);
   SRP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_csc_col_scan, dim3((A.d + 255) / 256), dim3(256), 0, st, nch, A.d, chunk, total);
+  const unsigned gthreads = (unsigned)(((int64_t)ngroups * A.d + 255) / 256);
+  hipLaunchKernelGGL(k_csc_group_sums, dim3(gthreads), dim3(256), 0, st, nch, A.d, chunk, gsum);
+  SRP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_csc_group_scan, dim3((A.d + 255) / 256), dim3(256), 0, st, ngroups, A.d, gsum, total);
+  SRP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_csc_chunk_offsets, dim3(gthreads), dim3(256), 0, st, nch, A.d, gsum, chunk);
   SRP_LAUNCH_CHECK();
   SRP_TRY(scan_excl_i32(total, A.d, out->ptr, st));
   if (A.dtype == SRP_F64) {
-    SRP_TRY(allow_dynamic_lds((const void*)k_csc_place<double>, lds));
-    hipLaunchKernelGGL(k_csc_place<double>, dim3(nch), dim3(64), lds, st, A.n, A.d, A.ptr, A.idx,
+    SRP_TRY(allow_dynamic_lds((const void*)k_csc_place<double>, lds_place));
+    hipLaunchKernelGGL(k_csc_place<double>, dim3(nch), dim3(64), lds_place, st, A.n, A.d, crows, A.ptr, A.idx,
                        (const double*)A.val, out->ptr, chunk, out->idx, (double*)out->val);
   } else {
-    SRP_TRY(allow_dynamic_lds((const void*)k_csc_place<float>, lds));
-    hipLaunchKernelGGL(k_csc_place<float>, dim3(nch), dim3(64), lds, st, A.n, A.d, A.ptr, A.idx,
+    SRP_TRY(allow_dynamic_lds((const void*)k_csc_place<float>, lds_place));
+    hipLaunchKernelGGL(k_csc_place<float>, dim3(nch), dim3(64), lds_place, st, A.n, A.d, crows, A.ptr, A.idx,
                        (const float*)A.val, out->ptr, chunk, out->idx, (float*)out->val);
   }
   SRP_LAUNCH_CHECK();
