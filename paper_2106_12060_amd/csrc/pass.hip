@@ -551,6 +551,9 @@ struct QuadShape {
   static constexpr int PP = 4 * C4 + 1;     // row pitch of [P_0 | P_1] in LDS
   static constexpr int PG = SV / 2;        // 4-tile groups of a wave's P products
   static constexpr int RED = kDmaRows * 4 * KG;   // one P partial (8 rows x 4 KG)
+  // LDS pitch of the partials: 2 mod 8 floats, so that the four lanes of a
+  // reducing quad (partials 8 apart) fall on different banks
+  static constexpr int REDP = RED + 2;
 };
 
 // Per-block work of k_pass_quad.  The LDS regions arrive as separate
@@ -575,16 +578,17 @@ __device__ __forceinline__ void quad_step(const float* __restrict__ xs, float* _
   constexpr int R = kDmaRows;
   constexpr int CH = 64 * VEC;
   constexpr int TPB = Q::TPB, KG = Q::KG, JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG;
-  constexpr int RED = Q::RED;
+  constexpr int RED = Q::RED, REDP = Q::REDP;
   const int tid = threadIdx.x;
   const int g = lane >> 4, l16 = lane & 15, cs = (lane >> 2) & 3, q4 = lane & 3;
   if (next_row0 >= 0) {
-    // wave w moves chunks j = w, w + 16, ... of every row; one buffer
-    // resource per view, rows past n read as zero
+    // waves 0-7 move chunks j = w, w + 8, ... of every row (the other
+    // eight waves go straight to the products); one buffer resource per
+    // view, rows past n read as zero
     const int rows = (int)(n - next_row0 < R ? n - next_row0 : R);
     const __amdgpu_buffer_rsrc_t r0 = make_rsrc(A0 + next_row0 * d0, (int64_t)rows * d0 * 4);
     const __amdgpu_buffer_rsrc_t r1 = make_rsrc(A1 + next_row0 * d1, (int64_t)rows * d1 * 4);
-    for (int j = w; j < nch; j += kF32Waves) {
+    for (int j = w; j < nch && w < kF32Waves / 2; j += kF32Waves / 2) {
       const bool s1 = j >= nch0;
       const int jj = s1 ? j - nch0 : j;
       const int span = (s1 ? T1 : T0) * 16;
@@ -601,25 +605,34 @@ __device__ __forceinline__ void quad_step(const float* __restrict__ xs, float* _
   // (b) P partials of this wave's view over its tiles: rows 4 rg + q4,
   // columns 4 cs .. 4 cs + 3 of each tile
   {
-    f32x4 pacc[2][KG];
+    f32x4 pacc[R / 4][KG];
 #pragma unroll
-    for (int rg = 0; rg < 2; ++rg)
+    for (int rg = 0; rg < R / 4; ++rg)
 #pragma unroll
       for (int kg = 0; kg < KG; ++kg) pacc[rg][kg] = f32x4{0, 0, 0, 0};
+    // all operand reads of the block issued before the first product
+    float4 a4[PG][R / 4];
 #pragma unroll
     for (int G = 0; G < PG; ++G)
 #pragma unroll
-      for (int rg = 0; rg < 2; ++rg) {
-        const float4 a = *reinterpret_cast<const float4*>(xs + (4 * rg + q4) * pitch + pcol[G]);
-        const float av[4] = {a.x, a.y, a.z, a.w};
+      for (int rg = 0; rg < R / 4; ++rg) a4[G][rg] = *reinterpret_cast<const float4*>(xs + (4 * rg + q4) * pitch + pcol[G]);
+#pragma unroll
+    for (int G = 0; G < PG; ++G)
+#pragma unroll
+      for (int rg = 0; rg < R / 4; ++rg) {
+        const float av[4] = {a4[G][rg].x, a4[G][rg].y, a4[G][rg].z, a4[G][rg].w};
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
           for (int kg = 0; kg < KG; ++kg) pacc[rg][kg] = mfma4x4(av[s], wreg[G][s][kg], pacc[rg][kg]);
       }
-    float* rw = red + (w * 4 + g) * RED + q4;
+    // Sum the four column phases in every lane (unconditionally, so that
+    // both rotations fold into the adds), then the phase-0 lanes publish
+    // the 16-lane row's partial: element ((rg KG + kg) 4 + q4) 4 + r is
+    // row 4 rg + r, direction column 4 kg + q4 (written as float pairs:
+    // the partial pitch is only 8-byte aligned).
 #pragma unroll
-    for (int rg = 0; rg < 2; ++rg)
+    for (int rg = 0; rg < R / 4; ++rg)
 #pragma unroll
       for (int kg = 0; kg < KG; ++kg)
 #pragma unroll
@@ -627,36 +640,55 @@ __device__ __forceinline__ void quad_step(const float* __restrict__ xs, float* _
           float x = pacc[rg][kg][r];
           x += dpp_row_ror<4>(x);
           x += dpp_row_ror<8>(x);
-          if (cs == 0) rw[(4 * rg + r) * (4 * KG) + 4 * kg] = x;
+          asm volatile("" : "+v"(x));
+          pacc[rg][kg][r] = x;
         }
+    if (cs == 0) {
+      float2* rw = reinterpret_cast<float2*>(red + (w * 4 + g) * REDP) + 2 * q4;
+#pragma unroll
+      for (int rg = 0; rg < R / 4; ++rg)
+#pragma unroll
+        for (int kg = 0; kg < KG; ++kg) {
+          rw[(rg * KG + kg) * 8] = float2{pacc[rg][kg][0], pacc[rg][kg][1]};
+          rw[(rg * KG + kg) * 8 + 1] = float2{pacc[rg][kg][2], pacc[rg][kg][3]};
+        }
+    }
   }
   lds_only_barrier();
-  if (tid < 2 * RED) {
-    // sum over a view's 32 (wave, 16-lane row) partials, in a fixed order.
-    // The indexes are recomputed per block (an opaque copy of tid):
-    // hoisted out of the loop they would stay live through the whole block
-    // and be spilled.
-    int t = tid;
+  // Sum over a view's 32 (wave, 16-lane row) partials in a fixed order: the
+  // four lanes of a quad add eight partials each (one batch of LDS reads),
+  // then two quad exchanges combine them.  The indexes are recomputed per
+  // block (an opaque copy of tid): hoisted out of the loop they would stay
+  // live through the whole block and be spilled.
+  for (int t4 = tid; t4 < 8 * RED; t4 += kF32Threads) {
+    int t = t4;
     asm volatile("" : "+v"(t));
-    const int v = t / RED, e = t - v * RED, row = e / (4 * KG), col = e - row * (4 * KG);
+    const int o = t >> 2, j = t & 3;
+    const int v = o / RED, e = o - v * RED;
+    const float* src = red + (v * 2 * kF32Waves + 8 * j) * REDP + e;
     float sum = 0.f;
-#pragma unroll 8
-    for (int h = 0; h < 2 * kF32Waves; ++h) sum += red[(v * 2 * kF32Waves + h) * RED + e];
-    if (col < k) pfull[row * PP + v * k + col] = sum;
+#pragma unroll
+    for (int h = 0; h < 8; ++h) sum += src[h * REDP];
+    sum += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, sum), 0xB1, 0xF, 0xF, true));
+    sum += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, sum), 0x4E, 0xF, 0xF, true));
+    const int r = e & 3, q = (e >> 2) & 3, rk = e >> 4;
+    const int rg = rk / KG, kg = rk - rg * KG;
+    const int col = 4 * kg + q;
+    if (j == 0 && col < k) pfull[(4 * rg + r) * PP + v * k + col] = sum;
   }
   lds_only_barrier();
   // (d) J = A_b^T [P_0 | P_1]
   if constexpr (JQ > 0) {
-    float pb[2][JQ];
+    float pb[R / 4][JQ];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < R / 4; ++s)
 #pragma unroll
       for (int jq = 0; jq < JQ; ++jq) pb[s][jq] = pfull[(g + 4 * s) * PP + 16 * jq + l16];
 #pragma unroll
     for (int i = 0; i < TPB; ++i) {
       const int col = 16 * (i < SV ? w + 16 * i : T0 + w + 16 * (i - SV));
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int s = 0; s < R / 4; ++s) {
         const float a = xs[(g + 4 * s) * pitch + col + l16];
 #pragma unroll
         for (int jq = 0; jq < JQ; ++jq) acc[i][jq] = mfma16x16x4(a, pb[s][jq], acc[i][jq]);
@@ -664,7 +696,7 @@ __device__ __forceinline__ void quad_step(const float* __restrict__ xs, float* _
     }
   }
   if constexpr (JR > 0) {
-    // step rho: lane row g takes block row (rho + g) mod 8 (the four tiles
+    // step rho: lane row g takes block row (rho + g) mod R (the four tiles
     // of an instruction then read different banks)
 #pragma unroll
     for (int rho = 0; rho < R; ++rho) {
@@ -693,14 +725,13 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restri
   constexpr int R = kDmaRows;
   constexpr int CH = 64 * VEC;
   constexpr int TPB = Q::TPB, KG = Q::KG, JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG;
-  constexpr int RED = Q::RED;
   extern __shared__ float dsm[];
   const int T0 = (d0 + 15) >> 4, T1 = (d1 + 15) >> 4;
   const int nch0 = (T0 * 16 + CH - 1) / CH, nch1 = (T1 * 16 + CH - 1) / CH;
   const int nch = nch0 + nch1;
   const int pitch = quad_pitch(TPB);
-  float* red = dsm + 2 * R * pitch;                 // [wave][16-lane row][R][4 KG]
-  float* pfull = red + kF32Waves * 4 * RED;         // [R][PP]
+  float* red = dsm + 2 * R * pitch;                 // [wave][16-lane row] partials, pitch REDP
+  float* pfull = red + kF32Waves * 4 * Q::REDP;     // [R][PP]
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1579,7 +1610,7 @@ static int quad_sv(int d0, int d1) {
 static size_t quad_lds_bytes(int sv, int c4) {
   const size_t pitch = (size_t)quad_pitch(2 * sv);
   const size_t kg = (size_t)(c4 + 1) / 2;
-  return (2 * kDmaRows * pitch + (size_t)kF32Waves * 4 * kDmaRows * 4 * kg + (size_t)kDmaRows * (4 * c4 + 1)) *
+  return (2 * kDmaRows * pitch + (size_t)kF32Waves * 4 * (kDmaRows * 4 * kg + 2) + (size_t)kDmaRows * (4 * c4 + 1)) *
          sizeof(float);
 }
 
