@@ -845,6 +845,7 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restri
   }
 }
 
+
 // ------------------------------------------------------------------
 // FP32, one view (FDA: J = A^T (A W), k <= 20): the same row stream with
 // the narrow products on 4x4 blocks.
@@ -852,27 +853,14 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restri
 //     16-lane rows g of an instruction take four tiles); a block is 4 rows
 //     x 4 direction columns over one column in four; rows 0-3 and 4-7 are
 //     done one after the other (20 accumulator registers at k = 20).  The
-//     column phases are summed by two DPP rotations and the four tiles of
-//     an instruction by two lane-row swaps (v_permlane16_swap,
-//     v_permlane32_swap), so each wave publishes one 8 x 4 KG partial.
+//     four tiles of an instruction are summed by lane-row swaps
+//     (v_permlane32_swap, v_permlane16_swap) that scatter the sums of four
+//     values over the four lane rows, the column phases by two DPP
+//     rotations, so each wave publishes one 8 x 4 KG partial.
 //   * J = A^T P: whole 16-column tiles of P on 16x16x4, the remaining
 //     4-column groups on 4x4 blocks over four tiles at once, as above.
 // Wave w owns J slots w + 16 i (i < TPB); slots and P tiles past the last
 // tile have zero directions and their rows are not stored.
-__device__ __forceinline__ float lane_rows_sum(float x) {
-  // Sum over the four 16-lane rows, in every lane: v_permlane16_swap on two
-  // copies of x leaves rows (1, 0, 3, 2) in one and (0, 1, 2, 3) in the
-  // other, so their sum holds rows 0 + 1 and 2 + 3; v_permlane32_swap then
-  // adds the halves.  Written as asm with both registers read and written:
-  // the compiler's builtin for these swaps drops the second result.  The
-  // s_nop pairs give the VALU-write / permlane wait states.
-  float a = x, b = x;
-  asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
-  float c = a + b, d = a + b;
-  asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(c), "+v"(d));
-  return c + d;
-}
-
 template <int TPB, int KG>
 struct Quad1Shape {
   static constexpr int PG = TPB / 4;        // 4-tile groups of a wave's P products
@@ -881,7 +869,42 @@ struct Quad1Shape {
   static constexpr int NG = TPB / 4;        // 4-slot groups of the remainder products
   static constexpr int PP = 4 * KG + 1;     // row pitch of P in LDS
   static constexpr int RED = kDmaRows * 4 * KG;
+  // LDS pitch of the wave partials: 4 mod 16 floats, so that the four lanes
+  // of a reducing quad (partials 4 apart) fall on different banks
+  static constexpr int REDP = RED + 4;
 };
+
+// The matrix-core results in p are complete before the lane swaps below
+// read them (the swaps are inline assembly, outside the compiler's hazard
+// tracking): 19 wait states cover the longest result latency.
+template <int KH>
+__device__ __forceinline__ void xdl_settle(f32x4 (&p)[KH]) {
+  if constexpr (KH == 1) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]));
+  else if constexpr (KH == 2) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]));
+  else if constexpr (KH == 3) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]), "+v"(p[2]));
+  else {
+    static_assert(KH == 4, "up to four accumulators");
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]), "+v"(p[2]), "+v"(p[3]));
+  }
+}
+
+// Sums of the four values x[0..3] over the four 16-lane rows, scattered:
+// afterwards 16-lane row g holds the sum of x[r], r = (0, 2, 1, 3)[g].
+// v_permlane32_swap exchanges the upper half of its first operand with the
+// lower half of its second, so the sum of the swapped pair (x[0], x[1])
+// holds x[0] over rows (g, g + 2) in rows 0-1 and x[1] in rows 2-3;
+// v_permlane16_swap (odd rows of the first operand with even rows of the
+// second) then finishes two such pairs in one step.  Four swaps and four
+// adds reduce four values, against two swaps and three adds per value for
+// separate full sums.
+__device__ __forceinline__ float rows_scatter_sum(f32x4 x) {
+  float u0 = x[0], v0 = x[1], u1 = x[2], v1 = x[3];
+  asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\tv_permlane32_swap_b32 %2, %3\n\ts_nop 1"
+      : "+v"(u0), "+v"(v0), "+v"(u1), "+v"(v1));
+  float p = u0 + v0, q = u1 + v1;
+  asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(p), "+v"(q));
+  return p + q;
+}
 
 template <int TPB, int KG, int VEC>
 __device__ __forceinline__ void quad1_step(const float* __restrict__ xs, float* __restrict__ xnext,
@@ -894,7 +917,7 @@ __device__ __forceinline__ void quad1_step(const float* __restrict__ xs, float* 
   using Q = Quad1Shape<TPB, KG>;
   constexpr int R = kDmaRows;
   constexpr int CH = 64 * VEC;
-  constexpr int JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG, RED = Q::RED;
+  constexpr int JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG, RED = Q::RED, REDP = Q::REDP;
   const int tid = threadIdx.x;
   const int g = lane >> 4, l16 = lane & 15, cs = (lane >> 2) & 3, q4 = lane & 3;
   if (next_row0 >= 0) {
@@ -933,27 +956,42 @@ __device__ __forceinline__ void quad1_step(const float* __restrict__ xs, float* 
         for (int kk = 0; kk < KH; ++kk)
           if (k0 + kk < KG) pacc[kk] = mfma4x4(av[s], wreg[G][s][k0 + kk], pacc[kk]);
     }
+    // the wave's partial: the four tiles of a lane row by a scattered
+    // row sum, then the four column phases (in every lane, so that both
+    // rotations fold into the adds); lane (g, 0, q4) holds row 4 rg + r,
+    // r = (0, 2, 1, 3)[g], direction column 4 kg + q4
+    xdl_settle<KH>(pacc);
+    float sums[KH];
 #pragma unroll
-    for (int kk = 0; kk < KH; ++kk)
+    for (int kk = 0; kk < KH; ++kk) {
+      float x = rows_scatter_sum(pacc[kk]);
+      x += dpp_row_ror<4>(x);
+      x += dpp_row_ror<8>(x);
+      asm volatile("" : "+v"(x));
+      sums[kk] = x;
+    }
+    if (cs == 0) {
+      const int r = ((g & 1) << 1) | (g >> 1);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (k0 + kk >= KG) continue;
-        float x = pacc[kk][r];
-        x += dpp_row_ror<4>(x);
-        x += dpp_row_ror<8>(x);
-        x = lane_rows_sum(x);
-        if (lane < 4) red[w * RED + (4 * rg + r) * (4 * KG) + 4 * (k0 + kk) + q4] = x;
-      }
+      for (int kk = 0; kk < KH; ++kk)
+        if (k0 + kk < KG) red[w * REDP + (4 * rg + r) * (4 * KG) + 4 * (k0 + kk) + q4] = sums[kk];
+    }
   }
   lds_only_barrier();
-  if (tid < RED) {   // sum over the 16 waves, in a fixed order
-    int t = tid;
+  // Sum over the 16 wave partials in a fixed order: the four lanes of a
+  // quad add four partials each, then two quad exchanges combine them.
+  for (int t4 = tid; t4 < 4 * RED; t4 += kF32Threads) {
+    int t = t4;
     asm volatile("" : "+v"(t));
-    const int row = t / (4 * KG), col = t - row * (4 * KG);
+    const int e = t >> 2, j = t & 3;
+    const float* src = red + 4 * j * REDP + e;
     float sum = 0.f;
 #pragma unroll
-    for (int h = 0; h < kF32Waves; ++h) sum += red[h * RED + t];
-    if (col < k) pfull[row * PP + col] = sum;
+    for (int h = 0; h < 4; ++h) sum += src[h * REDP];
+    sum += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, sum), 0xB1, 0xF, 0xF, true));
+    sum += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, sum), 0x4E, 0xF, 0xF, true));
+    const int row = e / (4 * KG), col = e - row * (4 * KG);
+    if (j == 0 && col < k) pfull[row * PP + col] = sum;
   }
   lds_only_barrier();
   // (d) J = A^T P
@@ -999,13 +1037,13 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad1(const float* __restr
   using Q = Quad1Shape<TPB, KG>;
   constexpr int R = kDmaRows;
   constexpr int CH = 64 * VEC;
-  constexpr int JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG, RED = Q::RED;
+  constexpr int JQ = Q::JQ, JR = Q::JR, NG = Q::NG, PP = Q::PP, PG = Q::PG;
   extern __shared__ float dsm[];
   const int T0 = (d0 + 15) >> 4;
   const int nch0 = (T0 * 16 + CH - 1) / CH;
   const int pitch = quad_pitch(TPB);
-  float* red = dsm + 2 * R * pitch;          // [wave][R][4 KG]
-  float* pfull = red + kF32Waves * RED;      // [R][PP]
+  float* red = dsm + 2 * R * pitch;          // [wave][R][4 KG], pitch REDP
+  float* pfull = red + kF32Waves * Q::REDP;  // [R][PP]
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, l16 = lane & 15, cs = (lane >> 2) & 3, q4 = lane & 3;
@@ -1674,7 +1712,7 @@ static int quad1_tpb(int d0) {
 }
 
 static size_t quad1_lds_bytes(int tpb, int kg) {
-  return (2 * kDmaRows * (size_t)quad_pitch(tpb) + (size_t)kF32Waves * kDmaRows * 4 * kg +
+  return (2 * kDmaRows * (size_t)quad_pitch(tpb) + (size_t)kF32Waves * (kDmaRows * 4 * kg + 4) +
           (size_t)kDmaRows * (4 * kg + 1)) * sizeof(float);
 }
 
