@@ -529,14 +529,9 @@ static int data_pass(const RcgProblem& P, RcgBuffers& B, double* const* W, int c
       SRP_HIP(hipEventCreate(&e1));
     }
     SRP_TRY(gram_pass_run(P.A[0], P.nb == 2 ? P.A[1] : nullptr, P.dtype, compute, P.n, P.d[0], P.d[1], P.k, W[0],
-                          P.nb == 2 ? W[1] : nullptr, B.J[0], P.nb == 2 ? B.J[1] : nullptr, done, pw, st, e0, e1));
-    if (e0) {
-      B.events->push_back({e0, e1});
-      if (B.ran) {
-        hipLaunchKernelGGL(k_count_pass, dim3(1), dim3(1), 0, st, done, B.ran);
-        SRP_LAUNCH_CHECK();
-      }
-    }
+                          P.nb == 2 ? W[1] : nullptr, B.J[0], P.nb == 2 ? B.J[1] : nullptr, done, pw, st, e0, e1,
+                          e0 ? B.ran : nullptr));
+    if (e0) B.events->push_back({e0, e1});
   }
   if (P.lda_cost) {   // S_B W = Yhat^T (Yhat W): c-row factor instead of the d x d matrix
     SRP_TRY(gemm_skinny_f64(P.c, P.d[0], P.k, P.Yhat, P.d[0], false, W[0], P.k, B.Tc, P.k, B.skw, B.skw_bytes, st));

@@ -101,13 +101,14 @@ int transpose_to_f64(const void* A, int dtype, int rows, int cols, double* AT, h
 
 // --------------------------------------------------------- data pass
 // J_b = A_b^T [A_0 W_0 | A_1 W_1] (see srp_gram_pass).  Arithmetic in
-// `compute` (SRP_F64 / SRP_F32).
+// `compute` (SRP_F64 / SRP_F32).  With `ran`, a pass that runs (done not
+// set) adds one to *ran on the device.
 size_t pass_ws_bytes(int64_t n, int d0, int d1, int k, int compute);
 const char* gram_pass_kernel_name(int dtype, int compute, int d0, int d1, int k);
 int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1,
                   int k, const double* W0, const double* W1, double* J0, double* J1, const int* done,
                   Arena& ws, hipStream_t st, hipEvent_t before_pass = nullptr,
-                  hipEvent_t after_pass = nullptr);
+                  hipEvent_t after_pass = nullptr, int* ran = nullptr);
 // FDA centring (Section 5.1): class counts and FP64 sums, Yhat rows
 // sqrt(n_k)(m_k - m), and the materialised Xhat = X - m_{y_i} in the data
 // type.  Returns SRP_EINVAL (via *bad) for labels out of range.

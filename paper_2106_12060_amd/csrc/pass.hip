@@ -1171,13 +1171,19 @@ template <class CT> static size_t pass_lds_bytes(int D, int NT) {
   return ((size_t)16 * pass_pitch(D) + (size_t)kPassWaves * NT * 256 + (size_t)NT * 272) * sizeof(CT);
 }
 
+// Counter that the pass reductions of the current gram_pass_run call on
+// this host thread bump (null: none).  Set for the length of one call.
+static thread_local int* t_pass_ran = nullptr;
+
 // J_b[c][j] = sum over partials, in a fixed order: each of 4 thread groups
 // sums a contiguous quarter of the partials, then the quarters are added.
+// A pass that ran (no done flag set) also counts itself in *ran when given.
 template <class CT>
 __global__ void __launch_bounds__(256) k_pass_reduce(const CT* __restrict__ partial, int nparts, int d0, int d1,
                                                      int W_out, double* __restrict__ J0, double* __restrict__ J1,
-                                                     const int* __restrict__ done) {
+                                                     const int* __restrict__ done, int* __restrict__ ran) {
   if (done && *done) return;
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) ++*ran;
   __shared__ double q4[4][64];
   const int64_t Dtot = d0 + d1;
   const int64_t count = Dtot * W_out;
@@ -1497,7 +1503,7 @@ static int pass_launch_bf(const unsigned short* A0, const unsigned short* A1, in
   if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
   const int64_t count = (int64_t)Dtot * NB * k;
   hipLaunchKernelGGL((k_pass_reduce<float>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, grid, d0,
-                     NB == 2 ? d1 : 0, NB * k, J0, J1, done);
+                     NB == 2 ? d1 : 0, NB * k, J0, J1, done, t_pass_ran);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -1581,7 +1587,7 @@ static int pass_launch(const DT* A0, const DT* A1, int64_t n, int d0, int d1, in
   if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
   const int64_t count = (int64_t)Dtot * NB * k;
   hipLaunchKernelGGL((k_pass_reduce<CT>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, groups, d0,
-                     NB == 2 ? d1 : 0, NB * k, J0, J1, done);
+                     NB == 2 ? d1 : 0, NB * k, J0, J1, done, t_pass_ran);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -1610,7 +1616,7 @@ static int pass_launch_dma(const float* A0, const float* A1, int64_t n, int d0, 
   if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
   const int64_t count = (int64_t)Dtot * NB * k;
   hipLaunchKernelGGL((k_pass_reduce<float>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, grid, d0,
-                     NB == 2 ? d1 : 0, NB * k, J0, J1, done);
+                     NB == 2 ? d1 : 0, NB * k, J0, J1, done, t_pass_ran);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -1680,7 +1686,7 @@ static int pass_launch_quad(const float* A0, const float* A1, int64_t n, int d0,
   if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
   const int64_t count = (int64_t)Dtot * 2 * k;
   hipLaunchKernelGGL((k_pass_reduce<float>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, grid, d0,
-                     d1, 2 * k, J0, J1, done);
+                     d1, 2 * k, J0, J1, done, t_pass_ran);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -1744,7 +1750,7 @@ static int pass_launch_quad1(const float* A0, int64_t n, int d0, int k, const do
   if (after_pass) SRP_HIP(hipEventRecord(after_pass, st));
   const int64_t count = (int64_t)d0 * k;
   hipLaunchKernelGGL((k_pass_reduce<float>), dim3((unsigned)((count + 63) / 64)), dim3(256), 0, st, part, grid, d0,
-                     0, k, J0, (double*)nullptr, done);
+                     0, k, J0, (double*)nullptr, done, t_pass_ran);
   SRP_LAUNCH_CHECK();
   return SRP_OK;
 }
@@ -1799,7 +1805,11 @@ const char* gram_pass_kernel_name(int dtype, int compute, int d0, int d1, int k)
 
 int gram_pass_run(const void* A0, const void* A1, int dtype, int compute, int64_t n, int d0, int d1, int k,
                   const double* W0, const double* W1, double* J0, double* J1, const int* done, Arena& ws,
-                  hipStream_t st, hipEvent_t before_pass, hipEvent_t after_pass) {
+                  hipStream_t st, hipEvent_t before_pass, hipEvent_t after_pass, int* ran) {
+  struct RanScope {
+    explicit RanScope(int* r) { t_pass_ran = r; }
+    ~RanScope() { t_pass_ran = nullptr; }
+  } ran_scope(ran);
   const int nb = A1 ? 2 : 1;
   if (!pass_limits_ok(dtype, compute, d0, d1, k, nb)) {
     set_error("gram_pass: unsupported shape (d0=%d d1=%d k=%d dtype=%d compute=%d)", d0, d1, k, dtype, compute);
