@@ -10,6 +10,7 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#include <type_traits>
 #include <vector>
 
 namespace srp {
@@ -222,6 +223,121 @@ __global__ void __launch_bounds__(256) k_gemm_f64_big(int m, int n, int kk, doub
       }
 }
 
+// FP32 operands (the sketch Grams of FP32 sketches): the tiles and wave
+// quadrants of k_gemm_f64_big, with the operand stages moved HBM -> LDS by
+// buffer loads with the LDS flag (no staging registers) into a ring of
+// kGdStages stages, the next three in flight while one is multiplied.  A
+// stage is 16 contraction rows of the tile's 128 columns of A and of B.
+// One load instruction moves rows r and r + 8 of one operand (16 B per
+// lane: lanes 0-31 row r, lanes 32-63 row r + 8) into slot r of 256 + 16
+// floats, so the four rows one matrix step reads (4 s .. 4 s + 3: slots
+// 16 floats apart) fall on distinct banks.  Each wave issues the same four
+// instructions per stage (slots 2 w, 2 w + 1 of A and of B), so waiting for
+// a stage leaves (stages issued after it) x 4 of its loads outstanding.
+// The operands are converted to FP64 as they are read.
+constexpr int kGdStages = 4;
+constexpr int kGdSlot = 272;                  // floats per slot: two rows + pad
+constexpr int kGdStage = 2 * 8 * kGdSlot;     // slots of A, then of B
+
+__device__ __forceinline__ void gd_wait(int n) {   // at most n of this wave's loads outstanding
+  if (n >= 8) __builtin_amdgcn_s_waitcnt(8 | (0x7 << 4) | (0xF << 8));
+  else if (n >= 4) __builtin_amdgcn_s_waitcnt(4 | (0x7 << 4) | (0xF << 8));
+  else __builtin_amdgcn_s_waitcnt(0 | (0x7 << 4) | (0xF << 8));
+}
+
+// One stage: issue the loads of stage `qi` (when issue) into nxt, then
+// multiply the stage in cur (when mult).  The two regions arrive as
+// separate restrict pointers, so the compiler sees the reads of cur as
+// disjoint from the writes into nxt and waits on no load before them.
+__device__ __forceinline__ void gd_step(const float* __restrict__ cur, float* __restrict__ nxt, bool issue, int k0,
+                                        int kend, __amdgpu_buffer_rsrc_t ars, __amdgpu_buffer_rsrc_t brs, int lda,
+                                        int ldb, int m, int n, int i0, int j0, int w, int lane, bool mult,
+                                        f64x4 (&acc)[4][4], int wi, int wj) {
+  if (issue) {
+    const int half = lane >> 5, c4 = 4 * (lane & 31);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int slot = 2 * w + u;
+      const int row = k0 + slot + 8 * half;
+      const int ia = i0 + c4, jb = j0 + c4;
+      const int oa = (row < kend && ia < m) ? (row * lda + ia) * 4 : kOob;
+      const int ob = (row < kend && jb < n) ? (row * ldb + jb) * 4 : kOob;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ars, (__attribute__((address_space(3))) void*)(nxt + slot * kGdSlot),
+                                               16, oa, 0, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(brs,
+                                               (__attribute__((address_space(3))) void*)(nxt + (8 + slot) * kGdSlot),
+                                               16, ob, 0, 0, 0);
+    }
+  }
+  if (!mult) return;
+  const int g = lane >> 4, l16 = lane & 15;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int kl = 4 * s + g;
+    const int base = (kl & 7) * kGdSlot + (kl >> 3) * 128 + l16;
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = (double)cur[base + wi + 16 * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = (double)cur[8 * kGdSlot + base + wj + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = mfma16x16x4(av[a], bv[b], acc[a][b]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gemm_f64_dma(int m, int n, int kk, double alpha, const float* __restrict__ A,
+                                                      int64_t lda, const float* __restrict__ B, int64_t ldb,
+                                                      double beta, double* __restrict__ C, int64_t ldc,
+                                                      int upper_only, int kchunk, int64_t c_split_stride) {
+  constexpr int NST = kGdStages, LOOK = NST - 1;
+  const int tj = blockIdx.x, ti = blockIdx.y, z = blockIdx.z;
+  if (upper_only && ti > tj) return;
+  const int i0 = ti * 128, j0 = tj * 128;
+  const int kbeg = z * kchunk;
+  const int kend = min(kk, kbeg + kchunk);
+  C += (int64_t)z * c_split_stride;
+  extern __shared__ float gsm[];
+  const int t = threadIdx.x, lane = t & 63;
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wi = (w >> 1) * 64, wj = (w & 1) * 64;
+  const __amdgpu_buffer_rsrc_t ars = make_rsrc(A, (int64_t)kk * lda * 4);
+  const __amdgpu_buffer_rsrc_t brs = make_rsrc(B, (int64_t)kk * ldb * 4);
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int nstg = kbeg < kend ? (kend - kbeg + 15) / 16 : 0;
+  // step q < 0 only issues stage q + LOOK; step q >= 0 waits for stage q
+  // (this wave's loads, then every wave's), issues stage q + LOOK into the
+  // slot stage q - 1 left and multiplies stage q
+  for (int q = -LOOK; q < nstg; ++q) {
+    if (q >= 0) {
+      gd_wait(4 * min(LOOK - 1, nstg - 1 - q));
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    }
+    const int qi = q + LOOK;
+    gd_step(gsm + ((q + NST) % NST) * kGdStage, gsm + (qi % NST) * kGdStage, qi < nstg, kbeg + 16 * qi, kend, ars,
+            brs, (int)lda, (int)ldb, m, n, i0, j0, w, lane, q >= 0, acc, wi, wj);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + wi + 16 * a + acc_row<double>(lane, r);
+        const int col = j0 + wj + 16 * b + (lane & 15);
+        if (row < m && col < n) {
+          double v = alpha * acc[a][b][r];
+          if (beta != 0.0) v += beta * C[(int64_t)row * ldc + col];
+          C[(int64_t)row * ldc + col] = v;
+        }
+      }
+}
+
 // The big-tile kernel takes A^T B with both output sides and the
 // contraction long enough to fill its tiles and stages.
 static bool gemm_big(const GemmArgs& g) {
@@ -235,6 +351,17 @@ static int gemm_dispatch_t(const GemmArgs& g, hipStream_t st) {
   if (g.ksplit > 1) kchunk = (((g.kk + g.ksplit - 1) / g.ksplit) + kGemmK - 1) / kGemmK * kGemmK;
   const AT* A = (const AT*)g.A;
   const BT* B = (const BT*)g.B;
+  if (gemm_big(g) && std::is_same<AT, float>::value && std::is_same<BT, float>::value && g.lda % 4 == 0 &&
+      g.ldb % 4 == 0 && ((uintptr_t)g.A & 15) == 0 && ((uintptr_t)g.B & 15) == 0 &&
+      (int64_t)g.kk * g.lda * 4 < kOob && (int64_t)g.kk * g.ldb * 4 < kOob) {
+    const dim3 gb((g.n + 127) / 128, (g.m + 127) / 128, g.ksplit);
+    const size_t lds = (size_t)kGdStages * kGdStage * sizeof(float);
+    SRP_TRY(allow_dynamic_lds((const void*)k_gemm_f64_dma, lds));
+    hipLaunchKernelGGL(k_gemm_f64_dma, gb, dim3(256), lds, st, g.m, g.n, g.kk, g.alpha, (const float*)g.A, g.lda,
+                       (const float*)g.B, g.ldb, g.beta, g.C, g.ldc, (int)g.upper_only, kchunk, g.c_split_stride);
+    SRP_LAUNCH_CHECK();
+    return SRP_OK;
+  }
   if (gemm_big(g)) {   // kchunk is a multiple of kGemmK, hence of kGemmBigK
     const dim3 gb((g.n + 127) / 128, (g.m + 127) / 128, g.ksplit);
     hipLaunchKernelGGL((k_gemm_f64_big<AT, BT>), gb, dim3(256), 0, st, g.m, g.n, g.kk, g.alpha, A, g.lda, B, g.ldb,
@@ -270,6 +397,22 @@ __global__ void k_sum_parts(const double* parts, int nparts, int64_t stride, int
   for (int z = 0; z < nparts; ++z) v += parts[z * stride + i];
   if (d > 0 && (i / d) == (i % d)) v += diag_add;
   out[i] = v;
+}
+
+// The symmetric d x d Gram from upper-tile partials: entries with i <= j
+// are summed in split order (diag_add on the diagonal); those below the
+// diagonal, which no upper tile need cover and nothing reads, are set to
+// zero without reading the partials (so the partials need no clearing).
+__global__ void k_sum_upper(const double* parts, int nparts, int64_t stride, int d, double diag_add, double* out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d * d) return;
+  const int i = (int)(e / d), j = (int)(e - (int64_t)i * d);
+  double v = 0.0;
+  if (i <= j) {
+    for (int z = 0; z < nparts; ++z) v += parts[z * stride + e];
+    if (i == j) v += diag_add;
+  }
+  out[e] = v;
 }
 
 int sum_parts_f64(const double* parts, int nparts, int64_t stride, int64_t count, double* out, int d,
@@ -947,11 +1090,14 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
   g.A = SA; g.lda = d; g.ta = true; g.a_f32 = f32;
   g.B = SA; g.ldb = d; g.tb = false; g.b_f32 = f32;
   g.upper_only = true;
+  // every upper-tile entry of every split is written by the GEMM, and only
+  // those (i <= j) are read: no clearing of the partials
   if (use_parts) {
     g.C = parts; g.ldc = d; g.ksplit = ksplit; g.c_split_stride = dd;
-    SRP_TRY(fill_f64(parts, dd * ksplit, 0.0, st));
     SRP_TRY(gemm_f64(g, st));
-    SRP_TRY(sum_parts_f64(parts, ksplit, dd, dd, G, d, lambda, st));
+    hipLaunchKernelGGL(k_sum_upper, dim3((unsigned)((dd + 255) / 256)), dim3(256), 0, st, parts, ksplit, dd, d,
+                       lambda, G);
+    SRP_LAUNCH_CHECK();
     if (Hfull) {
       hipLaunchKernelGGL(k_gram_full, dim3((unsigned)((dd + 255) / 256)), dim3(256), 0, st, parts, ksplit, dd, d,
                          Hfull);
@@ -959,9 +1105,9 @@ int sketch_factor_run(const void* SA, int dtype, int s, int d, double lambda, do
     }
   } else {
     g.C = G; g.ldc = d;
-    SRP_TRY(fill_f64(G, dd, 0.0, st));
     SRP_TRY(gemm_f64(g, st));
-    SRP_TRY(sum_parts_f64(G, 1, dd, dd, G, d, lambda, st));
+    hipLaunchKernelGGL(k_sum_upper, dim3((unsigned)((dd + 255) / 256)), dim3(256), 0, st, G, 1, dd, d, lambda, G);
+    SRP_LAUNCH_CHECK();
   }
   // Right-looking blocked Cholesky, 64-wide panels; column block kb of
   // X = R^-1 follows diagonal block kb, on the second stream when there is
