@@ -101,7 +101,10 @@ def test_srht_full_sample_is_isometry():
 @pytest.mark.parametrize("s,d,dt,lam", [(500, 120, "f64", 1e-3), (900, 200, "f32", 1e-2),
                                         (64, 64, "f64", 0.5), (300, 65, "f32", 1e-4),
                                         # 128 x 128 Gram tiles with ragged edges and a split contraction
-                                        (1300, 300, "f32", 1e-3), (2100, 520, "f64", 1e-2)])
+                                        # (FP32 rows of 16-byte multiples: load-to-LDS stages; else
+                                        # register-staged)
+                                        (1300, 300, "f32", 1e-3), (2100, 520, "f64", 1e-2),
+                                        (1100, 258, "f32", 1e-3)])
 def test_sketch_factor_matches_cholesky(s, d, dt, lam):
     srp = _srp()
     SA, SAq = quantised(rand_data(s, d, 11 + d, decades=1.0), dt)
