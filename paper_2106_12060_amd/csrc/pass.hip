@@ -541,6 +541,55 @@ __device__ __forceinline__ f32x4 mfma4x4(float a, float b, f32x4 c) {
 // as do the P operands' column quadruples of one 16-lane row.
 __host__ __device__ constexpr int quad_pitch(int TPB) { return ((16 * 16 * TPB + 63) / 64) * 64 + 16; }
 
+// The matrix-core results in p are complete before the lane swaps below
+// read them (the swaps are inline assembly, outside the compiler's hazard
+// tracking): 19 wait states cover the longest result latency.
+template <int KH>
+__device__ __forceinline__ void xdl_settle(f32x4 (&p)[KH]) {
+  if constexpr (KH == 1) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]));
+  else if constexpr (KH == 2) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]));
+  else if constexpr (KH == 3) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]), "+v"(p[2]));
+  else {
+    static_assert(KH == 4, "up to four accumulators");
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]), "+v"(p[2]), "+v"(p[3]));
+  }
+}
+
+// Sums of the four values x[0..3] over the four 16-lane rows, scattered:
+// afterwards 16-lane row g holds the sum of x[r], r = (0, 2, 1, 3)[g].
+// v_permlane32_swap exchanges the upper half of its first operand with the
+// lower half of its second, so the sum of the swapped pair (x[0], x[1])
+// holds x[0] over rows (g, g + 2) in rows 0-1 and x[1] in rows 2-3;
+// v_permlane16_swap (odd rows of the first operand with even rows of the
+// second) then finishes two such pairs in one step.  Four swaps and four
+// adds reduce four values, against two swaps and three adds per value for
+// separate full sums.
+__device__ __forceinline__ float rows_scatter_sum(f32x4 x) {
+  float u0 = x[0], v0 = x[1], u1 = x[2], v1 = x[3];
+  asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\tv_permlane32_swap_b32 %2, %3\n\ts_nop 1"
+      : "+v"(u0), "+v"(v0), "+v"(u1), "+v"(v1));
+  float p = u0 + v0, q = u1 + v1;
+  asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(p), "+v"(q));
+  return p + q;
+}
+
+// The same settle for two rows of KG accumulators.
+template <int KG>
+__device__ __forceinline__ void xdl_settle2(f32x4 (&p)[2][KG]) {
+  if constexpr (KG == 1) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0][0]), "+v"(p[1][0]));
+  else if constexpr (KG == 2)
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0][0]), "+v"(p[0][1]), "+v"(p[1][0]), "+v"(p[1][1]));
+  else if constexpr (KG == 3)
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3"
+                 : "+v"(p[0][0]), "+v"(p[0][1]), "+v"(p[0][2]), "+v"(p[1][0]), "+v"(p[1][1]), "+v"(p[1][2]));
+  else {
+    static_assert(KG == 4, "up to four accumulators per row group");
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3"
+                 : "+v"(p[0][0]), "+v"(p[0][1]), "+v"(p[0][2]), "+v"(p[0][3]), "+v"(p[1][0]), "+v"(p[1][1]),
+                   "+v"(p[1][2]), "+v"(p[1][3]));
+  }
+}
+
 template <int SV, int C4>
 struct QuadShape {
   static constexpr int TPB = 2 * SV;        // tile slots per wave
@@ -551,9 +600,9 @@ struct QuadShape {
   static constexpr int PP = 4 * C4 + 1;     // row pitch of [P_0 | P_1] in LDS
   static constexpr int PG = SV / 2;        // 4-tile groups of a wave's P products
   static constexpr int RED = kDmaRows * 4 * KG;   // one P partial (8 rows x 4 KG)
-  // LDS pitch of the partials: 2 mod 8 floats, so that the four lanes of a
-  // reducing quad (partials 8 apart) fall on different banks
-  static constexpr int REDP = RED + 2;
+  // LDS pitch of the wave partials: 8 mod 32 floats, so that the four lanes
+  // of a reducing quad (partials 2 apart) fall on different banks
+  static constexpr int REDP = RED + 8;
 };
 
 // Per-block work of k_pass_quad.  The LDS regions arrive as separate
@@ -626,38 +675,35 @@ __device__ __forceinline__ void quad_step(const float* __restrict__ xs, float* _
 #pragma unroll
           for (int kg = 0; kg < KG; ++kg) pacc[rg][kg] = mfma4x4(av[s], wreg[G][s][kg], pacc[rg][kg]);
       }
-    // Sum the four column phases in every lane (unconditionally, so that
-    // both rotations fold into the adds), then the phase-0 lanes publish
-    // the 16-lane row's partial: element ((rg KG + kg) 4 + q4) 4 + r is
-    // row 4 rg + r, direction column 4 kg + q4 (written as float pairs:
-    // the partial pitch is only 8-byte aligned).
+    // The wave's partial: the four tiles of a 16-lane row by a scattered
+    // row sum, then the four column phases (in every lane, so that both
+    // rotations fold into the adds); lane (g, 0, q4) holds row 4 rg + r,
+    // r = (0, 2, 1, 3)[g], direction column 4 kg + q4: element
+    // ((rg KG + kg) 4 + q4) 4 + r of the partial.
+    xdl_settle2<KG>(pacc);
+    float sums[2][KG];
 #pragma unroll
-    for (int rg = 0; rg < R / 4; ++rg)
+    for (int rg = 0; rg < 2; ++rg)
 #pragma unroll
-      for (int kg = 0; kg < KG; ++kg)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          float x = pacc[rg][kg][r];
-          x += dpp_row_ror<4>(x);
-          x += dpp_row_ror<8>(x);
-          asm volatile("" : "+v"(x));
-          pacc[rg][kg][r] = x;
-        }
+      for (int kg = 0; kg < KG; ++kg) {
+        float x = rows_scatter_sum(pacc[rg][kg]);
+        x += dpp_row_ror<4>(x);
+        x += dpp_row_ror<8>(x);
+        asm volatile("" : "+v"(x));
+        sums[rg][kg] = x;
+      }
     if (cs == 0) {
-      float2* rw = reinterpret_cast<float2*>(red + (w * 4 + g) * REDP) + 2 * q4;
+      const int r = ((g & 1) << 1) | (g >> 1);
+      float* rw = red + w * REDP + 4 * q4 + r;
 #pragma unroll
-      for (int rg = 0; rg < R / 4; ++rg)
+      for (int rg = 0; rg < 2; ++rg)
 #pragma unroll
-        for (int kg = 0; kg < KG; ++kg) {
-          rw[(rg * KG + kg) * 8] = float2{pacc[rg][kg][0], pacc[rg][kg][1]};
-          rw[(rg * KG + kg) * 8 + 1] = float2{pacc[rg][kg][2], pacc[rg][kg][3]};
-        }
+        for (int kg = 0; kg < KG; ++kg) rw[(rg * KG + kg) * 16] = sums[rg][kg];
     }
   }
   lds_only_barrier();
-  // Sum over a view's 32 (wave, 16-lane row) partials in a fixed order: the
-  // four lanes of a quad add eight partials each (one batch of LDS reads),
-  // then two quad exchanges combine them.  The indexes are recomputed per
+  // Sum over a view's 8 wave partials in a fixed order: the four lanes of a
+  // quad add two partials each, then two quad exchanges combine them.  The indexes are recomputed per
   // block (an opaque copy of tid): hoisted out of the loop they would stay
   // live through the whole block and be spilled.
   for (int t4 = tid; t4 < 8 * RED; t4 += kF32Threads) {
@@ -665,10 +711,8 @@ __device__ __forceinline__ void quad_step(const float* __restrict__ xs, float* _
     asm volatile("" : "+v"(t));
     const int o = t >> 2, j = t & 3;
     const int v = o / RED, e = o - v * RED;
-    const float* src = red + (v * 2 * kF32Waves + 8 * j) * REDP + e;
-    float sum = 0.f;
-#pragma unroll
-    for (int h = 0; h < 8; ++h) sum += src[h * REDP];
+    const float* src = red + (v * kF32Waves / 2 + 2 * j) * REDP + e;
+    float sum = src[0] + src[REDP];
     sum += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, sum), 0xB1, 0xF, 0xF, true));
     sum += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, sum), 0x4E, 0xF, 0xF, true));
     const int r = e & 3, q = (e >> 2) & 3, rk = e >> 4;
@@ -730,8 +774,8 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_quad(const float* __restri
   const int nch0 = (T0 * 16 + CH - 1) / CH, nch1 = (T1 * 16 + CH - 1) / CH;
   const int nch = nch0 + nch1;
   const int pitch = quad_pitch(TPB);
-  float* red = dsm + 2 * R * pitch;                 // [wave][16-lane row] partials, pitch REDP
-  float* pfull = red + kF32Waves * 4 * Q::REDP;     // [R][PP]
+  float* red = dsm + 2 * R * pitch;                 // [wave] partials, pitch REDP
+  float* pfull = red + kF32Waves * Q::REDP;         // [R][PP]
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -873,38 +917,6 @@ struct Quad1Shape {
   // of a reducing quad (partials 4 apart) fall on different banks
   static constexpr int REDP = RED + 4;
 };
-
-// The matrix-core results in p are complete before the lane swaps below
-// read them (the swaps are inline assembly, outside the compiler's hazard
-// tracking): 19 wait states cover the longest result latency.
-template <int KH>
-__device__ __forceinline__ void xdl_settle(f32x4 (&p)[KH]) {
-  if constexpr (KH == 1) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]));
-  else if constexpr (KH == 2) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]));
-  else if constexpr (KH == 3) asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]), "+v"(p[2]));
-  else {
-    static_assert(KH == 4, "up to four accumulators");
-    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 3" : "+v"(p[0]), "+v"(p[1]), "+v"(p[2]), "+v"(p[3]));
-  }
-}
-
-// Sums of the four values x[0..3] over the four 16-lane rows, scattered:
-// afterwards 16-lane row g holds the sum of x[r], r = (0, 2, 1, 3)[g].
-// v_permlane32_swap exchanges the upper half of its first operand with the
-// lower half of its second, so the sum of the swapped pair (x[0], x[1])
-// holds x[0] over rows (g, g + 2) in rows 0-1 and x[1] in rows 2-3;
-// v_permlane16_swap (odd rows of the first operand with even rows of the
-// second) then finishes two such pairs in one step.  Four swaps and four
-// adds reduce four values, against two swaps and three adds per value for
-// separate full sums.
-__device__ __forceinline__ float rows_scatter_sum(f32x4 x) {
-  float u0 = x[0], v0 = x[1], u1 = x[2], v1 = x[3];
-  asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\tv_permlane32_swap_b32 %2, %3\n\ts_nop 1"
-      : "+v"(u0), "+v"(v0), "+v"(u1), "+v"(v1));
-  float p = u0 + v0, q = u1 + v1;
-  asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(p), "+v"(q));
-  return p + q;
-}
 
 template <int TPB, int KG, int VEC>
 __device__ __forceinline__ void quad1_step(const float* __restrict__ xs, float* __restrict__ xnext,
@@ -1654,7 +1666,7 @@ static int quad_sv(int d0, int d1) {
 static size_t quad_lds_bytes(int sv, int c4) {
   const size_t pitch = (size_t)quad_pitch(2 * sv);
   const size_t kg = (size_t)(c4 + 1) / 2;
-  return (2 * kDmaRows * pitch + (size_t)kF32Waves * 4 * (kDmaRows * 4 * kg + 2) + (size_t)kDmaRows * (4 * c4 + 1)) *
+  return (2 * kDmaRows * pitch + (size_t)kF32Waves * (kDmaRows * 4 * kg + 8) + (size_t)kDmaRows * (4 * c4 + 1)) *
          sizeof(float);
 }
 
