@@ -514,9 +514,10 @@ __global__ void __launch_bounds__(kF32Threads) k_pass_dma(const float* __restric
 //   * P_b = A_b W_b (8 rows x k): waves 0-7 work on view 0, waves 8-15 on
 //     view 1.  A block is 4 rows x 4 direction columns of one tile over one
 //     of every four of its columns: the four 16-lane rows take four tiles,
-//     the four blocks of a row the four column phases (summed by two DPP
-//     rotations), rows 0-3 and 4-7 are separate instructions.  The four
-//     tiles' partials are added in the cross-wave sum.
+//     the four blocks of a row the four column phases, rows 0-3 and 4-7 are
+//     separate instructions.  The four tiles are summed in registers by
+//     lane-row swaps and the column phases by two DPP rotations, so each
+//     wave publishes one partial to the cross-wave sum.
 //   * J_b = A_b^T [P_0 | P_1]: whole 16-column tiles of [P_0 | P_1] on the
 //     16 x 16 x 4 products; the remaining 4-column groups on 4x4 blocks,
 //     one row of the block per instruction over four tiles at once (the
