@@ -1131,6 +1131,166 @@ __device__ void block_jacobi(double* const* Av, double* const* Vv, double* const
   __syncthreads();
 }
 
+// ------------------------------------------ register Jacobi, one wave
+// The same parallel cyclic Jacobi for n <= 20 (n even) with the matrix in
+// registers.  Positions 2i and 2i + 1 hold the two indices of pair i;
+// lane b owns the 2 x 2 block of pair rows i and pair columns j (i <= j;
+// the blocks below the diagonal are the transposes; P (P + 1) / 2 <= 64
+// blocks for P = n / 2 pairs).
+// A round rotates every block by the rotations of its two pairs, which
+// each lane computes itself from the diagonal blocks of those pairs (read
+// beside its own entries), then moves the entries to the next pairing in
+// one exchange through LDS at fixed addresses: position u takes the index
+// that stood at rr_src(u) (index 0 stays, the other n - 1 turn one step
+// round a circle), so every two indices meet once in a sweep of n - 1
+// rounds and a sweep ends in the order it began.  The entry a rotation
+// annihilates is set to zero.  The rows of V do not move; its column pairs
+// are rotated by lanes that already hold the pair's rotation: lane (i, j)
+// keeps rows 2i, 2i + 1 of column pair j and, for i < j, rows 2j, 2j + 1
+// of column pair i.  On return A holds the rotated matrix (the eigenvalues
+// on its diagonal) and V the eigenvectors, A_in = V D V^T.  Scratch T:
+// 2 n x n.
+__device__ __forceinline__ int rr_src(int u, int P) {
+  if (P == 1 || u == 0) return u;
+  const int i = u >> 1;
+  if ((u & 1) == 0) return i == 1 ? 1 : u - 2;
+  return i == P - 1 ? u - 1 : u + 2;
+}
+
+// Rotation of a pair from its diagonal block (app, apq, aqq), free of
+// divisions: x = aqq - app and y = 2 apq are scaled by a common power of
+// two (exactly, so that no square below can overflow), r = sqrt(x^2 + y^2)
+// and D = |x| + r give the tangent sign(x) y / D of the classical choice
+// (the smaller angle), hence c = D / sqrt(D^2 + y^2) and
+// s = sign(x) y / sqrt(D^2 + y^2) with two reciprocal square roots;
+// c = 1, s = 0 when apq is zero.
+__device__ __forceinline__ void pair_rot(double app, double apq, double aqq, double* c, double* s) {
+  const double x0 = aqq - app, y0 = 2.0 * apq;
+  const bool z = apq == 0.0;
+  const int e = __builtin_amdgcn_frexp_exp(z ? 1.0 : fmax(fabs(x0), fabs(y0)));
+  const double x = __builtin_amdgcn_ldexp(x0, -e), y = __builtin_amdgcn_ldexp(y0, -e);
+  const double h = fma(x, x, y * y);   // in [1/4, 2)
+  const double d = fabs(x) + h * fast_rsq(h);
+  const double q = fast_rsq(fma(d, d, y * y));
+  *c = z ? 1.0 : d * q;
+  *s = z ? 0.0 : (x0 >= 0.0 ? y : -y) * q;
+}
+
+__device__ void pair_jacobi(double* A, double* V, double* T, int n, int lane, double tol2) {
+  const int P = n >> 1;
+  double* MA = T;
+  double* MV = T + n * n;
+  // this lane's block (i, j): the upper blocks row by row
+  const bool ok = lane < P * (P + 1) / 2;
+  int i = 0, rem = ok ? lane : 0;
+  while (rem >= P - i) {
+    rem -= P - i;
+    ++i;
+  }
+  const int j = i + rem;
+  const bool diag = i == j;
+  // positions whose entries move to this lane's in the next round
+  const int si0 = rr_src(2 * i, P), si1 = rr_src(2 * i + 1, P);
+  const int sj0 = rr_src(2 * j, P), sj1 = rr_src(2 * j + 1, P);
+  double x[4];    // entry (2i + r, 2j + c) at 2r + c
+  double dg[6];   // diagonal blocks of pairs i and j: (pp, pq, qq) each
+  double v[8];    // V: rows 2i + r of column pair j at 2r + c; rows 2j + r of pair i at 4 + 2r + c
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = e >> 1, c = e & 1;
+    x[e] = A[(2 * i + r) * n + 2 * j + c];
+    v[e] = (diag && r == c) ? 1.0 : 0.0;
+    v[4 + e] = 0.0;
+  }
+  dg[0] = A[(2 * i) * n + 2 * i];
+  dg[1] = A[(2 * i) * n + 2 * i + 1];
+  dg[2] = A[(2 * i + 1) * n + 2 * i + 1];
+  dg[3] = A[(2 * j) * n + 2 * j];
+  dg[4] = A[(2 * j) * n + 2 * j + 1];
+  dg[5] = A[(2 * j + 1) * n + 2 * j + 1];
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    if (ok) {
+      if (diag) {
+        dia = x[0] * x[0] + x[3] * x[3];
+        off = 2.0 * x[1] * x[1];
+      } else {
+        off = 2.0 * (x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o, 64);
+      dia += __shfl_xor(dia, o, 64);
+    }
+    if (off <= tol2 * (dia + 1e-300)) break;
+    for (int round = 0; round < n - 1; ++round) {
+      double ci, si, cj, sj;
+      pair_rot(dg[0], dg[1], dg[2], &ci, &si);
+      pair_rot(dg[3], dg[4], dg[5], &cj, &sj);
+      // right by the rotation of pair j, then left by that of pair i
+      const double y00 = cj * x[0] - sj * x[1], y01 = cj * x[1] + sj * x[0];
+      const double y10 = cj * x[2] - sj * x[3], y11 = cj * x[3] + sj * x[2];
+      x[0] = ci * y00 - si * y10;
+      x[1] = diag ? 0.0 : ci * y01 - si * y11;
+      x[2] = diag ? 0.0 : ci * y10 + si * y00;
+      x[3] = ci * y11 + si * y01;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const double va = v[2 * r], vb = v[2 * r + 1];
+        v[2 * r] = cj * va - sj * vb;
+        v[2 * r + 1] = cj * vb + sj * va;
+        const double wa = v[4 + 2 * r], wb = v[5 + 2 * r];
+        v[4 + 2 * r] = ci * wa - si * wb;
+        v[5 + 2 * r] = ci * wb + si * wa;
+      }
+      if (ok) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = e >> 1, c = e & 1;
+          MA[(2 * i + r) * n + 2 * j + c] = x[e];
+          MV[(2 * i + r) * n + 2 * j + c] = v[e];
+          if (!diag) {
+            MA[(2 * j + c) * n + 2 * i + r] = x[e];
+            MV[(2 * j + r) * n + 2 * i + c] = v[4 + e];
+          }
+        }
+      }
+      wave_sync();
+      x[0] = MA[si0 * n + sj0];
+      x[1] = MA[si0 * n + sj1];
+      x[2] = MA[si1 * n + sj0];
+      x[3] = MA[si1 * n + sj1];
+      dg[0] = MA[si0 * n + si0];
+      dg[1] = MA[si0 * n + si1];
+      dg[2] = MA[si1 * n + si1];
+      dg[3] = MA[sj0 * n + sj0];
+      dg[4] = MA[sj0 * n + sj1];
+      dg[5] = MA[sj1 * n + sj1];
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        v[2 * r] = MV[(2 * i + r) * n + sj0];
+        v[2 * r + 1] = MV[(2 * i + r) * n + sj1];
+        v[4 + 2 * r] = MV[(2 * j + r) * n + si0];
+        v[5 + 2 * r] = MV[(2 * j + r) * n + si1];
+      }
+      wave_sync();
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int r = e >> 1, c = e & 1;
+      A[(2 * i + r) * n + 2 * j + c] = x[e];
+      V[(2 * i + r) * n + 2 * j + c] = v[e];
+      if (!diag) {
+        A[(2 * j + c) * n + 2 * i + r] = x[e];
+        V[(2 * j + r) * n + 2 * i + c] = v[4 + e];
+      }
+    }
+  }
+  wave_sync();
+}
+
 // ------------------------------------------------------- direction
 // C = op(A) op(B) for k x k blocks (k <= KC) by one wave on FP64 matrix
 // cores: 16x16 output tiles, 4 contraction steps per instruction; operands
@@ -1287,11 +1447,10 @@ __device__ __forceinline__ void ctrl_dir_body(const ProbView& p) {
       for (int e = gl; e < nn; e += 64 * G) JAg[e] = JTg[e];
     __syncthreads();
   }
-  // Eigenvectors of P: one wave per block for small k (a round is a few
-  // instructions per lane and block barriers would cost more), the whole
-  // workgroup from n = 16 (FDA's k = 19: 400 entries per round).
-  if (n < 16) {
-    if (b < nb) wave_jacobi(JA, JV, JT, n, lane, jsc[b], p.eig_tol2);
+  // Eigenvectors of P: one wave per block with the matrix in its registers
+  // up to n = 20; beyond, the whole workgroup.
+  if (n <= 20) {
+    if (b < nb) pair_jacobi(JA, JV, JT, n, lane, p.eig_tol2);
   } else {
     double* Av[2];
     double* Vv[2];
