@@ -1280,30 +1280,38 @@ static int warm_cca_iters(int dx, int dy, int k, int iters) {
   return (std::max(1, iters) + kWarmPower - 1) / kWarmPower * kWarmPower;
 }
 
+// Most contraction splits of the dense warm-start products (their partials
+// take this many d x d blocks of the workspace).
+constexpr int kWarmSplit = 4;
+
 // C = op(A)... : out (m x n) = A^T B for A kk x m, B kk x n (FP64), split
-// over the contraction into `parts` (the big-tile GEMM), summed in order.
+// over the contraction into `parts` (the big-tile GEMM), summed in order:
+// enough splits for about 256 workgroups of 128 x 128 tiles, each at least
+// 256 rows of the contraction (at d = 1000: 64 tiles, 4 splits).
 static int gemm_atb(int m, int n, int kk, const double* A, int64_t lda, const double* Bm, int64_t ldb, double* out,
                     double* parts, size_t parts_bytes, hipStream_t st) {
   const int64_t cnt = (int64_t)m * n;
-  int ks = gram_split(kk, m, n);
-  ks = (int)std::max<int64_t>(1, std::min<int64_t>(ks, (int64_t)(parts_bytes / bytes_of<double>((size_t)cnt))));
+  const int64_t tiles = (int64_t)((m + 127) / 128) * ((n + 127) / 128);
+  int64_t ks = std::min<int64_t>((256 + tiles - 1) / tiles, std::max(1, kk / 256));
+  ks = std::min<int64_t>(ks, (int64_t)(parts_bytes / bytes_of<double>((size_t)cnt)));
+  const int nsplit = (int)std::max<int64_t>(1, ks);
   GemmArgs g{};
   g.m = m; g.n = n; g.kk = kk; g.alpha = 1.0; g.beta = 0.0;
   g.A = A; g.lda = lda; g.ta = true; g.a_f32 = false;
   g.B = Bm; g.ldb = ldb; g.tb = false; g.b_f32 = false;
-  if (ks == 1) {
+  if (nsplit == 1) {
     g.C = out; g.ldc = n;
     return gemm_f64(g, st);
   }
-  g.C = parts; g.ldc = n; g.ksplit = ks; g.c_split_stride = cnt;
+  g.C = parts; g.ldc = n; g.ksplit = nsplit; g.c_split_stride = cnt;
   SRP_TRY(gemm_f64(g, st));
-  return sum_parts_f64(parts, ks, cnt, cnt, out, 0, 0.0, st);
+  return sum_parts_f64(parts, nsplit, cnt, cnt, out, 0, 0.0, st);
 }
 
 static size_t warm_ws_bytes(int nb, int k, const int* d, int c) {
   if (nb == 2) {
     const int dx = d[0], dy = d[1], q = warm_block(dx, dy, k), dm = std::max(dx, dy);
-    const size_t dense = 3 * bytes_of<double>((size_t)dm * dm) + 2 * bytes_of<double>((size_t)dm * dm);  // E, B1, B2, parts
+    const size_t dense = (3 + kWarmSplit) * bytes_of<double>((size_t)dm * dm);  // E, B1, B2, parts
     return dense + bytes_of<double>((size_t)(3 * dy + 2 * dx) * q + 64 * 64 + q * q + q * k + 64) +
            bytes_of<int>(4) + skinny_ws_bytes(dm, dm, q) + 16 * 256;
   }
@@ -1332,7 +1340,7 @@ static int warm_cca(const RcgProblem& P, const WarmStart& w, double* const* out,
   double* E = a.take<double>((size_t)dm * dm);
   double* B1 = a.take<double>((size_t)dm * dm);
   double* B2 = a.take<double>((size_t)dm * dm);
-  const size_t parts_bytes = 2 * bytes_of<double>((size_t)dm * dm);
+  const size_t parts_bytes = kWarmSplit * bytes_of<double>((size_t)dm * dm);
   double* parts = (double*)a.take<char>(parts_bytes);
   double* W = a.take<double>((size_t)dy * q);
   double* Wn = a.take<double>((size_t)dy * q);
