@@ -29,12 +29,14 @@ COMMON_FLAGS = [
 ]
 
 
-# Per-source additions.  factor.hip: keep matrix-core accumulators in
-# ordinary vector registers; the default choice put the GEMM tiles'
-# accumulators in accumulation registers and copied all of them out and
-# back on every pass of the contraction loop.
+# Per-source additions.  factor.hip and solver_kernels.hip: keep
+# matrix-core accumulators in ordinary vector registers; the default choice
+# put the GEMM tiles' (and the row-slice products') accumulators in
+# accumulation registers and copied all of them out and back on every pass
+# of the contraction loop.
 SOURCE_FLAGS = {
     "factor.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "solver_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 
